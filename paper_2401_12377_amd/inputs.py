@@ -1,0 +1,202 @@
+"""Seeded synthetic inputs shared by the oracle tests and the GPU path.
+
+This module only draws random numbers and lays out buffers.  It holds none of
+the scheduler's logic (segments, overlap tests, window state) and none of the
+task-body arithmetic: both sides receive the same arrays and kernel lists from
+here and compute everything else on their own.
+
+Random numbers come from SplitMix64 (Steele, Lea and Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014), used as a counter-based
+generator: draw k of stream s is mix(s + (k + 1) * GAMMA).
+
+Workloads (the paper's own suites are not available, so these synthetic ones
+stand in for them, shaped like the paper's evaluation workloads):
+
+* tiny random stream: 16 FP32 buffers of 256..4096 elements, 64 kernels drawn
+  from {scale, axpy, sum_reduce}, each reading 1..3 distinct buffers and
+  writing one buffer;
+* rigid-body RL step: N spheres in the unit box with random velocities, the
+  per-step kernel list of which depends on the contacts found at run time
+  (the paper's physics-engine case study, Section III-B);
+* batched scenes: many RL scenes of log-uniform size.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+GAMMA = 0x9E3779B97F4A7C15
+MASK64 = (1 << 64) - 1
+
+OP_SCALE, OP_AXPY, OP_SUM = 0, 1, 2
+OP_NAMES = {OP_SCALE: "scale", OP_AXPY: "axpy", OP_SUM: "sum_reduce"}
+
+
+def _mix(z: int) -> int:
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+class SplitMix64:
+    """Sequential SplitMix64 stream (scalar draws)."""
+
+    def __init__(self, seed: int):
+        self.state = seed & MASK64
+
+    def next(self) -> int:
+        self.state = (self.state + GAMMA) & MASK64
+        return _mix(self.state)
+
+    def below(self, n: int) -> int:
+        """Integer in [0, n) (plain modulo; the bias is part of the definition)."""
+        return self.next() % n
+
+    def uniform_pm1(self) -> np.float32:
+        return np.float32(((self.next() >> 40) * 2.0 ** -23) - 1.0)
+
+
+def splitmix64_array(seed: int, n: int) -> np.ndarray:
+    """Draws 0..n-1 of the stream seeded with `seed`, vectorised."""
+    k = np.arange(1, n + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed & MASK64) + k * np.uint64(GAMMA)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform_pm1(bits: np.ndarray) -> np.ndarray:
+    """U[-1, 1) in FP32 from the top 24 bits; every value is exact in FP32."""
+    return ((bits >> np.uint64(40)).astype(np.float64) * 2.0 ** -23 - 1.0).astype(np.float32)
+
+
+def uniform_01(bits: np.ndarray) -> np.ndarray:
+    """U[0, 1) in float64 from the top 24 bits."""
+    return (bits >> np.uint64(40)).astype(np.float64) * 2.0 ** -24
+
+
+# ---------------------------------------------------------------------------
+# Tiny random stream
+# ---------------------------------------------------------------------------
+
+@dataclass
+class TinyKernel:
+    op: int               # OP_SCALE / OP_AXPY / OP_SUM
+    out: int              # buffer written
+    ins: tuple            # buffers read (distinct), 1 for scale, 2 for axpy, 1..3 for sum
+    a: float              # scalar for scale / axpy
+    j: int                # element of `out` written by sum_reduce
+
+
+@dataclass
+class TinyStream:
+    seed: int
+    lengths: np.ndarray          # int64[n_buffers], elements
+    offsets: np.ndarray          # int64[n_buffers], elements from the arena start (256-B aligned)
+    arena_elems: int
+    init: np.ndarray             # float32[arena_elems], initial arena contents
+    kernels: list = field(default_factory=list)
+
+    @property
+    def n_buffers(self) -> int:
+        return len(self.lengths)
+
+
+def tiny_stream(seed: int = 0, n_kernels: int = 64, n_buffers: int = 16,
+                min_len: int = 256, max_len: int = 4096) -> TinyStream:
+    rng = SplitMix64(seed)
+    lengths = np.array([min_len + rng.below(max_len - min_len + 1) for _ in range(n_buffers)],
+                       dtype=np.int64)
+    offsets = np.zeros(n_buffers, dtype=np.int64)
+    pos = 0
+    for b in range(n_buffers):
+        offsets[b] = pos
+        pos += int(lengths[b])
+        pos = (pos + 63) // 64 * 64          # 64 floats = 256 bytes
+    arena = np.zeros(pos, dtype=np.float32)
+    data_seed = rng.next()
+    vals = uniform_pm1(splitmix64_array(data_seed, int(lengths.sum())))
+    k = 0
+    for b in range(n_buffers):
+        L = int(lengths[b])
+        arena[offsets[b]:offsets[b] + L] = vals[k:k + L]
+        k += L
+    kernels = []
+    for _ in range(n_kernels):
+        op = rng.below(3)
+        a = float(rng.uniform_pm1())
+        out = rng.below(n_buffers)
+        if op == OP_SCALE:
+            ins = (rng.below(n_buffers),)
+        elif op == OP_AXPY:
+            x = rng.below(n_buffers)
+            y = rng.below(n_buffers - 1)
+            if y >= x:
+                y += 1
+            ins = (x, y)
+        else:
+            nin = 1 + rng.below(3)
+            chosen: list = []
+            while len(chosen) < nin:
+                c = rng.below(n_buffers)
+                if c not in chosen:
+                    chosen.append(c)
+            ins = tuple(chosen)
+        j = rng.below(int(lengths[out]))
+        kernels.append(TinyKernel(op=op, out=out, ins=ins, a=a, j=j))
+    return TinyStream(seed=seed, lengths=lengths, offsets=offsets, arena_elems=pos,
+                      init=arena, kernels=kernels)
+
+
+# ---------------------------------------------------------------------------
+# Rigid-body RL scene
+# ---------------------------------------------------------------------------
+
+RL_DT = np.float32(1.0 / 120.0)
+RL_RADIUS_64 = 0.06
+RL_ITERS = 8
+
+
+@dataclass
+class RLScene:
+    seed: int
+    n: int
+    radius: np.float32
+    dt: np.float32
+    iters: int
+    x: np.ndarray     # float32[n, 4]  (x, y, z, 0)
+    v: np.ndarray     # float32[n, 4]  (vx, vy, vz, 0)
+
+
+def rl_scene(seed: int = 1, n: int = 64, radius: float | None = None) -> RLScene:
+    """Spheres uniform in [r, 1-r]^3 with velocities uniform in [-1, 1)^3.
+
+    The radius defaults to 0.06 * (64 / n)^(1/3), which keeps the body density
+    (and so the expected contact degree) the same for every scene size.
+    """
+    if radius is None:
+        radius = RL_RADIUS_64 * (64.0 / n) ** (1.0 / 3.0)
+    r = np.float32(radius)
+    bits = splitmix64_array(seed, 6 * n)
+    u = uniform_01(bits[:3 * n]).reshape(n, 3)
+    x = np.zeros((n, 4), dtype=np.float32)
+    x[:, :3] = (float(r) + (1.0 - 2.0 * float(r)) * u).astype(np.float32)
+    v = np.zeros((n, 4), dtype=np.float32)
+    v[:, :3] = uniform_pm1(bits[3 * n:]).reshape(n, 3)
+    return RLScene(seed=seed, n=n, radius=r, dt=RL_DT, iters=RL_ITERS, x=x, v=v)
+
+
+def batched_scene_sizes(seed: int = 3, n_scenes: int = 256, lo: int = 16, hi: int = 512) -> np.ndarray:
+    """Scene sizes log-uniform in [lo, hi]."""
+    u = uniform_01(splitmix64_array(seed, n_scenes))
+    n = np.rint(np.exp(math.log(lo) + u * (math.log(hi) - math.log(lo)))).astype(np.int64)
+    return np.clip(n, lo, hi)
+
+
+def batched_scenes(seed: int = 3, n_scenes: int = 256) -> list:
+    sizes = batched_scene_sizes(seed, n_scenes)
+    return [rl_scene(seed=(seed * 1_000_003 + i) & MASK64, n=int(s)) for i, s in enumerate(sizes)]
