@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark: windowed out-of-order kernel scheduling on one MI355X.
+
+Workload (one "step" of this benchmark = one episode): a synthetic rigid-body
+RL scene of 64 spheres advanced 200 physics steps.  Each physics step is an
+input-dependent kernel graph (predict, broadphase, islands, permute, then
+8 Jacobi iterations x one kernel per multi-body island, then integrate),
+about 85 kernels; the island list is read back from the device every step.
+Inputs are seeded and synthetic (they stand in for the paper's Brax
+environments, which are not available here).
+
+Paths timed on the same episodes:
+  device   the persistent scheduler kernel (headline `value`)
+  inorder  every kernel launched into one HIP stream (the baseline)
+  plain    host-side window + pool of HIP streams
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(counts: dict, n: int) -> int:
+    """Bytes each kernel must move at least once (inputs read, outputs written),
+    summed over an episode.  Per physics step with E directed contact edges,
+    I islands and m multi-body islands:
+      predict 48n, broadphase 24n+4+4E, islands 20n+24+8E+4(I+1)+16m,
+      permute 36n, integrate 84n;
+    per Jacobi kernel over an island of b bodies and e edges: 36b+4+4e."""
+    steps = counts["steps"]
+    fixed = steps * (212 * n + 28) + 12 * counts["edges"] + 4 * (counts["islands"] + steps) \
+        + 16 * counts["multi_islands"]
+    jac = 36 * counts["jacobi_bodies"] + 4 * counts["jacobi_kernels"] + 4 * counts["jacobi_edges"]
+    return int(fixed + jac)
+
+
+def run_path(acs, inputs, torch, path, args, n_episodes, collect):
+    """Runs n_episodes fresh episodes; returns (seconds, kernels, step_ns list, kernel_ns list, counts)."""
+    scenes = [acs.RLSceneGPU(inputs.rl_scene(seed=args.seed, n=args.bodies)) for _ in range(n_episodes)]
+    torch.cuda.synchronize()
+    kernels = 0
+    step_ns, kern_ns, counts = [], [], None
+    t0 = time.perf_counter()
+    for g in scenes:
+        w = acs.Window(args.window, path=path, n_streams=args.streams, wg_per_task=1)
+        c, ns = acs.rl_run(w, g, args.physics_steps)
+        w.stop()
+        st = w.stats()
+        w.destroy()
+        kernels += c["kernels"]
+        if collect:
+            step_ns.extend(ns.tolist())
+            kern_ns.append(st["kernel_ns"])
+        counts = c
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt, kernels, step_ns, kern_ns, counts
+
+
+def overhead_probe(acs, path, n, chain):
+    w = acs.Window(32, path=path)
+    ns = acs.nop_run(w, n, chain)
+    w.destroy()
+    return ns / n / 1000.0
+
+
+def cpu_baseline(inputs, args):
+    from oracle import oracle as O
+    sc = inputs.rl_scene(seed=args.seed, n=args.bodies)
+    kernels, episodes = 0, 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < args.cpu_seconds:
+        s = O.Scene.from_inputs(sc)
+        for _ in range(args.physics_steps):
+            s.step()
+            kernels += 5 + s.c.iters * s.n_multi
+        episodes += 1
+    dt = time.perf_counter() - t0
+    return {"value": kernels / dt, "unit": "kernels/s", "cores": 1, "kind": "oracle",
+            "sample": f"{episodes} episodes of {args.physics_steps} steps x {args.bodies} spheres "
+                      f"({kernels} kernels, {dt:.1f} s, single thread, program order)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed episodes per path")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--physics-steps", type=int, default=200)
+    ap.add_argument("--bodies", type=int, default=64)
+    ap.add_argument("--window", type=int, default=32)
+    ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-probe", action="store_true")
+    ap.add_argument("--paths", default="device,inorder,plain")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs on a single MI355X; "
+              "independent scenes would shard across GPUs with no communication", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2401_12377_amd import acs, inputs
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    acs.lib()
+    paths = args.paths.split(",")
+    res = {}
+    for path in paths:
+        log(f"[bench] {path}: warmup {args.warmup} episodes")
+        run_path(acs, inputs, torch, path, args, args.warmup, False)
+        log(f"[bench] {path}: timing {args.steps} episodes")
+        res[path] = run_path(acs, inputs, torch, path, args, args.steps, True)
+        dt, k = res[path][0], res[path][1]
+        log(f"[bench] {path}: {dt * 1e3 / args.steps:.2f} ms/episode, {k / dt:.0f} kernels/s")
+
+    dev = res["device"]
+    dt, kernels, step_ns, kern_ns, counts = dev
+    value = kernels / dt
+    out = {
+        "metric": "kernels/sec and end-to-end speedup vs in-order stream; p50/p99 graph latency",
+        "value": value,
+        "unit": "kernels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"rigid-body RL step, {args.bodies} spheres x {args.physics_steps} steps, "
+                               f"W={args.window}, device-resident path",
+                   "bodies": args.bodies, "physics_steps": args.physics_steps, "window": args.window,
+                   "kernels_per_episode": counts["kernels"], "parallelism": "single GPU"},
+    }
+    if "inorder" in res:
+        out["speedup_vs_inorder"] = res["inorder"][0] / dt
+        out["inorder_kernels_per_s"] = res["inorder"][1] / res["inorder"][0]
+    if "plain" in res:
+        out["plain_kernels_per_s"] = res["plain"][1] / res["plain"][0]
+        out["plain_speedup_vs_inorder"] = res["inorder"][0] / res["plain"][0] if "inorder" in res else None
+    sn = np.array(step_ns) / 1e6
+    out["graph_latency_ms"] = {"p50": float(np.percentile(sn, 50)), "p99": float(np.percentile(sn, 99)),
+                               "graph": "one physics step"}
+    for p in res:
+        sp = np.array(res[p][2]) / 1e6
+        out.setdefault("graph_latency_ms_by_path", {})[p] = {"p50": float(np.percentile(sp, 50)),
+                                                             "p99": float(np.percentile(sp, 99))}
+    # roofline of the dominant (only) kernel of the device path: the persistent kernel
+    kns = float(np.mean(kern_ns))
+    bytes_per_launch = algorithmic_bytes(counts, args.bodies)
+    achieved = bytes_per_launch / kns   # bytes per ns = GB/s
+    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                       "kernel": "k_persistent", "launch_ms": kns / 1e6, "bytes_per_launch": bytes_per_launch}
+    if not args.no_probe:
+        log("[bench] overhead probes")
+        probes = {}
+        for p in paths:
+            probes[p] = {"independent_us_per_kernel": overhead_probe(acs, p, 20000 if p == "device" else 4000, False),
+                         "chain_us_per_kernel": overhead_probe(acs, p, 2000, True)}
+        out["overhead_us_per_kernel"] = probes
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline ({args.cpu_seconds:.0f} s of oracle)")
+        out["cpu_baseline"] = cpu_baseline(inputs, args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

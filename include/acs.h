@@ -1,0 +1,204 @@
+/*
+ * acs.h - windowed out-of-order kernel scheduler for MI355X (gfx950).
+ *
+ * The method is ACS (Durvasula et al., "ACS: Concurrent Kernel Execution on
+ * Irregular, Input-Dependent Computational Graphs", arXiv 2401.12377).  Each
+ * submitted kernel carries the byte ranges it reads and writes (Section IV-A,
+ * "Determining inter-kernel dependencies"; Section V-A, the kernel wrapper and
+ * its get_addresses function).  Kernels enter a fixed-size scheduling window
+ * in submission order (Section IV-B, "Mechanism Walkthrough"); on entry each
+ * one is tested for overlap against every kernel already in the window
+ * (Algorithm 1), which gives its list of upstream kernels and makes it
+ * pending, or ready when that list is empty (Section IV-A, "Tracking kernel
+ * state at runtime").  Ready kernels run concurrently; a completion removes
+ * the kernel from the window and from every upstream list (Section V-B,
+ * Algorithm 2; Section V-C).
+ *
+ * Paths (acs_config.path):
+ *   ACS_PATH_INORDER  every kernel is launched at submit into one HIP stream;
+ *                     no window.  The single-stream baseline of Section III.
+ *   ACS_PATH_PLAIN    window checks on the host, ready kernels launched into a
+ *                     pool of HIP streams, one kernel per stream at a time,
+ *                     completions seen through HIP events (Section V-B).
+ *   ACS_PATH_DEVICE   window held on the GPU by a persistent scheduler kernel:
+ *                     one wavefront keeps one window slot per lane, tests the
+ *                     overlaps, builds the ready mask with a ballot and
+ *                     publishes ready work to resident worker workgroups that
+ *                     run the task bodies and signal completion with atomic
+ *                     counters.  The software analogue of ACS-HW (Section V-C):
+ *                     no host round trip per kernel.
+ *   ACS_PATH_MANUAL   window only, no GPU: the caller takes ready kernels and
+ *                     reports their completion (a stand-in executor for tests).
+ *
+ * Conventions.  Functions return ACS_OK (0) or a negative ACS_E* code.  A
+ * window is driven by one host thread at a time.  Device buffers named in
+ * task arguments are borrowed: the caller owns them and keeps them alive until
+ * acs_sync returns.  Segment lists and argument blocks are copied before
+ * acs_submit returns.
+ */
+#ifndef ACS_H
+#define ACS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct acs_window acs_window;
+
+/* A byte range [start, start + size) of virtual memory (Section IV-A: a start
+ * address and a size).  Zero-size ranges are dropped.  The range
+ * {0, UINT64_MAX} stands for "may touch any memory", the conservative fallback
+ * of Section V-A for kernels whose accesses cannot be stated. */
+typedef struct {
+    uint64_t start;
+    uint64_t size;
+} acs_seg;
+
+#define ACS_SEG_ALL_START 0ull
+#define ACS_SEG_ALL_SIZE UINT64_MAX
+
+/* Kernel states in the window (Section IV-A; two bits per slot in Section V-C). */
+enum { ACS_PENDING = 0, ACS_READY = 1, ACS_EXECUTING = 2 };
+
+enum {
+    ACS_OK = 0,
+    ACS_EINVAL = -1,     /* bad argument: W outside [1,64], unknown kernel id, overflowing range ... */
+    ACS_ENOMEM = -2,     /* host or device allocation failed */
+    ACS_EAGAIN = -3,     /* input FIFO full and the window is non-blocking (or manual and stalled) */
+    ACS_EDEVICE = -4,    /* a HIP call failed */
+    ACS_ETIMEDOUT = -5,  /* acs_sync_timeout ran out of time */
+    ACS_EKERNEL = -6,    /* a kernel failed; its dependents were not run */
+    ACS_ESTATE = -7      /* call not valid in this state (e.g. configure after submit) */
+};
+
+enum { ACS_PATH_INORDER = 0, ACS_PATH_PLAIN = 1, ACS_PATH_DEVICE = 2, ACS_PATH_MANUAL = 3 };
+
+#define ACS_W_MAX 64       /* one window slot per wavefront lane */
+#define ACS_K_MAX 8        /* read + write segments kept per kernel */
+#define ACS_ARGS_MAX 64    /* bytes of task arguments */
+
+typedef struct {
+    int32_t path;            /* ACS_PATH_* (default ACS_PATH_DEVICE) */
+    int32_t n_streams;       /* plain path: HIP streams in the pool (default 4) */
+    int32_t wg_per_task;     /* workgroups per splittable task body (default 1) */
+    int32_t n_workers;       /* device path: worker workgroups (0 = one per compute unit) */
+    int32_t queue_depth;     /* input FIFO capacity in kernels (default 4096) */
+    int32_t nonblocking;     /* 1: acs_submit returns ACS_EAGAIN when the FIFO is full */
+    int32_t trace;           /* 1: record a per-kernel trace (see acs_trace_read) */
+    int32_t trace_capacity;  /* kernels the trace can hold (default 1 << 16) */
+    int32_t device;          /* HIP device ordinal (default 0) */
+    int32_t reserved[7];
+} acs_config;
+
+/* One entry of the scheduled list (Section V-C): the kernels currently in the
+ * window.  On the device path the list is a snapshot and may be stale. */
+typedef struct {
+    uint64_t seq;            /* submission index */
+    int32_t kernel_id;
+    int32_t state;           /* ACS_PENDING / ACS_READY / ACS_EXECUTING */
+    uint64_t upstream_mask;  /* window slots this kernel still waits for */
+    int32_t slot;
+    int32_t reserved;
+} acs_entry;
+
+/* One trace record per kernel (all times on one clock, in nanoseconds). */
+typedef struct {
+    int64_t seq, slot, kernel_id;
+    int64_t ev_insert, ev_dispatch, ev_retire;  /* positions in the window's event order */
+    uint64_t valid_mask;     /* slots held by older kernels when this kernel was inserted */
+    uint64_t up_mask;        /* its upstream slots at insert */
+    int64_t t_start, t_end;  /* execution interval, -1 if not recorded */
+} acs_trace_rec;
+
+typedef struct {
+    uint64_t submitted, retired, dispatched;
+    uint64_t coalesced;      /* kernels whose segment lists were merged to fit ACS_K_MAX */
+    uint64_t overlap_tests;  /* segment-pair tests made by the dependency checks */
+    uint64_t poisoned;       /* kernels not run because an upstream kernel failed */
+    int32_t path, W;
+    int32_t n_workers, n_streams;
+    uint64_t kernel_ns;      /* device path, after acs_window_stop: duration of the
+                                persistent kernel from HIP events on its stream */
+} acs_stats;
+
+/* Fills *cfg with the defaults listed above. */
+void acs_config_default(acs_config *cfg);
+
+/* New window of W slots, 1 <= W <= 64 (the paper evaluates W = 32 and 16,
+ * Section VI and Section VII-E).  NULL on error; see acs_last_error(). */
+acs_window *acs_window_create(int32_t W);
+
+/* Chooses the path and its resources; valid before the first submit only.
+ * Without this call the window uses acs_config_default(). */
+int acs_window_configure(acs_window *w, const acs_config *cfg);
+
+/* Submits one kernel in program order.
+ *   kernel_id   task type from acs_tasks.h (the body the library runs).
+ *   read_segs   n_read byte ranges the kernel reads; write_segs likewise.
+ *               Beyond ACS_K_MAX segments in total, neighbouring ranges of the
+ *               same kind are merged into their bounding range (conservative).
+ *   args        args_size <= ACS_ARGS_MAX bytes, the task's argument struct.
+ *   seq_out     receives the kernel's submission index (may be NULL).
+ * Blocks while the input FIFO is full unless the window is non-blocking.
+ * Errors: ACS_EINVAL for an unknown kernel id, args_size too large, a range
+ * that wraps past 2^64 (other than the all-memory range), NULL lists with
+ * non-zero counts; ACS_EAGAIN when full and non-blocking; ACS_EDEVICE. */
+int acs_submit(acs_window *w, int32_t kernel_id,
+               const acs_seg *read_segs, int32_t n_read,
+               const acs_seg *write_segs, int32_t n_write,
+               const void *args, size_t args_size, uint64_t *seq_out);
+
+/* Waits until every submitted kernel has completed.  Returns the first
+ * sticky asynchronous error (ACS_EKERNEL, ACS_EDEVICE) if there was one. */
+int acs_sync(acs_window *w);
+
+/* As acs_sync but gives up after timeout_ns nanoseconds (ACS_ETIMEDOUT). */
+int acs_sync_timeout(acs_window *w, uint64_t timeout_ns);
+
+/* Copies up to cap entries of the scheduled list into out (oldest first). */
+int acs_scheduled_list(acs_window *w, acs_entry *out, int32_t cap, int32_t *n_out);
+
+/* Copies the trace (requires acs_config.trace; call after acs_sync). */
+int acs_trace_read(acs_window *w, acs_trace_rec *out, int64_t cap, int64_t *n_out);
+
+int acs_stats_get(acs_window *w, acs_stats *out);
+
+/* Waits for outstanding work and releases the path's execution resources
+ * (the device path's persistent kernel exits).  Statistics and the trace stay
+ * readable; further submits fail with ACS_ESTATE.  Returns the acs_sync status. */
+int acs_window_stop(acs_window *w);
+
+/* Waits for outstanding work, stops the persistent kernel if any, frees
+ * everything the library owns.  Returns the final acs_sync status. */
+int acs_window_destroy(acs_window *w);
+
+/* Manual path only: moves up to cap ready kernels (oldest first) to the
+ * executing state and returns their seqs. */
+int acs_manual_take_ready(acs_window *w, uint64_t *seqs, int32_t cap, int32_t *n_out);
+/* Manual path only: reports completion of an executing kernel; status != 0
+ * marks it failed, which poisons every kernel that depends on it. */
+int acs_manual_complete(acs_window *w, uint64_t seq, int32_t status);
+
+/* What the device path would use on a device (no kernel is launched). */
+typedef struct {
+    int32_t compute_units;          /* multiprocessor count */
+    int32_t wall_clock_khz;         /* constant clock of the device timestamps */
+    int32_t persistent_wg_per_cu;   /* resident persistent-kernel workgroups per compute unit */
+    int32_t runtime_version;        /* HIP runtime actually loaded in this process */
+    int32_t lds_bytes_per_wg;       /* LDS of one persistent-kernel workgroup */
+    int32_t reserved[3];
+} acs_device_info;
+
+int acs_device_query(int32_t device, acs_device_info *out);
+
+/* Error code of the last failing call on this thread, and its text. */
+int acs_last_error(void);
+const char *acs_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ACS_H */

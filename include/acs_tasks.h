@@ -1,0 +1,84 @@
+/*
+ * acs_tasks.h - the closed table of task bodies the library can run, and the
+ * argument struct of each.  A kernel_id passed to acs_submit names one of
+ * these; its args block is the matching struct (at most ACS_ARGS_MAX bytes).
+ *
+ * The paper's kernel wrapper pairs a kernel with a function that states its
+ * read and write ranges from its launch arguments (Section V-A).  Here the
+ * body is chosen from this table and the caller states the ranges; the
+ * Python binding has one range helper per task type.
+ *
+ * Every body runs with 256-thread workgroups.  A splittable body is cut into
+ * "pieces" (one workgroup each); its result never depends on the number of
+ * pieces, so all paths produce identical bits.
+ */
+#ifndef ACS_TASKS_H
+#define ACS_TASKS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum acs_kernel_id {
+    ACS_K_NOP = 0,            /* empty body, optional busy wait (overhead measurements) */
+    /* tiny random stream */
+    ACS_K_SCALE = 1,          /* out[i] = a * x[i],            i < n */
+    ACS_K_AXPY = 2,           /* out[i] = fma(a, x[i], y[i]),  i < n */
+    ACS_K_SUM = 3,            /* *out = pairwise sum of in[0..nin) concatenated */
+    /* rigid-body RL step (one scene; see acs_rl_layout) */
+    ACS_K_RL_PREDICT = 10,    /* P = fma(dt, V, X) */
+    ACS_K_RL_BROADPHASE = 11, /* all-pairs contact test on P -> degree + adjacency (CSR) */
+    ACS_K_RL_ISLANDS = 12,    /* connected components -> permutation, permuted CSR, plan */
+    ACS_K_RL_PERMUTE = 13,    /* Q0[p] = P[perm[p]] */
+    ACS_K_RL_JACOBI = 14,     /* one Jacobi contact iteration over one island */
+    ACS_K_RL_INTEGRATE = 15,  /* X, V from Q0 with wall reflection */
+    ACS_K_COUNT = 16
+};
+
+#define ACS_BLOCK 256
+
+typedef struct { uint64_t spin_ns; } acs_args_nop;
+
+typedef struct { float *out; const float *x; float a; uint32_t n; } acs_args_scale;
+
+typedef struct { float *out; const float *x; const float *y; float a; uint32_t n; } acs_args_axpy;
+
+/* in[k] holds len[k] floats; the sum runs over in[0] ++ in[1] ++ ... (nin <= 3).
+ * Pairwise tree: pad with zeros to the next power of two P and, for
+ * s = P/2, ..., 1, add element i + s into element i. */
+typedef struct { float *out; const float *in[3]; uint32_t len[3]; uint32_t nin; } acs_args_sum;
+
+/* Rigid-body RL scene.  `base` is the scene's device arena (acs_rl_layout);
+ * `plan` is a host-visible int32 buffer of 4 + 4 * (n / 2) entries written by
+ * the islands kernel: [0] islands, [1] multi-body islands, [2] directed edges,
+ * then per multi-body island: first position, end position, first edge, end edge. */
+typedef struct {
+    uint64_t base;
+    uint64_t plan;
+    int32_t n;
+    float r;
+    float dt;
+    int32_t iter;            /* Jacobi: iteration index (even: Q0 -> Q1, odd: Q1 -> Q0) */
+    int32_t b0, b1;          /* Jacobi: positions [b0, b1) of the island */
+} acs_args_rl;
+
+/* Regions of an RL scene arena, in order; byte offsets from acs_rl_layout. */
+enum acs_rl_region {
+    ACS_RL_X = 0, ACS_RL_V, ACS_RL_P, ACS_RL_Q0, ACS_RL_Q1,       /* float4[n] */
+    ACS_RL_DEG, ACS_RL_ADJ_OFF, ACS_RL_ADJ,                       /* int[n], int[n+1], int[n(n-1)] */
+    ACS_RL_LABEL, ACS_RL_PERM, ACS_RL_INV_PERM, ACS_RL_ISL_OFF,   /* int[n] x3, int[n+1] */
+    ACS_RL_PADJ_OFF, ACS_RL_PADJ,                                 /* int[n+1], int[n(n-1)] */
+    ACS_RL_END,                                                   /* total arena bytes */
+    ACS_RL_NREGIONS
+};
+
+/* Fills off[ACS_RL_NREGIONS] with 256-byte-aligned offsets for n bodies;
+ * returns 0, or ACS_EINVAL (-1) when n is outside [2, 1024]. */
+int acs_rl_layout(int32_t n, uint64_t *off);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ACS_TASKS_H */

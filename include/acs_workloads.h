@@ -1,0 +1,66 @@
+/*
+ * acs_workloads.h - native drivers that play the application on top of the
+ * acs.h API for the synthetic workloads (the paper's evaluation runs
+ * physics-simulation steps whose kernel graph depends on the input,
+ * Section III-B and Section VII).  They only call acs_submit / acs_sync and
+ * read results; they hold no scheduling logic of their own.
+ */
+#ifndef ACS_WORKLOADS_H
+#define ACS_WORKLOADS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "acs.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Pinned, coherent host memory that kernels can write directly (the RL plan
+ * buffer).  NULL on failure.  Free with acs_host_free. */
+void *acs_host_alloc(size_t bytes);
+int acs_host_free(void *p);
+
+/* One rigid-body RL scene.  arena: device memory of acs_rl_layout(n)[ACS_RL_END]
+ * bytes with X and V initialised (float4 per body); plan: acs_host_alloc'd
+ * int32 buffer of 4 + 4 * (n / 2) entries. */
+typedef struct {
+    int32_t n;
+    int32_t iters;          /* Jacobi iterations per step (8) */
+    float r, dt;
+    uint64_t arena;
+    int32_t *plan;
+} acs_rl_scene;
+
+/* Work done by acs_rl_run, summed over its steps. */
+typedef struct {
+    uint64_t kernels;          /* kernels submitted */
+    uint64_t steps;
+    uint64_t islands;          /* connected components found */
+    uint64_t multi_islands;    /* components with two or more bodies */
+    uint64_t edges;            /* directed contact edges (twice the contacts) */
+    uint64_t jacobi_kernels;
+    uint64_t jacobi_bodies;    /* bodies covered by Jacobi kernels */
+    uint64_t jacobi_edges;     /* adjacency entries read by Jacobi kernels */
+} acs_rl_counts;
+
+/* Runs `steps` steps.  Per step: predict, broadphase, islands, permute are
+ * submitted, the window is drained so that the plan (input-dependent island
+ * list) can be read, then iters x (multi-body islands) Jacobi kernels in
+ * iteration-major order and the integrate kernel are submitted.  step_ns (if
+ * not NULL, `steps` entries) receives the wall time of each step measured
+ * between consecutive plan reads; counts (if not NULL) the work done.
+ * Returns the first error. */
+int acs_rl_run(acs_window *w, const acs_rl_scene *scene, int32_t steps, double *step_ns, acs_rl_counts *counts);
+
+/* Overhead probe: n no-op kernels, each spinning spin_ns on the device.
+ * chain = 0: all independent (distinct one-byte write ranges);
+ * chain = 1: each reads and writes the same byte (a serial chain).
+ * Drains the window at the end; wall_ns receives submit-to-drain time. */
+int acs_nop_run(acs_window *w, int32_t n, int32_t chain, uint64_t spin_ns, double *wall_ns);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ACS_WORKLOADS_H */

@@ -1,0 +1,452 @@
+"""Python binding of libacs (include/acs.h, acs_tasks.h, acs_workloads.h).
+
+Argument marshalling only: every step of the scheduling path and every task
+body runs inside libacs.so.  PyTorch is used for device memory.  Importing
+works without a GPU; creating a GPU window needs the built library and a
+device, and fails loudly otherwise (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes as C
+import os
+import weakref
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libacs.so")
+
+# ---------------------------------------------------------------------------
+# constants mirrored from the headers
+# ---------------------------------------------------------------------------
+OK, EINVAL, ENOMEM, EAGAIN, EDEVICE, ETIMEDOUT, EKERNEL, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
+PENDING, READY, EXECUTING = 0, 1, 2
+PATH_INORDER, PATH_PLAIN, PATH_DEVICE, PATH_MANUAL = 0, 1, 2, 3
+PATHS = {"inorder": PATH_INORDER, "plain": PATH_PLAIN, "device": PATH_DEVICE, "manual": PATH_MANUAL}
+W_MAX, K_MAX, ARGS_MAX = 64, 8, 64
+SEG_ALL = (0, (1 << 64) - 1)
+
+K_NOP, K_SCALE, K_AXPY, K_SUM = 0, 1, 2, 3
+K_RL_PREDICT, K_RL_BROADPHASE, K_RL_ISLANDS, K_RL_PERMUTE, K_RL_JACOBI, K_RL_INTEGRATE = 10, 11, 12, 13, 14, 15
+
+RL_X, RL_V, RL_P, RL_Q0, RL_Q1, RL_DEG, RL_ADJ_OFF, RL_ADJ, RL_LABEL, RL_PERM, RL_INV_PERM, RL_ISL_OFF, \
+    RL_PADJ_OFF, RL_PADJ, RL_END = range(15)
+RL_NREGIONS = 15
+
+
+class AcsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"acs error {code}: {msg}")
+        self.code = code
+
+
+class Seg(C.Structure):
+    _fields_ = [("start", C.c_uint64), ("size", C.c_uint64)]
+
+
+class Config(C.Structure):
+    _fields_ = [("path", C.c_int32), ("n_streams", C.c_int32), ("wg_per_task", C.c_int32), ("n_workers", C.c_int32),
+                ("queue_depth", C.c_int32), ("nonblocking", C.c_int32), ("trace", C.c_int32),
+                ("trace_capacity", C.c_int32), ("device", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
+class Entry(C.Structure):
+    _fields_ = [("seq", C.c_uint64), ("kernel_id", C.c_int32), ("state", C.c_int32), ("upstream_mask", C.c_uint64),
+                ("slot", C.c_int32), ("reserved", C.c_int32)]
+
+
+TRACE_DTYPE = np.dtype([("seq", np.int64), ("slot", np.int64), ("kid", np.int64),
+                        ("ev_insert", np.int64), ("ev_dispatch", np.int64), ("ev_retire", np.int64),
+                        ("valid_mask", np.uint64), ("up_mask", np.uint64),
+                        ("t_start", np.int64), ("t_end", np.int64)])
+
+
+class Stats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("retired", C.c_uint64), ("dispatched", C.c_uint64),
+                ("coalesced", C.c_uint64), ("overlap_tests", C.c_uint64), ("poisoned", C.c_uint64),
+                ("path", C.c_int32), ("W", C.c_int32), ("n_workers", C.c_int32), ("n_streams", C.c_int32),
+                ("kernel_ns", C.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# task argument structs (acs_tasks.h)
+class ArgsNop(C.Structure):
+    _fields_ = [("spin_ns", C.c_uint64)]
+
+
+class ArgsScale(C.Structure):
+    _fields_ = [("out", C.c_uint64), ("x", C.c_uint64), ("a", C.c_float), ("n", C.c_uint32)]
+
+
+class ArgsAxpy(C.Structure):
+    _fields_ = [("out", C.c_uint64), ("x", C.c_uint64), ("y", C.c_uint64), ("a", C.c_float), ("n", C.c_uint32)]
+
+
+class ArgsSum(C.Structure):
+    _fields_ = [("out", C.c_uint64), ("ins", C.c_uint64 * 3), ("len", C.c_uint32 * 3), ("nin", C.c_uint32)]
+
+
+class ArgsRL(C.Structure):
+    _fields_ = [("base", C.c_uint64), ("plan", C.c_uint64), ("n", C.c_int32), ("r", C.c_float), ("dt", C.c_float),
+                ("iter", C.c_int32), ("b0", C.c_int32), ("b1", C.c_int32)]
+
+
+class DeviceInfo(C.Structure):
+    _fields_ = [("compute_units", C.c_int32), ("wall_clock_khz", C.c_int32), ("persistent_wg_per_cu", C.c_int32),
+                ("runtime_version", C.c_int32), ("lds_bytes_per_wg", C.c_int32), ("reserved", C.c_int32 * 3)]
+
+
+class RLCounts(C.Structure):
+    _fields_ = [(f, C.c_uint64) for f in ("kernels", "steps", "islands", "multi_islands", "edges", "jacobi_kernels",
+                                          "jacobi_bodies", "jacobi_edges")]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class RLSceneC(C.Structure):
+    _fields_ = [("n", C.c_int32), ("iters", C.c_int32), ("r", C.c_float), ("dt", C.c_float),
+                ("arena", C.c_uint64), ("plan", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libacs.so; raises if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2401_12377_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        L.acs_config_default.argtypes = [P(Config)]
+        L.acs_config_default.restype = None
+        L.acs_window_create.argtypes = [C.c_int32]
+        L.acs_window_create.restype = C.c_void_p
+        L.acs_window_configure.argtypes = [C.c_void_p, P(Config)]
+        L.acs_submit.argtypes = [C.c_void_p, C.c_int32, P(Seg), C.c_int32, P(Seg), C.c_int32, C.c_void_p, C.c_size_t,
+                                 P(C.c_uint64)]
+        L.acs_sync.argtypes = [C.c_void_p]
+        L.acs_sync_timeout.argtypes = [C.c_void_p, C.c_uint64]
+        L.acs_scheduled_list.argtypes = [C.c_void_p, P(Entry), C.c_int32, P(C.c_int32)]
+        L.acs_trace_read.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, P(C.c_int64)]
+        L.acs_stats_get.argtypes = [C.c_void_p, P(Stats)]
+        L.acs_window_destroy.argtypes = [C.c_void_p]
+        L.acs_window_stop.argtypes = [C.c_void_p]
+        L.acs_manual_take_ready.argtypes = [C.c_void_p, P(C.c_uint64), C.c_int32, P(C.c_int32)]
+        L.acs_manual_complete.argtypes = [C.c_void_p, C.c_uint64, C.c_int32]
+        L.acs_last_error.argtypes = []
+        L.acs_strerror.argtypes = [C.c_int]
+        L.acs_strerror.restype = C.c_char_p
+        L.acs_rl_layout.argtypes = [C.c_int32, P(C.c_uint64)]
+        L.acs_device_query.argtypes = [C.c_int32, P(DeviceInfo)]
+        L.acs_device_query.restype = C.c_int
+        L.acs_host_alloc.argtypes = [C.c_size_t]
+        L.acs_host_alloc.restype = C.c_void_p
+        L.acs_host_free.argtypes = [C.c_void_p]
+        L.acs_rl_run.argtypes = [C.c_void_p, P(RLSceneC), C.c_int32, P(C.c_double), P(RLCounts)]
+        L.acs_nop_run.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, P(C.c_double)]
+        for f in ("acs_window_configure", "acs_submit", "acs_sync", "acs_sync_timeout", "acs_scheduled_list",
+                  "acs_trace_read", "acs_stats_get", "acs_window_destroy", "acs_window_stop", "acs_manual_take_ready",
+                  "acs_manual_complete", "acs_last_error", "acs_rl_layout", "acs_host_free", "acs_rl_run",
+                  "acs_nop_run"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc < 0:
+        raise AcsError(rc, lib().acs_strerror(rc).decode())
+    return rc
+
+
+def _segs(lst):
+    n = len(lst)
+    arr = (Seg * max(1, n))()
+    for i, (s, z) in enumerate(lst):
+        arr[i].start, arr[i].size = int(s), int(z)
+    return arr, n
+
+
+_live = weakref.WeakSet()
+
+
+class Window:
+    """One scheduling window (acs_window_create + acs_window_configure)."""
+
+    def __init__(self, W: int, path: str = "device", n_streams: int = 4, wg_per_task: int = 1, n_workers: int = 0,
+                 queue_depth: int = 4096, nonblocking: bool = False, trace: bool = False,
+                 trace_capacity: int = 1 << 16, device: int = 0):
+        L = lib()
+        h = L.acs_window_create(W)
+        if not h:
+            code = L.acs_last_error()
+            raise AcsError(code, L.acs_strerror(code).decode())
+        self._h = h
+        self.W = W
+        self.path = path
+        cfg = Config()
+        L.acs_config_default(C.byref(cfg))
+        cfg.path = PATHS[path]
+        cfg.n_streams, cfg.wg_per_task, cfg.n_workers = n_streams, wg_per_task, n_workers
+        cfg.queue_depth, cfg.nonblocking, cfg.trace = queue_depth, int(nonblocking), int(trace)
+        cfg.trace_capacity, cfg.device = trace_capacity, device
+        rc = L.acs_window_configure(h, C.byref(cfg))
+        if rc < 0:
+            msg = L.acs_strerror(rc).decode()
+            L.acs_window_destroy(h)
+            self._h = None
+            raise AcsError(rc, msg)
+        _live.add(self)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise AcsError(ESTATE, "window destroyed")
+        return self._h
+
+    def submit(self, kid: int, reads, writes, args) -> int:
+        r, nr = _segs(reads)
+        w, nw = _segs(writes)
+        seq = C.c_uint64()
+        _check(lib().acs_submit(self.handle, kid, r, nr, w, nw, C.byref(args) if args is not None else None,
+                                C.sizeof(args) if args is not None else 0, C.byref(seq)))
+        return seq.value
+
+    def submit_raw(self, kid, reads, writes, args_bytes: bytes):
+        """Like submit, with the argument block given as bytes (for tests)."""
+        r, nr = _segs(reads)
+        w, nw = _segs(writes)
+        buf = C.create_string_buffer(args_bytes, len(args_bytes)) if args_bytes else None
+        seq = C.c_uint64()
+        rc = lib().acs_submit(self.handle, kid, r, nr, w, nw, buf, len(args_bytes), C.byref(seq))
+        return rc, seq.value
+
+    def sync(self, timeout_ns: int | None = None) -> int:
+        if timeout_ns is None:
+            return _check(lib().acs_sync(self.handle))
+        return _check(lib().acs_sync_timeout(self.handle, timeout_ns))
+
+    def sync_rc(self, timeout_ns: int | None = None) -> int:
+        """Status code of a sync, without raising."""
+        if timeout_ns is None:
+            return lib().acs_sync(self.handle)
+        return lib().acs_sync_timeout(self.handle, timeout_ns)
+
+    def scheduled_list(self):
+        arr = (Entry * W_MAX)()
+        n = C.c_int32()
+        _check(lib().acs_scheduled_list(self.handle, arr, W_MAX, C.byref(n)))
+        return [(arr[i].seq, arr[i].kernel_id, arr[i].state, arr[i].upstream_mask, arr[i].slot)
+                for i in range(n.value)]
+
+    def trace(self, cap: int | None = None) -> np.ndarray:
+        st = self.stats()
+        cap = int(st["submitted"]) if cap is None else cap
+        out = np.zeros(max(1, cap), dtype=TRACE_DTYPE)
+        n = C.c_int64()
+        _check(lib().acs_trace_read(self.handle, out.ctypes.data, cap, C.byref(n)))
+        return out[:n.value]
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().acs_stats_get(self.handle, C.byref(s)))
+        return s.as_dict()
+
+    def take_ready(self):
+        arr = (C.c_uint64 * W_MAX)()
+        n = C.c_int32()
+        _check(lib().acs_manual_take_ready(self.handle, arr, W_MAX, C.byref(n)))
+        return [arr[i] for i in range(n.value)]
+
+    def complete(self, seq: int, status: int = 0):
+        _check(lib().acs_manual_complete(self.handle, seq, status))
+
+    def stop(self) -> int:
+        """Drains and releases the execution resources; stats and trace stay readable."""
+        return _check(lib().acs_window_stop(self.handle))
+
+    def destroy(self) -> int:
+        if self._h is None:
+            return OK
+        rc = lib().acs_window_destroy(self._h)
+        self._h = None
+        return rc
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+@atexit.register
+def _destroy_live_windows():
+    # a device window left alive would keep its persistent kernel running
+    for w in list(_live):
+        try:
+            w.destroy()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# range helpers (the get_addresses of each task type, Section V-A)
+# ---------------------------------------------------------------------------
+def tensor_seg(t, elem_offset: int = 0, n_elems: int | None = None):
+    """Byte range of n_elems elements of tensor t starting at elem_offset."""
+    es = t.element_size()
+    n = t.numel() - elem_offset if n_elems is None else n_elems
+    return (t.data_ptr() + es * elem_offset, es * n)
+
+
+def gemm_segments(a_ptr: int, b_ptr: int, c_ptr: int, m: int, n: int, k: int, elem_size: int):
+    """Read and write ranges of C[m,k] = A[m,n] @ B[n,k] (the paper's
+    get_addresses example for matrix multiply, Section V-A)."""
+    return [(a_ptr, m * n * elem_size), (b_ptr, n * k * elem_size)], [(c_ptr, m * k * elem_size)]
+
+
+def tiny_kernel_task(stream, k, base: int):
+    """(kernel_id, reads, writes, args) of one tiny-stream kernel whose buffers
+    live in an arena starting at device address `base`."""
+    from .inputs import OP_SCALE, OP_AXPY
+    addr = [base + 4 * int(o) for o in stream.offsets]
+    L = [int(x) for x in stream.lengths]
+    if k.op in (OP_SCALE, OP_AXPY):
+        n = min([L[k.out]] + [L[b] for b in k.ins])
+        reads = [(addr[b], 4 * n) for b in k.ins]
+        writes = [(addr[k.out], 4 * n)]
+        if k.op == OP_SCALE:
+            return K_SCALE, reads, writes, ArgsScale(addr[k.out], addr[k.ins[0]], k.a, n)
+        return K_AXPY, reads, writes, ArgsAxpy(addr[k.out], addr[k.ins[0]], addr[k.ins[1]], k.a, n)
+    reads = [(addr[b], 4 * L[b]) for b in k.ins]
+    out = addr[k.out] + 4 * k.j
+    a = ArgsSum()
+    a.out = out
+    for t, b in enumerate(k.ins):
+        a.ins[t] = addr[b]
+        a.len[t] = L[b]
+    a.nin = len(k.ins)
+    return K_SUM, reads, [(out, 4)], a
+
+
+def submit_tiny_stream(win: Window, stream, base: int):
+    return [win.submit(*tiny_kernel_task(stream, k, base)) for k in stream.kernels]
+
+
+# ---------------------------------------------------------------------------
+# RL scene
+# ---------------------------------------------------------------------------
+def device_query(device: int = 0) -> dict:
+    d = DeviceInfo()
+    _check(lib().acs_device_query(device, C.byref(d)))
+    return {f: getattr(d, f) for f, _ in DeviceInfo._fields_ if f != "reserved"}
+
+
+def rl_layout(n: int) -> np.ndarray:
+    off = (C.c_uint64 * RL_NREGIONS)()
+    _check(lib().acs_rl_layout(n, off))
+    return np.array(off[:], dtype=np.int64)
+
+
+def rl_plan_ints(n: int) -> int:
+    return 4 + 4 * (n // 2)
+
+
+class HostBuffer:
+    """Pinned, coherent host memory from acs_host_alloc, viewed as numpy."""
+
+    def __init__(self, nbytes: int):
+        p = lib().acs_host_alloc(nbytes)
+        if not p:
+            raise AcsError(ENOMEM, "acs_host_alloc failed")
+        self.ptr = p
+        self.nbytes = nbytes
+
+    def view(self, dtype=np.int32):
+        buf = (C.c_uint8 * self.nbytes).from_address(self.ptr)
+        return np.frombuffer(buf, dtype=dtype)
+
+    def free(self):
+        if self.ptr:
+            lib().acs_host_free(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class RLSceneGPU:
+    """Device arena and host plan buffer of one RL scene (torch for memory)."""
+
+    def __init__(self, scene, device="cuda"):
+        import torch
+        self.n = scene.n
+        self.r = float(scene.radius)
+        self.dt = float(scene.dt)
+        self.iters = scene.iters
+        self.off = rl_layout(self.n)
+        self.arena = torch.zeros(int(self.off[RL_END]), dtype=torch.uint8, device=device)
+        self.plan_buf = HostBuffer(4 * rl_plan_ints(self.n))
+        self.plan_buf.view()[:] = 0
+        self.set_state(scene.x, scene.v)
+
+    def region(self, r: int, dtype, count: int):
+        import torch
+        o = int(self.off[r])
+        es = torch.tensor([], dtype=dtype).element_size()
+        return self.arena[o:o + es * count].view(dtype)
+
+    def set_state(self, x, v):
+        import torch
+        self.region(RL_X, torch.float32, 4 * self.n).copy_(torch.as_tensor(np.ascontiguousarray(x, np.float32)).reshape(-1))
+        self.region(RL_V, torch.float32, 4 * self.n).copy_(torch.as_tensor(np.ascontiguousarray(v, np.float32)).reshape(-1))
+        torch.cuda.synchronize()   # the library's streams do not wait for torch's
+
+    def get(self, r: int):
+        import torch
+        n = self.n
+        if r in (RL_X, RL_V, RL_P, RL_Q0, RL_Q1):
+            return self.region(r, torch.float32, 4 * n).cpu().numpy().reshape(n, 4)
+        counts = {RL_DEG: n, RL_ADJ_OFF: n + 1, RL_ADJ: n * (n - 1), RL_LABEL: n, RL_PERM: n, RL_INV_PERM: n,
+                  RL_ISL_OFF: n + 1, RL_PADJ_OFF: n + 1, RL_PADJ: n * (n - 1)}
+        return self.region(r, torch.int32, counts[r]).cpu().numpy()
+
+    def plan(self) -> np.ndarray:
+        return self.plan_buf.view().copy()
+
+    def c_struct(self) -> RLSceneC:
+        s = RLSceneC()
+        s.n, s.iters, s.r, s.dt = self.n, self.iters, self.r, self.dt
+        s.arena = self.arena.data_ptr()
+        s.plan = self.plan_buf.ptr
+        return s
+
+
+def rl_run(win: Window, scene_gpu: RLSceneGPU, steps: int):
+    """Runs `steps` RL steps through the window; returns (counts dict, per-step ns)."""
+    sc = scene_gpu.c_struct()
+    step_ns = (C.c_double * max(1, steps))()
+    k = RLCounts()
+    _check(lib().acs_rl_run(win.handle, C.byref(sc), steps, step_ns, C.byref(k)))
+    return k.as_dict(), np.array(step_ns[:steps])
+
+
+def nop_run(win: Window, n: int, chain: bool, spin_ns: int = 0) -> float:
+    t = C.c_double()
+    _check(lib().acs_nop_run(win.handle, n, int(chain), spin_ns, C.byref(t)))
+    return t.value

@@ -1,0 +1,454 @@
+// Task bodies (device code).  Each body is a __device__ function run by one
+// 256-thread workgroup for one piece; the standalone kernels (in-order and
+// plain paths) and the persistent kernel's workers call the same functions,
+// so every path computes the same bits.
+//
+// Floating point: built with -ffp-contract=off and correctly rounded FP32
+// division and square root; fused multiply-adds appear only where the task
+// definition says fma.  Every reduction has a fixed order defined by the data
+// size, never by the number of pieces or workgroups.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "acs_tasks.h"
+#include "rl_layout.hpp"
+
+namespace acs {
+
+// LDS scratch every body may use (bytes).
+constexpr int kBodySmem = 40 * 1024;
+
+__device__ inline void piece_range(uint32_t n, uint32_t piece, uint32_t np, uint32_t &lo, uint32_t &hi)
+{
+    uint32_t per = (n + np - 1) / np;
+    per = (per + 255u) & ~255u;
+    lo = piece * per;
+    hi = lo + per < n ? lo + per : n;
+    if (lo > n) lo = n;
+}
+
+// ---------------------------------------------------------------------------
+// no-op with an optional busy wait on the constant wall clock
+// ---------------------------------------------------------------------------
+__device__ inline void body_nop(const acs_args_nop &a)
+{
+    // every wave waits on its own (uniform loop, no lane divergence);
+    // wall_clock64 runs at 100 MHz: 10 ns per tick
+    if (a.spin_ns != 0) {
+        const uint64_t t0 = wall_clock64(), ticks = a.spin_ns / 10;
+        while (wall_clock64() - t0 < ticks) __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// tiny random stream
+// ---------------------------------------------------------------------------
+__device__ inline void body_scale(const acs_args_scale &a, uint32_t piece, uint32_t np)
+{
+    uint32_t lo, hi;
+    piece_range(a.n, piece, np, lo, hi);
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += ACS_BLOCK) a.out[i] = a.a * a.x[i];
+}
+
+__device__ inline void body_axpy(const acs_args_axpy &a, uint32_t piece, uint32_t np)
+{
+    uint32_t lo, hi;
+    piece_range(a.n, piece, np, lo, hi);
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += ACS_BLOCK) a.out[i] = fmaf(a.a, a.x[i], a.y[i]);
+}
+
+__device__ inline float sum_leaf(const acs_args_sum &a, uint32_t g)
+{
+    const uint32_t l0 = a.len[0], l1 = a.nin > 1 ? a.len[1] : 0, l2 = a.nin > 2 ? a.len[2] : 0;
+    if (g < l0) return a.in[0][g];
+    g -= l0;
+    if (g < l1) return a.in[1][g];
+    g -= l1;
+    if (g < l2) return a.in[2][g];
+    return 0.0f;
+}
+
+constexpr uint32_t kSumMax = 256 * 64;
+
+// Pairwise tree over the zero-padded concatenation (length P, a power of two).
+// For the levels s >= 256 the pairs (i, i+s) share i mod 256, so thread t runs
+// those levels in registers over its leaves t + 256m; the last eight levels
+// run across threads in LDS.  Same additions, same order, as the definition.
+__device__ inline void body_sum(const acs_args_sum &a, float *red)
+{
+    const uint32_t t = threadIdx.x;
+    uint32_t T = a.len[0] + (a.nin > 1 ? a.len[1] : 0) + (a.nin > 2 ? a.len[2] : 0);
+    uint32_t P = 1;
+    while (P < T) P <<= 1;
+    uint32_t level;
+    if (P >= 256) {
+        const uint32_t M = P / 256;
+        float v[64];
+#pragma unroll
+        for (int m = 0; m < 64; m++) v[m] = ((uint32_t)m < M) ? sum_leaf(a, t + 256u * m) : 0.0f;
+#pragma unroll
+        for (int s = 32; s >= 1; s >>= 1) {
+            if ((uint32_t)s < M) {
+#pragma unroll
+                for (int m = 0; m < s; m++) v[m] = v[m] + v[m + s];
+            }
+        }
+        red[t] = v[0];
+        level = 128;
+    } else {
+        red[t] = (t < P) ? sum_leaf(a, t) : 0.0f;
+        level = P / 2;
+    }
+    __syncthreads();
+    for (uint32_t s = level; s >= 1; s >>= 1) {
+        if (t < s) red[t] = red[t] + red[t + s];
+        __syncthreads();
+    }
+    if (t == 0) *a.out = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// rigid-body RL step
+// ---------------------------------------------------------------------------
+struct RLView {
+    float4 *X, *V, *P, *Q0, *Q1;
+    int32_t *deg, *adj_off, *adj, *label, *perm, *inv_perm, *isl_off, *padj_off, *padj;
+};
+
+__device__ inline RLView rl_view(uint64_t base, int32_t n)
+{
+    uint64_t off[ACS_RL_NREGIONS];
+    rl_offsets(n, off);
+    char *b = reinterpret_cast<char *>(base);
+    RLView v;
+    v.X = reinterpret_cast<float4 *>(b + off[ACS_RL_X]);
+    v.V = reinterpret_cast<float4 *>(b + off[ACS_RL_V]);
+    v.P = reinterpret_cast<float4 *>(b + off[ACS_RL_P]);
+    v.Q0 = reinterpret_cast<float4 *>(b + off[ACS_RL_Q0]);
+    v.Q1 = reinterpret_cast<float4 *>(b + off[ACS_RL_Q1]);
+    v.deg = reinterpret_cast<int32_t *>(b + off[ACS_RL_DEG]);
+    v.adj_off = reinterpret_cast<int32_t *>(b + off[ACS_RL_ADJ_OFF]);
+    v.adj = reinterpret_cast<int32_t *>(b + off[ACS_RL_ADJ]);
+    v.label = reinterpret_cast<int32_t *>(b + off[ACS_RL_LABEL]);
+    v.perm = reinterpret_cast<int32_t *>(b + off[ACS_RL_PERM]);
+    v.inv_perm = reinterpret_cast<int32_t *>(b + off[ACS_RL_INV_PERM]);
+    v.isl_off = reinterpret_cast<int32_t *>(b + off[ACS_RL_ISL_OFF]);
+    v.padj_off = reinterpret_cast<int32_t *>(b + off[ACS_RL_PADJ_OFF]);
+    v.padj = reinterpret_cast<int32_t *>(b + off[ACS_RL_PADJ]);
+    return v;
+}
+
+__device__ inline float dist2(float dx, float dy, float dz) { return fmaf(dz, dz, fmaf(dy, dy, dx * dx)); }
+
+// Exclusive scan of data[0..n) in place (n <= 4 * 256 * 4); returns the total.
+// Thread t scans a contiguous chunk sequentially, then the chunk totals are
+// scanned across threads.  Integer only, so the order does not matter for
+// the result.
+__device__ inline int32_t block_exclusive_scan(int32_t *data, int32_t n, int32_t *tmp)
+{
+    const int32_t t = threadIdx.x;
+    const int32_t per = (n + ACS_BLOCK - 1) / ACS_BLOCK;
+    const int32_t lo = t * per, hi = lo + per < n ? lo + per : n;
+    int32_t s = 0;
+    for (int32_t i = lo; i < hi; i++) s += data[i];
+    tmp[t] = s;
+    __syncthreads();
+    for (int32_t d = 1; d < ACS_BLOCK; d <<= 1) {
+        int32_t v = (t >= d) ? tmp[t - d] : 0;
+        __syncthreads();
+        tmp[t] += v;
+        __syncthreads();
+    }
+    int32_t run = (t > 0) ? tmp[t - 1] : 0;
+    const int32_t total = tmp[ACS_BLOCK - 1];
+    for (int32_t i = lo; i < hi; i++) {
+        int32_t x = data[i];
+        data[i] = run;
+        run += x;
+    }
+    __syncthreads();
+    return total;
+}
+
+__device__ inline void body_rl_predict(const acs_args_rl &a, uint32_t piece, uint32_t np)
+{
+    RLView v = rl_view(a.base, a.n);
+    uint32_t lo, hi;
+    piece_range((uint32_t)a.n, piece, np, lo, hi);
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += ACS_BLOCK) {
+        float4 x = v.X[i], u = v.V[i], p;
+        p.x = fmaf(a.dt, u.x, x.x);
+        p.y = fmaf(a.dt, u.y, x.y);
+        p.z = fmaf(a.dt, u.z, x.z);
+        p.w = fmaf(a.dt, u.w, x.w);
+        v.P[i] = p;
+    }
+}
+
+// Contacts of every body, adjacency in ascending partner order (CSR).
+__device__ inline void body_rl_broadphase(const acs_args_rl &a, uint8_t *smem)
+{
+    const int32_t n = a.n, t = threadIdx.x;
+    RLView v = rl_view(a.base, n);
+    float4 *Ps = reinterpret_cast<float4 *>(smem);                 // 16 n bytes
+    int32_t *cnt = reinterpret_cast<int32_t *>(smem + 16 * n);     // 4 n bytes
+    int32_t *tmp = cnt + n;                                        // 256 ints
+    for (int32_t i = t; i < n; i += ACS_BLOCK) Ps[i] = v.P[i];
+    __syncthreads();
+    const float two_r = 2.0f * a.r, thr = two_r * two_r;
+    for (int32_t i = t; i < n; i += ACS_BLOCK) {
+        const float4 pi = Ps[i];
+        int32_t c = 0;
+        for (int32_t j = 0; j < n; j++) {
+            const float4 pj = Ps[j];
+            c += (j != i && dist2(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z) < thr) ? 1 : 0;
+        }
+        cnt[i] = c;
+        v.deg[i] = c;
+    }
+    __syncthreads();
+    const int32_t total = block_exclusive_scan(cnt, n, tmp);
+    for (int32_t i = t; i < n; i += ACS_BLOCK) {
+        v.adj_off[i] = cnt[i];
+        const float4 pi = Ps[i];
+        int32_t k = cnt[i];
+        for (int32_t j = 0; j < n; j++) {
+            const float4 pj = Ps[j];
+            if (j != i && dist2(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z) < thr) v.adj[k++] = j;
+        }
+    }
+    if (t == 0) v.adj_off[n] = total;
+}
+
+// Connected components by min-label propagation (the fixpoint labels every
+// body with the smallest body of its component), then islands ordered by that
+// smallest body, bodies inside an island in index order, the adjacency in
+// permuted positions, and the plan of multi-body islands for the host.
+__device__ inline void body_rl_islands(const acs_args_rl &a, uint8_t *smem)
+{
+    const int32_t n = a.n, t = threadIdx.x;
+    RLView v = rl_view(a.base, n);
+    int32_t *plan = reinterpret_cast<int32_t *>(a.plan);
+    int32_t *lab = reinterpret_cast<int32_t *>(smem);   // n
+    int32_t *aoff = lab + n;                            // n + 1
+    int32_t *ridx = aoff + n + 1;                       // n: island index of each root
+    int32_t *sz = ridx + n;                             // n + 1: island sizes -> offsets
+    int32_t *perm = sz + n + 1;                         // n
+    int32_t *inv = perm + n;                            // n
+    int32_t *poff = inv + n;                            // n + 1
+    int32_t *tmp = poff + n + 1;                        // 256
+
+    // offsets are clamped to the adjacency capacity so that a corrupt input
+    // can never index outside the arena
+    const int32_t cap = n * (n - 1);
+    for (int32_t i = t; i <= n; i += ACS_BLOCK) {
+        const int32_t o = v.adj_off[i];
+        aoff[i] = o < 0 ? 0 : (o > cap ? cap : o);
+    }
+    for (int32_t i = t; i < n; i += ACS_BLOCK) lab[i] = i;
+    __syncthreads();
+    for (;;) {
+        int changed = 0;
+        for (int32_t i = t; i < n; i += ACS_BLOCK) {
+            int32_t m = __hip_atomic_load(&lab[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const int32_t own = m;
+            for (int32_t k = aoff[i]; k < aoff[i + 1]; k++) {
+                const int32_t c = v.adj[k];
+                if ((uint32_t)c >= (uint32_t)n) continue;   // never true for broadphase output
+                int32_t l = __hip_atomic_load(&lab[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                m = l < m ? l : m;
+            }
+            if (m < own) {
+                __hip_atomic_store(&lab[i], m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                changed = 1;
+            }
+        }
+        if (!__syncthreads_or(changed)) break;
+    }
+    // island index of each root (roots in ascending order)
+    for (int32_t i = t; i < n; i += ACS_BLOCK) ridx[i] = (lab[i] == i) ? 1 : 0;
+    __syncthreads();
+    const int32_t nisl = block_exclusive_scan(ridx, n, tmp);
+    for (int32_t k = t; k <= n; k += ACS_BLOCK) sz[k] = 0;
+    __syncthreads();
+    for (int32_t i = t; i < n; i += ACS_BLOCK) atomicAdd(&sz[ridx[lab[i]]], 1);
+    __syncthreads();
+    block_exclusive_scan(sz, nisl, tmp);
+    if (t == 0) sz[nisl] = n;
+    __syncthreads();
+    for (int32_t k = t; k <= nisl; k += ACS_BLOCK) v.isl_off[k] = sz[k];
+    // position of each body: island start + members before it
+    for (int32_t i = t; i < n; i += ACS_BLOCK) {
+        const int32_t root = lab[i];
+        int32_t rank = 0;
+        for (int32_t j = root; j < i; j++) rank += (lab[j] == root) ? 1 : 0;
+        const int32_t pos = sz[ridx[root]] + rank;
+        perm[pos] = i;
+        inv[i] = pos;
+        v.label[i] = root;
+        v.perm[pos] = i;
+        v.inv_perm[i] = pos;
+    }
+    __syncthreads();
+    for (int32_t p = t; p < n; p += ACS_BLOCK) {
+        const int32_t d = aoff[perm[p] + 1] - aoff[perm[p]];
+        poff[p] = d > 0 ? d : 0;
+    }
+    __syncthreads();
+    const int32_t E = block_exclusive_scan(poff, n, tmp);
+    if (t == 0) poff[n] = E;
+    __syncthreads();
+    for (int32_t p = t; p <= n; p += ACS_BLOCK) v.padj_off[p] = poff[p];
+    for (int32_t p = t; p < n; p += ACS_BLOCK) {
+        const int32_t b = perm[p], k0 = aoff[b], d = aoff[b + 1] - k0, o = poff[p];
+        for (int32_t k = 0; k < d; k++) {
+            const int32_t c = v.adj[k0 + k];
+            if (o + k < cap) v.padj[o + k] = ((uint32_t)c < (uint32_t)n) ? inv[c] : p;
+        }
+    }
+    // plan: multi-body islands in island order (reuse ridx as flags)
+    __syncthreads();
+    for (int32_t k = t; k < nisl; k += ACS_BLOCK) ridx[k] = (sz[k + 1] - sz[k] >= 2) ? 1 : 0;
+    __syncthreads();
+    const int32_t nmulti = block_exclusive_scan(ridx, nisl, tmp);
+    for (int32_t k = t; k < nisl; k += ACS_BLOCK) {
+        if (sz[k + 1] - sz[k] >= 2) {
+            const int32_t m = ridx[k];
+            plan[4 + 4 * m + 0] = sz[k];
+            plan[4 + 4 * m + 1] = sz[k + 1];
+            plan[4 + 4 * m + 2] = poff[sz[k]];
+            plan[4 + 4 * m + 3] = poff[sz[k + 1]];
+        }
+    }
+    if (t == 0) {
+        plan[0] = nisl;
+        plan[1] = nmulti;
+        plan[2] = E;
+        plan[3] = 0;
+    }
+}
+
+__device__ inline void body_rl_permute(const acs_args_rl &a, uint32_t piece, uint32_t np)
+{
+    RLView v = rl_view(a.base, a.n);
+    uint32_t lo, hi;
+    piece_range((uint32_t)a.n, piece, np, lo, hi);
+    for (uint32_t p = lo + threadIdx.x; p < hi; p += ACS_BLOCK) {
+        const uint32_t b = (uint32_t)v.perm[p];
+        v.Q0[p] = v.P[b < (uint32_t)a.n ? b : p];
+    }
+}
+
+// One Jacobi iteration over the island's positions [b0, b1).
+__device__ inline void body_rl_jacobi(const acs_args_rl &a)
+{
+    RLView v = rl_view(a.base, a.n);
+    const float4 *src = (a.iter % 2 == 0) ? v.Q0 : v.Q1;
+    float4 *dst = (a.iter % 2 == 0) ? v.Q1 : v.Q0;
+    const float two_r = 2.0f * a.r;
+    for (int32_t p = a.b0 + (int32_t)threadIdx.x; p < a.b1; p += ACS_BLOCK) {
+        const float4 qp = src[p];
+        float ax = 0.0f, ay = 0.0f, az = 0.0f;
+        const int32_t cap = a.n * (a.n - 1);
+        int32_t e0 = v.padj_off[p], e1 = v.padj_off[p + 1];
+        e0 = e0 < 0 ? 0 : (e0 > cap ? cap : e0);
+        e1 = e1 < e0 ? e0 : (e1 > cap ? cap : e1);
+        for (int32_t e = e0; e < e1; e++) {
+            int32_t q = v.padj[e];
+            if ((uint32_t)q >= (uint32_t)a.n) q = p;   // never true for islands output
+            const float4 qq = src[q];
+            const float dx = qp.x - qq.x, dy = qp.y - qq.y, dz = qp.z - qq.z;
+            const float d = sqrtf(dist2(dx, dy, dz));
+            const float pen = two_r - d;
+            if (pen > 0.0f) {
+                const float h = 0.5f * pen;
+                float nx, ny, nz;
+                if (d > 0.0f) {
+                    nx = dx / d;
+                    ny = dy / d;
+                    nz = dz / d;
+                } else {
+                    nx = (p < q) ? 1.0f : -1.0f;
+                    ny = 0.0f;
+                    nz = 0.0f;
+                }
+                ax = fmaf(h, nx, ax);
+                ay = fmaf(h, ny, ay);
+                az = fmaf(h, nz, az);
+            }
+        }
+        const float deg = (float)(e1 - e0);
+        float4 o;
+        o.x = qp.x + ax / deg;
+        o.y = qp.y + ay / deg;
+        o.z = qp.z + az / deg;
+        o.w = qp.w;
+        dst[p] = o;
+    }
+}
+
+__device__ inline float wall(float x, float &vel, float lo, float hi)
+{
+    if (x < lo) {
+        vel = fabsf(vel);
+        return lo;
+    }
+    if (x > hi) {
+        vel = -fabsf(vel);
+        return hi;
+    }
+    return x;
+}
+
+__device__ inline void body_rl_integrate(const acs_args_rl &a, uint32_t piece, uint32_t np)
+{
+    RLView v = rl_view(a.base, a.n);
+    uint32_t lo, hi;
+    piece_range((uint32_t)a.n, piece, np, lo, hi);
+    const float wlo = a.r, whi = 1.0f - a.r;
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += ACS_BLOCK) {
+        const uint32_t ip = (uint32_t)v.inv_perm[i];
+        const float4 q = v.Q0[ip < (uint32_t)a.n ? ip : i], p = v.P[i];
+        float4 u = v.V[i], x;
+        u.x = u.x + (q.x - p.x) / a.dt;
+        u.y = u.y + (q.y - p.y) / a.dt;
+        u.z = u.z + (q.z - p.z) / a.dt;
+        x.x = wall(q.x, u.x, wlo, whi);
+        x.y = wall(q.y, u.y, wlo, whi);
+        x.z = wall(q.z, u.z, wlo, whi);
+        x.w = q.w;
+        v.X[i] = x;
+        v.V[i] = u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// dispatch by task type
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline T load_args(const void *p)
+{
+    T a;
+    __builtin_memcpy(&a, p, sizeof(T));
+    return a;
+}
+
+__device__ __forceinline__ void run_body(int32_t kid, const void *args, uint32_t piece, uint32_t np, uint8_t *smem)
+{
+    switch (kid) {
+    case ACS_K_NOP: body_nop(load_args<acs_args_nop>(args)); break;
+    case ACS_K_SCALE: body_scale(load_args<acs_args_scale>(args), piece, np); break;
+    case ACS_K_AXPY: body_axpy(load_args<acs_args_axpy>(args), piece, np); break;
+    case ACS_K_SUM: body_sum(load_args<acs_args_sum>(args), reinterpret_cast<float *>(smem)); break;
+    case ACS_K_RL_PREDICT: body_rl_predict(load_args<acs_args_rl>(args), piece, np); break;
+    case ACS_K_RL_BROADPHASE: body_rl_broadphase(load_args<acs_args_rl>(args), smem); break;
+    case ACS_K_RL_ISLANDS: body_rl_islands(load_args<acs_args_rl>(args), smem); break;
+    case ACS_K_RL_PERMUTE: body_rl_permute(load_args<acs_args_rl>(args), piece, np); break;
+    case ACS_K_RL_JACOBI: body_rl_jacobi(load_args<acs_args_rl>(args)); break;
+    case ACS_K_RL_INTEGRATE: body_rl_integrate(load_args<acs_args_rl>(args), piece, np); break;
+    default: break;
+    }
+}
+
+}  // namespace acs

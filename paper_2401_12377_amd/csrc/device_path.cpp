@@ -1,0 +1,298 @@
+// Host side of the device-resident path: descriptor ring in pinned host
+// memory, persistent kernel launch, completion counter polling.
+#include <hip/hip_runtime_api.h>
+#include <immintrin.h>
+#include <string.h>
+
+#include <algorithm>
+#include <thread>
+#include <vector>
+
+#include "dev_shared.hpp"
+#include "internal.hpp"
+#include "launch.hpp"
+
+namespace acs {
+
+namespace {
+
+int hip_fail(hipError_t e, const char *what)
+{
+    set_error(ACS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return ACS_EDEVICE;
+}
+
+uint32_t pow2_at_least(uint32_t x)
+{
+    uint32_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+class DevicePath : public Path {
+public:
+    DevicePath(int32_t W, const acs_config &cfg) : W_(W), cfg_(cfg) {}
+    ~DevicePath() override { shutdown(); }
+
+    int start() override
+    {
+        hipError_t e = hipSetDevice(cfg_.device);
+        if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+        int cus = 0, rate_khz = 0;
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg_.device);
+        (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, cfg_.device);
+        clock_khz_ = rate_khz > 0 ? rate_khz : 100000;
+        int32_t per_cu = 0;
+        if ((e = persistent_blocks_per_cu(&per_cu)) != hipSuccess) return hip_fail(e, "occupancy query");
+        const int32_t capacity = std::max(1, per_cu) * std::max(1, cus);
+        int32_t workers = cfg_.n_workers > 0 ? cfg_.n_workers : cus;
+        workers = std::min(workers, capacity - 1);
+        if (workers < 1) {
+            set_error(ACS_EDEVICE, "persistent kernel does not fit on the device");
+            return ACS_EDEVICE;
+        }
+        n_workers_ = workers;
+
+        ring_cap_ = pow2_at_least((uint32_t)std::max(16, cfg_.queue_depth));
+        if ((e = hipHostMalloc((void **)&ctrl_, sizeof(HostCtrl), hipHostMallocCoherent | hipHostMallocMapped)) != hipSuccess)
+            return hip_fail(e, "hipHostMalloc(ctrl)");
+        memset((void *)ctrl_, 0, sizeof(HostCtrl));
+        if ((e = hipHostMalloc((void **)&ring_, sizeof(DevDesc) * ring_cap_, hipHostMallocCoherent | hipHostMallocMapped)) !=
+            hipSuccess)
+            return hip_fail(e, "hipHostMalloc(ring)");
+        memset((void *)ring_, 0, sizeof(DevDesc) * ring_cap_);
+        if ((e = hipMalloc((void **)&st_, sizeof(DevState))) != hipSuccess) return hip_fail(e, "hipMalloc(state)");
+        if ((e = hipMemset(st_, 0, sizeof(DevState))) != hipSuccess) return hip_fail(e, "hipMemset(state)");
+        if (cfg_.trace) {
+            trace_cap_ = (uint32_t)cfg_.trace_capacity;
+            if ((e = hipMalloc((void **)&dtrace_, sizeof(acs_trace_rec) * trace_cap_)) != hipSuccess)
+                return hip_fail(e, "hipMalloc(trace)");
+            if ((e = hipMemset(dtrace_, 0, sizeof(acs_trace_rec) * trace_cap_)) != hipSuccess)
+                return hip_fail(e, "hipMemset(trace)");
+        }
+        if ((e = hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "hipStreamCreate");
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+
+        DevParams p;
+        memset(&p, 0, sizeof(p));
+        p.ctrl = ctrl_;
+        p.ring = ring_;
+        p.st = st_;
+        p.trace = dtrace_;
+        p.ring_mask = ring_cap_ - 1;
+        p.trace_cap = trace_cap_;
+        p.W = W_;
+        p.n_workers = n_workers_;
+        if ((e = hipEventCreate(&ev0_)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+        if ((e = hipEventCreate(&ev1_)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+        if ((e = hipEventRecord(ev0_, stream_)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        if ((e = launch_persistent(p, 1 + n_workers_, stream_)) != hipSuccess) return hip_fail(e, "persistent kernel launch");
+        if ((e = hipEventRecord(ev1_, stream_)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        running_ = true;
+        return ACS_OK;
+    }
+
+    int submit(const Desc &d) override
+    {
+        if (!running_) {
+            set_error(ACS_ESTATE, "device path is not running");
+            return ACS_ESTATE;
+        }
+        // back-pressure: the ring holds at most ring_cap_ unconsumed descriptors
+        while (submitted_ - __atomic_load_n(&ctrl_->consumed, __ATOMIC_ACQUIRE) >= ring_cap_) {
+            if (cfg_.nonblocking) {
+                set_error(ACS_EAGAIN, "input FIFO full");
+                return ACS_EAGAIN;
+            }
+            if (int rc = check_alive()) return rc;
+            _mm_pause();
+        }
+        DevDesc &r = ring_[submitted_ & (ring_cap_ - 1)];
+        DevDesc tmp;
+        memset(&tmp, 0, sizeof(tmp));
+        tmp.seq = d.seq;
+        tmp.kid = d.kid;
+        tmp.npieces = d.npieces;
+        tmp.nseg = d.nseg;
+        tmp.wbits = d.wbits;
+        for (int k = 0; k < ACS_K_MAX; k++) {
+            tmp.s[k] = d.s[k];
+            tmp.e[k] = d.e[k];
+        }
+        memcpy(tmp.args, d.args, ACS_ARGS_MAX);
+        memcpy((void *)&r, &tmp, sizeof(DevDesc));
+        submitted_++;
+        __atomic_store_n(&ctrl_->tail, submitted_, __ATOMIC_RELEASE);
+        return ACS_OK;
+    }
+
+    int sync(uint64_t timeout_ns) override
+    {
+        if (!running_) return err_;
+        const uint64_t t0 = now_ns();
+        uint32_t spins = 0;
+        while (__atomic_load_n(&ctrl_->retired, __ATOMIC_ACQUIRE) < submitted_) {
+            if (++spins % 4096 == 0) {
+                if (int rc = check_alive()) return rc;
+                if (timeout_ns && now_ns() - t0 > timeout_ns) {
+                    set_error(ACS_ETIMEDOUT, "sync timed out");
+                    return ACS_ETIMEDOUT;
+                }
+            }
+            _mm_pause();
+        }
+        if (ctrl_->error) err_ = ACS_EKERNEL;
+        return err_;
+    }
+
+    int scheduled_list(acs_entry *out, int32_t cap, int32_t *n) override
+    {
+        if (!running_) {
+            if (n) *n = 0;
+            return ACS_OK;
+        }
+        const uint64_t req = ++snap_req_;
+        __atomic_store_n(&ctrl_->snap_req, req, __ATOMIC_RELEASE);
+        const uint64_t t0 = now_ns();
+        while (__atomic_load_n(&ctrl_->snap_ack, __ATOMIC_ACQUIRE) < req) {
+            if (now_ns() - t0 > 2000000000ull) {
+                set_error(ACS_ETIMEDOUT, "no window snapshot from the device");
+                return ACS_ETIMEDOUT;
+            }
+            std::this_thread::yield();
+        }
+        const int32_t cnt = (int32_t)std::min<uint64_t>((uint64_t)ctrl_->snap_count, (uint64_t)ACS_W_MAX);
+        int32_t c = 0;
+        for (; c < cnt && c < cap; c++) out[c] = ctrl_->snap[c];
+        if (n) *n = c;
+        return ACS_OK;
+    }
+
+    int trace_read(acs_trace_rec *out, int64_t cap, int64_t *n) override
+    {
+        if (!dtrace_) {
+            if (n) *n = 0;
+            return ACS_OK;
+        }
+        const int64_t cnt = (int64_t)std::min<uint64_t>(submitted_, trace_cap_);
+        const int64_t c = std::min(cnt, cap);
+        std::vector<acs_trace_rec> tmp((size_t)c);
+        hipError_t e = hipMemcpy(tmp.data(), dtrace_, sizeof(acs_trace_rec) * (size_t)c, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy(trace)");
+        const double ns_per_tick = 1e6 / (double)clock_khz_;
+        for (int64_t i = 0; i < c; i++) {
+            acs_trace_rec r = tmp[(size_t)i];
+            if (r.t_start == INT64_MAX || r.t_end == 0) {
+                r.t_start = -1;
+                r.t_end = -1;
+            } else {
+                r.t_start = (int64_t)((double)r.t_start * ns_per_tick);
+                r.t_end = (int64_t)((double)r.t_end * ns_per_tick);
+            }
+            out[i] = r;
+        }
+        if (n) *n = c;
+        return ACS_OK;
+    }
+
+    int stop() override
+    {
+        int rc = ACS_OK;
+        if (running_) {
+            rc = sync(10ull * 1000000000ull);
+            __atomic_store_n(&ctrl_->stop, rc == ACS_OK ? 1ull : 2ull, __ATOMIC_RELEASE);
+            if (!wait_exit(10ull * 1000000000ull)) {
+                __atomic_store_n(&ctrl_->stop, 2ull, __ATOMIC_RELEASE);
+                if (!wait_exit(10ull * 1000000000ull)) {
+                    // the kernel did not leave: keep its memory rather than free it under a running kernel
+                    set_error(ACS_EDEVICE, "persistent kernel did not exit");
+                    running_ = false;
+                    leaked_ = true;
+                    return ACS_EDEVICE;
+                }
+            }
+            checks_ = ctrl_->checks;
+            running_ = false;
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, ev0_, ev1_) == hipSuccess) kernel_ns_ = (uint64_t)((double)ms * 1e6);
+        }
+        return rc;
+    }
+
+    int shutdown() override
+    {
+        const int rc = stop();
+        if (leaked_) return rc;
+        if (stream_) {
+            (void)hipStreamDestroy(stream_);
+            stream_ = nullptr;
+        }
+        if (ev0_) (void)hipEventDestroy(ev0_);
+        if (ev1_) (void)hipEventDestroy(ev1_);
+        ev0_ = ev1_ = nullptr;
+        if (st_) (void)hipFree(st_);
+        if (dtrace_) (void)hipFree(dtrace_);
+        if (ring_) (void)hipHostFree((void *)ring_);
+        if (ctrl_) (void)hipHostFree((void *)ctrl_);
+        st_ = nullptr;
+        dtrace_ = nullptr;
+        ring_ = nullptr;
+        ctrl_ = nullptr;
+        return rc;
+    }
+
+    void stats(acs_stats &s) override
+    {
+        s.retired = ctrl_ ? ctrl_->retired : submitted_;
+        s.dispatched = s.retired;
+        s.overlap_tests = running_ && ctrl_ ? ctrl_->checks : checks_;
+        s.n_workers = n_workers_;
+        s.kernel_ns = kernel_ns_;
+    }
+
+private:
+    // A persistent kernel that left early (fault or abort) can no longer
+    // retire anything: report it instead of spinning forever.
+    int check_alive()
+    {
+        const hipError_t q = hipStreamQuery(stream_);
+        if (q == hipErrorNotReady) return ACS_OK;
+        running_ = false;
+        err_ = ACS_EDEVICE;
+        if (q != hipSuccess) return hip_fail(q, "persistent kernel");
+        set_error(ACS_EDEVICE, "persistent kernel exited");
+        return ACS_EDEVICE;
+    }
+    bool wait_exit(uint64_t timeout_ns)
+    {
+        const uint64_t t0 = now_ns();
+        for (;;) {
+            const hipError_t q = hipStreamQuery(stream_);
+            if (q != hipErrorNotReady) return true;
+            if (now_ns() - t0 > timeout_ns) return false;
+            std::this_thread::yield();
+        }
+    }
+
+    int32_t W_;
+    acs_config cfg_;
+    HostCtrl *ctrl_ = nullptr;
+    DevDesc *ring_ = nullptr;
+    DevState *st_ = nullptr;
+    acs_trace_rec *dtrace_ = nullptr;
+    hipStream_t stream_ = nullptr;
+    hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
+    uint64_t kernel_ns_ = 0;
+    uint32_t ring_cap_ = 0, trace_cap_ = 0;
+    int32_t n_workers_ = 0;
+    int clock_khz_ = 100000;
+    uint64_t submitted_ = 0, snap_req_ = 0, checks_ = 0;
+    int err_ = ACS_OK;
+    bool running_ = false, leaked_ = false;
+};
+
+}  // namespace
+
+std::unique_ptr<Path> make_device_path(int32_t W, const acs_config &cfg) { return std::make_unique<DevicePath>(W, cfg); }
+
+}  // namespace acs

@@ -1,0 +1,97 @@
+// Device code: standalone task kernels (in-order and plain paths) and the
+// persistent scheduler kernel (device-resident path; its waves are in
+// persistent.hpp).
+#include <hip/hip_runtime.h>
+
+#include "bodies.hpp"
+#include "dev_shared.hpp"
+#include "launch.hpp"
+#include "persistent.hpp"
+
+namespace acs {
+
+// ---------------------------------------------------------------------------
+// standalone kernels (one per task type)
+// ---------------------------------------------------------------------------
+template <int KID>
+constexpr int smem_bytes()
+{
+    return (KID == ACS_K_SUM) ? 1024 : (KID == ACS_K_RL_BROADPHASE || KID == ACS_K_RL_ISLANDS) ? kBodySmem : 16;
+}
+
+template <int KID, typename A>
+__global__ __launch_bounds__(ACS_BLOCK) void k_task(A a, uint32_t npieces)
+{
+    __shared__ __align__(16) uint8_t smem[smem_bytes<KID>()];
+    run_body(KID, &a, blockIdx.x, npieces, smem);
+}
+
+static const void *const k_table[ACS_K_COUNT] = {
+    reinterpret_cast<const void *>(&k_task<ACS_K_NOP, acs_args_nop>),
+    reinterpret_cast<const void *>(&k_task<ACS_K_SCALE, acs_args_scale>),
+    reinterpret_cast<const void *>(&k_task<ACS_K_AXPY, acs_args_axpy>),
+    reinterpret_cast<const void *>(&k_task<ACS_K_SUM, acs_args_sum>),
+    nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+    reinterpret_cast<const void *>(&k_task<ACS_K_RL_PREDICT, acs_args_rl>),
+    reinterpret_cast<const void *>(&k_task<ACS_K_RL_BROADPHASE, acs_args_rl>),
+    reinterpret_cast<const void *>(&k_task<ACS_K_RL_ISLANDS, acs_args_rl>),
+    reinterpret_cast<const void *>(&k_task<ACS_K_RL_PERMUTE, acs_args_rl>),
+    reinterpret_cast<const void *>(&k_task<ACS_K_RL_JACOBI, acs_args_rl>),
+    reinterpret_cast<const void *>(&k_task<ACS_K_RL_INTEGRATE, acs_args_rl>),
+};
+
+hipError_t launch_task(int32_t kid, const void *args, uint32_t npieces, hipStream_t stream)
+{
+    if (kid < 0 || kid >= ACS_K_COUNT || k_table[kid] == nullptr || npieces == 0) return hipErrorInvalidValue;
+    void *argv[2] = {const_cast<void *>(args), &npieces};
+    return hipLaunchKernel(k_table[kid], dim3(npieces), dim3(ACS_BLOCK), argv, 0, stream);
+}
+
+__global__ __launch_bounds__(ACS_BLOCK) void k_persistent(DevParams p)
+{
+    __shared__ __align__(16) uint8_t smem[kBodySmem];
+    __shared__ Mail mail;
+    if (blockIdx.x == 0) {
+        FetchShared *fs = reinterpret_cast<FetchShared *>(smem);
+        if (threadIdx.x == 0) {
+            fs->tail = 0;
+            fs->head = 0;
+            fs->stop = 0;
+            fs->exit = 0;
+            fs->snap_req = 0;
+        }
+        __syncthreads();
+        const uint32_t wave = uni32(threadIdx.x) >> 6;   // uniform: whole waves take each branch
+        if (wave == 0)
+            window_wave(p, fs);
+        else if (wave == 1)
+            fifo_wave(p, fs);
+        return;
+    }
+    worker(p, smem, &mail);
+}
+
+hipError_t launch_persistent(const DevParams &p, int32_t grid, hipStream_t stream)
+{
+    DevParams copy = p;
+    void *argv[1] = {&copy};
+    return hipLaunchKernel(reinterpret_cast<const void *>(&k_persistent), dim3(grid), dim3(ACS_BLOCK), argv, 0, stream);
+}
+
+hipError_t persistent_blocks_per_cu(int32_t *blocks)
+{
+    int b = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, reinterpret_cast<const void *>(&k_persistent), ACS_BLOCK, 0);
+    *blocks = b;
+    return e;
+}
+
+hipError_t persistent_lds_bytes(int32_t *bytes)
+{
+    hipFuncAttributes a;
+    hipError_t e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(&k_persistent));
+    *bytes = (int32_t)a.sharedSizeBytes;
+    return e;
+}
+
+}  // namespace acs

@@ -1,0 +1,25 @@
+// Host-callable entry points of the HIP translation unit (kernels.hip).
+#pragma once
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#include "dev_shared.hpp"
+
+namespace acs {
+
+// Launches the standalone kernel of task `kid` with `npieces` workgroups of
+// 256 threads on `stream`.  `args` points at the task's argument struct.
+hipError_t launch_task(int32_t kid, const void *args, uint32_t npieces, hipStream_t stream);
+
+// Launches the persistent scheduler kernel: workgroup 0 holds the window,
+// workgroups 1 .. grid-1 are workers.
+hipError_t launch_persistent(const DevParams &p, int32_t grid, hipStream_t stream);
+
+// Workgroups of the persistent kernel that fit on one compute unit.
+hipError_t persistent_blocks_per_cu(int32_t *blocks);
+
+// Static LDS of one persistent-kernel workgroup.
+hipError_t persistent_lds_bytes(int32_t *bytes);
+
+}  // namespace acs

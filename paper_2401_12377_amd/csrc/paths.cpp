@@ -1,0 +1,446 @@
+// Manual, in-order and plain (host window + HIP stream pool) paths.
+#include <hip/hip_runtime_api.h>
+#include <immintrin.h>
+
+#include <chrono>
+#include <thread>
+#include <vector>
+
+#include "internal.hpp"
+#include "launch.hpp"
+#include "window.hpp"
+
+namespace acs {
+
+uint64_t now_ns()
+{
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+namespace {
+
+int hip_fail(hipError_t e, const char *what)
+{
+    set_error(ACS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return ACS_EDEVICE;
+}
+
+// ---------------------------------------------------------------------------
+// manual path: window only; the caller plays the executor
+// ---------------------------------------------------------------------------
+class ManualPath : public Path {
+public:
+    ManualPath(int32_t W, const acs_config &cfg)
+        : win_(W, (size_t)cfg.queue_depth, cfg.trace != 0, (size_t)cfg.trace_capacity)
+    {
+    }
+    int submit(const Desc &d) override
+    {
+        if (win_.fifo_full()) {
+            win_.admit();
+            if (win_.fifo_full()) {
+                set_error(ACS_EAGAIN, "input FIFO full; complete kernels first");
+                return ACS_EAGAIN;
+            }
+        }
+        win_.fifo_push(d);
+        pump();
+        return ACS_OK;
+    }
+    int sync(uint64_t) override
+    {
+        pump();
+        if (!win_.drained()) {
+            set_error(ACS_ETIMEDOUT, "manual window still holds kernels");
+            return ACS_ETIMEDOUT;
+        }
+        return win_.first_error() ? ACS_EKERNEL : ACS_OK;
+    }
+    int take_ready(uint64_t *seqs, int32_t cap, int32_t *n) override
+    {
+        pump();
+        int32_t slots[ACS_W_MAX];
+        const int32_t k = win_.ready_slots(slots, ACS_W_MAX);
+        int32_t c = 0;
+        for (int32_t q = 0; q < k && c < cap; q++) {
+            win_.mark_executing(slots[q]);
+            seqs[c++] = win_.slot_desc(slots[q]).seq;
+        }
+        if (n) *n = c;
+        return ACS_OK;
+    }
+    int complete(uint64_t seq, int32_t status) override
+    {
+        const int32_t s = win_.slot_of(seq);
+        if (s < 0 || !((win_.executing() >> s) & 1ull)) {
+            set_error(ACS_EINVAL, "kernel is not executing");
+            return ACS_EINVAL;
+        }
+        win_.retire(s, status);
+        pump();
+        return ACS_OK;
+    }
+    int scheduled_list(acs_entry *out, int32_t cap, int32_t *n) override { return win_.scheduled_list(out, cap, n); }
+    int trace_read(acs_trace_rec *out, int64_t cap, int64_t *n) override
+    {
+        const auto &t = win_.trace();
+        int64_t c = 0;
+        for (; c < (int64_t)t.size() && c < cap; c++) out[c] = t[c];
+        if (n) *n = c;
+        return ACS_OK;
+    }
+    void stats(acs_stats &s) override
+    {
+        s.retired = win_.retired();
+        s.dispatched = win_.dispatched();
+        s.overlap_tests = win_.overlap_tests();
+        s.poisoned = win_.poisoned_count();
+    }
+
+private:
+    // poisoned kernels that become ready are retired without running
+    void pump()
+    {
+        for (;;) {
+            win_.admit();
+            int32_t slots[ACS_W_MAX];
+            const int32_t k = win_.ready_slots(slots, ACS_W_MAX);
+            bool any = false;
+            for (int32_t q = 0; q < k; q++)
+                if (win_.poisoned(slots[q])) {
+                    win_.mark_executing(slots[q]);
+                    win_.retire(slots[q], 0);
+                    any = true;
+                }
+            if (!any) break;
+        }
+    }
+    HostWindow win_;
+};
+
+// ---------------------------------------------------------------------------
+// in-order path: the single-stream baseline, no window
+// ---------------------------------------------------------------------------
+class InorderPath : public Path {
+public:
+    explicit InorderPath(const acs_config &cfg) : cfg_(cfg) {}
+    ~InorderPath() override { shutdown(); }
+    int start() override
+    {
+        hipError_t e = hipSetDevice(cfg_.device);
+        if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+        e = hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+        if (cfg_.trace) {
+            e = hipEventCreate(&base_);
+            if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+            e = hipEventRecord(base_, stream_);
+            if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        }
+        return ACS_OK;
+    }
+    int submit(const Desc &d) override
+    {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        const bool tr = cfg_.trace && d.seq < (uint64_t)cfg_.trace_capacity;
+        if (tr) {
+            (void)hipEventCreate(&e0);
+            (void)hipEventCreate(&e1);
+            (void)hipEventRecord(e0, stream_);
+        }
+        hipError_t e = launch_task(d.kid, d.args, d.npieces, stream_);
+        if (e != hipSuccess) {
+            if (!err_) err_ = ACS_EDEVICE;
+            return hip_fail(e, "kernel launch");
+        }
+        if (tr) {
+            (void)hipEventRecord(e1, stream_);
+            pending_.push_back({d.seq, d.kid, e0, e1});
+        }
+        submitted_++;
+        return ACS_OK;
+    }
+    int sync(uint64_t timeout_ns) override
+    {
+        if (!stream_) return err_;
+        const uint64_t t0 = now_ns();
+        for (;;) {
+            hipError_t q = hipStreamQuery(stream_);
+            if (q == hipSuccess) break;
+            if (q != hipErrorNotReady) {
+                err_ = ACS_EDEVICE;
+                return hip_fail(q, "stream");
+            }
+            if (timeout_ns && now_ns() - t0 > timeout_ns) {
+                set_error(ACS_ETIMEDOUT, "sync timed out");
+                return ACS_ETIMEDOUT;
+            }
+            _mm_pause();
+        }
+        retired_ = submitted_;
+        resolve_trace();
+        return err_;
+    }
+    int scheduled_list(acs_entry *, int32_t, int32_t *n) override
+    {
+        if (n) *n = 0;
+        return ACS_OK;
+    }
+    int trace_read(acs_trace_rec *out, int64_t cap, int64_t *n) override
+    {
+        int64_t c = 0;
+        for (; c < (int64_t)trace_.size() && c < cap; c++) out[c] = trace_[c];
+        if (n) *n = c;
+        return ACS_OK;
+    }
+    int shutdown() override
+    {
+        if (stream_) {
+            (void)hipStreamSynchronize(stream_);
+            resolve_trace();
+            (void)hipStreamDestroy(stream_);
+            stream_ = nullptr;
+        }
+        if (base_) {
+            (void)hipEventDestroy(base_);
+            base_ = nullptr;
+        }
+        return ACS_OK;
+    }
+    void stats(acs_stats &s) override
+    {
+        s.retired = retired_;
+        s.dispatched = submitted_;
+    }
+
+private:
+    struct Pend {
+        uint64_t seq;
+        int32_t kid;
+        hipEvent_t e0, e1;
+    };
+    void resolve_trace()
+    {
+        for (auto &p : pending_) {
+            float a = 0, b = 0;
+            (void)hipEventElapsedTime(&a, base_, p.e0);
+            (void)hipEventElapsedTime(&b, base_, p.e1);
+            if (trace_.size() <= p.seq) trace_.resize(p.seq + 1);
+            acs_trace_rec &r = trace_[p.seq];
+            r.seq = (int64_t)p.seq;
+            r.slot = 0;
+            r.kernel_id = p.kid;
+            r.ev_insert = 3 * (int64_t)p.seq;
+            r.ev_dispatch = 3 * (int64_t)p.seq + 1;
+            r.ev_retire = 3 * (int64_t)p.seq + 2;
+            r.valid_mask = 0;
+            r.up_mask = 0;
+            r.t_start = (int64_t)((double)a * 1e6);
+            r.t_end = (int64_t)((double)b * 1e6);
+            (void)hipEventDestroy(p.e0);
+            (void)hipEventDestroy(p.e1);
+        }
+        pending_.clear();
+    }
+    acs_config cfg_;
+    hipStream_t stream_ = nullptr;
+    hipEvent_t base_ = nullptr;
+    uint64_t submitted_ = 0, retired_ = 0;
+    int err_ = ACS_OK;
+    std::vector<Pend> pending_;
+    std::vector<acs_trace_rec> trace_;
+};
+
+// ---------------------------------------------------------------------------
+// plain path: host window, ready kernels launched into a pool of streams
+// (one kernel per stream at a time), completions seen through events
+// ---------------------------------------------------------------------------
+class PlainPath : public Path {
+public:
+    PlainPath(int32_t W, const acs_config &cfg)
+        : cfg_(cfg), win_(W, (size_t)cfg.queue_depth, cfg.trace != 0, (size_t)cfg.trace_capacity)
+    {
+    }
+    ~PlainPath() override { shutdown(); }
+    int start() override
+    {
+        hipError_t e = hipSetDevice(cfg_.device);
+        if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+        const int S = cfg_.n_streams;
+        streams_.assign(S, nullptr);
+        done_.assign(S, nullptr);
+        begin_.assign(S, nullptr);
+        busy_.assign(S, -1);
+        const unsigned flags = cfg_.trace ? hipEventDefault : hipEventDisableTiming;
+        for (int s = 0; s < S; s++) {
+            if ((e = hipStreamCreateWithFlags(&streams_[s], hipStreamNonBlocking)) != hipSuccess)
+                return hip_fail(e, "hipStreamCreate");
+            if ((e = hipEventCreateWithFlags(&done_[s], flags)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+            if (cfg_.trace && (e = hipEventCreate(&begin_[s])) != hipSuccess) return hip_fail(e, "hipEventCreate");
+        }
+        if (cfg_.trace) {
+            if ((e = hipEventCreate(&base_)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+            if ((e = hipEventRecord(base_, streams_[0])) != hipSuccess) return hip_fail(e, "hipEventRecord");
+            (void)hipEventSynchronize(base_);
+        }
+        started_ = true;
+        return ACS_OK;
+    }
+    int submit(const Desc &d) override
+    {
+        while (win_.fifo_full()) {
+            if (cfg_.nonblocking) {
+                progress();
+                if (win_.fifo_full()) {
+                    set_error(ACS_EAGAIN, "input FIFO full");
+                    return ACS_EAGAIN;
+                }
+                break;
+            }
+            progress();
+            _mm_pause();
+        }
+        win_.fifo_push(d);
+        progress();
+        return ACS_OK;
+    }
+    int sync(uint64_t timeout_ns) override
+    {
+        const uint64_t t0 = now_ns();
+        while (!win_.drained()) {
+            progress();
+            if (win_.drained()) break;
+            if (timeout_ns && now_ns() - t0 > timeout_ns) {
+                set_error(ACS_ETIMEDOUT, "sync timed out");
+                return ACS_ETIMEDOUT;
+            }
+            _mm_pause();
+        }
+        if (dev_err_) return dev_err_;
+        return win_.first_error() ? ACS_EKERNEL : ACS_OK;
+    }
+    int scheduled_list(acs_entry *out, int32_t cap, int32_t *n) override { return win_.scheduled_list(out, cap, n); }
+    int trace_read(acs_trace_rec *out, int64_t cap, int64_t *n) override
+    {
+        const auto &t = win_.trace();
+        int64_t c = 0;
+        for (; c < (int64_t)t.size() && c < cap; c++) out[c] = t[c];
+        if (n) *n = c;
+        return ACS_OK;
+    }
+    int shutdown() override
+    {
+        if (!started_) return ACS_OK;
+        sync(0);
+        for (size_t s = 0; s < streams_.size(); s++) {
+            if (streams_[s]) (void)hipStreamDestroy(streams_[s]);
+            if (done_[s]) (void)hipEventDestroy(done_[s]);
+            if (begin_[s]) (void)hipEventDestroy(begin_[s]);
+        }
+        if (base_) (void)hipEventDestroy(base_);
+        streams_.clear();
+        base_ = nullptr;
+        started_ = false;
+        return ACS_OK;
+    }
+    void stats(acs_stats &s) override
+    {
+        s.retired = win_.retired();
+        s.dispatched = win_.dispatched();
+        s.overlap_tests = win_.overlap_tests();
+        s.poisoned = win_.poisoned_count();
+        s.n_streams = (int32_t)streams_.size();
+    }
+
+private:
+    // One pass of the window module and the scheduler module: retire what
+    // finished, admit from the FIFO, launch ready kernels into free streams.
+    void progress()
+    {
+        for (size_t s = 0; s < streams_.size(); s++) {
+            if (busy_[s] < 0) continue;
+            const hipError_t q = hipEventQuery(done_[s]);
+            if (q == hipErrorNotReady) continue;
+            int64_t ta = -1, tb = -1;
+            if (cfg_.trace) {
+                float a = 0, b = 0;
+                (void)hipEventElapsedTime(&a, base_, begin_[s]);
+                (void)hipEventElapsedTime(&b, base_, done_[s]);
+                ta = (int64_t)((double)a * 1e6);
+                tb = (int64_t)((double)b * 1e6);
+            }
+            int32_t status = 0;
+            if (q != hipSuccess) {
+                status = ACS_EDEVICE;
+                if (!dev_err_) dev_err_ = ACS_EDEVICE;
+                hip_fail(q, "kernel");
+            }
+            win_.retire(busy_[s], status, ta, tb);
+            busy_[s] = -1;
+        }
+        win_.admit();
+        int32_t ready[ACS_W_MAX];
+        for (;;) {
+            const int32_t k = win_.ready_slots(ready, ACS_W_MAX);
+            if (k == 0) break;
+            bool launched_any = false;
+            for (int32_t q = 0; q < k; q++) {
+                const int32_t slot = ready[q];
+                if (win_.poisoned(slot)) {
+                    win_.mark_executing(slot);
+                    win_.retire(slot, 0);
+                    launched_any = true;
+                    continue;
+                }
+                int32_t s = free_stream();
+                if (s < 0) return;
+                const Desc &d = win_.slot_desc(slot);
+                if (cfg_.trace) (void)hipEventRecord(begin_[s], streams_[s]);
+                hipError_t e = launch_task(d.kid, d.args, d.npieces, streams_[s]);
+                win_.mark_executing(slot);
+                if (e != hipSuccess) {
+                    hip_fail(e, "kernel launch");
+                    if (!dev_err_) dev_err_ = ACS_EDEVICE;
+                    win_.retire(slot, ACS_EDEVICE);
+                    continue;
+                }
+                (void)hipEventRecord(done_[s], streams_[s]);
+                busy_[s] = slot;
+                launched_any = true;
+            }
+            if (!launched_any) break;
+            win_.admit();
+        }
+    }
+    int32_t free_stream()
+    {
+        const int32_t S = (int32_t)streams_.size();
+        for (int32_t k = 0; k < S; k++) {
+            const int32_t s = (rr_ + k) % S;
+            if (busy_[s] < 0) {
+                rr_ = (s + 1) % S;
+                return s;
+            }
+        }
+        return -1;
+    }
+    acs_config cfg_;
+    HostWindow win_;
+    std::vector<hipStream_t> streams_;
+    std::vector<hipEvent_t> done_, begin_;
+    std::vector<int32_t> busy_;
+    hipEvent_t base_ = nullptr;
+    int32_t rr_ = 0;
+    int dev_err_ = ACS_OK;
+    bool started_ = false;
+};
+
+}  // namespace
+
+std::unique_ptr<Path> make_manual_path(int32_t W, const acs_config &cfg) { return std::make_unique<ManualPath>(W, cfg); }
+std::unique_ptr<Path> make_inorder_path(const acs_config &cfg) { return std::make_unique<InorderPath>(cfg); }
+std::unique_ptr<Path> make_plain_path(int32_t W, const acs_config &cfg) { return std::make_unique<PlainPath>(W, cfg); }
+
+}  // namespace acs

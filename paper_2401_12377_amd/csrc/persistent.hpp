@@ -1,0 +1,400 @@
+// Wave-level building blocks of the persistent scheduler kernel (device code).
+//
+// Workgroup 0 is the window:
+//   wave 0  the window module.  Lane i owns window slot i: its read/write
+//           ranges, its upstream bitmask and its completion target live in
+//           that lane's registers.  Inserting a kernel is one pass in which
+//           every lane tests the new kernel's ranges against its own slot
+//           (Algorithm 1, both directions) and a ballot gives the new
+//           kernel's upstream mask.  Completions are seen by polling the
+//           per-slot completion counters; a ballot of finished slots clears
+//           those bits in every lane's mask at once.  The ready mask is a
+//           ballot of (valid, not executing, empty upstream mask); ready
+//           kernels are published, oldest first, as (slot, piece) entries of a
+//           work queue in device memory.
+//   wave 1  the input FIFO: copies descriptors from the host-resident ring
+//           into a small ring in LDS, so that host-memory latency never
+//           stalls the window loop.
+// Workgroups 1.. are workers: each takes a ticket from the work queue, waits
+// for the entry with that ticket, runs one piece of the task body, and bumps
+// the slot's completion counter with release semantics.
+//
+// Only HIP device built-ins are used here, so the same source also builds
+// for the host against an emulation of those built-ins (a CPU build used by
+// the tests to run the scheduler logic without a GPU).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bodies.hpp"
+#include "dev_shared.hpp"
+
+namespace acs {
+
+constexpr uint32_t kLdsRing = 16;   // descriptors staged in LDS
+
+struct FetchShared {
+    uint32_t tail;       // descriptors staged (written by the FIFO wave)
+    uint32_t head;       // descriptors taken (written by the window wave)
+    uint32_t stop;       // mirror of the host stop flag
+    uint32_t exit;       // window wave -> FIFO wave: leave
+    uint64_t snap_req;   // mirror of the host snapshot request counter
+    uint64_t pad;
+    DevDesc ring[kLdsRing];
+};
+static_assert(sizeof(FetchShared) <= kBodySmem, "FIFO staging must fit the LDS scratch");
+
+struct Mail {
+    uint32_t slot, piece;
+    int32_t kid;
+    uint32_t np;
+    uint64_t seq;
+    uint64_t t0;
+    uint8_t args[ACS_ARGS_MAX];
+};
+
+#define LDS_LOAD(p) __hip_atomic_load((p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
+#define LDS_STORE(p, v) __hip_atomic_store((p), (v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
+
+// A value every lane of the wave must agree on is taken from the first lane,
+// so control flow that depends on it is uniform by construction.
+__device__ inline uint32_t uni32(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ inline uint64_t uni64(uint64_t x)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    uint64_t consumed = 0, htail = 0;
+    uint32_t ftail = 0;
+    for (;;) {
+        if (uni32(LDS_LOAD(&fs->exit))) break;
+        const uint32_t head = uni32(LDS_LOAD(&fs->head));
+        const uint32_t space = kLdsRing - (ftail - head);
+        bool moved = false;
+        if (space > 0) {
+            if (consumed == htail) {
+                htail = uni64(__hip_atomic_load(&p.ctrl->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
+                if (htail != consumed) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+            }
+            const uint64_t avail = htail - consumed;
+            const uint32_t n = avail < space ? (uint32_t)avail : space;
+            if (n > 0) {
+                // 16 bytes per lane per row, up to 4 rows (16 descriptors).  Rows
+                // past the end re-read the last published descriptor (always
+                // valid memory) and are not stored.
+                uint4 v[4];
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    uint32_t off = (r * 64u + lane) * 16u;
+                    if (off >= n * 256u) off = (n - 1) * 256u + (off % 256u);
+                    const uint32_t d = off / 256u, w = off % 256u;
+                    const char *src = reinterpret_cast<const char *>(&p.ring[(consumed + d) & p.ring_mask]) + w;
+                    v[r] = *reinterpret_cast<const uint4 *>(src);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const uint32_t off = (r * 64u + lane) * 16u;
+                    if (off < n * 256u) {
+                        const uint32_t d = off / 256u, w = off % 256u;
+                        char *dst = reinterpret_cast<char *>(&fs->ring[(ftail + d) % kLdsRing]) + w;
+                        *reinterpret_cast<uint4 *>(dst) = v[r];
+                    }
+                }
+                // every lane's part of the copy lands before lane 0 publishes it
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                ftail += n;
+                consumed += n;
+                if (lane == 0) {
+                    LDS_STORE(&fs->tail, ftail);
+                    __hip_atomic_store(&p.ctrl->consumed, consumed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                }
+                moved = true;
+            }
+        }
+        if (!moved) {
+            const uint64_t st = uni64(__hip_atomic_load(&p.ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
+            const uint64_t sr = uni64(__hip_atomic_load(&p.ctrl->snap_req, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
+            if (lane == 0) {
+                LDS_STORE(&fs->stop, (uint32_t)st);
+                LDS_STORE(&fs->snap_req, sr);
+            }
+            if (st == 2) break;   // host abort: leave even if the window wave is gone
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+}
+
+__device__ inline uint64_t readlane64(uint64_t x, int l)
+{
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(x >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline void window_wave(const DevParams &p, FetchShared *fs)
+{
+    const uint32_t lane = threadIdx.x;
+    const int W = p.W;
+    const uint64_t full = (W >= 64) ? ~0ull : ((1ull << W) - 1ull);
+    const bool tr = p.trace != nullptr;
+    const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+    // this lane's slot
+    uint64_t ss[kSegs], se[kSegs];
+#pragma unroll
+    for (int m = 0; m < kSegs; m++) ss[m] = se[m] = 0;
+    uint32_t sw = 0, target = 0, mynp = 0;
+    int32_t mykid = 0;
+    uint64_t up = 0, myseq = 0;
+
+    // wave-uniform state
+    uint64_t valid = 0, exec = 0, retired = 0, pub = 0, ev = 0, snap_seen = 0, checks = 0;
+    uint32_t head = 0;
+
+    if (lane == 0) __hip_atomic_store(&p.ctrl->alive, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+
+    for (uint32_t iter = 1;; iter++) {
+        bool progress = false;
+        if ((iter & 4095u) == 0 && uni32(LDS_LOAD(&fs->stop)) == 2u) break;   // abort is honoured even while busy
+
+        // ---- completions: clear finished slots from every upstream mask
+        if (exec) {
+            const bool mine = (exec >> lane) & 1ull;
+            const uint32_t c = mine ? __hip_atomic_load(&p.st->cnt[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+            const uint64_t done = __ballot(mine && c == target);
+            if (done) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                if (tr && ((done >> lane) & 1ull) && myseq < p.trace_cap)
+                    p.trace[myseq].ev_retire = (int64_t)(ev + __builtin_popcountll(done & lane_lt));
+                ev += __builtin_popcountll(done);
+                retired += __builtin_popcountll(done);
+                up &= ~done;
+                valid &= ~done;
+                exec &= ~done;
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+                if (lane == 0)
+                    __hip_atomic_store(&p.ctrl->retired, retired, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                progress = true;
+            }
+        }
+
+        // ---- admission in program order while a slot is free
+        const uint32_t ftail = uni32(LDS_LOAD(&fs->tail));
+        if (head != ftail && valid != full) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            while (head != ftail && valid != full) {
+                const DevDesc *d = &fs->ring[head % kLdsRing];
+                const int slot = __builtin_ctzll(~valid);
+                const uint32_t nseg = d->nseg < (uint32_t)kSegs ? d->nseg : (uint32_t)kSegs, wb = d->wbits;
+                bool conf = false;
+                if ((valid >> lane) & 1ull) {
+                    for (uint32_t k = 0; k < nseg; k++) {
+                        const uint64_t a0 = d->s[k], a1 = d->e[k];
+                        const bool wk = (wb >> k) & 1u;
+#pragma unroll
+                        for (int m = 0; m < kSegs; m++)
+                            conf |= (a0 < se[m]) & (a1 > ss[m]) & (wk | (((sw >> m) & 1u) != 0));
+                    }
+                }
+                checks += (uint64_t)__builtin_popcountll(valid) * nseg * kSegs;
+                const uint64_t upm = __ballot(conf);
+                const uint64_t seq = d->seq;
+                if ((int)lane == slot) {
+#pragma unroll
+                    for (int m = 0; m < kSegs; m++) {
+                        ss[m] = d->s[m];
+                        se[m] = d->e[m];
+                    }
+                    sw = wb;
+                    up = upm;
+                    myseq = seq;
+                    mykid = d->kid;
+                    mynp = d->npieces < kMaxPieces ? d->npieces : kMaxPieces;
+                    target += mynp;
+                }
+                TaskEntry *te = &p.st->task[slot];
+                if (lane < 16) reinterpret_cast<uint32_t *>(te->args)[lane] = reinterpret_cast<const uint32_t *>(d->args)[lane];
+                if (lane == 16) te->kid = d->kid;
+                if (lane == 17) te->npieces = d->npieces < kMaxPieces ? d->npieces : kMaxPieces;
+                if (lane == 18) te->seq = seq;
+                if (tr && lane == 0 && seq < p.trace_cap) {
+                    acs_trace_rec *r = &p.trace[seq];
+                    r->seq = (int64_t)seq;
+                    r->slot = slot;
+                    r->kernel_id = d->kid;
+                    r->ev_insert = (int64_t)ev;
+                    r->ev_dispatch = -1;
+                    r->ev_retire = -1;
+                    r->valid_mask = valid;
+                    r->up_mask = upm;
+                    r->t_start = INT64_MAX;
+                    r->t_end = 0;
+                }
+                ev++;
+                valid |= 1ull << slot;
+                head++;
+                progress = true;
+            }
+            // all lanes are done reading the staged descriptors before their
+            // LDS slots are handed back to the FIFO wave
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (lane == 0) LDS_STORE(&fs->head, head);
+        }
+
+        // ---- dispatch every ready kernel, oldest first
+        const bool rdy = (((valid & ~exec) >> lane) & 1ull) && up == 0;
+        const uint64_t ready = __ballot(rdy);
+        if (ready) {
+            // task-table entries written by other lanes are published before
+            // any work-queue entry that points at them
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            uint32_t before = 0, rank = 0, total = 0;
+            for (uint64_t m = ready; m; m &= m - 1) {
+                const int l = __builtin_ctzll(m);
+                const uint64_t sl = readlane64(myseq, l);
+                const uint32_t npl = __builtin_amdgcn_readlane(mynp, l);
+                if (sl < myseq) {
+                    before += npl;
+                    rank++;
+                }
+                total += npl;
+            }
+            if (rdy) {
+                for (uint32_t q = 0; q < mynp; q++) {
+                    const uint64_t t = pub + before + q;
+                    const uint64_t v = ((uint64_t)(uint32_t)(t + 1) << 32) | ((uint64_t)lane << 24) | q;
+                    __hip_atomic_store(&p.st->ent[t & (kQueueCap - 1)], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                if (tr && myseq < p.trace_cap) p.trace[myseq].ev_dispatch = (int64_t)(ev + rank);
+            }
+            pub += total;
+            ev += __builtin_popcountll(ready);
+            exec |= ready;
+            progress = true;
+        }
+
+        if (!progress) {
+            // snapshot of the window for the host (the scheduled list)
+            const uint64_t sr = uni64(LDS_LOAD(&fs->snap_req));
+            if (sr != snap_seen) {
+                const bool v = (valid >> lane) & 1ull;
+                uint32_t rank = 0;
+                for (uint64_t m = valid; m; m &= m - 1) {
+                    const int l = __builtin_ctzll(m);
+                    rank += (readlane64(myseq, l) < myseq) ? 1u : 0u;
+                }
+                if (v) {
+                    acs_entry e;
+                    e.seq = myseq;
+                    e.kernel_id = mykid;
+                    e.state = ((exec >> lane) & 1ull) ? ACS_EXECUTING : (up == 0 ? ACS_READY : ACS_PENDING);
+                    e.upstream_mask = up;
+                    e.slot = (int32_t)lane;
+                    e.reserved = 0;
+                    p.ctrl->snap[rank] = e;
+                }
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+                if (lane == 0) {
+                    __hip_atomic_store(&p.ctrl->snap_count, (uint64_t)__builtin_popcountll(valid), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_SYSTEM);
+                    __hip_atomic_store(&p.ctrl->snap_ack, sr, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+                }
+                snap_seen = sr;
+            }
+            const uint32_t st = uni32(LDS_LOAD(&fs->stop));
+            if (st == 2u || (st == 1u && valid == 0 && head == uni32(LDS_LOAD(&fs->tail)))) break;
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+
+    // leave: stop the FIFO wave and give every worker an exit entry
+    if (lane == 0) LDS_STORE(&fs->exit, 1u);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    for (uint32_t i = lane; i < (uint32_t)p.n_workers; i += 64) {
+        const uint64_t t = pub + i;
+        const uint64_t v = ((uint64_t)(uint32_t)(t + 1) << 32) | ((uint64_t)kSentinelSlot << 24);
+        __hip_atomic_store(&p.st->ent[t & (kQueueCap - 1)], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (lane == 0) {
+        __hip_atomic_store(&p.ctrl->checks, checks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&p.ctrl->exited, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+__device__ inline void worker(const DevParams &p, uint8_t *smem, Mail *mail)
+{
+    // Control flow here is uniform across each wave by construction: wave 0
+    // (selected through readfirstlane, so the compiler sees a uniform branch)
+    // claims tickets and reports completions with all 64 lanes active, only
+    // lane 0 contributing a non-zero increment, and every value that decides
+    // a branch is taken from the first lane.  A lane-divergent region next to
+    // the workgroup barriers of this loop can be compiled into a loop that
+    // re-enters the barrier without the lanes of that region, which never
+    // terminates.
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    const bool wave0 = uni32(tid) < 64u;
+    const bool tr = p.trace != nullptr;
+    uint64_t *margs = reinterpret_cast<uint64_t *>(mail->args);
+    for (;;) {
+        if (wave0) {
+            const uint64_t t = uni64(__hip_atomic_fetch_add(&p.st->deq, lane == 0 ? 1ull : 0ull, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT));
+            const uint32_t tag = (uint32_t)(t + 1);
+            uint64_t v;
+            for (uint32_t spin = 1;; spin++) {
+                v = uni64(__hip_atomic_load(&p.st->ent[t & (kQueueCap - 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                if ((uint32_t)(v >> 32) == tag) break;
+                // a host abort releases waiting workers even if the window wave has left
+                if ((spin & 1023u) == 0 &&
+                    uni64(__hip_atomic_load(&p.ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) == 2ull) {
+                    v = (uint64_t)kSentinelSlot << 24;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            const uint32_t slot = (uint32_t)(v >> 24) & 0xFFu;
+            // all lanes store the same values: no lane-divergent branch needed
+            mail->slot = slot;
+            mail->piece = (uint32_t)v & 0xFFFFFFu;
+            if (slot != kSentinelSlot) {
+                const TaskEntry *te = &p.st->task[slot];
+                mail->kid = te->kid;
+                mail->np = te->npieces;
+                mail->seq = te->seq;
+                margs[lane & 7u] = reinterpret_cast<const uint64_t *>(te->args)[lane & 7u];
+                if (tr) mail->t0 = wall_clock64();
+            }
+        }
+        __syncthreads();
+        const uint32_t slot = uni32(mail->slot);
+        if (slot == kSentinelSlot) break;
+        run_body((int32_t)uni32((uint32_t)mail->kid), mail->args, uni32(mail->piece), uni32(mail->np), smem);
+        // every thread publishes its own writes (system scope: some bodies
+        // write host-visible memory) before the workgroup reports completion
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+        __syncthreads();
+        if (wave0) {
+            const uint64_t seq = uni64(mail->seq);
+            if (tr && seq < p.trace_cap) {
+                // the same value from every lane: min and max are unchanged by repeats
+                atomicMin(reinterpret_cast<unsigned long long *>(&p.trace[seq].t_start), (unsigned long long)uni64(mail->t0));
+                atomicMax(reinterpret_cast<unsigned long long *>(&p.trace[seq].t_end), (unsigned long long)wall_clock64());
+            }
+            __hip_atomic_fetch_add(&p.st->cnt[slot], lane == 0 ? 1u : 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+}  // namespace acs

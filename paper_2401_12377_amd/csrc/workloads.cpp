@@ -1,0 +1,155 @@
+// Native application drivers for the synthetic workloads (acs_workloads.h).
+// They use the public API only; the range helpers below are the workload's
+// get_addresses functions (Section V-A): they state, from the launch
+// arguments, which bytes each kernel reads and writes.
+#include <hip/hip_runtime_api.h>
+
+#include <chrono>
+
+#include "acs.h"
+#include "acs_tasks.h"
+#include "acs_workloads.h"
+#include "rl_layout.hpp"
+
+namespace {
+
+double wall_ns()
+{
+    return (double)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+}  // namespace
+
+extern "C" {
+
+void *acs_host_alloc(size_t bytes)
+{
+    void *p = nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) return nullptr;
+    return p;
+}
+
+int acs_host_free(void *p)
+{
+    if (!p) return ACS_OK;
+    return hipHostFree(p) == hipSuccess ? ACS_OK : ACS_EDEVICE;
+}
+
+int acs_rl_run(acs_window *w, const acs_rl_scene *sc, int32_t steps, double *step_ns, acs_rl_counts *counts)
+{
+    if (!w || !sc || steps < 0 || sc->n < 2 || sc->n > acs::kRLMaxBodies || !sc->plan || sc->iters < 0)
+        return ACS_EINVAL;
+    uint64_t off[ACS_RL_NREGIONS];
+    acs::rl_offsets(sc->n, off);
+    const uint64_t A = sc->arena;
+    auto region = [&](int r) { return acs_seg{A + off[r], off[r + 1] - off[r]}; };
+    auto span = [&](int r0, int r1) { return acs_seg{A + off[r0], off[r1] - off[r0]}; };
+    auto vec = [&](int r, int32_t b0, int32_t b1) { return acs_seg{A + off[r] + 16ull * b0, 16ull * (uint64_t)(b1 - b0)}; };
+    auto ints = [&](int r, int32_t b0, int32_t b1) { return acs_seg{A + off[r] + 4ull * b0, 4ull * (uint64_t)(b1 - b0)}; };
+    const acs_seg plan_seg = {(uint64_t)(uintptr_t)sc->plan, 4ull * acs::rl_plan_ints(sc->n)};
+
+    acs_args_rl a = {};
+    a.base = A;
+    a.plan = (uint64_t)(uintptr_t)sc->plan;
+    a.n = sc->n;
+    a.r = sc->r;
+    a.dt = sc->dt;
+    acs_rl_counts cnt = {};
+    uint64_t &kernels = cnt.kernels;
+    int rc = ACS_OK;
+    double t_prev = wall_ns();
+#define SUBMIT(kid, R, nr, Wr, nw)                                                       \
+    do {                                                                                 \
+        rc = acs_submit(w, (kid), (R), (nr), (Wr), (nw), &a, sizeof(a), nullptr);        \
+        if (rc != ACS_OK) return rc;                                                     \
+        kernels++;                                                                       \
+    } while (0)
+
+    for (int32_t step = 0; step < steps; step++) {
+        {
+            const acs_seg r[2] = {region(ACS_RL_X), region(ACS_RL_V)};
+            const acs_seg wr[1] = {region(ACS_RL_P)};
+            SUBMIT(ACS_K_RL_PREDICT, r, 2, wr, 1);
+        }
+        {
+            const acs_seg r[1] = {region(ACS_RL_P)};
+            const acs_seg wr[1] = {span(ACS_RL_DEG, ACS_RL_LABEL)};
+            SUBMIT(ACS_K_RL_BROADPHASE, r, 1, wr, 1);
+        }
+        {
+            const acs_seg r[1] = {span(ACS_RL_DEG, ACS_RL_LABEL)};
+            const acs_seg wr[2] = {span(ACS_RL_LABEL, ACS_RL_END), plan_seg};
+            SUBMIT(ACS_K_RL_ISLANDS, r, 1, wr, 2);
+        }
+        {
+            const acs_seg r[2] = {region(ACS_RL_P), region(ACS_RL_PERM)};
+            const acs_seg wr[1] = {region(ACS_RL_Q0)};
+            SUBMIT(ACS_K_RL_PERMUTE, r, 2, wr, 1);
+        }
+        // the island list is known only now: drain, read the plan
+        rc = acs_sync(w);
+        if (rc != ACS_OK) return rc;
+        const double t_now = wall_ns();
+        if (step_ns && step > 0) step_ns[step - 1] = t_now - t_prev;
+        t_prev = t_now;
+        const int32_t *plan = (const int32_t *)sc->plan;
+        const int32_t nmulti = __atomic_load_n(&plan[1], __ATOMIC_ACQUIRE);
+        if (nmulti < 0 || nmulti > sc->n / 2) return ACS_EKERNEL;
+        cnt.steps++;
+        cnt.islands += (uint64_t)plan[0];
+        cnt.multi_islands += (uint64_t)nmulti;
+        cnt.edges += (uint64_t)plan[2];
+        for (int32_t it = 0; it < sc->iters; it++) {
+            const int src = (it % 2 == 0) ? ACS_RL_Q0 : ACS_RL_Q1, dst = (it % 2 == 0) ? ACS_RL_Q1 : ACS_RL_Q0;
+            for (int32_t k = 0; k < nmulti; k++) {
+                const int32_t b0 = plan[4 + 4 * k], b1 = plan[5 + 4 * k], e0 = plan[6 + 4 * k], e1 = plan[7 + 4 * k];
+                if (b0 < 0 || b1 > sc->n || b1 - b0 < 2 || e0 < 0 || e1 < e0 || e1 > sc->n * (sc->n - 1))
+                    return ACS_EKERNEL;   // a plan row the islands kernel cannot produce
+                a.iter = it;
+                a.b0 = b0;
+                a.b1 = b1;
+                const acs_seg r[3] = {vec(src, b0, b1), ints(ACS_RL_PADJ_OFF, b0, b1 + 1), ints(ACS_RL_PADJ, e0, e1)};
+                const acs_seg wr[1] = {vec(dst, b0, b1)};
+                SUBMIT(ACS_K_RL_JACOBI, r, 3, wr, 1);
+                cnt.jacobi_kernels++;
+                cnt.jacobi_bodies += (uint64_t)(b1 - b0);
+                cnt.jacobi_edges += (uint64_t)(e1 - e0);
+            }
+        }
+        a.iter = 0;
+        a.b0 = 0;
+        a.b1 = 0;
+        {
+            const acs_seg r[4] = {region(ACS_RL_P), region(ACS_RL_V), region(ACS_RL_Q0), region(ACS_RL_INV_PERM)};
+            const acs_seg wr[2] = {region(ACS_RL_X), region(ACS_RL_V)};
+            SUBMIT(ACS_K_RL_INTEGRATE, r, 4, wr, 2);
+        }
+    }
+#undef SUBMIT
+    rc = acs_sync(w);
+    const double t_end = wall_ns();
+    if (step_ns && steps > 0) step_ns[steps - 1] = t_end - t_prev;
+    if (counts) *counts = cnt;
+    return rc;
+}
+
+int acs_nop_run(acs_window *w, int32_t n, int32_t chain, uint64_t spin_ns, double *out_ns)
+{
+    if (!w || n < 0) return ACS_EINVAL;
+    static uint8_t dummy[1 << 16];
+    const uint64_t base = (uint64_t)(uintptr_t)dummy;
+    acs_args_nop a = {spin_ns};
+    const double t0 = wall_ns();
+    for (int32_t i = 0; i < n; i++) {
+        const acs_seg s = {chain ? base : base + (uint64_t)(i % (1 << 16)), 1};
+        const int rc = acs_submit(w, ACS_K_NOP, chain ? &s : nullptr, chain ? 1 : 0, &s, 1, &a, sizeof(a), nullptr);
+        if (rc != ACS_OK) return rc;
+    }
+    const int rc = acs_sync(w);
+    if (out_ns) *out_ns = wall_ns() - t0;
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,137 @@
+// Host emulation of the HIP device built-ins used by the scheduler's device
+// code, so that persistent.hpp and bodies.hpp build unchanged for the CPU.
+// Every GPU thread is an OS thread; a wavefront is 64 of them.  Ballot and
+// readlane are rendezvous of the 64 lanes; __syncthreads is a workgroup
+// barrier.  Atomics and fences map to sequentially consistent host atomics,
+// which is stronger than the GPU memory model (so this build checks the
+// scheduler's logic, not its GPU memory ordering).
+// Test infrastructure only: never part of libacs.
+#pragma once
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <atomic>
+#include <barrier>
+#include <thread>
+
+#define __device__
+#define __host__
+#define __global__
+#define __forceinline__ inline
+#define __launch_bounds__(x)
+#define __align__(x) alignas(x)
+
+#define __HIP_MEMORY_SCOPE_WAVEFRONT 1
+#define __HIP_MEMORY_SCOPE_WORKGROUP 2
+#define __HIP_MEMORY_SCOPE_AGENT 3
+#define __HIP_MEMORY_SCOPE_SYSTEM 4
+
+struct float4 {
+    float x, y, z, w;
+};
+struct uint4 {
+    uint32_t x, y, z, w;
+};
+
+namespace acs_sim {
+struct Dim {
+    uint32_t x, y, z;
+};
+struct Wave {
+    std::barrier<> bar{64};
+    uint64_t vals[64];
+};
+struct Group {
+    std::barrier<> *bar;
+    std::atomic<int> orflag{0};
+    Wave waves[4];
+};
+extern thread_local uint32_t tid, bid;
+extern thread_local Group *group;
+}  // namespace acs_sim
+
+#define threadIdx (acs_sim::Dim{acs_sim::tid, 0, 0})
+#define blockIdx (acs_sim::Dim{acs_sim::bid, 0, 0})
+
+#define __hip_atomic_load(p, order, scope) __atomic_load_n((p), __ATOMIC_SEQ_CST)
+#define __hip_atomic_store(p, v, order, scope) __atomic_store_n((p), (v), __ATOMIC_SEQ_CST)
+#define __hip_atomic_fetch_add(p, v, order, scope) __atomic_fetch_add((p), (v), __ATOMIC_SEQ_CST)
+
+inline void __builtin_amdgcn_fence(int, const char *) { std::atomic_thread_fence(std::memory_order_seq_cst); }
+inline void __builtin_amdgcn_s_sleep(int) { std::this_thread::yield(); }
+
+inline uint64_t wall_clock64()
+{
+    // 100 MHz ticks, like the GPU's constant clock
+    return (uint64_t)(std::chrono::duration_cast<std::chrono::nanoseconds>(
+                          std::chrono::steady_clock::now().time_since_epoch())
+                          .count() /
+                      10);
+}
+
+inline void __syncthreads() { acs_sim::group->bar->arrive_and_wait(); }
+
+inline int __syncthreads_or(int p)
+{
+    acs_sim::Group *g = acs_sim::group;
+    if (p) g->orflag.store(1);
+    g->bar->arrive_and_wait();
+    const int r = g->orflag.load();
+    g->bar->arrive_and_wait();
+    if (acs_sim::tid == 0) g->orflag.store(0);
+    g->bar->arrive_and_wait();
+    return r;
+}
+
+inline uint64_t __ballot(int pred)
+{
+    acs_sim::Wave &w = acs_sim::group->waves[acs_sim::tid / 64];
+    w.vals[acs_sim::tid % 64] = pred ? 1 : 0;
+    w.bar.arrive_and_wait();
+    uint64_t m = 0;
+    for (int l = 0; l < 64; l++)
+        if (w.vals[l]) m |= 1ull << l;
+    w.bar.arrive_and_wait();
+    return m;
+}
+
+inline uint32_t __builtin_amdgcn_readlane(uint32_t v, int l)
+{
+    acs_sim::Wave &w = acs_sim::group->waves[acs_sim::tid / 64];
+    w.vals[acs_sim::tid % 64] = v;
+    w.bar.arrive_and_wait();
+    const uint32_t r = (uint32_t)w.vals[l];
+    w.bar.arrive_and_wait();
+    return r;
+}
+
+inline void __builtin_amdgcn_wave_barrier() { acs_sim::group->waves[acs_sim::tid / 64].bar.arrive_and_wait(); }
+
+inline int __builtin_amdgcn_readfirstlane(int v)
+{
+    acs_sim::Wave &w = acs_sim::group->waves[acs_sim::tid / 64];
+    w.vals[acs_sim::tid % 64] = (uint32_t)v;
+    w.bar.arrive_and_wait();
+    const int r = (int)(uint32_t)w.vals[0];
+    w.bar.arrive_and_wait();
+    return r;
+}
+
+inline int atomicAdd(int *p, int v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
+
+inline unsigned long long atomicMin(unsigned long long *p, unsigned long long v)
+{
+    unsigned long long o = __atomic_load_n(p, __ATOMIC_SEQ_CST);
+    while (v < o && !__atomic_compare_exchange_n(p, &o, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST)) {
+    }
+    return o;
+}
+
+inline unsigned long long atomicMax(unsigned long long *p, unsigned long long v)
+{
+    unsigned long long o = __atomic_load_n(p, __ATOMIC_SEQ_CST);
+    while (v > o && !__atomic_compare_exchange_n(p, &o, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST)) {
+    }
+    return o;
+}

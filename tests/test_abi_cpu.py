@@ -1,0 +1,317 @@
+"""CPU tests of libacs: exports, argument checks, submission normalisation,
+range helpers, and the host window through the manual path (no GPU).
+
+The window's decisions are checked against the oracle: its DAG gives the
+reference ready sets and its trace checker validates every schedule.
+"""
+import itertools
+import json
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2401_12377_amd import acs, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def built():
+    if not os.path.exists(acs.LIB_PATH):
+        from paper_2401_12377_amd import build
+        build.build()
+    return acs.lib()
+
+
+def declared_functions():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if not h.endswith(".h"):
+            continue
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"\b(acs_[a-z0-9_]+)\s*\(", txt):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert len(names) >= 19
+    out = subprocess.run(["nm", "-D", "--defined-only", acs.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if " T " in l}
+    missing = names - exported
+    assert not missing, missing
+
+
+def manual(W, **kw):
+    return acs.Window(W, path="manual", **kw)
+
+
+NOP = acs.ArgsNop(0)
+
+
+def sub(win, reads, writes):
+    return win.submit(acs.K_NOP, reads, writes, NOP)
+
+
+def test_window_size_limits():
+    for bad in (0, -1, 65):
+        with pytest.raises(acs.AcsError) as e:
+            acs.Window(bad, path="manual")
+        assert e.value.code == acs.EINVAL
+    for ok in (1, 64):
+        manual(ok).destroy()
+
+
+def test_submit_argument_checks():
+    w = manual(4)
+    rc, _ = w.submit_raw(99, [], [(0, 4)], bytes(8))
+    assert rc == acs.EINVAL                         # unknown kernel id
+    rc, _ = w.submit_raw(acs.K_NOP, [], [(0, 4)], bytes(12))
+    assert rc == acs.EINVAL                         # args size mismatch
+    rc, _ = w.submit_raw(acs.K_NOP, [], [(2 ** 64 - 8, 16)], bytes(8))
+    assert rc == acs.EINVAL                         # range wraps
+    rc, _ = w.submit_raw(acs.K_NOP, [], [acs.SEG_ALL], bytes(8))
+    assert rc == acs.OK                             # the all-memory range is allowed
+    s = acs.ArgsSum()
+    s.nin = 0
+    rc, _ = w.submit_raw(acs.K_SUM, [], [(0, 4)], bytes(s))
+    assert rc == acs.EINVAL                         # sum needs 1..3 inputs
+    r = acs.ArgsRL()
+    r.n = 5000
+    rc, _ = w.submit_raw(acs.K_RL_PREDICT, [], [(0, 4)], bytes(r))
+    assert rc == acs.EINVAL                         # scene too large
+    w.destroy()
+
+
+def test_configure_rejects_bad_values():
+    for kw in (dict(n_streams=0), dict(wg_per_task=0), dict(wg_per_task=300), dict(queue_depth=0),
+               dict(trace=True, trace_capacity=0)):
+        with pytest.raises(acs.AcsError) as e:
+            acs.Window(4, path="manual", **kw)
+        assert e.value.code == acs.EINVAL
+
+
+def test_window_of_one_is_serial():
+    w = manual(1)
+    seqs = [sub(w, [], [(100 * i, 8)]) for i in range(5)]      # all independent
+    order = []
+    for _ in range(5):
+        r = w.take_ready()
+        assert len(r) == 1
+        order.append(r[0])
+        w.complete(r[0])
+    assert order == seqs
+    assert w.sync() == 0
+    w.destroy()
+
+
+def test_disjoint_kernels_all_ready():
+    w = manual(8, queue_depth=64)
+    for i in range(8):
+        sub(w, [(1000 + 16 * i, 16)], [(16 * i, 16)])
+    assert sorted(w.take_ready()) == list(range(8))
+    w.destroy()
+
+
+def test_raw_chain_is_serial():
+    w = manual(8)
+    for i in range(6):
+        sub(w, [(8 * i, 8)], [(8 * (i + 1), 8)])   # k_i reads what k_{i-1} wrote
+    for i in range(6):
+        r = w.take_ready()
+        assert r == [i]
+        w.complete(i)
+    w.destroy()
+
+
+def test_all_memory_kernel_is_a_barrier():
+    w = manual(16, queue_depth=64)
+    for i in range(3):
+        sub(w, [], [(64 * i, 8)])
+    sub(w, [acs.SEG_ALL], [acs.SEG_ALL])
+    for i in range(3):
+        sub(w, [], [(64 * i + 4096, 8)])
+    assert sorted(w.take_ready()) == [0, 1, 2]
+    for s in (0, 1, 2):
+        w.complete(s)
+    assert w.take_ready() == [3]
+    w.complete(3)
+    assert sorted(w.take_ready()) == [4, 5, 6]
+    w.destroy()
+
+
+def test_read_after_write_is_a_dependency():
+    """The case Algorithm 1 as printed misses: the newer kernel only reads
+    what the older one writes."""
+    w = manual(4)
+    sub(w, [], [(0, 64)])
+    sub(w, [(0, 64)], [(64, 64)])
+    assert w.take_ready() == [0]
+    w.complete(0)
+    assert w.take_ready() == [1]
+    w.destroy()
+
+
+def test_scheduled_list_states():
+    w = manual(4, queue_depth=16)
+    sub(w, [], [(0, 8)])
+    sub(w, [(0, 8)], [(8, 8)])
+    sub(w, [], [(100, 8)])
+    lst = w.scheduled_list()
+    assert [e[0] for e in lst] == [0, 1, 2]
+    st = {e[0]: e[2] for e in lst}
+    assert st == {0: acs.READY, 1: acs.PENDING, 2: acs.READY}
+    up = {e[0]: e[3] for e in lst}
+    slot = {e[0]: e[4] for e in lst}
+    assert up[1] == 1 << slot[0]
+    w.take_ready()
+    st = {e[0]: e[2] for e in w.scheduled_list()}
+    assert st == {0: acs.EXECUTING, 1: acs.PENDING, 2: acs.EXECUTING}
+    w.destroy()
+
+
+def reference_ready(adj, window, executing):
+    """Ready set from the oracle's DAG: in the window, not executing, no older
+    conflicting kernel still in the window."""
+    return sorted(j for j in window if j not in executing and not any(adj[i, j] for i in window if i < j))
+
+
+def drive(accs, W, pick, fifo=4096):
+    """Runs a manual window; pick(ready_running) chooses which kernel completes."""
+    adj = O.dag(accs)
+    w = manual(W, trace=True, queue_depth=fifo)
+    for a in accs:
+        w.submit(acs.K_NOP, a.reads(), a.writes(), NOP)
+    n = len(accs)
+    window, running, done = [], set(), set()
+    nxt = 0
+    while len(done) < n:
+        while nxt < n and len(window) < W:
+            window.append(nxt)
+            nxt += 1
+        want = reference_ready(adj, window, running)
+        got = sorted(w.take_ready())
+        assert got == want
+        running |= set(got)
+        j = pick(sorted(running))
+        w.complete(j)
+        running.discard(j)
+        window.remove(j)
+        done.add(j)
+    assert w.sync() == 0
+    tr = w.trace()
+    code, msg = O.check_trace(accs, W, tr)
+    w.destroy()
+    assert code == 0, msg
+    return tr
+
+
+@pytest.mark.parametrize("W", [1, 2, 3, 8, 64])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_random_completion_orders_match_oracle(W, seed):
+    st = inputs.tiny_stream(seed)
+    accs = O.tiny_accesses(st, base=1 << 32)
+    rng = np.random.default_rng(seed * 100 + W)
+    drive(accs, W, lambda run: run[int(rng.integers(len(run)))])
+
+
+def test_every_completion_order_small_stream():
+    st = inputs.tiny_stream(4, n_kernels=6)
+    accs = O.tiny_accesses(st)
+    for W in (2, 3, 6):
+        # enumerate completion choices by index into the running list
+        for choice in itertools.product(range(3), repeat=6):
+            it = iter(choice)
+            drive(accs, W, lambda run: run[next(it) % len(run)])
+
+
+def test_fifo_backpressure_in_manual_mode():
+    w = manual(2, queue_depth=2)
+    for i in range(4):
+        sub(w, [], [(0, 8)])                      # a chain through one range
+    rc, _ = w.submit_raw(acs.K_NOP, [], [(0, 8)], bytes(NOP))
+    assert rc == acs.EAGAIN
+    assert w.sync_rc() == acs.ETIMEDOUT          # nothing completes by itself in manual mode
+    for i in range(4):
+        r = w.take_ready()
+        assert r == [i]
+        w.complete(i)
+    assert w.sync() == 0
+    w.destroy()
+
+
+def test_failed_kernel_poisons_dependents_only():
+    w = manual(8, queue_depth=64)
+    a = sub(w, [], [(0, 8)])            # will fail
+    b = sub(w, [(0, 8)], [(8, 8)])      # reads a's output: poisoned
+    c = sub(w, [], [(100, 8)])          # independent
+    d = sub(w, [(8, 8)], [(200, 8)])    # depends on b: poisoned transitively
+    assert sorted(w.take_ready()) == [a, c]
+    w.complete(a, status=-6)
+    w.complete(c)
+    assert w.take_ready() == []         # b and d retire without running
+    e = sub(w, [(0, 4)], [(300, 8)])    # admitted after a retired: still sees the failure
+    f = sub(w, [], [(400, 8)])
+    assert w.take_ready() == [f]
+    w.complete(f)
+    assert w.sync_rc() == acs.EKERNEL
+    s = w.stats()
+    assert s["poisoned"] == 3 and s["retired"] == 6
+    w.destroy()
+
+
+def test_coalescing_is_conservative():
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        nr, nw = int(rng.integers(0, 12)), int(rng.integers(0, 12))
+        reads = [(int(rng.integers(0, 4000)), int(rng.integers(1, 50))) for _ in range(nr)]
+        writes = [(int(rng.integers(0, 4000)), int(rng.integers(1, 50))) for _ in range(nw)]
+        probe_r = [(int(rng.integers(0, 4000)), int(rng.integers(1, 50)))]
+        probe_w = [(int(rng.integers(0, 4000)), int(rng.integers(1, 50)))]
+        w = manual(2)
+        sub(w, reads, writes)
+        sub(w, probe_r, probe_w)
+        lst = w.scheduled_list()
+        got = lst[1][3] != 0
+        want = O.conflict(O.make_access(reads, writes), O.make_access(probe_r, probe_w))
+        if want:
+            assert got
+        if nr + nw <= acs.K_MAX:
+            assert got == want
+        w.destroy()
+
+
+def test_package_tiny_ranges_equal_oracle_ranges():
+    st = inputs.tiny_stream(7)
+    base = 1 << 36
+    ours = [acs.tiny_kernel_task(st, k, base) for k in st.kernels]
+    theirs = O.tiny_accesses(st, base=base)
+    for (kid, r, w, _), a in zip(ours, theirs):
+        assert sorted(r) == sorted(a.reads())
+        assert sorted(w) == sorted(a.writes())
+
+
+def test_gemm_ranges_match_the_paper_example():
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "get_addresses_matmul.json")))
+    for c in g["cases"]:
+        r, w = acs.gemm_segments(c["a"], c["b"], c["c"], c["m"], c["n"], c["k"], g["elem_size"])
+        assert [list(x) for x in r] == c["reads"]
+        assert [list(x) for x in w] == c["writes"]
+
+
+def test_rl_layout_is_contiguous_and_aligned():
+    for n in (2, 16, 64, 511, 1024):
+        off = acs.rl_layout(n)
+        assert np.all(off % 256 == 0) and np.all(np.diff(off) >= 0)
+        assert off[acs.RL_ADJ_OFF] - off[acs.RL_DEG] >= 4 * n
+        assert off[acs.RL_END] - off[acs.RL_PADJ] >= 4 * n * (n - 1)
+    with pytest.raises(acs.AcsError):
+        acs.rl_layout(1)
+    with pytest.raises(acs.AcsError):
+        acs.rl_layout(2000)
