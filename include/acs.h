@@ -111,6 +111,8 @@ typedef struct {
     uint64_t valid_mask;     /* slots held by older kernels when this kernel was inserted */
     uint64_t up_mask;        /* its upstream slots at insert */
     int64_t t_start, t_end;  /* execution interval, -1 if not recorded */
+    int64_t t_dispatch;      /* when the window made it runnable (device path; else -1) */
+    int64_t t_retire;        /* when the window saw it complete (device path; else -1) */
 } acs_trace_rec;
 
 typedef struct {

@@ -75,8 +75,9 @@ void or_dag(int32_t n, const or_access *acc, int32_t literal, uint8_t *adj)
                              free(adj); return (code); } while (0)
 
 int32_t or_check_trace(int32_t n, const or_access *acc, int32_t W, const or_trace_rec *tr,
-                       int32_t check_times, char *msg, int32_t msglen)
+                       int32_t check_times, int32_t early, char *msg, int32_t msglen)
 {
+    if (early) check_times = 1;
     if (msg && msglen > 0) msg[0] = 0;
     uint8_t *adj = NULL;
     if (W < 1 || W > 64) FAIL(1, "window size %d outside [1,64]", W);
@@ -117,8 +118,10 @@ int32_t or_check_trace(int32_t n, const or_access *acc, int32_t W, const or_trac
             } else if (dep && !(tr[i].ev_retire < t->ev_insert)) {
                 FAIL(12, "kernel %d depends on %d, which was neither in the window nor retired", j, i);
             }
-            if (dep && !(tr[i].ev_retire < t->ev_dispatch))
+            if (dep && !early && !(tr[i].ev_retire < t->ev_dispatch))
                 FAIL(13, "kernel %d dispatched before its upstream kernel %d retired", j, i);
+            if (dep && early && !(tr[i].ev_dispatch < t->ev_dispatch))
+                FAIL(17, "kernel %d handed out before its upstream kernel %d", j, i);
         }
         if (count > W - 1) FAIL(14, "window held %d kernels besides %d (W=%d)", count, j, W);
         if (valid != t->valid_mask)

@@ -45,12 +45,16 @@ typedef struct {
     uint64_t valid_mask;   /* slots occupied by older kernels when this one was inserted */
     uint64_t up_mask;      /* upstream slots recorded at insert */
     int64_t t_start, t_end;/* execution interval on one clock, or -1 when not recorded */
+    int64_t t_dispatch, t_retire; /* informational, not checked */
 } or_trace_rec;
 
 /* 0 when the trace is a valid schedule of the stream with window W; else a code
- * and a message. check_times != 0 also checks the execution intervals. */
+ * and a message.  check_times != 0 also checks the execution intervals.
+ * early != 0 accepts a kernel handed out before its upstream kernels retired,
+ * provided they were handed out before it and (times then required) its
+ * execution interval starts after theirs end. */
 int32_t or_check_trace(int32_t n, const or_access *acc, int32_t W, const or_trace_rec *tr,
-                       int32_t check_times, char *msg, int32_t msglen);
+                       int32_t check_times, int32_t early, char *msg, int32_t msglen);
 
 /* ---------------- tiny random stream ---------------- */
 enum { OR_OP_SCALE = 0, OR_OP_AXPY = 1, OR_OP_SUM = 2 };

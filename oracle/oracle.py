@@ -31,7 +31,8 @@ class Access(C.Structure):
 TRACE_DTYPE = np.dtype([("seq", np.int64), ("slot", np.int64), ("kid", np.int64),
                         ("ev_insert", np.int64), ("ev_dispatch", np.int64), ("ev_retire", np.int64),
                         ("valid_mask", np.uint64), ("up_mask", np.uint64),
-                        ("t_start", np.int64), ("t_end", np.int64)])
+                        ("t_start", np.int64), ("t_end", np.int64),
+                        ("t_dispatch", np.int64), ("t_retire", np.int64)])
 
 
 class TinyKernelC(C.Structure):
@@ -71,7 +72,7 @@ def lib():
         L.or_dag.argtypes = [C.c_int32, C.POINTER(Access), C.c_int32, C.c_void_p]
         L.or_dag.restype = None
         L.or_check_trace.argtypes = [C.c_int32, C.POINTER(Access), C.c_int32, C.c_void_p, C.c_int32,
-                                     C.c_char_p, C.c_int32]
+                                     C.c_int32, C.c_char_p, C.c_int32]
         L.or_check_trace.restype = C.c_int32
         L.or_tiny_access.argtypes = [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(TinyKernelC),
                                      C.POINTER(Access)]
@@ -131,12 +132,14 @@ def dag(accs, literal: bool = False) -> np.ndarray:
     return adj
 
 
-def check_trace(accs, W: int, trace: np.ndarray, check_times: bool = False):
-    """Returns (code, message); code 0 means the trace is a valid schedule."""
+def check_trace(accs, W: int, trace: np.ndarray, check_times: bool = False, early: bool = False):
+    """Returns (code, message); code 0 means the trace is a valid schedule.
+    early=True: kernels may be handed out before their upstream kernels retire
+    (they must be handed out after them and must start after they end)."""
     trace = np.ascontiguousarray(trace, dtype=TRACE_DTYPE)
     buf = C.create_string_buffer(512)
     code = lib().or_check_trace(len(accs), access_array(accs), W, trace.ctypes.data,
-                                int(check_times), buf, 512)
+                                int(check_times), int(early), buf, 512)
     return int(code), buf.value.decode()
 
 

@@ -59,7 +59,8 @@ class Entry(C.Structure):
 TRACE_DTYPE = np.dtype([("seq", np.int64), ("slot", np.int64), ("kid", np.int64),
                         ("ev_insert", np.int64), ("ev_dispatch", np.int64), ("ev_retire", np.int64),
                         ("valid_mask", np.uint64), ("up_mask", np.uint64),
-                        ("t_start", np.int64), ("t_end", np.int64)])
+                        ("t_start", np.int64), ("t_end", np.int64),
+                        ("t_dispatch", np.int64), ("t_retire", np.int64)])
 
 
 class Stats(C.Structure):

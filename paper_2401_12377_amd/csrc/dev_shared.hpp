@@ -47,14 +47,20 @@ struct HostCtrl {
 
 // What a worker needs to run one piece of a task: copied by the scheduler
 // into the slot's entry of the task table when the kernel is inserted.
+// A kernel is handed to the workers as soon as every kernel it waits for has
+// been handed out; wait_mask / wait_target then tell its workers which
+// completion counters must reach which values before the body may start.
 struct TaskEntry {
     int32_t kid;
     uint32_t npieces;
     uint64_t seq;
     uint8_t args[ACS_ARGS_MAX];
-    uint8_t pad[48];
+    uint64_t wait_mask;                   // window slots still running when dispatched
+    uint32_t pad0[2];
+    uint32_t wait_target[ACS_W_MAX];      // completion-counter value that means "done"
+    uint8_t pad[160];
 };
-static_assert(sizeof(TaskEntry) == 128, "task entry must be 128 bytes");
+static_assert(sizeof(TaskEntry) == 512, "task entry must be 512 bytes");
 
 constexpr uint32_t kQueueCap = 1u << 16;       // work queue entries (power of two)
 constexpr uint32_t kMaxPieces = 256;           // pieces per task

@@ -189,6 +189,8 @@ public:
                 r.t_start = (int64_t)((double)r.t_start * ns_per_tick);
                 r.t_end = (int64_t)((double)r.t_end * ns_per_tick);
             }
+            if (r.t_dispatch > 0) r.t_dispatch = (int64_t)((double)r.t_dispatch * ns_per_tick);
+            if (r.t_retire > 0) r.t_retire = (int64_t)((double)r.t_retire * ns_per_tick);
             out[i] = r;
         }
         if (n) *n = c;

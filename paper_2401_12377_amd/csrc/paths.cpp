@@ -239,6 +239,8 @@ private:
             r.up_mask = 0;
             r.t_start = (int64_t)((double)a * 1e6);
             r.t_end = (int64_t)((double)b * 1e6);
+            r.t_dispatch = -1;
+            r.t_retire = -1;
             (void)hipEventDestroy(p.e0);
             (void)hipEventDestroy(p.e1);
         }

@@ -154,7 +154,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
     uint64_t up = 0, myseq = 0;
 
     // wave-uniform state
-    uint64_t valid = 0, exec = 0, retired = 0, pub = 0, ev = 0, snap_seen = 0, checks = 0;
+    uint64_t valid = 0, exec = 0, retired = 0, published = 0, pub = 0, ev = 0, snap_seen = 0, checks = 0;
     uint32_t head = 0;
 
     if (lane == 0) __hip_atomic_store(&p.ctrl->alive, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -170,17 +170,18 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
             const uint64_t done = __ballot(mine && c == target);
             if (done) {
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                if (tr && ((done >> lane) & 1ull) && myseq < p.trace_cap)
-                    p.trace[myseq].ev_retire = (int64_t)(ev + __builtin_popcountll(done & lane_lt));
+                if (tr) {
+                    const uint64_t now = wall_clock64();
+                    if (((done >> lane) & 1ull) && myseq < p.trace_cap) {
+                        p.trace[myseq].ev_retire = (int64_t)(ev + __builtin_popcountll(done & lane_lt));
+                        p.trace[myseq].t_retire = (int64_t)now;
+                    }
+                }
                 ev += __builtin_popcountll(done);
                 retired += __builtin_popcountll(done);
                 up &= ~done;
                 valid &= ~done;
                 exec &= ~done;
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
-                if (lane == 0)
-                    __hip_atomic_store(&p.ctrl->retired, retired, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 progress = true;
             }
         }
@@ -236,6 +237,8 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                     r->up_mask = upm;
                     r->t_start = INT64_MAX;
                     r->t_end = 0;
+                    r->t_dispatch = -1;
+                    r->t_retire = -1;
                 }
                 ev++;
                 valid |= 1ull << slot;
@@ -249,16 +252,37 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
             if (lane == 0) LDS_STORE(&fs->head, head);
         }
 
-        // ---- dispatch every ready kernel, oldest first
-        const bool rdy = (((valid & ~exec) >> lane) & 1ull) && up == 0;
-        const uint64_t ready = __ballot(rdy);
-        if (ready) {
+        // ---- dispatch.  A kernel with an empty upstream mask is ready (it
+        // may start at once); a kernel whose upstream kernels have all been
+        // handed to the workers is dispatched as well, together with the
+        // completion-counter values its workers must see before starting, so
+        // that a dependent kernel starts without a round trip through this
+        // wave.  Rounds repeat so that a chain inside the window goes out in
+        // one pass; entries are published oldest first, so every upstream
+        // kernel's work items precede its dependents' in the queue.
+        uint64_t newly = 0;
+        for (;;) {
+            const uint64_t out = exec | newly;
+            const bool cand = (((valid & ~out) >> lane) & 1ull) && (up & ~out) == 0;
+            const uint64_t r = __ballot(cand);
+            if (!r) break;
+            newly |= r;
+        }
+        if (newly) {
+            for (uint64_t m = newly; m; m &= m - 1) {
+                const int j = __builtin_ctzll(m);
+                const uint64_t upj = readlane64(up, j);
+                TaskEntry *te = &p.st->task[j];
+                if ((upj >> lane) & 1ull) te->wait_target[lane] = target;
+                if (lane == 0) te->wait_mask = upj;
+            }
             // task-table entries written by other lanes are published before
             // any work-queue entry that points at them
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const bool mine = (newly >> lane) & 1ull;
             uint32_t before = 0, rank = 0, total = 0;
-            for (uint64_t m = ready; m; m &= m - 1) {
+            for (uint64_t m = newly; m; m &= m - 1) {
                 const int l = __builtin_ctzll(m);
                 const uint64_t sl = readlane64(myseq, l);
                 const uint32_t npl = __builtin_amdgcn_readlane(mynp, l);
@@ -268,18 +292,31 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                 }
                 total += npl;
             }
-            if (rdy) {
+            if (mine) {
                 for (uint32_t q = 0; q < mynp; q++) {
                     const uint64_t t = pub + before + q;
                     const uint64_t v = ((uint64_t)(uint32_t)(t + 1) << 32) | ((uint64_t)lane << 24) | q;
                     __hip_atomic_store(&p.st->ent[t & (kQueueCap - 1)], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
-                if (tr && myseq < p.trace_cap) p.trace[myseq].ev_dispatch = (int64_t)(ev + rank);
+                if (tr && myseq < p.trace_cap) {
+                    p.trace[myseq].ev_dispatch = (int64_t)(ev + rank);
+                    p.trace[myseq].t_dispatch = (int64_t)wall_clock64();
+                }
             }
             pub += total;
-            ev += __builtin_popcountll(ready);
-            exec |= ready;
+            ev += __builtin_popcountll(newly);
+            exec |= newly;
             progress = true;
+        }
+
+        // ---- the host learns about completions when the window drains: one
+        // system-scope release covers every result (and trace record) of the
+        // kernels retired so far
+        if (valid == 0 && retired != published) {
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+            if (lane == 0) __hip_atomic_store(&p.ctrl->retired, retired, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            published = retired;
         }
 
         if (!progress) {
@@ -296,7 +333,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                     acs_entry e;
                     e.seq = myseq;
                     e.kernel_id = mykid;
-                    e.state = ((exec >> lane) & 1ull) ? ACS_EXECUTING : (up == 0 ? ACS_READY : ACS_PENDING);
+                    e.state = up != 0 ? ACS_PENDING : (((exec >> lane) & 1ull) ? ACS_EXECUTING : ACS_READY);
                     e.upstream_mask = up;
                     e.slot = (int32_t)lane;
                     e.reserved = 0;
@@ -374,6 +411,26 @@ __device__ inline void worker(const DevParams &p, uint8_t *smem, Mail *mail)
                 mail->np = te->npieces;
                 mail->seq = te->seq;
                 margs[lane & 7u] = reinterpret_cast<const uint64_t *>(te->args)[lane & 7u];
+                // dispatched early: wait until every upstream kernel's counter
+                // has reached the value that marks it complete (lane s watches slot s)
+                const uint64_t wm = uni64(te->wait_mask);
+                if (wm != 0) {
+                    const bool watch = (wm >> lane) & 1ull;
+                    const uint32_t tgt = watch ? te->wait_target[lane] : 0u;
+                    for (uint32_t spin = 1;; spin++) {
+                        bool ok = true;
+                        if (watch) {
+                            const uint32_t c = __hip_atomic_load(&p.st->cnt[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            ok = (int32_t)(c - tgt) >= 0;
+                        }
+                        if (__ballot(!ok) == 0) break;
+                        if ((spin & 1023u) == 0 &&
+                            uni64(__hip_atomic_load(&p.ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) == 2ull)
+                            break;
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                }
                 if (tr) mail->t0 = wall_clock64();
             }
         }
@@ -381,9 +438,11 @@ __device__ inline void worker(const DevParams &p, uint8_t *smem, Mail *mail)
         const uint32_t slot = uni32(mail->slot);
         if (slot == kSentinelSlot) break;
         run_body((int32_t)uni32((uint32_t)mail->kid), mail->args, uni32(mail->piece), uni32(mail->np), smem);
-        // every thread publishes its own writes (system scope: some bodies
-        // write host-visible memory) before the workgroup reports completion
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+        // each wave waits for its own stores to complete (the workgroup
+        // barrier alone waits only for LDS traffic), then wave 0's release
+        // below makes every wave's results visible device-wide before the
+        // completion counter moves.  0x0F70: vmcnt 0, expcnt 7, lgkmcnt 15.
+        __builtin_amdgcn_s_waitcnt(0x0F70);
         __syncthreads();
         if (wave0) {
             const uint64_t seq = uni64(mail->seq);

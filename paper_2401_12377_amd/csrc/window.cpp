@@ -43,6 +43,8 @@ int HostWindow::admit()
             r.up_mask = up;
             r.t_start = -1;
             r.t_end = -1;
+            r.t_dispatch = -1;
+            r.t_retire = -1;
         }
         ev_++;
         up_[slot] = up;

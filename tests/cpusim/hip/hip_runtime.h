@@ -60,6 +60,7 @@ extern thread_local Group *group;
 
 inline void __builtin_amdgcn_fence(int, const char *) { std::atomic_thread_fence(std::memory_order_seq_cst); }
 inline void __builtin_amdgcn_s_sleep(int) { std::this_thread::yield(); }
+inline void __builtin_amdgcn_s_waitcnt(int) {}
 
 inline uint64_t wall_clock64()
 {

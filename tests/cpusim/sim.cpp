@@ -150,6 +150,8 @@ int sim_run(int32_t W, int32_t n_workers, int32_t n, const sim_desc *descs, uint
                 r.t_start *= 10;
                 r.t_end *= 10;
             }
+            if (r.t_dispatch > 0) r.t_dispatch *= 10;
+            if (r.t_retire > 0) r.t_retire *= 10;
             trace_out[i] = r;
         }
         free(tr);

@@ -20,6 +20,8 @@ def simulate(accs, W, rng, adj):
     tr["seq"] = np.arange(n)
     tr["t_start"] = -1
     tr["t_end"] = -1
+    tr["t_dispatch"] = -1
+    tr["t_retire"] = -1
     ev = 0
     window = {}          # slot -> seq
     running = set()
@@ -156,3 +158,28 @@ def test_serial_schedule_is_valid_for_any_window():
     for W in (1, 8, 64):
         code, msg = O.check_trace(accs, W, tr, check_times=True)
         assert code == 0, msg
+
+
+def test_early_dispatch_mode():
+    """Handing a kernel out before its upstream kernels retire is accepted in
+    early mode only if they were handed out first and the execution intervals
+    stay ordered; both mistakes are caught."""
+    st = inputs.tiny_stream(12)
+    accs = O.tiny_accesses(st)
+    adj = O.dag(accs)
+    tr = simulate(accs, 8, np.random.default_rng(1), adj)
+    pairs = [(i, j) for i in range(len(tr)) for j in range(i + 1, len(tr)) if adj[i, j]]
+    i, j = pairs[0]
+    code, msg = O.check_trace(accs, 8, tr, early=True)
+    assert code == 0, msg
+    # handed out before the upstream kernel: caught
+    bad = tr.copy()
+    bad[j]["ev_dispatch"] = bad[i]["ev_dispatch"] - 1
+    bad[j]["ev_insert"] = min(bad[j]["ev_insert"], bad[j]["ev_dispatch"] - 1)
+    code, msg = O.check_trace(accs, 8, bad, early=True)
+    assert code != 0
+    # execution overlap: caught (times are required in early mode)
+    ov = tr.copy()
+    ov[i]["t_end"] = ov[j]["t_start"] + 1
+    code, msg = O.check_trace(accs, 8, ov, early=True)
+    assert code == 21, msg

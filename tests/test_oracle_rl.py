@@ -197,13 +197,16 @@ def test_step_kernel_list_shape():
 
 
 def test_scene_statistics_match_the_workload_shape():
-    """64 spheres of radius 0.06: about 15 contacts and 10 multi-body islands per step."""
+    """64 spheres at the default density keep several multi-body islands (and
+    so several independent Jacobi chains) per step after the start-up overlaps
+    are resolved."""
     multis, contacts = [], []
-    for seed in range(1, 6):
+    for seed in range(1, 4):
         s = scene(seed, 64)
-        for _ in range(5):
+        for step in range(80):
             s.step()
-            multis.append(s.n_multi)
-            contacts.append(s.meta[2] // 2)
+            if step >= 40:
+                multis.append(s.n_multi)
+                contacts.append(s.meta[2] // 2)
     assert 4 <= np.mean(multis) <= 20
-    assert 5 <= np.mean(contacts) <= 30
+    assert 5 <= np.mean(contacts) <= 60
