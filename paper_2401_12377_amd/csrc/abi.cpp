@@ -33,35 +33,65 @@ struct Range {
     uint64_t s, e;
 };
 
+// A small list of ranges on the stack (submissions rarely carry more than a
+// handful); larger lists spill to the heap.
+struct RangeList {
+    Range fixed[32];
+    std::vector<Range> heap;
+    Range *v = fixed;
+    size_t n = 0, cap = 32;
+    void push(Range r)
+    {
+        if (n == cap) {
+            heap.assign(v, v + n);
+            heap.resize(cap * 2);
+            cap *= 2;
+            v = heap.data();
+        }
+        v[n++] = r;
+    }
+};
+
 // Sorts and merges overlapping or touching ranges (exact: the union is
 // unchanged), then, while more than `budget` remain, merges the neighbours
 // with the smallest gap (conservative: the union only grows).
-bool shrink(std::vector<Range> &v, size_t budget)
+bool shrink(RangeList &L, size_t budget)
 {
-    std::sort(v.begin(), v.end(), [](const Range &a, const Range &b) { return a.s < b.s || (a.s == b.s && a.e < b.e); });
-    std::vector<Range> m;
-    for (const Range &r : v) {
-        if (!m.empty() && r.s <= m.back().e)
-            m.back().e = std::max(m.back().e, r.e);
-        else
-            m.push_back(r);
+    Range *v = L.v;
+    for (size_t i = 1; i < L.n; i++) {   // insertion sort: lists are short
+        Range x = v[i];
+        size_t j = i;
+        while (j > 0 && (v[j - 1].s > x.s || (v[j - 1].s == x.s && v[j - 1].e > x.e))) {
+            v[j] = v[j - 1];
+            j--;
+        }
+        v[j] = x;
+    }
+    size_t m = 0;
+    for (size_t i = 0; i < L.n; i++) {
+        if (m > 0 && v[i].s <= v[m - 1].e) {
+            if (v[i].e > v[m - 1].e) v[m - 1].e = v[i].e;
+        } else {
+            v[m++] = v[i];
+        }
     }
     bool lossy = false;
-    while (m.size() > budget && m.size() > 1) {
+    while (m > budget && m > 1) {
         size_t best = 0;
         uint64_t gap = UINT64_MAX;
-        for (size_t i = 0; i + 1 < m.size(); i++) {
-            const uint64_t g = m[i + 1].s - m[i].e;
+        for (size_t i = 0; i + 1 < m; i++) {
+            const uint64_t g = v[i + 1].s - v[i].e;
             if (g < gap) {
                 gap = g;
                 best = i;
             }
         }
-        m[best].e = std::max(m[best].e, m[best + 1].e);
-        m.erase(m.begin() + (long)best + 1);
+        if (v[best + 1].e > v[best].e) v[best].e = v[best + 1].e;
+        for (size_t i = best + 1; i + 1 < m; i++) v[i] = v[i + 1];
+        m--;
         lossy = true;
     }
-    v.swap(m);
+    L.n = m;
     return lossy;
 }
 
@@ -168,21 +198,21 @@ int make_desc(int32_t kid, const acs_seg *r, int32_t nr, const acs_seg *w, int32
         *why = "bad segment list";
         return ACS_EINVAL;
     }
-    std::vector<Range> rr, ww;
-    auto take = [&](const acs_seg *lst, int32_t n, std::vector<Range> &dst) -> bool {
+    RangeList rr, ww;
+    auto take = [&](const acs_seg *lst, int32_t n, RangeList &dst) -> bool {
         for (int32_t i = 0; i < n; i++) {
-            const uint64_t s = lst[i].start, z = lst[i].size;
+            const uint64_t st = lst[i].start, z = lst[i].size;
             if (z == 0) continue;
             uint64_t e;
-            if (z > UINT64_MAX - s) {
-                if (s == ACS_SEG_ALL_START && z == ACS_SEG_ALL_SIZE)
+            if (z > UINT64_MAX - st) {
+                if (st == ACS_SEG_ALL_START && z == ACS_SEG_ALL_SIZE)
                     e = UINT64_MAX;
                 else
                     return false;
             } else {
-                e = s + z;
+                e = st + z;
             }
-            dst.push_back({s, e});
+            dst.push({st, e});
         }
         return true;
     };
@@ -193,29 +223,29 @@ int make_desc(int32_t kid, const acs_seg *r, int32_t nr, const acs_seg *w, int32
     bool lossy = false;
     shrink(rr, ACS_K_MAX);
     shrink(ww, ACS_K_MAX);
-    while (rr.size() + ww.size() > ACS_K_MAX) {
+    while (rr.n + ww.n > ACS_K_MAX) {
         // give the writes at least half of the budget, the reads the rest
-        const size_t wbud = std::min(ww.size(), (size_t)std::max<int>(ACS_K_MAX / 2, ACS_K_MAX - (int)rr.size()));
+        const size_t wbud = std::min(ww.n, (size_t)std::max<int>(ACS_K_MAX / 2, ACS_K_MAX - (int)rr.n));
         lossy |= shrink(ww, std::max<size_t>(1, wbud));
-        lossy |= shrink(rr, ACS_K_MAX - ww.size());
+        lossy |= shrink(rr, ACS_K_MAX - ww.n);
     }
-    out = Desc();
     out.kid = kid;
     memcpy(out.args, args, args_size);
+    if (args_size < ACS_ARGS_MAX) memset(out.args + args_size, 0, ACS_ARGS_MAX - args_size);
     out.args_size = (uint32_t)args_size;
+    out.wbits = 0;
     uint32_t k = 0;
-    for (const Range &x : rr) {
-        out.s[k] = x.s;
-        out.e[k] = x.e;
-        k++;
+    for (size_t i = 0; i < rr.n; i++, k++) {
+        out.s[k] = rr.v[i].s;
+        out.e[k] = rr.v[i].e;
     }
-    for (const Range &x : ww) {
-        out.s[k] = x.s;
-        out.e[k] = x.e;
+    for (size_t i = 0; i < ww.n; i++, k++) {
+        out.s[k] = ww.v[i].s;
+        out.e[k] = ww.v[i].e;
         out.wbits |= 1u << k;
-        k++;
     }
     out.nseg = k;
+    for (; k < ACS_K_MAX; k++) out.s[k] = out.e[k] = 0;
     uint32_t np = 1;
     if (!check_args(kid, out.args, wg_per_task, np, why)) return ACS_EINVAL;
     out.npieces = np;

@@ -141,31 +141,33 @@ __device__ inline RLView rl_view(uint64_t base, int32_t n)
 
 __device__ inline float dist2(float dx, float dy, float dz) { return fmaf(dz, dz, fmaf(dy, dy, dx * dx)); }
 
-// Exclusive scan of data[0..n) in place (n <= 4 * 256 * 4); returns the total.
-// Thread t scans a contiguous chunk sequentially, then the chunk totals are
-// scanned across threads.  Integer only, so the order does not matter for
-// the result.
+// Exclusive scan of data[0..n) in place; returns the total.  Thread t sums a
+// contiguous chunk; the 256 chunk sums are scanned inside each wave with
+// shuffles and across the four waves through tmp (4 ints).  Integer only, so
+// the grouping does not change the result.
 __device__ inline int32_t block_exclusive_scan(int32_t *data, int32_t n, int32_t *tmp)
 {
-    const int32_t t = threadIdx.x;
+    const int32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int32_t per = (n + ACS_BLOCK - 1) / ACS_BLOCK;
-    const int32_t lo = t * per, hi = lo + per < n ? lo + per : n;
+    const int32_t lo = t * per < n ? t * per : n, hi = lo + per < n ? lo + per : n;
     int32_t s = 0;
     for (int32_t i = lo; i < hi; i++) s += data[i];
-    tmp[t] = s;
-    __syncthreads();
-    for (int32_t d = 1; d < ACS_BLOCK; d <<= 1) {
-        int32_t v = (t >= d) ? tmp[t - d] : 0;
-        __syncthreads();
-        tmp[t] += v;
-        __syncthreads();
+    int32_t x = s;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t y = __shfl_up(x, (unsigned)d, 64);
+        if (lane >= d) x += y;
     }
-    int32_t run = (t > 0) ? tmp[t - 1] : 0;
-    const int32_t total = tmp[ACS_BLOCK - 1];
+    if (lane == 63) tmp[wv] = x;
+    __syncthreads();
+    int32_t woff = 0;
+    for (int k = 0; k < wv; k++) woff += tmp[k];
+    const int32_t total = tmp[0] + tmp[1] + tmp[2] + tmp[3];
+    int32_t run = woff + x - s;
     for (int32_t i = lo; i < hi; i++) {
-        int32_t x = data[i];
+        const int32_t v = data[i];
         data[i] = run;
-        run += x;
+        run += v;
     }
     __syncthreads();
     return total;
@@ -186,17 +188,60 @@ __device__ inline void body_rl_predict(const acs_args_rl &a, uint32_t piece, uin
     }
 }
 
-// Contacts of every body, adjacency in ascending partner order (CSR).
+// Contacts of every body, adjacency in ascending partner order (CSR).  With
+// n <= 128 each body's partners are split into Q = 256 / n contiguous chunks,
+// one thread per (body, chunk), so that every thread of the workgroup works;
+// chunk counts give each thread its write position, which keeps the
+// adjacency in partner order.
 __device__ inline void body_rl_broadphase(const acs_args_rl &a, uint8_t *smem)
 {
     const int32_t n = a.n, t = threadIdx.x;
     RLView v = rl_view(a.base, n);
     float4 *Ps = reinterpret_cast<float4 *>(smem);                 // 16 n bytes
-    int32_t *cnt = reinterpret_cast<int32_t *>(smem + 16 * n);     // 4 n bytes
-    int32_t *tmp = cnt + n;                                        // 256 ints
+    int32_t *cnt = reinterpret_cast<int32_t *>(smem + 16 * n);     // max(n, 256) ints
+    int32_t *deg = cnt + (n > ACS_BLOCK ? n : ACS_BLOCK);          // n ints
+    int32_t *tmp = deg + n;                                        // 4 ints
     for (int32_t i = t; i < n; i += ACS_BLOCK) Ps[i] = v.P[i];
     __syncthreads();
     const float two_r = 2.0f * a.r, thr = two_r * two_r;
+    const int32_t Q = n <= 128 ? ACS_BLOCK / n : 1;   // chunks per body
+    const int32_t chunk = (n + Q - 1) / Q;
+    if (Q > 1) {
+        // cnt[q * n + i]: contacts of body i among partners [q*chunk, (q+1)*chunk)
+        const int32_t i = t % n, q = t / n;
+        if (q < Q) {
+            const float4 pi = Ps[i];
+            const int32_t j0 = q * chunk, j1 = j0 + chunk < n ? j0 + chunk : n;
+            int32_t c = 0;
+            for (int32_t j = j0; j < j1; j++) {
+                const float4 pj = Ps[j];
+                c += (j != i && dist2(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z) < thr) ? 1 : 0;
+            }
+            cnt[q * n + i] = c;
+        }
+        __syncthreads();
+        for (int32_t b = t; b < n; b += ACS_BLOCK) {
+            int32_t d = 0;
+            for (int32_t q2 = 0; q2 < Q; q2++) d += cnt[q2 * n + b];
+            deg[b] = d;
+            v.deg[b] = d;
+        }
+        __syncthreads();
+        const int32_t total = block_exclusive_scan(deg, n, tmp);
+        if (q < Q) {
+            const float4 pi = Ps[i];
+            int32_t k = deg[i];
+            for (int32_t q2 = 0; q2 < q; q2++) k += cnt[q2 * n + i];
+            if (q == 0) v.adj_off[i] = deg[i];
+            const int32_t j0 = q * chunk, j1 = j0 + chunk < n ? j0 + chunk : n;
+            for (int32_t j = j0; j < j1; j++) {
+                const float4 pj = Ps[j];
+                if (j != i && dist2(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z) < thr) v.adj[k++] = j;
+            }
+        }
+        if (t == 0) v.adj_off[n] = total;
+        return;
+    }
     for (int32_t i = t; i < n; i += ACS_BLOCK) {
         const float4 pi = Ps[i];
         int32_t c = 0;
@@ -204,15 +249,15 @@ __device__ inline void body_rl_broadphase(const acs_args_rl &a, uint8_t *smem)
             const float4 pj = Ps[j];
             c += (j != i && dist2(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z) < thr) ? 1 : 0;
         }
-        cnt[i] = c;
+        deg[i] = c;
         v.deg[i] = c;
     }
     __syncthreads();
-    const int32_t total = block_exclusive_scan(cnt, n, tmp);
+    const int32_t total = block_exclusive_scan(deg, n, tmp);
     for (int32_t i = t; i < n; i += ACS_BLOCK) {
-        v.adj_off[i] = cnt[i];
+        v.adj_off[i] = deg[i];
         const float4 pi = Ps[i];
-        int32_t k = cnt[i];
+        int32_t k = deg[i];
         for (int32_t j = 0; j < n; j++) {
             const float4 pj = Ps[j];
             if (j != i && dist2(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z) < thr) v.adj[k++] = j;
@@ -237,7 +282,9 @@ __device__ inline void body_rl_islands(const acs_args_rl &a, uint8_t *smem)
     int32_t *perm = sz + n + 1;                         // n
     int32_t *inv = perm + n;                            // n
     int32_t *poff = inv + n;                            // n + 1
-    int32_t *tmp = poff + n + 1;                        // 256
+    int32_t *tmp = poff + n + 1;                        // 4
+    int32_t *adjs = tmp + 4;                            // adjacency copy when it fits
+    const int32_t lds_cap = (int32_t)(kBodySmem / 4) - (int32_t)(adjs - lab);
 
     // offsets are clamped to the adjacency capacity so that a corrupt input
     // can never index outside the arena
@@ -248,13 +295,22 @@ __device__ inline void body_rl_islands(const acs_args_rl &a, uint8_t *smem)
     }
     for (int32_t i = t; i < n; i += ACS_BLOCK) lab[i] = i;
     __syncthreads();
+    // one coalesced copy of the adjacency into LDS instead of dependent
+    // global loads inside the propagation loop
+    const int32_t E = aoff[n];
+    const int32_t *A = v.adj;
+    if (E <= lds_cap) {
+        for (int32_t k = t; k < E; k += ACS_BLOCK) adjs[k] = v.adj[k];
+        __syncthreads();
+        A = adjs;
+    }
     for (;;) {
         int changed = 0;
         for (int32_t i = t; i < n; i += ACS_BLOCK) {
             int32_t m = __hip_atomic_load(&lab[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             const int32_t own = m;
             for (int32_t k = aoff[i]; k < aoff[i + 1]; k++) {
-                const int32_t c = v.adj[k];
+                const int32_t c = A[k];
                 if ((uint32_t)c >= (uint32_t)n) continue;   // never true for broadphase output
                 int32_t l = __hip_atomic_load(&lab[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 m = l < m ? l : m;
@@ -296,14 +352,14 @@ __device__ inline void body_rl_islands(const acs_args_rl &a, uint8_t *smem)
         poff[p] = d > 0 ? d : 0;
     }
     __syncthreads();
-    const int32_t E = block_exclusive_scan(poff, n, tmp);
-    if (t == 0) poff[n] = E;
+    const int32_t Ep = block_exclusive_scan(poff, n, tmp);
+    if (t == 0) poff[n] = Ep;
     __syncthreads();
     for (int32_t p = t; p <= n; p += ACS_BLOCK) v.padj_off[p] = poff[p];
     for (int32_t p = t; p < n; p += ACS_BLOCK) {
         const int32_t b = perm[p], k0 = aoff[b], d = aoff[b + 1] - k0, o = poff[p];
         for (int32_t k = 0; k < d; k++) {
-            const int32_t c = v.adj[k0 + k];
+            const int32_t c = A[k0 + k];
             if (o + k < cap) v.padj[o + k] = ((uint32_t)c < (uint32_t)n) ? inv[c] : p;
         }
     }
@@ -324,7 +380,7 @@ __device__ inline void body_rl_islands(const acs_args_rl &a, uint8_t *smem)
     if (t == 0) {
         plan[0] = nisl;
         plan[1] = nmulti;
-        plan[2] = E;
+        plan[2] = Ep;
         plan[3] = 0;
     }
 }

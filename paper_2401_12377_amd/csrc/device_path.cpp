@@ -98,8 +98,13 @@ public:
             set_error(ACS_ESTATE, "device path is not running");
             return ACS_ESTATE;
         }
-        // back-pressure: the ring holds at most ring_cap_ unconsumed descriptors
-        while (submitted_ - __atomic_load_n(&ctrl_->consumed, __ATOMIC_ACQUIRE) >= ring_cap_) {
+        // back-pressure: the ring holds at most ring_cap_ unconsumed
+        // descriptors.  The device-written counter is read only when the
+        // cached value says the ring may be full (reading a line the device
+        // keeps writing costs a cross-fabric miss).
+        while (submitted_ - consumed_seen_ >= ring_cap_) {
+            consumed_seen_ = __atomic_load_n(&ctrl_->consumed, __ATOMIC_ACQUIRE);
+            if (submitted_ - consumed_seen_ < ring_cap_) break;
             if (cfg_.nonblocking) {
                 set_error(ACS_EAGAIN, "input FIFO full");
                 return ACS_EAGAIN;
@@ -288,7 +293,7 @@ private:
     uint32_t ring_cap_ = 0, trace_cap_ = 0;
     int32_t n_workers_ = 0;
     int clock_khz_ = 100000;
-    uint64_t submitted_ = 0, snap_req_ = 0, checks_ = 0;
+    uint64_t submitted_ = 0, consumed_seen_ = 0, snap_req_ = 0, checks_ = 0;
     int err_ = ACS_OK;
     bool running_ = false, leaked_ = false;
 };

@@ -431,7 +431,7 @@ __device__ inline void worker(const DevParams &p, uint8_t *smem, Mail *mail)
                     }
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 }
-                if (tr) mail->t0 = wall_clock64();
+                if (tr) mail->t0 = uni64(wall_clock64());
             }
         }
         __syncthreads();
@@ -448,8 +448,9 @@ __device__ inline void worker(const DevParams &p, uint8_t *smem, Mail *mail)
             const uint64_t seq = uni64(mail->seq);
             if (tr && seq < p.trace_cap) {
                 // the same value from every lane: min and max are unchanged by repeats
+                const uint64_t t1 = uni64(wall_clock64());
                 atomicMin(reinterpret_cast<unsigned long long *>(&p.trace[seq].t_start), (unsigned long long)uni64(mail->t0));
-                atomicMax(reinterpret_cast<unsigned long long *>(&p.trace[seq].t_end), (unsigned long long)wall_clock64());
+                atomicMax(reinterpret_cast<unsigned long long *>(&p.trace[seq].t_end), (unsigned long long)t1);
             }
             __hip_atomic_fetch_add(&p.st->cnt[slot], lane == 0 ? 1u : 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }

@@ -119,6 +119,18 @@ inline int __builtin_amdgcn_readfirstlane(int v)
     return r;
 }
 
+inline int __shfl_up(int v, unsigned d, int width)
+{
+    (void)width;
+    acs_sim::Wave &w = acs_sim::group->waves[acs_sim::tid / 64];
+    const uint32_t lane = acs_sim::tid % 64;
+    w.vals[lane] = (uint32_t)v;
+    w.bar.arrive_and_wait();
+    const int r = lane >= d ? (int)(uint32_t)w.vals[lane - d] : v;
+    w.bar.arrive_and_wait();
+    return r;
+}
+
 inline int atomicAdd(int *p, int v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
 
 inline unsigned long long atomicMin(unsigned long long *p, unsigned long long v)
