@@ -12,7 +12,10 @@ constexpr int kSegs = ACS_K_MAX;
 
 // One submitted kernel as it travels from the host to the scheduler wave.
 // Segments are stored as [start, end) with end saturated at 2^64 - 1; unused
-// entries are the empty range [0, 0), which overlaps nothing.
+// entries are the empty range [0, 0), which overlaps nothing.  The scheduler
+// copies the whole descriptor into the task table when it inserts the kernel
+// (one 4-byte store per lane); the last 40 bytes are left to the scheduler,
+// which keeps there what the workers need at dispatch.
 struct DevDesc {
     uint64_t seq;
     int32_t kid;
@@ -22,9 +25,13 @@ struct DevDesc {
     uint64_t s[kSegs];
     uint64_t e[kSegs];
     uint8_t args[ACS_ARGS_MAX];
-    uint8_t pad[40];
+    // scheduler-owned part (the host leaves it zero)
+    uint64_t wait_mask;     // window slots still running when the kernel was dispatched
+    uint32_t ptarget;       // cnt[slot] after this kernel's last piece (npieces > 1)
+    uint32_t pad[7];
 };
 static_assert(sizeof(DevDesc) == 256, "descriptor must be 256 bytes");
+constexpr uint32_t kDescCopyDwords = 54;   // dwords of DevDesc written by the host
 
 // Host-resident control block (pinned, coherent).  The first cache line is
 // written by the host, the rest by the device.
@@ -45,22 +52,19 @@ struct HostCtrl {
     acs_entry snap[ACS_W_MAX];
 };
 
-// What a worker needs to run one piece of a task: copied by the scheduler
-// into the slot's entry of the task table when the kernel is inserted.
-// A kernel is handed to the workers as soon as every kernel it waits for has
-// been handed out; wait_mask / wait_target then tell its workers which
-// completion counters must reach which values before the body may start.
-struct TaskEntry {
-    int32_t kid;
-    uint32_t npieces;
-    uint64_t seq;
-    uint8_t args[ACS_ARGS_MAX];
-    uint64_t wait_mask;                   // window slots still running when dispatched
-    uint32_t pad0[2];
-    uint32_t wait_target[ACS_W_MAX];      // completion-counter value that means "done"
-    uint8_t pad[160];
-};
-static_assert(sizeof(TaskEntry) == 512, "task entry must be 512 bytes");
+// The task table holds, per window slot, the descriptor of the kernel in
+// that slot.  A kernel is handed to the workers as soon as every kernel it
+// waits for has been handed out; wait_mask and wait_target then tell its
+// workers which completion words must reach which values before the body may
+// start.
+//
+// Completion is signalled with plain stores: the worker that finishes a
+// kernel's last piece writes seq + 1 (mod 2^32) into done[slot].  Plain
+// stores reach another XCD's polling load in a few hundred nanoseconds, an
+// atomic read-modify-write takes several times longer, so the per-slot piece
+// counter cnt[] is touched only by kernels of more than one piece, to find
+// which piece is the last.
+using TaskEntry = DevDesc;
 
 constexpr uint32_t kQueueCap = 1u << 16;       // work queue entries (power of two)
 constexpr uint32_t kMaxPieces = 256;           // pieces per task
@@ -70,9 +74,12 @@ constexpr uint32_t kSentinelSlot = 0xFF;
 struct DevState {
     uint64_t deq;                 // work-queue tickets taken by workers
     uint64_t pad0[31];
-    uint32_t cnt[ACS_W_MAX];      // per-slot completion counters (monotonic)
+    uint32_t cnt[ACS_W_MAX];      // per-slot piece counters (monotonic, multi-piece kernels only)
     uint64_t pad1[32];
+    uint32_t done[ACS_W_MAX];     // per-slot completion words: seq + 1 of the last kernel finished
+    uint64_t pad2[32];
     TaskEntry task[ACS_W_MAX];
+    uint32_t wait_target[ACS_W_MAX][ACS_W_MAX];   // [slot][upstream slot]: done[] value to wait for
     uint64_t ent[kQueueCap];      // work-queue entries: tag(32) | slot(8) | piece(24)
 };
 

@@ -32,6 +32,7 @@
 namespace acs {
 
 constexpr uint32_t kLdsRing = 16;   // descriptors staged in LDS
+constexpr uint32_t kAdmitBatch = 16; // insertions per pass of the window loop
 
 struct FetchShared {
     uint32_t tail;       // descriptors staged (written by the FIFO wave)
@@ -47,7 +48,7 @@ static_assert(sizeof(FetchShared) <= kBodySmem, "FIFO staging must fit the LDS s
 struct Mail {
     uint32_t slot, piece;
     int32_t kid;
-    uint32_t np;
+    uint32_t np, ptarget, pad;
     uint64_t seq;
     uint64_t t0;
     uint8_t args[ACS_ARGS_MAX];
@@ -130,12 +131,16 @@ __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
     }
 }
 
+// readlane returns int: every use goes through these, which zero-extend
+__device__ inline uint32_t readlane32(uint32_t x, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)x, l); }
 __device__ inline uint64_t readlane64(uint64_t x, int l)
 {
-    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, l);
-    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(x >> 32), l);
+    const uint32_t lo = readlane32((uint32_t)x, l);
+    const uint32_t hi = readlane32((uint32_t)(x >> 32), l);
     return ((uint64_t)hi << 32) | lo;
 }
+// a 64-bit field held in dwords l (low) and l + 1 (high) of a wave-wide word
+__device__ inline uint64_t readpair(uint32_t x, int l) { return ((uint64_t)readlane32(x, l + 1) << 32) | readlane32(x, l); }
 
 __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
 {
@@ -145,17 +150,36 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
     const bool tr = p.trace != nullptr;
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
-    // this lane's slot
+    // Lanes 0..W-1 own the window slots.  When the window is narrower than
+    // the wave, the slots' ranges are replicated: with Wp = W rounded up to a
+    // power of two, lane l holds the ranges of slot l mod Wp, and its replica
+    // index l / Wp selects which of the new kernel's segments it tests, so R
+    // replicas divide the pair tests of an insertion by R.
+    const uint32_t Wp = W <= 1 ? 1u : (W <= 2 ? 2u : (W <= 4 ? 4u : (W <= 8 ? 8u : (W <= 16 ? 16u : (W <= 32 ? 32u : 64u)))));
+    const uint32_t R = (64u / Wp) < (uint32_t)kSegs ? 64u / Wp : (uint32_t)kSegs;   // replicas in use
+    const uint32_t rslot = lane & (Wp - 1), rep = lane / Wp;
+    const uint64_t wpmask = Wp >= 64 ? ~0ull : ((1ull << Wp) - 1ull);
+    uint64_t repmul = 0;   // bit r * Wp set for every replica r
+    for (uint32_t r = 0; r < R; r++) repmul |= 1ull << (r * Wp);
+
+    // this lane's slot (rslot; lanes whose replica index is R or more hold nothing)
     uint64_t ss[kSegs], se[kSegs];
 #pragma unroll
     for (int m = 0; m < kSegs; m++) ss[m] = se[m] = 0;
-    uint32_t sw = 0, target = 0, mynp = 0;
+    uint32_t target = 0, mynp = 0;
     int32_t mykid = 0;
     uint64_t up = 0, myseq = 0;
 
     // wave-uniform state
     uint64_t valid = 0, exec = 0, retired = 0, published = 0, pub = 0, ev = 0, snap_seen = 0, checks = 0;
     uint32_t head = 0;
+    // wmask[m]: lanes whose slot segment m is a write.  Segments a slot does
+    // not use, and every segment of a free slot, are the empty range [0, 0),
+    // which intersects nothing, so the pair test needs no occupancy mask.
+    uint64_t wmask[kSegs];
+#pragma unroll
+    for (int m = 0; m < kSegs; m++) wmask[m] = 0;
+    uint32_t nsl = 0;   // segments of this lane's slot
 
     if (lane == 0) __hip_atomic_store(&p.ctrl->alive, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 
@@ -163,73 +187,90 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
         bool progress = false;
         if ((iter & 4095u) == 0 && uni32(LDS_LOAD(&fs->stop)) == 2u) break;   // abort is honoured even while busy
 
-        // ---- completions: clear finished slots from every upstream mask
-        if (exec) {
-            const bool mine = (exec >> lane) & 1ull;
-            const uint32_t c = mine ? __hip_atomic_load(&p.st->cnt[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
-            const uint64_t done = __ballot(mine && c == target);
-            if (done) {
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                if (tr) {
-                    const uint64_t now = wall_clock64();
-                    if (((done >> lane) & 1ull) && myseq < p.trace_cap) {
-                        p.trace[myseq].ev_retire = (int64_t)(ev + __builtin_popcountll(done & lane_lt));
-                        p.trace[myseq].t_retire = (int64_t)now;
-                    }
-                }
-                ev += __builtin_popcountll(done);
-                retired += __builtin_popcountll(done);
-                up &= ~done;
-                valid &= ~done;
-                exec &= ~done;
-                progress = true;
-            }
-        }
+        // The completion words are polled first and examined after admission,
+        // so that the load's latency overlaps the insertion work.  They are
+        // read relaxed; the acquire that pairs with the workers' releases is
+        // taken once, just before the host is told (below).
+        const bool mine = (exec >> lane) & 1ull;
+        const uint32_t cdone = mine ? __hip_atomic_load(&p.st->done[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
 
-        // ---- admission in program order while a slot is free
+        // ---- admission in program order while a slot is free, at most
+        // kAdmitBatch per pass
         const uint32_t ftail = uni32(LDS_LOAD(&fs->tail));
         if (head != ftail && valid != full) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            while (head != ftail && valid != full) {
-                const DevDesc *d = &fs->ring[head % kLdsRing];
-                const int slot = __builtin_ctzll(~valid);
-                const uint32_t nseg = d->nseg < (uint32_t)kSegs ? d->nseg : (uint32_t)kSegs, wb = d->wbits;
-                bool conf = false;
-                if ((valid >> lane) & 1ull) {
-                    for (uint32_t k = 0; k < nseg; k++) {
-                        const uint64_t a0 = d->s[k], a1 = d->e[k];
-                        const bool wk = (wb >> k) & 1u;
+            // segment positions in use by any occupied slot
+            uint32_t mtop = 0;
 #pragma unroll
-                        for (int m = 0; m < kSegs; m++)
-                            conf |= (a0 < se[m]) & (a1 > ss[m]) & (wk | (((sw >> m) & 1u) != 0));
-                    }
+            for (int m = 0; m < kSegs; m++)
+                if (__builtin_amdgcn_ballot_w64(nsl > (uint32_t)m)) mtop = m + 1;
+            for (uint32_t budget = kAdmitBatch; head != ftail && valid != full && budget > 0; budget--) {
+                const DevDesc *d = &fs->ring[head % kLdsRing];
+                // one LDS read brings the whole descriptor into the wave: lane
+                // i holds its 4-byte word i; fields are taken with readlane
+                const uint32_t dw = reinterpret_cast<const uint32_t *>(d)[lane];
+                const int slot = __builtin_ctzll(~valid);
+                const uint64_t bit = 1ull << slot;
+                const uint32_t nraw = readlane32(dw, 4);
+                const uint32_t nseg = nraw < (uint32_t)kSegs ? nraw : (uint32_t)kSegs;
+                const uint32_t wb = readlane32(dw, 5);
+                const uint64_t seq = readpair(dw, 0);
+                const int32_t kid = (int32_t)readlane32(dw, 2);
+                const uint32_t npr = readlane32(dw, 3);
+                const uint32_t np = npr < kMaxPieces ? npr : kMaxPieces;
+                // the descriptor goes to the task table as it is
+                if (lane < kDescCopyDwords) reinterpret_cast<uint32_t *>(&p.st->task[slot])[lane] = dw;
+                // Algorithm 1 in both directions: segment k of the new kernel
+                // against segment m of every occupied slot.  A new write
+                // conflicts with any intersecting segment, a new read only with
+                // an intersecting write.  Replica r takes k = r, r + R, ...;
+                // segments past nseg are the empty range and match nothing.
+                uint64_t hits = 0;
+                for (uint32_t k0 = 0; k0 < nseg; k0 += R) {
+                    const uint32_t k = k0 + rep;
+                    const bool kin = rep < R && k < nseg;
+                    const uint32_t kk = kin ? k : 0u;
+                    const uint64_t a0 = kin ? d->s[kk] : 0ull, a1 = kin ? d->e[kk] : 0ull;
+                    const bool wk = kin && ((wb >> kk) & 1u);
+#pragma unroll
+                    for (int m = 0; m < kSegs; m++)
+                        if ((uint32_t)m < mtop)
+                            hits |= __builtin_amdgcn_ballot_w64(a0 < se[m] && a1 > ss[m]) &
+                                    (__builtin_amdgcn_ballot_w64(wk) | wmask[m]);
                 }
-                checks += (uint64_t)__builtin_popcountll(valid) * nseg * kSegs;
-                const uint64_t upm = __ballot(conf);
-                const uint64_t seq = d->seq;
-                if ((int)lane == slot) {
+                // fold the replicas' lanes onto their slots; the new slot's own
+                // lanes may already hold its ranges: only occupied slots count
+                uint64_t upm = 0;
+                for (uint32_t r = 0; r < R; r++) upm |= (hits >> (r * Wp)) & wpmask;
+                upm &= valid;
+                if (rslot == (uint32_t)slot && rep < R) {
+                    // the new occupant's ranges, in every replica of its slot
 #pragma unroll
                     for (int m = 0; m < kSegs; m++) {
                         ss[m] = d->s[m];
                         se[m] = d->e[m];
                     }
-                    sw = wb;
+                    nsl = nseg;
+                }
+                checks += (uint64_t)__builtin_popcountll(valid) * nseg * mtop;
+                if ((int)lane == slot) {
                     up = upm;
                     myseq = seq;
-                    mykid = d->kid;
-                    mynp = d->npieces < kMaxPieces ? d->npieces : kMaxPieces;
-                    target += mynp;
+                    mykid = kid;
+                    mynp = np;
+                    if (np > 1) target += np;
+                    p.st->task[slot].ptarget = target;
                 }
-                TaskEntry *te = &p.st->task[slot];
-                if (lane < 16) reinterpret_cast<uint32_t *>(te->args)[lane] = reinterpret_cast<const uint32_t *>(d->args)[lane];
-                if (lane == 16) te->kid = d->kid;
-                if (lane == 17) te->npieces = d->npieces < kMaxPieces ? d->npieces : kMaxPieces;
-                if (lane == 18) te->seq = seq;
+                const uint64_t rbit = bit * repmul;
+#pragma unroll
+                for (int m = 0; m < kSegs; m++)
+                    wmask[m] = ((uint32_t)m < nseg && ((wb >> m) & 1u)) ? (wmask[m] | rbit) : (wmask[m] & ~rbit);
+                mtop = nseg > mtop ? nseg : mtop;
                 if (tr && lane == 0 && seq < p.trace_cap) {
                     acs_trace_rec *r = &p.trace[seq];
                     r->seq = (int64_t)seq;
                     r->slot = slot;
-                    r->kernel_id = d->kid;
+                    r->kernel_id = kid;
                     r->ev_insert = (int64_t)ev;
                     r->ev_dispatch = -1;
                     r->ev_retire = -1;
@@ -241,7 +282,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                     r->t_retire = -1;
                 }
                 ev++;
-                valid |= 1ull << slot;
+                valid |= bit;
                 head++;
                 progress = true;
             }
@@ -250,6 +291,34 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             if (lane == 0) LDS_STORE(&fs->head, head);
+        }
+
+        // ---- completions: clear finished slots from every upstream mask
+        {
+            const uint64_t done = __ballot(mine && (int32_t)(cdone - (uint32_t)(myseq + 1)) >= 0);
+            if (done) {
+                if (tr) {
+                    const uint64_t now = wall_clock64();
+                    if (((done >> lane) & 1ull) && myseq < p.trace_cap) {
+                        p.trace[myseq].ev_retire = (int64_t)(ev + __builtin_popcountll(done & lane_lt));
+                        p.trace[myseq].t_retire = (int64_t)now;
+                    }
+                }
+                ev += __builtin_popcountll(done);
+                retired += __builtin_popcountll(done);
+                if (((done >> rslot) & 1ull) && rep < R) {
+#pragma unroll
+                    for (int m = 0; m < kSegs; m++) ss[m] = se[m] = 0;
+                    nsl = 0;
+                }
+                const uint64_t rdone = done * repmul;
+#pragma unroll
+                for (int m = 0; m < kSegs; m++) wmask[m] &= ~rdone;
+                up &= ~done;
+                valid &= ~done;
+                exec &= ~done;
+                progress = true;
+            }
         }
 
         // ---- dispatch.  A kernel with an empty upstream mask is ready (it
@@ -272,9 +341,8 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
             for (uint64_t m = newly; m; m &= m - 1) {
                 const int j = __builtin_ctzll(m);
                 const uint64_t upj = readlane64(up, j);
-                TaskEntry *te = &p.st->task[j];
-                if ((upj >> lane) & 1ull) te->wait_target[lane] = target;
-                if (lane == 0) te->wait_mask = upj;
+                if ((upj >> lane) & 1ull) p.st->wait_target[j][lane] = (uint32_t)(myseq + 1);
+                if (lane == 0) p.st->task[j].wait_mask = upj;
             }
             // task-table entries written by other lanes are published before
             // any work-queue entry that points at them
@@ -285,7 +353,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
             for (uint64_t m = newly; m; m &= m - 1) {
                 const int l = __builtin_ctzll(m);
                 const uint64_t sl = readlane64(myseq, l);
-                const uint32_t npl = __builtin_amdgcn_readlane(mynp, l);
+                const uint32_t npl = readlane32(mynp, l);
                 if (sl < myseq) {
                     before += npl;
                     rank++;
@@ -313,7 +381,10 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
         // system-scope release covers every result (and trace record) of the
         // kernels retired so far
         if (valid == 0 && retired != published) {
+            // pairs with the release of every completion counted so far ...
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             __builtin_amdgcn_wave_barrier();
+            // ... and hands their results on to the host
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
             if (lane == 0) __hip_atomic_store(&p.ctrl->retired, retired, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             published = retired;
@@ -409,6 +480,7 @@ __device__ inline void worker(const DevParams &p, uint8_t *smem, Mail *mail)
                 const TaskEntry *te = &p.st->task[slot];
                 mail->kid = te->kid;
                 mail->np = te->npieces;
+                mail->ptarget = te->ptarget;
                 mail->seq = te->seq;
                 margs[lane & 7u] = reinterpret_cast<const uint64_t *>(te->args)[lane & 7u];
                 // dispatched early: wait until every upstream kernel's counter
@@ -416,11 +488,11 @@ __device__ inline void worker(const DevParams &p, uint8_t *smem, Mail *mail)
                 const uint64_t wm = uni64(te->wait_mask);
                 if (wm != 0) {
                     const bool watch = (wm >> lane) & 1ull;
-                    const uint32_t tgt = watch ? te->wait_target[lane] : 0u;
+                    const uint32_t tgt = watch ? p.st->wait_target[slot][lane] : 0u;
                     for (uint32_t spin = 1;; spin++) {
                         bool ok = true;
                         if (watch) {
-                            const uint32_t c = __hip_atomic_load(&p.st->cnt[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            const uint32_t c = __hip_atomic_load(&p.st->done[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                             ok = (int32_t)(c - tgt) >= 0;
                         }
                         if (__ballot(!ok) == 0) break;
@@ -447,12 +519,26 @@ __device__ inline void worker(const DevParams &p, uint8_t *smem, Mail *mail)
         if (wave0) {
             const uint64_t seq = uni64(mail->seq);
             if (tr && seq < p.trace_cap) {
-                // the same value from every lane: min and max are unchanged by repeats
-                const uint64_t t1 = uni64(wall_clock64());
-                atomicMin(reinterpret_cast<unsigned long long *>(&p.trace[seq].t_start), (unsigned long long)uni64(mail->t0));
-                atomicMax(reinterpret_cast<unsigned long long *>(&p.trace[seq].t_end), (unsigned long long)t1);
+                // one lane: 64 read-modify-writes of one address would queue
+                // behind each other before the completion store below
+                const uint64_t t1 = uni64(wall_clock64()), t0 = uni64(mail->t0);
+                if (lane == 0) {
+                    atomicMin(reinterpret_cast<unsigned long long *>(&p.trace[seq].t_start), (unsigned long long)t0);
+                    atomicMax(reinterpret_cast<unsigned long long *>(&p.trace[seq].t_end), (unsigned long long)t1);
+                }
             }
-            __hip_atomic_fetch_add(&p.st->cnt[slot], lane == 0 ? 1u : 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            // a kernel of several pieces is complete when the last piece is
+            // counted; that piece's read-modify-write also acquires the other
+            // pieces' results, so its release below covers them
+            const uint32_t np = uni32(mail->np);
+            bool last = true;
+            if (np > 1) {
+                const uint32_t old = uni32(__hip_atomic_fetch_add(&p.st->cnt[slot], lane == 0 ? 1u : 0u, __ATOMIC_ACQ_REL,
+                                                                  __HIP_MEMORY_SCOPE_AGENT));
+                last = old + 1u == uni32(mail->ptarget);
+            }
+            if (last)
+                __hip_atomic_store(&p.st->done[slot], (uint32_t)(seq + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }

@@ -97,12 +97,16 @@ inline uint64_t __ballot(int pred)
     return m;
 }
 
-inline uint32_t __builtin_amdgcn_readlane(uint32_t v, int l)
+inline uint64_t __builtin_amdgcn_ballot_w64(bool pred) { return __ballot(pred ? 1 : 0); }
+
+// int result, as the device built-in: a caller that widens it without a cast
+// sign-extends, exactly as on the GPU
+inline int __builtin_amdgcn_readlane(int v, int l)
 {
     acs_sim::Wave &w = acs_sim::group->waves[acs_sim::tid / 64];
-    w.vals[acs_sim::tid % 64] = v;
+    w.vals[acs_sim::tid % 64] = (uint32_t)v;
     w.bar.arrive_and_wait();
-    const uint32_t r = (uint32_t)w.vals[l];
+    const int r = (int)(uint32_t)w.vals[l];
     w.bar.arrive_and_wait();
     return r;
 }

@@ -73,12 +73,18 @@ def _descs(st, base):
     return descs
 
 
+# a deadlock in the emulated kernel would block inside the C call: the thread
+# method ends the run instead of hanging it
+@pytest.mark.timeout(180, method="thread")
 @pytest.mark.parametrize("seed,W,workers,ring", [
     (0, 8, 2, 64),
     (1, 4, 1, 64),
     (2, 64, 3, 64),
     (3, 16, 2, 4),      # ring smaller than the stream: host back-pressure
     (4, 1, 2, 64),      # window of one: strictly in order
+    (5, 32, 2, 64),     # two lanes per slot
+    (6, 3, 2, 64),      # window not a power of two
+    (7, 20, 3, 16),
 ])
 def test_tiny_stream_through_kernel_source(sim, seed, W, workers, ring):
     st = inputs.tiny_stream(seed)
