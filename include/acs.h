@@ -3,29 +3,29 @@
  *
  * The method is ACS (Durvasula et al., "ACS: Concurrent Kernel Execution on
  * Irregular, Input-Dependent Computational Graphs", arXiv 2401.12377).  Each
- * submitted kernel carries the byte ranges it reads and writes (Section IV-A,
- * "Determining inter-kernel dependencies"; Section V-A, the kernel wrapper and
+ * submitted kernel carries the byte ranges it reads and writes (Section III-C,
+ * "Determining inter-kernel dependencies"; Section IV-A, the kernel wrapper and
  * its get_addresses function).  Kernels enter a fixed-size scheduling window
- * in submission order (Section IV-B, "Mechanism Walkthrough"); on entry each
+ * in submission order (Section III-D, "Mechanism Walkthrough"); on entry each
  * one is tested for overlap against every kernel already in the window
  * (Algorithm 1), which gives its list of upstream kernels and makes it
- * pending, or ready when that list is empty (Section IV-A, "Tracking kernel
+ * pending, or ready when that list is empty (Section III-C, "Tracking kernel
  * state at runtime").  Ready kernels run concurrently; a completion removes
- * the kernel from the window and from every upstream list (Section V-B,
- * Algorithm 2; Section V-C).
+ * the kernel from the window and from every upstream list (Section IV-B,
+ * Algorithm 2; Section IV-C).
  *
  * Paths (acs_config.path):
  *   ACS_PATH_INORDER  every kernel is launched at submit into one HIP stream;
- *                     no window.  The single-stream baseline of Section III.
+ *                     no window.  The single-stream baseline of Section II.
  *   ACS_PATH_PLAIN    window checks on the host, ready kernels launched into a
  *                     pool of HIP streams, one kernel per stream at a time,
- *                     completions seen through HIP events (Section V-B).
+ *                     completions seen through HIP events (Section IV-B).
  *   ACS_PATH_DEVICE   window held on the GPU by a persistent scheduler kernel:
  *                     one wavefront keeps one window slot per lane, tests the
  *                     overlaps, builds the ready mask with a ballot and
  *                     publishes ready work to resident worker workgroups that
  *                     run the task bodies and signal completion with atomic
- *                     counters.  The software analogue of ACS-HW (Section V-C):
+ *                     counters.  The software analogue of ACS-HW (Section IV-C):
  *                     no host round trip per kernel.
  *   ACS_PATH_MANUAL   window only, no GPU: the caller takes ready kernels and
  *                     reports their completion (a stand-in executor for tests).
@@ -48,10 +48,10 @@ extern "C" {
 
 typedef struct acs_window acs_window;
 
-/* A byte range [start, start + size) of virtual memory (Section IV-A: a start
+/* A byte range [start, start + size) of virtual memory (Section III-C: a start
  * address and a size).  Zero-size ranges are dropped.  The range
  * {0, UINT64_MAX} stands for "may touch any memory", the conservative fallback
- * of Section V-A for kernels whose accesses cannot be stated. */
+ * of Section IV-A for kernels whose accesses cannot be stated. */
 typedef struct {
     uint64_t start;
     uint64_t size;
@@ -60,7 +60,7 @@ typedef struct {
 #define ACS_SEG_ALL_START 0ull
 #define ACS_SEG_ALL_SIZE UINT64_MAX
 
-/* Kernel states in the window (Section IV-A; two bits per slot in Section V-C). */
+/* Kernel states in the window (Section III-C; two bits per slot in Section IV-C). */
 enum { ACS_PENDING = 0, ACS_READY = 1, ACS_EXECUTING = 2 };
 
 enum {
@@ -93,7 +93,7 @@ typedef struct {
     int32_t reserved[7];
 } acs_config;
 
-/* One entry of the scheduled list (Section V-C): the kernels currently in the
+/* One entry of the scheduled list (Section IV-C): the kernels currently in the
  * window.  On the device path the list is a snapshot and may be stale. */
 typedef struct {
     uint64_t seq;            /* submission index */
@@ -130,7 +130,7 @@ typedef struct {
 void acs_config_default(acs_config *cfg);
 
 /* New window of W slots, 1 <= W <= 64 (the paper evaluates W = 32 and 16,
- * Section VI and Section VII-E).  NULL on error; see acs_last_error(). */
+ * Section V and Section VI-D).  NULL on error; see acs_last_error(). */
 acs_window *acs_window_create(int32_t W);
 
 /* Chooses the path and its resources; valid before the first submit only.

@@ -4,7 +4,7 @@
  * these; its args block is the matching struct (at most ACS_ARGS_MAX bytes).
  *
  * The paper's kernel wrapper pairs a kernel with a function that states its
- * read and write ranges from its launch arguments (Section V-A).  Here the
+ * read and write ranges from its launch arguments (Section IV-A).  Here the
  * body is chosen from this table and the caller states the ranges; the
  * Python binding has one range helper per task type.
  *

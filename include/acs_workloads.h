@@ -2,7 +2,7 @@
  * acs_workloads.h - native drivers that play the application on top of the
  * acs.h API for the synthetic workloads (the paper's evaluation runs
  * physics-simulation steps whose kernel graph depends on the input,
- * Section III-B and Section VII).  They only call acs_submit / acs_sync and
+ * Section II-B and Section VI).  They only call acs_submit / acs_sync and
  * read results; they hold no scheduling logic of their own.
  */
 #ifndef ACS_WORKLOADS_H

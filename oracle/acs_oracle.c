@@ -17,12 +17,12 @@
 #include <string.h>
 
 /* ------------------------------------------------------------------------ */
-/* Overlap and conflict (Section IV-A; Algorithm 1)                          */
+/* Overlap and conflict (Section III-C; Section IV-B, Algorithm 1)                          */
 /* ------------------------------------------------------------------------ */
 
 static uint64_t seg_end(uint64_t start, uint64_t size)
 {
-    /* saturate: {0, UINT64_MAX} stands for "all of memory" (Section V-A) */
+    /* saturate: {0, UINT64_MAX} stands for "all of memory" (Section IV-A) */
     return (size > UINT64_MAX - start) ? UINT64_MAX : start + size;
 }
 

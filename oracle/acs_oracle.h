@@ -7,14 +7,14 @@
  *
  * What it computes (all plain loops, no blocking, no reordering):
  *   - the byte-range overlap test of Algorithm 1 and the kernel-pair conflict
- *     relation built from it (Section IV-A, "Determining inter-kernel
- *     dependencies"; Section V-B, Algorithm 1);
+ *     relation built from it (Section III-C, "Determining inter-kernel
+ *     dependencies"; Section IV-B, Algorithm 1);
  *   - the all-pairs dependency DAG of a kernel stream;
  *   - a checker that validates a scheduler trace against that DAG (window
  *     admission, upstream lists, dispatch order, execution intervals);
  *   - in-order (program order) execution of the synthetic workloads' task
  *     bodies, which is by definition the result the scheduler must reproduce
- *     (Section IV: the window only reorders kernels it has proven independent).
+ *     (Section III: the window only reorders kernels it has proven independent).
  */
 #ifndef ACS_ORACLE_H
 #define ACS_ORACLE_H

@@ -303,7 +303,7 @@ def _destroy_live_windows():
 
 
 # ---------------------------------------------------------------------------
-# range helpers (the get_addresses of each task type, Section V-A)
+# range helpers (the get_addresses of each task type, Section IV-A)
 # ---------------------------------------------------------------------------
 def tensor_seg(t, elem_offset: int = 0, n_elems: int | None = None):
     """Byte range of n_elems elements of tensor t starting at elem_offset."""
@@ -314,7 +314,7 @@ def tensor_seg(t, elem_offset: int = 0, n_elems: int | None = None):
 
 def gemm_segments(a_ptr: int, b_ptr: int, c_ptr: int, m: int, n: int, k: int, elem_size: int):
     """Read and write ranges of C[m,k] = A[m,n] @ B[n,k] (the paper's
-    get_addresses example for matrix multiply, Section V-A)."""
+    get_addresses example for matrix multiply, Section IV-A)."""
     return [(a_ptr, m * n * elem_size), (b_ptr, n * k * elem_size)], [(c_ptr, m * k * elem_size)]
 
 

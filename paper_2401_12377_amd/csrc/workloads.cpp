@@ -1,6 +1,6 @@
 // Native application drivers for the synthetic workloads (acs_workloads.h).
 // They use the public API only; the range helpers below are the workload's
-// get_addresses functions (Section V-A): they state, from the launch
+// get_addresses functions (Section IV-A): they state, from the launch
 // arguments, which bytes each kernel reads and writes.
 #include <hip/hip_runtime_api.h>
 

@@ -17,7 +17,7 @@ stand in for them, shaped like the paper's evaluation workloads):
   writing one buffer;
 * rigid-body RL step: N spheres in the unit box with random velocities, the
   per-step kernel list of which depends on the contacts found at run time
-  (the paper's physics-engine case study, Section III-B);
+  (the paper's physics-engine case study, Section II-B);
 * batched scenes: many RL scenes of log-uniform size.
 """
 from __future__ import annotations

@@ -4,9 +4,9 @@ tests/cpusim/sim.cpp compiles the window wave, the FIFO wave and the worker
 loop (persistent.hpp, bodies.hpp) against a host emulation of the HIP
 built-ins they use, one OS thread per GPU thread.  These tests push the tiny
 random stream through that build and compare with the oracle: the arena must
-be bit-identical to in-order execution (Section IV: reordering only among
+be bit-identical to in-order execution (Section III: reordering only among
 proven-independent kernels leaves the result unchanged) and the trace must be
-a valid windowed schedule of the stream's dependency DAG (Section IV-A,
+a valid windowed schedule of the stream's dependency DAG (Section III-C,
 Algorithm 1), with execution intervals of dependent kernels disjoint.
 
 The emulation's atomics are sequentially consistent, so these runs check the

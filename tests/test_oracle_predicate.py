@@ -1,7 +1,7 @@
 """Pins for the oracle's overlap test, conflict relation and DAG.
 
 Everything here is checked against brute-force set intersection over small
-address spaces, not against the formula itself (Algorithm 1; Section IV-A).
+address spaces, not against the formula itself (Algorithm 1; Section III-C).
 """
 import itertools
 
