@@ -481,3 +481,83 @@ void or_rl_step(or_scene *s)
         }
     k.op = OR_RL_INTEGRATE; or_rl_run_kernel(s, &k);
 }
+
+/* ------------------------------------------------------------------------- */
+/* Dynamic DNN (Section II-C), batch 1, NHWC                                 */
+/* ------------------------------------------------------------------------- */
+
+int32_t or_conv_hout(int32_t hin, int32_t k, int32_t s)
+{
+    const int32_t p = (k - 1) / 2;
+    return (hin + 2 * p - k) / s + 1;
+}
+
+void or_conv_f32(const float *in, const float *w, const float *b, float *out,
+                 int32_t hin, int32_t cin, int32_t cout, int32_t k, int32_t s)
+{
+    const int32_t p = (k - 1) / 2, hout = or_conv_hout(hin, k, s);
+    for (int32_t y = 0; y < hout; y++)
+        for (int32_t x = 0; x < hout; x++)
+            for (int32_t co = 0; co < cout; co++) {
+                float acc = 0.0f;
+                for (int32_t ky = 0; ky < k; ky++)
+                    for (int32_t kx = 0; kx < k; kx++) {
+                        const int32_t iy = y * s + ky - p, ix = x * s + kx - p;
+                        for (int32_t ci = 0; ci < cin; ci++) {
+                            const float a = (iy >= 0 && iy < hin && ix >= 0 && ix < hin)
+                                                ? in[((int64_t)iy * hin + ix) * cin + ci] : 0.0f;
+                            acc = fmaf(a, w[(((int64_t)ky * k + kx) * cin + ci) * cout + co], acc);
+                        }
+                    }
+                out[((int64_t)y * hout + x) * cout + co] = acc + b[co];
+            }
+}
+
+void or_conv_f64(const float *in, const float *w, const float *b, double *out, double *mag,
+                 int32_t hin, int32_t cin, int32_t cout, int32_t k, int32_t s)
+{
+    const int32_t p = (k - 1) / 2, hout = or_conv_hout(hin, k, s);
+    for (int32_t y = 0; y < hout; y++)
+        for (int32_t x = 0; x < hout; x++)
+            for (int32_t co = 0; co < cout; co++) {
+                double acc = (double)b[co], m = fabs((double)b[co]);
+                for (int32_t ky = 0; ky < k; ky++)
+                    for (int32_t kx = 0; kx < k; kx++) {
+                        const int32_t iy = y * s + ky - p, ix = x * s + kx - p;
+                        if (iy < 0 || iy >= hin || ix < 0 || ix >= hin) continue;
+                        for (int32_t ci = 0; ci < cin; ci++) {
+                            const double t = (double)in[((int64_t)iy * hin + ix) * cin + ci] *
+                                             (double)w[(((int64_t)ky * k + kx) * cin + ci) * cout + co];
+                            acc += t;
+                            m += fabs(t);
+                        }
+                    }
+                out[((int64_t)y * hout + x) * cout + co] = acc;
+                mag[((int64_t)y * hout + x) * cout + co] = m;
+            }
+}
+
+float or_relu(float x) { return x > 0.0f ? x : 0.0f; }
+
+void or_join(float *out, const float *a, const float *b, int64_t n)
+{
+    for (int64_t i = 0; i < n; i++) out[i] = or_relu(b ? a[i] + b[i] : a[i]);
+}
+
+void or_avgpool(float *out, const float *in, int32_t hw, int32_t c)
+{
+    for (int32_t ch = 0; ch < c; ch++) {
+        float acc = 0.0f;
+        for (int32_t q = 0; q < hw; q++) acc += in[(int64_t)q * c + ch];
+        out[ch] = acc / (float)hw;
+    }
+}
+
+void or_fc(float *out, const float *in, const float *w, const float *b, int32_t cin, int32_t cout)
+{
+    for (int32_t j = 0; j < cout; j++) {
+        float acc = b[j];
+        for (int32_t i = 0; i < cin; i++) acc = fmaf(in[i], w[(int64_t)i * cout + j], acc);
+        out[j] = acc;
+    }
+}

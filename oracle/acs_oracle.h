@@ -90,4 +90,30 @@ int32_t or_rl_step_kernels(const or_scene *s, or_rl_kernel *out, int32_t cap);
 /* One whole step in program order. */
 void or_rl_step(or_scene *s);
 
+/* ---------------- dynamic DNN (batch 1, NHWC) ----------------
+ * The dynamic-network case study (Section II-C): convolutions whose execution
+ * is decided per input.  Tensors are NHWC with batch 1: act[y][x][c].
+ *
+ * Convolution with kernel k in {1, 3} (3x3 zero-padded by 1) and stride s:
+ *   out[y][x][co] = bias[co] + sum over (ky, kx, ci) of
+ *                   in[y*s + ky - p][x*s + kx - p][ci] * w[ky][kx][ci][co]
+ * with p = (k - 1) / 2 and hout = (hin + 2p - k) / s + 1.
+ * or_conv_f32: FP32, the products accumulated with fmaf from 0 in
+ *   (ky, kx, ci) order, the bias added last (one defined order).
+ * or_conv_f64: the same sum in double, and mag = the sum of the absolute
+ *   values of its terms (|bias| included), for error bounds. */
+int32_t or_conv_hout(int32_t hin, int32_t k, int32_t s);
+void or_conv_f32(const float *in, const float *w, const float *b, float *out,
+                 int32_t hin, int32_t cin, int32_t cout, int32_t k, int32_t s);
+void or_conv_f64(const float *in, const float *w, const float *b, double *out, double *mag,
+                 int32_t hin, int32_t cin, int32_t cout, int32_t k, int32_t s);
+/* relu(x) = x if x > 0 else +0 (so -0 and NaN give +0) */
+float or_relu(float x);
+/* out = relu(a + b) elementwise, or relu(a) when b is NULL */
+void or_join(float *out, const float *a, const float *b, int64_t n);
+/* out[c] = (sum over the hw pixels, in pixel order, in FP32) / hw */
+void or_avgpool(float *out, const float *in, int32_t hw, int32_t c);
+/* out[j] = b[j] + sum_i in[i] * w[i][j]: acc = b[j], then acc = fmaf(in[i], w[i][j], acc) for i = 0.. */
+void or_fc(float *out, const float *in, const float *w, const float *b, int32_t cin, int32_t cout);
+
 #endif

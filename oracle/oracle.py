@@ -90,6 +90,20 @@ def lib():
         L.or_rl_step_kernels.restype = C.c_int32
         L.or_rl_step.argtypes = [C.POINTER(SceneC)]
         L.or_rl_step.restype = None
+        L.or_conv_hout.argtypes = [C.c_int32] * 3
+        L.or_conv_hout.restype = C.c_int32
+        L.or_conv_f32.argtypes = [C.c_void_p] * 4 + [C.c_int32] * 5
+        L.or_conv_f32.restype = None
+        L.or_conv_f64.argtypes = [C.c_void_p] * 5 + [C.c_int32] * 5
+        L.or_conv_f64.restype = None
+        L.or_relu.argtypes = [C.c_float]
+        L.or_relu.restype = C.c_float
+        L.or_join.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]
+        L.or_join.restype = None
+        L.or_avgpool.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32]
+        L.or_avgpool.restype = None
+        L.or_fc.argtypes = [C.c_void_p] * 4 + [C.c_int32] * 2
+        L.or_fc.restype = None
         _lib = L
     return _lib
 
@@ -272,3 +286,161 @@ class Scene:
 
     def plan_rows(self):
         return self.plan[:4 * self.n_multi].reshape(-1, 4)
+
+
+# ---------------------------------------------------------------------------
+# dynamic DNN, batch 1 (Section II-C)
+# ---------------------------------------------------------------------------
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def conv_f32(x, w, b, k, s):
+    """FP32 convolution in the defined order (see or_conv_f32).  x: [h, h, cin]."""
+    x, w, b = _f32(x), _f32(w), _f32(b)
+    h, cin = x.shape[0], x.shape[2]
+    cout = b.shape[0]
+    ho = lib().or_conv_hout(h, k, s)
+    out = np.zeros((ho, ho, cout), np.float32)
+    lib().or_conv_f32(x.ctypes.data, w.ctypes.data, b.ctypes.data, out.ctypes.data, h, cin, cout, k, s)
+    return out
+
+
+def conv_f64(x, w, b, k, s):
+    """The same convolution in double, and the sum of |terms| per output."""
+    x, w, b = _f32(x), _f32(w), _f32(b)
+    h, cin = x.shape[0], x.shape[2]
+    cout = b.shape[0]
+    ho = lib().or_conv_hout(h, k, s)
+    out = np.zeros((ho, ho, cout), np.float64)
+    mag = np.zeros((ho, ho, cout), np.float64)
+    lib().or_conv_f64(x.ctypes.data, w.ctypes.data, b.ctypes.data, out.ctypes.data, mag.ctypes.data,
+                      h, cin, cout, k, s)
+    return out, mag
+
+
+def join(a, b=None):
+    a = _f32(a)
+    out = np.zeros_like(a)
+    bb = _f32(b) if b is not None else None
+    lib().or_join(out.ctypes.data, a.ctypes.data, bb.ctypes.data if bb is not None else None, a.size)
+    return out
+
+
+def avgpool(x):
+    x = _f32(x)
+    hw, c = x.shape[0] * x.shape[1], x.shape[2]
+    out = np.zeros(c, np.float32)
+    lib().or_avgpool(out.ctypes.data, x.ctypes.data, hw, c)
+    return out
+
+
+def fc(x, w, b):
+    x, w, b = _f32(x), _f32(w), _f32(b)
+    out = np.zeros(b.shape[0], np.float32)
+    lib().or_fc(out.ctypes.data, x.ctypes.data, w.ctypes.data, b.ctypes.data, w.shape[0], w.shape[1])
+    return out
+
+
+DNN_CONV3, DNN_CONV1, DNN_JOIN, DNN_POOL, DNN_FC = range(5)
+
+
+class DNN:
+    """One inference of the gated network, run strictly in program order.
+
+    Cell c reads the current activation; its 3x3 branch runs when logit[c][0]
+    > 0, its 1x1 branch when logit[c][1] > 0 or the cell changes resolution
+    (stride 2, so that the cell always produces an output); the join is
+    relu(t3 + t1), relu(t3) or relu(t1).  A cell with neither branch is the
+    identity.  The head is an average pool and a fully connected layer.
+
+    Tensors get abstract, disjoint address ranges (tensor index << 40), so the
+    kernels' read/write sets give the dataflow dependencies."""
+
+    def __init__(self, weights, inp, cells):
+        self.wts, self.inp, self.cells = weights, inp, cells
+        self.g3 = [bool(inp.logits[c, 0] > 0) for c in range(len(cells))]
+        self.g1 = [bool(inp.logits[c, 1] > 0) or cells[c][3] == 2 for c in range(len(cells))]
+        self.t3, self.t1, self.y = {}, {}, {}
+        self.pool = self.out = None
+
+    # tensor ids: 0 input; per cell 1 + 7c + {0 w3, 1 b3, 2 w1, 3 b1, 4 t3, 5 t1, 6 y}; then pool, fc_w, fc_b, out
+    def _tid(self, c, part):
+        return 1 + 7 * c + part
+
+    def _tensor_bytes(self, tid):
+        n = len(self.cells)
+        if tid == 0:
+            return self.inp.x.nbytes
+        if tid < 1 + 7 * n:
+            c, part = divmod(tid - 1, 7)
+            h, cin, cout, st = self.cells[c]
+            ho = h // st
+            return 4 * [9 * cin * cout, cout, cin * cout, cout, ho * ho * cout, ho * ho * cout, ho * ho * cout][part]
+        extra = tid - (1 + 7 * n)
+        cl = self.cells[-1][2]
+        return 4 * [cl, cl * self.wts.fc_w.shape[1], self.wts.fc_b.shape[0], self.wts.fc_b.shape[0]][extra]
+
+    def kernels(self):
+        """Program-order kernel list: (op, cell, reads, writes) with reads and
+        writes as tensor ids."""
+        ks = []
+        cur = 0
+        for c in range(len(self.cells)):
+            ins = []
+            if self.g3[c]:
+                ks.append((DNN_CONV3, c, [cur, self._tid(c, 0), self._tid(c, 1)], [self._tid(c, 4)]))
+                ins.append(self._tid(c, 4))
+            if self.g1[c]:
+                ks.append((DNN_CONV1, c, [cur, self._tid(c, 2), self._tid(c, 3)], [self._tid(c, 5)]))
+                ins.append(self._tid(c, 5))
+            if ins:
+                ks.append((DNN_JOIN, c, ins, [self._tid(c, 6)]))
+                cur = self._tid(c, 6)
+        n = len(self.cells)
+        pool, fcw, fcb, out = 1 + 7 * n, 2 + 7 * n, 3 + 7 * n, 4 + 7 * n
+        ks.append((DNN_POOL, -1, [cur], [pool]))
+        ks.append((DNN_FC, -1, [pool, fcw, fcb], [out]))
+        return ks
+
+    def accesses(self):
+        def seg(t):
+            return (t << 40, self._tensor_bytes(t))
+        return [make_access([seg(t) for t in r], [seg(t) for t in w]) for (_, _, r, w) in self.kernels()]
+
+    def run(self, order=None):
+        """Executes the kernels (program order, or the given permutation of the
+        kernel list, which must respect the dependencies)."""
+        ks = self.kernels()
+        vals = {0: self.inp.x}
+        idx = order if order is not None else range(len(ks))
+        for i in idx:
+            op, c, r, w = ks[i]
+            if op in (DNN_CONV3, DNN_CONV1):
+                h, cin, cout, st = self.cells[c]
+                if op == DNN_CONV3:
+                    vals[w[0]] = conv_f32(vals[r[0]], self.wts.w3[c], self.wts.b3[c], 3, st)
+                else:
+                    vals[w[0]] = conv_f32(vals[r[0]], self.wts.w1[c], self.wts.b1[c], 1, st)
+            elif op == DNN_JOIN:
+                vals[w[0]] = join(vals[r[0]], vals[r[1]] if len(r) > 1 else None)
+            elif op == DNN_POOL:
+                vals[w[0]] = avgpool(vals[r[0]])
+            else:
+                vals[w[0]] = fc(vals[r[0]], self.wts.fc_w, self.wts.fc_b)
+        for c in range(len(self.cells)):
+            for part, dst in ((4, self.t3), (5, self.t1), (6, self.y)):
+                if self._tid(c, part) in vals:
+                    dst[c] = vals[self._tid(c, part)]
+        n = len(self.cells)
+        self.pool = vals[1 + 7 * n]
+        self.out = vals[4 + 7 * n]
+        return self.out
+
+    def cell_input(self, c):
+        """The activation cell c reads (after run())."""
+        for cc in range(c - 1, -1, -1):
+            if cc in self.y:
+                return self.y[cc]
+        return self.inp.x

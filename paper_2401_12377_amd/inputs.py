@@ -18,7 +18,11 @@ stand in for them, shaped like the paper's evaluation workloads):
 * rigid-body RL step: N spheres in the unit box with random velocities, the
   per-step kernel list of which depends on the contacts found at run time
   (the paper's physics-engine case study, Section II-B);
-* batched scenes: many RL scenes of log-uniform size.
+* batched scenes: many RL scenes of log-uniform size;
+* dynamic DNN, batch 1: 12 cells of two gated parallel branches (3x3 and 1x1
+  convolutions), 32x32x32 -> 8x8x128 NHWC, average pool and a 128 -> 10 fully
+  connected head; which branches run depends on seeded per-input logits (the
+  paper's dynamic-network case study, Section II-C).
 """
 from __future__ import annotations
 
@@ -203,3 +207,64 @@ def batched_scene_sizes(seed: int = 3, n_scenes: int = 256, lo: int = 16, hi: in
 def batched_scenes(seed: int = 3, n_scenes: int = 256) -> list:
     sizes = batched_scene_sizes(seed, n_scenes)
     return [rl_scene(seed=(seed * 1_000_003 + i) & MASK64, n=int(s)) for i, s in enumerate(sizes)]
+
+
+# ---------------------------------------------------------------------------
+# Dynamic DNN (batch 1)
+# ---------------------------------------------------------------------------
+
+# (input height = width, input channels, output channels, stride) per cell.
+# Cells 4 and 8 halve the resolution and double the channels.
+DNN_CELLS = ([(32, 32, 32, 1)] * 4 + [(32, 32, 64, 2)] + [(16, 64, 64, 1)] * 3 +
+             [(16, 64, 128, 2)] + [(8, 128, 128, 1)] * 3)
+DNN_CLASSES = 10
+DNN_INPUT = (32, 32, 32)   # H, W, C (NHWC, batch 1)
+
+
+@dataclass
+class DNNWeights:
+    w3: list      # per cell float32[3, 3, cin, cout]
+    b3: list      # per cell float32[cout]
+    w1: list      # per cell float32[cin, cout]
+    b1: list      # per cell float32[cout]
+    fc_w: np.ndarray   # float32[128, 10]
+    fc_b: np.ndarray   # float32[10]
+
+
+def _uniform_sym(seed: int, n: int, bound: float) -> np.ndarray:
+    """U[-bound, bound) in FP32 (bound times an exact U[-1, 1) draw, rounded once)."""
+    return (uniform_pm1(splitmix64_array(seed, n)).astype(np.float64) * bound).astype(np.float32)
+
+
+def dnn_weights(seed: int = 2) -> DNNWeights:
+    """He-uniform weights (bound sqrt(6 / fan_in)) and biases U[-1/sqrt(fan_in), ...)."""
+    w3, b3, w1, b1 = [], [], [], []
+    for c, (h, cin, cout, st) in enumerate(DNN_CELLS):
+        base = (seed * 1_000_003 + 97 * c) & MASK64
+        f3, f1 = 9 * cin, cin
+        w3.append(_uniform_sym(base + 1, 9 * cin * cout, math.sqrt(6.0 / f3)).reshape(3, 3, cin, cout))
+        b3.append(_uniform_sym(base + 2, cout, 1.0 / math.sqrt(f3)))
+        w1.append(_uniform_sym(base + 3, cin * cout, math.sqrt(6.0 / f1)).reshape(cin, cout))
+        b1.append(_uniform_sym(base + 4, cout, 1.0 / math.sqrt(f1)))
+    cl = DNN_CELLS[-1][2]
+    base = (seed * 1_000_003 + 97 * len(DNN_CELLS)) & MASK64
+    fc_w = _uniform_sym(base + 1, cl * DNN_CLASSES, math.sqrt(6.0 / cl)).reshape(cl, DNN_CLASSES)
+    fc_b = _uniform_sym(base + 2, DNN_CLASSES, 1.0 / math.sqrt(cl))
+    return DNNWeights(w3, b3, w1, b1, fc_w, fc_b)
+
+
+@dataclass
+class DNNInput:
+    seed: int
+    x: np.ndarray        # float32[32, 32, 32] NHWC
+    logits: np.ndarray   # float32[12, 2]: gate logits of the 3x3 and 1x1 branch of each cell
+
+
+def dnn_input(seed: int = 0) -> DNNInput:
+    """Input image U[-1, 1) and one gate logit U[-1, 1) per branch; a branch
+    runs when its logit is positive (only the sign is used)."""
+    h, w, c = DNN_INPUT
+    bits = splitmix64_array((0xD22 << 32) ^ seed, h * w * c + 2 * len(DNN_CELLS))
+    x = uniform_pm1(bits[:h * w * c]).reshape(h, w, c)
+    logits = uniform_pm1(bits[h * w * c:]).reshape(len(DNN_CELLS), 2)
+    return DNNInput(seed=seed, x=x, logits=logits)
