@@ -34,7 +34,12 @@ enum acs_kernel_id {
     ACS_K_RL_PERMUTE = 13,    /* Q0[p] = P[perm[p]] */
     ACS_K_RL_JACOBI = 14,     /* one Jacobi contact iteration over one island */
     ACS_K_RL_INTEGRATE = 15,  /* X, V from Q0 with wall reflection */
-    ACS_K_COUNT = 16
+    /* dynamic DNN, batch 1, NHWC FP32 (acs_args_conv etc.) */
+    ACS_K_CONV = 20,          /* 3x3 (pad 1) or 1x1 convolution, stride 1 or 2, + bias; FP32 MFMA */
+    ACS_K_JOIN = 21,          /* out = relu(a + b), or relu(a) when b is NULL */
+    ACS_K_AVGPOOL = 22,       /* out[c] = (sum of in[q][c] over the hw pixels, in pixel order) / hw */
+    ACS_K_FC = 23,            /* out[j] = b[j] + sum_i in[i] w[i][j], fmaf chain in i order */
+    ACS_K_COUNT = 24
 };
 
 #define ACS_BLOCK 256
@@ -63,6 +68,25 @@ typedef struct {
     int32_t iter;            /* Jacobi: iteration index (even: Q0 -> Q1, odd: Q1 -> Q0) */
     int32_t b0, b1;          /* Jacobi: positions [b0, b1) of the island */
 } acs_args_rl;
+
+/* Convolution over an NHWC activation in[hin][hin][cin] with weights
+ * w[k][k][cin][cout] (k = 1: w[cin][cout]) and bias[cout], into
+ * out[hout][hout][cout], hout = (hin + 2p - k) / stride + 1, p = (k - 1) / 2.
+ * Implicit GEMM M = hout^2, N = cout, K = k^2 cin on 16x16x4 FP32 MFMA tiles;
+ * requires cin % 32 == 0, cout % 32 == 0, hout^2 % 64 == 0.  Sums are FP32
+ * in the matrix unit's order (not the scalar reference's): checked against a
+ * float64 reference within 1e-5 of the sum of |terms|.  One piece per 64 x 32
+ * output tile. */
+typedef struct {
+    const float *in;
+    const float *w;
+    const float *bias;
+    float *out;
+    int32_t hin, cin, cout, k, stride;
+} acs_args_conv;
+typedef struct { float *out; const float *a; const float *b; uint32_t n; } acs_args_join;
+typedef struct { float *out; const float *in; int32_t hw, c; } acs_args_avgpool;
+typedef struct { float *out; const float *in; const float *w; const float *bias; int32_t cin, cout; } acs_args_fc;
 
 /* Regions of an RL scene arena, in order; byte offsets from acs_rl_layout. */
 enum acs_rl_region {

@@ -60,6 +60,37 @@ int acs_rl_run(acs_window *w, const acs_rl_scene *scene, int32_t steps, double *
  * Drains the window at the end; wall_ns receives submit-to-drain time. */
 int acs_nop_run(acs_window *w, int32_t n, int32_t chain, uint64_t spin_ns, double *wall_ns);
 
+/* Dynamic DNN, batch 1 (the dynamic-network case study, Section II-C): cells
+ * of two parallel gated branches, a 3x3 (pad 1) and a 1x1 convolution with
+ * the cell's stride, joined by relu(sum of the branches that ran); a cell
+ * with no branch is the identity.  Then an average pool and a fully connected
+ * head.  All tensors are FP32 NHWC device buffers owned by the caller. */
+#define ACS_DNN_MAX_CELLS 16
+typedef struct {
+    int32_t hin, cin, cout, stride;   /* stride 1 or 2; hout = hin / stride */
+    const float *w3, *b3;             /* w3[3][3][cin][cout], b3[cout] */
+    const float *w1, *b1;             /* w1[cin][cout], b1[cout] */
+    float *t3, *t1, *y;               /* [hout][hout][cout]: 3x3 branch, 1x1 branch, cell output */
+} acs_dnn_cell;
+typedef struct {
+    int32_t n_cells;                  /* 1..ACS_DNN_MAX_CELLS */
+    int32_t classes;
+    const float *x;                   /* input [hin][hin][cin] of cell 0 */
+    acs_dnn_cell cell[ACS_DNN_MAX_CELLS];
+    float *pool;                      /* [cout of the last cell] */
+    const float *fc_w, *fc_b;         /* [cout_last][classes], [classes] */
+    float *out;                       /* [classes] */
+} acs_dnn_graph;
+
+/* Submits one inference in program order (no drain).  Per cell c: the 3x3
+ * branch if logits[2c] > 0; the 1x1 branch if logits[2c+1] > 0 or the cell
+ * has stride 2 (so that a cell that changes shape always has an output); the
+ * join if either ran, reading the previous cell output that exists (or x).
+ * Then average pool and the head.  Each kernel's ranges are its whole input
+ * and output tensors and its weights.  *n_kernels (if not NULL) receives the
+ * number of kernels submitted.  Returns 0 or the first error. */
+int acs_dnn_submit(acs_window *w, const acs_dnn_graph *g, const float *logits, uint64_t *n_kernels);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,6 +29,8 @@ SEG_ALL = (0, (1 << 64) - 1)
 
 K_NOP, K_SCALE, K_AXPY, K_SUM = 0, 1, 2, 3
 K_RL_PREDICT, K_RL_BROADPHASE, K_RL_ISLANDS, K_RL_PERMUTE, K_RL_JACOBI, K_RL_INTEGRATE = 10, 11, 12, 13, 14, 15
+K_CONV, K_JOIN, K_AVGPOOL, K_FC = 20, 21, 22, 23
+DNN_MAX_CELLS = 16
 
 RL_X, RL_V, RL_P, RL_Q0, RL_Q1, RL_DEG, RL_ADJ_OFF, RL_ADJ, RL_LABEL, RL_PERM, RL_INV_PERM, RL_ISL_OFF, \
     RL_PADJ_OFF, RL_PADJ, RL_END = range(15)
@@ -88,6 +90,36 @@ class ArgsAxpy(C.Structure):
 
 class ArgsSum(C.Structure):
     _fields_ = [("out", C.c_uint64), ("ins", C.c_uint64 * 3), ("len", C.c_uint32 * 3), ("nin", C.c_uint32)]
+
+
+class ArgsConv(C.Structure):
+    _fields_ = [("inp", C.c_uint64), ("w", C.c_uint64), ("bias", C.c_uint64), ("out", C.c_uint64),
+                ("hin", C.c_int32), ("cin", C.c_int32), ("cout", C.c_int32), ("k", C.c_int32), ("stride", C.c_int32)]
+
+
+class ArgsJoin(C.Structure):
+    _fields_ = [("out", C.c_uint64), ("a", C.c_uint64), ("b", C.c_uint64), ("n", C.c_uint32)]
+
+
+class ArgsAvgpool(C.Structure):
+    _fields_ = [("out", C.c_uint64), ("inp", C.c_uint64), ("hw", C.c_int32), ("c", C.c_int32)]
+
+
+class ArgsFC(C.Structure):
+    _fields_ = [("out", C.c_uint64), ("inp", C.c_uint64), ("w", C.c_uint64), ("bias", C.c_uint64),
+                ("cin", C.c_int32), ("cout", C.c_int32)]
+
+
+class DNNCellC(C.Structure):
+    _fields_ = [("hin", C.c_int32), ("cin", C.c_int32), ("cout", C.c_int32), ("stride", C.c_int32),
+                ("w3", C.c_uint64), ("b3", C.c_uint64), ("w1", C.c_uint64), ("b1", C.c_uint64),
+                ("t3", C.c_uint64), ("t1", C.c_uint64), ("y", C.c_uint64)]
+
+
+class DNNGraphC(C.Structure):
+    _fields_ = [("n_cells", C.c_int32), ("classes", C.c_int32), ("x", C.c_uint64),
+                ("cell", DNNCellC * DNN_MAX_CELLS), ("pool", C.c_uint64), ("fc_w", C.c_uint64),
+                ("fc_b", C.c_uint64), ("out", C.c_uint64)]
 
 
 class ArgsRL(C.Structure):
@@ -151,10 +183,11 @@ def lib():
         L.acs_host_free.argtypes = [C.c_void_p]
         L.acs_rl_run.argtypes = [C.c_void_p, P(RLSceneC), C.c_int32, P(C.c_double), P(RLCounts)]
         L.acs_nop_run.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, P(C.c_double)]
+        L.acs_dnn_submit.argtypes = [C.c_void_p, P(DNNGraphC), C.c_void_p, P(C.c_uint64)]
         for f in ("acs_window_configure", "acs_submit", "acs_sync", "acs_sync_timeout", "acs_scheduled_list",
                   "acs_trace_read", "acs_stats_get", "acs_window_destroy", "acs_window_stop", "acs_manual_take_ready",
                   "acs_manual_complete", "acs_last_error", "acs_rl_layout", "acs_host_free", "acs_rl_run",
-                  "acs_nop_run"):
+                  "acs_nop_run", "acs_dnn_submit"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -451,3 +484,77 @@ def nop_run(win: Window, n: int, chain: bool, spin_ns: int = 0) -> float:
     t = C.c_double()
     _check(lib().acs_nop_run(win.handle, n, int(chain), spin_ns, C.byref(t)))
     return t.value
+
+
+# ---------------------------------------------------------------------------
+# dynamic DNN (batch 1, NHWC)
+# ---------------------------------------------------------------------------
+def conv_task(x, w, b, out, k: int, stride: int):
+    """(kernel_id, reads, writes, args) of one convolution over torch tensors
+    x[h][h][cin], w[k][k][cin][cout] (or [cin][cout]), b[cout], out[ho][ho][cout]."""
+    h, cin, cout = x.shape[0], x.shape[2], b.shape[0]
+    a = ArgsConv(x.data_ptr(), w.data_ptr(), b.data_ptr(), out.data_ptr(), h, cin, cout, k, stride)
+    return K_CONV, [tensor_seg(x), tensor_seg(w), tensor_seg(b)], [tensor_seg(out)], a
+
+
+def join_task(out, a, b=None):
+    args = ArgsJoin(out.data_ptr(), a.data_ptr(), b.data_ptr() if b is not None else 0, out.numel())
+    reads = [tensor_seg(a)] + ([tensor_seg(b)] if b is not None else [])
+    return K_JOIN, reads, [tensor_seg(out)], args
+
+
+class DNNGPU:
+    """Device weights and the per-inference activation buffers of the gated
+    network (torch tensors for memory; every kernel runs in libacs)."""
+
+    def __init__(self, weights, cells, classes: int, device="cuda"):
+        import torch
+        self.cells = cells
+        self.classes = classes
+        dev = torch.device(device)
+
+        def t(a):
+            return torch.as_tensor(np.ascontiguousarray(a, np.float32)).to(dev)
+        self.w3 = [t(a) for a in weights.w3]
+        self.b3 = [t(a) for a in weights.b3]
+        self.w1 = [t(a) for a in weights.w1]
+        self.b1 = [t(a) for a in weights.b1]
+        self.fc_w, self.fc_b = t(weights.fc_w), t(weights.fc_b)
+        h0, c0 = cells[0][0], cells[0][1]
+        self.x = torch.zeros((h0, h0, c0), dtype=torch.float32, device=dev)
+        self.t3, self.t1, self.y = [], [], []
+        for (h, cin, cout, st) in cells:
+            ho = h // st
+            for lst in (self.t3, self.t1, self.y):
+                lst.append(torch.full((ho, ho, cout), float("nan"), dtype=torch.float32, device=dev))
+        self.pool = torch.zeros(cells[-1][2], dtype=torch.float32, device=dev)
+        self.out = torch.zeros(classes, dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+
+    def set_input(self, x):
+        import torch
+        self.x.copy_(torch.as_tensor(np.ascontiguousarray(x, np.float32)))
+        torch.cuda.synchronize()   # the library's streams do not wait for torch's
+
+    def c_struct(self) -> DNNGraphC:
+        g = DNNGraphC()
+        g.n_cells, g.classes = len(self.cells), self.classes
+        g.x = self.x.data_ptr()
+        for c, (h, cin, cout, st) in enumerate(self.cells):
+            L = g.cell[c]
+            L.hin, L.cin, L.cout, L.stride = h, cin, cout, st
+            L.w3, L.b3, L.w1, L.b1 = (self.w3[c].data_ptr(), self.b3[c].data_ptr(), self.w1[c].data_ptr(),
+                                      self.b1[c].data_ptr())
+            L.t3, L.t1, L.y = self.t3[c].data_ptr(), self.t1[c].data_ptr(), self.y[c].data_ptr()
+        g.pool, g.fc_w, g.fc_b, g.out = (self.pool.data_ptr(), self.fc_w.data_ptr(), self.fc_b.data_ptr(),
+                                         self.out.data_ptr())
+        return g
+
+
+def dnn_submit(win: Window, net: DNNGPU, logits) -> int:
+    """Submits one inference (no drain); returns the number of kernels."""
+    g = net.c_struct()
+    lg = np.ascontiguousarray(logits, np.float32).reshape(-1)
+    n = C.c_uint64()
+    _check(lib().acs_dnn_submit(win.handle, C.byref(g), lg.ctypes.data, C.byref(n)))
+    return n.value

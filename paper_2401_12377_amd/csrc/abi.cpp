@@ -108,6 +108,10 @@ size_t args_size_of(int32_t kid)
     case ACS_K_RL_PERMUTE:
     case ACS_K_RL_JACOBI:
     case ACS_K_RL_INTEGRATE: return sizeof(acs_args_rl);
+    case ACS_K_CONV: return sizeof(acs_args_conv);
+    case ACS_K_JOIN: return sizeof(acs_args_join);
+    case ACS_K_AVGPOOL: return sizeof(acs_args_avgpool);
+    case ACS_K_FC: return sizeof(acs_args_fc);
     default: return 0;
     }
 }
@@ -169,6 +173,52 @@ bool check_args(int32_t kid, const uint8_t *args, int32_t g, uint32_t &np, std::
         }
         if (kid == ACS_K_RL_PREDICT || kid == ACS_K_RL_PERMUTE || kid == ACS_K_RL_INTEGRATE)
             np = std::max(1u, std::min(gg, div_up((uint32_t)a.n, 256)));
+        return true;
+    }
+    case ACS_K_CONV: {
+        acs_args_conv a;
+        memcpy(&a, args, sizeof(a));
+        if ((a.k != 1 && a.k != 3) || (a.stride != 1 && a.stride != 2) || a.hin < 1 || a.hin > 4096 ||
+            a.cin < 32 || a.cin % 32 != 0 || a.cout < 32 || a.cout % 32 != 0 || a.cin > 4096 || a.cout > 4096 ||
+            !a.in || !a.w || !a.bias || !a.out) {
+            if (why) *why = "conv: k in {1,3}, stride in {1,2}, cin and cout multiples of 32, non-null buffers";
+            return false;
+        }
+        const int64_t pad = (a.k - 1) / 2, hout = (a.hin + 2 * pad - a.k) / a.stride + 1, m = hout * hout;
+        if (hout < 1 || m % 64 != 0) {
+            if (why) *why = "conv: output pixels must be a multiple of 64";
+            return false;
+        }
+        // one piece per 64 x 32 output tile, at most 256 pieces (tiles are dealt round-robin)
+        np = (uint32_t)std::min<int64_t>((m / 64) * (a.cout / 32), 256);
+        return true;
+    }
+    case ACS_K_JOIN: {
+        acs_args_join a;
+        memcpy(&a, args, sizeof(a));
+        if (!a.out || !a.a) {
+            if (why) *why = "join: null buffer";
+            return false;
+        }
+        np = std::max(1u, std::min(gg, div_up(a.n, 1024)));
+        return true;
+    }
+    case ACS_K_AVGPOOL: {
+        acs_args_avgpool a;
+        memcpy(&a, args, sizeof(a));
+        if (a.hw < 1 || a.c < 1 || a.c > 4096 || !a.in || !a.out) {
+            if (why) *why = "avgpool: bad shape";
+            return false;
+        }
+        return true;
+    }
+    case ACS_K_FC: {
+        acs_args_fc a;
+        memcpy(&a, args, sizeof(a));
+        if (a.cin < 1 || a.cout < 1 || a.cout > 4096 || !a.in || !a.w || !a.bias || !a.out) {
+            if (why) *why = "fc: bad shape";
+            return false;
+        }
         return true;
     }
     default: return true;

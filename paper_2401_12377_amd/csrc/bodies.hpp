@@ -482,6 +482,117 @@ __device__ inline void body_rl_integrate(const acs_args_rl &a, uint32_t piece, u
 // ---------------------------------------------------------------------------
 // dispatch by task type
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// dynamic DNN bodies (NHWC, batch 1)
+// ---------------------------------------------------------------------------
+typedef float acs_v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kConvKC = 32;              // K columns staged per step
+constexpr int kConvLdA = kConvKC + 4;    // LDS row pitch of the A tile (floats)
+constexpr int kConvLdB = 32 + 4;         // LDS row pitch of the B tile
+
+// Implicit-GEMM convolution: C[M x N] = A[M x K] B[K x N], M = output pixels,
+// N = output channels, K = (ky, kx, ci).  One workgroup computes a 64 x 32
+// tile: wave w owns rows [16w, 16w + 16) and both 16-column halves, each a
+// 16x16 accumulator of v_mfma_f32_16x16x4f32 (A element (i, k) from lane
+// i + 16k, B element (k, j) from lane j + 16k, result (4q + r, j) in lane
+// j + 16q, register r).  K is staged 32 columns at a time; because cin is a
+// multiple of 32, a step never straddles two (ky, kx) taps.
+__device__ inline void conv_tile(const acs_args_conv &a, int32_t m0, int32_t n0, uint8_t *smem)
+{
+    const int32_t k = a.k, st = a.stride, pad = (k - 1) / 2, hin = a.hin, cin = a.cin, cout = a.cout;
+    const int32_t hout = (hin + 2 * pad - k) / st + 1;
+    const int32_t K = k * k * cin;
+    float *As = reinterpret_cast<float *>(smem);   // [64][kConvLdA]
+    float *Bs = As + 64 * kConvLdA;                // [kConvKC][kConvLdB]
+    const int32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    // staging coordinates: A row ar (pixel m0 + ar), 8 channels from ac; B row br, 4 columns from bc
+    const int32_t ar = t >> 2, ac = (t & 3) * 8, br = t >> 3, bc = (t & 7) * 4;
+    const int32_t pm = m0 + ar, py = pm / hout, px = pm % hout;
+    acs_v4f acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int32_t kc0 = 0; kc0 < K; kc0 += kConvKC) {
+        const int32_t tap = kc0 / cin, ci0 = kc0 - tap * cin, ky = tap / k, kx = tap - ky * k;
+        const int32_t iy = py * st + ky - pad, ix = px * st + kx - pad;
+        float4 v0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), v1 = v0;
+        if (iy >= 0 && iy < hin && ix >= 0 && ix < hin) {
+            const float4 *src = reinterpret_cast<const float4 *>(a.in + ((int64_t)iy * hin + ix) * cin + ci0 + ac);
+            v0 = src[0];
+            v1 = src[1];
+        }
+        const float4 wv4 = *reinterpret_cast<const float4 *>(a.w + (int64_t)(kc0 + br) * cout + n0 + bc);
+        float *arow = As + ar * kConvLdA + ac;
+        arow[0] = v0.x; arow[1] = v0.y; arow[2] = v0.z; arow[3] = v0.w;
+        arow[4] = v1.x; arow[5] = v1.y; arow[6] = v1.z; arow[7] = v1.w;
+        float *brow = Bs + br * kConvLdB + bc;
+        brow[0] = wv4.x; brow[1] = wv4.y; brow[2] = wv4.z; brow[3] = wv4.w;
+        __syncthreads();
+        const float *ap = As + (16 * wv + (lane & 15)) * kConvLdA + (lane >> 4);
+        const float *bp = Bs + (lane >> 4) * kConvLdB + (lane & 15);
+#pragma unroll
+        for (int32_t k4 = 0; k4 < kConvKC; k4 += 4) {
+            const float av = ap[k4];
+            const float b0 = bp[k4 * kConvLdB], b1 = bp[k4 * kConvLdB + 16];
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b1, acc1, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    const int32_t col = lane & 15;
+    const float bias0 = a.bias[n0 + col], bias1 = a.bias[n0 + 16 + col];
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const int32_t row = m0 + 16 * wv + 4 * (lane >> 4) + r;
+        float *o = a.out + (int64_t)row * cout + n0;
+        o[col] = acc0[r] + bias0;
+        o[16 + col] = acc1[r] + bias1;
+    }
+}
+
+// Tiles are dealt to pieces round-robin: each output element is computed by
+// one tile in one order, whatever the piece count.
+__device__ inline void body_conv(const acs_args_conv &a, uint32_t piece, uint32_t np, uint8_t *smem)
+{
+    const int32_t pad = (a.k - 1) / 2, hout = (a.hin + 2 * pad - a.k) / a.stride + 1;
+    const uint32_t ntn = (uint32_t)a.cout / 32u, ntiles = (uint32_t)(hout * hout / 64) * ntn;
+    for (uint32_t tile = piece; tile < ntiles; tile += np) {
+        conv_tile(a, (int32_t)(tile / ntn) * 64, (int32_t)(tile % ntn) * 32, smem);
+        __syncthreads();   // the next tile reuses the staging buffers
+    }
+}
+
+__device__ inline float relu(float x) { return x > 0.0f ? x : 0.0f; }
+
+__device__ inline void body_join(const acs_args_join &a, uint32_t piece, uint32_t np)
+{
+    uint32_t lo, hi;
+    piece_range(a.n, piece, np, lo, hi);
+    if (a.b) {
+        for (uint32_t i = lo + threadIdx.x; i < hi; i += ACS_BLOCK) a.out[i] = relu(a.a[i] + a.b[i]);
+    } else {
+        for (uint32_t i = lo + threadIdx.x; i < hi; i += ACS_BLOCK) a.out[i] = relu(a.a[i]);
+    }
+}
+
+// one thread per channel; pixel order, FP32
+__device__ inline void body_avgpool(const acs_args_avgpool &a)
+{
+    for (int32_t c = threadIdx.x; c < a.c; c += ACS_BLOCK) {
+        float acc = 0.0f;
+        for (int32_t q = 0; q < a.hw; q++) acc += a.in[(int64_t)q * a.c + c];
+        a.out[c] = acc / (float)a.hw;
+    }
+}
+
+// one thread per output; fmaf chain in input order (a GEMV: no matrix unit)
+__device__ inline void body_fc(const acs_args_fc &a)
+{
+    for (int32_t j = threadIdx.x; j < a.cout; j += ACS_BLOCK) {
+        float acc = a.bias[j];
+        for (int32_t i = 0; i < a.cin; i++) acc = fmaf(a.in[i], a.w[(int64_t)i * a.cout + j], acc);
+        a.out[j] = acc;
+    }
+}
+
 template <typename T>
 __device__ inline T load_args(const void *p)
 {
@@ -503,6 +614,10 @@ __device__ __forceinline__ void run_body(int32_t kid, const void *args, uint32_t
     case ACS_K_RL_PERMUTE: body_rl_permute(load_args<acs_args_rl>(args), piece, np); break;
     case ACS_K_RL_JACOBI: body_rl_jacobi(load_args<acs_args_rl>(args)); break;
     case ACS_K_RL_INTEGRATE: body_rl_integrate(load_args<acs_args_rl>(args), piece, np); break;
+    case ACS_K_CONV: body_conv(load_args<acs_args_conv>(args), piece, np, smem); break;
+    case ACS_K_JOIN: body_join(load_args<acs_args_join>(args), piece, np); break;
+    case ACS_K_AVGPOOL: body_avgpool(load_args<acs_args_avgpool>(args)); break;
+    case ACS_K_FC: body_fc(load_args<acs_args_fc>(args)); break;
     default: break;
     }
 }

@@ -16,7 +16,10 @@ namespace acs {
 template <int KID>
 constexpr int smem_bytes()
 {
-    return (KID == ACS_K_SUM) ? 1024 : (KID == ACS_K_RL_BROADPHASE || KID == ACS_K_RL_ISLANDS) ? kBodySmem : 16;
+    return (KID == ACS_K_SUM) ? 1024
+           : (KID == ACS_K_RL_BROADPHASE || KID == ACS_K_RL_ISLANDS) ? kBodySmem
+           : (KID == ACS_K_CONV) ? (64 * kConvLdA + kConvKC * kConvLdB) * 4
+                                 : 16;
 }
 
 template <int KID, typename A>
@@ -38,7 +41,13 @@ static const void *const k_table[ACS_K_COUNT] = {
     reinterpret_cast<const void *>(&k_task<ACS_K_RL_PERMUTE, acs_args_rl>),
     reinterpret_cast<const void *>(&k_task<ACS_K_RL_JACOBI, acs_args_rl>),
     reinterpret_cast<const void *>(&k_task<ACS_K_RL_INTEGRATE, acs_args_rl>),
+    nullptr, nullptr, nullptr, nullptr,
+    reinterpret_cast<const void *>(&k_task<ACS_K_CONV, acs_args_conv>),
+    reinterpret_cast<const void *>(&k_task<ACS_K_JOIN, acs_args_join>),
+    reinterpret_cast<const void *>(&k_task<ACS_K_AVGPOOL, acs_args_avgpool>),
+    reinterpret_cast<const void *>(&k_task<ACS_K_FC, acs_args_fc>),
 };
+static_assert(sizeof(k_table) / sizeof(k_table[0]) == ACS_K_COUNT, "task table size");
 
 hipError_t launch_task(int32_t kid, const void *args, uint32_t npieces, hipStream_t stream)
 {

@@ -152,4 +152,72 @@ int acs_nop_run(acs_window *w, int32_t n, int32_t chain, uint64_t spin_ns, doubl
     return rc;
 }
 
+int acs_dnn_submit(acs_window *w, const acs_dnn_graph *g, const float *logits, uint64_t *n_kernels)
+{
+    if (!w || !g || !logits || g->n_cells < 1 || g->n_cells > ACS_DNN_MAX_CELLS || g->classes < 1 || !g->x ||
+        !g->pool || !g->fc_w || !g->fc_b || !g->out)
+        return ACS_EINVAL;
+    auto seg = [](const void *p, uint64_t bytes) { return acs_seg{(uint64_t)(uintptr_t)p, bytes}; };
+    uint64_t kernels = 0;
+    const float *cur = g->x;
+    uint64_t cur_bytes = 4ull * g->cell[0].hin * g->cell[0].hin * g->cell[0].cin;
+    int32_t cur_c = g->cell[0].cin, cur_h = g->cell[0].hin;
+    for (int32_t c = 0; c < g->n_cells; c++) {
+        const acs_dnn_cell &L = g->cell[c];
+        if (L.hin != cur_h || L.cin != cur_c || (L.stride != 1 && L.stride != 2) || L.hin % L.stride != 0)
+            return ACS_EINVAL;
+        const int32_t hout = L.hin / L.stride;
+        const uint64_t out_bytes = 4ull * hout * hout * L.cout;
+        const bool g3 = logits[2 * c] > 0.0f, g1 = logits[2 * c + 1] > 0.0f || L.stride == 2;
+        const float *parts[2];
+        int np = 0;
+        if (g3) {
+            acs_args_conv a = {cur, L.w3, L.b3, L.t3, L.hin, L.cin, L.cout, 3, L.stride};
+            const acs_seg r[3] = {seg(cur, cur_bytes), seg(L.w3, 36ull * L.cin * L.cout), seg(L.b3, 4ull * L.cout)};
+            const acs_seg wr[1] = {seg(L.t3, out_bytes)};
+            if (int rc = acs_submit(w, ACS_K_CONV, r, 3, wr, 1, &a, sizeof(a), nullptr)) return rc;
+            parts[np++] = L.t3;
+            kernels++;
+        }
+        if (g1) {
+            acs_args_conv a = {cur, L.w1, L.b1, L.t1, L.hin, L.cin, L.cout, 1, L.stride};
+            const acs_seg r[3] = {seg(cur, cur_bytes), seg(L.w1, 4ull * L.cin * L.cout), seg(L.b1, 4ull * L.cout)};
+            const acs_seg wr[1] = {seg(L.t1, out_bytes)};
+            if (int rc = acs_submit(w, ACS_K_CONV, r, 3, wr, 1, &a, sizeof(a), nullptr)) return rc;
+            parts[np++] = L.t1;
+            kernels++;
+        }
+        if (np > 0) {
+            acs_args_join a = {L.y, parts[0], np > 1 ? parts[1] : nullptr, (uint32_t)(out_bytes / 4)};
+            const acs_seg r[2] = {seg(parts[0], out_bytes), seg(np > 1 ? parts[1] : nullptr, np > 1 ? out_bytes : 0)};
+            const acs_seg wr[1] = {seg(L.y, out_bytes)};
+            if (int rc = acs_submit(w, ACS_K_JOIN, r, np, wr, 1, &a, sizeof(a), nullptr)) return rc;
+            kernels++;
+            cur = L.y;
+            cur_bytes = out_bytes;
+            cur_h = hout;
+            cur_c = L.cout;
+        } else if (L.stride != 1 || L.cout != L.cin) {
+            return ACS_EINVAL;   // unreachable: a cell that changes shape always runs its 1x1 branch
+        }
+    }
+    {
+        acs_args_avgpool a = {g->pool, cur, cur_h * cur_h, cur_c};
+        const acs_seg r[1] = {seg(cur, cur_bytes)};
+        const acs_seg wr[1] = {seg(g->pool, 4ull * cur_c)};
+        if (int rc = acs_submit(w, ACS_K_AVGPOOL, r, 1, wr, 1, &a, sizeof(a), nullptr)) return rc;
+        kernels++;
+    }
+    {
+        acs_args_fc a = {g->out, g->pool, g->fc_w, g->fc_b, cur_c, g->classes};
+        const acs_seg r[3] = {seg(g->pool, 4ull * cur_c), seg(g->fc_w, 4ull * cur_c * g->classes),
+                              seg(g->fc_b, 4ull * g->classes)};
+        const acs_seg wr[1] = {seg(g->out, 4ull * g->classes)};
+        if (int rc = acs_submit(w, ACS_K_FC, r, 3, wr, 1, &a, sizeof(a), nullptr)) return rc;
+        kernels++;
+    }
+    if (n_kernels) *n_kernels = kernels;
+    return ACS_OK;
+}
+
 }  // extern "C"

@@ -30,6 +30,7 @@
 struct float4 {
     float x, y, z, w;
 };
+inline float4 make_float4(float x, float y, float z, float w) { return float4{x, y, z, w}; }
 struct uint4 {
     uint32_t x, y, z, w;
 };
@@ -109,6 +110,36 @@ inline int __builtin_amdgcn_readlane(int v, int l)
     const int r = (int)(uint32_t)w.vals[l];
     w.bar.arrive_and_wait();
     return r;
+}
+
+// 16x16x4 FP32 matrix step: lane l supplies A(l % 16, l / 16) and
+// B(l / 16, l % 16) and holds C(4 (l / 16) + r, l % 16) in element r.
+typedef float acs_sim_v4f __attribute__((ext_vector_type(4)));
+inline acs_sim_v4f __builtin_amdgcn_mfma_f32_16x16x4f32(float a, float b, acs_sim_v4f c, int, int, int)
+{
+    acs_sim::Wave &w = acs_sim::group->waves[acs_sim::tid / 64];
+    const uint32_t lane = acs_sim::tid % 64;
+    uint32_t ab[2];
+    memcpy(&ab[0], &a, 4);
+    memcpy(&ab[1], &b, 4);
+    w.vals[lane] = ((uint64_t)ab[1] << 32) | ab[0];
+    w.bar.arrive_and_wait();
+    acs_sim_v4f d = c;
+    for (int r = 0; r < 4; r++) {
+        const uint32_t i = 4 * (lane / 16) + r, j = lane % 16;
+        float acc = 0.0f;
+        for (uint32_t k = 0; k < 4; k++) {
+            const uint32_t la = i + 16 * k, lb = j + 16 * k;
+            const uint32_t ua = (uint32_t)w.vals[la], ub = (uint32_t)(w.vals[lb] >> 32);
+            float fa, fb;
+            memcpy(&fa, &ua, 4);
+            memcpy(&fb, &ub, 4);
+            acc += fa * fb;
+        }
+        d[r] += acc;
+    }
+    w.bar.arrive_and_wait();
+    return d;
 }
 
 inline void __builtin_amdgcn_wave_barrier() { acs_sim::group->waves[acs_sim::tid / 64].bar.arrive_and_wait(); }

@@ -315,3 +315,76 @@ def test_rl_layout_is_contiguous_and_aligned():
         acs.rl_layout(1)
     with pytest.raises(acs.AcsError):
         acs.rl_layout(2000)
+
+
+# ---------------------------------------------------------------------------
+# the native DNN driver's ranges, on the manual path (no GPU, no memory touched)
+# ---------------------------------------------------------------------------
+def fake_dnn_graph(cells, classes):
+    """A graph whose tensors are disjoint fake address ranges."""
+    nxt = [1 << 40]
+
+    def alloc(nbytes):
+        p = nxt[0]
+        nxt[0] += (nbytes + 4095) // 4096 * 4096 + 4096
+        return p
+    g = acs.DNNGraphC()
+    g.n_cells, g.classes = len(cells), classes
+    h0, c0 = cells[0][0], cells[0][1]
+    g.x = alloc(4 * h0 * h0 * c0)
+    for c, (h, cin, cout, st) in enumerate(cells):
+        L = g.cell[c]
+        L.hin, L.cin, L.cout, L.stride = h, cin, cout, st
+        L.w3, L.b3 = alloc(36 * cin * cout), alloc(4 * cout)
+        L.w1, L.b1 = alloc(4 * cin * cout), alloc(4 * cout)
+        ho = h // st
+        L.t3, L.t1, L.y = (alloc(4 * ho * ho * cout) for _ in range(3))
+    g.pool = alloc(4 * cells[-1][2])
+    g.fc_w, g.fc_b, g.out = alloc(4 * cells[-1][2] * classes), alloc(4 * classes), alloc(4 * classes)
+    return g
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 5])
+def test_dnn_driver_dependencies_match_oracle_dataflow(seed):
+    inp = inputs.dnn_input(seed)
+    net = O.DNN(inputs.dnn_weights(), inp, inputs.DNN_CELLS)
+    adj = O.dag(net.accesses())
+    n = len(net.kernels())
+    W = 16
+    w = manual(W, trace=True, queue_depth=4096)
+    g = fake_dnn_graph(inputs.DNN_CELLS, inputs.DNN_CLASSES)
+    lg = np.ascontiguousarray(inp.logits, np.float32).reshape(-1)
+    cnt = acs.C.c_uint64()
+    assert acs.lib().acs_dnn_submit(w.handle, acs.C.byref(g), lg.ctypes.data, acs.C.byref(cnt)) == 0
+    assert cnt.value == n
+    rng = np.random.default_rng(seed)
+    window, running, done, nxt = [], set(), set(), 0
+    while len(done) < n:
+        while nxt < n and len(window) < W:
+            window.append(nxt)
+            nxt += 1
+        got = sorted(w.take_ready())
+        assert got == reference_ready(adj, window, running)
+        running |= set(got)
+        j = sorted(running)[int(rng.integers(len(running)))]
+        w.complete(j)
+        running.discard(j)
+        window.remove(j)
+        done.add(j)
+    assert w.sync() == 0
+    code, msg = O.check_trace(net.accesses(), W, w.trace())
+    w.destroy()
+    assert code == 0, msg
+
+
+def test_conv_argument_checks():
+    w = manual(4)
+    good = acs.ArgsConv(1 << 20, 2 << 20, 3 << 20, 4 << 20, 8, 32, 32, 3, 1)
+    rc, _ = w.submit_raw(acs.K_CONV, [], [(4 << 20, 4)], bytes(good))
+    assert rc == acs.OK
+    for field, val in (("k", 2), ("stride", 3), ("cin", 16), ("cout", 48), ("hin", 4)):
+        a = acs.ArgsConv(1 << 20, 2 << 20, 3 << 20, 4 << 20, 8, 32, 32, 3, 1)
+        setattr(a, field, val)
+        rc, _ = w.submit_raw(acs.K_CONV, [], [(4 << 20, 4)], bytes(a))
+        assert rc == acs.EINVAL, field
+    w.destroy()
