@@ -173,6 +173,34 @@ __device__ inline int32_t block_exclusive_scan(int32_t *data, int32_t n, int32_t
     return total;
 }
 
+// Wave-level helpers for scenes of at most 64 bodies (one lane per body).
+// The wave index comes from readfirstlane so that branches on it are uniform
+// to the compiler as well.
+__device__ inline int32_t wave_index() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
+__device__ inline uint64_t lane_read64(uint64_t x, int32_t l)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline float lane_readf(float x, int32_t l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l)); }
+
+// exclusive prefix sum over the wave's lanes in lane order; *total = sum of all
+__device__ inline int32_t wave_exclusive_scan(int32_t x, int32_t *total)
+{
+    const int32_t lane = threadIdx.x & 63;
+    int32_t inc = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t y = __shfl_up(inc, (unsigned)d, 64);
+        if (lane >= d) inc += y;
+    }
+    *total = __shfl(inc, 63, 64);
+    return inc - x;
+}
+
 __device__ inline void body_rl_predict(const acs_args_rl &a, uint32_t piece, uint32_t np)
 {
     RLView v = rl_view(a.base, a.n);
@@ -193,10 +221,47 @@ __device__ inline void body_rl_predict(const acs_args_rl &a, uint32_t piece, uin
 // one thread per (body, chunk), so that every thread of the workgroup works;
 // chunk counts give each thread its write position, which keeps the
 // adjacency in partner order.
+// At most 64 bodies: lane i holds body i in every wave; wave w tests the
+// partners j = w, w + 4, ... against all bodies at once, and the ballot of the
+// contact test is body j's neighbour set (the test is symmetric bit for bit:
+// the differences only change sign).  Wave 0 then writes degrees, offsets and
+// the adjacency in ascending partner order.
+__device__ inline void broadphase_small(const acs_args_rl &a, const RLView &v, uint8_t *smem)
+{
+    const int32_t n = a.n, lane = threadIdx.x & 63, wv = wave_index();
+    uint64_t *rows = reinterpret_cast<uint64_t *>(smem);   // [64]
+    const bool in = lane < n;
+    const float4 pi = in ? v.P[lane] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const float two_r = 2.0f * a.r, thr = two_r * two_r;
+    for (int32_t j = wv; j < n; j += 4) {
+        const float xj = lane_readf(pi.x, j), yj = lane_readf(pi.y, j), zj = lane_readf(pi.z, j);
+        const bool hit = in && lane != j && dist2(pi.x - xj, pi.y - yj, pi.z - zj) < thr;
+        const uint64_t row = __builtin_amdgcn_ballot_w64(hit);
+        if (lane == 0) rows[j] = row;
+    }
+    __syncthreads();
+    if (wv != 0) return;
+    const uint64_t mine = in ? rows[lane] : 0ull;
+    const int32_t deg = __builtin_popcountll(mine);
+    int32_t total;
+    const int32_t off = wave_exclusive_scan(deg, &total);
+    if (in) {
+        v.deg[lane] = deg;
+        v.adj_off[lane] = off;
+    }
+    if (lane == 0) v.adj_off[n] = total;
+    int32_t k = off;
+    for (uint64_t m = mine; m; m &= m - 1) v.adj[k++] = __builtin_ctzll(m);
+}
+
 __device__ inline void body_rl_broadphase(const acs_args_rl &a, uint8_t *smem)
 {
     const int32_t n = a.n, t = threadIdx.x;
     RLView v = rl_view(a.base, n);
+    if (n <= 64) {
+        broadphase_small(a, v, smem);
+        return;
+    }
     float4 *Ps = reinterpret_cast<float4 *>(smem);                 // 16 n bytes
     int32_t *cnt = reinterpret_cast<int32_t *>(smem + 16 * n);     // max(n, 256) ints
     int32_t *deg = cnt + (n > ACS_BLOCK ? n : ACS_BLOCK);          // n ints
@@ -270,11 +335,105 @@ __device__ inline void body_rl_broadphase(const acs_args_rl &a, uint8_t *smem)
 // body with the smallest body of its component), then islands ordered by that
 // smallest body, bodies inside an island in index order, the adjacency in
 // permuted positions, and the plan of multi-body islands for the host.
+// At most 64 bodies, one wave: neighbour sets as 64-bit masks, components by
+// Warshall's transitive closure (row k is final once step k has run, so all
+// lanes update in parallel), each body's island is its closure and its label
+// the closure's smallest body.  Positions: islands in label order, bodies in
+// index order inside an island.
+__device__ inline void islands_small(const acs_args_rl &a, const RLView &v, int32_t *plan, uint8_t *smem)
+{
+    if (wave_index() != 0) return;
+    const int32_t n = a.n, lane = threadIdx.x & 63;
+    const bool in = lane < n;
+    int32_t *s_perm = reinterpret_cast<int32_t *>(smem);   // [64] body at each position
+    int32_t *s_inv = s_perm + 64;                          // [64] position of each body
+    const int32_t cap = n * (n - 1);
+    int32_t o0 = 0, o1 = 0;
+    if (in) {
+        o0 = v.adj_off[lane];
+        o1 = v.adj_off[lane + 1];
+        o0 = o0 < 0 ? 0 : (o0 > cap ? cap : o0);
+        o1 = o1 < o0 ? o0 : (o1 > cap ? cap : o1);
+    }
+    uint64_t reach = in ? (1ull << lane) : 0ull;
+    for (int32_t k = o0; k < o1; k++) {
+        const int32_t c = v.adj[k];
+        if ((uint32_t)c < (uint32_t)n) reach |= 1ull << c;
+    }
+    for (int32_t k = 0; k < n; k++) {
+        const uint64_t rk = lane_read64(reach, k);
+        if ((reach >> k) & 1ull) reach |= rk;
+    }
+    const int32_t root = in ? __builtin_ctzll(reach) : lane;
+    const bool isroot = in && root == lane;
+    const uint64_t roots = __builtin_amdgcn_ballot_w64(isroot);
+    const int32_t nisl = __builtin_popcountll(roots);
+    const int32_t size = __builtin_popcountll(reach);
+    // first position of each island: sizes of the islands with smaller labels
+    int32_t start = 0, run = 0;
+    for (uint64_t rm = roots; rm; rm &= rm - 1) {
+        const int32_t r = __builtin_ctzll(rm);
+        if (root == r) start = run;
+        run += __builtin_popcountll(lane_read64(reach, r));
+    }
+    const uint64_t below = (1ull << lane) - 1ull;   // lane 0: empty
+    const int32_t pos = start + __builtin_popcountll(reach & below);
+    const int32_t ridx = __builtin_popcountll(roots & ((1ull << root) - 1ull));
+    if (in) {
+        v.label[lane] = root;
+        v.perm[pos] = lane;
+        v.inv_perm[lane] = pos;
+        s_perm[pos] = lane;
+        s_inv[lane] = pos;
+    }
+    if (isroot) v.isl_off[ridx] = start;
+    if (lane == 0) v.isl_off[nisl] = n;
+    // the stores above land before the loads below (one wave, LDS in order)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int32_t b = in ? s_perm[lane] : 0;           // body at position `lane`
+    const int32_t db = __shfl(o1 - o0, b, 64);
+    const int32_t ob = __shfl(o0, b, 64);
+    int32_t ep;
+    const int32_t poff = wave_exclusive_scan(in ? db : 0, &ep);
+    if (in) v.padj_off[lane] = poff;
+    if (lane == 0) v.padj_off[n] = ep;
+    for (int32_t k = 0; in && k < db; k++) {
+        const int32_t c = v.adj[ob + k];
+        if (poff + k < cap) v.padj[poff + k] = ((uint32_t)c < (uint32_t)n) ? s_inv[c] : lane;
+    }
+    // plan: multi-body islands in label order
+    const bool multi = isroot && size >= 2;
+    const uint64_t multis = __builtin_amdgcn_ballot_w64(multi);
+    const int32_t e0 = __shfl(poff, start & 63, 64);
+    const int32_t endp = start + size;
+    const int32_t e1s = __shfl(poff, endp & 63, 64);   // every lane takes part in the shuffle
+    const int32_t e1 = endp < n ? e1s : ep;
+    if (multi) {
+        const int32_t m = __builtin_popcountll(multis & below);
+        plan[4 + 4 * m + 0] = start;
+        plan[4 + 4 * m + 1] = endp;
+        plan[4 + 4 * m + 2] = e0;
+        plan[4 + 4 * m + 3] = e1;
+    }
+    if (lane == 0) {
+        plan[0] = nisl;
+        plan[1] = __builtin_popcountll(multis);
+        plan[2] = ep;
+        plan[3] = 0;
+    }
+}
+
 __device__ inline void body_rl_islands(const acs_args_rl &a, uint8_t *smem)
 {
     const int32_t n = a.n, t = threadIdx.x;
     RLView v = rl_view(a.base, n);
     int32_t *plan = reinterpret_cast<int32_t *>(a.plan);
+    if (n <= 64) {
+        islands_small(a, v, plan, smem);
+        return;
+    }
     int32_t *lab = reinterpret_cast<int32_t *>(smem);   // n
     int32_t *aoff = lab + n;                            // n + 1
     int32_t *ridx = aoff + n + 1;                       // n: island index of each root

@@ -179,7 +179,6 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
     uint64_t wmask[kSegs];
 #pragma unroll
     for (int m = 0; m < kSegs; m++) wmask[m] = 0;
-    uint32_t nsl = 0;   // segments of this lane's slot
 
     if (lane == 0) __hip_atomic_store(&p.ctrl->alive, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 
@@ -199,11 +198,6 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
         const uint32_t ftail = uni32(LDS_LOAD(&fs->tail));
         if (head != ftail && valid != full) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            // segment positions in use by any occupied slot
-            uint32_t mtop = 0;
-#pragma unroll
-            for (int m = 0; m < kSegs; m++)
-                if (__builtin_amdgcn_ballot_w64(nsl > (uint32_t)m)) mtop = m + 1;
             for (uint32_t budget = kAdmitBatch; head != ftail && valid != full && budget > 0; budget--) {
                 const DevDesc *d = &fs->ring[head % kLdsRing];
                 // one LDS read brings the whole descriptor into the wave: lane
@@ -231,12 +225,16 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                     const bool kin = rep < R && k < nseg;
                     const uint32_t kk = kin ? k : 0u;
                     const uint64_t a0 = kin ? d->s[kk] : 0ull, a1 = kin ? d->e[kk] : 0ull;
-                    const bool wk = kin && ((wb >> kk) & 1u);
+                    // lanes whose new range is a write: they match any slot range
+                    const uint64_t wkm = __builtin_amdgcn_ballot_w64(kin && ((wb >> kk) & 1u));
+                    // all eight positions, no branch: unused positions hold the empty
+                    // range; on the window wave a branch per position costs more than
+                    // the two compares it would skip.  The compares go straight into
+                    // lane masks; the rest is scalar.
 #pragma unroll
                     for (int m = 0; m < kSegs; m++)
-                        if ((uint32_t)m < mtop)
-                            hits |= __builtin_amdgcn_ballot_w64(a0 < se[m] && a1 > ss[m]) &
-                                    (__builtin_amdgcn_ballot_w64(wk) | wmask[m]);
+                        hits |= __builtin_amdgcn_ballot_w64(a0 < se[m]) & __builtin_amdgcn_ballot_w64(a1 > ss[m]) &
+                                (wkm | wmask[m]);
                 }
                 // fold the replicas' lanes onto their slots; the new slot's own
                 // lanes may already hold its ranges: only occupied slots count
@@ -250,9 +248,8 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                         ss[m] = d->s[m];
                         se[m] = d->e[m];
                     }
-                    nsl = nseg;
                 }
-                checks += (uint64_t)__builtin_popcountll(valid) * nseg * mtop;
+                checks += (uint64_t)__builtin_popcountll(valid) * nseg * kSegs;
                 if ((int)lane == slot) {
                     up = upm;
                     myseq = seq;
@@ -265,7 +262,6 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
 #pragma unroll
                 for (int m = 0; m < kSegs; m++)
                     wmask[m] = ((uint32_t)m < nseg && ((wb >> m) & 1u)) ? (wmask[m] | rbit) : (wmask[m] & ~rbit);
-                mtop = nseg > mtop ? nseg : mtop;
                 if (tr && lane == 0 && seq < p.trace_cap) {
                     acs_trace_rec *r = &p.trace[seq];
                     r->seq = (int64_t)seq;
@@ -309,7 +305,6 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                 if (((done >> rslot) & 1ull) && rep < R) {
 #pragma unroll
                     for (int m = 0; m < kSegs; m++) ss[m] = se[m] = 0;
-                    nsl = 0;
                 }
                 const uint64_t rdone = done * repmul;
 #pragma unroll

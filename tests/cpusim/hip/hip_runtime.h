@@ -154,6 +154,32 @@ inline int __builtin_amdgcn_readfirstlane(int v)
     return r;
 }
 
+inline int __shfl(int v, int src, int width)
+{
+    (void)width;
+    acs_sim::Wave &w = acs_sim::group->waves[acs_sim::tid / 64];
+    const uint32_t lane = acs_sim::tid % 64;
+    w.vals[lane] = (uint32_t)v;
+    w.bar.arrive_and_wait();
+    const int r = (int)(uint32_t)w.vals[(uint32_t)src & 63u];
+    w.bar.arrive_and_wait();
+    return r;
+}
+
+inline int __float_as_int(float x)
+{
+    int r;
+    memcpy(&r, &x, 4);
+    return r;
+}
+
+inline float __int_as_float(int x)
+{
+    float r;
+    memcpy(&r, &x, 4);
+    return r;
+}
+
 inline int __shfl_up(int v, unsigned d, int width)
 {
     (void)width;

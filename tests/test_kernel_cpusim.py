@@ -128,3 +128,48 @@ def test_conv_tile_through_kernel_source(sim, h, cin, cout, k, s):
     assert sim.sim_run(4, 2, 1, descs, 4, None, 60.0, C.byref(retired)) == 0
     assert retired.value == 1
     assert np.all(np.abs(out.astype(np.float64) - exact) <= 1e-5 * np.maximum(np.abs(exact), mag))
+
+
+@pytest.mark.timeout(180, method="thread")
+@pytest.mark.parametrize("n", [8, 33, 64, 80])
+def test_rl_prefix_through_kernel_source(sim, n):
+    """predict, broadphase, islands and permute of one RL step through the
+    kernel source (the one-wave paths for at most 64 bodies, the workgroup
+    paths above), against the oracle's step: integer buffers bit-exact."""
+    sc = inputs.rl_scene(seed=11, n=n)
+    off = acs.rl_layout(n)
+    arena = np.zeros(int(off[acs.RL_END]), np.uint8)
+    plan = np.zeros(acs.rl_plan_ints(n), np.int32)
+
+    def region(r, dtype, count):
+        return arena[int(off[r]):int(off[r]) + np.dtype(dtype).itemsize * count].view(dtype)
+    region(acs.RL_X, np.float32, 4 * n)[:] = sc.x.reshape(-1)
+    region(acs.RL_V, np.float32, 4 * n)[:] = sc.v.reshape(-1)
+    kids = [acs.K_RL_PREDICT, acs.K_RL_BROADPHASE, acs.K_RL_ISLANDS, acs.K_RL_PERMUTE]
+    descs = (SimDesc * len(kids))()
+    for i, kid in enumerate(kids):
+        a = acs.ArgsRL()
+        a.base, a.plan, a.n, a.r, a.dt = arena.ctypes.data, plan.ctypes.data, n, float(sc.radius), float(sc.dt)
+        d = descs[i]
+        d.kid, d.npieces, d.nseg, d.wbits = kid, 1, 1, 1
+        d.s[0], d.e[0] = arena.ctypes.data, arena.ctypes.data + arena.nbytes   # one chain
+        C.memmove(d.args, bytes(a), C.sizeof(a))
+    retired = C.c_uint64()
+    assert sim.sim_run(4, 2, len(kids), descs, 8, None, 120.0, C.byref(retired)) == 0
+    ref = O.Scene.from_inputs(sc)
+    for op in (O.RL_PREDICT, O.RL_BROADPHASE, O.RL_ISLANDS, O.RL_PERMUTE):
+        ref.run_kernel(op)
+    assert np.array_equal(region(acs.RL_P, np.uint32, 4 * n), ref.P.view(np.uint32).reshape(-1))
+    for r, name, cnt in ((acs.RL_DEG, "deg", n), (acs.RL_ADJ_OFF, "adj_off", n + 1), (acs.RL_LABEL, "label", n),
+                         (acs.RL_PERM, "perm", n), (acs.RL_INV_PERM, "inv_perm", n),
+                         (acs.RL_PADJ_OFF, "padj_off", n + 1)):
+        assert np.array_equal(region(r, np.int32, cnt), getattr(ref, name)[:cnt]), name
+    e = int(ref.adj_off[n])
+    assert np.array_equal(region(acs.RL_ADJ, np.int32, e), ref.adj[:e])
+    assert np.array_equal(region(acs.RL_PADJ, np.int32, e), ref.padj[:e])
+    k = int(ref.meta[0])
+    assert np.array_equal(region(acs.RL_ISL_OFF, np.int32, k + 1), ref.isl_off[:k + 1])
+    m = int(ref.meta[1])
+    assert plan[0] == ref.meta[0] and plan[1] == ref.meta[1] and plan[2] == ref.meta[2]
+    assert np.array_equal(plan[4:4 + 4 * m], ref.plan[:4 * m])
+    assert np.array_equal(region(acs.RL_Q0, np.uint32, 4 * n), ref.Q0.view(np.uint32).reshape(-1))
