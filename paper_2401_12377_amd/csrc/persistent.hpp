@@ -32,7 +32,9 @@
 namespace acs {
 
 constexpr uint32_t kLdsRing = 16;   // descriptors staged in LDS
-constexpr uint32_t kAdmitBatch = 16; // insertions per pass of the window loop
+constexpr uint32_t kAdmitBatch = 16; // insertions per pass of the window loop while workers are busy
+constexpr uint32_t kAdmitFew = 2;     // ... and while fewer than kBusyKernels kernels are out
+constexpr uint32_t kBusyKernels = 4;
 
 struct FetchShared {
     uint32_t tail;       // descriptors staged (written by the FIFO wave)
@@ -72,16 +74,29 @@ __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
     const uint32_t lane = threadIdx.x & 63u;
     uint64_t consumed = 0, htail = 0;
     uint32_t ftail = 0;
+    bool idle = true;
     for (;;) {
         if (uni32(LDS_LOAD(&fs->exit))) break;
         const uint32_t head = uni32(LDS_LOAD(&fs->head));
         const uint32_t space = kLdsRing - (ftail - head);
         bool moved = false;
-        if (space > 0) {
-            if (consumed == htail) {
-                htail = uni64(__hip_atomic_load(&p.ctrl->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
-                if (htail != consumed) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+        uint64_t st = 0;
+        if (consumed == htail || idle) {
+            // the host's line holds tail, stop and the snapshot request: the three
+            // loads are issued together, one round trip to host memory
+            const uint64_t t = __hip_atomic_load(&p.ctrl->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            const uint64_t s0 = __hip_atomic_load(&p.ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            const uint64_t sr = __hip_atomic_load(&p.ctrl->snap_req, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            htail = uni64(t);
+            st = uni64(s0);
+            const uint64_t sru = uni64(sr);
+            if (lane == 0) {
+                LDS_STORE(&fs->stop, (uint32_t)st);
+                LDS_STORE(&fs->snap_req, sru);
             }
+            if (htail != consumed) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+        }
+        if (space > 0) {
             const uint64_t avail = htail - consumed;
             const uint32_t n = avail < space ? (uint32_t)avail : space;
             if (n > 0) {
@@ -118,15 +133,10 @@ __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
                 moved = true;
             }
         }
+        idle = !moved;
         if (!moved) {
-            const uint64_t st = uni64(__hip_atomic_load(&p.ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
-            const uint64_t sr = uni64(__hip_atomic_load(&p.ctrl->snap_req, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
-            if (lane == 0) {
-                LDS_STORE(&fs->stop, (uint32_t)st);
-                LDS_STORE(&fs->snap_req, sr);
-            }
             if (st == 2) break;   // host abort: leave even if the window wave is gone
-            __builtin_amdgcn_s_sleep(2);
+            __builtin_amdgcn_s_sleep(1);
         }
     }
 }
@@ -193,12 +203,14 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
         const bool mine = (exec >> lane) & 1ull;
         const uint32_t cdone = mine ? __hip_atomic_load(&p.st->done[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
 
-        // ---- admission in program order while a slot is free, at most
-        // kAdmitBatch per pass
+        // ---- admission in program order while a slot is free, a bounded
+        // number per pass
         const uint32_t ftail = uni32(LDS_LOAD(&fs->tail));
         if (head != ftail && valid != full) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            for (uint32_t budget = kAdmitBatch; head != ftail && valid != full && budget > 0; budget--) {
+            // with few kernels out, dispatch soon rather than admit a long run first
+            const uint32_t batch = (uint32_t)__builtin_popcountll(exec) < kBusyKernels ? kAdmitFew : kAdmitBatch;
+            for (uint32_t budget = batch; head != ftail && valid != full && budget > 0; budget--) {
                 const DevDesc *d = &fs->ring[head % kLdsRing];
                 // one LDS read brings the whole descriptor into the wave: lane
                 // i holds its 4-byte word i; fields are taken with readlane
