@@ -90,7 +90,8 @@ typedef struct {
     int32_t trace;           /* 1: record a per-kernel trace (see acs_trace_read) */
     int32_t trace_capacity;  /* kernels the trace can hold (default 1 << 16) */
     int32_t device;          /* HIP device ordinal (default 0) */
-    int32_t reserved[7];
+    int32_t n_groups;        /* independent windows of W slots each (default 1; see acs_submit_group) */
+    int32_t reserved[6];
 } acs_config;
 
 /* One entry of the scheduled list (Section IV-C): the kernels currently in the
@@ -159,6 +160,27 @@ int acs_sync(acs_window *w);
 
 /* As acs_sync but gives up after timeout_ns nanoseconds (ACS_ETIMEDOUT). */
 int acs_sync_timeout(acs_window *w, uint64_t timeout_ns);
+
+/* Window groups, for many independent task graphs in one launch.  With
+ * acs_config.n_groups = G > 1 the window is G independent windows of W slots
+ * each (the device path needs G * pow2(W) <= 64; G <= 8); acs_submit is
+ * acs_submit_group(w, 0, ...).  Kernels of one group are scheduled exactly
+ * as in a single window, in their submission order.  Kernels of different
+ * groups are never checked against each other: the caller guarantees that
+ * no kernel reads or writes bytes that a kernel of another group writes
+ * while both can be in flight (graphs on disjoint memory, as separate
+ * streams would be).  The in-order and plain paths run all groups through
+ * one stream or one host window, which is valid under the same guarantee.
+ * Sequence numbers are shared by all groups.  ACS_EINVAL for a group outside
+ * [0, G). */
+int acs_submit_group(acs_window *w, int32_t group, int32_t kernel_id,
+                     const acs_seg *read_segs, int32_t n_read,
+                     const acs_seg *write_segs, int32_t n_write,
+                     const void *args, size_t args_size, uint64_t *seq_out);
+
+/* Waits until every kernel submitted to `group` has completed (the other
+ * groups keep running).  Same return values as acs_sync_timeout (0 = no limit). */
+int acs_sync_group(acs_window *w, int32_t group, uint64_t timeout_ns);
 
 /* Copies up to cap entries of the scheduled list into out (oldest first). */
 int acs_scheduled_list(acs_window *w, acs_entry *out, int32_t cap, int32_t *n_out);

@@ -54,6 +54,18 @@ typedef struct {
  * Returns the first error. */
 int acs_rl_run(acs_window *w, const acs_rl_scene *scene, int32_t steps, double *step_ns, acs_rl_counts *counts);
 
+/* Batched scenes (many independent input-dependent graphs in one launch):
+ * n_scenes scenes with disjoint arenas, scene i in window group i % n_groups
+ * (the window must have acs_config.n_groups >= n_groups; use 1 on paths
+ * without groups).  Per batched step: every scene's predict, broadphase,
+ * islands and permute are submitted; then, group by group, the group is
+ * drained, its scenes' plans read and their Jacobi and integrate kernels
+ * submitted.  step_ns (if not NULL, `steps` entries) receives the wall time
+ * of each batched step, which then ends with a full drain; counts the work
+ * summed over scenes. */
+int acs_rl_run_batch(acs_window *w, const acs_rl_scene *scenes, int32_t n_scenes, int32_t n_groups, int32_t steps,
+                     double *step_ns, acs_rl_counts *counts);
+
 /* Overhead probe: n no-op kernels, each spinning spin_ns on the device.
  * chain = 0: all independent (distinct one-byte write ranges);
  * chain = 1: each reads and writes the same byte (a serial chain).

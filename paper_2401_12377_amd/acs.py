@@ -50,7 +50,8 @@ class Seg(C.Structure):
 class Config(C.Structure):
     _fields_ = [("path", C.c_int32), ("n_streams", C.c_int32), ("wg_per_task", C.c_int32), ("n_workers", C.c_int32),
                 ("queue_depth", C.c_int32), ("nonblocking", C.c_int32), ("trace", C.c_int32),
-                ("trace_capacity", C.c_int32), ("device", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("trace_capacity", C.c_int32), ("device", C.c_int32), ("n_groups", C.c_int32),
+                ("reserved", C.c_int32 * 6)]
 
 
 class Entry(C.Structure):
@@ -184,10 +185,15 @@ def lib():
         L.acs_rl_run.argtypes = [C.c_void_p, P(RLSceneC), C.c_int32, P(C.c_double), P(RLCounts)]
         L.acs_nop_run.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, P(C.c_double)]
         L.acs_dnn_submit.argtypes = [C.c_void_p, P(DNNGraphC), C.c_void_p, P(C.c_uint64)]
+        L.acs_submit_group.argtypes = [C.c_void_p, C.c_int32, C.c_int32, P(Seg), C.c_int32, P(Seg), C.c_int32,
+                                       C.c_void_p, C.c_size_t, P(C.c_uint64)]
+        L.acs_sync_group.argtypes = [C.c_void_p, C.c_int32, C.c_uint64]
+        L.acs_rl_run_batch.argtypes = [C.c_void_p, P(RLSceneC), C.c_int32, C.c_int32, C.c_int32, P(C.c_double),
+                                       P(RLCounts)]
         for f in ("acs_window_configure", "acs_submit", "acs_sync", "acs_sync_timeout", "acs_scheduled_list",
                   "acs_trace_read", "acs_stats_get", "acs_window_destroy", "acs_window_stop", "acs_manual_take_ready",
                   "acs_manual_complete", "acs_last_error", "acs_rl_layout", "acs_host_free", "acs_rl_run",
-                  "acs_nop_run", "acs_dnn_submit"):
+                  "acs_nop_run", "acs_dnn_submit", "acs_submit_group", "acs_sync_group", "acs_rl_run_batch"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -215,7 +221,7 @@ class Window:
 
     def __init__(self, W: int, path: str = "device", n_streams: int = 4, wg_per_task: int = 1, n_workers: int = 0,
                  queue_depth: int = 4096, nonblocking: bool = False, trace: bool = False,
-                 trace_capacity: int = 1 << 16, device: int = 0):
+                 trace_capacity: int = 1 << 16, device: int = 0, n_groups: int = 1):
         L = lib()
         h = L.acs_window_create(W)
         if not h:
@@ -229,7 +235,8 @@ class Window:
         cfg.path = PATHS[path]
         cfg.n_streams, cfg.wg_per_task, cfg.n_workers = n_streams, wg_per_task, n_workers
         cfg.queue_depth, cfg.nonblocking, cfg.trace = queue_depth, int(nonblocking), int(trace)
-        cfg.trace_capacity, cfg.device = trace_capacity, device
+        cfg.trace_capacity, cfg.device, cfg.n_groups = trace_capacity, device, n_groups
+        self.n_groups = n_groups
         rc = L.acs_window_configure(h, C.byref(cfg))
         if rc < 0:
             msg = L.acs_strerror(rc).decode()
@@ -251,6 +258,18 @@ class Window:
         _check(lib().acs_submit(self.handle, kid, r, nr, w, nw, C.byref(args) if args is not None else None,
                                 C.sizeof(args) if args is not None else 0, C.byref(seq)))
         return seq.value
+
+    def submit_group(self, group: int, kid: int, reads, writes, args) -> int:
+        r, nr = _segs(reads)
+        w, nw = _segs(writes)
+        seq = C.c_uint64()
+        _check(lib().acs_submit_group(self.handle, group, kid, r, nr, w, nw,
+                                      C.byref(args) if args is not None else None,
+                                      C.sizeof(args) if args is not None else 0, C.byref(seq)))
+        return seq.value
+
+    def sync_group(self, group: int, timeout_ns: int = 0) -> int:
+        return _check(lib().acs_sync_group(self.handle, group, timeout_ns))
 
     def submit_raw(self, kid, reads, writes, args_bytes: bytes):
         """Like submit, with the argument block given as bytes (for tests)."""
@@ -477,6 +496,18 @@ def rl_run(win: Window, scene_gpu: RLSceneGPU, steps: int):
     step_ns = (C.c_double * max(1, steps))()
     k = RLCounts()
     _check(lib().acs_rl_run(win.handle, C.byref(sc), steps, step_ns, C.byref(k)))
+    return k.as_dict(), np.array(step_ns[:steps])
+
+
+def rl_run_batch(win: Window, scenes_gpu, steps: int, n_groups: int = 1):
+    """Runs `steps` batched steps of independent scenes (scene i in group
+    i % n_groups); returns (counts dict, per-batched-step ns)."""
+    arr = (RLSceneC * len(scenes_gpu))()
+    for i, g in enumerate(scenes_gpu):
+        arr[i] = g.c_struct()
+    step_ns = (C.c_double * max(1, steps))()
+    k = RLCounts()
+    _check(lib().acs_rl_run_batch(win.handle, arr, len(scenes_gpu), n_groups, steps, step_ns, C.byref(k)))
     return k.as_dict(), np.array(step_ns[:steps])
 
 

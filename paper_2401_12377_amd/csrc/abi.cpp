@@ -320,9 +320,11 @@ int ensure_started(acs_window *w)
     if (!w->configured) acs_config_default(&w->cfg);
     switch (w->cfg.path) {
     case ACS_PATH_INORDER: w->path = make_inorder_path(w->cfg); break;
-    case ACS_PATH_PLAIN: w->path = make_plain_path(w->W, w->cfg); break;
+    // groups share one host window on the plain and manual paths (valid
+    // because kernels of different groups touch disjoint memory)
+    case ACS_PATH_PLAIN: w->path = make_plain_path(std::min(ACS_W_MAX, w->W * w->cfg.n_groups), w->cfg); break;
     case ACS_PATH_DEVICE: w->path = make_device_path(w->W, w->cfg); break;
-    case ACS_PATH_MANUAL: w->path = make_manual_path(w->W, w->cfg); break;
+    case ACS_PATH_MANUAL: w->path = make_manual_path(std::min(ACS_W_MAX, w->W * w->cfg.n_groups), w->cfg); break;
     default: return fail(ACS_EINVAL, "unknown path");
     }
     const int rc = w->path->start();
@@ -350,6 +352,7 @@ void acs_config_default(acs_config *cfg)
     cfg->trace = 0;
     cfg->trace_capacity = 1 << 16;
     cfg->device = 0;
+    cfg->n_groups = 1;
 }
 
 acs_window *acs_window_create(int32_t W)
@@ -379,6 +382,13 @@ int acs_window_configure(acs_window *w, const acs_config *cfg)
     if (cfg->queue_depth < 1 || cfg->queue_depth > (1 << 20)) return fail(ACS_EINVAL, "queue_depth must be in [1, 2^20]");
     if (cfg->trace && (cfg->trace_capacity < 1 || cfg->trace_capacity > (1 << 24)))
         return fail(ACS_EINVAL, "trace_capacity must be in [1, 2^24]");
+    if (cfg->n_groups < 1 || cfg->n_groups > 8) return fail(ACS_EINVAL, "n_groups must be in [1, 8]");
+    if (cfg->path == ACS_PATH_DEVICE) {
+        int32_t wp = 1;
+        while (wp < w->W) wp <<= 1;
+        if (wp * cfg->n_groups > ACS_W_MAX)
+            return fail(ACS_EINVAL, "device path: n_groups times W rounded up to a power of two must be at most 64");
+    }
     w->cfg = *cfg;
     w->configured = true;
     return ensure_started(w);
@@ -387,9 +397,16 @@ int acs_window_configure(acs_window *w, const acs_config *cfg)
 int acs_submit(acs_window *w, int32_t kernel_id, const acs_seg *read_segs, int32_t n_read, const acs_seg *write_segs,
                int32_t n_write, const void *args, size_t args_size, uint64_t *seq_out)
 {
+    return acs_submit_group(w, 0, kernel_id, read_segs, n_read, write_segs, n_write, args, args_size, seq_out);
+}
+
+int acs_submit_group(acs_window *w, int32_t group, int32_t kernel_id, const acs_seg *read_segs, int32_t n_read,
+                     const acs_seg *write_segs, int32_t n_write, const void *args, size_t args_size, uint64_t *seq_out)
+{
     if (!w) return fail(ACS_EINVAL, "null window");
     if (w->stopped) return fail(ACS_ESTATE, "window was stopped");
     if (int rc = ensure_started(w)) return rc;
+    if (group < 0 || group >= w->cfg.n_groups) return fail(ACS_EINVAL, "group outside [0, n_groups)");
     Desc d;
     bool lossy = false;
     std::string why;
@@ -397,7 +414,7 @@ int acs_submit(acs_window *w, int32_t kernel_id, const acs_seg *read_segs, int32
                        &why);
     if (rc != ACS_OK) return fail(rc, why);
     d.seq = w->next_seq;
-    rc = w->path->submit(d);
+    rc = w->path->submit_group(d, group);
     if (rc != ACS_OK) return rc;
     if (lossy) w->coalesced++;
     if (seq_out) *seq_out = d.seq;
@@ -417,6 +434,14 @@ int acs_sync_timeout(acs_window *w, uint64_t timeout_ns)
     if (!w) return fail(ACS_EINVAL, "null window");
     if (!w->started) return ACS_OK;
     return w->path->sync(timeout_ns == 0 ? 1 : timeout_ns);
+}
+
+int acs_sync_group(acs_window *w, int32_t group, uint64_t timeout_ns)
+{
+    if (!w) return fail(ACS_EINVAL, "null window");
+    if (group < 0 || group >= w->cfg.n_groups) return fail(ACS_EINVAL, "group outside [0, n_groups)");
+    if (!w->started) return ACS_OK;
+    return w->path->sync_group(group, timeout_ns);
 }
 
 int acs_scheduled_list(acs_window *w, acs_entry *out, int32_t cap, int32_t *n_out)

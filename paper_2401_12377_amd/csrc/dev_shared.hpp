@@ -33,22 +33,25 @@ struct DevDesc {
 static_assert(sizeof(DevDesc) == 256, "descriptor must be 256 bytes");
 constexpr uint32_t kDescCopyDwords = 54;   // dwords of DevDesc written by the host
 
-// Host-resident control block (pinned, coherent).  The first cache line is
-// written by the host, the rest by the device.
+constexpr int kMaxGroups = 8;   // independent windows served by one window wave
+
+// Host-resident control block (pinned, coherent).  The first 128 bytes are
+// written by the host (one tail per window group, then stop and the snapshot
+// request), the rest by the device.
 struct HostCtrl {
-    volatile uint64_t tail;       // descriptors published by the host
-    volatile uint64_t stop;       // 1: exit when idle, 2: abort now
-    volatile uint64_t snap_req;   // bumped by the host to ask for a window snapshot
-    uint64_t pad0[13];
-    volatile uint64_t consumed;   // descriptors copied off the ring by the device
-    volatile uint64_t retired;    // kernels completed
-    volatile uint64_t error;      // sticky device-side error code (0 = none)
-    volatile uint64_t snap_ack;   // last snapshot request served
-    volatile uint64_t snap_count; // entries in the snapshot
-    volatile uint64_t alive;      // set when the scheduler wave starts
-    volatile uint64_t exited;     // set when the scheduler wave leaves
-    volatile uint64_t checks;     // overlap tests made (statistics)
-    uint64_t pad1[8];
+    volatile uint64_t tail[kMaxGroups];     // descriptors published by the host, per group
+    volatile uint64_t stop;                 // 1: exit when idle, 2: abort now
+    volatile uint64_t snap_req;             // bumped by the host to ask for a window snapshot
+    uint64_t pad0[6];
+    volatile uint64_t consumed[kMaxGroups]; // descriptors copied off each group's ring by the device
+    volatile uint64_t retired[kMaxGroups];  // kernels completed, per group
+    volatile uint64_t error;                // sticky device-side error code (0 = none)
+    volatile uint64_t snap_ack;             // last snapshot request served
+    volatile uint64_t snap_count;           // entries in the snapshot
+    volatile uint64_t alive;                // set when the scheduler wave starts
+    volatile uint64_t exited;               // set when the scheduler wave leaves
+    volatile uint64_t checks;               // overlap tests made (statistics)
+    uint64_t pad1[2];
     acs_entry snap[ACS_W_MAX];
 };
 
@@ -85,13 +88,15 @@ struct DevState {
 
 struct DevParams {
     HostCtrl *ctrl;
-    DevDesc *ring;                // host-resident descriptor ring
+    DevDesc *ring;                // host-resident descriptor rings, group g at ring + g * (ring_mask + 1)
     DevState *st;
-    acs_trace_rec *trace;         // device trace (or null)
+    acs_trace_rec *trace;         // device trace (or null), indexed by sequence number
     uint32_t ring_mask;
     uint32_t trace_cap;
-    int32_t W;
+    int32_t W;                    // slots per group
     int32_t n_workers;
+    int32_t n_groups;             // independent windows, 1..kMaxGroups; n_groups * pow2(W) <= 64
+    int32_t pad;
 };
 
 }  // namespace acs

@@ -53,14 +53,15 @@ public:
         }
         n_workers_ = workers;
 
+        groups_ = std::max(1, std::min(cfg_.n_groups, kMaxGroups));
         ring_cap_ = pow2_at_least((uint32_t)std::max(16, cfg_.queue_depth));
         if ((e = hipHostMalloc((void **)&ctrl_, sizeof(HostCtrl), hipHostMallocCoherent | hipHostMallocMapped)) != hipSuccess)
             return hip_fail(e, "hipHostMalloc(ctrl)");
         memset((void *)ctrl_, 0, sizeof(HostCtrl));
-        if ((e = hipHostMalloc((void **)&ring_, sizeof(DevDesc) * ring_cap_, hipHostMallocCoherent | hipHostMallocMapped)) !=
-            hipSuccess)
+        const size_t ring_bytes = sizeof(DevDesc) * ring_cap_ * (size_t)groups_;
+        if ((e = hipHostMalloc((void **)&ring_, ring_bytes, hipHostMallocCoherent | hipHostMallocMapped)) != hipSuccess)
             return hip_fail(e, "hipHostMalloc(ring)");
-        memset((void *)ring_, 0, sizeof(DevDesc) * ring_cap_);
+        memset((void *)ring_, 0, ring_bytes);
         if ((e = hipMalloc((void **)&st_, sizeof(DevState))) != hipSuccess) return hip_fail(e, "hipMalloc(state)");
         if ((e = hipMemset(st_, 0, sizeof(DevState))) != hipSuccess) return hip_fail(e, "hipMemset(state)");
         if (cfg_.trace) {
@@ -83,6 +84,7 @@ public:
         p.trace_cap = trace_cap_;
         p.W = W_;
         p.n_workers = n_workers_;
+        p.n_groups = groups_;
         if ((e = hipEventCreate(&ev0_)) != hipSuccess) return hip_fail(e, "hipEventCreate");
         if ((e = hipEventCreate(&ev1_)) != hipSuccess) return hip_fail(e, "hipEventCreate");
         if ((e = hipEventRecord(ev0_, stream_)) != hipSuccess) return hip_fail(e, "hipEventRecord");
@@ -92,19 +94,21 @@ public:
         return ACS_OK;
     }
 
-    int submit(const Desc &d) override
+    int submit(const Desc &d) override { return submit_group(d, 0); }
+
+    int submit_group(const Desc &d, int32_t g) override
     {
         if (!running_) {
             set_error(ACS_ESTATE, "device path is not running");
             return ACS_ESTATE;
         }
-        // back-pressure: the ring holds at most ring_cap_ unconsumed
+        // back-pressure: each group's ring holds at most ring_cap_ unconsumed
         // descriptors.  The device-written counter is read only when the
         // cached value says the ring may be full (reading a line the device
         // keeps writing costs a cross-fabric miss).
-        while (submitted_ - consumed_seen_ >= ring_cap_) {
-            consumed_seen_ = __atomic_load_n(&ctrl_->consumed, __ATOMIC_ACQUIRE);
-            if (submitted_ - consumed_seen_ < ring_cap_) break;
+        while (submitted_[g] - consumed_seen_[g] >= ring_cap_) {
+            consumed_seen_[g] = __atomic_load_n(&ctrl_->consumed[g], __ATOMIC_ACQUIRE);
+            if (submitted_[g] - consumed_seen_[g] < ring_cap_) break;
             if (cfg_.nonblocking) {
                 set_error(ACS_EAGAIN, "input FIFO full");
                 return ACS_EAGAIN;
@@ -112,7 +116,7 @@ public:
             if (int rc = check_alive()) return rc;
             _mm_pause();
         }
-        DevDesc &r = ring_[submitted_ & (ring_cap_ - 1)];
+        DevDesc &r = ring_[(size_t)g * ring_cap_ + (submitted_[g] & (ring_cap_ - 1))];
         DevDesc tmp;
         memset(&tmp, 0, sizeof(tmp));
         tmp.seq = d.seq;
@@ -126,17 +130,25 @@ public:
         }
         memcpy(tmp.args, d.args, ACS_ARGS_MAX);
         memcpy((void *)&r, &tmp, sizeof(DevDesc));
-        submitted_++;
-        __atomic_store_n(&ctrl_->tail, submitted_, __ATOMIC_RELEASE);
+        submitted_[g]++;
+        total_submitted_++;
+        __atomic_store_n(&ctrl_->tail[g], submitted_[g], __ATOMIC_RELEASE);
         return ACS_OK;
     }
 
     int sync(uint64_t timeout_ns) override
     {
+        for (int32_t g = 0; g < groups_; g++)
+            if (int rc = sync_group(g, timeout_ns)) return rc;
+        return err_;
+    }
+
+    int sync_group(int32_t g, uint64_t timeout_ns) override
+    {
         if (!running_) return err_;
         const uint64_t t0 = now_ns();
         uint32_t spins = 0;
-        while (__atomic_load_n(&ctrl_->retired, __ATOMIC_ACQUIRE) < submitted_) {
+        while (__atomic_load_n(&ctrl_->retired[g], __ATOMIC_ACQUIRE) < submitted_[g]) {
             if (++spins % 4096 == 0) {
                 if (int rc = check_alive()) return rc;
                 if (timeout_ns && now_ns() - t0 > timeout_ns) {
@@ -179,7 +191,7 @@ public:
             if (n) *n = 0;
             return ACS_OK;
         }
-        const int64_t cnt = (int64_t)std::min<uint64_t>(submitted_, trace_cap_);
+        const int64_t cnt = (int64_t)std::min<uint64_t>(total_submitted_, trace_cap_);
         const int64_t c = std::min(cnt, cap);
         std::vector<acs_trace_rec> tmp((size_t)c);
         hipError_t e = hipMemcpy(tmp.data(), dtrace_, sizeof(acs_trace_rec) * (size_t)c, hipMemcpyDeviceToHost);
@@ -250,7 +262,9 @@ public:
 
     void stats(acs_stats &s) override
     {
-        s.retired = ctrl_ ? ctrl_->retired : submitted_;
+        uint64_t ret = 0;
+        for (int32_t g = 0; g < groups_; g++) ret += ctrl_ ? ctrl_->retired[g] : submitted_[g];
+        s.retired = ret;
         s.dispatched = s.retired;
         s.overlap_tests = running_ && ctrl_ ? ctrl_->checks : checks_;
         s.n_workers = n_workers_;
@@ -293,7 +307,9 @@ private:
     uint32_t ring_cap_ = 0, trace_cap_ = 0;
     int32_t n_workers_ = 0;
     int clock_khz_ = 100000;
-    uint64_t submitted_ = 0, consumed_seen_ = 0, snap_req_ = 0, checks_ = 0;
+    int32_t groups_ = 1;
+    uint64_t submitted_[kMaxGroups] = {}, consumed_seen_[kMaxGroups] = {};
+    uint64_t total_submitted_ = 0, snap_req_ = 0, checks_ = 0;
     int err_ = ACS_OK;
     bool running_ = false, leaked_ = false;
 };

@@ -62,19 +62,22 @@ __global__ __launch_bounds__(ACS_BLOCK) void k_persistent(DevParams p)
     __shared__ Mail mail;
     if (blockIdx.x == 0) {
         FetchShared *fs = reinterpret_cast<FetchShared *>(smem);
-        if (threadIdx.x == 0) {
-            fs->tail = 0;
-            fs->head = 0;
-            fs->stop = 0;
-            fs->exit = 0;
-            fs->snap_req = 0;
-        }
+        if (threadIdx.x == 0) fetch_init(fs);
         __syncthreads();
         const uint32_t wave = uni32(threadIdx.x) >> 6;   // uniform: whole waves take each branch
-        if (wave == 0)
-            window_wave(p, fs);
-        else if (wave == 1)
-            fifo_wave(p, fs);
+        // the smallest compiled group bound that covers the window's groups
+        const int32_t ng = p.n_groups;
+        if (wave == 0) {
+            if (ng <= 1) window_wave<1>(p, fs);
+            else if (ng <= 2) window_wave<2>(p, fs);
+            else if (ng <= 4) window_wave<4>(p, fs);
+            else window_wave<8>(p, fs);
+        } else if (wave == 1) {
+            if (ng <= 1) fifo_wave<1>(p, fs);
+            else if (ng <= 2) fifo_wave<2>(p, fs);
+            else if (ng <= 4) fifo_wave<4>(p, fs);
+            else fifo_wave<8>(p, fs);
+        }
         return;
     }
     worker(p, smem, &mail);

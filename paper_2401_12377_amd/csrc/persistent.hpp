@@ -12,9 +12,13 @@
 //           ballot of (valid, not executing, empty upstream mask); ready
 //           kernels are published, oldest first, as (slot, piece) entries of a
 //           work queue in device memory.
-//   wave 1  the input FIFO: copies descriptors from the host-resident ring
-//           into a small ring in LDS, so that host-memory latency never
+//   wave 1  the input FIFO: copies descriptors from the host-resident rings
+//           into small rings in LDS, so that host-memory latency never
 //           stalls the window loop.
+// The lanes of the window wave may be split into up to eight groups, each an
+// independent window with its own input ring (for many independent task
+// graphs in one launch): one insertion pass then admits one kernel into every
+// group that has one waiting, with the same instructions.
 // Workgroups 1.. are workers: each takes a ticket from the work queue, waits
 // for the entry with that ticket, runs one piece of the task body, and bumps
 // the slot's completion counter with release semantics.
@@ -31,21 +35,31 @@
 
 namespace acs {
 
-constexpr uint32_t kLdsRing = 16;   // descriptors staged in LDS
-constexpr uint32_t kAdmitBatch = 16; // insertions per pass of the window loop while workers are busy
+constexpr uint32_t kLdsDescs = 128;   // descriptors staged in LDS (32 KB), split evenly between groups
+constexpr uint32_t kAdmitBatch = 16;  // insertion passes per loop while workers are busy
 constexpr uint32_t kAdmitFew = 2;     // ... and while fewer than kBusyKernels kernels are out
 constexpr uint32_t kBusyKernels = 4;
 
 struct FetchShared {
-    uint32_t tail;       // descriptors staged (written by the FIFO wave)
-    uint32_t head;       // descriptors taken (written by the window wave)
-    uint32_t stop;       // mirror of the host stop flag
-    uint32_t exit;       // window wave -> FIFO wave: leave
-    uint64_t snap_req;   // mirror of the host snapshot request counter
-    uint64_t pad;
-    DevDesc ring[kLdsRing];
+    uint32_t tail[kMaxGroups];   // descriptors staged per group (written by the FIFO wave)
+    uint32_t head[kMaxGroups];   // descriptors taken per group (written by the window wave)
+    uint32_t stop;               // mirror of the host stop flag
+    uint32_t exit;               // window wave -> FIFO wave: leave
+    uint64_t snap_req;           // mirror of the host snapshot request counter
+    DevDesc ring[kLdsDescs];     // group g: ring[g * depth, (g + 1) * depth)
 };
 static_assert(sizeof(FetchShared) <= kBodySmem, "FIFO staging must fit the LDS scratch");
+
+__device__ inline uint32_t lds_depth(int32_t groups) { return kLdsDescs / (uint32_t)groups; }
+
+// by one thread of workgroup 0, before the workgroup barrier that starts the waves
+__device__ inline void fetch_init(FetchShared *fs)
+{
+    for (int g = 0; g < kMaxGroups; g++) fs->tail[g] = fs->head[g] = 0;
+    fs->stop = 0;
+    fs->exit = 0;
+    fs->snap_req = 0;
+}
 
 struct Mail {
     uint32_t slot, piece;
@@ -69,74 +83,121 @@ __device__ inline uint64_t uni64(uint64_t x)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// NG: compile-time bound on the group count (1, 2, 4 or 8), so that the
+// per-group loops disappear for a single window
+template <int NG>
 __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
 {
     const uint32_t lane = threadIdx.x & 63u;
-    uint64_t consumed = 0, htail = 0;
-    uint32_t ftail = 0;
-    bool idle = true;
+    const int32_t G = p.n_groups;
+    const uint32_t depth = lds_depth(G), ring_cap = p.ring_mask + 1;
+    constexpr uint32_t kRows = 8, kJobs = kRows * 4;   // descriptors per copy round
+    uint64_t consumed[NG], htail[NG], told[NG];
+    uint32_t ftail[NG];
+#pragma unroll
+    for (int g = 0; g < NG; g++) consumed[g] = htail[g] = told[g] = ftail[g] = 0;
+    // The host needs `consumed` only for back-pressure on its ring, so it is
+    // published every ring_cap / 8 descriptors and when the wave goes idle:
+    // a store to host memory per copy would make every copy wait for it.
+    const uint64_t tell_every = ring_cap / 8 > 0 ? ring_cap / 8 : 1;
     for (;;) {
         if (uni32(LDS_LOAD(&fs->exit))) break;
-        const uint32_t head = uni32(LDS_LOAD(&fs->head));
-        const uint32_t space = kLdsRing - (ftail - head);
-        bool moved = false;
-        uint64_t st = 0;
-        if (consumed == htail || idle) {
-            // the host's line holds tail, stop and the snapshot request: the three
-            // loads are issued together, one round trip to host memory
-            const uint64_t t = __hip_atomic_load(&p.ctrl->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            const uint64_t s0 = __hip_atomic_load(&p.ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            const uint64_t sr = __hip_atomic_load(&p.ctrl->snap_req, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            htail = uni64(t);
-            st = uni64(s0);
-            const uint64_t sru = uni64(sr);
-            if (lane == 0) {
-                LDS_STORE(&fs->stop, (uint32_t)st);
-                LDS_STORE(&fs->snap_req, sru);
-            }
-            if (htail != consumed) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
-        }
-        if (space > 0) {
-            const uint64_t avail = htail - consumed;
-            const uint32_t n = avail < space ? (uint32_t)avail : space;
-            if (n > 0) {
-                // 16 bytes per lane per row, up to 4 rows (16 descriptors).  Rows
-                // past the end re-read the last published descriptor (always
-                // valid memory) and are not stored.
-                uint4 v[4];
+        // Each round issues, together: the loads of the host's control lines
+        // (the tails, stop and the snapshot request) and the loads of up to
+        // 32 descriptors that earlier rounds already know to be published.
+        // So one round costs one round trip to host memory.
+        uint64_t t[NG];
 #pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    uint32_t off = (r * 64u + lane) * 16u;
-                    if (off >= n * 256u) off = (n - 1) * 256u + (off % 256u);
-                    const uint32_t d = off / 256u, w = off % 256u;
-                    const char *src = reinterpret_cast<const char *>(&p.ring[(consumed + d) & p.ring_mask]) + w;
-                    v[r] = *reinterpret_cast<const uint4 *>(src);
-                }
+        for (int g = 0; g < NG; g++)
+            t[g] = g < G ? __hip_atomic_load(&p.ctrl->tail[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) : 0ull;
+        const uint64_t s0 = __hip_atomic_load(&p.ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        const uint64_t sr = __hip_atomic_load(&p.ctrl->snap_req, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        // Job j of the round is descriptor consumed[g] + (j - start[g]) of the
+        // group g whose range [start[g], start[g] + cnt[g]) holds j.
+        uint32_t cnt[NG], start[NG], total = 0;
 #pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    const uint32_t off = (r * 64u + lane) * 16u;
-                    if (off < n * 256u) {
-                        const uint32_t d = off / 256u, w = off % 256u;
-                        char *dst = reinterpret_cast<char *>(&fs->ring[(ftail + d) % kLdsRing]) + w;
-                        *reinterpret_cast<uint4 *>(dst) = v[r];
-                    }
-                }
-                // every lane's part of the copy lands before lane 0 publishes it
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                ftail += n;
-                consumed += n;
-                if (lane == 0) {
-                    LDS_STORE(&fs->tail, ftail);
-                    __hip_atomic_store(&p.ctrl->consumed, consumed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                }
-                moved = true;
+        for (int g = 0; g < NG; g++) {
+            cnt[g] = 0;
+            start[g] = total;
+            if (g < G) {
+                const uint32_t space = depth - (ftail[g] - uni32(LDS_LOAD(&fs->head[g])));
+                const uint64_t avail = htail[g] - consumed[g];
+                uint32_t n = avail < space ? (uint32_t)avail : space;
+                if (n > kJobs - total) n = kJobs - total;
+                cnt[g] = n;
+                total += n;
             }
         }
-        idle = !moved;
-        if (!moved) {
+        // 16 bytes per lane per row: lane l of row r copies chunk l % 16 of
+        // job 4r + l / 16
+        uint4 v[kRows];
+        uint32_t dst_off[kRows];
+#pragma unroll
+        for (int r = 0; r < (int)kRows; r++) {
+            const uint32_t j = (uint32_t)r * 4u + lane / 16u, c = lane % 16u;
+            uint32_t gg = 0, ii = 0, ft = 0;
+            uint64_t cons = 0;
+#pragma unroll
+            for (int g = 0; g < NG; g++)
+                if (j >= start[g] && j < start[g] + cnt[g]) {
+                    gg = (uint32_t)g;
+                    ii = j - start[g];
+                    cons = consumed[g];
+                    ft = ftail[g];
+                }
+            dst_off[r] = ~0u;
+            v[r] = make_uint4(0u, 0u, 0u, 0u);
+            if (j < total) {
+                const DevDesc *src = p.ring + (uint64_t)gg * ring_cap + ((cons + ii) & p.ring_mask);
+                v[r] = reinterpret_cast<const uint4 *>(src)[c];
+                dst_off[r] = (gg * depth + (ft + ii) % depth) * 256u + c * 16u;
+            }
+        }
+        // control lines: newly published descriptors are read in later
+        // rounds, after this acquire
+        bool fresh = false;
+#pragma unroll
+        for (int g = 0; g < NG; g++) {
+            const uint64_t nt = uni64(t[g]);
+            fresh |= nt != htail[g];
+            htail[g] = nt;
+        }
+        const uint64_t st = uni64(s0);
+        const uint64_t sru = uni64(sr);
+        if (lane == 0) {
+            LDS_STORE(&fs->stop, (uint32_t)st);
+            LDS_STORE(&fs->snap_req, sru);
+        }
+        if (fresh) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+        if (total > 0) {
+#pragma unroll
+            for (int r = 0; r < (int)kRows; r++)
+                if (dst_off[r] != ~0u) *reinterpret_cast<uint4 *>(reinterpret_cast<char *>(fs->ring) + dst_off[r]) = v[r];
+            // every lane's part of the copy lands before lane 0 publishes it
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+#pragma unroll
+            for (int g = 0; g < NG; g++) {
+                if (cnt[g] == 0) continue;
+                ftail[g] += cnt[g];
+                consumed[g] += cnt[g];
+                if (lane == 0) LDS_STORE(&fs->tail[g], ftail[g]);
+                if (consumed[g] - told[g] >= tell_every) {
+                    if (lane == 0)
+                        __hip_atomic_store(&p.ctrl->consumed[g], consumed[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    told[g] = consumed[g];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int g = 0; g < NG; g++)
+                if (g < G && told[g] != consumed[g]) {
+                    if (lane == 0)
+                        __hip_atomic_store(&p.ctrl->consumed[g], consumed[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    told[g] = consumed[g];
+                }
             if (st == 2) break;   // host abort: leave even if the window wave is gone
-            __builtin_amdgcn_s_sleep(1);
+            if (!fresh) __builtin_amdgcn_s_sleep(1);
         }
     }
 }
@@ -152,27 +213,33 @@ __device__ inline uint64_t readlane64(uint64_t x, int l)
 // a 64-bit field held in dwords l (low) and l + 1 (high) of a wave-wide word
 __device__ inline uint64_t readpair(uint32_t x, int l) { return ((uint64_t)readlane32(x, l + 1) << 32) | readlane32(x, l); }
 
+template <int NG>
 __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
 {
     const uint32_t lane = threadIdx.x;
-    const int W = p.W;
-    const uint64_t full = (W >= 64) ? ~0ull : ((1ull << W) - 1ull);
+    const int W = p.W, G = p.n_groups;
     const bool tr = p.trace != nullptr;
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t depth = lds_depth(G);
 
-    // Lanes 0..W-1 own the window slots.  When the window is narrower than
-    // the wave, the slots' ranges are replicated: with Wp = W rounded up to a
-    // power of two, lane l holds the ranges of slot l mod Wp, and its replica
-    // index l / Wp selects which of the new kernel's segments it tests, so R
-    // replicas divide the pair tests of an insertion by R.
+    // Slots: group g owns lanes [g * Wp, g * Wp + W), Wp = W rounded up to a
+    // power of two; span = G * Wp lanes hold slots.  When span < 64 the
+    // slots' ranges are replicated: lane l holds the ranges of slot lane
+    // l mod span, and its replica index l / span selects which of the new
+    // kernel's segments it tests, so R replicas divide the pair tests of an
+    // insertion by R.  Masks (valid, exec, upstream) are over slot lanes.
     const uint32_t Wp = W <= 1 ? 1u : (W <= 2 ? 2u : (W <= 4 ? 4u : (W <= 8 ? 8u : (W <= 16 ? 16u : (W <= 32 ? 32u : 64u)))));
-    const uint32_t R = (64u / Wp) < (uint32_t)kSegs ? 64u / Wp : (uint32_t)kSegs;   // replicas in use
-    const uint32_t rslot = lane & (Wp - 1), rep = lane / Wp;
+    const uint32_t span = Wp * (uint32_t)G;
+    const uint32_t R = (64u / span) < (uint32_t)kSegs ? 64u / span : (uint32_t)kSegs;   // replicas in use
+    const uint32_t sl = lane % span, rep = lane / span, grp = sl / Wp;   // slot lane, replica, group
     const uint64_t wpmask = Wp >= 64 ? ~0ull : ((1ull << Wp) - 1ull);
-    uint64_t repmul = 0;   // bit r * Wp set for every replica r
-    for (uint32_t r = 0; r < R; r++) repmul |= 1ull << (r * Wp);
+    const uint64_t spanmask = span >= 64 ? ~0ull : ((1ull << span) - 1ull);
+    const uint64_t wmaskslots = W >= 64 ? ~0ull : ((1ull << W) - 1ull);   // usable slots of a group
+    const uint64_t mygroup = (wmaskslots & wpmask) << (grp * Wp);
+    uint64_t repmul = 0;   // bit r * span set for every replica r
+    for (uint32_t r = 0; r < R; r++) repmul |= 1ull << (r * span);
 
-    // this lane's slot (rslot; lanes whose replica index is R or more hold nothing)
+    // this lane's slot (sl; lanes whose replica index is R or more hold nothing)
     uint64_t ss[kSegs], se[kSegs];
 #pragma unroll
     for (int m = 0; m < kSegs; m++) ss[m] = se[m] = 0;
@@ -181,8 +248,14 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
     uint64_t up = 0, myseq = 0;
 
     // wave-uniform state
-    uint64_t valid = 0, exec = 0, retired = 0, published = 0, pub = 0, ev = 0, snap_seen = 0, checks = 0;
-    uint32_t head = 0;
+    uint64_t valid = 0, exec = 0, pub = 0, ev = 0, snap_seen = 0, checks = 0;
+    uint32_t head[NG];
+    uint64_t retired[NG], published[NG];
+#pragma unroll
+    for (int g = 0; g < NG; g++) {
+        head[g] = 0;
+        retired[g] = published[g] = 0;
+    }
     // wmask[m]: lanes whose slot segment m is a write.  Segments a slot does
     // not use, and every segment of a free slot, are the empty range [0, 0),
     // which intersects nothing, so the pair test needs no occupancy mask.
@@ -203,57 +276,91 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
         const bool mine = (exec >> lane) & 1ull;
         const uint32_t cdone = mine ? __hip_atomic_load(&p.st->done[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
 
-        // ---- admission in program order while a slot is free, a bounded
-        // number per pass
-        const uint32_t ftail = uni32(LDS_LOAD(&fs->tail));
-        if (head != ftail && valid != full) {
+        // ---- admission in program order (per group) while a slot is free, a
+        // bounded number of passes; each pass admits one kernel into every
+        // group that has one staged and a free slot
+        uint32_t ftail[NG];
+#pragma unroll
+        for (int g = 0; g < NG; g++) ftail[g] = g < G ? uni32(LDS_LOAD(&fs->tail[g])) : 0u;
+        bool staged = false;
+#pragma unroll
+        for (int g = 0; g < NG; g++) staged |= g < G && head[g] != ftail[g];
+        if (staged) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             // with few kernels out, dispatch soon rather than admit a long run first
-            const uint32_t batch = (uint32_t)__builtin_popcountll(exec) < kBusyKernels ? kAdmitFew : kAdmitBatch;
-            for (uint32_t budget = batch; head != ftail && valid != full && budget > 0; budget--) {
-                const DevDesc *d = &fs->ring[head % kLdsRing];
-                // one LDS read brings the whole descriptor into the wave: lane
-                // i holds its 4-byte word i; fields are taken with readlane
-                const uint32_t dw = reinterpret_cast<const uint32_t *>(d)[lane];
-                const int slot = __builtin_ctzll(~valid);
-                const uint64_t bit = 1ull << slot;
-                const uint32_t nraw = readlane32(dw, 4);
+            const uint32_t passes = (uint32_t)__builtin_popcountll(exec) < kBusyKernels ? kAdmitFew : kAdmitBatch;
+            for (uint32_t pass = 0; pass < passes; pass++) {
+                // which groups admit in this pass, and into which slot lane
+                uint32_t adm = 0;
+                uint32_t newl[NG];
+#pragma unroll
+                for (int g = 0; g < NG; g++) {
+                    newl[g] = 0;
+                    if (g < G && head[g] != ftail[g]) {
+                        const uint64_t fr = ~valid & (((wmaskslots & wpmask)) << (g * Wp));
+                        if (fr) {
+                            adm |= 1u << g;
+                            newl[g] = (uint32_t)__builtin_ctzll(fr);
+                        }
+                    }
+                }
+                if (!adm) break;
+                // this lane's group: does it admit, from which staged descriptor, into which lane
+                const bool gin = (adm >> grp) & 1u;
+                uint32_t hsel = 0, nsel = 0;
+#pragma unroll
+                for (int g = 0; g < NG; g++)
+                    if ((uint32_t)g == grp) {
+                        hsel = head[g];
+                        nsel = newl[g];
+                    }
+                const DevDesc *d = &fs->ring[grp * depth + hsel % depth];
+                // each admitted descriptor goes to the task table as it is (one
+                // 4-byte word per lane); all groups' words are read first so the
+                // LDS latency is paid once
+                uint32_t dwg[NG];
+#pragma unroll
+                for (int g = 0; g < NG; g++)
+                    dwg[g] = g < G ? reinterpret_cast<const uint32_t *>(&fs->ring[g * depth + head[g] % depth])[lane] : 0u;
+                uint64_t newbits = 0;
+#pragma unroll
+                for (int g = 0; g < NG; g++)
+                    if ((adm >> g) & 1u) {
+                        if (lane < kDescCopyDwords) reinterpret_cast<uint32_t *>(&p.st->task[newl[g]])[lane] = dwg[g];
+                        newbits |= 1ull << newl[g];
+                    }
+                const uint32_t nraw = gin ? d->nseg : 0u;
                 const uint32_t nseg = nraw < (uint32_t)kSegs ? nraw : (uint32_t)kSegs;
-                const uint32_t wb = readlane32(dw, 5);
-                const uint64_t seq = readpair(dw, 0);
-                const int32_t kid = (int32_t)readlane32(dw, 2);
-                const uint32_t npr = readlane32(dw, 3);
-                const uint32_t np = npr < kMaxPieces ? npr : kMaxPieces;
-                // the descriptor goes to the task table as it is
-                if (lane < kDescCopyDwords) reinterpret_cast<uint32_t *>(&p.st->task[slot])[lane] = dw;
-                // Algorithm 1 in both directions: segment k of the new kernel
-                // against segment m of every occupied slot.  A new write
-                // conflicts with any intersecting segment, a new read only with
-                // an intersecting write.  Replica r takes k = r, r + R, ...;
-                // segments past nseg are the empty range and match nothing.
+                const uint32_t wb = d->wbits;
+                // Algorithm 1 in both directions: segment k of the group's new
+                // kernel against segment m of every occupied slot of the group.
+                // A new write conflicts with any intersecting segment, a new
+                // read only with an intersecting write.  Replica r takes k = r,
+                // r + R, ...; segments past nseg are the empty range.
                 uint64_t hits = 0;
-                for (uint32_t k0 = 0; k0 < nseg; k0 += R) {
+                for (uint32_t k0 = 0; __builtin_amdgcn_ballot_w64(rep < R && k0 + rep < nseg) != 0; k0 += R) {
                     const uint32_t k = k0 + rep;
                     const bool kin = rep < R && k < nseg;
                     const uint32_t kk = kin ? k : 0u;
                     const uint64_t a0 = kin ? d->s[kk] : 0ull, a1 = kin ? d->e[kk] : 0ull;
                     // lanes whose new range is a write: they match any slot range
                     const uint64_t wkm = __builtin_amdgcn_ballot_w64(kin && ((wb >> kk) & 1u));
-                    // all eight positions, no branch: unused positions hold the empty
-                    // range; on the window wave a branch per position costs more than
-                    // the two compares it would skip.  The compares go straight into
-                    // lane masks; the rest is scalar.
+                    // all eight positions, no branch: unused positions hold the
+                    // empty range; on the window wave a branch per position costs
+                    // more than the two compares it would skip.  The compares go
+                    // straight into lane masks; the rest is scalar.
 #pragma unroll
                     for (int m = 0; m < kSegs; m++)
                         hits |= __builtin_amdgcn_ballot_w64(a0 < se[m]) & __builtin_amdgcn_ballot_w64(a1 > ss[m]) &
                                 (wkm | wmask[m]);
                 }
-                // fold the replicas' lanes onto their slots; the new slot's own
-                // lanes may already hold its ranges: only occupied slots count
-                uint64_t upm = 0;
-                for (uint32_t r = 0; r < R; r++) upm |= (hits >> (r * Wp)) & wpmask;
-                upm &= valid;
-                if (rslot == (uint32_t)slot && rep < R) {
+                // fold the replicas onto their slot lanes; a new slot's own lanes
+                // may already hold its ranges: only occupied slots count
+                uint64_t upall = 0;
+                for (uint32_t r = 0; r < R; r++) upall |= (hits >> (r * span)) & spanmask;
+                upall &= valid;
+                checks += (uint64_t)__builtin_popcountll(valid) * kSegs * kSegs;
+                if (gin && sl == nsel && rep < R) {
                     // the new occupant's ranges, in every replica of its slot
 #pragma unroll
                     for (int m = 0; m < kSegs; m++) {
@@ -261,44 +368,58 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                         se[m] = d->e[m];
                     }
                 }
-                checks += (uint64_t)__builtin_popcountll(valid) * nseg * kSegs;
-                if ((int)lane == slot) {
-                    up = upm;
-                    myseq = seq;
-                    mykid = kid;
-                    mynp = np;
-                    if (np > 1) target += np;
-                    p.st->task[slot].ptarget = target;
+                if (gin && lane == nsel) {
+                    up = upall & mygroup;
+                    myseq = d->seq;
+                    mykid = d->kid;
+                    const uint32_t npr = d->npieces;
+                    mynp = npr < kMaxPieces ? npr : kMaxPieces;
+                    if (mynp > 1) target += mynp;
+                    p.st->task[lane].ptarget = target;
+                    if (tr && myseq < p.trace_cap) {
+                        acs_trace_rec *r = &p.trace[myseq];
+                        r->seq = (int64_t)myseq;
+                        r->slot = (int32_t)lane;
+                        r->kernel_id = mykid;
+                        r->ev_insert = (int64_t)ev;
+                        r->ev_dispatch = -1;
+                        r->ev_retire = -1;
+                        r->valid_mask = valid & mygroup;
+                        r->up_mask = up;
+                        r->t_start = INT64_MAX;
+                        r->t_end = 0;
+                        r->t_dispatch = -1;
+                        r->t_retire = -1;
+                    }
                 }
-                const uint64_t rbit = bit * repmul;
+                // write flags of the new occupants' ranges, for every replica lane
+                // of a new slot at once: lane l is a new slot's replica when its
+                // group admitted and its slot lane is that group's new lane
+                {
+                    const bool newrep = gin && sl == nsel && rep < R;
+                    const uint64_t newlanes = __builtin_amdgcn_ballot_w64(newrep);
 #pragma unroll
-                for (int m = 0; m < kSegs; m++)
-                    wmask[m] = ((uint32_t)m < nseg && ((wb >> m) & 1u)) ? (wmask[m] | rbit) : (wmask[m] & ~rbit);
-                if (tr && lane == 0 && seq < p.trace_cap) {
-                    acs_trace_rec *r = &p.trace[seq];
-                    r->seq = (int64_t)seq;
-                    r->slot = slot;
-                    r->kernel_id = kid;
-                    r->ev_insert = (int64_t)ev;
-                    r->ev_dispatch = -1;
-                    r->ev_retire = -1;
-                    r->valid_mask = valid;
-                    r->up_mask = upm;
-                    r->t_start = INT64_MAX;
-                    r->t_end = 0;
-                    r->t_dispatch = -1;
-                    r->t_retire = -1;
+                    for (int m = 0; m < kSegs; m++) {
+                        const uint64_t wr = __builtin_amdgcn_ballot_w64(newrep && (uint32_t)m < nseg && ((wb >> m) & 1u));
+                        wmask[m] = (wmask[m] & ~newlanes) | wr;
+                    }
                 }
-                ev++;
-                valid |= bit;
-                head++;
+#pragma unroll
+                for (int g = 0; g < NG; g++)
+                    if ((adm >> g) & 1u) head[g]++;
+                ev += (uint64_t)__builtin_popcount(adm);
+                valid |= newbits;
                 progress = true;
             }
             // all lanes are done reading the staged descriptors before their
             // LDS slots are handed back to the FIFO wave
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            if (lane == 0) LDS_STORE(&fs->head, head);
+            if (lane == 0) {
+#pragma unroll
+                for (int g = 0; g < NG; g++)
+                    if (g < G) LDS_STORE(&fs->head[g], head[g]);
+            }
         }
 
         // ---- completions: clear finished slots from every upstream mask
@@ -313,8 +434,10 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                     }
                 }
                 ev += __builtin_popcountll(done);
-                retired += __builtin_popcountll(done);
-                if (((done >> rslot) & 1ull) && rep < R) {
+#pragma unroll
+                for (int g = 0; g < NG; g++)
+                    if (g < G) retired[g] += __builtin_popcountll(done & (wpmask << (g * Wp)));
+                if (((done >> sl) & 1ull) && rep < R) {
 #pragma unroll
                     for (int m = 0; m < kSegs; m++) ss[m] = se[m] = 0;
                 }
@@ -387,14 +510,23 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
         // ---- the host learns about completions when the window drains: one
         // system-scope release covers every result (and trace record) of the
         // kernels retired so far
-        if (valid == 0 && retired != published) {
+        uint32_t drained = 0;   // groups that are empty and have news for the host
+#pragma unroll
+        for (int g = 0; g < NG; g++)
+            if (g < G && (valid & (wpmask << (g * Wp))) == 0 && retired[g] != published[g]) drained |= 1u << g;
+        if (drained) {
             // pairs with the release of every completion counted so far ...
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             __builtin_amdgcn_wave_barrier();
             // ... and hands their results on to the host
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
-            if (lane == 0) __hip_atomic_store(&p.ctrl->retired, retired, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            published = retired;
+#pragma unroll
+            for (int g = 0; g < NG; g++)
+                if ((drained >> g) & 1u) {
+                    if (lane == 0)
+                        __hip_atomic_store(&p.ctrl->retired[g], retired[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    published[g] = retired[g];
+                }
         }
 
         if (!progress) {
@@ -427,7 +559,10 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                 snap_seen = sr;
             }
             const uint32_t st = uni32(LDS_LOAD(&fs->stop));
-            if (st == 2u || (st == 1u && valid == 0 && head == uni32(LDS_LOAD(&fs->tail)))) break;
+            bool empty = valid == 0;
+#pragma unroll
+            for (int g = 0; g < NG; g++) empty &= g >= G || head[g] == uni32(LDS_LOAD(&fs->tail[g]));
+            if (st == 2u || (st == 1u && empty)) break;
             __builtin_amdgcn_s_sleep(1);
         }
     }

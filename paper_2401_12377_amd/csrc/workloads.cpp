@@ -5,6 +5,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <chrono>
+#include <vector>
 
 #include "acs.h"
 #include "acs_tasks.h"
@@ -37,102 +38,169 @@ int acs_host_free(void *p)
     return hipHostFree(p) == hipSuccess ? ACS_OK : ACS_EDEVICE;
 }
 
-int acs_rl_run(acs_window *w, const acs_rl_scene *sc, int32_t steps, double *step_ns, acs_rl_counts *counts)
-{
-    if (!w || !sc || steps < 0 || sc->n < 2 || sc->n > acs::kRLMaxBodies || !sc->plan || sc->iters < 0)
-        return ACS_EINVAL;
-    uint64_t off[ACS_RL_NREGIONS];
-    acs::rl_offsets(sc->n, off);
-    const uint64_t A = sc->arena;
-    auto region = [&](int r) { return acs_seg{A + off[r], off[r + 1] - off[r]}; };
-    auto span = [&](int r0, int r1) { return acs_seg{A + off[r0], off[r1] - off[r0]}; };
-    auto vec = [&](int r, int32_t b0, int32_t b1) { return acs_seg{A + off[r] + 16ull * b0, 16ull * (uint64_t)(b1 - b0)}; };
-    auto ints = [&](int r, int32_t b0, int32_t b1) { return acs_seg{A + off[r] + 4ull * b0, 4ull * (uint64_t)(b1 - b0)}; };
-    const acs_seg plan_seg = {(uint64_t)(uintptr_t)sc->plan, 4ull * acs::rl_plan_ints(sc->n)};
+}  // extern "C"
 
-    acs_args_rl a = {};
-    a.base = A;
-    a.plan = (uint64_t)(uintptr_t)sc->plan;
-    a.n = sc->n;
-    a.r = sc->r;
-    a.dt = sc->dt;
-    acs_rl_counts cnt = {};
-    uint64_t &kernels = cnt.kernels;
-    int rc = ACS_OK;
-    double t_prev = wall_ns();
-#define SUBMIT(kid, R, nr, Wr, nw)                                                       \
-    do {                                                                                 \
-        rc = acs_submit(w, (kid), (R), (nr), (Wr), (nw), &a, sizeof(a), nullptr);        \
-        if (rc != ACS_OK) return rc;                                                     \
-        kernels++;                                                                       \
-    } while (0)
+namespace {
 
-    for (int32_t step = 0; step < steps; step++) {
+// One scene's kernels of a step, in the two halves the host submits
+// (before and after reading the input-dependent island plan).
+class RLStep {
+public:
+    RLStep(acs_window *w, int32_t group, const acs_rl_scene *sc) : w_(w), g_(group), sc_(sc)
+    {
+        acs::rl_offsets(sc->n, off_);
+        a_ = {};
+        a_.base = sc->arena;
+        a_.plan = (uint64_t)(uintptr_t)sc->plan;
+        a_.n = sc->n;
+        a_.r = sc->r;
+        a_.dt = sc->dt;
+    }
+
+    // predict, broadphase, islands, permute
+    int submit_prefix(acs_rl_counts &cnt)
+    {
+        const acs_seg plan_seg = {(uint64_t)(uintptr_t)sc_->plan, 4ull * acs::rl_plan_ints(sc_->n)};
+        a_.iter = a_.b0 = a_.b1 = 0;
         {
             const acs_seg r[2] = {region(ACS_RL_X), region(ACS_RL_V)};
             const acs_seg wr[1] = {region(ACS_RL_P)};
-            SUBMIT(ACS_K_RL_PREDICT, r, 2, wr, 1);
+            if (int rc = submit(ACS_K_RL_PREDICT, r, 2, wr, 1, cnt)) return rc;
         }
         {
             const acs_seg r[1] = {region(ACS_RL_P)};
             const acs_seg wr[1] = {span(ACS_RL_DEG, ACS_RL_LABEL)};
-            SUBMIT(ACS_K_RL_BROADPHASE, r, 1, wr, 1);
+            if (int rc = submit(ACS_K_RL_BROADPHASE, r, 1, wr, 1, cnt)) return rc;
         }
         {
             const acs_seg r[1] = {span(ACS_RL_DEG, ACS_RL_LABEL)};
             const acs_seg wr[2] = {span(ACS_RL_LABEL, ACS_RL_END), plan_seg};
-            SUBMIT(ACS_K_RL_ISLANDS, r, 1, wr, 2);
+            if (int rc = submit(ACS_K_RL_ISLANDS, r, 1, wr, 2, cnt)) return rc;
         }
-        {
-            const acs_seg r[2] = {region(ACS_RL_P), region(ACS_RL_PERM)};
-            const acs_seg wr[1] = {region(ACS_RL_Q0)};
-            SUBMIT(ACS_K_RL_PERMUTE, r, 2, wr, 1);
-        }
-        // the island list is known only now: drain, read the plan
-        rc = acs_sync(w);
-        if (rc != ACS_OK) return rc;
-        const double t_now = wall_ns();
-        if (step_ns && step > 0) step_ns[step - 1] = t_now - t_prev;
-        t_prev = t_now;
-        const int32_t *plan = (const int32_t *)sc->plan;
+        const acs_seg r[2] = {region(ACS_RL_P), region(ACS_RL_PERM)};
+        const acs_seg wr[1] = {region(ACS_RL_Q0)};
+        return submit(ACS_K_RL_PERMUTE, r, 2, wr, 1, cnt);
+    }
+
+    // after the prefix has completed: the plan's Jacobi kernels
+    // (iteration-major) and integrate
+    int submit_tail(acs_rl_counts &cnt)
+    {
+        const int32_t *plan = (const int32_t *)sc_->plan;
         const int32_t nmulti = __atomic_load_n(&plan[1], __ATOMIC_ACQUIRE);
-        if (nmulti < 0 || nmulti > sc->n / 2) return ACS_EKERNEL;
+        if (nmulti < 0 || nmulti > sc_->n / 2) return ACS_EKERNEL;
         cnt.steps++;
         cnt.islands += (uint64_t)plan[0];
         cnt.multi_islands += (uint64_t)nmulti;
         cnt.edges += (uint64_t)plan[2];
-        for (int32_t it = 0; it < sc->iters; it++) {
+        for (int32_t it = 0; it < sc_->iters; it++) {
             const int src = (it % 2 == 0) ? ACS_RL_Q0 : ACS_RL_Q1, dst = (it % 2 == 0) ? ACS_RL_Q1 : ACS_RL_Q0;
             for (int32_t k = 0; k < nmulti; k++) {
                 const int32_t b0 = plan[4 + 4 * k], b1 = plan[5 + 4 * k], e0 = plan[6 + 4 * k], e1 = plan[7 + 4 * k];
-                if (b0 < 0 || b1 > sc->n || b1 - b0 < 2 || e0 < 0 || e1 < e0 || e1 > sc->n * (sc->n - 1))
+                if (b0 < 0 || b1 > sc_->n || b1 - b0 < 2 || e0 < 0 || e1 < e0 || e1 > sc_->n * (sc_->n - 1))
                     return ACS_EKERNEL;   // a plan row the islands kernel cannot produce
-                a.iter = it;
-                a.b0 = b0;
-                a.b1 = b1;
+                a_.iter = it;
+                a_.b0 = b0;
+                a_.b1 = b1;
                 const acs_seg r[3] = {vec(src, b0, b1), ints(ACS_RL_PADJ_OFF, b0, b1 + 1), ints(ACS_RL_PADJ, e0, e1)};
                 const acs_seg wr[1] = {vec(dst, b0, b1)};
-                SUBMIT(ACS_K_RL_JACOBI, r, 3, wr, 1);
+                if (int rc = submit(ACS_K_RL_JACOBI, r, 3, wr, 1, cnt)) return rc;
                 cnt.jacobi_kernels++;
                 cnt.jacobi_bodies += (uint64_t)(b1 - b0);
                 cnt.jacobi_edges += (uint64_t)(e1 - e0);
             }
         }
-        a.iter = 0;
-        a.b0 = 0;
-        a.b1 = 0;
-        {
-            const acs_seg r[4] = {region(ACS_RL_P), region(ACS_RL_V), region(ACS_RL_Q0), region(ACS_RL_INV_PERM)};
-            const acs_seg wr[2] = {region(ACS_RL_X), region(ACS_RL_V)};
-            SUBMIT(ACS_K_RL_INTEGRATE, r, 4, wr, 2);
-        }
+        a_.iter = a_.b0 = a_.b1 = 0;
+        const acs_seg r[4] = {region(ACS_RL_P), region(ACS_RL_V), region(ACS_RL_Q0), region(ACS_RL_INV_PERM)};
+        const acs_seg wr[2] = {region(ACS_RL_X), region(ACS_RL_V)};
+        return submit(ACS_K_RL_INTEGRATE, r, 4, wr, 2, cnt);
     }
-#undef SUBMIT
-    rc = acs_sync(w);
+
+private:
+    acs_seg region(int r) const { return acs_seg{sc_->arena + off_[r], off_[r + 1] - off_[r]}; }
+    acs_seg span(int r0, int r1) const { return acs_seg{sc_->arena + off_[r0], off_[r1] - off_[r0]}; }
+    acs_seg vec(int r, int32_t b0, int32_t b1) const
+    {
+        return acs_seg{sc_->arena + off_[r] + 16ull * b0, 16ull * (uint64_t)(b1 - b0)};
+    }
+    acs_seg ints(int r, int32_t b0, int32_t b1) const
+    {
+        return acs_seg{sc_->arena + off_[r] + 4ull * b0, 4ull * (uint64_t)(b1 - b0)};
+    }
+    int submit(int32_t kid, const acs_seg *r, int32_t nr, const acs_seg *wr, int32_t nw, acs_rl_counts &cnt)
+    {
+        const int rc = acs_submit_group(w_, g_, kid, r, nr, wr, nw, &a_, sizeof(a_), nullptr);
+        if (rc == ACS_OK) cnt.kernels++;
+        return rc;
+    }
+
+    acs_window *w_;
+    int32_t g_;
+    const acs_rl_scene *sc_;
+    uint64_t off_[ACS_RL_NREGIONS];
+    acs_args_rl a_;
+};
+
+bool scene_ok(const acs_rl_scene *sc)
+{
+    return sc && sc->n >= 2 && sc->n <= acs::kRLMaxBodies && sc->plan && sc->iters >= 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int acs_rl_run(acs_window *w, const acs_rl_scene *sc, int32_t steps, double *step_ns, acs_rl_counts *counts)
+{
+    if (!w || !scene_ok(sc) || steps < 0) return ACS_EINVAL;
+    RLStep s(w, 0, sc);
+    acs_rl_counts cnt = {};
+    double t_prev = wall_ns();
+    for (int32_t step = 0; step < steps; step++) {
+        if (int rc = s.submit_prefix(cnt)) return rc;
+        // the island list is known only now: drain, read the plan
+        if (int rc = acs_sync(w)) return rc;
+        const double t_now = wall_ns();
+        if (step_ns && step > 0) step_ns[step - 1] = t_now - t_prev;
+        t_prev = t_now;
+        if (int rc = s.submit_tail(cnt)) return rc;
+    }
+    const int rc = acs_sync(w);
     const double t_end = wall_ns();
     if (step_ns && steps > 0) step_ns[steps - 1] = t_end - t_prev;
     if (counts) *counts = cnt;
     return rc;
+}
+
+int acs_rl_run_batch(acs_window *w, const acs_rl_scene *scenes, int32_t n_scenes, int32_t n_groups, int32_t steps,
+                     double *step_ns, acs_rl_counts *counts)
+{
+    if (!w || !scenes || n_scenes < 1 || n_groups < 1 || n_groups > 8 || steps < 0) return ACS_EINVAL;
+    std::vector<RLStep> st;
+    st.reserve((size_t)n_scenes);
+    for (int32_t i = 0; i < n_scenes; i++) {
+        if (!scene_ok(&scenes[i])) return ACS_EINVAL;
+        st.emplace_back(w, i % n_groups, &scenes[i]);
+    }
+    acs_rl_counts cnt = {};
+    for (int32_t step = 0; step < steps; step++) {
+        const double t0 = wall_ns();
+        for (auto &s : st)
+            if (int rc = s.submit_prefix(cnt)) return rc;
+        // group by group: once a group has drained, its scenes' plans are
+        // readable; the other groups keep running meanwhile
+        for (int32_t g = 0; g < n_groups; g++) {
+            if (int rc = acs_sync_group(w, g, 0)) return rc;
+            for (int32_t i = g; i < n_scenes; i += n_groups)
+                if (int rc = st[(size_t)i].submit_tail(cnt)) return rc;
+        }
+        if (step == steps - 1 || step_ns) {
+            if (int rc = acs_sync(w)) return rc;
+        }
+        if (step_ns) step_ns[step] = wall_ns() - t0;
+    }
+    if (counts) *counts = cnt;
+    return ACS_OK;
 }
 
 int acs_nop_run(acs_window *w, int32_t n, int32_t chain, uint64_t spin_ns, double *out_ns)

@@ -34,6 +34,7 @@ inline float4 make_float4(float x, float y, float z, float w) { return float4{x,
 struct uint4 {
     uint32_t x, y, z, w;
 };
+inline uint4 make_uint4(uint32_t x, uint32_t y, uint32_t z, uint32_t w) { return uint4{x, y, z, w}; }
 
 namespace acs_sim {
 struct Dim {

@@ -40,19 +40,22 @@ void run_thread(const acs::DevParams &p, Block *b, uint32_t t, uint32_t blk)
     acs_sim::group = &b->g;
     if (blk == 0) {
         FetchShared *fs = reinterpret_cast<FetchShared *>(b->lds);
-        if (t == 0) {
-            fs->tail = 0;
-            fs->head = 0;
-            fs->stop = 0;
-            fs->exit = 0;
-            fs->snap_req = 0;
-        }
+        if (t == 0) acs::fetch_init(fs);
         __syncthreads();
         const uint32_t wave = acs::uni32(threadIdx.x) >> 6;
-        if (wave == 0)
-            window_wave(p, fs);
-        else if (wave == 1)
-            fifo_wave(p, fs);
+        // the smallest compiled group bound that covers the window's groups
+        const int32_t ng = p.n_groups;
+        if (wave == 0) {
+            if (ng <= 1) acs::window_wave<1>(p, fs);
+            else if (ng <= 2) acs::window_wave<2>(p, fs);
+            else if (ng <= 4) acs::window_wave<4>(p, fs);
+            else acs::window_wave<8>(p, fs);
+        } else if (wave == 1) {
+            if (ng <= 1) acs::fifo_wave<1>(p, fs);
+            else if (ng <= 2) acs::fifo_wave<2>(p, fs);
+            else if (ng <= 4) acs::fifo_wave<4>(p, fs);
+            else acs::fifo_wave<8>(p, fs);
+        }
     } else {
         worker(p, b->lds, &b->mail);
     }
@@ -71,15 +74,22 @@ typedef struct {
 
 // Returns 0, or -5 when the window did not retire everything within
 // timeout_s (the emulated kernel is then aborted through the stop flag).
-int sim_run(int32_t W, int32_t n_workers, int32_t n, const sim_desc *descs, uint32_t ring_cap,
-            acs_trace_rec *trace_out, double timeout_s, uint64_t *retired_out)
+// groups[i] (NULL: all 0) is the window group of descriptor i, n_groups the
+// number of groups of W slots.
+int sim_run_groups(int32_t W, int32_t n_groups, int32_t n_workers, int32_t n, const sim_desc *descs,
+                   const int32_t *groups, uint32_t ring_cap, acs_trace_rec *trace_out, double timeout_s,
+                   uint64_t *retired_out)
 {
     using namespace acs;
-    if (W < 1 || W > 64 || n_workers < 1 || n < 0 || ring_cap == 0 || (ring_cap & (ring_cap - 1))) return -1;
+    int32_t wp = 1;
+    while (wp < W) wp <<= 1;
+    if (W < 1 || W > 64 || n_groups < 1 || n_groups > kMaxGroups || wp * n_groups > 64 || n_workers < 1 || n < 0 ||
+        ring_cap == 0 || (ring_cap & (ring_cap - 1)))
+        return -1;
     HostCtrl *ctrl = static_cast<HostCtrl *>(aligned_alloc(64, sizeof(HostCtrl)));
     memset((void *)ctrl, 0, sizeof(HostCtrl));
-    DevDesc *ring = static_cast<DevDesc *>(aligned_alloc(256, sizeof(DevDesc) * ring_cap));
-    memset(ring, 0, sizeof(DevDesc) * ring_cap);
+    DevDesc *ring = static_cast<DevDesc *>(aligned_alloc(256, sizeof(DevDesc) * ring_cap * n_groups));
+    memset(ring, 0, sizeof(DevDesc) * ring_cap * n_groups);
     DevState *st = static_cast<DevState *>(aligned_alloc(256, sizeof(DevState)));
     memset(st, 0, sizeof(DevState));
     acs_trace_rec *tr = nullptr;
@@ -96,6 +106,7 @@ int sim_run(int32_t W, int32_t n_workers, int32_t n, const sim_desc *descs, uint
     p.trace_cap = (uint32_t)n;
     p.W = W;
     p.n_workers = n_workers;
+    p.n_groups = n_groups;
 
     const int nblk = 1 + n_workers;
     std::vector<std::unique_ptr<Block>> blocks;
@@ -111,8 +122,14 @@ int sim_run(int32_t W, int32_t n_workers, int32_t n, const sim_desc *descs, uint
 
     const double t0 = now_s();
     int rc = 0;
+    uint64_t sub[kMaxGroups] = {};
     for (int32_t i = 0; i < n && rc == 0; i++) {
-        while ((uint64_t)i - __atomic_load_n(&ctrl->consumed, __ATOMIC_SEQ_CST) >= ring_cap) {
+        const int32_t g = groups ? groups[i] : 0;
+        if (g < 0 || g >= n_groups) {
+            rc = -1;
+            break;
+        }
+        while (sub[g] - __atomic_load_n(&ctrl->consumed[g], __ATOMIC_SEQ_CST) >= ring_cap) {
             if (now_s() - t0 > timeout_s) {
                 rc = -5;
                 break;
@@ -130,16 +147,22 @@ int sim_run(int32_t W, int32_t n_workers, int32_t n, const sim_desc *descs, uint
         memcpy(d.s, descs[i].s, sizeof(d.s));
         memcpy(d.e, descs[i].e, sizeof(d.e));
         memcpy(d.args, descs[i].args, sizeof(d.args));
-        ring[(uint32_t)i & (ring_cap - 1)] = d;
-        __atomic_store_n(&ctrl->tail, (uint64_t)(i + 1), __ATOMIC_SEQ_CST);
+        ring[(size_t)g * ring_cap + (sub[g] & (ring_cap - 1))] = d;
+        sub[g]++;
+        __atomic_store_n(&ctrl->tail[g], sub[g], __ATOMIC_SEQ_CST);
     }
-    while (rc == 0 && __atomic_load_n(&ctrl->retired, __ATOMIC_SEQ_CST) < (uint64_t)n) {
+    auto retired_total = [&]() {
+        uint64_t r = 0;
+        for (int g = 0; g < n_groups; g++) r += __atomic_load_n(&ctrl->retired[g], __ATOMIC_SEQ_CST);
+        return r;
+    };
+    while (rc == 0 && retired_total() < (uint64_t)n) {
         if (now_s() - t0 > timeout_s) rc = -5;
         std::this_thread::yield();
     }
     __atomic_store_n(&ctrl->stop, rc == 0 ? 1ull : 2ull, __ATOMIC_SEQ_CST);
     for (auto &t : threads) t.join();
-    if (retired_out) *retired_out = ctrl->retired;
+    if (retired_out) *retired_out = retired_total();
     if (tr) {
         for (int32_t i = 0; i < n; i++) {
             acs_trace_rec r = tr[i];
@@ -160,6 +183,12 @@ int sim_run(int32_t W, int32_t n_workers, int32_t n, const sim_desc *descs, uint
     free(ring);
     free(ctrl);
     return rc;
+}
+
+int sim_run(int32_t W, int32_t n_workers, int32_t n, const sim_desc *descs, uint32_t ring_cap,
+            acs_trace_rec *trace_out, double timeout_s, uint64_t *retired_out)
+{
+    return sim_run_groups(W, 1, n_workers, n, descs, nullptr, ring_cap, trace_out, timeout_s, retired_out);
 }
 
 }  // extern "C"

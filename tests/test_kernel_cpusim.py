@@ -173,3 +173,58 @@ def test_rl_prefix_through_kernel_source(sim, n):
     assert plan[0] == ref.meta[0] and plan[1] == ref.meta[1] and plan[2] == ref.meta[2]
     assert np.array_equal(plan[4:4 + 4 * m], ref.plan[:4 * m])
     assert np.array_equal(region(acs.RL_Q0, np.uint32, 4 * n), ref.Q0.view(np.uint32).reshape(-1))
+
+
+def group_trace(tr, ids, g, Wp):
+    """The records of the kernels `ids` (global sequence numbers, in their
+    group's program order) as a single-window trace of group g."""
+    sub = tr[ids].copy()
+    sub["seq"] = np.arange(len(ids))
+    assert np.all(sub["slot"] // Wp == g)
+    sub["slot"] = sub["slot"] % Wp
+    m = np.uint64((1 << Wp) - 1)
+    sub["valid_mask"] = (sub["valid_mask"] >> np.uint64(g * Wp)) & m
+    sub["up_mask"] = (sub["up_mask"] >> np.uint64(g * Wp)) & m
+    return sub
+
+
+@pytest.mark.timeout(300, method="thread")
+@pytest.mark.parametrize("G,W,workers", [(2, 8, 2), (4, 16, 3), (8, 8, 3), (3, 5, 2)])
+def test_window_groups_through_kernel_source(sim, G, W, workers):
+    """Independent tiny streams in the groups of one window wave: each
+    stream's buffers bit-identical to its in-order run, each group's trace a
+    valid windowed schedule of its own stream."""
+    streams = [inputs.tiny_stream(100 + s, n_kernels=24) for s in range(G + 1)]   # one group gets two streams
+    arenas = [st.init.copy() for st in streams]
+    per = [(_descs(st, ar.ctypes.data), st) for st, ar in zip(streams, arenas)]
+    group_of_stream = [s % G for s in range(len(streams))]
+    # interleave the streams' kernels round robin; a group's streams stay in order
+    order, pos = [], [0] * len(streams)
+    while any(pos[s] < len(streams[s].kernels) for s in range(len(streams))):
+        for s in range(len(streams)):
+            if pos[s] < len(streams[s].kernels):
+                order.append((s, pos[s]))
+                pos[s] += 1
+    n = len(order)
+    descs = (SimDesc * n)()
+    groups = np.zeros(n, np.int32)
+    for i, (s, k) in enumerate(order):
+        C.memmove(C.addressof(descs[i]), C.addressof(per[s][0][k]), C.sizeof(SimDesc))
+        groups[i] = group_of_stream[s]
+    tr = np.zeros(n, dtype=acs.TRACE_DTYPE)
+    retired = C.c_uint64()
+    sim.sim_run_groups.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_uint32,
+                                   C.c_void_p, C.c_double, C.POINTER(C.c_uint64)]
+    rc = sim.sim_run_groups(W, G, workers, n, descs, groups.ctypes.data, 16, tr.ctypes.data, 120.0, C.byref(retired))
+    assert rc == 0 and retired.value == n
+    for st, ar in zip(streams, arenas):
+        assert np.array_equal(ar.view(np.uint32), O.tiny_run(st).view(np.uint32))
+    Wp = 1 << (W - 1).bit_length()
+    for g in range(G):
+        ids = [i for i, (s, k) in enumerate(order) if group_of_stream[s] == g]
+        accs = []
+        for i in ids:
+            s, k = order[i]
+            accs.append(O.tiny_accesses(streams[s], base=(s + 1) << 40)[k])
+        code, msg = O.check_trace(accs, W, group_trace(tr, ids, g, Wp), check_times=True, early=True)
+        assert code == 0, (g, msg)
