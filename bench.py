@@ -138,6 +138,79 @@ def cpu_baseline(inputs, args):
                       f"({kernels} kernels, {dt:.1f} s, single thread, program order)"}
 
 
+def batched_section(acs, inputs, torch, args):
+    """Batched scenes: autotune, then time the tuned device path and the
+    in-order stream on fresh copies of the same scenes."""
+    import numpy as np
+    from paper_2401_12377_amd import tune
+    scenes = inputs.batched_scenes(3, args.batch_scenes)
+    log(f"[bench] batched: autotuning over {args.batch_scenes} scenes")
+    best, table = tune.autotune(scenes, steps=1, log=log, wg=(1, 2))
+    res = {}
+    finals = {}
+    for path, cfg in (("device", best), ("inorder", {"W": 8, "n_groups": 1, "wg_per_task": 1, "queue_depth": 4096})):
+        gpu = [acs.RLSceneGPU(sc) for sc in scenes]
+        torch.cuda.synchronize()
+        with acs.Window(cfg["W"], path=path, n_groups=cfg["n_groups"], wg_per_task=cfg["wg_per_task"],
+                        queue_depth=cfg["queue_depth"]) as w:
+            t0 = time.perf_counter()
+            counts, step_ns = acs.rl_run_batch(w, gpu, args.batch_steps, n_groups=cfg["n_groups"])
+            dt = time.perf_counter() - t0
+        res[path] = (counts["kernels"] / dt, np.array(step_ns) / 1e6, counts)
+        finals[path] = [g.get(acs.RL_X) for g in gpu]
+        log(f"[bench] batched {path}: {counts['kernels'] / dt / 1e3:.0f}k kernels/s")
+    same = all(np.array_equal(a.view(np.uint32), b.view(np.uint32)) for a, b in zip(finals["device"], finals["inorder"]))
+    dev, ino = res["device"], res["inorder"]
+    return {"workload": f"{args.batch_scenes} independent scenes, 16-512 bodies log-uniform, {args.batch_steps} steps, "
+                        "one persistent launch",
+            "kernels": dev[2]["kernels"], "kernels_per_s": dev[0], "inorder_kernels_per_s": ino[0],
+            "speedup_vs_inorder": dev[0] / ino[0],
+            "batched_step_ms": {"p50": float(np.percentile(dev[1], 50)), "p99": float(np.percentile(dev[1], 99))},
+            "inorder_batched_step_ms": {"p50": float(np.percentile(ino[1], 50)), "p99": float(np.percentile(ino[1], 99))},
+            "tuned": best, "candidates": len(table), "device_equals_inorder": bool(same)}
+
+
+def dnn_section(acs, inputs, torch, args):
+    """Dynamic DNN, batch 1: per-inference latency on each path, and
+    throughput with many inferences in one window."""
+    import numpy as np
+    wts = inputs.dnn_weights()
+    seeds = list(range(args.dnn_inputs))
+    out = {}
+    for path in ("device", "inorder"):
+        nets = [acs.DNNGPU(wts, inputs.DNN_CELLS, inputs.DNN_CLASSES) for _ in range(8)]
+        lat = []
+        kernels = 0
+        with acs.Window(16, path=path) as w:
+            for i, sd in enumerate(seeds):
+                inp = inputs.dnn_input(sd)
+                net = nets[i % len(nets)]
+                net.set_input(inp.x)
+                t0 = time.perf_counter()
+                kernels += acs.dnn_submit(w, net, inp.logits)
+                w.sync()
+                lat.append(time.perf_counter() - t0)
+            # throughput: inferences submitted back to back, 8 at a time in flight
+            for net in nets:
+                net.set_input(inputs.dnn_input(0).x)
+            t0 = time.perf_counter()
+            k2 = 0
+            for i, sd in enumerate(seeds):
+                k2 += acs.dnn_submit(w, nets[i % len(nets)], inputs.dnn_input(sd).logits)
+                if i % len(nets) == len(nets) - 1:
+                    w.sync()
+            w.sync()
+            dt = time.perf_counter() - t0
+        lat = np.array(lat[2:]) * 1e3
+        out[path] = {"latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+                     "kernels_per_s": k2 / dt, "inferences_per_s": len(seeds) / dt}
+        log(f"[bench] dnn {path}: p50 {out[path]['latency_ms']['p50']:.3f} ms, {len(seeds) / dt:.0f} inferences/s")
+    return {"workload": f"gated 12-cell conv network, batch 1, {len(seeds)} inputs, W=16",
+            "device": out["device"], "inorder": out["inorder"],
+            "latency_speedup_p50": out["inorder"]["latency_ms"]["p50"] / out["device"]["latency_ms"]["p50"],
+            "throughput_speedup": out["device"]["inferences_per_s"] / out["inorder"]["inferences_per_s"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +225,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--paths", default="device,inorder,plain")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-scenes section")
+    ap.add_argument("--batch-scenes", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--no-dnn", action="store_true", help="skip the dynamic-DNN section")
+    ap.add_argument("--dnn-inputs", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run device copies of known size (for PMC byte-counter scaling)")
     args = ap.parse_args()
@@ -229,6 +307,10 @@ def main():
             probes[p] = {"independent_us_per_kernel": overhead_probe(acs, p, 20000 if p == "device" else 4000, False),
                          "chain_us_per_kernel": overhead_probe(acs, p, 2000, True)}
         out["overhead_us_per_kernel"] = probes
+    if not args.no_batch:
+        out["batched"] = batched_section(acs, inputs, torch, args)
+    if not args.no_dnn:
+        out["dnn"] = dnn_section(acs, inputs, torch, args)
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline ({args.cpu_seconds:.0f} s of oracle)")
         out["cpu_baseline"] = cpu_baseline(inputs, args)

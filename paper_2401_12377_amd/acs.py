@@ -468,7 +468,10 @@ class RLSceneGPU:
         import torch
         self.region(RL_X, torch.float32, 4 * self.n).copy_(torch.as_tensor(np.ascontiguousarray(x, np.float32)).reshape(-1))
         self.region(RL_V, torch.float32, 4 * self.n).copy_(torch.as_tensor(np.ascontiguousarray(v, np.float32)).reshape(-1))
-        torch.cuda.synchronize()   # the library's streams do not wait for torch's
+        # the library's streams do not wait for torch's; a stream-level wait
+        # (not a device-wide one, which would wait for a resident persistent
+        # kernel that only stops when its window is closed)
+        torch.cuda.current_stream().synchronize()
 
     def get(self, r: int):
         import torch
@@ -560,12 +563,15 @@ class DNNGPU:
                 lst.append(torch.full((ho, ho, cout), float("nan"), dtype=torch.float32, device=dev))
         self.pool = torch.zeros(cells[-1][2], dtype=torch.float32, device=dev)
         self.out = torch.zeros(classes, dtype=torch.float32, device=dev)
-        torch.cuda.synchronize()
+        torch.cuda.current_stream().synchronize()
 
     def set_input(self, x):
         import torch
         self.x.copy_(torch.as_tensor(np.ascontiguousarray(x, np.float32)))
-        torch.cuda.synchronize()   # the library's streams do not wait for torch's
+        # the library's streams do not wait for torch's; a stream-level wait
+        # (not a device-wide one, which would wait for a resident persistent
+        # kernel that only stops when its window is closed)
+        torch.cuda.current_stream().synchronize()
 
     def c_struct(self) -> DNNGraphC:
         g = DNNGraphC()

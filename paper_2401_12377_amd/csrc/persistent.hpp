@@ -36,9 +36,9 @@
 namespace acs {
 
 constexpr uint32_t kLdsDescs = 128;   // descriptors staged in LDS (32 KB), split evenly between groups
-constexpr uint32_t kAdmitBatch = 16;  // insertion passes per loop while workers are busy
-constexpr uint32_t kAdmitFew = 2;     // ... and while fewer than kBusyKernels kernels are out
-constexpr uint32_t kBusyKernels = 4;
+constexpr uint32_t kAdmitBatch = 16;  // insertion passes per loop (measured: admitting fewer
+                                      // while few kernels are out costs more in extra
+                                      // dispatch rounds than it saves in latency)
 
 struct FetchShared {
     uint32_t tail[kMaxGroups];   // descriptors staged per group (written by the FIFO wave)
@@ -287,129 +287,205 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
         for (int g = 0; g < NG; g++) staged |= g < G && head[g] != ftail[g];
         if (staged) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            // with few kernels out, dispatch soon rather than admit a long run first
-            const uint32_t passes = (uint32_t)__builtin_popcountll(exec) < kBusyKernels ? kAdmitFew : kAdmitBatch;
-            for (uint32_t pass = 0; pass < passes; pass++) {
-                // which groups admit in this pass, and into which slot lane
-                uint32_t adm = 0;
-                uint32_t newl[NG];
+            const uint32_t passes = kAdmitBatch;
+            if constexpr (NG == 1) {
+                // one window: the descriptor is read once by the whole wave
+                // (lane i holds its 4-byte word i) and its fields are taken with
+                // readlane, so everything but the pair tests is scalar
+                const uint64_t full = wmaskslots & wpmask;
+                for (uint32_t pass = 0; pass < passes && head[0] != ftail[0] && valid != full; pass++) {
+                    const DevDesc *d = &fs->ring[head[0] % depth];
+                    const uint32_t dw = reinterpret_cast<const uint32_t *>(d)[lane];
+                    const int slot = __builtin_ctzll(~valid & full);
+                    const uint64_t bit = 1ull << slot;
+                    const uint32_t nraw = readlane32(dw, 4);
+                    const uint32_t nseg = nraw < (uint32_t)kSegs ? nraw : (uint32_t)kSegs;
+                    const uint32_t wb = readlane32(dw, 5);
+                    const uint64_t seq = readpair(dw, 0);
+                    const int32_t kid = (int32_t)readlane32(dw, 2);
+                    const uint32_t npr = readlane32(dw, 3);
+                    const uint32_t np = npr < kMaxPieces ? npr : kMaxPieces;
+                    // the descriptor goes to the task table as it is
+                    if (lane < kDescCopyDwords) reinterpret_cast<uint32_t *>(&p.st->task[slot])[lane] = dw;
+                    // Algorithm 1 in both directions (see the group case below)
+                    uint64_t hits = 0;
+                    for (uint32_t k0 = 0; k0 < nseg; k0 += R) {
+                        const uint32_t k = k0 + rep;
+                        const bool kin = rep < R && k < nseg;
+                        const uint32_t kk = kin ? k : 0u;
+                        const uint64_t a0 = kin ? d->s[kk] : 0ull, a1 = kin ? d->e[kk] : 0ull;
+                        const uint64_t wkm = __builtin_amdgcn_ballot_w64(kin && ((wb >> kk) & 1u));
 #pragma unroll
-                for (int g = 0; g < NG; g++) {
-                    newl[g] = 0;
-                    if (g < G && head[g] != ftail[g]) {
-                        const uint64_t fr = ~valid & (((wmaskslots & wpmask)) << (g * Wp));
-                        if (fr) {
-                            adm |= 1u << g;
-                            newl[g] = (uint32_t)__builtin_ctzll(fr);
+                        for (int m = 0; m < kSegs; m++)
+                            hits |= __builtin_amdgcn_ballot_w64(a0 < se[m]) & __builtin_amdgcn_ballot_w64(a1 > ss[m]) &
+                                    (wkm | wmask[m]);
+                    }
+                    uint64_t upm = 0;
+                    for (uint32_t r = 0; r < R; r++) upm |= (hits >> (r * span)) & spanmask;
+                    upm &= valid;
+                    if (sl == (uint32_t)slot && rep < R) {
+#pragma unroll
+                        for (int m = 0; m < kSegs; m++) {
+                            ss[m] = d->s[m];
+                            se[m] = d->e[m];
                         }
                     }
-                }
-                if (!adm) break;
-                // this lane's group: does it admit, from which staged descriptor, into which lane
-                const bool gin = (adm >> grp) & 1u;
-                uint32_t hsel = 0, nsel = 0;
-#pragma unroll
-                for (int g = 0; g < NG; g++)
-                    if ((uint32_t)g == grp) {
-                        hsel = head[g];
-                        nsel = newl[g];
+                    checks += (uint64_t)__builtin_popcountll(valid) * nseg * kSegs;
+                    if ((int)lane == slot) {
+                        up = upm;
+                        myseq = seq;
+                        mykid = kid;
+                        mynp = np;
+                        if (np > 1) target += np;
+                        p.st->task[slot].ptarget = target;
                     }
-                const DevDesc *d = &fs->ring[grp * depth + hsel % depth];
-                // each admitted descriptor goes to the task table as it is (one
-                // 4-byte word per lane); all groups' words are read first so the
-                // LDS latency is paid once
-                uint32_t dwg[NG];
-#pragma unroll
-                for (int g = 0; g < NG; g++)
-                    dwg[g] = g < G ? reinterpret_cast<const uint32_t *>(&fs->ring[g * depth + head[g] % depth])[lane] : 0u;
-                uint64_t newbits = 0;
-#pragma unroll
-                for (int g = 0; g < NG; g++)
-                    if ((adm >> g) & 1u) {
-                        if (lane < kDescCopyDwords) reinterpret_cast<uint32_t *>(&p.st->task[newl[g]])[lane] = dwg[g];
-                        newbits |= 1ull << newl[g];
-                    }
-                const uint32_t nraw = gin ? d->nseg : 0u;
-                const uint32_t nseg = nraw < (uint32_t)kSegs ? nraw : (uint32_t)kSegs;
-                const uint32_t wb = d->wbits;
-                // Algorithm 1 in both directions: segment k of the group's new
-                // kernel against segment m of every occupied slot of the group.
-                // A new write conflicts with any intersecting segment, a new
-                // read only with an intersecting write.  Replica r takes k = r,
-                // r + R, ...; segments past nseg are the empty range.
-                uint64_t hits = 0;
-                for (uint32_t k0 = 0; __builtin_amdgcn_ballot_w64(rep < R && k0 + rep < nseg) != 0; k0 += R) {
-                    const uint32_t k = k0 + rep;
-                    const bool kin = rep < R && k < nseg;
-                    const uint32_t kk = kin ? k : 0u;
-                    const uint64_t a0 = kin ? d->s[kk] : 0ull, a1 = kin ? d->e[kk] : 0ull;
-                    // lanes whose new range is a write: they match any slot range
-                    const uint64_t wkm = __builtin_amdgcn_ballot_w64(kin && ((wb >> kk) & 1u));
-                    // all eight positions, no branch: unused positions hold the
-                    // empty range; on the window wave a branch per position costs
-                    // more than the two compares it would skip.  The compares go
-                    // straight into lane masks; the rest is scalar.
+                    const uint64_t rbit = bit * repmul;
 #pragma unroll
                     for (int m = 0; m < kSegs; m++)
-                        hits |= __builtin_amdgcn_ballot_w64(a0 < se[m]) & __builtin_amdgcn_ballot_w64(a1 > ss[m]) &
-                                (wkm | wmask[m]);
-                }
-                // fold the replicas onto their slot lanes; a new slot's own lanes
-                // may already hold its ranges: only occupied slots count
-                uint64_t upall = 0;
-                for (uint32_t r = 0; r < R; r++) upall |= (hits >> (r * span)) & spanmask;
-                upall &= valid;
-                checks += (uint64_t)__builtin_popcountll(valid) * kSegs * kSegs;
-                if (gin && sl == nsel && rep < R) {
-                    // the new occupant's ranges, in every replica of its slot
-#pragma unroll
-                    for (int m = 0; m < kSegs; m++) {
-                        ss[m] = d->s[m];
-                        se[m] = d->e[m];
-                    }
-                }
-                if (gin && lane == nsel) {
-                    up = upall & mygroup;
-                    myseq = d->seq;
-                    mykid = d->kid;
-                    const uint32_t npr = d->npieces;
-                    mynp = npr < kMaxPieces ? npr : kMaxPieces;
-                    if (mynp > 1) target += mynp;
-                    p.st->task[lane].ptarget = target;
-                    if (tr && myseq < p.trace_cap) {
-                        acs_trace_rec *r = &p.trace[myseq];
-                        r->seq = (int64_t)myseq;
-                        r->slot = (int32_t)lane;
-                        r->kernel_id = mykid;
+                        wmask[m] = ((uint32_t)m < nseg && ((wb >> m) & 1u)) ? (wmask[m] | rbit) : (wmask[m] & ~rbit);
+                    if (tr && lane == 0 && seq < p.trace_cap) {
+                        acs_trace_rec *r = &p.trace[seq];
+                        r->seq = (int64_t)seq;
+                        r->slot = slot;
+                        r->kernel_id = kid;
                         r->ev_insert = (int64_t)ev;
                         r->ev_dispatch = -1;
                         r->ev_retire = -1;
-                        r->valid_mask = valid & mygroup;
-                        r->up_mask = up;
+                        r->valid_mask = valid;
+                        r->up_mask = upm;
                         r->t_start = INT64_MAX;
                         r->t_end = 0;
                         r->t_dispatch = -1;
                         r->t_retire = -1;
                     }
+                    ev++;
+                    valid |= bit;
+                    head[0]++;
+                    progress = true;
                 }
-                // write flags of the new occupants' ranges, for every replica lane
-                // of a new slot at once: lane l is a new slot's replica when its
-                // group admitted and its slot lane is that group's new lane
-                {
-                    const bool newrep = gin && sl == nsel && rep < R;
-                    const uint64_t newlanes = __builtin_amdgcn_ballot_w64(newrep);
-#pragma unroll
-                    for (int m = 0; m < kSegs; m++) {
-                        const uint64_t wr = __builtin_amdgcn_ballot_w64(newrep && (uint32_t)m < nseg && ((wb >> m) & 1u));
-                        wmask[m] = (wmask[m] & ~newlanes) | wr;
+            } else {
+                for (uint32_t pass = 0; pass < passes; pass++) {
+                    // which groups admit in this pass, and into which slot lane
+                    uint32_t adm = 0;
+                    uint32_t newl[NG];
+    #pragma unroll
+                    for (int g = 0; g < NG; g++) {
+                        newl[g] = 0;
+                        if (g < G && head[g] != ftail[g]) {
+                            const uint64_t fr = ~valid & (((wmaskslots & wpmask)) << (g * Wp));
+                            if (fr) {
+                                adm |= 1u << g;
+                                newl[g] = (uint32_t)__builtin_ctzll(fr);
+                            }
+                        }
                     }
+                    if (!adm) break;
+                    // this lane's group: does it admit, from which staged descriptor, into which lane
+                    const bool gin = (adm >> grp) & 1u;
+                    uint32_t hsel = 0, nsel = 0;
+    #pragma unroll
+                    for (int g = 0; g < NG; g++)
+                        if ((uint32_t)g == grp) {
+                            hsel = head[g];
+                            nsel = newl[g];
+                        }
+                    const DevDesc *d = &fs->ring[grp * depth + hsel % depth];
+                    // each admitted descriptor goes to the task table as it is (one
+                    // 4-byte word per lane); all groups' words are read first so the
+                    // LDS latency is paid once
+                    uint32_t dwg[NG];
+    #pragma unroll
+                    for (int g = 0; g < NG; g++)
+                        dwg[g] = g < G ? reinterpret_cast<const uint32_t *>(&fs->ring[g * depth + head[g] % depth])[lane] : 0u;
+                    uint64_t newbits = 0;
+    #pragma unroll
+                    for (int g = 0; g < NG; g++)
+                        if ((adm >> g) & 1u) {
+                            if (lane < kDescCopyDwords) reinterpret_cast<uint32_t *>(&p.st->task[newl[g]])[lane] = dwg[g];
+                            newbits |= 1ull << newl[g];
+                        }
+                    const uint32_t nraw = gin ? d->nseg : 0u;
+                    const uint32_t nseg = nraw < (uint32_t)kSegs ? nraw : (uint32_t)kSegs;
+                    const uint32_t wb = d->wbits;
+                    // Algorithm 1 in both directions: segment k of the group's new
+                    // kernel against segment m of every occupied slot of the group.
+                    // A new write conflicts with any intersecting segment, a new
+                    // read only with an intersecting write.  Replica r takes k = r,
+                    // r + R, ...; segments past nseg are the empty range.
+                    uint64_t hits = 0;
+                    for (uint32_t k0 = 0; __builtin_amdgcn_ballot_w64(rep < R && k0 + rep < nseg) != 0; k0 += R) {
+                        const uint32_t k = k0 + rep;
+                        const bool kin = rep < R && k < nseg;
+                        const uint32_t kk = kin ? k : 0u;
+                        const uint64_t a0 = kin ? d->s[kk] : 0ull, a1 = kin ? d->e[kk] : 0ull;
+                        // lanes whose new range is a write: they match any slot range
+                        const uint64_t wkm = __builtin_amdgcn_ballot_w64(kin && ((wb >> kk) & 1u));
+                        // all eight positions, no branch: unused positions hold the
+                        // empty range; on the window wave a branch per position costs
+                        // more than the two compares it would skip.  The compares go
+                        // straight into lane masks; the rest is scalar.
+    #pragma unroll
+                        for (int m = 0; m < kSegs; m++)
+                            hits |= __builtin_amdgcn_ballot_w64(a0 < se[m]) & __builtin_amdgcn_ballot_w64(a1 > ss[m]) &
+                                    (wkm | wmask[m]);
+                    }
+                    // fold the replicas onto their slot lanes; a new slot's own lanes
+                    // may already hold its ranges: only occupied slots count
+                    uint64_t upall = 0;
+                    for (uint32_t r = 0; r < R; r++) upall |= (hits >> (r * span)) & spanmask;
+                    upall &= valid;
+                    checks += (uint64_t)__builtin_popcountll(valid) * kSegs * kSegs;
+                    if (gin && sl == nsel && rep < R) {
+                        // the new occupant's ranges, in every replica of its slot
+    #pragma unroll
+                        for (int m = 0; m < kSegs; m++) {
+                            ss[m] = d->s[m];
+                            se[m] = d->e[m];
+                        }
+                    }
+                    if (gin && lane == nsel) {
+                        up = upall & mygroup;
+                        myseq = d->seq;
+                        mykid = d->kid;
+                        const uint32_t npr = d->npieces;
+                        mynp = npr < kMaxPieces ? npr : kMaxPieces;
+                        if (mynp > 1) target += mynp;
+                        p.st->task[lane].ptarget = target;
+                        if (tr && myseq < p.trace_cap) {
+                            acs_trace_rec *r = &p.trace[myseq];
+                            r->seq = (int64_t)myseq;
+                            r->slot = (int32_t)lane;
+                            r->kernel_id = mykid;
+                            r->ev_insert = (int64_t)ev;
+                            r->ev_dispatch = -1;
+                            r->ev_retire = -1;
+                            r->valid_mask = valid & mygroup;
+                            r->up_mask = up;
+                            r->t_start = INT64_MAX;
+                            r->t_end = 0;
+                            r->t_dispatch = -1;
+                            r->t_retire = -1;
+                        }
+                    }
+                    // write flags of the new occupants' ranges, for every replica lane
+                    // of a new slot at once: lane l is a new slot's replica when its
+                    // group admitted and its slot lane is that group's new lane
+                    {
+                        const bool newrep = gin && sl == nsel && rep < R;
+                        const uint64_t newlanes = __builtin_amdgcn_ballot_w64(newrep);
+    #pragma unroll
+                        for (int m = 0; m < kSegs; m++) {
+                            const uint64_t wr = __builtin_amdgcn_ballot_w64(newrep && (uint32_t)m < nseg && ((wb >> m) & 1u));
+                            wmask[m] = (wmask[m] & ~newlanes) | wr;
+                        }
+                    }
+    #pragma unroll
+                    for (int g = 0; g < NG; g++)
+                        if ((adm >> g) & 1u) head[g]++;
+                    ev += (uint64_t)__builtin_popcount(adm);
+                    valid |= newbits;
+                    progress = true;
                 }
-#pragma unroll
-                for (int g = 0; g < NG; g++)
-                    if ((adm >> g) & 1u) head[g]++;
-                ev += (uint64_t)__builtin_popcount(adm);
-                valid |= newbits;
-                progress = true;
             }
             // all lanes are done reading the staged descriptors before their
             // LDS slots are handed back to the FIFO wave

@@ -1,0 +1,64 @@
+"""Autotuner for batched task graphs: picks the window size W, the number
+of window groups, the workgroups per splittable task and the input queue
+depth for a set of independent scenes by timing short runs of each
+candidate on the device path.
+
+Each candidate runs on its own copy of the scenes (the tuning steps do not
+advance the caller's scenes).  The search is exhaustive over (W, groups,
+workgroups per task) with W in {8, 16, 32} and groups * pow2(W) <= 64, then
+over the queue depth for the best of those.
+"""
+from __future__ import annotations
+
+import itertools
+import time
+
+from . import acs
+
+
+def _pow2(x: int) -> int:
+    p = 1
+    while p < x:
+        p <<= 1
+    return p
+
+
+def candidates(windows=(8, 16, 32), groups=(1, 2, 4, 8), wg=(1, 2, 4)):
+    for W, G, g in itertools.product(windows, groups, wg):
+        if G * _pow2(W) <= acs.W_MAX:
+            yield {"W": W, "n_groups": G, "wg_per_task": g, "queue_depth": 4096}
+
+
+def time_config(scenes, cfg: dict, steps: int = 2, warmup: int = 1) -> float:
+    """kernels/s of `steps` batched steps of fresh copies of `scenes` (RLScene
+    inputs) under cfg, after `warmup` untimed steps."""
+    import torch
+    gpu = [acs.RLSceneGPU(sc) for sc in scenes]
+    torch.cuda.synchronize()
+    with acs.Window(cfg["W"], path="device", n_groups=cfg["n_groups"], wg_per_task=cfg["wg_per_task"],
+                    queue_depth=cfg["queue_depth"]) as w:
+        if warmup:
+            acs.rl_run_batch(w, gpu, warmup, n_groups=cfg["n_groups"])
+        t0 = time.perf_counter()
+        counts, _ = acs.rl_run_batch(w, gpu, steps, n_groups=cfg["n_groups"])
+        dt = time.perf_counter() - t0
+    return counts["kernels"] / dt
+
+
+def autotune(scenes, steps: int = 2, log=None, **space):
+    """Returns (best config, table of (config, kernels/s))."""
+    table = []
+    for cfg in candidates(**space):
+        v = time_config(scenes, cfg, steps)
+        table.append((cfg, v))
+        if log:
+            log(f"[tune] {cfg}: {v / 1e3:.0f}k kernels/s")
+    best = dict(max(table, key=lambda t: t[1])[0])
+    for qd in (256, 1024):
+        cfg = dict(best, queue_depth=qd)
+        v = time_config(scenes, cfg, steps)
+        table.append((cfg, v))
+        if log:
+            log(f"[tune] {cfg}: {v / 1e3:.0f}k kernels/s")
+    best = dict(max(table, key=lambda t: t[1])[0])
+    return best, table
