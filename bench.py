@@ -205,7 +205,45 @@ def dnn_section(acs, inputs, torch, args):
         out[path] = {"latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
                      "kernels_per_s": k2 / dt, "inferences_per_s": len(seeds) / dt}
         log(f"[bench] dnn {path}: p50 {out[path]['latency_ms']['p50']:.3f} ms, {len(seeds) / dt:.0f} inferences/s")
+    # steady state: the network with every branch on (a static graph),
+    # recorded once and replayed as a HIP graph, against the window paths
+    import numpy as np
+    static = np.ones((len(inputs.DNN_CELLS), 2), np.float32)
+    steady = {}
+    net = acs.DNNGPU(wts, inputs.DNN_CELLS, inputs.DNN_CLASSES)
+    net.set_input(inputs.dnn_input(0).x)
+    with acs.Window(16, path="inorder") as w:
+        w.graph_begin()
+        acs.dnn_submit(w, net, static)
+        g = w.graph_end()
+    with g:
+        g.launch()
+        g.sync()
+        lat = []
+        for _ in seeds:
+            t0 = time.perf_counter()
+            g.launch()
+            g.sync()
+            lat.append(time.perf_counter() - t0)
+        lat = np.array(lat) * 1e3
+        steady["graph"] = {"latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+                           "edges": g.info()["edges"], "kernels": g.info()["kernels"]}
+    for path in ("device", "inorder"):
+        with acs.Window(16, path=path) as w:
+            acs.dnn_submit(w, net, static)
+            w.sync()
+            lat = []
+            for _ in seeds:
+                t0 = time.perf_counter()
+                acs.dnn_submit(w, net, static)
+                w.sync()
+                lat.append(time.perf_counter() - t0)
+        lat = np.array(lat) * 1e3
+        steady[path] = {"latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}}
+    log(f"[bench] dnn steady state p50: graph {steady['graph']['latency_ms']['p50']:.3f} ms, device "
+        f"{steady['device']['latency_ms']['p50']:.3f} ms, inorder {steady['inorder']['latency_ms']['p50']:.3f} ms")
     return {"workload": f"gated 12-cell conv network, batch 1, {len(seeds)} inputs, W=16",
+            "steady_state": dict(steady, workload="every branch on (static graph), replayed"),
             "device": out["device"], "inorder": out["inorder"],
             "latency_speedup_p50": out["inorder"]["latency_ms"]["p50"] / out["device"]["latency_ms"]["p50"],
             "throughput_speedup": out["device"]["inferences_per_s"] / out["inorder"]["inferences_per_s"]}

@@ -182,6 +182,30 @@ int acs_submit_group(acs_window *w, int32_t group, int32_t kernel_id,
  * groups keep running).  Same return values as acs_sync_timeout (0 = no limit). */
 int acs_sync_group(acs_window *w, int32_t group, uint64_t timeout_ns);
 
+/* Graph capture for a steady state where the same task graph repeats
+ * (static networks, repeated requests).  Between acs_graph_begin and
+ * acs_graph_end, acs_submit / acs_submit_group record kernels instead of
+ * running them (arguments and ranges are checked as usual; sequence numbers
+ * advance).  acs_graph_end builds a HIP graph with one kernel node per
+ * recorded kernel and an edge from every earlier kernel it conflicts with
+ * (the same read/write test as the window, over all pairs, reduced to the
+ * edges not implied by others), instantiates it and returns it in *out.
+ * The graph borrows the buffers its kernels name: keep them alive until it
+ * is destroyed.  Replays see the buffers' contents at launch time.
+ * acs_graph_begin: ACS_ESTATE if already recording or the window was stopped.
+ * acs_graph_end: ACS_ESTATE if not recording; ACS_EINVAL if nothing was
+ * recorded; ACS_EDEVICE if a HIP graph call fails. */
+typedef struct acs_graph acs_graph;
+int acs_graph_begin(acs_window *w);
+int acs_graph_end(acs_window *w, acs_graph **out);
+/* Launches one replay on the graph's own stream (asynchronous). */
+int acs_graph_launch(acs_graph *g);
+/* Waits for every replay launched so far. */
+int acs_graph_sync(acs_graph *g);
+/* Kernels and dependency edges of the graph. */
+int acs_graph_info(const acs_graph *g, int64_t *n_kernels, int64_t *n_edges);
+int acs_graph_destroy(acs_graph *g);
+
 /* Copies up to cap entries of the scheduled list into out (oldest first). */
 int acs_scheduled_list(acs_window *w, acs_entry *out, int32_t cap, int32_t *n_out);
 

@@ -185,6 +185,12 @@ def lib():
         L.acs_rl_run.argtypes = [C.c_void_p, P(RLSceneC), C.c_int32, P(C.c_double), P(RLCounts)]
         L.acs_nop_run.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, P(C.c_double)]
         L.acs_dnn_submit.argtypes = [C.c_void_p, P(DNNGraphC), C.c_void_p, P(C.c_uint64)]
+        L.acs_graph_begin.argtypes = [C.c_void_p]
+        L.acs_graph_end.argtypes = [C.c_void_p, P(C.c_void_p)]
+        L.acs_graph_launch.argtypes = [C.c_void_p]
+        L.acs_graph_sync.argtypes = [C.c_void_p]
+        L.acs_graph_info.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int64)]
+        L.acs_graph_destroy.argtypes = [C.c_void_p]
         L.acs_submit_group.argtypes = [C.c_void_p, C.c_int32, C.c_int32, P(Seg), C.c_int32, P(Seg), C.c_int32,
                                        C.c_void_p, C.c_size_t, P(C.c_uint64)]
         L.acs_sync_group.argtypes = [C.c_void_p, C.c_int32, C.c_uint64]
@@ -193,10 +199,47 @@ def lib():
         for f in ("acs_window_configure", "acs_submit", "acs_sync", "acs_sync_timeout", "acs_scheduled_list",
                   "acs_trace_read", "acs_stats_get", "acs_window_destroy", "acs_window_stop", "acs_manual_take_ready",
                   "acs_manual_complete", "acs_last_error", "acs_rl_layout", "acs_host_free", "acs_rl_run",
-                  "acs_nop_run", "acs_dnn_submit", "acs_submit_group", "acs_sync_group", "acs_rl_run_batch"):
+                  "acs_nop_run", "acs_dnn_submit", "acs_submit_group", "acs_sync_group", "acs_rl_run_batch",
+                  "acs_graph_begin", "acs_graph_end", "acs_graph_launch", "acs_graph_sync", "acs_graph_info",
+                  "acs_graph_destroy"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
+
+
+class Graph:
+    """A recorded task graph (acs_graph_*): replayed as one HIP graph."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    def launch(self):
+        _check(lib().acs_graph_launch(self._h))
+
+    def sync(self):
+        _check(lib().acs_graph_sync(self._h))
+
+    def info(self):
+        k, e = C.c_int64(), C.c_int64()
+        _check(lib().acs_graph_info(self._h, C.byref(k), C.byref(e)))
+        return {"kernels": k.value, "edges": e.value}
+
+    def destroy(self):
+        if self._h:
+            lib().acs_graph_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 def _check(rc):
@@ -270,6 +313,15 @@ class Window:
 
     def sync_group(self, group: int, timeout_ns: int = 0) -> int:
         return _check(lib().acs_sync_group(self.handle, group, timeout_ns))
+
+    def graph_begin(self):
+        """Subsequent submits are recorded instead of run (see acs_graph_begin)."""
+        _check(lib().acs_graph_begin(self.handle))
+
+    def graph_end(self) -> "Graph":
+        h = C.c_void_p()
+        _check(lib().acs_graph_end(self.handle, C.byref(h)))
+        return Graph(h.value)
 
     def submit_raw(self, kid, reads, writes, args_bytes: bytes):
         """Like submit, with the argument block given as bytes (for tests)."""

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <memory>
 #include <string>
+#include <vector>
 
 #include <hip/hip_runtime_api.h>
 
@@ -12,16 +13,6 @@
 #include "launch.hpp"
 #include "rl_layout.hpp"
 
-struct acs_window {
-    int32_t W = 0;
-    acs_config cfg;
-    bool configured = false;
-    bool started = false;
-    bool stopped = false;
-    uint64_t next_seq = 0;
-    uint64_t coalesced = 0;
-    std::unique_ptr<acs::Path> path;
-};
 
 namespace acs {
 
@@ -414,6 +405,13 @@ int acs_submit_group(acs_window *w, int32_t group, int32_t kernel_id, const acs_
                        &why);
     if (rc != ACS_OK) return fail(rc, why);
     d.seq = w->next_seq;
+    if (w->recording) {
+        w->recorded.push_back(d);
+        if (lossy) w->coalesced++;
+        if (seq_out) *seq_out = d.seq;
+        w->next_seq++;
+        return ACS_OK;
+    }
     rc = w->path->submit_group(d, group);
     if (rc != ACS_OK) return rc;
     if (lossy) w->coalesced++;

@@ -85,3 +85,17 @@ std::unique_ptr<Path> make_device_path(int32_t W, const acs_config &cfg);
 uint64_t now_ns();
 
 }  // namespace acs
+
+// The window object behind the opaque acs_window handle.
+struct acs_window {
+    int32_t W = 0;
+    acs_config cfg;
+    bool configured = false;
+    bool started = false;
+    bool stopped = false;
+    uint64_t next_seq = 0;
+    uint64_t coalesced = 0;
+    std::unique_ptr<acs::Path> path;
+    bool recording = false;              // between acs_graph_begin and acs_graph_end
+    std::vector<acs::Desc> recorded;
+};

@@ -49,6 +49,8 @@ static const void *const k_table[ACS_K_COUNT] = {
 };
 static_assert(sizeof(k_table) / sizeof(k_table[0]) == ACS_K_COUNT, "task table size");
 
+const void *task_kernel(int32_t kid) { return (kid < 0 || kid >= ACS_K_COUNT) ? nullptr : k_table[kid]; }
+
 hipError_t launch_task(int32_t kid, const void *args, uint32_t npieces, hipStream_t stream)
 {
     if (kid < 0 || kid >= ACS_K_COUNT || k_table[kid] == nullptr || npieces == 0) return hipErrorInvalidValue;

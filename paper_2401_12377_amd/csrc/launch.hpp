@@ -12,6 +12,9 @@ namespace acs {
 // 256 threads on `stream`.  `args` points at the task's argument struct.
 hipError_t launch_task(int32_t kid, const void *args, uint32_t npieces, hipStream_t stream);
 
+// The standalone kernel of task `kid` (for graph nodes), or null.
+const void *task_kernel(int32_t kid);
+
 // Launches the persistent scheduler kernel: workgroup 0 holds the window,
 // workgroups 1 .. grid-1 are workers.
 hipError_t launch_persistent(const DevParams &p, int32_t grid, hipStream_t stream);

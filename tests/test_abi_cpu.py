@@ -388,3 +388,24 @@ def test_conv_argument_checks():
         rc, _ = w.submit_raw(acs.K_CONV, [], [(4 << 20, 4)], bytes(a))
         assert rc == acs.EINVAL, field
     w.destroy()
+
+
+def test_graph_recording_states():
+    w = manual(4)
+    with pytest.raises(acs.AcsError) as e:
+        w.graph_end()
+    assert e.value.code == acs.ESTATE                 # not recording
+    w.graph_begin()
+    with pytest.raises(acs.AcsError) as e:
+        w.graph_begin()
+    assert e.value.code == acs.ESTATE                 # already recording
+    with pytest.raises(acs.AcsError) as e:
+        w.graph_end()
+    assert e.value.code == acs.EINVAL                 # nothing recorded
+    # recorded kernels do not reach the window
+    w.graph_begin()
+    s0 = sub(w, [], [(0, 8)])
+    s1 = sub(w, [(0, 8)], [(8, 8)])
+    assert (s0, s1) == (0, 1)
+    assert w.take_ready() == []
+    w.destroy()
