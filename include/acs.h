@@ -182,6 +182,14 @@ int acs_submit_group(acs_window *w, int32_t group, int32_t kernel_id,
  * groups keep running).  Same return values as acs_sync_timeout (0 = no limit). */
 int acs_sync_group(acs_window *w, int32_t group, uint64_t timeout_ns);
 
+/* One non-blocking pass of the host side, for callers that interleave other
+ * work with the window (a serving loop): the plain path retires kernels
+ * whose completion events fired, admits from the FIFO and launches ready
+ * kernels (one turn of the scheduler loop, Algorithm 2); the device and
+ * in-order paths have nothing to advance on the host.  Returns the sticky
+ * asynchronous error if there is one (ACS_EKERNEL, ACS_EDEVICE), else 0. */
+int acs_poll(acs_window *w);
+
 /* Graph capture for a steady state where the same task graph repeats
  * (static networks, repeated requests).  Between acs_graph_begin and
  * acs_graph_end, acs_submit / acs_submit_group record kernels instead of

@@ -39,7 +39,10 @@ enum acs_kernel_id {
     ACS_K_JOIN = 21,          /* out = relu(a + b), or relu(a) when b is NULL */
     ACS_K_AVGPOOL = 22,       /* out[c] = (sum of in[q][c] over the hw pixels, in pixel order) / hw */
     ACS_K_FC = 23,            /* out[j] = b[j] + sum_i in[i] w[i][j], fmaf chain in i order */
-    ACS_K_COUNT = 24
+    /* request plumbing (serving) */
+    ACS_K_COPY = 24,          /* dst[0..bytes) = src[0..bytes), bit copy */
+    ACS_K_SIGNAL = 25,        /* *addr = value, a release store visible to the host */
+    ACS_K_COUNT = 26
 };
 
 #define ACS_BLOCK 256
@@ -87,6 +90,17 @@ typedef struct {
 typedef struct { float *out; const float *a; const float *b; uint32_t n; } acs_args_join;
 typedef struct { float *out; const float *in; int32_t hw, c; } acs_args_avgpool;
 typedef struct { float *out; const float *in; const float *w; const float *bias; int32_t cin, cout; } acs_args_fc;
+
+/* Bit copy of `bytes` bytes; dst and src 16-byte aligned, bytes a multiple
+ * of 16, the two ranges disjoint.  Used to stage a request's input into its
+ * working memory and its result out of it. */
+typedef struct { void *dst; const void *src; uint64_t bytes; } acs_args_copy;
+
+/* Stores `value` into the 8-byte word at addr (host-visible memory allowed)
+ * with release ordering at system scope: every write of a kernel this one
+ * depended on is visible before the value is.  Its read ranges state what
+ * it waits for; its write range is the word.  One workgroup. */
+typedef struct { uint64_t *addr; uint64_t value; } acs_args_signal;
 
 /* Regions of an RL scene arena, in order; byte offsets from acs_rl_layout. */
 enum acs_rl_region {

@@ -18,7 +18,10 @@ extern "C" {
 #endif
 
 /* Pinned, coherent host memory that kernels can write directly (the RL plan
- * buffer).  NULL on failure.  Free with acs_host_free. */
+ * buffer, the serving loop's signal words).  NULL on failure.  Free with
+ * acs_host_free.  Call neither while a device-path window is open: the HIP
+ * host allocator synchronises the whole device, which never completes while
+ * the window's scheduler kernel is resident. */
 void *acs_host_alloc(size_t bytes);
 int acs_host_free(void *p);
 
@@ -102,6 +105,100 @@ typedef struct {
  * and output tensors and its weights.  *n_kernels (if not NULL) receives the
  * number of kernels submitted.  Returns 0 or the first error. */
 int acs_dnn_submit(acs_window *w, const acs_dnn_graph *g, const float *logits, uint64_t *n_kernels);
+
+/* Working-memory pool: a host-side allocator over a caller-owned device
+ * range [base, base + bytes) (the serving loop's admission budget).  Blocks
+ * are 256-byte aligned and sized; best fit, freed blocks merge with free
+ * neighbours.  The pool only hands out addresses: it never touches the
+ * memory.  acs_pool_create: NULL if base is not 256-byte aligned or bytes <
+ * 256.  acs_pool_alloc: ACS_EINVAL for 0 bytes, ACS_ENOMEM when no free block
+ * is large enough.  acs_pool_free: ACS_EINVAL for an address that is not a
+ * live block.  acs_pool_info: bytes in live blocks, largest free block, live
+ * block count (any pointer may be NULL). */
+typedef struct acs_pool acs_pool;
+acs_pool *acs_pool_create(uint64_t base, uint64_t bytes);
+int acs_pool_alloc(acs_pool *p, uint64_t bytes, uint64_t *addr);
+int acs_pool_free(acs_pool *p, uint64_t addr);
+int acs_pool_info(const acs_pool *p, uint64_t *used, uint64_t *largest_free, int64_t *n_blocks);
+void acs_pool_destroy(acs_pool *p);
+
+/* Serving: requests (each one task graph) arrive over time and run
+ * concurrently through one window that stays open for the whole run
+ * (on the device path: one persistent kernel, window state in device memory).
+ *
+ * A request is admitted in arrival order (no bypass) once fewer than
+ * max_resident requests are in flight and the pool has a block for its
+ * working memory; it is then submitted to the window group with the fewest
+ * requests in flight.  An RL request is one step of a scene: its input
+ * image is copied into its block, predict / broadphase / islands / permute
+ * run, and a signal kernel tells the host that the island plan is readable;
+ * the host then submits the plan's Jacobi kernels, integrate, a copy of the
+ * result out of the block and a final signal.  A DNN request is one
+ * inference (acs_dnn_submit's kernels with activations in its block) and a
+ * final signal.  The final signal reads the whole block and the output, so
+ * it runs after every kernel of the request that wrote them; when the host
+ * sees it, the block and the request's slot are released.  Memory reuse
+ * between requests is ordered by the window's own range checks within a
+ * group, and by the final signal across groups.  Latency is the host time
+ * of the final signal minus the arrival time (an open-loop load: a request
+ * arrives at its time whether or not the server keeps up). */
+enum { ACS_SERVE_RL = 0, ACS_SERVE_DNN = 1 };
+typedef struct {
+    int32_t kind;              /* ACS_SERVE_RL or ACS_SERVE_DNN */
+    int32_t n;                 /* RL: bodies, 2..1024 */
+    int32_t iters;             /* RL: Jacobi iterations */
+    float r, dt;               /* RL: radius, time step */
+    int32_t pad;
+    double arrival_ns;         /* after the start of the run; non-decreasing over the array */
+    uint64_t input;            /* RL: device image of a scene arena's first bytes, X and V at their
+                                * acs_rl_layout offsets (off[ACS_RL_V] + 16 n bytes); DNN: x */
+    uint64_t output;           /* RL: same layout, X and V after the step; DNN: logits [classes] */
+    const float *logits;       /* DNN: host gate logits, 2 per cell; RL: unused */
+} acs_serve_request;
+
+typedef struct {
+    double admit_ns;           /* first kernel submitted */
+    double done_ns;            /* final signal seen by the host */
+    uint64_t kernels;          /* kernels submitted, signals and copies included */
+    uint64_t footprint;        /* pool bytes held */
+    int32_t group;
+    int32_t multi_islands;     /* RL: multi-body islands of the step; DNN: -1 */
+} acs_serve_result;
+
+typedef struct {
+    uint64_t pool, pool_bytes;    /* device range for request working memory (256-byte aligned) */
+    void *host;                   /* acs_host_alloc'd, at least acs_serve_host_bytes(max_resident)
+                                   * bytes: signal words and island plans, one slot per request in
+                                   * flight (allocate it before opening the window) */
+    uint64_t host_bytes;
+    int32_t max_resident;         /* requests in flight at most, 1..1024 */
+    int32_t pad;
+    const acs_dnn_graph *model;   /* shapes, weights and head of the network; its
+                                   * x, t3, t1, y, pool and out are ignored (NULL if no DNN request) */
+    uint64_t stall_ns;            /* ACS_ETIMEDOUT when requests are in flight and none has made
+                                   * progress for this long (0: 60 s) */
+} acs_serve_config;
+
+typedef struct {
+    double wall_ns;               /* start of the run to the last completion */
+    uint64_t kernels;
+    uint64_t peak_resident;
+    uint64_t peak_pool_bytes;
+    uint64_t waited_memory;       /* requests that waited at the head of the queue for pool memory */
+    uint64_t waited_resident;     /* ... for a free request slot */
+} acs_serve_stats;
+
+/* Bytes of host memory acs_serve_run needs for max_resident slots. */
+uint64_t acs_serve_host_bytes(int32_t max_resident);
+
+/* Runs n_req requests through window w and drains it.  res (n_req entries)
+ * and stats may be NULL.  ACS_EINVAL for bad arguments (a request whose
+ * working memory exceeds the whole pool, arrivals out of order, DNN requests
+ * without a model, host memory missing or too small); ACS_ETIMEDOUT on a
+ * stall; otherwise the window's first error.  It allocates no device or
+ * pinned host memory. */
+int acs_serve_run(acs_window *w, const acs_serve_config *cfg, const acs_serve_request *req, int32_t n_req,
+                  acs_serve_result *res, acs_serve_stats *stats);
 
 #ifdef __cplusplus
 }

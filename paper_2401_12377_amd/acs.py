@@ -30,6 +30,8 @@ SEG_ALL = (0, (1 << 64) - 1)
 K_NOP, K_SCALE, K_AXPY, K_SUM = 0, 1, 2, 3
 K_RL_PREDICT, K_RL_BROADPHASE, K_RL_ISLANDS, K_RL_PERMUTE, K_RL_JACOBI, K_RL_INTEGRATE = 10, 11, 12, 13, 14, 15
 K_CONV, K_JOIN, K_AVGPOOL, K_FC = 20, 21, 22, 23
+K_COPY, K_SIGNAL = 24, 25
+SERVE_RL, SERVE_DNN = 0, 1
 DNN_MAX_CELLS = 16
 
 RL_X, RL_V, RL_P, RL_Q0, RL_Q1, RL_DEG, RL_ADJ_OFF, RL_ADJ, RL_LABEL, RL_PERM, RL_INV_PERM, RL_ISL_OFF, \
@@ -123,6 +125,39 @@ class DNNGraphC(C.Structure):
                 ("fc_b", C.c_uint64), ("out", C.c_uint64)]
 
 
+class ArgsCopy(C.Structure):
+    _fields_ = [("dst", C.c_uint64), ("src", C.c_uint64), ("bytes", C.c_uint64)]
+
+
+class ArgsSignal(C.Structure):
+    _fields_ = [("addr", C.c_uint64), ("value", C.c_uint64)]
+
+
+class ServeRequestC(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n", C.c_int32), ("iters", C.c_int32), ("r", C.c_float), ("dt", C.c_float),
+                ("pad", C.c_int32), ("arrival_ns", C.c_double), ("input", C.c_uint64), ("output", C.c_uint64),
+                ("logits", C.c_void_p)]
+
+
+class ServeResultC(C.Structure):
+    _fields_ = [("admit_ns", C.c_double), ("done_ns", C.c_double), ("kernels", C.c_uint64),
+                ("footprint", C.c_uint64), ("group", C.c_int32), ("multi_islands", C.c_int32)]
+
+
+class ServeConfigC(C.Structure):
+    _fields_ = [("pool", C.c_uint64), ("pool_bytes", C.c_uint64), ("host", C.c_void_p), ("host_bytes", C.c_uint64),
+                ("max_resident", C.c_int32), ("pad", C.c_int32),
+                ("model", C.c_void_p), ("stall_ns", C.c_uint64)]
+
+
+class ServeStatsC(C.Structure):
+    _fields_ = [("wall_ns", C.c_double)] + [(f, C.c_uint64) for f in ("kernels", "peak_resident", "peak_pool_bytes",
+                                                                       "waited_memory", "waited_resident")]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class ArgsRL(C.Structure):
     _fields_ = [("base", C.c_uint64), ("plan", C.c_uint64), ("n", C.c_int32), ("r", C.c_float), ("dt", C.c_float),
                 ("iter", C.c_int32), ("b0", C.c_int32), ("b1", C.c_int32)]
@@ -196,7 +231,20 @@ def lib():
         L.acs_sync_group.argtypes = [C.c_void_p, C.c_int32, C.c_uint64]
         L.acs_rl_run_batch.argtypes = [C.c_void_p, P(RLSceneC), C.c_int32, C.c_int32, C.c_int32, P(C.c_double),
                                        P(RLCounts)]
-        for f in ("acs_window_configure", "acs_submit", "acs_sync", "acs_sync_timeout", "acs_scheduled_list",
+        L.acs_poll.argtypes = [C.c_void_p]
+        L.acs_pool_create.argtypes = [C.c_uint64, C.c_uint64]
+        L.acs_pool_create.restype = C.c_void_p
+        L.acs_pool_alloc.argtypes = [C.c_void_p, C.c_uint64, P(C.c_uint64)]
+        L.acs_pool_free.argtypes = [C.c_void_p, C.c_uint64]
+        L.acs_pool_info.argtypes = [C.c_void_p, P(C.c_uint64), P(C.c_uint64), P(C.c_int64)]
+        L.acs_pool_destroy.argtypes = [C.c_void_p]
+        L.acs_pool_destroy.restype = None
+        L.acs_serve_host_bytes.argtypes = [C.c_int32]
+        L.acs_serve_host_bytes.restype = C.c_uint64
+        L.acs_serve_run.argtypes = [C.c_void_p, P(ServeConfigC), P(ServeRequestC), C.c_int32, P(ServeResultC),
+                                    P(ServeStatsC)]
+        for f in ("acs_poll", "acs_pool_alloc", "acs_pool_free", "acs_pool_info", "acs_serve_run",
+                  "acs_window_configure", "acs_submit", "acs_sync", "acs_sync_timeout", "acs_scheduled_list",
                   "acs_trace_read", "acs_stats_get", "acs_window_destroy", "acs_window_stop", "acs_manual_take_ready",
                   "acs_manual_complete", "acs_last_error", "acs_rl_layout", "acs_host_free", "acs_rl_run",
                   "acs_nop_run", "acs_dnn_submit", "acs_submit_group", "acs_sync_group", "acs_rl_run_batch",
@@ -381,6 +429,7 @@ class Window:
             return OK
         rc = lib().acs_window_destroy(self._h)
         self._h = None
+        _flush_host_frees()
         return rc
 
     def __enter__(self):
@@ -469,10 +518,31 @@ def rl_plan_ints(n: int) -> int:
     return 4 + 4 * (n // 2)
 
 
+_deferred_host_frees = []
+
+
+def _device_window_open() -> bool:
+    return any(w._h is not None and w.path == "device" for w in list(_live))
+
+
+def _flush_host_frees():
+    """Frees host buffers released while a device window was open (the HIP
+    host allocator synchronises the whole device, which would wait forever
+    on a resident scheduler kernel)."""
+    if _deferred_host_frees and not _device_window_open():
+        while _deferred_host_frees:
+            lib().acs_host_free(_deferred_host_frees.pop())
+
+
 class HostBuffer:
-    """Pinned, coherent host memory from acs_host_alloc, viewed as numpy."""
+    """Pinned, coherent host memory from acs_host_alloc, viewed as numpy.
+    Allocate it before opening a device-path window; a free while one is
+    open is deferred until the last one closes."""
 
     def __init__(self, nbytes: int):
+        if _device_window_open():
+            raise AcsError(ESTATE, "allocate host buffers before opening a device window "
+                                   "(the host allocator synchronises the device)")
         p = lib().acs_host_alloc(nbytes)
         if not p:
             raise AcsError(ENOMEM, "acs_host_alloc failed")
@@ -485,8 +555,9 @@ class HostBuffer:
 
     def free(self):
         if self.ptr:
-            lib().acs_host_free(self.ptr)
+            _deferred_host_frees.append(self.ptr)
             self.ptr = None
+            _flush_host_frees()
 
     def __del__(self):
         try:
@@ -647,3 +718,152 @@ def dnn_submit(win: Window, net: DNNGPU, logits) -> int:
     n = C.c_uint64()
     _check(lib().acs_dnn_submit(win.handle, C.byref(g), lg.ctypes.data, C.byref(n)))
     return n.value
+
+
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+class Pool:
+    """Host-side allocator over a device address range (acs_pool_*)."""
+
+    def __init__(self, base: int, nbytes: int):
+        self.h = lib().acs_pool_create(base, nbytes)
+        if not self.h:
+            raise AcsError(EINVAL, "acs_pool_create: base must be 256-byte aligned and the range at least 256 bytes")
+
+    def alloc(self, nbytes: int):
+        """Block address, or None when no free block is large enough."""
+        a = C.c_uint64()
+        rc = lib().acs_pool_alloc(self.h, nbytes, C.byref(a))
+        if rc == ENOMEM:
+            return None
+        _check(rc)
+        return a.value
+
+    def free(self, addr: int):
+        _check(lib().acs_pool_free(self.h, addr))
+
+    def info(self) -> dict:
+        u, f, n = C.c_uint64(), C.c_uint64(), C.c_int64()
+        _check(lib().acs_pool_info(self.h, C.byref(u), C.byref(f), C.byref(n)))
+        return {"used": u.value, "largest_free": f.value, "blocks": n.value}
+
+    def destroy(self):
+        if self.h:
+            lib().acs_pool_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def _align(x: int, a: int = 256) -> int:
+    return (x + a - 1) // a * a
+
+
+class ServeSet:
+    """Device-resident inputs and outputs of a list of serving requests
+    (inputs.ServeSpec), and the request array acs_serve_run takes."""
+
+    def __init__(self, specs, rl_scenes: dict, dnn_inputs: dict, classes: int, device="cuda"):
+        import torch
+        self.specs = specs
+        self.classes = classes
+        in_off, out_off, self.out_bytes = [], [], []
+        ip = op = 0
+        for sp in specs:
+            if sp.kind == SERVE_RL:
+                off = rl_layout(sp.n)
+                nb = int(off[RL_V]) + 16 * sp.n
+            else:
+                nb = int(np.prod(dnn_inputs[sp.seed].x.shape)) * 4
+            ob = nb if sp.kind == SERVE_RL else 4 * classes
+            in_off.append(ip)
+            out_off.append(op)
+            self.out_bytes.append(ob)
+            ip += _align(nb)
+            op += _align(ob)
+        host_in = np.zeros(max(ip, 256), np.uint8)
+        for sp, o in zip(specs, in_off):
+            if sp.kind == SERVE_RL:
+                sc = rl_scenes[sp.seed]
+                off = rl_layout(sp.n)
+                host_in[o:o + 16 * sp.n] = np.ascontiguousarray(sc.x, np.float32).view(np.uint8).reshape(-1)
+                v0 = o + int(off[RL_V])
+                host_in[v0:v0 + 16 * sp.n] = np.ascontiguousarray(sc.v, np.float32).view(np.uint8).reshape(-1)
+            else:
+                x = np.ascontiguousarray(dnn_inputs[sp.seed].x, np.float32).view(np.uint8).reshape(-1)
+                host_in[o:o + x.size] = x
+        self.inp = torch.from_numpy(host_in).to(device)
+        self.out = torch.zeros(max(op, 256), dtype=torch.uint8, device=device)
+        self.out_off = out_off
+        self.logits = [np.ascontiguousarray(dnn_inputs[sp.seed].logits, np.float32).reshape(-1)
+                       if sp.kind == SERVE_DNN else None for sp in specs]
+        self.req = (ServeRequestC * max(1, len(specs)))()
+        for i, sp in enumerate(specs):
+            q = self.req[i]
+            q.kind = sp.kind
+            q.arrival_ns = sp.arrival_ns
+            q.input = self.inp.data_ptr() + in_off[i]
+            q.output = self.out.data_ptr() + out_off[i]
+            if sp.kind == SERVE_RL:
+                sc = rl_scenes[sp.seed]
+                q.n, q.iters, q.r, q.dt = sp.n, sc.iters, float(sc.radius), float(sc.dt)
+            else:
+                q.logits = self.logits[i].ctypes.data
+        torch.cuda.current_stream().synchronize()
+
+    def clear_outputs(self):
+        import torch
+        self.out.fill_(0xFF)
+        torch.cuda.current_stream().synchronize()
+
+    def outputs(self):
+        """Per request: (X, V) float32[n, 4] for an RL step, logits for a DNN inference."""
+        host = self.out.cpu().numpy()
+        res = []
+        for sp, o, nb in zip(self.specs, self.out_off, self.out_bytes):
+            if sp.kind == SERVE_RL:
+                off = rl_layout(sp.n)
+                x = host[o:o + 16 * sp.n].view(np.float32).reshape(sp.n, 4).copy()
+                v0 = o + int(off[RL_V])
+                v = host[v0:v0 + 16 * sp.n].view(np.float32).reshape(sp.n, 4).copy()
+                res.append((x, v))
+            else:
+                res.append(host[o:o + nb].view(np.float32).copy())
+        return res
+
+
+def serve_footprint_rl(n: int) -> int:
+    return int(rl_layout(n)[RL_END])
+
+
+def serve_host(max_resident: int = 256) -> HostBuffer:
+    """Host signal and plan memory for serve_run (allocate before opening the window)."""
+    return HostBuffer(int(lib().acs_serve_host_bytes(max_resident)))
+
+
+def serve_run(win: Window, sset: ServeSet, pool, host: HostBuffer, pool_bytes: int | None = None,
+              max_resident: int = 256, model: "DNNGPU | None" = None, stall_ns: int = 0):
+    """Runs the requests of `sset` through `win` (acs_serve_run) with working
+    memory from the device tensor `pool` and host memory from serve_host();
+    returns (results, stats) with one dict per request (admit_ns, done_ns,
+    kernels, footprint, group, multi_islands)."""
+    cfg = ServeConfigC()
+    cfg.host, cfg.host_bytes = host.ptr, host.nbytes
+    cfg.pool = pool.data_ptr()
+    cfg.pool_bytes = pool.numel() * pool.element_size() if pool_bytes is None else pool_bytes
+    cfg.max_resident = max_resident
+    g = model.c_struct() if model is not None else None
+    cfg.model = C.cast(C.pointer(g), C.c_void_p) if g is not None else None
+    cfg.stall_ns = stall_ns
+    n = len(sset.specs)
+    res = (ServeResultC * max(1, n))()
+    st = ServeStatsC()
+    _check(lib().acs_serve_run(win.handle, C.byref(cfg), sset.req, n, res, C.byref(st)))
+    out = [{f: getattr(res[i], f) for f, _ in ServeResultC._fields_} for i in range(n)]
+    return out, st.as_dict()
+

@@ -103,6 +103,8 @@ size_t args_size_of(int32_t kid)
     case ACS_K_JOIN: return sizeof(acs_args_join);
     case ACS_K_AVGPOOL: return sizeof(acs_args_avgpool);
     case ACS_K_FC: return sizeof(acs_args_fc);
+    case ACS_K_COPY: return sizeof(acs_args_copy);
+    case ACS_K_SIGNAL: return sizeof(acs_args_signal);
     default: return 0;
     }
 }
@@ -208,6 +210,26 @@ bool check_args(int32_t kid, const uint8_t *args, int32_t g, uint32_t &np, std::
         memcpy(&a, args, sizeof(a));
         if (a.cin < 1 || a.cout < 1 || a.cout > 4096 || !a.in || !a.w || !a.bias || !a.out) {
             if (why) *why = "fc: bad shape";
+            return false;
+        }
+        return true;
+    }
+    case ACS_K_COPY: {
+        acs_args_copy a;
+        memcpy(&a, args, sizeof(a));
+        const uint64_t d = (uint64_t)(uintptr_t)a.dst, s = (uint64_t)(uintptr_t)a.src;
+        if (!a.dst || !a.src || (d | s | a.bytes) % 16 != 0 || a.bytes > (1ull << 40) || (d < s + a.bytes && s < d + a.bytes)) {
+            if (why) *why = "copy: null, unaligned or overlapping buffers";
+            return false;
+        }
+        np = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(gg, (a.bytes + 4095) / 4096));
+        return true;
+    }
+    case ACS_K_SIGNAL: {
+        acs_args_signal a;
+        memcpy(&a, args, sizeof(a));
+        if (!a.addr || (uint64_t)(uintptr_t)a.addr % 8 != 0) {
+            if (why) *why = "signal: null or unaligned word";
             return false;
         }
         return true;
@@ -440,6 +462,13 @@ int acs_sync_group(acs_window *w, int32_t group, uint64_t timeout_ns)
     if (group < 0 || group >= w->cfg.n_groups) return fail(ACS_EINVAL, "group outside [0, n_groups)");
     if (!w->started) return ACS_OK;
     return w->path->sync_group(group, timeout_ns);
+}
+
+int acs_poll(acs_window *w)
+{
+    if (!w) return fail(ACS_EINVAL, "null window");
+    if (!w->started) return ACS_OK;
+    return w->path->poll();
 }
 
 int acs_scheduled_list(acs_window *w, acs_entry *out, int32_t cap, int32_t *n_out)

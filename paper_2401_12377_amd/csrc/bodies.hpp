@@ -752,6 +752,23 @@ __device__ inline void body_fc(const acs_args_fc &a)
     }
 }
 
+// uint4 copy, pieces take consecutive 4 KiB chunks round-robin
+__device__ inline void body_copy(const acs_args_copy &a, uint32_t piece, uint32_t np)
+{
+    const uint64_t nv = a.bytes / 16;
+    const uint4 *src = reinterpret_cast<const uint4 *>(a.src);
+    uint4 *dst = reinterpret_cast<uint4 *>(a.dst);
+    for (uint64_t i = (uint64_t)piece * ACS_BLOCK + threadIdx.x; i < nv; i += (uint64_t)np * ACS_BLOCK) dst[i] = src[i];
+}
+
+// one lane stores; the system-scope release orders it after the writes of
+// every kernel this one waited for (their completions were acquired before
+// the body started)
+__device__ inline void body_signal(const acs_args_signal &a)
+{
+    if (threadIdx.x == 0) __hip_atomic_store(a.addr, a.value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 template <typename T>
 __device__ inline T load_args(const void *p)
 {
@@ -777,6 +794,8 @@ __device__ __forceinline__ void run_body(int32_t kid, const void *args, uint32_t
     case ACS_K_JOIN: body_join(load_args<acs_args_join>(args), piece, np); break;
     case ACS_K_AVGPOOL: body_avgpool(load_args<acs_args_avgpool>(args)); break;
     case ACS_K_FC: body_fc(load_args<acs_args_fc>(args)); break;
+    case ACS_K_COPY: body_copy(load_args<acs_args_copy>(args), piece, np); break;
+    case ACS_K_SIGNAL: body_signal(load_args<acs_args_signal>(args)); break;
     default: break;
     }
 }

@@ -162,6 +162,15 @@ public:
         return err_;
     }
 
+    int poll() override
+    {
+        if (!running_) return err_;
+        if (++polls_ % 1024 == 0)
+            if (int rc = check_alive()) return rc;
+        if (ctrl_->error) err_ = ACS_EKERNEL;
+        return err_;
+    }
+
     int scheduled_list(acs_entry *out, int32_t cap, int32_t *n) override
     {
         if (!running_) {
@@ -296,6 +305,7 @@ private:
     }
 
     int32_t W_;
+    uint64_t polls_ = 0;
     acs_config cfg_;
     HostCtrl *ctrl_ = nullptr;
     DevDesc *ring_ = nullptr;

@@ -1,0 +1,122 @@
+// Application-side graph builders shared by the native drivers (the RL
+// step and the gated network); they call the public API only.  The range
+// helpers are the workload's get_addresses functions (Section IV-A): they
+// state, from the launch arguments, which bytes each kernel reads and writes.
+#pragma once
+#include <stdint.h>
+
+#include "acs.h"
+#include "acs_tasks.h"
+#include "acs_workloads.h"
+#include "rl_layout.hpp"
+
+namespace acs {
+
+// One scene's kernels of a step, in the two halves the host submits
+// (before and after reading the input-dependent island plan).
+class RLStep {
+public:
+    RLStep(acs_window *w, int32_t group, const acs_rl_scene *sc) : w_(w), g_(group), sc_(sc)
+    {
+        acs::rl_offsets(sc->n, off_);
+        a_ = {};
+        a_.base = sc->arena;
+        a_.plan = (uint64_t)(uintptr_t)sc->plan;
+        a_.n = sc->n;
+        a_.r = sc->r;
+        a_.dt = sc->dt;
+    }
+
+    // predict, broadphase, islands, permute
+    int submit_prefix(acs_rl_counts &cnt)
+    {
+        const acs_seg plan_seg = {(uint64_t)(uintptr_t)sc_->plan, 4ull * acs::rl_plan_ints(sc_->n)};
+        a_.iter = a_.b0 = a_.b1 = 0;
+        {
+            const acs_seg r[2] = {region(ACS_RL_X), region(ACS_RL_V)};
+            const acs_seg wr[1] = {region(ACS_RL_P)};
+            if (int rc = submit(ACS_K_RL_PREDICT, r, 2, wr, 1, cnt)) return rc;
+        }
+        {
+            const acs_seg r[1] = {region(ACS_RL_P)};
+            const acs_seg wr[1] = {span(ACS_RL_DEG, ACS_RL_LABEL)};
+            if (int rc = submit(ACS_K_RL_BROADPHASE, r, 1, wr, 1, cnt)) return rc;
+        }
+        {
+            const acs_seg r[1] = {span(ACS_RL_DEG, ACS_RL_LABEL)};
+            const acs_seg wr[2] = {span(ACS_RL_LABEL, ACS_RL_END), plan_seg};
+            if (int rc = submit(ACS_K_RL_ISLANDS, r, 1, wr, 2, cnt)) return rc;
+        }
+        const acs_seg r[2] = {region(ACS_RL_P), region(ACS_RL_PERM)};
+        const acs_seg wr[1] = {region(ACS_RL_Q0)};
+        return submit(ACS_K_RL_PERMUTE, r, 2, wr, 1, cnt);
+    }
+
+    // once the plan is readable: the plan's Jacobi kernels
+    // (iteration-major) and integrate
+    int submit_tail(acs_rl_counts &cnt)
+    {
+        const int32_t *plan = (const int32_t *)sc_->plan;
+        const int32_t nmulti = __atomic_load_n(&plan[1], __ATOMIC_ACQUIRE);
+        if (nmulti < 0 || nmulti > sc_->n / 2) return ACS_EKERNEL;
+        cnt.steps++;
+        cnt.islands += (uint64_t)plan[0];
+        cnt.multi_islands += (uint64_t)nmulti;
+        cnt.edges += (uint64_t)plan[2];
+        for (int32_t it = 0; it < sc_->iters; it++) {
+            const int src = (it % 2 == 0) ? ACS_RL_Q0 : ACS_RL_Q1, dst = (it % 2 == 0) ? ACS_RL_Q1 : ACS_RL_Q0;
+            for (int32_t k = 0; k < nmulti; k++) {
+                const int32_t b0 = plan[4 + 4 * k], b1 = plan[5 + 4 * k], e0 = plan[6 + 4 * k], e1 = plan[7 + 4 * k];
+                if (b0 < 0 || b1 > sc_->n || b1 - b0 < 2 || e0 < 0 || e1 < e0 || e1 > sc_->n * (sc_->n - 1))
+                    return ACS_EKERNEL;   // a plan row the islands kernel cannot produce
+                a_.iter = it;
+                a_.b0 = b0;
+                a_.b1 = b1;
+                const acs_seg r[3] = {vec(src, b0, b1), ints(ACS_RL_PADJ_OFF, b0, b1 + 1), ints(ACS_RL_PADJ, e0, e1)};
+                const acs_seg wr[1] = {vec(dst, b0, b1)};
+                if (int rc = submit(ACS_K_RL_JACOBI, r, 3, wr, 1, cnt)) return rc;
+                cnt.jacobi_kernels++;
+                cnt.jacobi_bodies += (uint64_t)(b1 - b0);
+                cnt.jacobi_edges += (uint64_t)(e1 - e0);
+            }
+        }
+        a_.iter = a_.b0 = a_.b1 = 0;
+        const acs_seg r[4] = {region(ACS_RL_P), region(ACS_RL_V), region(ACS_RL_Q0), region(ACS_RL_INV_PERM)};
+        const acs_seg wr[2] = {region(ACS_RL_X), region(ACS_RL_V)};
+        return submit(ACS_K_RL_INTEGRATE, r, 4, wr, 2, cnt);
+    }
+
+private:
+    acs_seg region(int r) const { return acs_seg{sc_->arena + off_[r], off_[r + 1] - off_[r]}; }
+    acs_seg span(int r0, int r1) const { return acs_seg{sc_->arena + off_[r0], off_[r1] - off_[r0]}; }
+    acs_seg vec(int r, int32_t b0, int32_t b1) const
+    {
+        return acs_seg{sc_->arena + off_[r] + 16ull * b0, 16ull * (uint64_t)(b1 - b0)};
+    }
+    acs_seg ints(int r, int32_t b0, int32_t b1) const
+    {
+        return acs_seg{sc_->arena + off_[r] + 4ull * b0, 4ull * (uint64_t)(b1 - b0)};
+    }
+    int submit(int32_t kid, const acs_seg *r, int32_t nr, const acs_seg *wr, int32_t nw, acs_rl_counts &cnt)
+    {
+        const int rc = acs_submit_group(w_, g_, kid, r, nr, wr, nw, &a_, sizeof(a_), nullptr);
+        if (rc == ACS_OK) cnt.kernels++;
+        return rc;
+    }
+
+    acs_window *w_;
+    int32_t g_;
+    const acs_rl_scene *sc_;
+    uint64_t off_[ACS_RL_NREGIONS];
+    acs_args_rl a_;
+};
+
+// Submits one inference of the gated network into window group `group`
+// (acs_dnn_submit is this with group 0).
+int dnn_submit_group(acs_window *w, int32_t group, const acs_dnn_graph *g, const float *logits, uint64_t *n_kernels);
+
+// Device bytes of the activations of one inference (every cell's two branch
+// outputs and output, and the pooled vector), each 256-byte aligned.
+uint64_t dnn_activation_bytes(const acs_dnn_graph *g);
+
+}  // namespace acs

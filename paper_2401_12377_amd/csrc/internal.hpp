@@ -67,6 +67,7 @@ public:
     virtual int submit_group(const Desc &d, int32_t group) { (void)group; return submit(d); }
     virtual int sync(uint64_t timeout_ns) = 0;                     // 0 = wait forever
     virtual int sync_group(int32_t group, uint64_t timeout_ns) { (void)group; return sync(timeout_ns); }
+    virtual int poll() { return ACS_OK; }
     virtual int scheduled_list(acs_entry *out, int32_t cap, int32_t *n) = 0;
     virtual int trace_read(acs_trace_rec *out, int64_t cap, int64_t *n) = 0;
     virtual int take_ready(uint64_t *, int32_t, int32_t *) { return ACS_ESTATE; }

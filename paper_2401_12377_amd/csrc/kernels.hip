@@ -46,6 +46,8 @@ static const void *const k_table[ACS_K_COUNT] = {
     reinterpret_cast<const void *>(&k_task<ACS_K_JOIN, acs_args_join>),
     reinterpret_cast<const void *>(&k_task<ACS_K_AVGPOOL, acs_args_avgpool>),
     reinterpret_cast<const void *>(&k_task<ACS_K_FC, acs_args_fc>),
+    reinterpret_cast<const void *>(&k_task<ACS_K_COPY, acs_args_copy>),
+    reinterpret_cast<const void *>(&k_task<ACS_K_SIGNAL, acs_args_signal>),
 };
 static_assert(sizeof(k_table) / sizeof(k_table[0]) == ACS_K_COUNT, "task table size");
 

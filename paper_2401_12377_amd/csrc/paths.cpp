@@ -183,6 +183,16 @@ public:
         resolve_trace();
         return err_;
     }
+    int poll() override
+    {
+        if (!stream_ || err_) return err_;
+        const hipError_t q = hipStreamQuery(stream_);
+        if (q != hipSuccess && q != hipErrorNotReady) {
+            err_ = ACS_EDEVICE;
+            return hip_fail(q, "stream");
+        }
+        return ACS_OK;
+    }
     int scheduled_list(acs_entry *, int32_t, int32_t *n) override
     {
         if (n) *n = 0;
@@ -320,6 +330,13 @@ public:
             }
             _mm_pause();
         }
+        if (dev_err_) return dev_err_;
+        return win_.first_error() ? ACS_EKERNEL : ACS_OK;
+    }
+    int poll() override
+    {
+        if (!started_) return ACS_OK;
+        progress();
         if (dev_err_) return dev_err_;
         return win_.first_error() ? ACS_EKERNEL : ACS_OK;
     }

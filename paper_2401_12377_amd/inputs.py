@@ -22,7 +22,9 @@ stand in for them, shaped like the paper's evaluation workloads):
 * dynamic DNN, batch 1: 12 cells of two gated parallel branches (3x3 and 1x1
   convolutions), 32x32x32 -> 8x8x128 NHWC, average pool and a 128 -> 10 fully
   connected head; which branches run depends on seeded per-input logits (the
-  paper's dynamic-network case study, Section II-C).
+  paper's dynamic-network case study, Section II-C);
+* serving: an open-loop request stream with Poisson arrivals mixing RL scene
+  steps (log-uniform size) and DNN inferences.
 """
 from __future__ import annotations
 
@@ -268,3 +270,38 @@ def dnn_input(seed: int = 0) -> DNNInput:
     x = uniform_pm1(bits[:h * w * c]).reshape(h, w, c)
     logits = uniform_pm1(bits[h * w * c:]).reshape(len(DNN_CELLS), 2)
     return DNNInput(seed=seed, x=x, logits=logits)
+
+
+# ---------------------------------------------------------------------------
+# Serving: Poisson arrivals of mixed requests
+# ---------------------------------------------------------------------------
+
+SERVE_RL, SERVE_DNN = 0, 1
+
+
+@dataclass
+class ServeSpec:
+    kind: int             # SERVE_RL or SERVE_DNN
+    arrival_ns: float     # after the start of the run
+    seed: int             # scene or input seed
+    n: int = 0            # RL bodies
+
+
+def serve_requests(seed: int = 4, rate_per_s: float = 5000.0, n_requests: int = 2000, rl_fraction: float = 0.5,
+                   lo: int = 16, hi: int = 512) -> list:
+    """Poisson arrivals at rate_per_s (exponential gaps by inversion of
+    U[0, 1)); each request is an RL step of a scene of log-uniform size in
+    [lo, hi] with probability rl_fraction, else a DNN inference."""
+    u = uniform_01(splitmix64_array((0x5E27E << 32) ^ seed, 3 * n_requests)).reshape(n_requests, 3)
+    gaps = -np.log1p(-u[:, 0]) / rate_per_s * 1e9
+    t = np.cumsum(gaps)
+    sizes = np.clip(np.rint(np.exp(math.log(lo) + u[:, 2] * (math.log(hi) - math.log(lo)))), lo, hi).astype(np.int64)
+    out = []
+    for i in range(n_requests):
+        req_seed = (seed * 1_000_003 + 7919 * i) & MASK64
+        if u[i, 1] < rl_fraction:
+            out.append(ServeSpec(SERVE_RL, float(t[i]), req_seed, int(sizes[i])))
+        else:
+            out.append(ServeSpec(SERVE_DNN, float(t[i]), req_seed))
+    return out
+
