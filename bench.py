@@ -249,6 +249,64 @@ def dnn_section(acs, inputs, torch, args):
             "throughput_speedup": out["device"]["inferences_per_s"] / out["inorder"]["inferences_per_s"]}
 
 
+def serve_section(acs, inputs, torch, args):
+    """Serving: an open-loop Poisson stream of mixed requests (RL scene steps,
+    DNN inferences) at several arrival rates through one open window per
+    run; latency = completion seen by the host minus arrival."""
+    import numpy as np
+    rates = [float(r) for r in args.serve_rates.split(",")]
+    n = args.serve_requests
+    specs0 = inputs.serve_requests(seed=4, rate_per_s=rates[0], n_requests=n)
+    rl = {s.seed: inputs.rl_scene(seed=s.seed, n=s.n) for s in specs0 if s.kind == inputs.SERVE_RL}
+    dnn = {s.seed: inputs.dnn_input(s.seed) for s in specs0 if s.kind == inputs.SERVE_DNN}
+    net = acs.DNNGPU(inputs.dnn_weights(), inputs.DNN_CELLS, inputs.DNN_CLASSES)
+    pool = torch.empty(args.serve_pool_mib << 20, dtype=torch.uint8, device="cuda")
+    host = acs.serve_host(args.serve_resident)
+    configs = [("device", 32, 1), ("device", 16, 4), ("device", 8, 8), ("inorder", 8, 1)]
+    table = {}
+    outputs = {}
+    for path, W, G in configs:
+        key = f"{path}_W{W}_G{G}" if path == "device" else path
+        rows = []
+        for lam in rates:
+            specs = inputs.serve_requests(seed=4, rate_per_s=lam, n_requests=n)
+            sset = acs.ServeSet(specs, rl, dnn, inputs.DNN_CLASSES)
+            with acs.Window(W, path=path, n_groups=G) as w:
+                res, st = acs.serve_run(w, sset, pool, host, max_resident=args.serve_resident, model=net,
+                                        stall_ns=60 * 10 ** 9)
+            lat = np.array([r["done_ns"] - s.arrival_ns for r, s in zip(res, specs)]) / 1e6
+            kinds = np.array([s.kind for s in specs])
+            row = {"rate_per_s": lam, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                   "mean_ms": float(lat.mean()),
+                   "p50_ms_rl": float(np.percentile(lat[kinds == inputs.SERVE_RL], 50)),
+                   "p50_ms_dnn": float(np.percentile(lat[kinds == inputs.SERVE_DNN], 50)),
+                   "requests_per_s": n / (st["wall_ns"] * 1e-9), "kernels_per_s": st["kernels"] / (st["wall_ns"] * 1e-9),
+                   "kernels": st["kernels"], "peak_resident": st["peak_resident"],
+                   "peak_pool_mib": st["peak_pool_bytes"] / 2 ** 20, "waited_memory": st["waited_memory"],
+                   "waited_resident": st["waited_resident"]}
+            rows.append(row)
+            if lam == rates[len(rates) // 2]:
+                outputs[key] = sset.outputs()
+            log(f"[bench] serve {key} rate {lam:.0f}/s: p50 {row['p50_ms']:.3f} ms, p99 {row['p99_ms']:.3f} ms, "
+                f"{row['requests_per_s']:.0f} req/s")
+            del sset
+        table[key] = rows
+
+    def same(a, b):
+        for x, y in zip(a, b):
+            xs = x if isinstance(x, tuple) else (x,)
+            ys = y if isinstance(y, tuple) else (y,)
+            if not all(np.array_equal(u.view(np.uint32), v.view(np.uint32)) for u, v in zip(xs, ys)):
+                return False
+        return True
+    ref = outputs["inorder"]
+    return {"workload": f"{n} requests per rate, Poisson arrivals, half RL scene steps (16-512 bodies log-uniform) "
+                        f"and half DNN inferences, pool {args.serve_pool_mib} MiB, at most {args.serve_resident} "
+                        "in flight",
+            "by_config": table,
+            "results_equal_inorder": {k: same(v, ref) for k, v in outputs.items() if k != "inorder"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -268,6 +326,11 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--no-dnn", action="store_true", help="skip the dynamic-DNN section")
     ap.add_argument("--dnn-inputs", type=int, default=64)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-rates", default="1000,2000,5000,10000,20000")
+    ap.add_argument("--serve-pool-mib", type=int, default=256)
+    ap.add_argument("--serve-resident", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run device copies of known size (for PMC byte-counter scaling)")
     args = ap.parse_args()
@@ -349,6 +412,8 @@ def main():
         out["batched"] = batched_section(acs, inputs, torch, args)
     if not args.no_dnn:
         out["dnn"] = dnn_section(acs, inputs, torch, args)
+    if not args.no_serve:
+        out["serving"] = serve_section(acs, inputs, torch, args)
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline ({args.cpu_seconds:.0f} s of oracle)")
         out["cpu_baseline"] = cpu_baseline(inputs, args)
