@@ -10,9 +10,12 @@ Inputs are seeded and synthetic (they stand in for the paper's Brax
 environments, which are not available here).
 
 Paths timed on the same episodes:
-  device   the persistent scheduler kernel (headline `value`)
-  inorder  every kernel launched into one HIP stream (the baseline)
-  plain    host-side window + pool of HIP streams
+  device            the persistent scheduler kernel (headline `value`)
+  device_hostcheck  the same kernel with the dependency checks made on the
+                    host against its list of the last W kernels (the
+                    host/device split), the window wave only filtering
+  inorder           every kernel launched into one HIP stream (the baseline)
+  plain             host-side window + pool of HIP streams
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -91,31 +94,41 @@ def algorithmic_bytes(counts: dict, n: int) -> int:
     return int(fixed + jac)
 
 
+def open_window(acs, path, W, **kw):
+    """`device_hostcheck` is the device path with the dependency checks on
+    the host (a scheduled list of the last W kernels) instead of the window wave."""
+    if path == "device_hostcheck":
+        return acs.Window(W, path="device", host_check_depth=W, **kw)
+    return acs.Window(W, path=path, **kw)
+
+
 def run_path(acs, inputs, torch, path, args, n_episodes, collect):
     """Runs n_episodes fresh episodes; returns (seconds, kernels, step_ns list, kernel_ns list, counts)."""
     scenes = [acs.RLSceneGPU(inputs.rl_scene(seed=args.seed, n=args.bodies)) for _ in range(n_episodes)]
     torch.cuda.synchronize()
     kernels = 0
     step_ns, kern_ns, counts = [], [], None
+    tests = 0
     t0 = time.perf_counter()
     for g in scenes:
-        w = acs.Window(args.window, path=path, n_streams=args.streams, wg_per_task=1)
+        w = open_window(acs, path, args.window, n_streams=args.streams, wg_per_task=1)
         c, ns = acs.rl_run(w, g, args.physics_steps)
         w.stop()
         st = w.stats()
         w.destroy()
         kernels += c["kernels"]
+        tests += st["overlap_tests"]
         if collect:
             step_ns.extend(ns.tolist())
             kern_ns.append(st["kernel_ns"])
         counts = c
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return dt, kernels, step_ns, kern_ns, counts
+    return dt, kernels, step_ns, kern_ns, counts, tests / max(1, kernels)
 
 
 def overhead_probe(acs, path, n, chain):
-    w = acs.Window(32, path=path)
+    w = open_window(acs, path, 32)
     ns = acs.nop_run(w, n, chain)
     w.destroy()
     return ns / n / 1000.0
@@ -320,7 +333,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
-    ap.add_argument("--paths", default="device,inorder,plain")
+    ap.add_argument("--paths", default="device,device_hostcheck,inorder,plain")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-scenes section")
     ap.add_argument("--batch-scenes", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=20)
@@ -360,7 +373,7 @@ def main():
         log(f"[bench] {path}: {dt * 1e3 / args.steps:.2f} ms/episode, {k / dt:.0f} kernels/s")
 
     dev = res["device"]
-    dt, kernels, step_ns, kern_ns, counts = dev
+    dt, kernels, step_ns, kern_ns, counts, _ = dev
     value = kernels / dt
     out = {
         "metric": "kernels/sec and end-to-end speedup vs in-order stream; p50/p99 graph latency",
@@ -383,6 +396,10 @@ def main():
     if "inorder" in res:
         out["speedup_vs_inorder"] = res["inorder"][0] / dt
         out["inorder_kernels_per_s"] = res["inorder"][1] / res["inorder"][0]
+    if "device_hostcheck" in res:
+        hc = res["device_hostcheck"]
+        out["host_check_split"] = {"kernels_per_s": hc[1] / hc[0], "vs_device_checks": dt / hc[0],
+                                   "host_overlap_tests_per_kernel": hc[5]}
     if "plain" in res:
         out["plain_kernels_per_s"] = res["plain"][1] / res["plain"][0]
         out["plain_speedup_vs_inorder"] = res["inorder"][0] / res["plain"][0] if "inorder" in res else None
@@ -405,7 +422,8 @@ def main():
         log("[bench] overhead probes")
         probes = {}
         for p in paths:
-            probes[p] = {"independent_us_per_kernel": overhead_probe(acs, p, 20000 if p == "device" else 4000, False),
+            probes[p] = {"independent_us_per_kernel": overhead_probe(acs, p, 20000 if p.startswith("device") else 4000,
+                                                                     False),
                          "chain_us_per_kernel": overhead_probe(acs, p, 2000, True)}
         out["overhead_us_per_kernel"] = probes
     if not args.no_batch:

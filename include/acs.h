@@ -91,7 +91,14 @@ typedef struct {
     int32_t trace_capacity;  /* kernels the trace can hold (default 1 << 16) */
     int32_t device;          /* HIP device ordinal (default 0) */
     int32_t n_groups;        /* independent windows of W slots each (default 1; see acs_submit_group) */
-    int32_t reserved[6];
+    int32_t host_check_depth;/* device path, one group: 0 (default) = dependency checks in the window
+                                wave; M in [1, 64] = the host/device split of Section IV-C: the host
+                                checks each kernel against the kernels of the M sequence numbers
+                                before it (its scheduled list, possibly stale), the device drops
+                                upstream kernels that already completed and holds a kernel back
+                                while one more than M older is still in the window.  Same
+                                schedules; other paths ignore it. */
+    int32_t reserved[5];
 } acs_config;
 
 /* One entry of the scheduled list (Section IV-C): the kernels currently in the

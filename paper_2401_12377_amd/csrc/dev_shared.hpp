@@ -2,6 +2,7 @@
 // the host compiler) and the persistent scheduler kernel (built by hipcc).
 // Plain fixed-width fields only, so both compilers agree on the layout.
 #pragma once
+#include <stddef.h>
 #include <stdint.h>
 
 #include "acs.h"
@@ -13,9 +14,10 @@ constexpr int kSegs = ACS_K_MAX;
 // One submitted kernel as it travels from the host to the scheduler wave.
 // Segments are stored as [start, end) with end saturated at 2^64 - 1; unused
 // entries are the empty range [0, 0), which overlaps nothing.  The scheduler
-// copies the whole descriptor into the task table when it inserts the kernel
-// (one 4-byte store per lane); the last 40 bytes are left to the scheduler,
-// which keeps there what the workers need at dispatch.
+// copies the first kDescCopyDwords words into the task table when it inserts
+// the kernel (one 4-byte store per lane); the last 40 bytes hold what the
+// scheduler fills in at dispatch for the workers and, in host-check mode,
+// the upstream list the host computed.
 struct DevDesc {
     uint64_t seq;
     int32_t kid;
@@ -28,10 +30,17 @@ struct DevDesc {
     // scheduler-owned part (the host leaves it zero)
     uint64_t wait_mask;     // window slots still running when the kernel was dispatched
     uint32_t ptarget;       // cnt[slot] after this kernel's last piece (npieces > 1)
-    uint32_t pad[7];
+    uint32_t pad0;
+    // host-check mode: bit d set when the host found the kernel submitted
+    // d + 1 places earlier in conflict with this one (read by the window wave
+    // from the staged copy; not part of the task table)
+    uint64_t host_up;
+    uint32_t pad[4];
 };
 static_assert(sizeof(DevDesc) == 256, "descriptor must be 256 bytes");
-constexpr uint32_t kDescCopyDwords = 54;   // dwords of DevDesc written by the host
+static_assert(offsetof(DevDesc, host_up) == 232, "host_up is dwords 58 and 59 of the descriptor");
+constexpr uint32_t kDescCopyDwords = 54;   // dwords of DevDesc the task table needs
+constexpr int kHostUpDword = 58;
 
 constexpr int kMaxGroups = 8;   // independent windows served by one window wave
 
@@ -96,7 +105,8 @@ struct DevParams {
     int32_t W;                    // slots per group
     int32_t n_workers;
     int32_t n_groups;             // independent windows, 1..kMaxGroups; n_groups * pow2(W) <= 64
-    int32_t pad;
+    int32_t host_check;           // 0: dependency checks on the device; M > 0: the host checks each
+                                  // kernel against the M submitted before it (one window only)
 };
 
 }  // namespace acs

@@ -85,6 +85,9 @@ public:
         p.W = W_;
         p.n_workers = n_workers_;
         p.n_groups = groups_;
+        hc_ = groups_ == 1 ? std::max(0, std::min(cfg_.host_check_depth, ACS_W_MAX)) : 0;
+        p.host_check = hc_;
+        hist_.assign((size_t)std::max(1, hc_), Desc{});
         if ((e = hipEventCreate(&ev0_)) != hipSuccess) return hip_fail(e, "hipEventCreate");
         if ((e = hipEventCreate(&ev1_)) != hipSuccess) return hip_fail(e, "hipEventCreate");
         if ((e = hipEventRecord(ev0_, stream_)) != hipSuccess) return hip_fail(e, "hipEventRecord");
@@ -129,6 +132,7 @@ public:
             tmp.e[k] = d.e[k];
         }
         memcpy(tmp.args, d.args, ACS_ARGS_MAX);
+        if (hc_ > 0) tmp.host_up = host_check(d);
         memcpy((void *)&r, &tmp, sizeof(DevDesc));
         submitted_[g]++;
         total_submitted_++;
@@ -275,12 +279,33 @@ public:
         for (int32_t g = 0; g < groups_; g++) ret += ctrl_ ? ctrl_->retired[g] : submitted_[g];
         s.retired = ret;
         s.dispatched = s.retired;
-        s.overlap_tests = running_ && ctrl_ ? ctrl_->checks : checks_;
+        s.overlap_tests = (running_ && ctrl_ ? ctrl_->checks : checks_) + host_tests_;
         s.n_workers = n_workers_;
         s.kernel_ns = kernel_ns_;
     }
 
 private:
+    // Host-check mode (the split of Section IV-C): the new kernel is checked
+    // against the kernels submitted with the M sequence numbers before its
+    // own, the host's scheduled list.  The list is stale by design: some of
+    // them may have completed (the device drops those), and none older can
+    // still be in the window when the kernel is inserted (the device holds it
+    // back until that is so).  Bit d of the result: sequence number seq - 1 - d.
+    uint64_t host_check(const Desc &d)
+    {
+        const uint64_t M = (uint64_t)hc_;
+        uint64_t mask = 0;
+        for (uint64_t k = 0; k < std::min<uint64_t>(M, hist_n_); k++) {
+            const Desc &o = hist_[(size_t)((hist_n_ - 1 - k) % M)];
+            const uint64_t back = d.seq - 1 - o.seq;
+            if (back >= M) break;   // older entries are farther back still
+            if (descs_conflict(o, d, &host_tests_)) mask |= 1ull << back;
+        }
+        hist_[(size_t)(hist_n_ % M)] = d;
+        hist_n_++;
+        return mask;
+    }
+
     // A persistent kernel that left early (fault or abort) can no longer
     // retire anything: report it instead of spinning forever.
     int check_alive()
@@ -306,6 +331,10 @@ private:
 
     int32_t W_;
     uint64_t polls_ = 0;
+    int32_t hc_ = 0;                 // host-check depth M (0: checks on the device)
+    std::vector<Desc> hist_;         // the last M descriptors submitted, by submission index % M
+    uint64_t hist_n_ = 0;
+    uint64_t host_tests_ = 0;
     acs_config cfg_;
     HostCtrl *ctrl_ = nullptr;
     DevDesc *ring_ = nullptr;

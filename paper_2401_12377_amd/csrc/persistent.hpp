@@ -221,6 +221,8 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
     const bool tr = p.trace != nullptr;
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint32_t depth = lds_depth(G);
+    const bool hc = NG == 1 && p.host_check > 0;
+    const uint64_t hcm = (uint64_t)(p.host_check > 0 ? p.host_check : 0);
 
     // Slots: group g owns lanes [g * Wp, g * Wp + W), Wp = W rounded up to a
     // power of two; span = G * Wp lanes hold slots.  When span < 64 the
@@ -296,12 +298,16 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                 for (uint32_t pass = 0; pass < passes && head[0] != ftail[0] && valid != full; pass++) {
                     const DevDesc *d = &fs->ring[head[0] % depth];
                     const uint32_t dw = reinterpret_cast<const uint32_t *>(d)[lane];
+                    const uint64_t seq = readpair(dw, 0);
+                    // host-check mode: the host compared this kernel with the M
+                    // submitted before it only, so it waits while an older kernel
+                    // is still in the window (the upstream load module's gate)
+                    if (hc && __builtin_amdgcn_ballot_w64(((valid >> lane) & 1ull) && myseq + hcm < seq) != 0) break;
                     const int slot = __builtin_ctzll(~valid & full);
                     const uint64_t bit = 1ull << slot;
                     const uint32_t nraw = readlane32(dw, 4);
                     const uint32_t nseg = nraw < (uint32_t)kSegs ? nraw : (uint32_t)kSegs;
                     const uint32_t wb = readlane32(dw, 5);
-                    const uint64_t seq = readpair(dw, 0);
                     const int32_t kid = (int32_t)readlane32(dw, 2);
                     const uint32_t npr = readlane32(dw, 3);
                     const uint32_t np = npr < kMaxPieces ? npr : kMaxPieces;
@@ -309,7 +315,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                     if (lane < kDescCopyDwords) reinterpret_cast<uint32_t *>(&p.st->task[slot])[lane] = dw;
                     // Algorithm 1 in both directions (see the group case below)
                     uint64_t hits = 0;
-                    for (uint32_t k0 = 0; k0 < nseg; k0 += R) {
+                    for (uint32_t k0 = 0; !hc && k0 < nseg; k0 += R) {
                         const uint32_t k = k0 + rep;
                         const bool kin = rep < R && k < nseg;
                         const uint32_t kk = kin ? k : 0u;
@@ -322,6 +328,13 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                     }
                     uint64_t upm = 0;
                     for (uint32_t r = 0; r < R; r++) upm |= (hits >> (r * span)) & spanmask;
+                    if (hc) {
+                        // the host's list, by distance back in submission order;
+                        // kernels that already left the window drop out here
+                        const uint64_t hup = readpair(dw, kHostUpDword), back = seq - 1 - myseq;
+                        upm = __builtin_amdgcn_ballot_w64(((valid >> lane) & 1ull) && back < hcm &&
+                                                          ((hup >> (back & 63u)) & 1ull));
+                    }
                     upm &= valid;
                     if (sl == (uint32_t)slot && rep < R) {
 #pragma unroll
@@ -330,7 +343,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                             se[m] = d->e[m];
                         }
                     }
-                    checks += (uint64_t)__builtin_popcountll(valid) * nseg * kSegs;
+                    if (!hc) checks += (uint64_t)__builtin_popcountll(valid) * nseg * kSegs;
                     if ((int)lane == slot) {
                         up = upm;
                         myseq = seq;

@@ -76,9 +76,9 @@ typedef struct {
 // timeout_s (the emulated kernel is then aborted through the stop flag).
 // groups[i] (NULL: all 0) is the window group of descriptor i, n_groups the
 // number of groups of W slots.
-int sim_run_groups(int32_t W, int32_t n_groups, int32_t n_workers, int32_t n, const sim_desc *descs,
-                   const int32_t *groups, uint32_t ring_cap, acs_trace_rec *trace_out, double timeout_s,
-                   uint64_t *retired_out)
+static int run_sim(int32_t W, int32_t n_groups, int32_t host_check, int32_t n_workers, int32_t n,
+                   const sim_desc *descs, const int32_t *groups, const uint64_t *host_up, uint32_t ring_cap,
+                   acs_trace_rec *trace_out, double timeout_s, uint64_t *retired_out)
 {
     using namespace acs;
     int32_t wp = 1;
@@ -107,6 +107,7 @@ int sim_run_groups(int32_t W, int32_t n_groups, int32_t n_workers, int32_t n, co
     p.W = W;
     p.n_workers = n_workers;
     p.n_groups = n_groups;
+    p.host_check = host_check;
 
     const int nblk = 1 + n_workers;
     std::vector<std::unique_ptr<Block>> blocks;
@@ -147,6 +148,7 @@ int sim_run_groups(int32_t W, int32_t n_groups, int32_t n_workers, int32_t n, co
         memcpy(d.s, descs[i].s, sizeof(d.s));
         memcpy(d.e, descs[i].e, sizeof(d.e));
         memcpy(d.args, descs[i].args, sizeof(d.args));
+        if (host_up) d.host_up = host_up[i];
         ring[(size_t)g * ring_cap + (sub[g] & (ring_cap - 1))] = d;
         sub[g]++;
         __atomic_store_n(&ctrl->tail[g], sub[g], __ATOMIC_SEQ_CST);
@@ -185,10 +187,27 @@ int sim_run_groups(int32_t W, int32_t n_groups, int32_t n_workers, int32_t n, co
     return rc;
 }
 
+int sim_run_groups(int32_t W, int32_t n_groups, int32_t n_workers, int32_t n, const sim_desc *descs,
+                   const int32_t *groups, uint32_t ring_cap, acs_trace_rec *trace_out, double timeout_s,
+                   uint64_t *retired_out)
+{
+    return run_sim(W, n_groups, 0, n_workers, n, descs, groups, nullptr, ring_cap, trace_out, timeout_s, retired_out);
+}
+
 int sim_run(int32_t W, int32_t n_workers, int32_t n, const sim_desc *descs, uint32_t ring_cap,
             acs_trace_rec *trace_out, double timeout_s, uint64_t *retired_out)
 {
-    return sim_run_groups(W, 1, n_workers, n, descs, nullptr, ring_cap, trace_out, timeout_s, retired_out);
+    return run_sim(W, 1, 0, n_workers, n, descs, nullptr, nullptr, ring_cap, trace_out, timeout_s, retired_out);
+}
+
+// Host-check mode: host_up[i] is descriptor i's upstream list from the
+// caller (bit d: descriptor i - 1 - d), checked against the M before it.
+int sim_run_hostcheck(int32_t W, int32_t M, int32_t n_workers, int32_t n, const sim_desc *descs,
+                      const uint64_t *host_up, uint32_t ring_cap, acs_trace_rec *trace_out, double timeout_s,
+                      uint64_t *retired_out)
+{
+    if (M < 1 || M > 64 || !host_up) return -1;
+    return run_sim(W, 1, M, n_workers, n, descs, nullptr, host_up, ring_cap, trace_out, timeout_s, retired_out);
 }
 
 }  // extern "C"

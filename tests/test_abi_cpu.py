@@ -409,3 +409,13 @@ def test_graph_recording_states():
     assert (s0, s1) == (0, 1)
     assert w.take_ready() == []
     w.destroy()
+
+
+def test_host_check_depth_validation():
+    for kw in ({"host_check_depth": 65}, {"host_check_depth": -1}, {"host_check_depth": 4, "n_groups": 2}):
+        with pytest.raises(acs.AcsError) as e:
+            acs.Window(8, path="device", **kw)
+        assert e.value.code == acs.EINVAL
+    # other paths accept and ignore it
+    with acs.Window(8, path="manual", host_check_depth=4) as w:
+        w.submit(acs.K_NOP, [], [(0, 1)], acs.ArgsNop(0))

@@ -228,3 +228,79 @@ def test_window_groups_through_kernel_source(sim, G, W, workers):
             accs.append(O.tiny_accesses(streams[s], base=(s + 1) << 40)[k])
         code, msg = O.check_trace(accs, W, group_trace(tr, ids, g, Wp), check_times=True, early=True)
         assert code == 0, (g, msg)
+
+
+def host_lists(accs, M):
+    """The host side of host-check mode, from the oracle's conflict test:
+    bit d of entry j set when kernel j - 1 - d (d < M) conflicts with j."""
+    out = np.zeros(len(accs), np.uint64)
+    for j in range(len(accs)):
+        for d in range(min(M, j)):
+            if O.conflict(accs[j - 1 - d], accs[j]):
+                out[j] |= np.uint64(1 << d)
+    return out
+
+
+def _run_hostcheck(sim, W, M, workers, descs, up, n, ring=64):
+    sim.sim_run_hostcheck.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_uint32,
+                                      C.c_void_p, C.c_double, C.POINTER(C.c_uint64)]
+    tr = np.zeros(n, dtype=acs.TRACE_DTYPE)
+    retired = C.c_uint64()
+    rc = sim.sim_run_hostcheck(W, M, workers, n, descs, up.ctypes.data, ring, tr.ctypes.data, 120.0, C.byref(retired))
+    assert rc == 0 and retired.value == n
+    return tr
+
+
+@pytest.mark.timeout(300, method="thread")
+@pytest.mark.parametrize("seed,W,M,workers", [(0, 8, 8, 2), (1, 16, 4, 3), (2, 32, 64, 2), (3, 8, 1, 2),
+                                              (4, 5, 12, 3)])
+def test_host_check_mode_through_kernel_source(sim, seed, W, M, workers):
+    """The host/device split: upstream lists computed on the host over the
+    M previous kernels, filtered and gated in the window wave.  Same bits as
+    in-order execution, and the trace passes the same checker as the device
+    check (the upstream set at each insert is every conflicting kernel in the
+    window, none missed)."""
+    st = inputs.tiny_stream(seed)
+    arena = st.init.copy()
+    descs = _descs(st, arena.ctypes.data)
+    accs = O.tiny_accesses(st, base=arena.ctypes.data)
+    up = host_lists(accs, M)
+    tr = _run_hostcheck(sim, W, M, workers, descs, up, len(st.kernels))
+    assert np.array_equal(arena.view(np.uint32), O.tiny_run(st).view(np.uint32))
+    code, msg = O.check_trace(O.tiny_accesses(st), W, tr, check_times=True, early=True)
+    assert code == 0, msg
+
+
+@pytest.mark.timeout(300, method="thread")
+def test_host_check_gate_holds_back_past_a_long_kernel(sim):
+    """A long kernel writes byte 0, twenty short independent kernels follow,
+    then one reads byte 0.  The host's list (M = 4) cannot see the long
+    kernel from the reader; the gate keeps every kernel more than M younger
+    out of the window until the long one is done, so the reader still waits."""
+    buf = np.zeros(4096, np.uint8)
+    base = buf.ctypes.data
+    specs = [([], [(base, 1)], 3_000_000)] + [([], [(base + 64 * (i + 1), 1)], 0) for i in range(20)] + \
+        [([(base, 1)], [(base + 2048, 1)], 0)]
+    n = len(specs)
+    descs = (SimDesc * n)()
+    accs = []
+    for i, (r, w, spin) in enumerate(specs):
+        d = descs[i]
+        d.kid, d.npieces = acs.K_NOP, 1
+        segs = [(s, s + z) for s, z in r] + [(s, s + z) for s, z in w]
+        d.nseg = len(segs)
+        d.wbits = sum(1 << (len(r) + j) for j in range(len(w)))
+        for j, (s0, e0) in enumerate(segs):
+            d.s[j], d.e[j] = s0, e0
+        a = bytes(acs.ArgsNop(spin))
+        C.memmove(d.args, a, len(a))
+        accs.append(O.make_access(r, w))
+    M = 4
+    up = host_lists(accs, M)
+    assert up[n - 1] == 0                      # the reader's list misses the writer
+    tr = _run_hostcheck(sim, 8, M, 3, descs, up, n)
+    code, msg = O.check_trace(accs, 8, tr, check_times=True, early=True)
+    assert code == 0, msg
+    assert tr["t_start"][n - 1] >= tr["t_end"][0]
+    # kernels M + 1 places after the long one were inserted only once it had left
+    assert np.all(tr["ev_insert"][M + 1:] > tr["ev_retire"][0])
