@@ -29,6 +29,14 @@
  *                     no host round trip per kernel.
  *   ACS_PATH_MANUAL   window only, no GPU: the caller takes ready kernels and
  *                     reports their completion (a stand-in executor for tests).
+ *   ACS_PATH_EVENTS   no window: the multi-stream baseline of Section III-A.
+ *                     Every kernel is launched at submit into one of n_streams
+ *                     streams (that of its newest upstream kernel, else the
+ *                     next in turn); an upstream kernel in another stream
+ *                     becomes a hipStreamWaitEvent on its completion event.
+ *                     Upstream kernels are found with the same range test
+ *                     against the last 64 kernels, and a kernel leaves that
+ *                     list only once its event has fired.  No trace.
  *
  * Conventions.  Functions return ACS_OK (0) or a negative ACS_E* code.  A
  * window is driven by one host thread at a time.  Device buffers named in
@@ -74,7 +82,7 @@ enum {
     ACS_ESTATE = -7      /* call not valid in this state (e.g. configure after submit) */
 };
 
-enum { ACS_PATH_INORDER = 0, ACS_PATH_PLAIN = 1, ACS_PATH_DEVICE = 2, ACS_PATH_MANUAL = 3 };
+enum { ACS_PATH_INORDER = 0, ACS_PATH_PLAIN = 1, ACS_PATH_DEVICE = 2, ACS_PATH_MANUAL = 3, ACS_PATH_EVENTS = 4 };
 
 #define ACS_W_MAX 64       /* one window slot per wavefront lane */
 #define ACS_K_MAX 8        /* read + write segments kept per kernel */
@@ -82,7 +90,7 @@ enum { ACS_PATH_INORDER = 0, ACS_PATH_PLAIN = 1, ACS_PATH_DEVICE = 2, ACS_PATH_M
 
 typedef struct {
     int32_t path;            /* ACS_PATH_* (default ACS_PATH_DEVICE) */
-    int32_t n_streams;       /* plain path: HIP streams in the pool (default 4) */
+    int32_t n_streams;       /* plain and events paths: HIP streams in the pool (default 4) */
     int32_t wg_per_task;     /* workgroups per splittable task body (default 1) */
     int32_t n_workers;       /* device path: worker workgroups (0 = one per compute unit) */
     int32_t queue_depth;     /* input FIFO capacity in kernels (default 4096) */

@@ -69,6 +69,16 @@ int acs_rl_run(acs_window *w, const acs_rl_scene *scene, int32_t steps, double *
 int acs_rl_run_batch(acs_window *w, const acs_rl_scene *scenes, int32_t n_scenes, int32_t n_groups, int32_t steps,
                      double *step_ns, acs_rl_counts *counts);
 
+/* The graph-per-input baseline (a DAG framework used on an input-dependent
+ * graph, Section II-D and Section VI-A): every step's two halves are
+ * recorded, built into a HIP graph with their conflict edges (acs_graph_end),
+ * launched, waited for and destroyed; the plan is read between them.  Runs
+ * on HIP device `device` without a window.  step_ns and counts as for
+ * acs_rl_run; build_ns (if not NULL) receives the total time spent
+ * recording, building and instantiating the graphs. */
+int acs_rl_run_graphs(const acs_rl_scene *scene, int32_t steps, int32_t device, double *step_ns,
+                      acs_rl_counts *counts, double *build_ns);
+
 /* Overhead probe: n no-op kernels, each spinning spin_ns on the device.
  * chain = 0: all independent (distinct one-byte write ranges);
  * chain = 1: each reads and writes the same byte (a serial chain).

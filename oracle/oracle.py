@@ -444,3 +444,90 @@ class DNN:
             if cc in self.y:
                 return self.y[cc]
         return self.inp.x
+
+
+DAG_CONV, DAG_JOIN, DAG_POOL, DAG_FC = range(4)
+
+
+class StaticDAG:
+    """One inference of the randomly wired network, run strictly in program
+    order (the static-network workload of Section VI-C).
+
+    Node i with no predecessor convolves the input; otherwise it first
+    aggregates its predecessors p0, p1, ...: agg = relu(y[p0] (+ y[p1])), then
+    agg = relu(agg + y[pq]) for q >= 2, and convolves agg.  Every convolution
+    is 3x3, stride 1, with bias.  The nodes nobody reads are aggregated the
+    same way into `sink`, followed by an average pool and the head.  Tensors
+    get abstract, disjoint address ranges (tensor index << 40)."""
+
+    def __init__(self, graph, weights, x):
+        self.g, self.wts, self.x = graph, weights, x
+        self.n = len(graph.preds)
+        self.y, self.agg = {}, {}
+        self.sink = self.pool = self.out = None
+
+    # tensor ids: 0 input; node i: 1 + 4i + {0 w, 1 b, 2 agg, 3 y}; then sink, pool, fc_w, fc_b, out
+    def _tid(self, i, part):
+        return 1 + 4 * i + part
+
+    def _tensor_bytes(self, tid):
+        h, c, k = self.g.h, self.g.c, self.g.classes
+        act = 4 * h * h * c
+        if tid == 0:
+            return act
+        if tid < 1 + 4 * self.n:
+            return [4 * 9 * c * c, 4 * c, act, act][(tid - 1) % 4]
+        return [act, 4 * c, 4 * c * k, 4 * k, 4 * k][tid - 1 - 4 * self.n]
+
+    def _chain(self, node, srcs, dst):
+        ks = [(DAG_JOIN, node, srcs[:2], [dst])]
+        for s in srcs[2:]:
+            ks.append((DAG_JOIN, node, [dst, s], [dst]))
+        return ks
+
+    def kernels(self):
+        """Program-order kernel list: (op, node, reads, writes), tensor ids."""
+        ks = []
+        for i, ps in enumerate(self.g.preds):
+            if ps:
+                ks += self._chain(i, [self._tid(p, 3) for p in ps], self._tid(i, 2))
+                src = self._tid(i, 2)
+            else:
+                src = 0
+            ks.append((DAG_CONV, i, [src, self._tid(i, 0), self._tid(i, 1)], [self._tid(i, 3)]))
+        n = self.n
+        sink, pool, fcw, fcb, out = 1 + 4 * n, 2 + 4 * n, 3 + 4 * n, 4 + 4 * n, 5 + 4 * n
+        ks += self._chain(-1, [self._tid(s, 3) for s in self.g.sinks], sink)
+        ks.append((DAG_POOL, -1, [sink], [pool]))
+        ks.append((DAG_FC, -1, [pool, fcw, fcb], [out]))
+        return ks
+
+    def accesses(self):
+        def seg(t):
+            return (t << 40, self._tensor_bytes(t))
+        return [make_access([seg(t) for t in r], [seg(t) for t in w]) for (_, _, r, w) in self.kernels()]
+
+    def run(self, order=None):
+        ks = self.kernels()
+        vals = {0: self.x}
+        for i in (order if order is not None else range(len(ks))):
+            op, node, r, w = ks[i]
+            if op == DAG_CONV:
+                vals[w[0]] = conv_f32(vals[r[0]], self.wts.w[node], self.wts.b[node], 3, 1)
+            elif op == DAG_JOIN:
+                vals[w[0]] = join(vals[r[0]], vals[r[1]] if len(r) > 1 else None)
+            elif op == DAG_POOL:
+                vals[w[0]] = avgpool(vals[r[0]])
+            else:
+                vals[w[0]] = fc(vals[r[0]], self.wts.fc_w, self.wts.fc_b)
+        for i in range(self.n):
+            self.y[i] = vals[self._tid(i, 3)]
+            if self._tid(i, 2) in vals:
+                self.agg[i] = vals[self._tid(i, 2)]
+        n = self.n
+        self.sink, self.pool, self.out = vals[1 + 4 * n], vals[2 + 4 * n], vals[5 + 4 * n]
+        return self.out
+
+    def node_input(self, i):
+        """The activation node i convolves (after run())."""
+        return self.agg[i] if self.g.preds[i] else self.x

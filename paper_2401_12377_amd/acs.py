@@ -22,8 +22,9 @@ LIB_PATH = os.path.join(PKG, "libacs.so")
 # ---------------------------------------------------------------------------
 OK, EINVAL, ENOMEM, EAGAIN, EDEVICE, ETIMEDOUT, EKERNEL, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
 PENDING, READY, EXECUTING = 0, 1, 2
-PATH_INORDER, PATH_PLAIN, PATH_DEVICE, PATH_MANUAL = 0, 1, 2, 3
-PATHS = {"inorder": PATH_INORDER, "plain": PATH_PLAIN, "device": PATH_DEVICE, "manual": PATH_MANUAL}
+PATH_INORDER, PATH_PLAIN, PATH_DEVICE, PATH_MANUAL, PATH_EVENTS = 0, 1, 2, 3, 4
+PATHS = {"inorder": PATH_INORDER, "plain": PATH_PLAIN, "device": PATH_DEVICE, "manual": PATH_MANUAL,
+         "events": PATH_EVENTS}
 W_MAX, K_MAX, ARGS_MAX = 64, 8, 64
 SEG_ALL = (0, (1 << 64) - 1)
 

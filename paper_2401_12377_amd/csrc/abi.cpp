@@ -338,6 +338,7 @@ int ensure_started(acs_window *w)
     case ACS_PATH_PLAIN: w->path = make_plain_path(std::min(ACS_W_MAX, w->W * w->cfg.n_groups), w->cfg); break;
     case ACS_PATH_DEVICE: w->path = make_device_path(w->W, w->cfg); break;
     case ACS_PATH_MANUAL: w->path = make_manual_path(std::min(ACS_W_MAX, w->W * w->cfg.n_groups), w->cfg); break;
+    case ACS_PATH_EVENTS: w->path = make_events_path(w->cfg); break;
     default: return fail(ACS_EINVAL, "unknown path");
     }
     const int rc = w->path->start();
@@ -388,7 +389,7 @@ int acs_window_configure(acs_window *w, const acs_config *cfg)
 {
     if (!w || !cfg) return fail(ACS_EINVAL, "null argument");
     if (w->started) return fail(ACS_ESTATE, "configure must come before the first submit");
-    if (cfg->path < ACS_PATH_INORDER || cfg->path > ACS_PATH_MANUAL) return fail(ACS_EINVAL, "unknown path");
+    if (cfg->path < ACS_PATH_INORDER || cfg->path > ACS_PATH_EVENTS) return fail(ACS_EINVAL, "unknown path");
     if (cfg->n_streams < 1 || cfg->n_streams > 64) return fail(ACS_EINVAL, "n_streams must be in [1, 64]");
     if (cfg->wg_per_task < 1 || cfg->wg_per_task > 256) return fail(ACS_EINVAL, "wg_per_task must be in [1, 256]");
     if (cfg->n_workers < 0 || cfg->n_workers > 8192) return fail(ACS_EINVAL, "n_workers must be in [0, 8192]");

@@ -3,6 +3,8 @@
 // conflicts among them, replayed without a window.
 #include <hip/hip_runtime_api.h>
 
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -13,6 +15,7 @@ struct acs_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t stream = nullptr;
+    int32_t device = 0;
     int64_t n_kernels = 0, n_edges = 0;
 };
 
@@ -24,11 +27,36 @@ int graph_fail(hipError_t e, const char *what)
     return ACS_EDEVICE;
 }
 
+// Launch streams are kept for reuse once their graph is destroyed: a graph
+// rebuilt for every input then costs its construction, not a stream.
+std::mutex g_pool_mu;
+std::map<int32_t, std::vector<hipStream_t>> g_stream_pool;
+
+hipError_t take_stream(int32_t device, hipStream_t *out)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        auto &v = g_stream_pool[device];
+        if (!v.empty()) {
+            *out = v.back();
+            v.pop_back();
+            return hipSuccess;
+        }
+    }
+    return hipStreamCreateWithFlags(out, hipStreamNonBlocking);
+}
+
+void give_stream(int32_t device, hipStream_t s)
+{
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    g_stream_pool[device].push_back(s);
+}
+
 void destroy_parts(acs_graph *g)
 {
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
-    if (g->stream) (void)hipStreamDestroy(g->stream);
+    if (g->stream) give_stream(g->device, g->stream);
     g->exec = nullptr;
     g->graph = nullptr;
     g->stream = nullptr;
@@ -128,8 +156,9 @@ int acs_graph_end(acs_window *w, acs_graph **out)
             return graph_fail(e, "hipGraphAddKernelNode");
         }
     }
+    g->device = w->cfg.device;
     if ((e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)) != hipSuccess ||
-        (e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking)) != hipSuccess) {
+        (e = take_stream(g->device, &g->stream)) != hipSuccess) {
         destroy_parts(g);
         delete g;
         return graph_fail(e, "hipGraphInstantiate");

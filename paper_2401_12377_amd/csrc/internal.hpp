@@ -82,6 +82,7 @@ std::unique_ptr<Path> make_inorder_path(const acs_config &cfg);
 std::unique_ptr<Path> make_plain_path(int32_t W, const acs_config &cfg);
 std::unique_ptr<Path> make_manual_path(int32_t W, const acs_config &cfg);
 std::unique_ptr<Path> make_device_path(int32_t W, const acs_config &cfg);
+std::unique_ptr<Path> make_events_path(const acs_config &cfg);
 
 uint64_t now_ns();
 

@@ -456,8 +456,163 @@ private:
     bool started_ = false;
 };
 
+// ---------------------------------------------------------------------------
+// events path: the multi-stream baseline.  Every kernel is launched when it
+// is submitted, into one of S streams; a dependency on a kernel of another
+// stream becomes a wait on that kernel's completion event.  Dependencies
+// come from the same range test, against every kernel that may still be
+// running: the last kHist kernels, where a kernel leaves that history only
+// after its event has fired (the host waits for it if need be).
+// ---------------------------------------------------------------------------
+class EventsPath : public Path {
+public:
+    explicit EventsPath(const acs_config &cfg) : cfg_(cfg) {}
+    ~EventsPath() override { shutdown(); }
+    int start() override
+    {
+        hipError_t e = hipSetDevice(cfg_.device);
+        if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+        streams_.assign((size_t)cfg_.n_streams, nullptr);
+        for (auto &st : streams_)
+            if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "hipStreamCreate");
+        for (int32_t i = 0; i < kHist + 1; i++) {
+            hipEvent_t ev;
+            if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+            free_events_.push_back(ev);
+        }
+        started_ = true;
+        return ACS_OK;
+    }
+    int submit(const Desc &d) override
+    {
+        if (err_) return err_;
+        if ((int32_t)hist_.size() == kHist)
+            if (int rc = retire_oldest()) return rc;
+        // newest conflicting kernel per stream: stream order covers the older ones
+        int32_t dep_on[ACS_W_MAX];
+        int64_t newest = -1;
+        int32_t pick = -1;
+        for (int32_t s = 0; s < (int32_t)streams_.size(); s++) dep_on[s] = -1;
+        for (int32_t k = (int32_t)hist_.size() - 1; k >= 0; k--) {
+            const Rec &o = hist_[(size_t)k];
+            if (dep_on[o.stream] >= 0) continue;
+            if (descs_conflict(o.d, d, &tests_)) {
+                dep_on[o.stream] = k;
+                if ((int64_t)o.d.seq > newest) {
+                    newest = (int64_t)o.d.seq;
+                    pick = o.stream;
+                }
+            }
+        }
+        // the stream of the newest upstream kernel, else the next stream in turn
+        if (pick < 0) {
+            pick = rr_;
+            rr_ = (rr_ + 1) % (int32_t)streams_.size();
+        }
+        hipStream_t st = streams_[(size_t)pick];
+        hipError_t e;
+        for (int32_t s = 0; s < (int32_t)streams_.size(); s++) {
+            if (s == pick || dep_on[s] < 0) continue;
+            if ((e = hipStreamWaitEvent(st, hist_[(size_t)dep_on[s]].ev, 0)) != hipSuccess) return fail_dev(e, "hipStreamWaitEvent");
+        }
+        if ((e = launch_task(d.kid, d.args, d.npieces, st)) != hipSuccess) return fail_dev(e, "kernel launch");
+        Rec r;
+        r.d = d;
+        r.stream = pick;
+        r.ev = free_events_.back();
+        free_events_.pop_back();
+        if ((e = hipEventRecord(r.ev, st)) != hipSuccess) return fail_dev(e, "hipEventRecord");
+        hist_.push_back(r);
+        submitted_++;
+        return ACS_OK;
+    }
+    int sync(uint64_t timeout_ns) override
+    {
+        const uint64_t t0 = now_ns();
+        for (auto st : streams_) {
+            for (;;) {
+                const hipError_t q = hipStreamQuery(st);
+                if (q == hipSuccess) break;
+                if (q != hipErrorNotReady) return fail_dev(q, "stream");
+                if (timeout_ns && now_ns() - t0 > timeout_ns) {
+                    set_error(ACS_ETIMEDOUT, "sync timed out");
+                    return ACS_ETIMEDOUT;
+                }
+                _mm_pause();
+            }
+        }
+        while (!hist_.empty()) {
+            free_events_.push_back(hist_.front().ev);
+            hist_.erase(hist_.begin());
+        }
+        retired_ = submitted_;
+        return err_;
+    }
+    int poll() override { return err_; }
+    int scheduled_list(acs_entry *, int32_t, int32_t *n) override
+    {
+        if (n) *n = 0;
+        return ACS_OK;
+    }
+    int trace_read(acs_trace_rec *, int64_t, int64_t *n) override
+    {
+        if (n) *n = 0;
+        return ACS_OK;
+    }
+    int shutdown() override
+    {
+        if (!started_) return ACS_OK;
+        (void)sync(0);
+        for (auto st : streams_)
+            if (st) (void)hipStreamDestroy(st);
+        for (auto ev : free_events_) (void)hipEventDestroy(ev);
+        streams_.clear();
+        free_events_.clear();
+        started_ = false;
+        return ACS_OK;
+    }
+    void stats(acs_stats &s) override
+    {
+        s.retired = retired_;
+        s.dispatched = submitted_;
+        s.overlap_tests = tests_;
+        s.n_streams = (int32_t)streams_.size();
+    }
+
+private:
+    static constexpr int32_t kHist = 64;
+    struct Rec {
+        Desc d;
+        int32_t stream = 0;
+        hipEvent_t ev = nullptr;
+    };
+    int retire_oldest()
+    {
+        const hipError_t e = hipEventSynchronize(hist_.front().ev);
+        if (e != hipSuccess) return fail_dev(e, "hipEventSynchronize");
+        free_events_.push_back(hist_.front().ev);
+        hist_.erase(hist_.begin());
+        retired_++;
+        return ACS_OK;
+    }
+    int fail_dev(hipError_t e, const char *what)
+    {
+        if (!err_) err_ = ACS_EDEVICE;
+        return hip_fail(e, what);
+    }
+    acs_config cfg_;
+    std::vector<hipStream_t> streams_;
+    std::vector<hipEvent_t> free_events_;
+    std::vector<Rec> hist_;
+    int32_t rr_ = 0;
+    uint64_t submitted_ = 0, retired_ = 0, tests_ = 0;
+    int err_ = ACS_OK;
+    bool started_ = false;
+};
+
 }  // namespace
 
+std::unique_ptr<Path> make_events_path(const acs_config &cfg) { return std::make_unique<EventsPath>(cfg); }
 std::unique_ptr<Path> make_manual_path(int32_t W, const acs_config &cfg) { return std::make_unique<ManualPath>(W, cfg); }
 std::unique_ptr<Path> make_inorder_path(const acs_config &cfg) { return std::make_unique<InorderPath>(cfg); }
 std::unique_ptr<Path> make_plain_path(int32_t W, const acs_config &cfg) { return std::make_unique<PlainPath>(W, cfg); }

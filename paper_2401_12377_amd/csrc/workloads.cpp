@@ -105,6 +105,51 @@ int acs_rl_run_batch(acs_window *w, const acs_rl_scene *scenes, int32_t n_scenes
     return ACS_OK;
 }
 
+int acs_rl_run_graphs(const acs_rl_scene *sc, int32_t steps, int32_t device, double *step_ns, acs_rl_counts *counts,
+                      double *build_ns)
+{
+    if (!scene_ok(sc) || steps < 0) return ACS_EINVAL;
+    // a window that only records: its own stream never runs anything
+    acs_window *w = acs_window_create(ACS_W_MAX);
+    if (!w) return acs_last_error();
+    acs_config cfg;
+    acs_config_default(&cfg);
+    cfg.path = ACS_PATH_INORDER;
+    cfg.device = device;
+    int rc = acs_window_configure(w, &cfg);
+    acs::RLStep s(w, 0, sc);
+    acs_rl_counts cnt = {};
+    double built = 0;
+    // one half of a step: record, build, run, wait, destroy
+    auto half = [&](bool tail) -> int {
+        const double t0 = wall_ns();
+        if (int r = acs_graph_begin(w)) return r;
+        int r = tail ? s.submit_tail(cnt) : s.submit_prefix(cnt);
+        acs_graph *g = nullptr;
+        const int re = acs_graph_end(w, &g);
+        if (r == ACS_OK) r = re;
+        built += wall_ns() - t0;
+        if (r != ACS_OK) {
+            acs_graph_destroy(g);
+            return r;
+        }
+        r = acs_graph_launch(g);
+        if (r == ACS_OK) r = acs_graph_sync(g);
+        acs_graph_destroy(g);
+        return r;
+    };
+    for (int32_t step = 0; rc == ACS_OK && step < steps; step++) {
+        const double t0 = wall_ns();
+        rc = half(false);
+        if (rc == ACS_OK) rc = half(true);
+        if (step_ns) step_ns[step] = wall_ns() - t0;
+    }
+    acs_window_destroy(w);
+    if (counts) *counts = cnt;
+    if (build_ns) *build_ns = built;
+    return rc;
+}
+
 int acs_nop_run(acs_window *w, int32_t n, int32_t chain, uint64_t spin_ns, double *out_ns)
 {
     if (!w || n < 0) return ACS_EINVAL;

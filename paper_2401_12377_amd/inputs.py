@@ -305,3 +305,81 @@ def serve_requests(seed: int = 4, rate_per_s: float = 5000.0, n_requests: int = 
             out.append(ServeSpec(SERVE_DNN, float(t[i]), req_seed))
     return out
 
+
+
+# ---------------------------------------------------------------------------
+# Static irregular DAG network (randomly wired, batch 1)
+# ---------------------------------------------------------------------------
+
+DAG_MAX_IN = 8
+DAG_H, DAG_C = 32, 32      # every node's activation is DAG_H x DAG_H x DAG_C (NHWC)
+
+
+@dataclass
+class DAGGraph:
+    preds: list            # per node: sorted earlier nodes it reads (empty: reads the input)
+    h: int
+    c: int
+    classes: int
+
+    @property
+    def sinks(self):
+        used = {p for ps in self.preds for p in ps}
+        return [i for i in range(len(self.preds)) if i not in used]
+
+
+def dag_graph(seed: int = 5, nodes: int = 32, k: int = 4, p: float = 0.75) -> DAGGraph:
+    """A randomly wired network in the style of the randomly wired NAS
+    networks: a Watts-Strogatz small-world graph (ring lattice where each
+    node links to its k / 2 next neighbours, each link rewired with
+    probability p to a uniformly drawn node that is neither itself nor
+    already linked), made acyclic by directing every link from the lower to
+    the higher node index.  At most DAG_MAX_IN inputs per node (the lowest
+    indices are kept)."""
+    rng = SplitMix64((0xDA6 << 40) ^ seed)
+    adj = [set() for _ in range(nodes)]
+    for i in range(nodes):
+        for j in range(1, k // 2 + 1):
+            adj[i].add((i + j) % nodes)
+            adj[(i + j) % nodes].add(i)
+    for j in range(1, k // 2 + 1):
+        for i in range(nodes):
+            t = (i + j) % nodes
+            u = rng.next() >> 11
+            if u * 2.0 ** -53 < p and t in adj[i]:
+                cands = [v for v in range(nodes) if v != i and v not in adj[i]]
+                if cands:
+                    v = cands[rng.below(len(cands))]
+                    adj[i].discard(t)
+                    adj[t].discard(i)
+                    adj[i].add(v)
+                    adj[v].add(i)
+    preds = [sorted(v for v in adj[i] if v < i)[:DAG_MAX_IN] for i in range(nodes)]
+    return DAGGraph(preds=preds, h=DAG_H, c=DAG_C, classes=DNN_CLASSES)
+
+
+@dataclass
+class DAGWeights:
+    w: list                # per node float32[3, 3, c, c]
+    b: list                # per node float32[c]
+    fc_w: np.ndarray       # float32[c, classes]
+    fc_b: np.ndarray
+
+
+def dag_weights(graph: DAGGraph, seed: int = 6) -> DAGWeights:
+    c = graph.c
+    w, b = [], []
+    for i in range(len(graph.preds)):
+        base = (seed * 1_000_003 + 131 * i) & MASK64
+        w.append(_uniform_sym(base + 1, 9 * c * c, math.sqrt(6.0 / (9 * c))).reshape(3, 3, c, c))
+        b.append(_uniform_sym(base + 2, c, 1.0 / math.sqrt(9 * c)))
+    base = (seed * 1_000_003 + 131 * len(graph.preds)) & MASK64
+    fc_w = _uniform_sym(base + 1, c * graph.classes, math.sqrt(6.0 / c)).reshape(c, graph.classes)
+    fc_b = _uniform_sym(base + 2, graph.classes, 1.0 / math.sqrt(c))
+    return DAGWeights(w, b, fc_w, fc_b)
+
+
+def dag_input(graph: DAGGraph, seed: int = 0) -> np.ndarray:
+    """Input image U[-1, 1), h x h x c."""
+    n = graph.h * graph.h * graph.c
+    return uniform_pm1(splitmix64_array((0xDA7 << 32) ^ seed, n)).reshape(graph.h, graph.h, graph.c)
