@@ -116,6 +116,39 @@ typedef struct {
  * number of kernels submitted.  Returns 0 or the first error. */
 int acs_dnn_submit(acs_window *w, const acs_dnn_graph *g, const float *logits, uint64_t *n_kernels);
 
+/* Static irregular network, batch 1 (the static-network workload of Section
+ * VI-C; randomly wired): nodes in topological order, all activations
+ * h x h x c FP32 NHWC.  A node with no predecessor convolves the input x; a
+ * node with predecessors p0, p1, ... first aggregates them into its agg
+ * buffer, agg = relu(y[p0] (+ y[p1])), then agg = relu(agg + y[pq]) for
+ * q >= 2 (one join kernel each), and convolves agg.  Every convolution is
+ * 3x3, stride 1, pad 1, with bias, c -> c.  The nodes no other node reads are
+ * aggregated the same way into sink, followed by an average pool and the
+ * fully connected head. */
+#define ACS_DAG_MAX_NODES 64
+#define ACS_DAG_MAX_IN 8
+typedef struct {
+    int32_t n_in;                     /* 0..ACS_DAG_MAX_IN */
+    int32_t in[ACS_DAG_MAX_IN];       /* earlier node indices */
+    const float *w, *b;               /* w[3][3][c][c], b[c] */
+    float *agg, *y;                   /* [h][h][c] each (agg unused when n_in == 0) */
+} acs_dag_node;
+typedef struct {
+    int32_t n_nodes;                  /* 1..ACS_DAG_MAX_NODES */
+    int32_t h, c, classes;
+    const float *x;                   /* [h][h][c] */
+    acs_dag_node node[ACS_DAG_MAX_NODES];
+    float *sink, *pool;               /* [h][h][c], [c] */
+    const float *fc_w, *fc_b;         /* [c][classes], [classes] */
+    float *out;                       /* [classes] */
+} acs_dag_graph;
+
+/* Submits one inference in program order (no drain); *n_kernels (if not
+ * NULL) receives the number of kernels.  ACS_EINVAL for a malformed graph
+ * (a predecessor that is not an earlier node, shapes the convolution does
+ * not take). */
+int acs_dag_submit(acs_window *w, const acs_dag_graph *g, uint64_t *n_kernels);
+
 /* Working-memory pool: a host-side allocator over a caller-owned device
  * range [base, base + bytes) (the serving loop's admission budget).  Blocks
  * are 256-byte aligned and sized; best fit, freed blocks merge with free

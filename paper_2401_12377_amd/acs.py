@@ -159,6 +159,20 @@ class ServeStatsC(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+DAG_MAX_NODES, DAG_MAX_IN = 64, 8
+
+
+class DAGNodeC(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("inp", C.c_int32 * DAG_MAX_IN), ("w", C.c_uint64), ("b", C.c_uint64),
+                ("agg", C.c_uint64), ("y", C.c_uint64)]
+
+
+class DAGGraphC(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("h", C.c_int32), ("c", C.c_int32), ("classes", C.c_int32),
+                ("x", C.c_uint64), ("node", DAGNodeC * DAG_MAX_NODES), ("sink", C.c_uint64), ("pool", C.c_uint64),
+                ("fc_w", C.c_uint64), ("fc_b", C.c_uint64), ("out", C.c_uint64)]
+
+
 class ArgsRL(C.Structure):
     _fields_ = [("base", C.c_uint64), ("plan", C.c_uint64), ("n", C.c_int32), ("r", C.c_float), ("dt", C.c_float),
                 ("iter", C.c_int32), ("b0", C.c_int32), ("b1", C.c_int32)]
@@ -233,6 +247,9 @@ def lib():
         L.acs_rl_run_batch.argtypes = [C.c_void_p, P(RLSceneC), C.c_int32, C.c_int32, C.c_int32, P(C.c_double),
                                        P(RLCounts)]
         L.acs_poll.argtypes = [C.c_void_p]
+        L.acs_dag_submit.argtypes = [C.c_void_p, P(DAGGraphC), P(C.c_uint64)]
+        L.acs_rl_run_graphs.argtypes = [P(RLSceneC), C.c_int32, C.c_int32, P(C.c_double), P(RLCounts),
+                                        P(C.c_double)]
         L.acs_pool_create.argtypes = [C.c_uint64, C.c_uint64]
         L.acs_pool_create.restype = C.c_void_p
         L.acs_pool_alloc.argtypes = [C.c_void_p, C.c_uint64, P(C.c_uint64)]
@@ -244,7 +261,7 @@ def lib():
         L.acs_serve_host_bytes.restype = C.c_uint64
         L.acs_serve_run.argtypes = [C.c_void_p, P(ServeConfigC), P(ServeRequestC), C.c_int32, P(ServeResultC),
                                     P(ServeStatsC)]
-        for f in ("acs_poll", "acs_pool_alloc", "acs_pool_free", "acs_pool_info", "acs_serve_run",
+        for f in ("acs_dag_submit", "acs_rl_run_graphs", "acs_poll", "acs_pool_alloc", "acs_pool_free", "acs_pool_info", "acs_serve_run",
                   "acs_window_configure", "acs_submit", "acs_sync", "acs_sync_timeout", "acs_scheduled_list",
                   "acs_trace_read", "acs_stats_get", "acs_window_destroy", "acs_window_stop", "acs_manual_take_ready",
                   "acs_manual_complete", "acs_last_error", "acs_rl_layout", "acs_host_free", "acs_rl_run",
@@ -639,6 +656,17 @@ def rl_run_batch(win: Window, scenes_gpu, steps: int, n_groups: int = 1):
     return k.as_dict(), np.array(step_ns[:steps])
 
 
+def rl_run_graphs(scene_gpu: RLSceneGPU, steps: int, device: int = 0):
+    """The graph-per-input baseline: each step's halves recorded, built into a
+    HIP graph, run and destroyed; returns (counts, per-step ns, build ns)."""
+    sc = scene_gpu.c_struct()
+    step_ns = (C.c_double * max(1, steps))()
+    k = RLCounts()
+    b = C.c_double()
+    _check(lib().acs_rl_run_graphs(C.byref(sc), steps, device, step_ns, C.byref(k), C.byref(b)))
+    return k.as_dict(), np.array(step_ns[:steps]), b.value
+
+
 def nop_run(win: Window, n: int, chain: bool, spin_ns: int = 0) -> float:
     t = C.c_double()
     _check(lib().acs_nop_run(win.handle, n, int(chain), spin_ns, C.byref(t)))
@@ -868,4 +896,59 @@ def serve_run(win: Window, sset: ServeSet, pool, host: HostBuffer, pool_bytes: i
     _check(lib().acs_serve_run(win.handle, C.byref(cfg), sset.req, n, res, C.byref(st)))
     out = [{f: getattr(res[i], f) for f, _ in ServeResultC._fields_} for i in range(n)]
     return out, st.as_dict()
+
+
+# ---------------------------------------------------------------------------
+# static irregular network (randomly wired, batch 1)
+# ---------------------------------------------------------------------------
+class DAGGPU:
+    """Device weights and activation buffers of the randomly wired network
+    (torch tensors for memory; every kernel runs in libacs)."""
+
+    def __init__(self, graph, weights, device="cuda"):
+        import torch
+        self.graph = graph
+        dev = torch.device(device)
+
+        def t(a):
+            return torch.as_tensor(np.ascontiguousarray(a, np.float32)).to(dev)
+        h, c = graph.h, graph.c
+        self.w = [t(a) for a in weights.w]
+        self.b = [t(a) for a in weights.b]
+        self.fc_w, self.fc_b = t(weights.fc_w), t(weights.fc_b)
+        self.x = torch.zeros((h, h, c), dtype=torch.float32, device=dev)
+        self.agg = [torch.full((h, h, c), float("nan"), dtype=torch.float32, device=dev) for _ in graph.preds]
+        self.y = [torch.full((h, h, c), float("nan"), dtype=torch.float32, device=dev) for _ in graph.preds]
+        self.sink = torch.zeros((h, h, c), dtype=torch.float32, device=dev)
+        self.pool = torch.zeros(c, dtype=torch.float32, device=dev)
+        self.out = torch.zeros(graph.classes, dtype=torch.float32, device=dev)
+        torch.cuda.current_stream().synchronize()
+
+    def set_input(self, x):
+        import torch
+        self.x.copy_(torch.as_tensor(np.ascontiguousarray(x, np.float32)))
+        torch.cuda.current_stream().synchronize()
+
+    def c_struct(self) -> DAGGraphC:
+        g = DAGGraphC()
+        g.n_nodes, g.h, g.c, g.classes = len(self.graph.preds), self.graph.h, self.graph.c, self.graph.classes
+        g.x = self.x.data_ptr()
+        for i, ps in enumerate(self.graph.preds):
+            nd = g.node[i]
+            nd.n_in = len(ps)
+            for q, p in enumerate(ps):
+                nd.inp[q] = p
+            nd.w, nd.b = self.w[i].data_ptr(), self.b[i].data_ptr()
+            nd.agg, nd.y = self.agg[i].data_ptr(), self.y[i].data_ptr()
+        g.sink, g.pool = self.sink.data_ptr(), self.pool.data_ptr()
+        g.fc_w, g.fc_b, g.out = self.fc_w.data_ptr(), self.fc_b.data_ptr(), self.out.data_ptr()
+        return g
+
+
+def dag_submit(win: Window, net: DAGGPU) -> int:
+    """Submits one inference of the randomly wired network (no drain); returns the kernel count."""
+    g = net.c_struct()
+    n = C.c_uint64()
+    _check(lib().acs_dag_submit(win.handle, C.byref(g), C.byref(n)))
+    return n.value
 

@@ -172,6 +172,84 @@ int acs_dnn_submit(acs_window *w, const acs_dnn_graph *g, const float *logits, u
     return acs::dnn_submit_group(w, 0, g, logits, n_kernels);
 }
 
+int acs_dag_submit(acs_window *w, const acs_dag_graph *g, uint64_t *n_kernels)
+{
+    if (!w || !g || g->n_nodes < 1 || g->n_nodes > ACS_DAG_MAX_NODES || g->h < 1 || g->c < 1 || g->classes < 1 || !g->x ||
+        !g->sink || !g->pool || !g->fc_w || !g->fc_b || !g->out)
+        return ACS_EINVAL;
+    const uint64_t act = 4ull * (uint64_t)g->h * (uint64_t)g->h * (uint64_t)g->c;
+    const uint32_t n_act = (uint32_t)(act / 4);
+    auto seg = [](const void *p, uint64_t bytes) { return acs_seg{(uint64_t)(uintptr_t)p, bytes}; };
+    uint64_t kernels = 0;
+    // dst = relu(srcs[0] (+ srcs[1])), then dst = relu(dst + srcs[q])
+    auto chain = [&](const float *const *srcs, int32_t n, float *dst) -> int {
+        {
+            acs_args_join a = {dst, srcs[0], n > 1 ? srcs[1] : nullptr, n_act};
+            const acs_seg r[2] = {seg(srcs[0], act), seg(n > 1 ? srcs[1] : nullptr, n > 1 ? act : 0)};
+            const acs_seg wr[1] = {seg(dst, act)};
+            if (int rc = acs_submit(w, ACS_K_JOIN, r, n > 1 ? 2 : 1, wr, 1, &a, sizeof(a), nullptr)) return rc;
+            kernels++;
+        }
+        for (int32_t q = 2; q < n; q++) {
+            acs_args_join a = {dst, dst, srcs[q], n_act};
+            const acs_seg r[2] = {seg(dst, act), seg(srcs[q], act)};
+            const acs_seg wr[1] = {seg(dst, act)};
+            if (int rc = acs_submit(w, ACS_K_JOIN, r, 2, wr, 1, &a, sizeof(a), nullptr)) return rc;
+            kernels++;
+        }
+        return ACS_OK;
+    };
+    // the whole graph is checked before anything is submitted
+    if (g->c % 32 != 0 || (g->h * g->h) % 64 != 0) return ACS_EINVAL;
+    bool read_by_later[ACS_DAG_MAX_NODES] = {};
+    for (int32_t i = 0; i < g->n_nodes; i++) {
+        const acs_dag_node &nd = g->node[i];
+        if (nd.n_in < 0 || nd.n_in > ACS_DAG_MAX_IN || !nd.w || !nd.b || !nd.y || (nd.n_in > 0 && !nd.agg))
+            return ACS_EINVAL;
+        for (int32_t q = 0; q < nd.n_in; q++) {
+            if (nd.in[q] < 0 || nd.in[q] >= i) return ACS_EINVAL;
+            read_by_later[nd.in[q]] = true;
+        }
+    }
+    for (int32_t i = 0; i < g->n_nodes; i++) {
+        const acs_dag_node &nd = g->node[i];
+        const float *srcs[ACS_DAG_MAX_IN];
+        for (int32_t q = 0; q < nd.n_in; q++) srcs[q] = g->node[nd.in[q]].y;
+        const float *src = g->x;
+        if (nd.n_in > 0) {
+            if (int rc = chain(srcs, nd.n_in, nd.agg)) return rc;
+            src = nd.agg;
+        }
+        acs_args_conv a = {src, nd.w, nd.b, nd.y, g->h, g->c, g->c, 3, 1};
+        const acs_seg r[3] = {seg(src, act), seg(nd.w, 36ull * g->c * g->c), seg(nd.b, 4ull * g->c)};
+        const acs_seg wr[1] = {seg(nd.y, act)};
+        if (int rc = acs_submit(w, ACS_K_CONV, r, 3, wr, 1, &a, sizeof(a), nullptr)) return rc;
+        kernels++;
+    }
+    const float *sinks[ACS_DAG_MAX_NODES];
+    int32_t ns = 0;
+    for (int32_t i = 0; i < g->n_nodes; i++)
+        if (!read_by_later[i]) sinks[ns++] = g->node[i].y;
+    if (int rc = chain(sinks, ns, g->sink)) return rc;
+    {
+        acs_args_avgpool a = {g->pool, g->sink, g->h * g->h, g->c};
+        const acs_seg r[1] = {seg(g->sink, act)};
+        const acs_seg wr[1] = {seg(g->pool, 4ull * g->c)};
+        if (int rc = acs_submit(w, ACS_K_AVGPOOL, r, 1, wr, 1, &a, sizeof(a), nullptr)) return rc;
+        kernels++;
+    }
+    {
+        acs_args_fc a = {g->out, g->pool, g->fc_w, g->fc_b, g->c, g->classes};
+        const acs_seg r[3] = {seg(g->pool, 4ull * g->c), seg(g->fc_w, 4ull * g->c * g->classes),
+                              seg(g->fc_b, 4ull * g->classes)};
+        const acs_seg wr[1] = {seg(g->out, 4ull * g->classes)};
+        if (int rc = acs_submit(w, ACS_K_FC, r, 3, wr, 1, &a, sizeof(a), nullptr)) return rc;
+        kernels++;
+    }
+    if (n_kernels) *n_kernels = kernels;
+    return ACS_OK;
+}
+
 }  // extern "C"
 
 namespace acs {

@@ -419,3 +419,72 @@ def test_host_check_depth_validation():
     # other paths accept and ignore it
     with acs.Window(8, path="manual", host_check_depth=4) as w:
         w.submit(acs.K_NOP, [], [(0, 1)], acs.ArgsNop(0))
+
+
+def fake_dag_graph(graph):
+    nxt = [1 << 40]
+
+    def alloc(nbytes):
+        p = nxt[0]
+        nxt[0] += (nbytes + 4095) // 4096 * 4096 + 4096
+        return p
+    h, c, k = graph.h, graph.c, graph.classes
+    g = acs.DAGGraphC()
+    g.n_nodes, g.h, g.c, g.classes = len(graph.preds), h, c, k
+    g.x = alloc(4 * h * h * c)
+    for i, ps in enumerate(graph.preds):
+        nd = g.node[i]
+        nd.n_in = len(ps)
+        for q, p in enumerate(ps):
+            nd.inp[q] = p
+        nd.w, nd.b, nd.agg, nd.y = alloc(36 * c * c), alloc(4 * c), alloc(4 * h * h * c), alloc(4 * h * h * c)
+    g.sink, g.pool = alloc(4 * h * h * c), alloc(4 * c)
+    g.fc_w, g.fc_b, g.out = alloc(4 * c * k), alloc(4 * k), alloc(4 * k)
+    return g
+
+
+@pytest.mark.parametrize("seed", [5, 7])
+def test_dag_driver_dependencies_match_oracle_dataflow(seed):
+    graph = inputs.dag_graph(seed=seed)
+    net = O.StaticDAG(graph, None, None)
+    adj = O.dag(net.accesses())
+    n = len(net.kernels())
+    W = 16
+    w = manual(W, trace=True, queue_depth=4096)
+    cnt = acs.C.c_uint64()
+    assert acs.lib().acs_dag_submit(w.handle, acs.C.byref(fake_dag_graph(graph)), acs.C.byref(cnt)) == 0
+    assert cnt.value == n
+    rng = np.random.default_rng(seed)
+    window, running, done, nxt = [], set(), set(), 0
+    while len(done) < n:
+        while nxt < n and len(window) < W:
+            window.append(nxt)
+            nxt += 1
+        got = sorted(w.take_ready())
+        assert got == reference_ready(adj, window, running)
+        running |= set(got)
+        j = sorted(running)[int(rng.integers(len(running)))]
+        w.complete(j)
+        running.discard(j)
+        window.remove(j)
+        done.add(j)
+    assert w.sync() == 0
+    code, msg = O.check_trace(net.accesses(), W, w.trace())
+    w.destroy()
+    assert code == 0, msg
+
+
+def test_dag_driver_rejects_malformed_graphs():
+    graph = inputs.dag_graph(nodes=8)
+    for mutate in ("forward_edge", "too_many_inputs", "bad_shape"):
+        g = fake_dag_graph(graph)
+        if mutate == "forward_edge":
+            g.node[3].n_in, g.node[3].inp[0] = 1, 5
+        elif mutate == "too_many_inputs":
+            g.node[3].n_in = 9
+        else:
+            g.c = 48
+        w = manual(16)
+        assert acs.lib().acs_dag_submit(w.handle, acs.C.byref(g), None) == acs.EINVAL, mutate
+        assert w.stats()["submitted"] == 0, mutate           # nothing went in before the check
+        w.destroy()

@@ -1,0 +1,159 @@
+"""GPU parity for the comparison baselines and the static irregular network.
+
+* events path (multi-stream launch with event waits, Section III-A): the
+  same bits as the oracle on the tiny stream and the RL step, and as the
+  in-order path on the dynamic network;
+* graph per input (Section II-D, VI-A): each RL step recorded, built, run
+  and destroyed gives the oracle's bits;
+* randomly wired static network (Section VI-C): every path gives the
+  in-order bits, the window schedules pass the oracle's trace checker with
+  the oracle's own dataflow ranges, the logits agree with the oracle's FP32
+  network, and a captured graph replays to the same bits.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2401_12377_amd import acs, inputs
+
+pytestmark = pytest.mark.gpu
+
+SYNC_NS = 30 * 10 ** 9
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    acs.lib()
+    return t
+
+
+def bits(a):
+    return np.ascontiguousarray(a).view(np.uint32)
+
+
+@pytest.mark.parametrize("streams", [1, 4, 8])
+def test_events_tiny_stream(torch, streams):
+    for seed in range(4):
+        say(f"events tiny seed={seed} streams={streams}")
+        st = inputs.tiny_stream(seed + 50)
+        arena = torch.from_numpy(st.init.copy()).cuda()
+        torch.cuda.current_stream().synchronize()
+        with acs.Window(8, path="events", n_streams=streams) as w:
+            acs.submit_tiny_stream(w, st, arena.data_ptr())
+            assert w.sync_rc(SYNC_NS) == 0
+            assert w.stats()["retired"] == len(st.kernels)
+        assert np.array_equal(bits(arena.cpu().numpy()), bits(O.tiny_run(st)))
+
+
+def test_events_rl_steps(torch):
+    sc = inputs.rl_scene(seed=1, n=64)
+    g = acs.RLSceneGPU(sc)
+    ref = O.Scene.from_inputs(sc)
+    say("events rl")
+    with acs.Window(32, path="events", n_streams=4) as w:
+        for step in range(4):
+            acs.rl_run(w, g, 1)
+            ref.step()
+            assert np.array_equal(bits(g.get(acs.RL_X)), bits(ref.X)), step
+            assert np.array_equal(bits(g.get(acs.RL_V)), bits(ref.V)), step
+
+
+def test_graph_per_input_rl_steps(torch):
+    sc = inputs.rl_scene(seed=3, n=100)
+    g = acs.RLSceneGPU(sc)
+    ref = O.Scene.from_inputs(sc)
+    say("graph per input rl")
+    counts, step_ns, build_ns = acs.rl_run_graphs(g, 5)
+    for _ in range(5):
+        ref.step()
+    assert np.array_equal(bits(g.get(acs.RL_X)), bits(ref.X))
+    assert np.array_equal(bits(g.get(acs.RL_V)), bits(ref.V))
+    assert counts["steps"] == 5 and 0 < build_ns < step_ns.sum()
+
+
+def test_events_dnn_matches_inorder(torch):
+    wts = inputs.dnn_weights()
+    inp = inputs.dnn_input(4)
+    outs = {}
+    for path in ("inorder", "events"):
+        say(f"dnn {path}")
+        net = acs.DNNGPU(wts, inputs.DNN_CELLS, inputs.DNN_CLASSES)
+        net.set_input(inp.x)
+        with acs.Window(16, path=path) as w:
+            acs.dnn_submit(w, net, inp.logits)
+            assert w.sync_rc(SYNC_NS) == 0
+        outs[path] = net.out.cpu().numpy()
+    assert np.array_equal(bits(outs["events"]), bits(outs["inorder"]))
+
+
+@pytest.fixture(scope="module")
+def dag():
+    graph = inputs.dag_graph()
+    wts = inputs.dag_weights(graph)
+    return graph, wts
+
+
+def run_dag(torch, graph, wts, x, path, W=16, trace=False, **kw):
+    net = acs.DAGGPU(graph, wts)
+    net.set_input(x)
+    with acs.Window(W, path=path, trace=trace, **kw) as w:
+        n = acs.dag_submit(w, net)
+        assert w.sync_rc(SYNC_NS) == 0
+        tr = w.trace() if trace else None
+    ys = [y.cpu().numpy() for y in net.y]
+    return n, net.out.cpu().numpy(), ys, tr
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_dag_paths_agree_and_schedules_valid(torch, dag, seed):
+    graph, wts = dag
+    x = inputs.dag_input(graph, seed)
+    ref = O.StaticDAG(graph, wts, x)
+    ref.run()
+    accs = ref.accesses()
+    res = {}
+    for path, kw in (("inorder", {}), ("plain", {}), ("device", {}), ("device", {"host_check_depth": 16}),
+                     ("events", {})):
+        key = path + ("_hc" if kw else "")
+        say(f"dag seed={seed} {key}")
+        trace = path in ("plain", "device")
+        n, out, ys, tr = run_dag(torch, graph, wts, x, path, trace=trace, **kw)
+        assert n == len(ref.kernels())
+        res[key] = (out, ys)
+        if tr is not None:
+            code, msg = O.check_trace(accs, 16, tr, check_times=True, early=(path == "device"))
+            assert code == 0, (key, msg)
+    for key, (out, ys) in res.items():
+        assert np.array_equal(bits(out), bits(res["inorder"][0])), key
+        for i, y in enumerate(ys):
+            assert np.array_equal(bits(y), bits(res["inorder"][1][i])), (key, i)
+    assert np.allclose(res["device"][0].astype(np.float64), ref.out, rtol=1e-4, atol=1e-4 * np.abs(ref.out).max())
+
+
+def test_dag_graph_replays(torch, dag):
+    graph, wts = dag
+    xs = [inputs.dag_input(graph, s) for s in (7, 8)]
+    want = [run_dag(torch, graph, wts, x, "inorder")[1] for x in xs]
+    net = acs.DAGGPU(graph, wts)
+    say("dag graph record")
+    with acs.Window(16, path="inorder") as w:
+        w.graph_begin()
+        n = acs.dag_submit(w, net)
+        g = w.graph_end()
+    with g:
+        assert g.info()["kernels"] == n
+        for x, ref in zip(xs, want):
+            net.set_input(x)
+            g.launch()
+            g.sync()
+            assert np.array_equal(bits(net.out.cpu().numpy()), bits(ref))
