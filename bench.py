@@ -103,12 +103,26 @@ def open_window(acs, path, W, **kw):
 
 
 def run_path(acs, inputs, torch, path, args, n_episodes, collect):
-    """Runs n_episodes fresh episodes; returns (seconds, kernels, step_ns list, kernel_ns list, counts)."""
+    """Runs n_episodes fresh episodes; returns (seconds, kernels, step_ns list,
+    kernel_ns list, counts, overlap tests per kernel)."""
     scenes = [acs.RLSceneGPU(inputs.rl_scene(seed=args.seed, n=args.bodies)) for _ in range(n_episodes)]
     torch.cuda.synchronize()
     kernels = 0
     step_ns, kern_ns, counts = [], [], None
     tests = 0
+    if path == "graph_per_input":
+        build = 0.0
+        t0 = time.perf_counter()
+        for g in scenes:
+            c, ns, b = acs.rl_run_graphs(g, args.physics_steps)
+            kernels += c["kernels"]
+            build += b
+            if collect:
+                step_ns.extend(ns.tolist())
+            counts = c
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return dt, kernels, step_ns, [build * 1e-9 / dt], counts, 0.0
     t0 = time.perf_counter()
     for g in scenes:
         w = open_window(acs, path, args.window, n_streams=args.streams, wg_per_task=1)
@@ -190,11 +204,11 @@ def dnn_section(acs, inputs, torch, args):
     wts = inputs.dnn_weights()
     seeds = list(range(args.dnn_inputs))
     out = {}
-    for path in ("device", "inorder"):
+    for path in ("device", "device_hostcheck", "inorder", "events"):
         nets = [acs.DNNGPU(wts, inputs.DNN_CELLS, inputs.DNN_CLASSES) for _ in range(8)]
         lat = []
         kernels = 0
-        with acs.Window(16, path=path) as w:
+        with open_window(acs, path, 16) as w:
             for i, sd in enumerate(seeds):
                 inp = inputs.dnn_input(sd)
                 net = nets[i % len(nets)]
@@ -218,6 +232,30 @@ def dnn_section(acs, inputs, torch, args):
         out[path] = {"latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
                      "kernels_per_s": k2 / dt, "inferences_per_s": len(seeds) / dt}
         log(f"[bench] dnn {path}: p50 {out[path]['latency_ms']['p50']:.3f} ms, {len(seeds) / dt:.0f} inferences/s")
+    # a DAG framework on the dynamic graph: each input's graph recorded,
+    # built, run and destroyed (construction included)
+    net = acs.DNNGPU(wts, inputs.DNN_CELLS, inputs.DNN_CLASSES)
+    lat, build = [], []
+    with acs.Window(16, path="inorder") as w:
+        for sd in seeds:
+            inp = inputs.dnn_input(sd)
+            net.set_input(inp.x)
+            t0 = time.perf_counter()
+            w.graph_begin()
+            acs.dnn_submit(w, net, inp.logits)
+            g = w.graph_end()
+            t1 = time.perf_counter()
+            g.launch()
+            g.sync()
+            g.destroy()
+            lat.append(time.perf_counter() - t0)
+            build.append(t1 - t0)
+    lat_s, build = np.array(lat[2:]), np.array(build[2:])
+    lat = lat_s * 1e3
+    out["graph_per_input"] = {"latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+                              "inferences_per_s": 1.0 / float(lat_s.mean()),
+                              "build_fraction": float(build.sum() / lat_s.sum())}
+    log(f"[bench] dnn graph_per_input: p50 {out['graph_per_input']['latency_ms']['p50']:.3f} ms")
     # steady state: the network with every branch on (a static graph),
     # recorded once and replayed as a HIP graph, against the window paths
     import numpy as np
@@ -257,7 +295,7 @@ def dnn_section(acs, inputs, torch, args):
         f"{steady['device']['latency_ms']['p50']:.3f} ms, inorder {steady['inorder']['latency_ms']['p50']:.3f} ms")
     return {"workload": f"gated 12-cell conv network, batch 1, {len(seeds)} inputs, W=16",
             "steady_state": dict(steady, workload="every branch on (static graph), replayed"),
-            "device": out["device"], "inorder": out["inorder"],
+            "by_path": out, "device": out["device"], "inorder": out["inorder"],
             "latency_speedup_p50": out["inorder"]["latency_ms"]["p50"] / out["device"]["latency_ms"]["p50"],
             "throughput_speedup": out["device"]["inferences_per_s"] / out["inorder"]["inferences_per_s"]}
 
@@ -320,6 +358,78 @@ def serve_section(acs, inputs, torch, args):
             "results_equal_inorder": {k: same(v, ref) for k, v in outputs.items() if k != "inorder"}}
 
 
+def dag_section(acs, inputs, torch, args):
+    """Static irregular network (randomly wired, 32 nodes, batch 1): latency
+    per inference on every path, the graph captured once and replayed, and
+    the graph rebuilt for every input."""
+    import numpy as np
+    graph = inputs.dag_graph()
+    wts = inputs.dag_weights(graph)
+    xs = [inputs.dag_input(graph, s) for s in range(args.dag_inputs)]
+    res = {}
+
+    def summary(lat):
+        lat = np.array(lat[2:]) * 1e3
+        return {"latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}}
+    ref_out = None
+    for path in ("device", "device_hostcheck", "inorder", "events", "plain"):
+        net = acs.DAGGPU(graph, wts)
+        lat = []
+        with open_window(acs, path, 16, n_streams=args.streams) as w:
+            for x in xs:
+                net.set_input(x)
+                t0 = time.perf_counter()
+                n = acs.dag_submit(w, net)
+                w.sync()
+                lat.append(time.perf_counter() - t0)
+        res[path] = summary(lat)
+        out = net.out.cpu().numpy()
+        if ref_out is None:
+            ref_out = out
+        res[path]["last_output_equals_device"] = bool(np.array_equal(out.view(np.uint32), ref_out.view(np.uint32)))
+        log(f"[bench] dag {path}: p50 {res[path]['latency_ms']['p50']:.3f} ms")
+    # graph captured once, replayed per input
+    net = acs.DAGGPU(graph, wts)
+    with acs.Window(16, path="inorder") as w:
+        w.graph_begin()
+        acs.dag_submit(w, net)
+        g = w.graph_end()
+    with g:
+        lat = []
+        for x in xs:
+            net.set_input(x)
+            t0 = time.perf_counter()
+            g.launch()
+            g.sync()
+            lat.append(time.perf_counter() - t0)
+        res["graph_replay"] = summary(lat)
+        res["graph_replay"]["edges"] = g.info()["edges"]
+    log(f"[bench] dag graph_replay: p50 {res['graph_replay']['latency_ms']['p50']:.3f} ms")
+    # graph rebuilt per input
+    net = acs.DAGGPU(graph, wts)
+    lat, build = [], []
+    with acs.Window(16, path="inorder") as w:
+        for x in xs:
+            net.set_input(x)
+            t0 = time.perf_counter()
+            w.graph_begin()
+            acs.dag_submit(w, net)
+            g = w.graph_end()
+            t1 = time.perf_counter()
+            g.launch()
+            g.sync()
+            g.destroy()
+            lat.append(time.perf_counter() - t0)
+            build.append(t1 - t0)
+    res["graph_per_input"] = summary(lat)
+    res["graph_per_input"]["build_fraction"] = float(np.sum(build[2:]) / np.sum(lat[2:]))
+    log(f"[bench] dag graph_per_input: p50 {res['graph_per_input']['latency_ms']['p50']:.3f} ms")
+    base = res["inorder"]["latency_ms"]["p50"]
+    return {"workload": f"randomly wired network, {len(graph.preds)} nodes (3x3 conv 32x32x32 each), batch 1, "
+                        f"{n} kernels, {len(xs)} inputs, W=16",
+            "by_path": res, "speedup_p50_vs_inorder": {k: base / v["latency_ms"]["p50"] for k, v in res.items()}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -333,12 +443,14 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
-    ap.add_argument("--paths", default="device,device_hostcheck,inorder,plain")
+    ap.add_argument("--paths", default="device,device_hostcheck,inorder,plain,events,graph_per_input")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-scenes section")
     ap.add_argument("--batch-scenes", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--no-dnn", action="store_true", help="skip the dynamic-DNN section")
     ap.add_argument("--dnn-inputs", type=int, default=64)
+    ap.add_argument("--no-dag", action="store_true", help="skip the static-network section")
+    ap.add_argument("--dag-inputs", type=int, default=32)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rates", default="1000,2000,5000,10000,20000")
@@ -400,6 +512,11 @@ def main():
         hc = res["device_hostcheck"]
         out["host_check_split"] = {"kernels_per_s": hc[1] / hc[0], "vs_device_checks": dt / hc[0],
                                    "host_overlap_tests_per_kernel": hc[5]}
+    if "events" in res:
+        out["events_kernels_per_s"] = res["events"][1] / res["events"][0]
+    if "graph_per_input" in res:
+        gp = res["graph_per_input"]
+        out["graph_per_input"] = {"kernels_per_s": gp[1] / gp[0], "build_fraction": gp[3][0]}
     if "plain" in res:
         out["plain_kernels_per_s"] = res["plain"][1] / res["plain"][0]
         out["plain_speedup_vs_inorder"] = res["inorder"][0] / res["plain"][0] if "inorder" in res else None
@@ -422,6 +539,8 @@ def main():
         log("[bench] overhead probes")
         probes = {}
         for p in paths:
+            if p == "graph_per_input":
+                continue
             probes[p] = {"independent_us_per_kernel": overhead_probe(acs, p, 20000 if p.startswith("device") else 4000,
                                                                      False),
                          "chain_us_per_kernel": overhead_probe(acs, p, 2000, True)}
@@ -430,6 +549,8 @@ def main():
         out["batched"] = batched_section(acs, inputs, torch, args)
     if not args.no_dnn:
         out["dnn"] = dnn_section(acs, inputs, torch, args)
+    if not args.no_dag:
+        out["static_dag"] = dag_section(acs, inputs, torch, args)
     if not args.no_serve:
         out["serving"] = serve_section(acs, inputs, torch, args)
     if not args.no_cpu_baseline:
