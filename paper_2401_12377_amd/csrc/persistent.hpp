@@ -213,6 +213,36 @@ __device__ inline uint64_t readlane64(uint64_t x, int l)
 // a 64-bit field held in dwords l (low) and l + 1 (high) of a wave-wide word
 __device__ inline uint64_t readpair(uint32_t x, int l) { return ((uint64_t)readlane32(x, l + 1) << 32) | readlane32(x, l); }
 
+// Pair tests of one insertion pass (Algorithm 1 in both directions): segment
+// k of the new kernel, k = rep, rep + R, ... below nseg, against positions
+// m < MP of this lane's slot.  A new write conflicts with any intersecting
+// segment, a new read only with an intersecting write.  Positions a slot
+// does not use hold the empty range [0, 0), which intersects nothing, so MP
+// only has to cover the segment counts of the occupied slots.  UNI: nseg is
+// the same on every lane (one window), so the loop test is scalar.
+template <int MP, bool UNI>
+__device__ __forceinline__ uint64_t pair_hits(const DevDesc *d, uint32_t nseg, uint32_t wb, uint32_t R, uint32_t rep,
+                                              const uint64_t (&ss)[kSegs], const uint64_t (&se)[kSegs],
+                                              const uint64_t (&wmask)[kSegs])
+{
+    uint64_t hits = 0;
+    for (uint32_t k0 = 0; UNI ? k0 < nseg : __builtin_amdgcn_ballot_w64(rep < R && k0 + rep < nseg) != 0; k0 += R) {
+        const uint32_t k = k0 + rep;
+        const bool kin = rep < R && k < nseg;
+        const uint32_t kk = kin ? k : 0u;
+        const uint64_t a0 = kin ? d->s[kk] : 0ull, a1 = kin ? d->e[kk] : 0ull;
+        // lanes whose new range is a write: they match any slot range
+        const uint64_t wkm = __builtin_amdgcn_ballot_w64(kin && ((wb >> kk) & 1u));
+        // no branch per position: on the window wave a branch costs more than
+        // the two compares it would skip.  The compares go straight into lane
+        // masks; the rest is scalar.
+#pragma unroll
+        for (int m = 0; m < MP; m++)
+            hits |= __builtin_amdgcn_ballot_w64(a0 < se[m]) & __builtin_amdgcn_ballot_w64(a1 > ss[m]) & (wkm | wmask[m]);
+    }
+    return hits;
+}
+
 template <int NG>
 __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
 {
@@ -264,6 +294,9 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
     uint64_t wmask[kSegs];
 #pragma unroll
     for (int m = 0; m < kSegs; m++) wmask[m] = 0;
+    // slots whose kernel uses more than 4 (more than 2) range positions; with
+    // valid they bound the positions an insertion must test
+    uint64_t over4 = 0, over2 = 0;
 
     if (lane == 0) __hip_atomic_store(&p.ctrl->alive, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 
@@ -313,18 +346,11 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                     const uint32_t np = npr < kMaxPieces ? npr : kMaxPieces;
                     // the descriptor goes to the task table as it is
                     if (lane < kDescCopyDwords) reinterpret_cast<uint32_t *>(&p.st->task[slot])[lane] = dw;
-                    // Algorithm 1 in both directions (see the group case below)
                     uint64_t hits = 0;
-                    for (uint32_t k0 = 0; !hc && k0 < nseg; k0 += R) {
-                        const uint32_t k = k0 + rep;
-                        const bool kin = rep < R && k < nseg;
-                        const uint32_t kk = kin ? k : 0u;
-                        const uint64_t a0 = kin ? d->s[kk] : 0ull, a1 = kin ? d->e[kk] : 0ull;
-                        const uint64_t wkm = __builtin_amdgcn_ballot_w64(kin && ((wb >> kk) & 1u));
-#pragma unroll
-                        for (int m = 0; m < kSegs; m++)
-                            hits |= __builtin_amdgcn_ballot_w64(a0 < se[m]) & __builtin_amdgcn_ballot_w64(a1 > ss[m]) &
-                                    (wkm | wmask[m]);
+                    if (!hc) {
+                        if (valid & over4) hits = pair_hits<8, true>(d, nseg, wb, R, rep, ss, se, wmask);
+                        else if (valid & over2) hits = pair_hits<4, true>(d, nseg, wb, R, rep, ss, se, wmask);
+                        else hits = pair_hits<2, true>(d, nseg, wb, R, rep, ss, se, wmask);
                     }
                     uint64_t upm = 0;
                     for (uint32_t r = 0; r < R; r++) upm |= (hits >> (r * span)) & spanmask;
@@ -356,6 +382,8 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
 #pragma unroll
                     for (int m = 0; m < kSegs; m++)
                         wmask[m] = ((uint32_t)m < nseg && ((wb >> m) & 1u)) ? (wmask[m] | rbit) : (wmask[m] & ~rbit);
+                    over4 = nseg > 4u ? (over4 | bit) : (over4 & ~bit);
+                    over2 = nseg > 2u ? (over2 | bit) : (over2 & ~bit);
                     if (tr && lane == 0 && seq < p.trace_cap) {
                         acs_trace_rec *r = &p.trace[seq];
                         r->seq = (int64_t)seq;
@@ -420,28 +448,12 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                     const uint32_t nraw = gin ? d->nseg : 0u;
                     const uint32_t nseg = nraw < (uint32_t)kSegs ? nraw : (uint32_t)kSegs;
                     const uint32_t wb = d->wbits;
-                    // Algorithm 1 in both directions: segment k of the group's new
-                    // kernel against segment m of every occupied slot of the group.
-                    // A new write conflicts with any intersecting segment, a new
-                    // read only with an intersecting write.  Replica r takes k = r,
-                    // r + R, ...; segments past nseg are the empty range.
-                    uint64_t hits = 0;
-                    for (uint32_t k0 = 0; __builtin_amdgcn_ballot_w64(rep < R && k0 + rep < nseg) != 0; k0 += R) {
-                        const uint32_t k = k0 + rep;
-                        const bool kin = rep < R && k < nseg;
-                        const uint32_t kk = kin ? k : 0u;
-                        const uint64_t a0 = kin ? d->s[kk] : 0ull, a1 = kin ? d->e[kk] : 0ull;
-                        // lanes whose new range is a write: they match any slot range
-                        const uint64_t wkm = __builtin_amdgcn_ballot_w64(kin && ((wb >> kk) & 1u));
-                        // all eight positions, no branch: unused positions hold the
-                        // empty range; on the window wave a branch per position costs
-                        // more than the two compares it would skip.  The compares go
-                        // straight into lane masks; the rest is scalar.
-    #pragma unroll
-                        for (int m = 0; m < kSegs; m++)
-                            hits |= __builtin_amdgcn_ballot_w64(a0 < se[m]) & __builtin_amdgcn_ballot_w64(a1 > ss[m]) &
-                                    (wkm | wmask[m]);
-                    }
+                    // segment k of each group's new kernel against every occupied
+                    // slot of the group; replica r takes k = r, r + R, ...
+                    uint64_t hits;
+                    if (valid & over4) hits = pair_hits<8, false>(d, nseg, wb, R, rep, ss, se, wmask);
+                    else if (valid & over2) hits = pair_hits<4, false>(d, nseg, wb, R, rep, ss, se, wmask);
+                    else hits = pair_hits<2, false>(d, nseg, wb, R, rep, ss, se, wmask);
                     // fold the replicas onto their slot lanes; a new slot's own lanes
                     // may already hold its ranges: only occupied slots count
                     uint64_t upall = 0;
@@ -491,6 +503,11 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                             const uint64_t wr = __builtin_amdgcn_ballot_w64(newrep && (uint32_t)m < nseg && ((wb >> m) & 1u));
                             wmask[m] = (wmask[m] & ~newlanes) | wr;
                         }
+                        // segment-count classes of the new occupants (slot lanes only)
+                        const uint64_t big4 = __builtin_amdgcn_ballot_w64(newrep && rep == 0 && nseg > 4u);
+                        const uint64_t big2 = __builtin_amdgcn_ballot_w64(newrep && rep == 0 && nseg > 2u);
+                        over4 = (over4 & ~newbits) | big4;
+                        over2 = (over2 & ~newbits) | big2;
                     }
     #pragma unroll
                     for (int g = 0; g < NG; g++)
