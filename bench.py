@@ -405,29 +405,16 @@ def dag_section(acs, inputs, torch, args):
         res["graph_replay"] = summary(lat)
         res["graph_replay"]["edges"] = g.info()["edges"]
     log(f"[bench] dag graph_replay: p50 {res['graph_replay']['latency_ms']['p50']:.3f} ms")
-    # graph rebuilt per input
-    net = acs.DAGGPU(graph, wts)
-    lat, build = [], []
-    with acs.Window(16, path="inorder") as w:
-        for x in xs:
-            net.set_input(x)
-            t0 = time.perf_counter()
-            w.graph_begin()
-            acs.dag_submit(w, net)
-            g = w.graph_end()
-            t1 = time.perf_counter()
-            g.launch()
-            g.sync()
-            g.destroy()
-            lat.append(time.perf_counter() - t0)
-            build.append(t1 - t0)
-    res["graph_per_input"] = summary(lat)
-    res["graph_per_input"]["build_fraction"] = float(np.sum(build[2:]) / np.sum(lat[2:]))
-    log(f"[bench] dag graph_per_input: p50 {res['graph_per_input']['latency_ms']['p50']:.3f} ms")
+    # The graph rebuilt for every input is not measured on this network: its
+    # host process once ended with a segmentation fault inside that loop (no
+    # GPU fault reported) and no cause has been found in this code; it is
+    # measured on the RL episode and the dynamic network.
+    res["graph_per_input"] = None
     base = res["inorder"]["latency_ms"]["p50"]
     return {"workload": f"randomly wired network, {len(graph.preds)} nodes (3x3 conv 32x32x32 each), batch 1, "
                         f"{n} kernels, {len(xs)} inputs, W=16",
-            "by_path": res, "speedup_p50_vs_inorder": {k: base / v["latency_ms"]["p50"] for k, v in res.items()}}
+            "by_path": res,
+            "speedup_p50_vs_inorder": {k: base / v["latency_ms"]["p50"] for k, v in res.items() if v is not None}}
 
 
 def main():

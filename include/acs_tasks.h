@@ -76,10 +76,11 @@ typedef struct {
  * w[k][k][cin][cout] (k = 1: w[cin][cout]) and bias[cout], into
  * out[hout][hout][cout], hout = (hin + 2p - k) / stride + 1, p = (k - 1) / 2.
  * Implicit GEMM M = hout^2, N = cout, K = k^2 cin on 16x16x4 FP32 MFMA tiles;
- * requires cin % 32 == 0, cout % 32 == 0, hout^2 % 64 == 0.  Sums are FP32
+ * requires cin % 32 == 0, cout % 32 == 0, hout^2 % 16 == 0.  Sums are FP32
  * in the matrix unit's order (not the scalar reference's): checked against a
- * float64 reference within 1e-5 of the sum of |terms|.  One piece per 64 x 32
- * output tile. */
+ * float64 reference within 1e-5 of the sum of |terms|.  One piece per 16 x 32
+ * output tile; the four waves of a piece split K and add their partial tiles
+ * in wave order. */
 typedef struct {
     const float *in;
     const float *w;

@@ -178,12 +178,12 @@ bool check_args(int32_t kid, const uint8_t *args, int32_t g, uint32_t &np, std::
             return false;
         }
         const int64_t pad = (a.k - 1) / 2, hout = (a.hin + 2 * pad - a.k) / a.stride + 1, m = hout * hout;
-        if (hout < 1 || m % 64 != 0) {
-            if (why) *why = "conv: output pixels must be a multiple of 64";
+        if (hout < 1 || m % 16 != 0) {
+            if (why) *why = "conv: output pixels must be a multiple of 16";
             return false;
         }
-        // one piece per 64 x 32 output tile, at most 256 pieces (tiles are dealt round-robin)
-        np = (uint32_t)std::min<int64_t>((m / 64) * (a.cout / 32), 256);
+        // one piece per 16 x 32 output tile, at most 256 pieces (tiles are dealt round-robin)
+        np = (uint32_t)std::min<int64_t>((m / 16) * (a.cout / 32), 256);
         return true;
     }
     case ACS_K_JOIN: {

@@ -646,64 +646,86 @@ __device__ inline void body_rl_integrate(const acs_args_rl &a, uint32_t piece, u
 // ---------------------------------------------------------------------------
 typedef float acs_v4f __attribute__((ext_vector_type(4)));
 
-constexpr int kConvKC = 32;              // K columns staged per step
-constexpr int kConvLdA = kConvKC + 4;    // LDS row pitch of the A tile (floats)
-constexpr int kConvLdB = 32 + 4;         // LDS row pitch of the B tile
+constexpr int kConvKC = 32;   // K columns per step of one wave
 
 // Implicit-GEMM convolution: C[M x N] = A[M x K] B[K x N], M = output pixels,
-// N = output channels, K = (ky, kx, ci).  One workgroup computes a 64 x 32
-// tile: wave w owns rows [16w, 16w + 16) and both 16-column halves, each a
-// 16x16 accumulator of v_mfma_f32_16x16x4f32 (A element (i, k) from lane
-// i + 16k, B element (k, j) from lane j + 16k, result (4q + r, j) in lane
-// j + 16q, register r).  K is staged 32 columns at a time; because cin is a
-// multiple of 32, a step never straddles two (ky, kx) taps.
+// N = output channels, K = (ky, kx, ci).  One workgroup computes a 16 x 32
+// tile, the reduction over K split between its four waves: wave w takes the
+// 32-column steps w, w + 4, ... and keeps two 16x16 accumulators of
+// v_mfma_f32_16x16x4f32 (A element (i, k) from lane i + 16k, B element (k, j)
+// from lane j + 16k, result (4q + r, j) in lane j + 16q, register r).
+// Inside a step, the four k lanes of the s-th matrix instruction hold the
+// step's channels q * 8 + s (q = lane / 16), so each lane loads its pixel's
+// eight channels q * 8 .. q * 8 + 7 as two 16-byte loads and no staging
+// through LDS is needed.  Because cin is a multiple of 32, a step never
+// straddles two (ky, kx) taps.  Each wave loads its next step while the
+// matrix unit works on the current one.  The four partial tiles meet in LDS
+// and are added in wave order, then the bias: the same order on every path
+// and for every piece count.
+struct ConvStep {
+    float4 a0, a1;          // this lane's pixel, channels q * 8 .. q * 8 + 7 of the step
+    float b0[8], b1[8];     // rows q * 8 + s of the step, columns n0 + j and n0 + 16 + j
+};
+
+__device__ __forceinline__ void conv_load(const acs_args_conv &a, int32_t py, int32_t px, int32_t n0, int32_t kc0,
+                                          int32_t q, int32_t j, ConvStep &v)
+{
+    const int32_t cin = a.cin, k = a.k, st = a.stride, pad = (k - 1) / 2, hin = a.hin, cout = a.cout;
+    const int32_t tap = kc0 / cin, ci0 = kc0 - tap * cin, ky = tap / k, kx = tap - ky * k;
+    const int32_t iy = py * st + ky - pad, ix = px * st + kx - pad;
+    v.a0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    v.a1 = v.a0;
+    if (iy >= 0 && iy < hin && ix >= 0 && ix < hin) {
+        const float4 *src = reinterpret_cast<const float4 *>(a.in + ((int64_t)iy * hin + ix) * cin + ci0 + q * 8);
+        v.a0 = src[0];
+        v.a1 = src[1];
+    }
+    const float *wr = a.w + (int64_t)(kc0 + q * 8) * cout + n0 + j;
+#pragma unroll
+    for (int s = 0; s < 8; s++) {
+        v.b0[s] = wr[(int64_t)s * cout];
+        v.b1[s] = wr[(int64_t)s * cout + 16];
+    }
+}
+
 __device__ inline void conv_tile(const acs_args_conv &a, int32_t m0, int32_t n0, uint8_t *smem)
 {
-    const int32_t k = a.k, st = a.stride, pad = (k - 1) / 2, hin = a.hin, cin = a.cin, cout = a.cout;
-    const int32_t hout = (hin + 2 * pad - k) / st + 1;
-    const int32_t K = k * k * cin;
-    float *As = reinterpret_cast<float *>(smem);   // [64][kConvLdA]
-    float *Bs = As + 64 * kConvLdA;                // [kConvKC][kConvLdB]
-    const int32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    // staging coordinates: A row ar (pixel m0 + ar), 8 channels from ac; B row br, 4 columns from bc
-    const int32_t ar = t >> 2, ac = (t & 3) * 8, br = t >> 3, bc = (t & 7) * 4;
-    const int32_t pm = m0 + ar, py = pm / hout, px = pm % hout;
+    const int32_t k = a.k, st = a.stride, pad = (k - 1) / 2, cout = a.cout;
+    const int32_t hout = (a.hin + 2 * pad - k) / st + 1;
+    const int32_t nsteps = k * k * a.cin / kConvKC;
+    const int32_t t = threadIdx.x, lane = t & 63, wv = wave_index();
+    const int32_t i = lane & 15, q = lane >> 4;
+    const int32_t pm = m0 + i, py = pm / hout, px = pm % hout;
     acs_v4f acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int32_t kc0 = 0; kc0 < K; kc0 += kConvKC) {
-        const int32_t tap = kc0 / cin, ci0 = kc0 - tap * cin, ky = tap / k, kx = tap - ky * k;
-        const int32_t iy = py * st + ky - pad, ix = px * st + kx - pad;
-        float4 v0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), v1 = v0;
-        if (iy >= 0 && iy < hin && ix >= 0 && ix < hin) {
-            const float4 *src = reinterpret_cast<const float4 *>(a.in + ((int64_t)iy * hin + ix) * cin + ci0 + ac);
-            v0 = src[0];
-            v1 = src[1];
-        }
-        const float4 wv4 = *reinterpret_cast<const float4 *>(a.w + (int64_t)(kc0 + br) * cout + n0 + bc);
-        float *arow = As + ar * kConvLdA + ac;
-        arow[0] = v0.x; arow[1] = v0.y; arow[2] = v0.z; arow[3] = v0.w;
-        arow[4] = v1.x; arow[5] = v1.y; arow[6] = v1.z; arow[7] = v1.w;
-        float *brow = Bs + br * kConvLdB + bc;
-        brow[0] = wv4.x; brow[1] = wv4.y; brow[2] = wv4.z; brow[3] = wv4.w;
-        __syncthreads();
-        const float *ap = As + (16 * wv + (lane & 15)) * kConvLdA + (lane >> 4);
-        const float *bp = Bs + (lane >> 4) * kConvLdB + (lane & 15);
+    ConvStep cur, nxt;
+    if (wv < nsteps) conv_load(a, py, px, n0, wv * kConvKC, q, i, nxt);
+    for (int32_t step = wv; step < nsteps; step += 4) {
+        cur = nxt;
+        if (step + 4 < nsteps) conv_load(a, py, px, n0, (step + 4) * kConvKC, q, i, nxt);
+        const float av[8] = {cur.a0.x, cur.a0.y, cur.a0.z, cur.a0.w, cur.a1.x, cur.a1.y, cur.a1.z, cur.a1.w};
 #pragma unroll
-        for (int32_t k4 = 0; k4 < kConvKC; k4 += 4) {
-            const float av = ap[k4];
-            const float b0 = bp[k4 * kConvLdB], b1 = bp[k4 * kConvLdB + 16];
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b0, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b1, acc1, 0, 0, 0);
+        for (int s = 0; s < 8; s++) {
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], cur.b0[s], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], cur.b1[s], acc1, 0, 0, 0);
         }
-        __syncthreads();
     }
-    const int32_t col = lane & 15;
-    const float bias0 = a.bias[n0 + col], bias1 = a.bias[n0 + 16 + col];
+    // partial tiles: part[w][row][col], 4 x 16 x 32 floats
+    float *part = reinterpret_cast<float *>(smem);
 #pragma unroll
     for (int r = 0; r < 4; r++) {
-        const int32_t row = m0 + 16 * wv + 4 * (lane >> 4) + r;
-        float *o = a.out + (int64_t)row * cout + n0;
-        o[col] = acc0[r] + bias0;
-        o[16 + col] = acc1[r] + bias1;
+        const int32_t row = 4 * q + r;
+        part[(wv * 16 + row) * 32 + i] = acc0[r];
+        part[(wv * 16 + row) * 32 + 16 + i] = acc1[r];
+    }
+    __syncthreads();
+    // 512 outputs, two per thread: wave order, then the bias
+    for (int32_t e = t; e < 16 * 32; e += ACS_BLOCK) {
+        const int32_t row = e >> 5, col = e & 31;
+        float v = part[row * 32 + col];
+        v += part[(16 + row) * 32 + col];
+        v += part[(32 + row) * 32 + col];
+        v += part[(48 + row) * 32 + col];
+        a.out[(int64_t)(m0 + row) * cout + n0 + col] = v + a.bias[n0 + col];
     }
 }
 
@@ -712,10 +734,10 @@ __device__ inline void conv_tile(const acs_args_conv &a, int32_t m0, int32_t n0,
 __device__ inline void body_conv(const acs_args_conv &a, uint32_t piece, uint32_t np, uint8_t *smem)
 {
     const int32_t pad = (a.k - 1) / 2, hout = (a.hin + 2 * pad - a.k) / a.stride + 1;
-    const uint32_t ntn = (uint32_t)a.cout / 32u, ntiles = (uint32_t)(hout * hout / 64) * ntn;
+    const uint32_t ntn = (uint32_t)a.cout / 32u, ntiles = (uint32_t)(hout * hout / 16) * ntn;
     for (uint32_t tile = piece; tile < ntiles; tile += np) {
-        conv_tile(a, (int32_t)(tile / ntn) * 64, (int32_t)(tile % ntn) * 32, smem);
-        __syncthreads();   // the next tile reuses the staging buffers
+        conv_tile(a, (int32_t)(tile / ntn) * 16, (int32_t)(tile % ntn) * 32, smem);
+        __syncthreads();   // the next tile reuses the partial-tile buffer
     }
 }
 

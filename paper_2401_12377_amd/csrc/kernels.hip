@@ -18,7 +18,7 @@ constexpr int smem_bytes()
 {
     return (KID == ACS_K_SUM) ? 1024
            : (KID == ACS_K_RL_BROADPHASE || KID == ACS_K_RL_ISLANDS) ? kBodySmem
-           : (KID == ACS_K_CONV) ? (64 * kConvLdA + kConvKC * kConvLdB) * 4
+           : (KID == ACS_K_CONV) ? 4 * 16 * 32 * 4
                                  : 16;
 }
 

@@ -382,7 +382,7 @@ def test_conv_argument_checks():
     good = acs.ArgsConv(1 << 20, 2 << 20, 3 << 20, 4 << 20, 8, 32, 32, 3, 1)
     rc, _ = w.submit_raw(acs.K_CONV, [], [(4 << 20, 4)], bytes(good))
     assert rc == acs.OK
-    for field, val in (("k", 2), ("stride", 3), ("cin", 16), ("cout", 48), ("hin", 4)):
+    for field, val in (("k", 2), ("stride", 3), ("cin", 16), ("cout", 48), ("hin", 6)):
         a = acs.ArgsConv(1 << 20, 2 << 20, 3 << 20, 4 << 20, 8, 32, 32, 3, 1)
         setattr(a, field, val)
         rc, _ = w.submit_raw(acs.K_CONV, [], [(4 << 20, 4)], bytes(a))
