@@ -576,8 +576,8 @@ int acs_device_query(int32_t device, acs_device_info *out)
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, device) == hipSuccess) out->wall_clock_khz = v;
     if (hipRuntimeGetVersion(&v) == hipSuccess) out->runtime_version = v;
     int32_t b = 0;
-    if (persistent_blocks_per_cu(&b) == hipSuccess) out->persistent_wg_per_cu = b;
-    if (persistent_lds_bytes(&b) == hipSuccess) out->lds_bytes_per_wg = b;
+    if (persistent_blocks_per_cu(1, &b) == hipSuccess) out->persistent_wg_per_cu = b;
+    if (persistent_lds_bytes(1, &b) == hipSuccess) out->lds_bytes_per_wg = b;
     return ACS_OK;
 }
 

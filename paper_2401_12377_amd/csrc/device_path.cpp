@@ -43,7 +43,8 @@ public:
         (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, cfg_.device);
         clock_khz_ = rate_khz > 0 ? rate_khz : 100000;
         int32_t per_cu = 0;
-        if ((e = persistent_blocks_per_cu(&per_cu)) != hipSuccess) return hip_fail(e, "occupancy query");
+        if ((e = persistent_blocks_per_cu(std::max(1, std::min(cfg_.n_groups, kMaxGroups)), &per_cu)) != hipSuccess)
+            return hip_fail(e, "occupancy query");
         const int32_t capacity = std::max(1, per_cu) * std::max(1, cus);
         int32_t workers = cfg_.n_workers > 0 ? cfg_.n_workers : cus;
         workers = std::min(workers, capacity - 1);

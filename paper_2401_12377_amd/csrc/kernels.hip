@@ -60,6 +60,9 @@ hipError_t launch_task(int32_t kid, const void *args, uint32_t npieces, hipStrea
     return hipLaunchKernel(k_table[kid], dim3(npieces), dim3(ACS_BLOCK), argv, 0, stream);
 }
 
+// One instance per bound on the window groups (1, 2, 4, 8), so that a
+// single window does not carry the register pressure of eight.
+template <int NG>
 __global__ __launch_bounds__(ACS_BLOCK) void k_persistent(DevParams p)
 {
     __shared__ __align__(16) uint8_t smem[kBodySmem];
@@ -69,43 +72,41 @@ __global__ __launch_bounds__(ACS_BLOCK) void k_persistent(DevParams p)
         if (threadIdx.x == 0) fetch_init(fs);
         __syncthreads();
         const uint32_t wave = uni32(threadIdx.x) >> 6;   // uniform: whole waves take each branch
-        // the smallest compiled group bound that covers the window's groups
-        const int32_t ng = p.n_groups;
-        if (wave == 0) {
-            if (ng <= 1) window_wave<1>(p, fs);
-            else if (ng <= 2) window_wave<2>(p, fs);
-            else if (ng <= 4) window_wave<4>(p, fs);
-            else window_wave<8>(p, fs);
-        } else if (wave == 1) {
-            if (ng <= 1) fifo_wave<1>(p, fs);
-            else if (ng <= 2) fifo_wave<2>(p, fs);
-            else if (ng <= 4) fifo_wave<4>(p, fs);
-            else fifo_wave<8>(p, fs);
-        }
+        if (wave == 0) window_wave<NG>(p, fs);
+        else if (wave == 1) fifo_wave<NG>(p, fs);
         return;
     }
     worker(p, smem, &mail);
+}
+
+// the smallest compiled group bound that covers the window's groups
+static const void *persistent_kernel(int32_t n_groups)
+{
+    if (n_groups <= 1) return reinterpret_cast<const void *>(&k_persistent<1>);
+    if (n_groups <= 2) return reinterpret_cast<const void *>(&k_persistent<2>);
+    if (n_groups <= 4) return reinterpret_cast<const void *>(&k_persistent<4>);
+    return reinterpret_cast<const void *>(&k_persistent<8>);
 }
 
 hipError_t launch_persistent(const DevParams &p, int32_t grid, hipStream_t stream)
 {
     DevParams copy = p;
     void *argv[1] = {&copy};
-    return hipLaunchKernel(reinterpret_cast<const void *>(&k_persistent), dim3(grid), dim3(ACS_BLOCK), argv, 0, stream);
+    return hipLaunchKernel(persistent_kernel(p.n_groups), dim3(grid), dim3(ACS_BLOCK), argv, 0, stream);
 }
 
-hipError_t persistent_blocks_per_cu(int32_t *blocks)
+hipError_t persistent_blocks_per_cu(int32_t n_groups, int32_t *blocks)
 {
     int b = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, reinterpret_cast<const void *>(&k_persistent), ACS_BLOCK, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, persistent_kernel(n_groups), ACS_BLOCK, 0);
     *blocks = b;
     return e;
 }
 
-hipError_t persistent_lds_bytes(int32_t *bytes)
+hipError_t persistent_lds_bytes(int32_t n_groups, int32_t *bytes)
 {
     hipFuncAttributes a;
-    hipError_t e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(&k_persistent));
+    hipError_t e = hipFuncGetAttributes(&a, persistent_kernel(n_groups));
     *bytes = (int32_t)a.sharedSizeBytes;
     return e;
 }

@@ -19,10 +19,11 @@ const void *task_kernel(int32_t kid);
 // workgroups 1 .. grid-1 are workers.
 hipError_t launch_persistent(const DevParams &p, int32_t grid, hipStream_t stream);
 
-// Workgroups of the persistent kernel that fit on one compute unit.
-hipError_t persistent_blocks_per_cu(int32_t *blocks);
+// Workgroups of the persistent kernel (the instance for n_groups window
+// groups) that fit on one compute unit.
+hipError_t persistent_blocks_per_cu(int32_t n_groups, int32_t *blocks);
 
-// Static LDS of one persistent-kernel workgroup.
-hipError_t persistent_lds_bytes(int32_t *bytes);
+// Static LDS of one persistent-kernel workgroup (instance for n_groups).
+hipError_t persistent_lds_bytes(int32_t n_groups, int32_t *bytes);
 
 }  // namespace acs
