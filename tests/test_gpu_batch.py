@@ -107,3 +107,22 @@ def test_group_sync_and_validation(torch):
         for g in range(4):
             assert w.sync_group(g) == 0
         assert w.stats()["retired"] == counts["kernels"]
+
+
+@pytest.mark.parametrize("G,W,wg", [(1, 16, 2), (4, 16, 1)])
+def test_full_size_batch_matches_oracle(torch, G, W, wg):
+    """The batched workload at full size (256 scenes of 16-512 bodies, 20
+    steps, one persistent launch): every scene's final state bit-identical to
+    the oracle's program-order run of that scene alone."""
+    scs = inputs.batched_scenes(3, 256)
+    gpu = [acs.RLSceneGPU(sc) for sc in scs]
+    say(f"full batch G={G} W={W} wg={wg}")
+    with acs.Window(W, path="device", n_groups=G, wg_per_task=wg) as w:
+        counts, _ = acs.rl_run_batch(w, gpu, 20, n_groups=G)
+    assert counts["steps"] == 20 * 256
+    for i, (g, sc) in enumerate(zip(gpu, scs)):
+        ref = O.Scene.from_inputs(sc)
+        for _ in range(20):
+            ref.step()
+        assert np.array_equal(bits(g.get(acs.RL_X)), bits(ref.X)), (i, sc.n)
+        assert np.array_equal(bits(g.get(acs.RL_V)), bits(ref.V)), (i, sc.n)

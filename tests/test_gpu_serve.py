@@ -152,3 +152,34 @@ def test_repeated_runs_reuse_memory(torch, model):
             assert np.array_equal(bits(a[0]), bits(b[0])) and np.array_equal(bits(a[1]), bits(b[1]))
         else:
             assert np.array_equal(bits(a), bits(b))
+
+
+def test_larger_mix_device_equals_inorder(torch, model):
+    """300 requests at 10k/s (over capacity of the in-order path): the device
+    path with four window groups gives every request the in-order path's bits,
+    and a sample of the RL requests the oracle's."""
+    specs = inputs.serve_requests(seed=12, rate_per_s=10000.0, n_requests=300)
+    rl, dnn = build(specs)
+    sset = acs.ServeSet(specs, rl, dnn, inputs.DNN_CLASSES)
+    net = acs.DNNGPU(model, inputs.DNN_CELLS, inputs.DNN_CLASSES)
+    pool = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    host = acs.serve_host(256)
+    torch.cuda.current_stream().synchronize()
+    outs = {}
+    for path, W, G in (("inorder", 8, 1), ("device", 16, 4)):
+        sset.clear_outputs()
+        say(f"serve 300 requests path={path}")
+        with acs.Window(W, path=path, n_groups=G) as w:
+            res, st = acs.serve_run(w, sset, pool, host, max_resident=256, model=net, stall_ns=60 * 10 ** 9)
+        assert st["kernels"] == sum(r["kernels"] for r in res)
+        outs[path] = sset.outputs()
+    for i, (a, b) in enumerate(zip(outs["device"], outs["inorder"])):
+        if isinstance(a, tuple):
+            assert np.array_equal(bits(a[0]), bits(b[0])) and np.array_equal(bits(a[1]), bits(b[1])), i
+        else:
+            assert np.array_equal(bits(a), bits(b)), i
+    rl_ids = [i for i, s in enumerate(specs) if s.kind == inputs.SERVE_RL][:20]
+    for i in rl_ids:
+        ref = O.Scene.from_inputs(rl[specs[i].seed])
+        ref.step()
+        assert np.array_equal(bits(outs["device"][i][0]), bits(ref.X)), i
