@@ -193,7 +193,8 @@ bool check_args(int32_t kid, const uint8_t *args, int32_t g, uint32_t &np, std::
             if (why) *why = "join: null buffer";
             return false;
         }
-        np = std::max(1u, std::min(gg, div_up(a.n, 1024)));
+        // one piece per 2048 elements (an activation tensor is not a small body)
+        np = std::max(1u, std::min(256u, div_up(a.n, 2048)));
         return true;
     }
     case ACS_K_AVGPOOL: {

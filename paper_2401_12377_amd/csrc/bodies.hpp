@@ -743,33 +743,79 @@ __device__ inline void body_conv(const acs_args_conv &a, uint32_t piece, uint32_
 
 __device__ inline float relu(float x) { return x > 0.0f ? x : 0.0f; }
 
+// Elementwise; 16-byte accesses where the piece and the buffers allow
+// (pieces start on multiples of 256 elements), scalar otherwise.
 __device__ inline void body_join(const acs_args_join &a, uint32_t piece, uint32_t np)
 {
     uint32_t lo, hi;
     piece_range(a.n, piece, np, lo, hi);
+    const bool v4 = ((uintptr_t)a.out | (uintptr_t)a.a | (uintptr_t)(a.b ? a.b : a.a)) % 16 == 0;
+    uint32_t i = lo;
+    if (v4) {
+        const uint32_t hv = lo + (hi - lo) / 4 * 4;
+        for (uint32_t q = lo / 4 + threadIdx.x; q < hv / 4; q += ACS_BLOCK) {
+            const float4 x = reinterpret_cast<const float4 *>(a.a)[q];
+            float4 y = a.b ? reinterpret_cast<const float4 *>(a.b)[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            float4 r;
+            if (a.b) {
+                r.x = relu(x.x + y.x);
+                r.y = relu(x.y + y.y);
+                r.z = relu(x.z + y.z);
+                r.w = relu(x.w + y.w);
+            } else {
+                r.x = relu(x.x);
+                r.y = relu(x.y);
+                r.z = relu(x.z);
+                r.w = relu(x.w);
+            }
+            reinterpret_cast<float4 *>(a.out)[q] = r;
+        }
+        i = hv;
+    }
     if (a.b) {
-        for (uint32_t i = lo + threadIdx.x; i < hi; i += ACS_BLOCK) a.out[i] = relu(a.a[i] + a.b[i]);
+        for (uint32_t e = i + threadIdx.x; e < hi; e += ACS_BLOCK) a.out[e] = relu(a.a[e] + a.b[e]);
     } else {
-        for (uint32_t i = lo + threadIdx.x; i < hi; i += ACS_BLOCK) a.out[i] = relu(a.a[i]);
+        for (uint32_t e = i + threadIdx.x; e < hi; e += ACS_BLOCK) a.out[e] = relu(a.a[e]);
     }
 }
 
-// one thread per channel; pixel order, FP32
+// one thread per channel; pixel order, FP32.  The loads of a block of 16
+// pixels are issued before its additions, which stay in pixel order.
 __device__ inline void body_avgpool(const acs_args_avgpool &a)
 {
     for (int32_t c = threadIdx.x; c < a.c; c += ACS_BLOCK) {
         float acc = 0.0f;
-        for (int32_t q = 0; q < a.hw; q++) acc += a.in[(int64_t)q * a.c + c];
+        int32_t q = 0;
+        for (; q + 16 <= a.hw; q += 16) {
+            float v[16];
+#pragma unroll
+            for (int u = 0; u < 16; u++) v[u] = a.in[(int64_t)(q + u) * a.c + c];
+#pragma unroll
+            for (int u = 0; u < 16; u++) acc += v[u];
+        }
+        for (; q < a.hw; q++) acc += a.in[(int64_t)q * a.c + c];
         a.out[c] = acc / (float)a.hw;
     }
 }
 
-// one thread per output; fmaf chain in input order (a GEMV: no matrix unit)
+// one thread per output; fmaf chain in input order (a GEMV: no matrix unit),
+// loads of 16 inputs issued ahead of their part of the chain
 __device__ inline void body_fc(const acs_args_fc &a)
 {
     for (int32_t j = threadIdx.x; j < a.cout; j += ACS_BLOCK) {
         float acc = a.bias[j];
-        for (int32_t i = 0; i < a.cin; i++) acc = fmaf(a.in[i], a.w[(int64_t)i * a.cout + j], acc);
+        int32_t i = 0;
+        for (; i + 16 <= a.cin; i += 16) {
+            float x[16], w[16];
+#pragma unroll
+            for (int u = 0; u < 16; u++) {
+                x[u] = a.in[i + u];
+                w[u] = a.w[(int64_t)(i + u) * a.cout + j];
+            }
+#pragma unroll
+            for (int u = 0; u < 16; u++) acc = fmaf(x[u], w[u], acc);
+        }
+        for (; i < a.cin; i++) acc = fmaf(a.in[i], a.w[(int64_t)i * a.cout + j], acc);
         a.out[j] = acc;
     }
 }

@@ -29,7 +29,7 @@ struct DevDesc {
     uint8_t args[ACS_ARGS_MAX];
     // scheduler-owned part (the host leaves it zero)
     uint64_t wait_mask;     // window slots still running when the kernel was dispatched
-    uint32_t ptarget;       // cnt[slot] after this kernel's last piece (npieces > 1)
+    uint32_t ptarget;       // cnt[slot] after this kernel's last piece (npieces > 1; 64 per piece)
     uint32_t pad0;
     // host-check mode: bit d set when the host found the kernel submitted
     // d + 1 places earlier in conflict with this one (read by the window wave
@@ -84,9 +84,9 @@ constexpr uint32_t kSentinelSlot = 0xFF;
 
 // Device-resident scheduler state (device memory).
 struct DevState {
-    uint64_t deq;                 // work-queue tickets taken by workers
+    uint64_t deq;                 // work-queue tickets taken by workers, 64 per ticket
     uint64_t pad0[31];
-    uint32_t cnt[ACS_W_MAX];      // per-slot piece counters (monotonic, multi-piece kernels only)
+    uint32_t cnt[ACS_W_MAX];      // per-slot piece counters, 64 per piece (monotonic, multi-piece kernels only)
     uint64_t pad1[32];
     uint32_t done[ACS_W_MAX];     // per-slot completion words: seq + 1 of the last kernel finished
     uint64_t pad2[32];

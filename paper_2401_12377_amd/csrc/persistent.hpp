@@ -35,6 +35,7 @@
 
 namespace acs {
 
+constexpr uint32_t kWave = 64;        // lanes of a wavefront
 constexpr uint32_t kLdsDescs = 128;   // descriptors staged in LDS (32 KB), split evenly between groups
 constexpr uint32_t kAdmitBatch = 16;  // insertion passes per loop (measured: admitting fewer
                                       // while few kernels are out costs more in extra
@@ -375,7 +376,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                         myseq = seq;
                         mykid = kid;
                         mynp = np;
-                        if (np > 1) target += np;
+                        if (np > 1) target += kWave * np;
                         p.st->task[slot].ptarget = target;
                     }
                     const uint64_t rbit = bit * repmul;
@@ -474,7 +475,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                         mykid = d->kid;
                         const uint32_t npr = d->npieces;
                         mynp = npr < kMaxPieces ? npr : kMaxPieces;
-                        if (mynp > 1) target += mynp;
+                        if (mynp > 1) target += kWave * mynp;
                         p.st->task[lane].ptarget = target;
                         if (tr && myseq < p.trace_cap) {
                             acs_trace_rec *r = &p.trace[myseq];
@@ -596,12 +597,23 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                 }
                 total += npl;
             }
-            if (mine) {
-                for (uint32_t q = 0; q < mynp; q++) {
-                    const uint64_t t = pub + before + q;
-                    const uint64_t v = ((uint64_t)(uint32_t)(t + 1) << 32) | ((uint64_t)lane << 24) | q;
+            // a kernel of one piece: its own lane writes the entry (one store
+            // for all of them); a kernel of several: the whole wave does
+            if (mine && mynp == 1) {
+                const uint64_t t = pub + before;
+                const uint64_t v = ((uint64_t)(uint32_t)(t + 1) << 32) | ((uint64_t)lane << 24);
+                __hip_atomic_store(&p.st->ent[t & (kQueueCap - 1)], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            for (uint64_t m = __ballot(mine && mynp > 1); m; m &= m - 1) {
+                const int l = __builtin_ctzll(m);
+                const uint32_t bl = readlane32(before, l), nl = readlane32(mynp, l);
+                for (uint32_t q = lane; q < nl; q += kWave) {
+                    const uint64_t t = pub + bl + q;
+                    const uint64_t v = ((uint64_t)(uint32_t)(t + 1) << 32) | ((uint64_t)(uint32_t)l << 24) | q;
                     __hip_atomic_store(&p.st->ent[t & (kQueueCap - 1)], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
+            }
+            if (mine) {
                 if (tr && myseq < p.trace_cap) {
                     p.trace[myseq].ev_dispatch = (int64_t)(ev + rank);
                     p.trace[myseq].t_dispatch = (int64_t)wall_clock64();
@@ -704,8 +716,11 @@ __device__ inline void worker(const DevParams &p, uint8_t *smem, Mail *mail)
     uint64_t *margs = reinterpret_cast<uint64_t *>(mail->args);
     for (;;) {
         if (wave0) {
-            const uint64_t t = uni64(__hip_atomic_fetch_add(&p.st->deq, lane == 0 ? 1ull : 0ull, __ATOMIC_RELAXED,
-                                                            __HIP_MEMORY_SCOPE_AGENT));
+            // every lane adds 1, so one ticket is kWave counts of deq: with a
+            // value the same on all lanes the compiler issues one atomic and
+            // a popcount, where a per-lane value costs a loop over the lanes
+            const uint64_t t = uni64(__hip_atomic_fetch_add(&p.st->deq, 1ull, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT)) / kWave;
             const uint32_t tag = (uint32_t)(t + 1);
             uint64_t v;
             for (uint32_t spin = 1;; spin++) {
@@ -781,9 +796,10 @@ __device__ inline void worker(const DevParams &p, uint8_t *smem, Mail *mail)
             const uint32_t np = uni32(mail->np);
             bool last = true;
             if (np > 1) {
-                const uint32_t old = uni32(__hip_atomic_fetch_add(&p.st->cnt[slot], lane == 0 ? 1u : 0u, __ATOMIC_ACQ_REL,
+                // every lane adds 1: a piece counts kWave (see the ticket above)
+                const uint32_t old = uni32(__hip_atomic_fetch_add(&p.st->cnt[slot], 1u, __ATOMIC_ACQ_REL,
                                                                   __HIP_MEMORY_SCOPE_AGENT));
-                last = old + 1u == uni32(mail->ptarget);
+                last = old + kWave == uni32(mail->ptarget);
             }
             if (last)
                 __hip_atomic_store(&p.st->done[slot], (uint32_t)(seq + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);

@@ -43,6 +43,7 @@ struct Dim {
 struct Wave {
     std::barrier<> bar{64};
     uint64_t vals[64];
+    uint64_t base;
 };
 struct Group {
     std::barrier<> *bar;
@@ -58,7 +59,14 @@ extern thread_local Group *group;
 
 #define __hip_atomic_load(p, order, scope) __atomic_load_n((p), __ATOMIC_SEQ_CST)
 #define __hip_atomic_store(p, v, order, scope) __atomic_store_n((p), (v), __ATOMIC_SEQ_CST)
-#define __hip_atomic_fetch_add(p, v, order, scope) __atomic_fetch_add((p), (v), __ATOMIC_SEQ_CST)
+// An atomic add by a whole wave is one read-modify-write of the sum of the
+// lanes' values, each lane receiving the old value plus the values of the
+// lanes below it (what the device compiler emits for an atomic with a
+// wave-uniform address).  A rendezvous of the 64 lanes: only for calls made
+// by the whole wave, as the kernel source's are.
+template <typename T, typename V>
+inline T acs_sim_wave_fetch_add(T *p, V v);
+#define __hip_atomic_fetch_add(p, v, order, scope) acs_sim_wave_fetch_add((p), (v))
 
 inline void __builtin_amdgcn_fence(int, const char *) { std::atomic_thread_fence(std::memory_order_seq_cst); }
 inline void __builtin_amdgcn_s_sleep(int) { std::this_thread::yield(); }
@@ -100,6 +108,25 @@ inline uint64_t __ballot(int pred)
 }
 
 inline uint64_t __builtin_amdgcn_ballot_w64(bool pred) { return __ballot(pred ? 1 : 0); }
+
+template <typename T, typename V>
+inline T acs_sim_wave_fetch_add(T *p, V v)
+{
+    acs_sim::Wave &w = acs_sim::group->waves[acs_sim::tid / 64];
+    const uint32_t lane = acs_sim::tid % 64;
+    w.vals[lane] = (uint64_t)(T)v;
+    w.bar.arrive_and_wait();
+    if (lane == 0) {
+        T sum = 0;
+        for (int l = 0; l < 64; l++) sum = (T)(sum + (T)w.vals[l]);
+        w.base = (uint64_t)__atomic_fetch_add(p, sum, __ATOMIC_SEQ_CST);
+    }
+    w.bar.arrive_and_wait();
+    T r = (T)w.base;
+    for (uint32_t l = 0; l < lane; l++) r = (T)(r + (T)w.vals[l]);
+    w.bar.arrive_and_wait();
+    return r;
+}
 
 // int result, as the device built-in: a caller that widens it without a cast
 // sign-extends, exactly as on the GPU

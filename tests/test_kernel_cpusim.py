@@ -306,3 +306,43 @@ def test_host_check_gate_holds_back_past_a_long_kernel(sim):
     assert tr["t_start"][n - 1] >= tr["t_end"][0]
     # kernels M + 1 places after the long one were inserted only once it had left
     assert np.all(tr["ev_insert"][M + 1:] > tr["ev_retire"][0])
+
+
+@pytest.mark.timeout(300, method="thread")
+def test_join_pool_fc_bodies_through_kernel_source(sim):
+    """The elementwise join (vector and scalar tails, several pieces), the
+    average pool and the head with lengths that are not multiples of their
+    16-wide load blocks: bit-identical to the oracle."""
+    g = np.random.default_rng(3)
+    n = 2048 * 3 + 7
+    a, b = g.uniform(-1, 1, n).astype(np.float32), g.uniform(-1, 1, n).astype(np.float32)
+    o1, o2 = np.full(n, np.nan, np.float32), np.full(n, np.nan, np.float32)
+    hw, c = 20, 40
+    x = g.uniform(-1, 1, (hw, c)).astype(np.float32)
+    pool = np.full(c, np.nan, np.float32)
+    w, bias = g.uniform(-1, 1, (c, 10)).astype(np.float32), g.uniform(-1, 1, 10).astype(np.float32)
+    out = np.full(10, np.nan, np.float32)
+    specs = [(acs.K_JOIN, acs.ArgsJoin(o1.ctypes.data, a.ctypes.data, b.ctypes.data, n), 4, [o1]),
+             (acs.K_JOIN, acs.ArgsJoin(o2.ctypes.data, a.ctypes.data, 0, n), 4, [o2]),
+             (acs.K_AVGPOOL, acs.ArgsAvgpool(pool.ctypes.data, x.ctypes.data, hw, c), 1, [pool]),
+             (acs.K_FC, acs.ArgsFC(out.ctypes.data, pool.ctypes.data, w.ctypes.data, bias.ctypes.data, c, 10), 1,
+              [out])]
+    descs = (SimDesc * len(specs))()
+    for i, (kid, args, np_, writes) in enumerate(specs):
+        d = descs[i]
+        d.kid, d.npieces = kid, np_
+        # the head reads the pool: give both the pool's range so they stay ordered
+        rng = [(int(pool.ctypes.data), int(pool.ctypes.data) + pool.nbytes)] if kid in (acs.K_AVGPOOL, acs.K_FC) else []
+        segs = rng + [(int(t.ctypes.data), int(t.ctypes.data) + t.nbytes) for t in writes]
+        d.nseg = len(segs)
+        d.wbits = (1 << len(segs)) - 1
+        for j, (s0, e0) in enumerate(segs):
+            d.s[j], d.e[j] = s0, e0
+        C.memmove(d.args, bytes(args), C.sizeof(args))
+    retired = C.c_uint64()
+    assert sim.sim_run(4, 2, len(specs), descs, 8, None, 120.0, C.byref(retired)) == 0
+    assert retired.value == len(specs)
+    assert np.array_equal(o1.view(np.uint32), O.join(a, b).view(np.uint32))
+    assert np.array_equal(o2.view(np.uint32), O.join(a).view(np.uint32))
+    assert np.array_equal(pool.view(np.uint32), O.avgpool(x.reshape(hw, 1, c)).view(np.uint32))
+    assert np.array_equal(out.view(np.uint32), O.fc(O.avgpool(x.reshape(hw, 1, c)), w, bias).view(np.uint32))
