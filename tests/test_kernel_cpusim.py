@@ -42,11 +42,15 @@ def sim():
     if not os.path.exists(cxx):
         pytest.skip("clang++ (for the vector types of the kernel source) not available")
     os.makedirs(os.path.dirname(OUT), exist_ok=True)
+    # built under a private name and moved into place, so that parallel test
+    # processes never load a half-written library
+    tmp = f"{OUT}.{os.getpid()}"
     cmd = [cxx, "-std=c++20", "-O1", "-pthread", "-fPIC", "-shared",
            "-I", SIM_DIR, "-I", os.path.join(ROOT, "include"),
            "-I", os.path.join(ROOT, "paper_2401_12377_amd", "csrc"),
-           os.path.join(SIM_DIR, "sim.cpp"), "-o", OUT]
+           os.path.join(SIM_DIR, "sim.cpp"), "-o", tmp]
     subprocess.run(cmd, check=True, capture_output=True, timeout=300)
+    os.replace(tmp, OUT)
     lib = C.CDLL(OUT)
     lib.sim_run.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_uint32, C.c_void_p,
                             C.c_double, C.POINTER(C.c_uint64)]
