@@ -179,7 +179,7 @@ def batched_section(acs, inputs, torch, args):
         gpu = [acs.RLSceneGPU(sc) for sc in scenes]
         torch.cuda.synchronize()
         with acs.Window(cfg["W"], path=path, n_groups=cfg["n_groups"], wg_per_task=cfg["wg_per_task"],
-                        queue_depth=cfg["queue_depth"]) as w:
+                        queue_depth=cfg["queue_depth"], host_check_depth=cfg.get("host_check_depth", 0)) as w:
             t0 = time.perf_counter()
             counts, step_ns = acs.rl_run_batch(w, gpu, args.batch_steps, n_groups=cfg["n_groups"])
             dt = time.perf_counter() - t0
@@ -232,30 +232,10 @@ def dnn_section(acs, inputs, torch, args):
         out[path] = {"latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
                      "kernels_per_s": k2 / dt, "inferences_per_s": len(seeds) / dt}
         log(f"[bench] dnn {path}: p50 {out[path]['latency_ms']['p50']:.3f} ms, {len(seeds) / dt:.0f} inferences/s")
-    # a DAG framework on the dynamic graph: each input's graph recorded,
-    # built, run and destroyed (construction included)
-    net = acs.DNNGPU(wts, inputs.DNN_CELLS, inputs.DNN_CLASSES)
-    lat, build = [], []
-    with acs.Window(16, path="inorder") as w:
-        for sd in seeds:
-            inp = inputs.dnn_input(sd)
-            net.set_input(inp.x)
-            t0 = time.perf_counter()
-            w.graph_begin()
-            acs.dnn_submit(w, net, inp.logits)
-            g = w.graph_end()
-            t1 = time.perf_counter()
-            g.launch()
-            g.sync()
-            g.destroy()
-            lat.append(time.perf_counter() - t0)
-            build.append(t1 - t0)
-    lat_s, build = np.array(lat[2:]), np.array(build[2:])
-    lat = lat_s * 1e3
-    out["graph_per_input"] = {"latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-                              "inferences_per_s": 1.0 / float(lat_s.mean()),
-                              "build_fraction": float(build.sum() / lat_s.sum())}
-    log(f"[bench] dnn graph_per_input: p50 {out['graph_per_input']['latency_ms']['p50']:.3f} ms")
+    # The graph rebuilt for every input is not measured here: the rebuild
+    # loop's process has ended with a host-side segmentation fault (see the
+    # --paths option) and no cause has been found in this code.
+    out["graph_per_input"] = None
     # steady state: the network with every branch on (a static graph),
     # recorded once and replayed as a HIP graph, against the window paths
     import numpy as np
@@ -313,16 +293,17 @@ def serve_section(acs, inputs, torch, args):
     net = acs.DNNGPU(inputs.dnn_weights(), inputs.DNN_CELLS, inputs.DNN_CLASSES)
     pool = torch.empty(args.serve_pool_mib << 20, dtype=torch.uint8, device="cuda")
     host = acs.serve_host(args.serve_resident)
-    configs = [("device", 32, 1), ("device", 16, 4), ("device", 8, 8), ("inorder", 8, 1)]
+    configs = [("device", 32, 1, 0), ("device", 32, 1, 32), ("device", 16, 4, 0), ("device", 8, 8, 0),
+               ("inorder", 8, 1, 0)]
     table = {}
     outputs = {}
-    for path, W, G in configs:
-        key = f"{path}_W{W}_G{G}" if path == "device" else path
+    for path, W, G, hc in configs:
+        key = (f"{path}_W{W}_G{G}" + ("_hostcheck" if hc else "")) if path == "device" else path
         rows = []
         for lam in rates:
             specs = inputs.serve_requests(seed=4, rate_per_s=lam, n_requests=n)
             sset = acs.ServeSet(specs, rl, dnn, inputs.DNN_CLASSES)
-            with acs.Window(W, path=path, n_groups=G) as w:
+            with acs.Window(W, path=path, n_groups=G, host_check_depth=hc) as w:
                 res, st = acs.serve_run(w, sset, pool, host, max_resident=args.serve_resident, model=net,
                                         stall_ns=60 * 10 ** 9)
             lat = np.array([r["done_ns"] - s.arrival_ns for r, s in zip(res, specs)]) / 1e6
@@ -430,7 +411,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
-    ap.add_argument("--paths", default="device,device_hostcheck,inorder,plain,events,graph_per_input")
+    # graph_per_input (each step's graph rebuilt, run and destroyed) is not in
+    # the default set: its process has ended with a host-side segmentation
+    # fault inside that loop in two runs (no GPU fault reported; other runs of
+    # the same loop completed) and no cause has been found in this code
+    ap.add_argument("--paths", default="device,device_hostcheck,inorder,plain,events")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-scenes section")
     ap.add_argument("--batch-scenes", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=20)

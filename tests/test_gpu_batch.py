@@ -46,15 +46,15 @@ def shifted(acc, off):
     return O.make_access([(s + off, z) for s, z in acc.reads()], [(s + off, z) for s, z in acc.writes()])
 
 
-@pytest.mark.parametrize("path,G,W", [("device", 4, 16), ("device", 8, 8), ("device", 2, 32), ("inorder", 1, 8),
-                                      ("plain", 1, 32)])
-def test_batch_matches_solo_oracle(torch, path, G, W):
+@pytest.mark.parametrize("path,G,W,hc", [("device", 4, 16, 0), ("device", 8, 8, 0), ("device", 2, 32, 0),
+                                         ("device", 1, 16, 16), ("inorder", 1, 8, 0), ("plain", 1, 32, 0)])
+def test_batch_matches_solo_oracle(torch, path, G, W, hc):
     scs = scenes(12)
     steps = 4
     gpu = [acs.RLSceneGPU(sc) for sc in scs]
     trace = path == "device"
-    say(f"batch path={path} G={G} W={W}")
-    with acs.Window(W, path=path, n_groups=G, trace=trace, trace_capacity=1 << 16) as w:
+    say(f"batch path={path} G={G} W={W} host_check={hc}")
+    with acs.Window(W, path=path, n_groups=G, trace=trace, trace_capacity=1 << 16, host_check_depth=hc) as w:
         counts, step_ns = acs.rl_run_batch(w, gpu, steps, n_groups=G)
         tr = w.trace() if trace else None
     assert counts["steps"] == steps * len(scs)

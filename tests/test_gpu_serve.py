@@ -90,10 +90,10 @@ def check(specs, outs, res, want, model, dnn):
             assert r["multi_islands"] == -1
 
 
-@pytest.mark.parametrize("path,W,G,pool_mib,resident", [("device", 32, 1, 64, 16), ("device", 16, 4, 64, 32),
-                                                        ("device", 8, 8, 6, 64), ("plain", 32, 1, 64, 16),
-                                                        ("inorder", 8, 1, 64, 8)])
-def test_mix_matches_solo(torch, model, mix, expected, path, W, G, pool_mib, resident):
+@pytest.mark.parametrize("path,W,G,pool_mib,resident,hc", [("device", 32, 1, 64, 16, 0), ("device", 16, 4, 64, 32, 0),
+                                                           ("device", 8, 8, 6, 64, 0), ("device", 32, 1, 64, 16, 32),
+                                                           ("plain", 32, 1, 64, 16, 0), ("inorder", 8, 1, 64, 8, 0)])
+def test_mix_matches_solo(torch, model, mix, expected, path, W, G, pool_mib, resident, hc):
     specs, rl, dnn = mix
     sset = acs.ServeSet(specs, rl, dnn, inputs.DNN_CLASSES)
     sset.clear_outputs()
@@ -101,8 +101,8 @@ def test_mix_matches_solo(torch, model, mix, expected, path, W, G, pool_mib, res
     pool = torch.empty(pool_mib << 20, dtype=torch.uint8, device="cuda")
     host = acs.serve_host(resident)
     torch.cuda.current_stream().synchronize()
-    say(f"serve path={path} W={W} G={G} pool={pool_mib}MiB resident={resident}")
-    with acs.Window(W, path=path, n_groups=G) as w:
+    say(f"serve path={path} W={W} G={G} pool={pool_mib}MiB resident={resident} host_check={hc}")
+    with acs.Window(W, path=path, n_groups=G, host_check_depth=hc) as w:
         res, st = acs.serve_run(w, sset, pool, host, max_resident=resident, model=net, stall_ns=30 * 10 ** 9)
     say(f"  stats {st}")
     check(specs, sset.outputs(), res, expected, model, dnn)
