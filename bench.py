@@ -37,9 +37,9 @@ HBM_PEAK_GBS = 8000.0
 # dispatch) scaled by the same counters' reading on a device-to-device copy of
 # known size (--copy-calibration).  Valid only for the kernel sources whose
 # digest is recorded: any change to them makes the figure stale (null).
-TRAFFIC = {"digest": "c186e58b34c1fea2", "workload": (64, 200, 32, 1),
-           "fetch_kib": 12847.5625, "write_kib": 7893.25,
-           "copy_bytes": 268435456, "copy_fetch_kib": 131085.354, "copy_write_kib": 262144.0}
+TRAFFIC = {"digest": "60f973d8ae6e89b3", "workload": (64, 200, 32, 1),
+           "fetch_kib": 12658.125, "write_kib": 7891.84375,
+           "copy_bytes": 268435456, "copy_fetch_kib": 131085.25, "copy_write_kib": 262144.0}
 KERNEL_SOURCES = ["kernels.hip", "persistent.hpp", "bodies.hpp", "dev_shared.hpp"]
 
 
@@ -160,7 +160,17 @@ def cpu_baseline(inputs, args):
             kernels += 5 + s.c.iters * s.n_multi
         episodes += 1
     dt = time.perf_counter() - t0
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": kernels / dt, "unit": "kernels/s", "cores": 1, "kind": "oracle",
+            "host": f"{os.cpu_count()} logical CPUs visible, {model}",
             "sample": f"{episodes} episodes of {args.physics_steps} steps x {args.bodies} spheres "
                       f"({kernels} kernels, {dt:.1f} s, single thread, program order)"}
 
