@@ -28,6 +28,53 @@ __device__ inline void piece_range(uint32_t n, uint32_t piece, uint32_t np, uint
     if (lo > n) lo = n;
 }
 
+// Stores of task results.  A standalone kernel stores them plainly: the
+// end of the kernel makes them visible to whatever runs next.  Inside the
+// persistent kernel (DEV) a piece's results must be visible, as soon as the
+// piece is counted, to pieces of other kernels, which may run on another
+// XCD with its own L2.  They are stored with device scope, which writes them
+// through the L2 of the storing XCD, so that counting a piece only waits for
+// its own stores instead of writing back that whole L2.  Host memory (the
+// island plan) is stored with system scope.  The device-scope stores are
+// integer stores of the same bits (a 16-byte value as two 8-byte halves).
+template <bool DEV>
+__device__ __forceinline__ void put(int32_t *p, int32_t v)
+{
+    if constexpr (DEV) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+}
+
+template <bool DEV>
+__device__ __forceinline__ void put(float *p, float v)
+{
+    if constexpr (DEV)
+        __hip_atomic_store(reinterpret_cast<uint32_t *>(p), (uint32_t)__float_as_uint(v), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+}
+
+template <bool DEV, typename V16>
+__device__ __forceinline__ void put16(V16 *p, const V16 &v)
+{
+    static_assert(sizeof(V16) == 16, "16-byte value");
+    if constexpr (DEV) {
+        uint64_t h[2];
+        __builtin_memcpy(h, &v, 16);
+        uint64_t *q = reinterpret_cast<uint64_t *>(p);
+        __hip_atomic_store(q, h[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(q + 1, h[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        *p = v;
+    }
+}
+
+template <bool DEV>
+__device__ __forceinline__ void put_host(int32_t *p, int32_t v)
+{
+    if constexpr (DEV) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    else *p = v;
+}
+
 // ---------------------------------------------------------------------------
 // no-op with an optional busy wait on the constant wall clock
 // ---------------------------------------------------------------------------
@@ -44,18 +91,20 @@ __device__ inline void body_nop(const acs_args_nop &a)
 // ---------------------------------------------------------------------------
 // tiny random stream
 // ---------------------------------------------------------------------------
+template <bool DEV>
 __device__ inline void body_scale(const acs_args_scale &a, uint32_t piece, uint32_t np)
 {
     uint32_t lo, hi;
     piece_range(a.n, piece, np, lo, hi);
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += ACS_BLOCK) a.out[i] = a.a * a.x[i];
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += ACS_BLOCK) put<DEV>(&a.out[i], a.a * a.x[i]);
 }
 
+template <bool DEV>
 __device__ inline void body_axpy(const acs_args_axpy &a, uint32_t piece, uint32_t np)
 {
     uint32_t lo, hi;
     piece_range(a.n, piece, np, lo, hi);
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += ACS_BLOCK) a.out[i] = fmaf(a.a, a.x[i], a.y[i]);
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += ACS_BLOCK) put<DEV>(&a.out[i], fmaf(a.a, a.x[i], a.y[i]));
 }
 
 __device__ inline float sum_leaf(const acs_args_sum &a, uint32_t g)
@@ -75,6 +124,7 @@ constexpr uint32_t kSumMax = 256 * 64;
 // For the levels s >= 256 the pairs (i, i+s) share i mod 256, so thread t runs
 // those levels in registers over its leaves t + 256m; the last eight levels
 // run across threads in LDS.  Same additions, same order, as the definition.
+template <bool DEV>
 __device__ inline void body_sum(const acs_args_sum &a, float *red)
 {
     const uint32_t t = threadIdx.x;
@@ -105,7 +155,7 @@ __device__ inline void body_sum(const acs_args_sum &a, float *red)
         if (t < s) red[t] = red[t] + red[t + s];
         __syncthreads();
     }
-    if (t == 0) *a.out = red[0];
+    if (t == 0) put<DEV>(a.out, red[0]);
 }
 
 // ---------------------------------------------------------------------------
@@ -201,6 +251,7 @@ __device__ inline int32_t wave_exclusive_scan(int32_t x, int32_t *total)
     return inc - x;
 }
 
+template <bool DEV>
 __device__ inline void body_rl_predict(const acs_args_rl &a, uint32_t piece, uint32_t np)
 {
     RLView v = rl_view(a.base, a.n);
@@ -212,7 +263,7 @@ __device__ inline void body_rl_predict(const acs_args_rl &a, uint32_t piece, uin
         p.y = fmaf(a.dt, u.y, x.y);
         p.z = fmaf(a.dt, u.z, x.z);
         p.w = fmaf(a.dt, u.w, x.w);
-        v.P[i] = p;
+        put16<DEV>(&v.P[i], p);
     }
 }
 
@@ -226,6 +277,7 @@ __device__ inline void body_rl_predict(const acs_args_rl &a, uint32_t piece, uin
 // contact test is body j's neighbour set (the test is symmetric bit for bit:
 // the differences only change sign).  Wave 0 then writes degrees, offsets and
 // the adjacency in ascending partner order.
+template <bool DEV>
 __device__ inline void broadphase_small(const acs_args_rl &a, const RLView &v, uint8_t *smem)
 {
     const int32_t n = a.n, lane = threadIdx.x & 63, wv = wave_index();
@@ -246,20 +298,21 @@ __device__ inline void broadphase_small(const acs_args_rl &a, const RLView &v, u
     int32_t total;
     const int32_t off = wave_exclusive_scan(deg, &total);
     if (in) {
-        v.deg[lane] = deg;
-        v.adj_off[lane] = off;
+        put<DEV>(&v.deg[lane], deg);
+        put<DEV>(&v.adj_off[lane], off);
     }
-    if (lane == 0) v.adj_off[n] = total;
+    if (lane == 0) put<DEV>(&v.adj_off[n], total);
     int32_t k = off;
-    for (uint64_t m = mine; m; m &= m - 1) v.adj[k++] = __builtin_ctzll(m);
+    for (uint64_t m = mine; m; m &= m - 1) put<DEV>(&v.adj[k++], (int32_t)__builtin_ctzll(m));
 }
 
+template <bool DEV>
 __device__ inline void body_rl_broadphase(const acs_args_rl &a, uint8_t *smem)
 {
     const int32_t n = a.n, t = threadIdx.x;
     RLView v = rl_view(a.base, n);
     if (n <= 64) {
-        broadphase_small(a, v, smem);
+        broadphase_small<DEV>(a, v, smem);
         return;
     }
     float4 *Ps = reinterpret_cast<float4 *>(smem);                 // 16 n bytes
@@ -289,7 +342,7 @@ __device__ inline void body_rl_broadphase(const acs_args_rl &a, uint8_t *smem)
             int32_t d = 0;
             for (int32_t q2 = 0; q2 < Q; q2++) d += cnt[q2 * n + b];
             deg[b] = d;
-            v.deg[b] = d;
+            put<DEV>(&v.deg[b], d);
         }
         __syncthreads();
         const int32_t total = block_exclusive_scan(deg, n, tmp);
@@ -297,14 +350,14 @@ __device__ inline void body_rl_broadphase(const acs_args_rl &a, uint8_t *smem)
             const float4 pi = Ps[i];
             int32_t k = deg[i];
             for (int32_t q2 = 0; q2 < q; q2++) k += cnt[q2 * n + i];
-            if (q == 0) v.adj_off[i] = deg[i];
+            if (q == 0) put<DEV>(&v.adj_off[i], deg[i]);
             const int32_t j0 = q * chunk, j1 = j0 + chunk < n ? j0 + chunk : n;
             for (int32_t j = j0; j < j1; j++) {
                 const float4 pj = Ps[j];
-                if (j != i && dist2(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z) < thr) v.adj[k++] = j;
+                if (j != i && dist2(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z) < thr) put<DEV>(&v.adj[k++], j);
             }
         }
-        if (t == 0) v.adj_off[n] = total;
+        if (t == 0) put<DEV>(&v.adj_off[n], total);
         return;
     }
     for (int32_t i = t; i < n; i += ACS_BLOCK) {
@@ -315,20 +368,20 @@ __device__ inline void body_rl_broadphase(const acs_args_rl &a, uint8_t *smem)
             c += (j != i && dist2(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z) < thr) ? 1 : 0;
         }
         deg[i] = c;
-        v.deg[i] = c;
+        put<DEV>(&v.deg[i], c);
     }
     __syncthreads();
     const int32_t total = block_exclusive_scan(deg, n, tmp);
     for (int32_t i = t; i < n; i += ACS_BLOCK) {
-        v.adj_off[i] = deg[i];
+        put<DEV>(&v.adj_off[i], deg[i]);
         const float4 pi = Ps[i];
         int32_t k = deg[i];
         for (int32_t j = 0; j < n; j++) {
             const float4 pj = Ps[j];
-            if (j != i && dist2(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z) < thr) v.adj[k++] = j;
+            if (j != i && dist2(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z) < thr) put<DEV>(&v.adj[k++], j);
         }
     }
-    if (t == 0) v.adj_off[n] = total;
+    if (t == 0) put<DEV>(&v.adj_off[n], total);
 }
 
 // Connected components by min-label propagation (the fixpoint labels every
@@ -340,6 +393,7 @@ __device__ inline void body_rl_broadphase(const acs_args_rl &a, uint8_t *smem)
 // lanes update in parallel), each body's island is its closure and its label
 // the closure's smallest body.  Positions: islands in label order, bodies in
 // index order inside an island.
+template <bool DEV>
 __device__ inline void islands_small(const acs_args_rl &a, const RLView &v, int32_t *plan, uint8_t *smem)
 {
     if (wave_index() != 0) return;
@@ -380,14 +434,14 @@ __device__ inline void islands_small(const acs_args_rl &a, const RLView &v, int3
     const int32_t pos = start + __builtin_popcountll(reach & below);
     const int32_t ridx = __builtin_popcountll(roots & ((1ull << root) - 1ull));
     if (in) {
-        v.label[lane] = root;
-        v.perm[pos] = lane;
-        v.inv_perm[lane] = pos;
+        put<DEV>(&v.label[lane], root);
+        put<DEV>(&v.perm[pos], lane);
+        put<DEV>(&v.inv_perm[lane], pos);
         s_perm[pos] = lane;
         s_inv[lane] = pos;
     }
-    if (isroot) v.isl_off[ridx] = start;
-    if (lane == 0) v.isl_off[nisl] = n;
+    if (isroot) put<DEV>(&v.isl_off[ridx], start);
+    if (lane == 0) put<DEV>(&v.isl_off[nisl], n);
     // the stores above land before the loads below (one wave, LDS in order)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -397,11 +451,11 @@ __device__ inline void islands_small(const acs_args_rl &a, const RLView &v, int3
     const int32_t ob = __shfl(o0, b, 64);
     int32_t ep;
     const int32_t poff = wave_exclusive_scan(in ? db : 0, &ep);
-    if (in) v.padj_off[lane] = poff;
-    if (lane == 0) v.padj_off[n] = ep;
+    if (in) put<DEV>(&v.padj_off[lane], poff);
+    if (lane == 0) put<DEV>(&v.padj_off[n], ep);
     for (int32_t k = 0; in && k < db; k++) {
         const int32_t c = v.adj[ob + k];
-        if (poff + k < cap) v.padj[poff + k] = ((uint32_t)c < (uint32_t)n) ? s_inv[c] : lane;
+        if (poff + k < cap) put<DEV>(&v.padj[poff + k], ((uint32_t)c < (uint32_t)n) ? s_inv[c] : lane);
     }
     // plan: multi-body islands in label order
     const bool multi = isroot && size >= 2;
@@ -412,26 +466,27 @@ __device__ inline void islands_small(const acs_args_rl &a, const RLView &v, int3
     const int32_t e1 = endp < n ? e1s : ep;
     if (multi) {
         const int32_t m = __builtin_popcountll(multis & below);
-        plan[4 + 4 * m + 0] = start;
-        plan[4 + 4 * m + 1] = endp;
-        plan[4 + 4 * m + 2] = e0;
-        plan[4 + 4 * m + 3] = e1;
+        put_host<DEV>(&plan[4 + 4 * m + 0], start);
+        put_host<DEV>(&plan[4 + 4 * m + 1], endp);
+        put_host<DEV>(&plan[4 + 4 * m + 2], e0);
+        put_host<DEV>(&plan[4 + 4 * m + 3], e1);
     }
     if (lane == 0) {
-        plan[0] = nisl;
-        plan[1] = __builtin_popcountll(multis);
-        plan[2] = ep;
-        plan[3] = 0;
+        put_host<DEV>(&plan[0], nisl);
+        put_host<DEV>(&plan[1], (int32_t)__builtin_popcountll(multis));
+        put_host<DEV>(&plan[2], ep);
+        put_host<DEV>(&plan[3], 0);
     }
 }
 
+template <bool DEV>
 __device__ inline void body_rl_islands(const acs_args_rl &a, uint8_t *smem)
 {
     const int32_t n = a.n, t = threadIdx.x;
     RLView v = rl_view(a.base, n);
     int32_t *plan = reinterpret_cast<int32_t *>(a.plan);
     if (n <= 64) {
-        islands_small(a, v, plan, smem);
+        islands_small<DEV>(a, v, plan, smem);
         return;
     }
     int32_t *lab = reinterpret_cast<int32_t *>(smem);   // n
@@ -492,7 +547,7 @@ __device__ inline void body_rl_islands(const acs_args_rl &a, uint8_t *smem)
     block_exclusive_scan(sz, nisl, tmp);
     if (t == 0) sz[nisl] = n;
     __syncthreads();
-    for (int32_t k = t; k <= nisl; k += ACS_BLOCK) v.isl_off[k] = sz[k];
+    for (int32_t k = t; k <= nisl; k += ACS_BLOCK) put<DEV>(&v.isl_off[k], sz[k]);
     // position of each body: island start + members before it
     for (int32_t i = t; i < n; i += ACS_BLOCK) {
         const int32_t root = lab[i];
@@ -501,9 +556,9 @@ __device__ inline void body_rl_islands(const acs_args_rl &a, uint8_t *smem)
         const int32_t pos = sz[ridx[root]] + rank;
         perm[pos] = i;
         inv[i] = pos;
-        v.label[i] = root;
-        v.perm[pos] = i;
-        v.inv_perm[i] = pos;
+        put<DEV>(&v.label[i], root);
+        put<DEV>(&v.perm[pos], i);
+        put<DEV>(&v.inv_perm[i], pos);
     }
     __syncthreads();
     for (int32_t p = t; p < n; p += ACS_BLOCK) {
@@ -514,12 +569,12 @@ __device__ inline void body_rl_islands(const acs_args_rl &a, uint8_t *smem)
     const int32_t Ep = block_exclusive_scan(poff, n, tmp);
     if (t == 0) poff[n] = Ep;
     __syncthreads();
-    for (int32_t p = t; p <= n; p += ACS_BLOCK) v.padj_off[p] = poff[p];
+    for (int32_t p = t; p <= n; p += ACS_BLOCK) put<DEV>(&v.padj_off[p], poff[p]);
     for (int32_t p = t; p < n; p += ACS_BLOCK) {
         const int32_t b = perm[p], k0 = aoff[b], d = aoff[b + 1] - k0, o = poff[p];
         for (int32_t k = 0; k < d; k++) {
             const int32_t c = A[k0 + k];
-            if (o + k < cap) v.padj[o + k] = ((uint32_t)c < (uint32_t)n) ? inv[c] : p;
+            if (o + k < cap) put<DEV>(&v.padj[o + k], ((uint32_t)c < (uint32_t)n) ? inv[c] : p);
         }
     }
     // plan: multi-body islands in island order (reuse ridx as flags)
@@ -530,20 +585,21 @@ __device__ inline void body_rl_islands(const acs_args_rl &a, uint8_t *smem)
     for (int32_t k = t; k < nisl; k += ACS_BLOCK) {
         if (sz[k + 1] - sz[k] >= 2) {
             const int32_t m = ridx[k];
-            plan[4 + 4 * m + 0] = sz[k];
-            plan[4 + 4 * m + 1] = sz[k + 1];
-            plan[4 + 4 * m + 2] = poff[sz[k]];
-            plan[4 + 4 * m + 3] = poff[sz[k + 1]];
+            put_host<DEV>(&plan[4 + 4 * m + 0], sz[k]);
+            put_host<DEV>(&plan[4 + 4 * m + 1], sz[k + 1]);
+            put_host<DEV>(&plan[4 + 4 * m + 2], poff[sz[k]]);
+            put_host<DEV>(&plan[4 + 4 * m + 3], poff[sz[k + 1]]);
         }
     }
     if (t == 0) {
-        plan[0] = nisl;
-        plan[1] = nmulti;
-        plan[2] = Ep;
-        plan[3] = 0;
+        put_host<DEV>(&plan[0], nisl);
+        put_host<DEV>(&plan[1], nmulti);
+        put_host<DEV>(&plan[2], Ep);
+        put_host<DEV>(&plan[3], 0);
     }
 }
 
+template <bool DEV>
 __device__ inline void body_rl_permute(const acs_args_rl &a, uint32_t piece, uint32_t np)
 {
     RLView v = rl_view(a.base, a.n);
@@ -551,11 +607,12 @@ __device__ inline void body_rl_permute(const acs_args_rl &a, uint32_t piece, uin
     piece_range((uint32_t)a.n, piece, np, lo, hi);
     for (uint32_t p = lo + threadIdx.x; p < hi; p += ACS_BLOCK) {
         const uint32_t b = (uint32_t)v.perm[p];
-        v.Q0[p] = v.P[b < (uint32_t)a.n ? b : p];
+        put16<DEV>(&v.Q0[p], v.P[b < (uint32_t)a.n ? b : p]);
     }
 }
 
 // One Jacobi iteration over the island's positions [b0, b1).
+template <bool DEV>
 __device__ inline void body_rl_jacobi(const acs_args_rl &a)
 {
     RLView v = rl_view(a.base, a.n);
@@ -599,7 +656,7 @@ __device__ inline void body_rl_jacobi(const acs_args_rl &a)
         o.y = qp.y + ay / deg;
         o.z = qp.z + az / deg;
         o.w = qp.w;
-        dst[p] = o;
+        put16<DEV>(&dst[p], o);
     }
 }
 
@@ -616,6 +673,7 @@ __device__ inline float wall(float x, float &vel, float lo, float hi)
     return x;
 }
 
+template <bool DEV>
 __device__ inline void body_rl_integrate(const acs_args_rl &a, uint32_t piece, uint32_t np)
 {
     RLView v = rl_view(a.base, a.n);
@@ -633,8 +691,8 @@ __device__ inline void body_rl_integrate(const acs_args_rl &a, uint32_t piece, u
         x.y = wall(q.y, u.y, wlo, whi);
         x.z = wall(q.z, u.z, wlo, whi);
         x.w = q.w;
-        v.X[i] = x;
-        v.V[i] = u;
+        put16<DEV>(&v.X[i], x);
+        put16<DEV>(&v.V[i], u);
     }
 }
 
@@ -688,6 +746,7 @@ __device__ __forceinline__ void conv_load(const acs_args_conv &a, int32_t py, in
     }
 }
 
+template <bool DEV>
 __device__ inline void conv_tile(const acs_args_conv &a, int32_t m0, int32_t n0, uint8_t *smem)
 {
     const int32_t k = a.k, st = a.stride, pad = (k - 1) / 2, cout = a.cout;
@@ -725,18 +784,19 @@ __device__ inline void conv_tile(const acs_args_conv &a, int32_t m0, int32_t n0,
         v += part[(16 + row) * 32 + col];
         v += part[(32 + row) * 32 + col];
         v += part[(48 + row) * 32 + col];
-        a.out[(int64_t)(m0 + row) * cout + n0 + col] = v + a.bias[n0 + col];
+        put<DEV>(&a.out[(int64_t)(m0 + row) * cout + n0 + col], v + a.bias[n0 + col]);
     }
 }
 
 // Tiles are dealt to pieces round-robin: each output element is computed by
 // one tile in one order, whatever the piece count.
+template <bool DEV>
 __device__ inline void body_conv(const acs_args_conv &a, uint32_t piece, uint32_t np, uint8_t *smem)
 {
     const int32_t pad = (a.k - 1) / 2, hout = (a.hin + 2 * pad - a.k) / a.stride + 1;
     const uint32_t ntn = (uint32_t)a.cout / 32u, ntiles = (uint32_t)(hout * hout / 16) * ntn;
     for (uint32_t tile = piece; tile < ntiles; tile += np) {
-        conv_tile(a, (int32_t)(tile / ntn) * 16, (int32_t)(tile % ntn) * 32, smem);
+        conv_tile<DEV>(a, (int32_t)(tile / ntn) * 16, (int32_t)(tile % ntn) * 32, smem);
         __syncthreads();   // the next tile reuses the partial-tile buffer
     }
 }
@@ -745,6 +805,7 @@ __device__ inline float relu(float x) { return x > 0.0f ? x : 0.0f; }
 
 // Elementwise; 16-byte accesses where the piece and the buffers allow
 // (pieces start on multiples of 256 elements), scalar otherwise.
+template <bool DEV>
 __device__ inline void body_join(const acs_args_join &a, uint32_t piece, uint32_t np)
 {
     uint32_t lo, hi;
@@ -768,19 +829,20 @@ __device__ inline void body_join(const acs_args_join &a, uint32_t piece, uint32_
                 r.z = relu(x.z);
                 r.w = relu(x.w);
             }
-            reinterpret_cast<float4 *>(a.out)[q] = r;
+            put16<DEV>(&reinterpret_cast<float4 *>(a.out)[q], r);
         }
         i = hv;
     }
     if (a.b) {
-        for (uint32_t e = i + threadIdx.x; e < hi; e += ACS_BLOCK) a.out[e] = relu(a.a[e] + a.b[e]);
+        for (uint32_t e = i + threadIdx.x; e < hi; e += ACS_BLOCK) put<DEV>(&a.out[e], relu(a.a[e] + a.b[e]));
     } else {
-        for (uint32_t e = i + threadIdx.x; e < hi; e += ACS_BLOCK) a.out[e] = relu(a.a[e]);
+        for (uint32_t e = i + threadIdx.x; e < hi; e += ACS_BLOCK) put<DEV>(&a.out[e], relu(a.a[e]));
     }
 }
 
 // one thread per channel; pixel order, FP32.  The loads of a block of 16
 // pixels are issued before its additions, which stay in pixel order.
+template <bool DEV>
 __device__ inline void body_avgpool(const acs_args_avgpool &a)
 {
     for (int32_t c = threadIdx.x; c < a.c; c += ACS_BLOCK) {
@@ -794,12 +856,13 @@ __device__ inline void body_avgpool(const acs_args_avgpool &a)
             for (int u = 0; u < 16; u++) acc += v[u];
         }
         for (; q < a.hw; q++) acc += a.in[(int64_t)q * a.c + c];
-        a.out[c] = acc / (float)a.hw;
+        put<DEV>(&a.out[c], acc / (float)a.hw);
     }
 }
 
 // one thread per output; fmaf chain in input order (a GEMV: no matrix unit),
 // loads of 16 inputs issued ahead of their part of the chain
+template <bool DEV>
 __device__ inline void body_fc(const acs_args_fc &a)
 {
     for (int32_t j = threadIdx.x; j < a.cout; j += ACS_BLOCK) {
@@ -816,17 +879,18 @@ __device__ inline void body_fc(const acs_args_fc &a)
             for (int u = 0; u < 16; u++) acc = fmaf(x[u], w[u], acc);
         }
         for (; i < a.cin; i++) acc = fmaf(a.in[i], a.w[(int64_t)i * a.cout + j], acc);
-        a.out[j] = acc;
+        put<DEV>(&a.out[j], acc);
     }
 }
 
 // uint4 copy, pieces take consecutive 4 KiB chunks round-robin
+template <bool DEV>
 __device__ inline void body_copy(const acs_args_copy &a, uint32_t piece, uint32_t np)
 {
     const uint64_t nv = a.bytes / 16;
     const uint4 *src = reinterpret_cast<const uint4 *>(a.src);
     uint4 *dst = reinterpret_cast<uint4 *>(a.dst);
-    for (uint64_t i = (uint64_t)piece * ACS_BLOCK + threadIdx.x; i < nv; i += (uint64_t)np * ACS_BLOCK) dst[i] = src[i];
+    for (uint64_t i = (uint64_t)piece * ACS_BLOCK + threadIdx.x; i < nv; i += (uint64_t)np * ACS_BLOCK) put16<DEV>(&dst[i], src[i]);
 }
 
 // one lane stores; the system-scope release orders it after the writes of
@@ -845,24 +909,25 @@ __device__ inline T load_args(const void *p)
     return a;
 }
 
+template <bool DEV>
 __device__ __forceinline__ void run_body(int32_t kid, const void *args, uint32_t piece, uint32_t np, uint8_t *smem)
 {
     switch (kid) {
     case ACS_K_NOP: body_nop(load_args<acs_args_nop>(args)); break;
-    case ACS_K_SCALE: body_scale(load_args<acs_args_scale>(args), piece, np); break;
-    case ACS_K_AXPY: body_axpy(load_args<acs_args_axpy>(args), piece, np); break;
-    case ACS_K_SUM: body_sum(load_args<acs_args_sum>(args), reinterpret_cast<float *>(smem)); break;
-    case ACS_K_RL_PREDICT: body_rl_predict(load_args<acs_args_rl>(args), piece, np); break;
-    case ACS_K_RL_BROADPHASE: body_rl_broadphase(load_args<acs_args_rl>(args), smem); break;
-    case ACS_K_RL_ISLANDS: body_rl_islands(load_args<acs_args_rl>(args), smem); break;
-    case ACS_K_RL_PERMUTE: body_rl_permute(load_args<acs_args_rl>(args), piece, np); break;
-    case ACS_K_RL_JACOBI: body_rl_jacobi(load_args<acs_args_rl>(args)); break;
-    case ACS_K_RL_INTEGRATE: body_rl_integrate(load_args<acs_args_rl>(args), piece, np); break;
-    case ACS_K_CONV: body_conv(load_args<acs_args_conv>(args), piece, np, smem); break;
-    case ACS_K_JOIN: body_join(load_args<acs_args_join>(args), piece, np); break;
-    case ACS_K_AVGPOOL: body_avgpool(load_args<acs_args_avgpool>(args)); break;
-    case ACS_K_FC: body_fc(load_args<acs_args_fc>(args)); break;
-    case ACS_K_COPY: body_copy(load_args<acs_args_copy>(args), piece, np); break;
+    case ACS_K_SCALE: body_scale<DEV>(load_args<acs_args_scale>(args), piece, np); break;
+    case ACS_K_AXPY: body_axpy<DEV>(load_args<acs_args_axpy>(args), piece, np); break;
+    case ACS_K_SUM: body_sum<DEV>(load_args<acs_args_sum>(args), reinterpret_cast<float *>(smem)); break;
+    case ACS_K_RL_PREDICT: body_rl_predict<DEV>(load_args<acs_args_rl>(args), piece, np); break;
+    case ACS_K_RL_BROADPHASE: body_rl_broadphase<DEV>(load_args<acs_args_rl>(args), smem); break;
+    case ACS_K_RL_ISLANDS: body_rl_islands<DEV>(load_args<acs_args_rl>(args), smem); break;
+    case ACS_K_RL_PERMUTE: body_rl_permute<DEV>(load_args<acs_args_rl>(args), piece, np); break;
+    case ACS_K_RL_JACOBI: body_rl_jacobi<DEV>(load_args<acs_args_rl>(args)); break;
+    case ACS_K_RL_INTEGRATE: body_rl_integrate<DEV>(load_args<acs_args_rl>(args), piece, np); break;
+    case ACS_K_CONV: body_conv<DEV>(load_args<acs_args_conv>(args), piece, np, smem); break;
+    case ACS_K_JOIN: body_join<DEV>(load_args<acs_args_join>(args), piece, np); break;
+    case ACS_K_AVGPOOL: body_avgpool<DEV>(load_args<acs_args_avgpool>(args)); break;
+    case ACS_K_FC: body_fc<DEV>(load_args<acs_args_fc>(args)); break;
+    case ACS_K_COPY: body_copy<DEV>(load_args<acs_args_copy>(args), piece, np); break;
     case ACS_K_SIGNAL: body_signal(load_args<acs_args_signal>(args)); break;
     default: break;
     }

@@ -26,7 +26,7 @@ template <int KID, typename A>
 __global__ __launch_bounds__(ACS_BLOCK) void k_task(A a, uint32_t npieces)
 {
     __shared__ __align__(16) uint8_t smem[smem_bytes<KID>()];
-    run_body(KID, &a, blockIdx.x, npieces, smem);
+    run_body<false>(KID, &a, blockIdx.x, npieces, smem);
 }
 
 static const void *const k_table[ACS_K_COUNT] = {

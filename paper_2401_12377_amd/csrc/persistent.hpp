@@ -21,7 +21,17 @@
 // group that has one waiting, with the same instructions.
 // Workgroups 1.. are workers: each takes a ticket from the work queue, waits
 // for the entry with that ticket, runs one piece of the task body, and bumps
-// the slot's completion counter with release semantics.
+// the slot's completion counter.
+//
+// Visibility between the waves runs on device-scope stores.  Every store that
+// another workgroup reads (task-table entries, task results) is a device-scope
+// store, which the hardware writes through the L2 of the storing XCD (the
+// XCDs' L2 caches are not coherent with each other), and it is complete once
+// the storing wave's vector-memory counter has drained.  So a wave publishes
+// by waiting for its own stores and then storing or counting the word that
+// announces them; the reader acquires (invalidating its stale cache lines)
+// after it has seen that word.  A release at device scope would instead write
+// back the whole L2 of the XCD, which serialises the pieces of a wide kernel.
 //
 // Only HIP device built-ins are used here, so the same source also builds
 // for the host against an emulation of those built-ins (a CPU build used by
@@ -203,6 +213,29 @@ __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
     }
 }
 
+// Trace records are written with device-scope stores like everything else
+// that workers touch: workers update t_start and t_end of a record with
+// atomics, which the write-back of a plain store's dirty bytes from the
+// window wave's L2 could later overwrite.
+__device__ inline void tput(int64_t *f, int64_t v) { __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+__device__ inline void trace_insert(acs_trace_rec *r, uint64_t seq, int32_t slot, int32_t kid, uint64_t ev, uint64_t valid,
+                                    uint64_t up)
+{
+    tput(&r->seq, (int64_t)seq);
+    tput(&r->slot, slot);
+    tput(&r->kernel_id, kid);
+    tput(&r->ev_insert, (int64_t)ev);
+    tput(&r->ev_dispatch, -1);
+    tput(&r->ev_retire, -1);
+    tput(reinterpret_cast<int64_t *>(&r->valid_mask), (int64_t)valid);
+    tput(reinterpret_cast<int64_t *>(&r->up_mask), (int64_t)up);
+    tput(&r->t_start, INT64_MAX);
+    tput(&r->t_end, 0);
+    tput(&r->t_dispatch, -1);
+    tput(&r->t_retire, -1);
+}
+
 // readlane returns int: every use goes through these, which zero-extend
 __device__ inline uint32_t readlane32(uint32_t x, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)x, l); }
 __device__ inline uint64_t readlane64(uint64_t x, int l)
@@ -346,7 +379,9 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                     const uint32_t npr = readlane32(dw, 3);
                     const uint32_t np = npr < kMaxPieces ? npr : kMaxPieces;
                     // the descriptor goes to the task table as it is
-                    if (lane < kDescCopyDwords) reinterpret_cast<uint32_t *>(&p.st->task[slot])[lane] = dw;
+                    if (lane < kDescCopyDwords)
+                        __hip_atomic_store(reinterpret_cast<uint32_t *>(&p.st->task[slot]) + lane, dw, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
                     uint64_t hits = 0;
                     if (!hc) {
                         if (valid & over4) hits = pair_hits<8, true>(d, nseg, wb, R, rep, ss, se, wmask);
@@ -377,7 +412,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                         mykid = kid;
                         mynp = np;
                         if (np > 1) target += kWave * np;
-                        p.st->task[slot].ptarget = target;
+                        __hip_atomic_store(&p.st->task[slot].ptarget, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
                     const uint64_t rbit = bit * repmul;
 #pragma unroll
@@ -386,19 +421,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                     over4 = nseg > 4u ? (over4 | bit) : (over4 & ~bit);
                     over2 = nseg > 2u ? (over2 | bit) : (over2 & ~bit);
                     if (tr && lane == 0 && seq < p.trace_cap) {
-                        acs_trace_rec *r = &p.trace[seq];
-                        r->seq = (int64_t)seq;
-                        r->slot = slot;
-                        r->kernel_id = kid;
-                        r->ev_insert = (int64_t)ev;
-                        r->ev_dispatch = -1;
-                        r->ev_retire = -1;
-                        r->valid_mask = valid;
-                        r->up_mask = upm;
-                        r->t_start = INT64_MAX;
-                        r->t_end = 0;
-                        r->t_dispatch = -1;
-                        r->t_retire = -1;
+                        trace_insert(&p.trace[seq], seq, slot, kid, ev, valid, upm);
                     }
                     ev++;
                     valid |= bit;
@@ -443,7 +466,9 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
     #pragma unroll
                     for (int g = 0; g < NG; g++)
                         if ((adm >> g) & 1u) {
-                            if (lane < kDescCopyDwords) reinterpret_cast<uint32_t *>(&p.st->task[newl[g]])[lane] = dwg[g];
+                            if (lane < kDescCopyDwords)
+                                __hip_atomic_store(reinterpret_cast<uint32_t *>(&p.st->task[newl[g]]) + lane, dwg[g],
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                             newbits |= 1ull << newl[g];
                         }
                     const uint32_t nraw = gin ? d->nseg : 0u;
@@ -476,21 +501,9 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                         const uint32_t npr = d->npieces;
                         mynp = npr < kMaxPieces ? npr : kMaxPieces;
                         if (mynp > 1) target += kWave * mynp;
-                        p.st->task[lane].ptarget = target;
+                        __hip_atomic_store(&p.st->task[lane].ptarget, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         if (tr && myseq < p.trace_cap) {
-                            acs_trace_rec *r = &p.trace[myseq];
-                            r->seq = (int64_t)myseq;
-                            r->slot = (int32_t)lane;
-                            r->kernel_id = mykid;
-                            r->ev_insert = (int64_t)ev;
-                            r->ev_dispatch = -1;
-                            r->ev_retire = -1;
-                            r->valid_mask = valid & mygroup;
-                            r->up_mask = up;
-                            r->t_start = INT64_MAX;
-                            r->t_end = 0;
-                            r->t_dispatch = -1;
-                            r->t_retire = -1;
+                            trace_insert(&p.trace[myseq], myseq, (int32_t)lane, mykid, ev, valid & mygroup, up);
                         }
                     }
                     // write flags of the new occupants' ranges, for every replica lane
@@ -536,8 +549,8 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                 if (tr) {
                     const uint64_t now = wall_clock64();
                     if (((done >> lane) & 1ull) && myseq < p.trace_cap) {
-                        p.trace[myseq].ev_retire = (int64_t)(ev + __builtin_popcountll(done & lane_lt));
-                        p.trace[myseq].t_retire = (int64_t)now;
+                        tput(&p.trace[myseq].ev_retire, (int64_t)(ev + __builtin_popcountll(done & lane_lt)));
+                        tput(&p.trace[myseq].t_retire, (int64_t)now);
                     }
                 }
                 ev += __builtin_popcountll(done);
@@ -578,13 +591,16 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
             for (uint64_t m = newly; m; m &= m - 1) {
                 const int j = __builtin_ctzll(m);
                 const uint64_t upj = readlane64(up, j);
-                if ((upj >> lane) & 1ull) p.st->wait_target[j][lane] = (uint32_t)(myseq + 1);
-                if (lane == 0) p.st->task[j].wait_mask = upj;
+                if ((upj >> lane) & 1ull)
+                    __hip_atomic_store(&p.st->wait_target[j][lane], (uint32_t)(myseq + 1), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                if (lane == 0) __hip_atomic_store(&p.st->task[j].wait_mask, upj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            // task-table entries written by other lanes are published before
-            // any work-queue entry that points at them
+            // every task-table store of this wave (device scope) is complete
+            // before any work-queue entry that points at it is stored.
+            // 0x0F70: vmcnt 0, expcnt 7, lgkmcnt 15.
+            __builtin_amdgcn_s_waitcnt(0x0F70);
             __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const bool mine = (newly >> lane) & 1ull;
             uint32_t before = 0, rank = 0, total = 0;
             for (uint64_t m = newly; m; m &= m - 1) {
@@ -615,8 +631,8 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
             }
             if (mine) {
                 if (tr && myseq < p.trace_cap) {
-                    p.trace[myseq].ev_dispatch = (int64_t)(ev + rank);
-                    p.trace[myseq].t_dispatch = (int64_t)wall_clock64();
+                    tput(&p.trace[myseq].ev_dispatch, (int64_t)(ev + rank));
+                    tput(&p.trace[myseq].t_dispatch, (int64_t)wall_clock64());
                 }
             }
             pub += total;
@@ -633,10 +649,10 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
         for (int g = 0; g < NG; g++)
             if (g < G && (valid & (wpmask << (g * Wp))) == 0 && retired[g] != published[g]) drained |= 1u << g;
         if (drained) {
-            // pairs with the release of every completion counted so far ...
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            __builtin_amdgcn_wave_barrier();
-            // ... and hands their results on to the host
+            // every result was stored with device scope before its completion
+            // was counted; the acquire and the system-scope release order the
+            // completions seen so far (and this wave's trace records) before
+            // the host is told
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
 #pragma unroll
             for (int g = 0; g < NG; g++)
@@ -772,11 +788,11 @@ __device__ inline void worker(const DevParams &p, uint8_t *smem, Mail *mail)
         __syncthreads();
         const uint32_t slot = uni32(mail->slot);
         if (slot == kSentinelSlot) break;
-        run_body((int32_t)uni32((uint32_t)mail->kid), mail->args, uni32(mail->piece), uni32(mail->np), smem);
-        // each wave waits for its own stores to complete (the workgroup
-        // barrier alone waits only for LDS traffic), then wave 0's release
-        // below makes every wave's results visible device-wide before the
-        // completion counter moves.  0x0F70: vmcnt 0, expcnt 7, lgkmcnt 15.
+        run_body<true>((int32_t)uni32((uint32_t)mail->kid), mail->args, uni32(mail->piece), uni32(mail->np), smem);
+        // each wave waits until its own result stores (device scope) are
+        // complete, so that they are visible device-wide before wave 0 counts
+        // the piece (the workgroup barrier alone waits only for LDS traffic).
+        // 0x0F70: vmcnt 0, expcnt 7, lgkmcnt 15.
         __builtin_amdgcn_s_waitcnt(0x0F70);
         __syncthreads();
         if (wave0) {
@@ -791,18 +807,18 @@ __device__ inline void worker(const DevParams &p, uint8_t *smem, Mail *mail)
                 }
             }
             // a kernel of several pieces is complete when the last piece is
-            // counted; that piece's read-modify-write also acquires the other
-            // pieces' results, so its release below covers them
+            // counted; every piece's results were complete before its count,
+            // so the last count comes after all of them
             const uint32_t np = uni32(mail->np);
             bool last = true;
             if (np > 1) {
                 // every lane adds 1: a piece counts kWave (see the ticket above)
-                const uint32_t old = uni32(__hip_atomic_fetch_add(&p.st->cnt[slot], 1u, __ATOMIC_ACQ_REL,
+                const uint32_t old = uni32(__hip_atomic_fetch_add(&p.st->cnt[slot], 1u, __ATOMIC_RELAXED,
                                                                   __HIP_MEMORY_SCOPE_AGENT));
                 last = old + kWave == uni32(mail->ptarget);
             }
             if (last)
-                __hip_atomic_store(&p.st->done[slot], (uint32_t)(seq + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&p.st->done[slot], (uint32_t)(seq + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }

@@ -208,6 +208,13 @@ inline float __int_as_float(int x)
     return r;
 }
 
+inline unsigned __float_as_uint(float x)
+{
+    unsigned r;
+    memcpy(&r, &x, 4);
+    return r;
+}
+
 inline int __shfl_up(int v, unsigned d, int width)
 {
     (void)width;
