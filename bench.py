@@ -10,10 +10,14 @@ Inputs are seeded and synthetic (they stand in for the paper's Brax
 environments, which are not available here).
 
 Paths timed on the same episodes:
-  device            the persistent scheduler kernel (headline `value`)
-  device_hostcheck  the same kernel with the dependency checks made on the
-                    host against its list of the last W kernels (the
-                    host/device split), the window wave only filtering
+  device              the persistent scheduler kernel (headline `value`); the
+                      dependency checks run in a wave ahead of the window,
+                      against the last 64 kernels (the host/device split made
+                      inside the device), the window wave only filtering
+  device_windowcheck  the same kernel with the checks made by the window wave
+                      at insert
+  device_hostcheck    the same kernel with the checks made on the host
+                      against its list of the last W kernels
   inorder           every kernel launched into one HIP stream (the baseline)
   plain             host-side window + pool of HIP streams
 
@@ -95,10 +99,13 @@ def algorithmic_bytes(counts: dict, n: int) -> int:
 
 
 def open_window(acs, path, W, **kw):
-    """`device_hostcheck` is the device path with the dependency checks on
+    """`device_windowcheck`: the device path with the dependency checks made
+    by the window wave; `device_hostcheck` is the device path with them on
     the host (a scheduled list of the last W kernels) instead of the window wave."""
     if path == "device_hostcheck":
         return acs.Window(W, path="device", host_check_depth=W, **kw)
+    if path == "device_windowcheck":
+        return acs.Window(W, path="device", window_check=1, **kw)
     return acs.Window(W, path=path, **kw)
 
 
@@ -189,7 +196,8 @@ def batched_section(acs, inputs, torch, args):
         gpu = [acs.RLSceneGPU(sc) for sc in scenes]
         torch.cuda.synchronize()
         with acs.Window(cfg["W"], path=path, n_groups=cfg["n_groups"], wg_per_task=cfg["wg_per_task"],
-                        queue_depth=cfg["queue_depth"], host_check_depth=cfg.get("host_check_depth", 0)) as w:
+                        queue_depth=cfg["queue_depth"], host_check_depth=cfg.get("host_check_depth", 0),
+                        window_check=cfg.get("window_check", 0)) as w:
             t0 = time.perf_counter()
             counts, step_ns = acs.rl_run_batch(w, gpu, args.batch_steps, n_groups=cfg["n_groups"])
             dt = time.perf_counter() - t0
@@ -214,7 +222,7 @@ def dnn_section(acs, inputs, torch, args):
     wts = inputs.dnn_weights()
     seeds = list(range(args.dnn_inputs))
     out = {}
-    for path in ("device", "device_hostcheck", "inorder", "events"):
+    for path in ("device", "device_windowcheck", "device_hostcheck", "inorder", "events"):
         nets = [acs.DNNGPU(wts, inputs.DNN_CELLS, inputs.DNN_CLASSES) for _ in range(8)]
         lat = []
         kernels = 0
@@ -303,17 +311,19 @@ def serve_section(acs, inputs, torch, args):
     net = acs.DNNGPU(inputs.dnn_weights(), inputs.DNN_CELLS, inputs.DNN_CLASSES)
     pool = torch.empty(args.serve_pool_mib << 20, dtype=torch.uint8, device="cuda")
     host = acs.serve_host(args.serve_resident)
-    configs = [("device", 32, 1, 0), ("device", 32, 1, 32), ("device", 16, 4, 0), ("device", 8, 8, 0),
-               ("inorder", 8, 1, 0)]
+    # (path, W, groups, host-check depth, window wave checks)
+    configs = [("device", 32, 1, 0, 0), ("device", 32, 1, 0, 1), ("device", 32, 1, 32, 0), ("device", 16, 4, 0, 0),
+               ("device", 8, 8, 0, 0), ("inorder", 8, 1, 0, 0)]
     table = {}
     outputs = {}
-    for path, W, G, hc in configs:
-        key = (f"{path}_W{W}_G{G}" + ("_hostcheck" if hc else "")) if path == "device" else path
+    for path, W, G, hc, wc in configs:
+        key = (f"{path}_W{W}_G{G}" + ("_hostcheck" if hc else "") + ("_windowcheck" if wc else "")
+               if path == "device" else path)
         rows = []
         for lam in rates:
             specs = inputs.serve_requests(seed=4, rate_per_s=lam, n_requests=n)
             sset = acs.ServeSet(specs, rl, dnn, inputs.DNN_CLASSES)
-            with acs.Window(W, path=path, n_groups=G, host_check_depth=hc) as w:
+            with acs.Window(W, path=path, n_groups=G, host_check_depth=hc, window_check=wc) as w:
                 res, st = acs.serve_run(w, sset, pool, host, max_resident=args.serve_resident, model=net,
                                         stall_ns=60 * 10 ** 9)
             lat = np.array([r["done_ns"] - s.arrival_ns for r, s in zip(res, specs)]) / 1e6
@@ -363,7 +373,7 @@ def dag_section(acs, inputs, torch, args):
         lat = np.array(lat[2:]) * 1e3
         return {"latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}}
     ref_out = None
-    for path in ("device", "device_hostcheck", "inorder", "events", "plain"):
+    for path in ("device", "device_windowcheck", "device_hostcheck", "inorder", "events", "plain"):
         net = acs.DAGGPU(graph, wts)
         lat = []
         with open_window(acs, path, 16, n_streams=args.streams) as w:
@@ -425,7 +435,7 @@ def main():
     # the default set: its process has ended with a host-side segmentation
     # fault inside that loop in two runs (no GPU fault reported; other runs of
     # the same loop completed) and no cause has been found in this code
-    ap.add_argument("--paths", default="device,device_hostcheck,inorder,plain,events")
+    ap.add_argument("--paths", default="device,device_windowcheck,device_hostcheck,inorder,plain,events")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-scenes section")
     ap.add_argument("--batch-scenes", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=20)
@@ -490,6 +500,9 @@ def main():
     if "inorder" in res:
         out["speedup_vs_inorder"] = res["inorder"][0] / dt
         out["inorder_kernels_per_s"] = res["inorder"][1] / res["inorder"][0]
+    if "device_windowcheck" in res:
+        wc = res["device_windowcheck"]
+        out["window_wave_checks"] = {"kernels_per_s": wc[1] / wc[0], "vs_check_wave": dt / wc[0]}
     if "device_hostcheck" in res:
         hc = res["device_hostcheck"]
         out["host_check_split"] = {"kernels_per_s": hc[1] / hc[0], "vs_device_checks": dt / hc[0],

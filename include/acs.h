@@ -106,7 +106,14 @@ typedef struct {
                                 upstream kernels that already completed and holds a kernel back
                                 while one more than M older is still in the window.  Same
                                 schedules; other paths ignore it. */
-    int32_t reserved[5];
+    int32_t window_check;    /* device path, one group, host_check_depth 0: 0 (default) = the
+                                same split inside the device: a wave ahead of the window checks
+                                each kernel against the 64 submitted before it and the window
+                                wave only drops completed upstream kernels (M = 64 above);
+                                1 = the window wave makes the checks itself (Algorithm 1 at
+                                insert), as it always does with more than one group.  Same
+                                schedules either way. */
+    int32_t reserved[4];
 } acs_config;
 
 /* One entry of the scheduled list (Section IV-C): the kernels currently in the

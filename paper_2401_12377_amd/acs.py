@@ -54,7 +54,7 @@ class Config(C.Structure):
     _fields_ = [("path", C.c_int32), ("n_streams", C.c_int32), ("wg_per_task", C.c_int32), ("n_workers", C.c_int32),
                 ("queue_depth", C.c_int32), ("nonblocking", C.c_int32), ("trace", C.c_int32),
                 ("trace_capacity", C.c_int32), ("device", C.c_int32), ("n_groups", C.c_int32),
-                ("host_check_depth", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("host_check_depth", C.c_int32), ("window_check", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class Entry(C.Structure):
@@ -330,7 +330,8 @@ class Window:
 
     def __init__(self, W: int, path: str = "device", n_streams: int = 4, wg_per_task: int = 1, n_workers: int = 0,
                  queue_depth: int = 4096, nonblocking: bool = False, trace: bool = False,
-                 trace_capacity: int = 1 << 16, device: int = 0, n_groups: int = 1, host_check_depth: int = 0):
+                 trace_capacity: int = 1 << 16, device: int = 0, n_groups: int = 1, host_check_depth: int = 0,
+                 window_check: int = 0):
         L = lib()
         h = L.acs_window_create(W)
         if not h:
@@ -346,6 +347,7 @@ class Window:
         cfg.queue_depth, cfg.nonblocking, cfg.trace = queue_depth, int(nonblocking), int(trace)
         cfg.trace_capacity, cfg.device, cfg.n_groups = trace_capacity, device, n_groups
         cfg.host_check_depth = host_check_depth
+        cfg.window_check = window_check
         self.n_groups = n_groups
         rc = L.acs_window_configure(h, C.byref(cfg))
         if rc < 0:

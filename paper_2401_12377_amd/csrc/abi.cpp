@@ -297,16 +297,18 @@ int make_desc(int32_t kid, const acs_seg *r, int32_t nr, const acs_seg *w, int32
     memcpy(out.args, args, args_size);
     if (args_size < ACS_ARGS_MAX) memset(out.args + args_size, 0, ACS_ARGS_MAX - args_size);
     out.args_size = (uint32_t)args_size;
+    // writes first: a read only has to be tested against the first
+    // positions of the other kernels, up to the most writes any kernel has
     out.wbits = 0;
     uint32_t k = 0;
-    for (size_t i = 0; i < rr.n; i++, k++) {
-        out.s[k] = rr.v[i].s;
-        out.e[k] = rr.v[i].e;
-    }
     for (size_t i = 0; i < ww.n; i++, k++) {
         out.s[k] = ww.v[i].s;
         out.e[k] = ww.v[i].e;
         out.wbits |= 1u << k;
+    }
+    for (size_t i = 0; i < rr.n; i++, k++) {
+        out.s[k] = rr.v[i].s;
+        out.e[k] = rr.v[i].e;
     }
     out.nseg = k;
     for (; k < ACS_K_MAX; k++) out.s[k] = out.e[k] = 0;
@@ -408,6 +410,7 @@ int acs_window_configure(acs_window *w, const acs_config *cfg)
         return fail(ACS_EINVAL, "host_check_depth must be in [0, 64]");
     if (cfg->path == ACS_PATH_DEVICE && cfg->host_check_depth > 0 && cfg->n_groups != 1)
         return fail(ACS_EINVAL, "host checks need a single window group");
+    if (cfg->window_check != 0 && cfg->window_check != 1) return fail(ACS_EINVAL, "window_check must be 0 or 1");
     w->cfg = *cfg;
     w->configured = true;
     return ensure_started(w);

@@ -41,6 +41,10 @@ static_assert(sizeof(DevDesc) == 256, "descriptor must be 256 bytes");
 static_assert(offsetof(DevDesc, host_up) == 232, "host_up is dwords 58 and 59 of the descriptor");
 constexpr uint32_t kDescCopyDwords = 54;   // dwords of DevDesc the task table needs
 constexpr int kHostUpDword = 58;
+constexpr int kSegStartDword = 6;          // s[k] is dwords 6 + 2k and 7 + 2k
+constexpr int kSegEndDword = 22;           // e[k] is dwords 22 + 2k and 23 + 2k
+static_assert(offsetof(DevDesc, s) == 4 * kSegStartDword && offsetof(DevDesc, e) == 4 * kSegEndDword,
+              "segment dwords");
 
 constexpr int kMaxGroups = 8;   // independent windows served by one window wave
 
@@ -59,8 +63,9 @@ struct HostCtrl {
     volatile uint64_t snap_count;           // entries in the snapshot
     volatile uint64_t alive;                // set when the scheduler wave starts
     volatile uint64_t exited;               // set when the scheduler wave leaves
-    volatile uint64_t checks;               // overlap tests made (statistics)
-    uint64_t pad1[2];
+    volatile uint64_t checks;               // overlap tests made by the window wave (statistics)
+    volatile uint64_t check_wave_tests;     // overlap tests made by the check wave (statistics)
+    uint64_t pad1[1];
     acs_entry snap[ACS_W_MAX];
 };
 
@@ -70,12 +75,12 @@ struct HostCtrl {
 // workers which completion words must reach which values before the body may
 // start.
 //
-// Completion is signalled with plain stores: the worker that finishes a
-// kernel's last piece writes seq + 1 (mod 2^32) into done[slot].  Plain
-// stores reach another XCD's polling load in a few hundred nanoseconds, an
-// atomic read-modify-write takes several times longer, so the per-slot piece
-// counter cnt[] is touched only by kernels of more than one piece, to find
-// which piece is the last.
+// Completion is signalled with a device-scope store: the worker that
+// finishes a kernel's last piece writes seq + 1 (mod 2^32) into done[slot].
+// A store reaches another XCD's polling load in a few hundred nanoseconds,
+// an atomic read-modify-write takes several times longer, so the per-slot
+// piece counter cnt[] is touched only by kernels of more than one piece, to
+// find which piece is the last.
 using TaskEntry = DevDesc;
 
 constexpr uint32_t kQueueCap = 1u << 16;       // work queue entries (power of two)
@@ -105,8 +110,9 @@ struct DevParams {
     int32_t W;                    // slots per group
     int32_t n_workers;
     int32_t n_groups;             // independent windows, 1..kMaxGroups; n_groups * pow2(W) <= 64
-    int32_t host_check;           // 0: dependency checks on the device; M > 0: the host checks each
-                                  // kernel against the M submitted before it (one window only)
+    int32_t host_check;           // 0: dependency checks in the window wave; M > 0: each kernel comes
+                                  // checked against the M submitted before it (one window only)
+    int32_t check_wave;           // 1: a wave ahead of the window makes those checks (M = 64); 0: the host
 };
 
 }  // namespace acs

@@ -87,7 +87,11 @@ public:
         p.n_workers = n_workers_;
         p.n_groups = groups_;
         hc_ = groups_ == 1 ? std::max(0, std::min(cfg_.host_check_depth, ACS_W_MAX)) : 0;
-        p.host_check = hc_;
+        // one window: the checks run ahead of it, on the host when asked,
+        // else in the check wave unless the window wave is asked to make them
+        fc_ = groups_ == 1 && hc_ == 0 && cfg_.window_check == 0;
+        p.host_check = fc_ ? ACS_W_MAX : hc_;
+        p.check_wave = fc_ ? 1 : 0;
         hist_.assign((size_t)std::max(1, hc_), Desc{});
         if ((e = hipEventCreate(&ev0_)) != hipSuccess) return hip_fail(e, "hipEventCreate");
         if ((e = hipEventCreate(&ev1_)) != hipSuccess) return hip_fail(e, "hipEventCreate");
@@ -244,7 +248,7 @@ public:
                     return ACS_EDEVICE;
                 }
             }
-            checks_ = ctrl_->checks;
+            checks_ = ctrl_->checks + ctrl_->check_wave_tests;
             running_ = false;
             float ms = 0.0f;
             if (hipEventElapsedTime(&ms, ev0_, ev1_) == hipSuccess) kernel_ns_ = (uint64_t)((double)ms * 1e6);
@@ -280,7 +284,7 @@ public:
         for (int32_t g = 0; g < groups_; g++) ret += ctrl_ ? ctrl_->retired[g] : submitted_[g];
         s.retired = ret;
         s.dispatched = s.retired;
-        s.overlap_tests = (running_ && ctrl_ ? ctrl_->checks : checks_) + host_tests_;
+        s.overlap_tests = (running_ && ctrl_ ? ctrl_->checks + ctrl_->check_wave_tests : checks_) + host_tests_;
         s.n_workers = n_workers_;
         s.kernel_ns = kernel_ns_;
     }
@@ -333,6 +337,7 @@ private:
     int32_t W_;
     uint64_t polls_ = 0;
     int32_t hc_ = 0;                 // host-check depth M (0: checks on the device)
+    bool fc_ = false;                // checks made by the check wave
     std::vector<Desc> hist_;         // the last M descriptors submitted, by submission index % M
     uint64_t hist_n_ = 0;
     uint64_t host_tests_ = 0;

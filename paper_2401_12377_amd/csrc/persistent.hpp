@@ -15,6 +15,9 @@
 //   wave 1  the input FIFO: copies descriptors from the host-resident rings
 //           into small rings in LDS, so that host-memory latency never
 //           stalls the window loop.
+//   wave 2  (one window, checks ahead of the window) tests each staged
+//           kernel against the 64 submitted before it, then hands it on to
+//           the window wave.
 // The lanes of the window wave may be split into up to eight groups, each an
 // independent window with its own input ring (for many independent task
 // graphs in one launch): one insertion pass then admits one kernel into every
@@ -52,7 +55,8 @@ constexpr uint32_t kAdmitBatch = 16;  // insertion passes per loop (measured: ad
                                       // dispatch rounds than it saves in latency)
 
 struct FetchShared {
-    uint32_t tail[kMaxGroups];   // descriptors staged per group (written by the FIFO wave)
+    uint32_t tail[kMaxGroups];   // descriptors ready for the window wave per group (FIFO or check wave)
+    uint32_t staged;             // checks ahead of the window: descriptors copied, not yet checked
     uint32_t head[kMaxGroups];   // descriptors taken per group (written by the window wave)
     uint32_t stop;               // mirror of the host stop flag
     uint32_t exit;               // window wave -> FIFO wave: leave
@@ -67,6 +71,7 @@ __device__ inline uint32_t lds_depth(int32_t groups) { return kLdsDescs / (uint3
 __device__ inline void fetch_init(FetchShared *fs)
 {
     for (int g = 0; g < kMaxGroups; g++) fs->tail[g] = fs->head[g] = 0;
+    fs->staged = 0;
     fs->stop = 0;
     fs->exit = 0;
     fs->snap_req = 0;
@@ -94,6 +99,109 @@ __device__ inline uint64_t uni64(uint64_t x)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// readlane returns int: every use goes through these, which zero-extend
+__device__ inline uint32_t readlane32(uint32_t x, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)x, l); }
+__device__ inline uint64_t readlane64(uint64_t x, int l)
+{
+    const uint32_t lo = readlane32((uint32_t)x, l);
+    const uint32_t hi = readlane32((uint32_t)(x >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+// a 64-bit field held in dwords l (low) and l + 1 (high) of a wave-wide word
+__device__ inline uint64_t readpair(uint32_t x, int l) { return ((uint64_t)readlane32(x, l + 1) << 32) | readlane32(x, l); }
+
+// The dependency checks of a single window made while kernels are staged
+// (the host/device split of Section IV-C with the host's part done by the
+// FIFO wave): every kernel is tested, in submission order, against the 64
+// submitted before it.  Lane l keeps the ranges of the latest kernel whose
+// sequence number is l mod 64, so one pass tests all 64 at once (Algorithm 1
+// in both directions, as in the window wave).  A new read can only meet a
+// write, so it is tested against the first two positions only while no
+// kernel so far had a write at a later position (mw); the library lists a
+// kernel's writes before its reads, which keeps mw at the most writes any
+// kernel has.
+// The result goes into the staged descriptor as the upstream-by-distance
+// word of host-check mode: bit b set when the kernel submitted b + 1 places
+// earlier conflicts.  The window wave keeps from it the kernels still in the
+// window.
+struct SeqHistory {
+    uint64_t s[kSegs], e[kSegs];   // ranges of this lane's kernel; unused: empty [0, 0)
+    uint32_t w;                    // bit m: position m is a write
+    uint32_t mw;                   // highest write position + 1 of any kernel so far (the same on
+                                   // every lane)
+};
+
+__device__ inline void history_init(SeqHistory &h)
+{
+#pragma unroll
+    for (int m = 0; m < kSegs; m++) h.s[m] = h.e[m] = 0;
+    h.w = 0;
+    h.mw = 0;
+}
+
+// d: the staged descriptor (LDS); returns the pair tests made
+__device__ inline uint64_t history_check(DevDesc *d, SeqHistory &h, uint32_t lane)
+{
+    const uint32_t dw = reinterpret_cast<const uint32_t *>(d)[lane];
+    // the new kernel's ranges, for its place in the history: loaded by every
+    // lane (one address, a broadcast) now, so that the wait overlaps the tests
+    uint64_t ns[kSegs], ne[kSegs];
+#pragma unroll
+    for (int m = 0; m < kSegs; m++) {
+        ns[m] = d->s[m];
+        ne[m] = d->e[m];
+    }
+    const uint64_t seq = readpair(dw, 0);
+    const uint32_t nraw = readlane32(dw, 4);
+    const uint32_t nseg = nraw < (uint32_t)kSegs ? nraw : (uint32_t)kSegs;
+    const uint32_t segmask = (1u << nseg) - 1u;
+    const uint32_t wb = readlane32(dw, 5) & segmask;
+    const uint32_t wtop = wb ? 32u - (uint32_t)__builtin_clz(wb) : 0u;
+    bool hit = false;
+    for (uint32_t k = 0; k < nseg; k++) {
+        const uint64_t a0 = readpair(dw, kSegStartDword + 2 * (int)k), a1 = readpair(dw, kSegEndDword + 2 * (int)k);
+        // no branch per position: unused positions hold [0, 0), which
+        // meets nothing; only the reads' bound on positions is tested
+        if ((wb >> k) & 1u) {
+#pragma unroll
+            for (int m = 0; m < kSegs; m++) hit |= a0 < h.e[m] && a1 > h.s[m];
+        } else {
+#pragma unroll
+            for (int m = 0; m < 2; m++) hit |= a0 < h.e[m] && a1 > h.s[m] && ((h.w >> m) & 1u);
+            if (h.mw > 2u) {
+#pragma unroll
+                for (int m = 2; m < kSegs; m++) hit |= a0 < h.e[m] && a1 > h.s[m] && ((h.w >> m) & 1u);
+            }
+        }
+    }
+    const uint32_t nw = (uint32_t)__builtin_popcount(wb);
+    const uint64_t tests = (uint64_t)(nw * kSegs + (nseg - nw) * (h.mw > 2u ? kSegs : 2u)) * (seq < 64 ? seq : 64);
+    // bit b of the result is the kernel b + 1 places back, held by lane
+    // r - b mod 64 (r = seq - 1 mod 64): the lane mask reversed (lane l to
+    // bit 63 - l) and rotated right by 63 - r.  There is none when b >= seq.
+    const uint64_t hm = __builtin_amdgcn_ballot_w64(hit);
+    const uint32_t rot = (63u - (uint32_t)((seq - 1u) & 63u)) & 63u;
+    const uint64_t rv = __builtin_bitreverse64(hm);
+    uint64_t up = rot ? ((rv >> rot) | (rv << (64u - rot))) : rv;
+    if (seq < 64) up &= (1ull << seq) - 1ull;
+    uint32_t *words = reinterpret_cast<uint32_t *>(d);
+    if (lane == 0) {
+        words[kHostUpDword] = (uint32_t)up;
+        words[kHostUpDword + 1] = (uint32_t)(up >> 32);
+    }
+    // the kernel takes its place in the history
+    if (lane == (uint32_t)(seq & 63u)) {
+#pragma unroll
+        for (int m = 0; m < kSegs; m++) {
+            h.s[m] = (uint32_t)m < nseg ? ns[m] : 0ull;
+            h.e[m] = (uint32_t)m < nseg ? ne[m] : 0ull;
+        }
+        h.w = wb;
+    }
+    h.mw = wtop > h.mw ? wtop : h.mw;
+    return tests;
+}
+
 // NG: compile-time bound on the group count (1, 2, 4 or 8), so that the
 // per-group loops disappear for a single window
 template <int NG>
@@ -111,6 +219,8 @@ __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
     // published every ring_cap / 8 descriptors and when the wave goes idle:
     // a store to host memory per copy would make every copy wait for it.
     const uint64_t tell_every = ring_cap / 8 > 0 ? ring_cap / 8 : 1;
+    // checks ahead of the window: the copies go to the check wave instead
+    const bool fc = NG == 1 && p.check_wave != 0;
     for (;;) {
         if (uni32(LDS_LOAD(&fs->exit))) break;
         // Each round issues, together: the loads of the host's control lines
@@ -192,7 +302,7 @@ __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
                 if (cnt[g] == 0) continue;
                 ftail[g] += cnt[g];
                 consumed[g] += cnt[g];
-                if (lane == 0) LDS_STORE(&fs->tail[g], ftail[g]);
+                if (lane == 0) LDS_STORE(fc ? &fs->staged : &fs->tail[g], ftail[g]);
                 if (consumed[g] - told[g] >= tell_every) {
                     if (lane == 0)
                         __hip_atomic_store(&p.ctrl->consumed[g], consumed[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -211,6 +321,36 @@ __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
             if (!fresh) __builtin_amdgcn_s_sleep(1);
         }
     }
+}
+
+// Wave 2 when the checks run ahead of the window (one window): takes the
+// kernels the FIFO wave staged, in order, checks each against the history
+// and hands it to the window wave.  Leaves with the window wave.
+__device__ inline void check_wave(const DevParams &p, FetchShared *fs)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t depth = lds_depth(1);
+    SeqHistory hist;
+    history_init(hist);
+    uint64_t tests = 0;
+    uint32_t done = 0;
+    for (;;) {
+        const uint32_t staged = uni32(LDS_LOAD(&fs->staged));
+        if (staged == done) {
+            if (uni32(LDS_LOAD(&fs->exit)) || uni32(LDS_LOAD(&fs->stop)) == 2u) break;
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        for (; done != staged; done++) {
+            tests += history_check(&fs->ring[done % depth], hist, lane);
+            // the upstream word lands before the kernel is handed on
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (lane == 0) LDS_STORE(&fs->tail[0], done + 1);
+        }
+    }
+    if (lane == 0) __hip_atomic_store(&p.ctrl->check_wave_tests, tests, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Trace records are written with device-scope stores like everything else
@@ -235,17 +375,6 @@ __device__ inline void trace_insert(acs_trace_rec *r, uint64_t seq, int32_t slot
     tput(&r->t_dispatch, -1);
     tput(&r->t_retire, -1);
 }
-
-// readlane returns int: every use goes through these, which zero-extend
-__device__ inline uint32_t readlane32(uint32_t x, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)x, l); }
-__device__ inline uint64_t readlane64(uint64_t x, int l)
-{
-    const uint32_t lo = readlane32((uint32_t)x, l);
-    const uint32_t hi = readlane32((uint32_t)(x >> 32), l);
-    return ((uint64_t)hi << 32) | lo;
-}
-// a 64-bit field held in dwords l (low) and l + 1 (high) of a wave-wide word
-__device__ inline uint64_t readpair(uint32_t x, int l) { return ((uint64_t)readlane32(x, l + 1) << 32) | readlane32(x, l); }
 
 // Pair tests of one insertion pass (Algorithm 1 in both directions): segment
 // k of the new kernel, k = rep, rep + R, ... below nseg, against positions

@@ -6,8 +6,10 @@ candidate on the device path.
 Each candidate runs on its own copy of the scenes (the tuning steps do not
 advance the caller's scenes).  The search is exhaustive over (W, groups,
 workgroups per task, where the dependency checks run) with W in {8, 16, 32}
-and groups * pow2(W) <= 64 (checks on the host only for one group, against
-the last W kernels), then over the queue depth for the best of those.
+and groups * pow2(W) <= 64, then over the queue depth for the best of those.
+With one group the checks may run in the check wave ahead of the window
+(the default), on the host against the last W kernels, or in the window
+wave; with more groups always in the window wave.
 """
 from __future__ import annotations
 
@@ -24,10 +26,24 @@ def _pow2(x: int) -> int:
     return p
 
 
-def candidates(windows=(8, 16, 32), groups=(1, 2, 4, 8), wg=(1, 2, 4), host_checks=(False, True)):
-    for W, G, g, hc in itertools.product(windows, groups, wg, host_checks):
-        if G * _pow2(W) <= acs.W_MAX and (not hc or G == 1):
-            yield {"W": W, "n_groups": G, "wg_per_task": g, "queue_depth": 4096, "host_check_depth": W if hc else 0}
+CHECK_SITES = ("wave", "host", "window")
+
+
+def candidates(windows=(8, 16, 32), groups=(1, 2, 4, 8), wg=(1, 2, 4), sites=CHECK_SITES):
+    for W, G, g, site in itertools.product(windows, groups, wg, sites):
+        if G * _pow2(W) > acs.W_MAX:
+            continue
+        if G > 1 and site != sites[0]:
+            continue   # more than one group: the window wave checks, whatever is asked
+        yield {"W": W, "n_groups": G, "wg_per_task": g, "queue_depth": 4096,
+               "host_check_depth": W if (G == 1 and site == "host") else 0,
+               "window_check": 1 if (G == 1 and site == "window") else 0}
+
+
+def open_window(cfg: dict):
+    return acs.Window(cfg["W"], path="device", n_groups=cfg["n_groups"], wg_per_task=cfg["wg_per_task"],
+                      queue_depth=cfg["queue_depth"], host_check_depth=cfg.get("host_check_depth", 0),
+                      window_check=cfg.get("window_check", 0))
 
 
 def time_config(scenes, cfg: dict, steps: int = 2, warmup: int = 1) -> float:
@@ -36,8 +52,7 @@ def time_config(scenes, cfg: dict, steps: int = 2, warmup: int = 1) -> float:
     import torch
     gpu = [acs.RLSceneGPU(sc) for sc in scenes]
     torch.cuda.synchronize()
-    with acs.Window(cfg["W"], path="device", n_groups=cfg["n_groups"], wg_per_task=cfg["wg_per_task"],
-                    queue_depth=cfg["queue_depth"], host_check_depth=cfg.get("host_check_depth", 0)) as w:
+    with open_window(cfg) as w:
         if warmup:
             acs.rl_run_batch(w, gpu, warmup, n_groups=cfg["n_groups"])
         t0 = time.perf_counter()

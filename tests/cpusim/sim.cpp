@@ -55,6 +55,8 @@ void run_thread(const acs::DevParams &p, Block *b, uint32_t t, uint32_t blk)
             else if (ng <= 2) acs::fifo_wave<2>(p, fs);
             else if (ng <= 4) acs::fifo_wave<4>(p, fs);
             else acs::fifo_wave<8>(p, fs);
+        } else if (wave == 2 && ng <= 1 && p.check_wave) {
+            acs::check_wave(p, fs);
         }
     } else {
         worker(p, b->lds, &b->mail);
@@ -76,7 +78,7 @@ typedef struct {
 // timeout_s (the emulated kernel is then aborted through the stop flag).
 // groups[i] (NULL: all 0) is the window group of descriptor i, n_groups the
 // number of groups of W slots.
-static int run_sim(int32_t W, int32_t n_groups, int32_t host_check, int32_t n_workers, int32_t n,
+static int run_sim(int32_t W, int32_t n_groups, int32_t host_check, int32_t check_wave, int32_t n_workers, int32_t n,
                    const sim_desc *descs, const int32_t *groups, const uint64_t *host_up, uint32_t ring_cap,
                    acs_trace_rec *trace_out, double timeout_s, uint64_t *retired_out)
 {
@@ -108,6 +110,7 @@ static int run_sim(int32_t W, int32_t n_groups, int32_t host_check, int32_t n_wo
     p.n_workers = n_workers;
     p.n_groups = n_groups;
     p.host_check = host_check;
+    p.check_wave = check_wave;
 
     const int nblk = 1 + n_workers;
     std::vector<std::unique_ptr<Block>> blocks;
@@ -191,13 +194,13 @@ int sim_run_groups(int32_t W, int32_t n_groups, int32_t n_workers, int32_t n, co
                    const int32_t *groups, uint32_t ring_cap, acs_trace_rec *trace_out, double timeout_s,
                    uint64_t *retired_out)
 {
-    return run_sim(W, n_groups, 0, n_workers, n, descs, groups, nullptr, ring_cap, trace_out, timeout_s, retired_out);
+    return run_sim(W, n_groups, 0, 0, n_workers, n, descs, groups, nullptr, ring_cap, trace_out, timeout_s, retired_out);
 }
 
 int sim_run(int32_t W, int32_t n_workers, int32_t n, const sim_desc *descs, uint32_t ring_cap,
             acs_trace_rec *trace_out, double timeout_s, uint64_t *retired_out)
 {
-    return run_sim(W, 1, 0, n_workers, n, descs, nullptr, nullptr, ring_cap, trace_out, timeout_s, retired_out);
+    return run_sim(W, 1, 0, 0, n_workers, n, descs, nullptr, nullptr, ring_cap, trace_out, timeout_s, retired_out);
 }
 
 // Host-check mode: host_up[i] is descriptor i's upstream list from the
@@ -207,7 +210,15 @@ int sim_run_hostcheck(int32_t W, int32_t M, int32_t n_workers, int32_t n, const 
                       uint64_t *retired_out)
 {
     if (M < 1 || M > 64 || !host_up) return -1;
-    return run_sim(W, 1, M, n_workers, n, descs, nullptr, host_up, ring_cap, trace_out, timeout_s, retired_out);
+    return run_sim(W, 1, M, 0, n_workers, n, descs, nullptr, host_up, ring_cap, trace_out, timeout_s, retired_out);
+}
+
+// Check-wave mode: wave 2 computes each descriptor's upstream list over
+// the 64 before it; the caller provides none.
+int sim_run_checkwave(int32_t W, int32_t n_workers, int32_t n, const sim_desc *descs, uint32_t ring_cap,
+                      acs_trace_rec *trace_out, double timeout_s, uint64_t *retired_out)
+{
+    return run_sim(W, 1, 64, 1, n_workers, n, descs, nullptr, nullptr, ring_cap, trace_out, timeout_s, retired_out);
 }
 
 }  // extern "C"

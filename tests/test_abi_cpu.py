@@ -421,6 +421,18 @@ def test_host_check_depth_validation():
         w.submit(acs.K_NOP, [], [(0, 1)], acs.ArgsNop(0))
 
 
+def test_window_check_validation():
+    for v in (2, -1):
+        with pytest.raises(acs.AcsError) as e:
+            acs.Window(8, path="device", window_check=v)
+        assert e.value.code == acs.EINVAL
+    with pytest.raises(acs.AcsError):
+        acs.Window(8, path="manual", window_check=3)
+    # other paths accept and ignore it
+    with acs.Window(8, path="manual", window_check=1) as w:
+        w.submit(acs.K_NOP, [], [(0, 1)], acs.ArgsNop(0))
+
+
 def fake_dag_graph(graph):
     nxt = [1 << 40]
 

@@ -42,10 +42,19 @@ def bits(a):
 # ---------------------------------------------------------------------------
 # tiny random stream
 # ---------------------------------------------------------------------------
+def window(W, path, **kw):
+    """`device_window`: the device path with the dependency checks made by
+    the window wave itself (for one window the default makes them in a wave
+    ahead of it)."""
+    if path == "device_window":
+        return acs.Window(W, path="device", window_check=1, **kw)
+    return acs.Window(W, path=path, **kw)
+
+
 def run_tiny(torch, st, path, W, **kw):
     arena = torch.from_numpy(st.init.copy()).cuda()
     torch.cuda.synchronize()
-    with acs.Window(W, path=path, trace=True, **kw) as w:
+    with window(W, path, trace=True, **kw) as w:
         acs.submit_tiny_stream(w, st, arena.data_ptr())
         rc = w.sync_rc(SYNC_NS)
         assert rc == 0, acs.lib().acs_strerror(rc)
@@ -54,7 +63,7 @@ def run_tiny(torch, st, path, W, **kw):
     return arena.cpu().numpy(), tr, stats
 
 
-@pytest.mark.parametrize("path", ["inorder", "plain", "device"])
+@pytest.mark.parametrize("path", ["inorder", "plain", "device", "device_window"])
 def test_tiny_stream_matches_oracle(torch, path):
     for seed in range(4):
         say(f"tiny seed={seed} path={path}")
@@ -65,7 +74,8 @@ def test_tiny_stream_matches_oracle(torch, path):
         assert stats["retired"] == len(st.kernels)
 
 
-@pytest.mark.parametrize("path,W", [("plain", 8), ("device", 8), ("device", 1), ("device", 64), ("plain", 2)])
+@pytest.mark.parametrize("path,W", [("plain", 8), ("device", 8), ("device", 1), ("device", 64), ("plain", 2),
+                                    ("device_window", 8), ("device_window", 1), ("device_window", 64)])
 def test_tiny_stream_schedule_is_valid(torch, path, W):
     for seed in range(3):
         say(f"tiny schedule seed={seed} path={path} W={W}")
@@ -75,7 +85,7 @@ def test_tiny_stream_schedule_is_valid(torch, path, W):
         # the oracle's ranges on the same addresses as the run (any base works:
         # conflicts only depend on relative placement)
         accs = O.tiny_accesses(st, base=0)
-        code, msg = O.check_trace(accs, W, tr, check_times=True, early=(path == "device"))
+        code, msg = O.check_trace(accs, W, tr, check_times=True, early=path.startswith("device"))
         assert code == 0, msg
 
 
@@ -129,14 +139,15 @@ def compare_step(g, ref, step):
 
 @pytest.mark.parametrize("path,n,W,wg", [("inorder", 64, 32, 1), ("plain", 64, 32, 1), ("device", 64, 32, 1),
                                           ("device", 16, 8, 1), ("device", 300, 16, 2), ("plain", 300, 16, 2),
-                                          ("device", 1024, 32, 4)])
+                                          ("device", 1024, 32, 4), ("device_window", 64, 32, 1),
+                                          ("device_window", 300, 16, 2)])
 def test_rl_steps_match_oracle(torch, path, n, W, wg):
     steps = 6 if n <= 300 else 2
     sc = inputs.rl_scene(seed=1, n=n)
     g = acs.RLSceneGPU(sc)
     ref = O.Scene.from_inputs(sc)
     accs = []
-    with acs.Window(W, path=path, trace=True, wg_per_task=wg, trace_capacity=1 << 16) as w:
+    with window(W, path, trace=True, wg_per_task=wg, trace_capacity=1 << 16) as w:
         for step in range(steps):
             say(f"rl path={path} n={n} W={W} step={step}")
             counts, _ = acs.rl_run(w, g, 1)
@@ -147,7 +158,7 @@ def test_rl_steps_match_oracle(torch, path, n, W, wg):
             compare_step(g, ref, step)
         tr = w.trace()
     if path != "inorder":
-        code, msg = O.check_trace(accs, W, tr, check_times=True, early=(path == "device"))
+        code, msg = O.check_trace(accs, W, tr, check_times=True, early=path.startswith("device"))
         assert code == 0, msg
 
 

@@ -312,6 +312,104 @@ def test_host_check_gate_holds_back_past_a_long_kernel(sim):
     assert np.all(tr["ev_insert"][M + 1:] > tr["ev_retire"][0])
 
 
+def _run_checkwave(sim, W, workers, descs, n, ring=64):
+    sim.sim_run_checkwave.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_uint32, C.c_void_p, C.c_double,
+                                      C.POINTER(C.c_uint64)]
+    tr = np.zeros(n, dtype=acs.TRACE_DTYPE)
+    retired = C.c_uint64()
+    rc = sim.sim_run_checkwave(W, workers, n, descs, ring, tr.ctypes.data, 120.0, C.byref(retired))
+    assert rc == 0 and retired.value == n
+    return tr
+
+
+@pytest.mark.timeout(300, method="thread")
+@pytest.mark.parametrize("seed,W,workers,ring", [(0, 8, 2, 64), (1, 16, 3, 16), (2, 32, 2, 64), (5, 64, 3, 128),
+                                                 (6, 3, 2, 8)])
+def test_check_wave_mode_through_kernel_source(sim, seed, W, workers, ring):
+    """The split made inside the device: the check wave tests each staged
+    kernel against the 64 submitted before it, the window wave keeps the
+    ones still in the window.  Same bits as in-order execution, and the
+    trace passes the checker (every conflicting kernel in the window is an
+    upstream kernel at insert, none missed, none extra)."""
+    st = inputs.tiny_stream(seed, n_kernels=160)
+    arena = st.init.copy()
+    descs = _descs(st, arena.ctypes.data)
+    tr = _run_checkwave(sim, W, workers, descs, len(st.kernels), ring)
+    assert np.array_equal(arena.view(np.uint32), O.tiny_run(st).view(np.uint32))
+    code, msg = O.check_trace(O.tiny_accesses(st), W, tr, check_times=True, early=True)
+    assert code == 0, msg
+
+
+def random_nop_descs(seed, n, base):
+    """n no-op kernels with 0-3 writes and 0-4 reads (at least one range)
+    over a small address range, so that reads meet reads, writes and
+    partial overlaps; returns the descriptors and the oracle's accesses."""
+    g = np.random.default_rng(seed)
+    descs = (SimDesc * n)()
+    accs = []
+    for i in range(n):
+        nw, nr = int(g.integers(0, 4)), int(g.integers(0, 5))
+        if nw + nr == 0:
+            nw = 1
+        rng = [(base + int(g.integers(0, 4000)), int(g.integers(1, 300))) for _ in range(nw + nr)]
+        r, w = rng[:nr], rng[nr:]
+        d = descs[i]
+        d.kid, d.npieces = acs.K_NOP, 1
+        segs = [(s0, s0 + z) for s0, z in r] + [(s0, s0 + z) for s0, z in w]
+        d.nseg = len(segs)
+        d.wbits = sum(1 << (nr + j) for j in range(nw))
+        for j, (s0, e0) in enumerate(segs):
+            d.s[j], d.e[j] = s0, e0
+        a = bytes(acs.ArgsNop(0))
+        C.memmove(d.args, a, len(a))
+        accs.append(O.make_access(r, w))
+    return descs, accs
+
+
+@pytest.mark.timeout(300, method="thread")
+@pytest.mark.parametrize("seed,W", [(0, 16), (1, 64), (2, 5)])
+def test_check_wave_mixed_write_counts(sim, seed, W):
+    """Kernels with different numbers of writes (so that a kernel's first
+    positions are writes for some and reads for others): the upstream mask
+    recorded at every insert is exactly the window's conflicting kernels."""
+    buf = np.zeros(4096 + 512, np.uint8)
+    descs, accs = random_nop_descs(seed, 300, buf.ctypes.data)
+    tr = _run_checkwave(sim, W, 3, descs, len(accs))
+    code, msg = O.check_trace(accs, W, tr, check_times=True, early=True)
+    assert code == 0, msg
+
+
+@pytest.mark.timeout(300, method="thread")
+def test_check_wave_gate_holds_back_past_a_long_kernel(sim):
+    """A long kernel writes byte 0, seventy independent kernels follow, then
+    one reads byte 0: seventy-one places back, out of the check wave's reach.
+    The gate keeps every kernel more than 64 younger than the long one out
+    of the window until it is done, so the reader still waits for it."""
+    buf = np.zeros(8192, np.uint8)
+    base = buf.ctypes.data
+    specs = [([], [(base, 1)], 3_000_000)] + [([], [(base + 64 * (i + 1), 1)], 0) for i in range(70)] + \
+        [([(base, 1)], [(base + 6000, 1)], 0)]
+    n = len(specs)
+    descs = (SimDesc * n)()
+    accs = []
+    for i, (r, w, spin) in enumerate(specs):
+        d = descs[i]
+        d.kid, d.npieces = acs.K_NOP, 1
+        segs = [(s0, s0 + z) for s0, z in r] + [(s0, s0 + z) for s0, z in w]
+        d.nseg = len(segs)
+        d.wbits = sum(1 << (len(r) + j) for j in range(len(w)))
+        for j, (s0, e0) in enumerate(segs):
+            d.s[j], d.e[j] = s0, e0
+        a = bytes(acs.ArgsNop(spin))
+        C.memmove(d.args, a, len(a))
+        accs.append(O.make_access(r, w))
+    tr = _run_checkwave(sim, 16, 3, descs, n)
+    code, msg = O.check_trace(accs, 16, tr, check_times=True, early=True)
+    assert code == 0, msg
+    assert tr["t_start"][n - 1] >= tr["t_end"][0]
+    assert np.all(tr["ev_insert"][65:] > tr["ev_retire"][0])
+
+
 @pytest.mark.timeout(300, method="thread")
 def test_join_pool_fc_bodies_through_kernel_source(sim):
     """The elementwise join (vector and scalar tails, several pieces), the
