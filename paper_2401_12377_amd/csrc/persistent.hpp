@@ -527,7 +527,9 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                                                           ((hup >> (back & 63u)) & 1ull));
                     }
                     upm &= valid;
-                    if (sl == (uint32_t)slot && rep < R) {
+                    // the slot's ranges and their classes serve only the
+                    // window wave's own pair tests
+                    if (!hc && sl == (uint32_t)slot && rep < R) {
 #pragma unroll
                         for (int m = 0; m < kSegs; m++) {
                             ss[m] = d->s[m];
@@ -543,12 +545,14 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                         if (np > 1) target += kWave * np;
                         __hip_atomic_store(&p.st->task[slot].ptarget, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
-                    const uint64_t rbit = bit * repmul;
+                    if (!hc) {
+                        const uint64_t rbit = bit * repmul;
 #pragma unroll
-                    for (int m = 0; m < kSegs; m++)
-                        wmask[m] = ((uint32_t)m < nseg && ((wb >> m) & 1u)) ? (wmask[m] | rbit) : (wmask[m] & ~rbit);
-                    over4 = nseg > 4u ? (over4 | bit) : (over4 & ~bit);
-                    over2 = nseg > 2u ? (over2 | bit) : (over2 & ~bit);
+                        for (int m = 0; m < kSegs; m++)
+                            wmask[m] = ((uint32_t)m < nseg && ((wb >> m) & 1u)) ? (wmask[m] | rbit) : (wmask[m] & ~rbit);
+                        over4 = nseg > 4u ? (over4 | bit) : (over4 & ~bit);
+                        over2 = nseg > 2u ? (over2 | bit) : (over2 & ~bit);
+                    }
                     if (tr && lane == 0 && seq < p.trace_cap) {
                         trace_insert(&p.trace[seq], seq, slot, kid, ev, valid, upm);
                     }
@@ -686,13 +690,15 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
 #pragma unroll
                 for (int g = 0; g < NG; g++)
                     if (g < G) retired[g] += __builtin_popcountll(done & (wpmask << (g * Wp)));
-                if (((done >> sl) & 1ull) && rep < R) {
+                if (!hc) {
+                    if (((done >> sl) & 1ull) && rep < R) {
 #pragma unroll
-                    for (int m = 0; m < kSegs; m++) ss[m] = se[m] = 0;
+                        for (int m = 0; m < kSegs; m++) ss[m] = se[m] = 0;
+                    }
+                    const uint64_t rdone = done * repmul;
+#pragma unroll
+                    for (int m = 0; m < kSegs; m++) wmask[m] &= ~rdone;
                 }
-                const uint64_t rdone = done * repmul;
-#pragma unroll
-                for (int m = 0; m < kSegs; m++) wmask[m] &= ~rdone;
                 up &= ~done;
                 valid &= ~done;
                 exec &= ~done;
