@@ -64,8 +64,7 @@ struct HostCtrl {
     volatile uint64_t alive;                // set when the scheduler wave starts
     volatile uint64_t exited;               // set when the scheduler wave leaves
     volatile uint64_t checks;               // overlap tests made by the window wave (statistics)
-    volatile uint64_t check_wave_tests;     // overlap tests made by the check wave (statistics)
-    uint64_t pad1[1];
+    volatile uint64_t check_wave_tests[2];  // overlap tests made by each check wave (statistics)
     acs_entry snap[ACS_W_MAX];
 };
 

@@ -248,7 +248,7 @@ public:
                     return ACS_EDEVICE;
                 }
             }
-            checks_ = ctrl_->checks + ctrl_->check_wave_tests;
+            checks_ = ctrl_->checks + ctrl_->check_wave_tests[0] + ctrl_->check_wave_tests[1];
             running_ = false;
             float ms = 0.0f;
             if (hipEventElapsedTime(&ms, ev0_, ev1_) == hipSuccess) kernel_ns_ = (uint64_t)((double)ms * 1e6);
@@ -284,7 +284,9 @@ public:
         for (int32_t g = 0; g < groups_; g++) ret += ctrl_ ? ctrl_->retired[g] : submitted_[g];
         s.retired = ret;
         s.dispatched = s.retired;
-        s.overlap_tests = (running_ && ctrl_ ? ctrl_->checks + ctrl_->check_wave_tests : checks_) + host_tests_;
+        s.overlap_tests = (running_ && ctrl_ ? ctrl_->checks + ctrl_->check_wave_tests[0] + ctrl_->check_wave_tests[1]
+                                            : checks_) +
+                          host_tests_;
         s.n_workers = n_workers_;
         s.kernel_ns = kernel_ns_;
     }

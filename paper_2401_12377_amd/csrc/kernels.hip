@@ -74,7 +74,7 @@ __global__ __launch_bounds__(ACS_BLOCK) void k_persistent(DevParams p)
         const uint32_t wave = uni32(threadIdx.x) >> 6;   // uniform: whole waves take each branch
         if (wave == 0) window_wave<NG>(p, fs);
         else if (wave == 1) fifo_wave<NG>(p, fs);
-        else if (NG == 1 && wave == 2 && p.check_wave) check_wave(p, fs);
+        else if (NG == 1 && wave >= 2 && p.check_wave) check_wave(p, fs, wave - 2);
         return;
     }
     worker(p, smem, &mail);

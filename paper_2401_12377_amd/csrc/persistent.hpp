@@ -15,9 +15,9 @@
 //   wave 1  the input FIFO: copies descriptors from the host-resident rings
 //           into small rings in LDS, so that host-memory latency never
 //           stalls the window loop.
-//   wave 2  (one window, checks ahead of the window) tests each staged
-//           kernel against the 64 submitted before it, then hands it on to
-//           the window wave.
+//   waves 2 and 3  (one window, checks ahead of the window) test each staged
+//           kernel against the 64 submitted before it, alternating between
+//           them, then hand it on to the window wave.
 // The lanes of the window wave may be split into up to eight groups, each an
 // independent window with its own input ring (for many independent task
 // graphs in one launch): one insertion pass then admits one kernel into every
@@ -57,6 +57,7 @@ constexpr uint32_t kAdmitBatch = 16;  // insertion passes per loop (measured: ad
 struct FetchShared {
     uint32_t tail[kMaxGroups];   // descriptors ready for the window wave per group (FIFO or check wave)
     uint32_t staged;             // checks ahead of the window: descriptors copied, not yet checked
+    uint32_t recorded[2];        // checks ahead of the window: descriptors each check wave has read
     uint32_t head[kMaxGroups];   // descriptors taken per group (written by the window wave)
     uint32_t stop;               // mirror of the host stop flag
     uint32_t exit;               // window wave -> FIFO wave: leave
@@ -72,6 +73,7 @@ __device__ inline void fetch_init(FetchShared *fs)
 {
     for (int g = 0; g < kMaxGroups; g++) fs->tail[g] = fs->head[g] = 0;
     fs->staged = 0;
+    fs->recorded[0] = fs->recorded[1] = 0;
     fs->stop = 0;
     fs->exit = 0;
     fs->snap_req = 0;
@@ -139,8 +141,9 @@ __device__ inline void history_init(SeqHistory &h)
     h.mw = 0;
 }
 
-// d: the staged descriptor (LDS); returns the pair tests made
-__device__ inline uint64_t history_check(DevDesc *d, SeqHistory &h, uint32_t lane)
+// d: the staged descriptor (LDS).  test: check the kernel and write its
+// upstream word (else only record it); returns the pair tests made.
+__device__ inline uint64_t history_check(DevDesc *d, SeqHistory &h, uint32_t lane, bool test)
 {
     const uint32_t dw = reinterpret_cast<const uint32_t *>(d)[lane];
     // the new kernel's ranges, for its place in the history: loaded by every
@@ -158,7 +161,7 @@ __device__ inline uint64_t history_check(DevDesc *d, SeqHistory &h, uint32_t lan
     const uint32_t wb = readlane32(dw, 5) & segmask;
     const uint32_t wtop = wb ? 32u - (uint32_t)__builtin_clz(wb) : 0u;
     bool hit = false;
-    for (uint32_t k = 0; k < nseg; k++) {
+    for (uint32_t k = 0; test && k < nseg; k++) {
         const uint64_t a0 = readpair(dw, kSegStartDword + 2 * (int)k), a1 = readpair(dw, kSegEndDword + 2 * (int)k);
         // no branch per position: unused positions hold [0, 0), which
         // meets nothing; only the reads' bound on positions is tested
@@ -175,7 +178,8 @@ __device__ inline uint64_t history_check(DevDesc *d, SeqHistory &h, uint32_t lan
         }
     }
     const uint32_t nw = (uint32_t)__builtin_popcount(wb);
-    const uint64_t tests = (uint64_t)(nw * kSegs + (nseg - nw) * (h.mw > 2u ? kSegs : 2u)) * (seq < 64 ? seq : 64);
+    const uint64_t tests =
+        test ? (uint64_t)(nw * kSegs + (nseg - nw) * (h.mw > 2u ? kSegs : 2u)) * (seq < 64 ? seq : 64) : 0ull;
     // bit b of the result is the kernel b + 1 places back, held by lane
     // r - b mod 64 (r = seq - 1 mod 64): the lane mask reversed (lane l to
     // bit 63 - l) and rotated right by 63 - r.  There is none when b >= seq.
@@ -185,7 +189,7 @@ __device__ inline uint64_t history_check(DevDesc *d, SeqHistory &h, uint32_t lan
     uint64_t up = rot ? ((rv >> rot) | (rv << (64u - rot))) : rv;
     if (seq < 64) up &= (1ull << seq) - 1ull;
     uint32_t *words = reinterpret_cast<uint32_t *>(d);
-    if (lane == 0) {
+    if (test && lane == 0) {
         words[kHostUpDword] = (uint32_t)up;
         words[kHostUpDword + 1] = (uint32_t)(up >> 32);
     }
@@ -241,7 +245,15 @@ __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
             cnt[g] = 0;
             start[g] = total;
             if (g < G) {
-                const uint32_t space = depth - (ftail[g] - uni32(LDS_LOAD(&fs->head[g])));
+                // a slot is free once the window wave took its kernel and, with
+                // the checks ahead of the window, both check waves read it
+                uint32_t freed = uni32(LDS_LOAD(&fs->head[g]));
+                if (fc) {
+                    const uint32_t r0 = uni32(LDS_LOAD(&fs->recorded[0])), r1 = uni32(LDS_LOAD(&fs->recorded[1]));
+                    freed = (int32_t)(r0 - freed) < 0 ? r0 : freed;
+                    freed = (int32_t)(r1 - freed) < 0 ? r1 : freed;
+                }
+                const uint32_t space = depth - (ftail[g] - freed);
                 const uint64_t avail = htail[g] - consumed[g];
                 uint32_t n = avail < space ? (uint32_t)avail : space;
                 if (n > kJobs - total) n = kJobs - total;
@@ -323,10 +335,13 @@ __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
     }
 }
 
-// Wave 2 when the checks run ahead of the window (one window): takes the
-// kernels the FIFO wave staged, in order, checks each against the history
-// and hands it to the window wave.  Leaves with the window wave.
-__device__ inline void check_wave(const DevParams &p, FetchShared *fs)
+// Waves 2 and 3 when the checks run ahead of the window (one window): both
+// take every kernel the FIFO wave staged, in order, and record it in their
+// own copy of the history; wave 2 + c checks the kernels of staged index
+// c mod 2 and hands each to the window wave once the other wave has handed
+// on the kernel before it, so kernels reach the window in order while two
+// checks run at once.  They leave with the window wave, or on an abort.
+__device__ inline void check_wave(const DevParams &p, FetchShared *fs, uint32_t c)
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t depth = lds_depth(1);
@@ -334,7 +349,8 @@ __device__ inline void check_wave(const DevParams &p, FetchShared *fs)
     history_init(hist);
     uint64_t tests = 0;
     uint32_t done = 0;
-    for (;;) {
+    bool abort = false;
+    while (!abort) {
         const uint32_t staged = uni32(LDS_LOAD(&fs->staged));
         if (staged == done) {
             if (uni32(LDS_LOAD(&fs->exit)) || uni32(LDS_LOAD(&fs->stop)) == 2u) break;
@@ -343,14 +359,30 @@ __device__ inline void check_wave(const DevParams &p, FetchShared *fs)
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         for (; done != staged; done++) {
-            tests += history_check(&fs->ring[done % depth], hist, lane);
+            const bool mine = (done & 1u) == c;
+            tests += history_check(&fs->ring[done % depth], hist, lane, mine);
+            // this wave is done reading the staged descriptor
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (lane == 0) LDS_STORE(&fs->recorded[c], done + 1);
+            if (!mine) continue;
+            // the kernel before this one is handed on by the other wave
+            for (uint32_t spin = 1; uni32(LDS_LOAD(&fs->tail[0])) != done; spin++) {
+                if ((spin & 255u) == 0 && uni32(LDS_LOAD(&fs->stop)) == 2u) {
+                    abort = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (abort) break;
             // the upstream word lands before the kernel is handed on
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             if (lane == 0) LDS_STORE(&fs->tail[0], done + 1);
         }
     }
-    if (lane == 0) __hip_atomic_store(&p.ctrl->check_wave_tests, tests, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (lane == 0)
+        __hip_atomic_store(&p.ctrl->check_wave_tests[c], tests, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Trace records are written with device-scope stores like everything else

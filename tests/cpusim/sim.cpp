@@ -55,8 +55,8 @@ void run_thread(const acs::DevParams &p, Block *b, uint32_t t, uint32_t blk)
             else if (ng <= 2) acs::fifo_wave<2>(p, fs);
             else if (ng <= 4) acs::fifo_wave<4>(p, fs);
             else acs::fifo_wave<8>(p, fs);
-        } else if (wave == 2 && ng <= 1 && p.check_wave) {
-            acs::check_wave(p, fs);
+        } else if (wave >= 2 && ng <= 1 && p.check_wave) {
+            acs::check_wave(p, fs, wave - 2);
         }
     } else {
         worker(p, b->lds, &b->mail);

@@ -1,6 +1,6 @@
 """The persistent scheduler kernel's own source, built for the CPU.
 
-tests/cpusim/sim.cpp compiles the window wave, the FIFO wave and the worker
+tests/cpusim/sim.cpp compiles the window wave, the FIFO wave, the check waves and the worker
 loop (persistent.hpp, bodies.hpp) against a host emulation of the HIP
 built-ins they use, one OS thread per GPU thread.  These tests push the tiny
 random stream through that build and compare with the oracle: the arena must
@@ -367,14 +367,16 @@ def random_nop_descs(seed, n, base):
 
 
 @pytest.mark.timeout(300, method="thread")
-@pytest.mark.parametrize("seed,W", [(0, 16), (1, 64), (2, 5)])
-def test_check_wave_mixed_write_counts(sim, seed, W):
+@pytest.mark.parametrize("seed,W,n,ring", [(0, 16, 300, 64), (1, 64, 300, 64), (2, 5, 300, 64), (3, 64, 700, 16)])
+def test_check_wave_mixed_write_counts(sim, seed, W, n, ring):
     """Kernels with different numbers of writes (so that a kernel's first
     positions are writes for some and reads for others): the upstream mask
-    recorded at every insert is exactly the window's conflicting kernels."""
+    recorded at every insert is exactly the window's conflicting kernels.
+    700 kernels wrap the staging ring several times while the two check
+    waves alternate."""
     buf = np.zeros(4096 + 512, np.uint8)
-    descs, accs = random_nop_descs(seed, 300, buf.ctypes.data)
-    tr = _run_checkwave(sim, W, 3, descs, len(accs))
+    descs, accs = random_nop_descs(seed, n, buf.ctypes.data)
+    tr = _run_checkwave(sim, W, 3, descs, len(accs), ring)
     code, msg = O.check_trace(accs, W, tr, check_times=True, early=True)
     assert code == 0, msg
 
