@@ -716,8 +716,8 @@ constexpr int kConvKC = 32;   // K columns per step of one wave
 // step's channels q * 8 + s (q = lane / 16), so each lane loads its pixel's
 // eight channels q * 8 .. q * 8 + 7 as two 16-byte loads and no staging
 // through LDS is needed.  Because cin is a multiple of 32, a step never
-// straddles two (ky, kx) taps.  Each wave loads its next step while the
-// matrix unit works on the current one.  The four partial tiles meet in LDS
+// straddles two (ky, kx) taps.  Each wave keeps the loads of its next two
+// steps in flight while the matrix unit works on the current one.  The four partial tiles meet in LDS
 // and are added in wave order, then the bias: the same order on every path
 // and for every piece count.
 struct ConvStep {
@@ -746,6 +746,17 @@ __device__ __forceinline__ void conv_load(const acs_args_conv &a, int32_t py, in
     }
 }
 
+// one step: eight k of the 16x16 products of both column halves, in k order
+__device__ __forceinline__ void conv_mma(const ConvStep &v, acs_v4f &acc0, acs_v4f &acc1)
+{
+    const float av[8] = {v.a0.x, v.a0.y, v.a0.z, v.a0.w, v.a1.x, v.a1.y, v.a1.z, v.a1.w};
+#pragma unroll
+    for (int s = 0; s < 8; s++) {
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], v.b0[s], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], v.b1[s], acc1, 0, 0, 0);
+    }
+}
+
 template <bool DEV>
 __device__ inline void conv_tile(const acs_args_conv &a, int32_t m0, int32_t n0, uint8_t *smem)
 {
@@ -756,17 +767,20 @@ __device__ inline void conv_tile(const acs_args_conv &a, int32_t m0, int32_t n0,
     const int32_t i = lane & 15, q = lane >> 4;
     const int32_t pm = m0 + i, py = pm / hout, px = pm % hout;
     acs_v4f acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
-    ConvStep cur, nxt;
-    if (wv < nsteps) conv_load(a, py, px, n0, wv * kConvKC, q, i, nxt);
-    for (int32_t step = wv; step < nsteps; step += 4) {
-        cur = nxt;
-        if (step + 4 < nsteps) conv_load(a, py, px, n0, (step + 4) * kConvKC, q, i, nxt);
-        const float av[8] = {cur.a0.x, cur.a0.y, cur.a0.z, cur.a0.w, cur.a1.x, cur.a1.y, cur.a1.z, cur.a1.w};
-#pragma unroll
-        for (int s = 0; s < 8; s++) {
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], cur.b0[s], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], cur.b1[s], acc1, 0, 0, 0);
-        }
+    // this wave's steps wv, wv + 4, ... with the loads of the next two in
+    // flight while one is multiplied (three steps of operands resident)
+    ConvStep s0, s1, s2;
+    if (wv < nsteps) conv_load(a, py, px, n0, wv * kConvKC, q, i, s0);
+    if (wv + 4 < nsteps) conv_load(a, py, px, n0, (wv + 4) * kConvKC, q, i, s1);
+    for (int32_t step = wv; step < nsteps; step += 12) {
+        if (step + 8 < nsteps) conv_load(a, py, px, n0, (step + 8) * kConvKC, q, i, s2);
+        conv_mma(s0, acc0, acc1);
+        if (step + 4 >= nsteps) break;
+        if (step + 12 < nsteps) conv_load(a, py, px, n0, (step + 12) * kConvKC, q, i, s0);
+        conv_mma(s1, acc0, acc1);
+        if (step + 8 >= nsteps) break;
+        if (step + 16 < nsteps) conv_load(a, py, px, n0, (step + 16) * kConvKC, q, i, s1);
+        conv_mma(s2, acc0, acc1);
     }
     // partial tiles: part[w][row][col], 4 x 16 x 32 floats
     float *part = reinterpret_cast<float *>(smem);
