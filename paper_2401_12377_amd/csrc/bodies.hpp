@@ -388,7 +388,8 @@ __device__ inline void body_rl_broadphase(const acs_args_rl &a, uint8_t *smem)
 // body with the smallest body of its component), then islands ordered by that
 // smallest body, bodies inside an island in index order, the adjacency in
 // permuted positions, and the plan of multi-body islands for the host.
-// At most 64 bodies, one wave: neighbour sets as 64-bit masks, components by
+// At most 64 bodies: the workgroup stages the adjacency in LDS, then one
+// wave works: neighbour sets as 64-bit masks, components by
 // Warshall's transitive closure (row k is final once step k has run, so all
 // lanes update in parallel), each body's island is its closure and its label
 // the closure's smallest body.  Positions: islands in label order, bodies in
@@ -396,22 +397,37 @@ __device__ inline void body_rl_broadphase(const acs_args_rl &a, uint8_t *smem)
 template <bool DEV>
 __device__ inline void islands_small(const acs_args_rl &a, const RLView &v, int32_t *plan, uint8_t *smem)
 {
-    if (wave_index() != 0) return;
     const int32_t n = a.n, lane = threadIdx.x & 63;
     const bool in = lane < n;
     int32_t *s_perm = reinterpret_cast<int32_t *>(smem);   // [64] body at each position
     int32_t *s_inv = s_perm + 64;                          // [64] position of each body
+    int32_t *s_adj = s_inv + 64;                           // [cap] the adjacency, staged
     const int32_t cap = n * (n - 1);
+    // the whole workgroup stages the adjacency in LDS with independent
+    // loads, so that no lane walks its neighbours through dependent global
+    // loads; offsets past the staged part are clamped to it
+    int32_t ecount = v.adj_off[n];
+    ecount = ecount < 0 ? 0 : (ecount > cap ? cap : ecount);
+    for (int32_t k = (int32_t)threadIdx.x; k < ecount; k += 4 * ACS_BLOCK) {
+        int32_t c[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) c[u] = k + u * ACS_BLOCK < ecount ? v.adj[k + u * ACS_BLOCK] : 0;
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (k + u * ACS_BLOCK < ecount) s_adj[k + u * ACS_BLOCK] = c[u];
+    }
+    __syncthreads();
+    if (wave_index() != 0) return;
     int32_t o0 = 0, o1 = 0;
     if (in) {
         o0 = v.adj_off[lane];
         o1 = v.adj_off[lane + 1];
-        o0 = o0 < 0 ? 0 : (o0 > cap ? cap : o0);
-        o1 = o1 < o0 ? o0 : (o1 > cap ? cap : o1);
+        o0 = o0 < 0 ? 0 : (o0 > ecount ? ecount : o0);
+        o1 = o1 < o0 ? o0 : (o1 > ecount ? ecount : o1);
     }
     uint64_t reach = in ? (1ull << lane) : 0ull;
     for (int32_t k = o0; k < o1; k++) {
-        const int32_t c = v.adj[k];
+        const int32_t c = s_adj[k];
         if ((uint32_t)c < (uint32_t)n) reach |= 1ull << c;
     }
     for (int32_t k = 0; k < n; k++) {
@@ -454,7 +470,7 @@ __device__ inline void islands_small(const acs_args_rl &a, const RLView &v, int3
     if (in) put<DEV>(&v.padj_off[lane], poff);
     if (lane == 0) put<DEV>(&v.padj_off[n], ep);
     for (int32_t k = 0; in && k < db; k++) {
-        const int32_t c = v.adj[ob + k];
+        const int32_t c = s_adj[ob + k];
         if (poff + k < cap) put<DEV>(&v.padj[poff + k], ((uint32_t)c < (uint32_t)n) ? s_inv[c] : lane);
     }
     // plan: multi-body islands in label order
@@ -611,7 +627,36 @@ __device__ inline void body_rl_permute(const acs_args_rl &a, uint32_t piece, uin
     }
 }
 
-// One Jacobi iteration over the island's positions [b0, b1).
+// One Jacobi iteration over the island's positions [b0, b1).  The first
+// kJacobiAhead neighbours of a position are loaded ahead (their indices,
+// then their positions, each batch independent loads) and then taken in
+// edge order, as are any further ones: the same arithmetic in the same order.
+constexpr int kJacobiAhead = 8;
+
+__device__ __forceinline__ void jacobi_edge(const float4 &qp, const float4 &qq, int32_t p, int32_t q, float two_r,
+                                            float &ax, float &ay, float &az)
+{
+    const float dx = qp.x - qq.x, dy = qp.y - qq.y, dz = qp.z - qq.z;
+    const float d = sqrtf(dist2(dx, dy, dz));
+    const float pen = two_r - d;
+    if (pen > 0.0f) {
+        const float h = 0.5f * pen;
+        float nx, ny, nz;
+        if (d > 0.0f) {
+            nx = dx / d;
+            ny = dy / d;
+            nz = dz / d;
+        } else {
+            nx = (p < q) ? 1.0f : -1.0f;
+            ny = 0.0f;
+            nz = 0.0f;
+        }
+        ax = fmaf(h, nx, ax);
+        ay = fmaf(h, ny, ay);
+        az = fmaf(h, nz, az);
+    }
+}
+
 template <bool DEV>
 __device__ inline void body_rl_jacobi(const acs_args_rl &a)
 {
@@ -626,29 +671,23 @@ __device__ inline void body_rl_jacobi(const acs_args_rl &a)
         int32_t e0 = v.padj_off[p], e1 = v.padj_off[p + 1];
         e0 = e0 < 0 ? 0 : (e0 > cap ? cap : e0);
         e1 = e1 < e0 ? e0 : (e1 > cap ? cap : e1);
-        for (int32_t e = e0; e < e1; e++) {
-            int32_t q = v.padj[e];
+        int32_t qi[kJacobiAhead];
+#pragma unroll
+        for (int u = 0; u < kJacobiAhead; u++) {
+            int32_t q = e0 + u < e1 ? v.padj[e0 + u] : p;
             if ((uint32_t)q >= (uint32_t)a.n) q = p;   // never true for islands output
-            const float4 qq = src[q];
-            const float dx = qp.x - qq.x, dy = qp.y - qq.y, dz = qp.z - qq.z;
-            const float d = sqrtf(dist2(dx, dy, dz));
-            const float pen = two_r - d;
-            if (pen > 0.0f) {
-                const float h = 0.5f * pen;
-                float nx, ny, nz;
-                if (d > 0.0f) {
-                    nx = dx / d;
-                    ny = dy / d;
-                    nz = dz / d;
-                } else {
-                    nx = (p < q) ? 1.0f : -1.0f;
-                    ny = 0.0f;
-                    nz = 0.0f;
-                }
-                ax = fmaf(h, nx, ax);
-                ay = fmaf(h, ny, ay);
-                az = fmaf(h, nz, az);
-            }
+            qi[u] = q;
+        }
+        float4 qv[kJacobiAhead];
+#pragma unroll
+        for (int u = 0; u < kJacobiAhead; u++) qv[u] = src[qi[u]];
+#pragma unroll
+        for (int u = 0; u < kJacobiAhead; u++)
+            if (e0 + u < e1) jacobi_edge(qp, qv[u], p, qi[u], two_r, ax, ay, az);
+        for (int32_t e = e0 + kJacobiAhead; e < e1; e++) {
+            int32_t q = v.padj[e];
+            if ((uint32_t)q >= (uint32_t)a.n) q = p;
+            jacobi_edge(qp, src[q], p, q, two_r, ax, ay, az);
         }
         const float deg = (float)(e1 - e0);
         float4 o;

@@ -17,6 +17,7 @@ parity tests cover the latter.
 from __future__ import annotations
 
 import ctypes as C
+import time
 import os
 import subprocess
 
@@ -139,9 +140,10 @@ def test_conv_tile_through_kernel_source(sim, h, cin, cout, k, s):
 @pytest.mark.timeout(180, method="thread")
 @pytest.mark.parametrize("n", [8, 33, 64, 80])
 def test_rl_prefix_through_kernel_source(sim, n):
-    """predict, broadphase, islands and permute of one RL step through the
-    kernel source (the one-wave paths for at most 64 bodies, the workgroup
-    paths above), against the oracle's step: integer buffers bit-exact."""
+    """One RL step through the kernel source: predict, broadphase, islands
+    and permute (the one-wave paths for at most 64 bodies, the workgroup
+    paths above), then the plan's Jacobi kernels and integrate, against the
+    oracle's step: integer buffers and positions and velocities bit-exact."""
     sc = inputs.rl_scene(seed=11, n=n)
     off = acs.rl_layout(n)
     arena = np.zeros(int(off[acs.RL_END]), np.uint8)
@@ -179,6 +181,27 @@ def test_rl_prefix_through_kernel_source(sim, n):
     assert plan[0] == ref.meta[0] and plan[1] == ref.meta[1] and plan[2] == ref.meta[2]
     assert np.array_equal(plan[4:4 + 4 * m], ref.plan[:4 * m])
     assert np.array_equal(region(acs.RL_Q0, np.uint32, 4 * n), ref.Q0.view(np.uint32).reshape(-1))
+    # the rest of the step from the plan just written: the Jacobi kernels
+    # (iteration-major) and integrate, against the oracle's whole step
+    tail = []
+    for it in range(sc.iters):
+        for q in range(m):
+            tail.append((acs.K_RL_JACOBI, it, int(plan[4 + 4 * q]), int(plan[5 + 4 * q])))
+    tail.append((acs.K_RL_INTEGRATE, 0, 0, 0))
+    descs = (SimDesc * len(tail))()
+    for i, (kid, it, b0, b1) in enumerate(tail):
+        a = acs.ArgsRL()
+        a.base, a.plan, a.n, a.r, a.dt = arena.ctypes.data, plan.ctypes.data, n, float(sc.radius), float(sc.dt)
+        a.iter, a.b0, a.b1 = it, b0, b1
+        d = descs[i]
+        d.kid, d.npieces, d.nseg, d.wbits = kid, 1, 1, 1
+        d.s[0], d.e[0] = arena.ctypes.data, arena.ctypes.data + arena.nbytes
+        C.memmove(d.args, bytes(a), C.sizeof(a))
+    assert sim.sim_run(4, 2, len(tail), descs, 8, None, 120.0, C.byref(retired)) == 0
+    full = O.Scene.from_inputs(sc)
+    full.step()
+    assert np.array_equal(region(acs.RL_X, np.uint32, 4 * n), full.X.view(np.uint32).reshape(-1))
+    assert np.array_equal(region(acs.RL_V, np.uint32, 4 * n), full.V.view(np.uint32).reshape(-1))
 
 
 def group_trace(tr, ids, g, Wp):
@@ -410,6 +433,32 @@ def test_check_wave_gate_holds_back_past_a_long_kernel(sim):
     assert code == 0, msg
     assert tr["t_start"][n - 1] >= tr["t_end"][0]
     assert np.all(tr["ev_insert"][65:] > tr["ev_retire"][0])
+
+
+@pytest.mark.timeout(120, method="thread")
+def test_check_wave_mode_abort_releases_every_wave(sim):
+    """An abort while kernels are still queued behind a long one: the host
+    gives up after 0.3 s and sets the abort flag; the window, FIFO and check
+    waves and every worker leave (the call returns), with the long kernel's
+    followers not retired."""
+    buf = np.zeros(8192, np.uint8)
+    base = buf.ctypes.data
+    n = 120
+    descs = (SimDesc * n)()
+    for i in range(n):
+        d = descs[i]
+        d.kid, d.npieces, d.nseg, d.wbits = acs.K_NOP, 1, 1, 1
+        d.s[0], d.e[0] = (base, base + 1) if i % 3 == 0 else (base + 64 * i, base + 64 * i + 1)
+        a = bytes(acs.ArgsNop(1_500_000_000 if i == 0 else 0))
+        C.memmove(d.args, a, len(a))
+    sim.sim_run_checkwave.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_uint32, C.c_void_p, C.c_double,
+                                      C.POINTER(C.c_uint64)]
+    retired = C.c_uint64()
+    t0 = time.perf_counter()
+    rc = sim.sim_run_checkwave(8, 2, n, descs, 16, None, 0.3, C.byref(retired))
+    assert rc == -5
+    assert retired.value < n
+    assert time.perf_counter() - t0 < 30
 
 
 @pytest.mark.timeout(300, method="thread")
