@@ -213,7 +213,8 @@ __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
 {
     const uint32_t lane = threadIdx.x & 63u;
     const int32_t G = p.n_groups;
-    const uint32_t depth = lds_depth(G), ring_cap = p.ring_mask + 1;
+    // one window: a constant, so that ring positions are a mask, not a division
+    const uint32_t depth = NG == 1 ? kLdsDescs : lds_depth(G), ring_cap = p.ring_mask + 1;
     constexpr uint32_t kRows = 8, kJobs = kRows * 4;   // descriptors per copy round
     uint64_t consumed[NG], htail[NG], told[NG];
     uint32_t ftail[NG];
@@ -445,7 +446,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
     const int W = p.W, G = p.n_groups;
     const bool tr = p.trace != nullptr;
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const uint32_t depth = lds_depth(G);
+    const uint32_t depth = NG == 1 ? kLdsDescs : lds_depth(G);   // a constant for one window
     const bool hc = NG == 1 && p.host_check > 0;
     const uint64_t hcm = (uint64_t)(p.host_check > 0 ? p.host_check : 0);
 
