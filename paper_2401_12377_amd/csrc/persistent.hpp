@@ -49,7 +49,7 @@
 namespace acs {
 
 constexpr uint32_t kWave = 64;        // lanes of a wavefront
-constexpr uint32_t kLdsDescs = 128;   // descriptors staged in LDS (32 KB), split evenly between groups
+constexpr uint32_t kLdsDescs = 128;   // descriptors staged in LDS (32 KB), shared by the groups (lds_depth)
 constexpr uint32_t kAdmitBatch = 16;  // insertion passes per loop (measured: admitting fewer
                                       // while few kernels are out costs more in extra
                                       // dispatch rounds than it saves in latency)
@@ -66,7 +66,12 @@ struct FetchShared {
 };
 static_assert(sizeof(FetchShared) <= kBodySmem, "FIFO staging must fit the LDS scratch");
 
-__device__ inline uint32_t lds_depth(int32_t groups) { return kLdsDescs / (uint32_t)groups; }
+// Staging slots per group: a power of two (the share of kLdsDescs for the
+// group count rounded up to a power of two), so positions are a mask.
+__device__ inline uint32_t lds_depth(int32_t groups)
+{
+    return groups <= 1 ? kLdsDescs : kLdsDescs >> (32u - (uint32_t)__builtin_clz((uint32_t)groups - 1u));
+}
 
 // by one thread of workgroup 0, before the workgroup barrier that starts the waves
 __device__ inline void fetch_init(FetchShared *fs)
@@ -284,7 +289,7 @@ __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
             if (j < total) {
                 const DevDesc *src = p.ring + (uint64_t)gg * ring_cap + ((cons + ii) & p.ring_mask);
                 v[r] = reinterpret_cast<const uint4 *>(src)[c];
-                dst_off[r] = (gg * depth + (ft + ii) % depth) * 256u + c * 16u;
+                dst_off[r] = (gg * depth + ((ft + ii) & (depth - 1u))) * 256u + c * 16u;
             }
         }
         // control lines: newly published descriptors are read in later
@@ -361,7 +366,7 @@ __device__ inline void check_wave(const DevParams &p, FetchShared *fs, uint32_t 
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         for (; done != staged; done++) {
             const bool mine = (done & 1u) == c;
-            tests += history_check(&fs->ring[done % depth], hist, lane, mine);
+            tests += history_check(&fs->ring[done & (depth - 1u)], hist, lane, mine);
             // this wave is done reading the staged descriptor
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -525,7 +530,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                 // readlane, so everything but the pair tests is scalar
                 const uint64_t full = wmaskslots & wpmask;
                 for (uint32_t pass = 0; pass < passes && head[0] != ftail[0] && valid != full; pass++) {
-                    const DevDesc *d = &fs->ring[head[0] % depth];
+                    const DevDesc *d = &fs->ring[head[0] & (depth - 1u)];
                     const uint32_t dw = reinterpret_cast<const uint32_t *>(d)[lane];
                     const uint64_t seq = readpair(dw, 0);
                     // host-check mode: the host compared this kernel with the M
@@ -620,14 +625,15 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                             hsel = head[g];
                             nsel = newl[g];
                         }
-                    const DevDesc *d = &fs->ring[grp * depth + hsel % depth];
+                    const DevDesc *d = &fs->ring[grp * depth + (hsel & (depth - 1u))];
                     // each admitted descriptor goes to the task table as it is (one
                     // 4-byte word per lane); all groups' words are read first so the
                     // LDS latency is paid once
                     uint32_t dwg[NG];
     #pragma unroll
                     for (int g = 0; g < NG; g++)
-                        dwg[g] = g < G ? reinterpret_cast<const uint32_t *>(&fs->ring[g * depth + head[g] % depth])[lane] : 0u;
+                        dwg[g] = g < G ? reinterpret_cast<const uint32_t *>(&fs->ring[g * depth + (head[g] & (depth - 1u))])[lane]
+                                       : 0u;
                     uint64_t newbits = 0;
     #pragma unroll
                     for (int g = 0; g < NG; g++)
