@@ -947,8 +947,9 @@ __device__ inline void body_copy(const acs_args_copy &a, uint32_t piece, uint32_
 }
 
 // one lane stores; the system-scope release orders it after the writes of
-// every kernel this one waited for (their completions were acquired before
-// the body started)
+// every kernel this one waited for (written through with device scope and
+// counted before this body's worker acquired and started), so the host
+// that sees the flag sees their results
 __device__ inline void body_signal(const acs_args_signal &a)
 {
     if (threadIdx.x == 0) __hip_atomic_store(a.addr, a.value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);

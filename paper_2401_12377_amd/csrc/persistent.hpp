@@ -507,8 +507,8 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
 
         // The completion words are polled first and examined after admission,
         // so that the load's latency overlaps the insertion work.  They are
-        // read relaxed; the acquire that pairs with the workers' releases is
-        // taken once, just before the host is told (below).
+        // read relaxed: the window wave reads no task results, and the
+        // workers acquire before their bodies start.
         const bool mine = (exec >> lane) & 1ull;
         const uint32_t cdone = mine ? __hip_atomic_load(&p.st->done[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
 
@@ -549,17 +549,17 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                     if (lane < kDescCopyDwords)
                         __hip_atomic_store(reinterpret_cast<uint32_t *>(&p.st->task[slot]) + lane, dw, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
-                    uint64_t hits = 0;
+                    uint64_t upm = 0;
                     if (!hc) {
+                        uint64_t hits;
                         if (valid & over4) hits = pair_hits<8, true>(d, nseg, wb, R, rep, ss, se, wmask);
                         else if (valid & over2) hits = pair_hits<4, true>(d, nseg, wb, R, rep, ss, se, wmask);
                         else hits = pair_hits<2, true>(d, nseg, wb, R, rep, ss, se, wmask);
-                    }
-                    uint64_t upm = 0;
-                    for (uint32_t r = 0; r < R; r++) upm |= (hits >> (r * span)) & spanmask;
-                    if (hc) {
-                        // the host's list, by distance back in submission order;
-                        // kernels that already left the window drop out here
+                        for (uint32_t r = 0; r < R; r++) upm |= (hits >> (r * span)) & spanmask;
+                    } else {
+                        // the list made ahead of the window, by distance back in
+                        // submission order; kernels that already left the
+                        // window drop out here
                         const uint64_t hup = readpair(dw, kHostUpDword), back = seq - 1 - myseq;
                         upm = __builtin_amdgcn_ballot_w64(((valid >> lane) & 1ull) && back < hcm &&
                                                           ((hup >> (back & 63u)) & 1ull));
