@@ -627,36 +627,7 @@ __device__ inline void body_rl_permute(const acs_args_rl &a, uint32_t piece, uin
     }
 }
 
-// One Jacobi iteration over the island's positions [b0, b1).  The first
-// kJacobiAhead neighbours of a position are loaded ahead (their indices,
-// then their positions, each batch independent loads) and then taken in
-// edge order, as are any further ones: the same arithmetic in the same order.
-constexpr int kJacobiAhead = 8;
-
-__device__ __forceinline__ void jacobi_edge(const float4 &qp, const float4 &qq, int32_t p, int32_t q, float two_r,
-                                            float &ax, float &ay, float &az)
-{
-    const float dx = qp.x - qq.x, dy = qp.y - qq.y, dz = qp.z - qq.z;
-    const float d = sqrtf(dist2(dx, dy, dz));
-    const float pen = two_r - d;
-    if (pen > 0.0f) {
-        const float h = 0.5f * pen;
-        float nx, ny, nz;
-        if (d > 0.0f) {
-            nx = dx / d;
-            ny = dy / d;
-            nz = dz / d;
-        } else {
-            nx = (p < q) ? 1.0f : -1.0f;
-            ny = 0.0f;
-            nz = 0.0f;
-        }
-        ax = fmaf(h, nx, ax);
-        ay = fmaf(h, ny, ay);
-        az = fmaf(h, nz, az);
-    }
-}
-
+// One Jacobi iteration over the island's positions [b0, b1).
 template <bool DEV>
 __device__ inline void body_rl_jacobi(const acs_args_rl &a)
 {
@@ -671,23 +642,29 @@ __device__ inline void body_rl_jacobi(const acs_args_rl &a)
         int32_t e0 = v.padj_off[p], e1 = v.padj_off[p + 1];
         e0 = e0 < 0 ? 0 : (e0 > cap ? cap : e0);
         e1 = e1 < e0 ? e0 : (e1 > cap ? cap : e1);
-        int32_t qi[kJacobiAhead];
-#pragma unroll
-        for (int u = 0; u < kJacobiAhead; u++) {
-            int32_t q = e0 + u < e1 ? v.padj[e0 + u] : p;
-            if ((uint32_t)q >= (uint32_t)a.n) q = p;   // never true for islands output
-            qi[u] = q;
-        }
-        float4 qv[kJacobiAhead];
-#pragma unroll
-        for (int u = 0; u < kJacobiAhead; u++) qv[u] = src[qi[u]];
-#pragma unroll
-        for (int u = 0; u < kJacobiAhead; u++)
-            if (e0 + u < e1) jacobi_edge(qp, qv[u], p, qi[u], two_r, ax, ay, az);
-        for (int32_t e = e0 + kJacobiAhead; e < e1; e++) {
+        for (int32_t e = e0; e < e1; e++) {
             int32_t q = v.padj[e];
-            if ((uint32_t)q >= (uint32_t)a.n) q = p;
-            jacobi_edge(qp, src[q], p, q, two_r, ax, ay, az);
+            if ((uint32_t)q >= (uint32_t)a.n) q = p;   // never true for islands output
+            const float4 qq = src[q];
+            const float dx = qp.x - qq.x, dy = qp.y - qq.y, dz = qp.z - qq.z;
+            const float d = sqrtf(dist2(dx, dy, dz));
+            const float pen = two_r - d;
+            if (pen > 0.0f) {
+                const float h = 0.5f * pen;
+                float nx, ny, nz;
+                if (d > 0.0f) {
+                    nx = dx / d;
+                    ny = dy / d;
+                    nz = dz / d;
+                } else {
+                    nx = (p < q) ? 1.0f : -1.0f;
+                    ny = 0.0f;
+                    nz = 0.0f;
+                }
+                ax = fmaf(h, nx, ax);
+                ay = fmaf(h, ny, ay);
+                az = fmaf(h, nz, az);
+            }
         }
         const float deg = (float)(e1 - e0);
         float4 o;
