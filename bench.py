@@ -452,7 +452,7 @@ def main():
                     help="only run device copies of known size (for PMC byte-counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X; "
+        print("bench.py measures one GPU only: the scheduler runs on a single MI355X; "
               "independent scenes would shard across GPUs with no communication", file=sys.stderr)
         sys.exit(2)
 

@@ -3,7 +3,7 @@
 // Every GPU thread is an OS thread; a wavefront is 64 of them.  Ballot and
 // readlane are rendezvous of the 64 lanes; __syncthreads is a workgroup
 // barrier.  Atomics and fences map to sequentially consistent host atomics,
-// which is stronger than the GPU memory model (so this build checks the
+// which is stronger than the GPU memory model (so the emulation checks the
 // scheduler's logic, not its GPU memory ordering).
 // Test infrastructure only: never part of libacs.
 #pragma once
