@@ -104,6 +104,20 @@ def test_tiny_stream_pieces_do_not_change_bits(torch, wg):
     assert np.array_equal(bits(got), bits(O.tiny_run(st)))
 
 
+@pytest.mark.parametrize("path,W", [("device", 16), ("device", 64), ("device_window", 64)])
+def test_tiny_stream_long_streams_device(torch, path, W):
+    """Streams of 1000 kernels (the check waves' 64-kernel history and the
+    staging ring wrap many times): bits equal to the oracle's, and every
+    schedule valid with the exact upstream masks."""
+    for seed in range(200, 206):
+        say(f"tiny long seed={seed} path={path} W={W}")
+        st = inputs.tiny_stream(seed, n_kernels=1000)
+        got, tr, _ = run_tiny(torch, st, path, W, trace_capacity=4096)
+        assert np.array_equal(bits(got), bits(O.tiny_run(st))), seed
+        code, msg = O.check_trace(O.tiny_accesses(st), W, tr, check_times=True, early=True)
+        assert code == 0, (seed, msg)
+
+
 def test_tiny_stream_many_seeds_device(torch):
     for seed in range(100, 140):
         st = inputs.tiny_stream(seed)
