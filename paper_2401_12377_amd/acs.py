@@ -326,7 +326,11 @@ _live = weakref.WeakSet()
 
 
 class Window:
-    """One scheduling window (acs_window_create + acs_window_configure)."""
+    """One scheduling window (acs_window_create + acs_window_configure).
+    The keyword arguments are the fields of acs_config (include/acs.h); on
+    the device path with one group the dependency checks run in the check
+    waves ahead of the window unless host_check_depth > 0 (on the host) or
+    window_check = 1 (in the window wave at insert)."""
 
     def __init__(self, W: int, path: str = "device", n_streams: int = 4, wg_per_task: int = 1, n_workers: int = 0,
                  queue_depth: int = 4096, nonblocking: bool = False, trace: bool = False,
