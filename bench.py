@@ -495,7 +495,8 @@ def main():
         "config": {"workload": f"rigid-body RL step, {args.bodies} spheres x {args.physics_steps} steps, "
                                f"W={args.window}, device-resident path",
                    "bodies": args.bodies, "physics_steps": args.physics_steps, "window": args.window,
-                   "kernels_per_episode": counts["kernels"], "parallelism": "single GPU"},
+                   "kernels_per_episode": counts["kernels"], "parallelism": "single GPU",
+                   "dependency_checks": "check waves ahead of the window (default for one window)"},
     }
     if "inorder" in res:
         out["speedup_vs_inorder"] = res["inorder"][0] / dt
