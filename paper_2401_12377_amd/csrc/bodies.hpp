@@ -389,10 +389,10 @@ __device__ inline void body_rl_broadphase(const acs_args_rl &a, uint8_t *smem)
 // smallest body, bodies inside an island in index order, the adjacency in
 // permuted positions, and the plan of multi-body islands for the host.
 // At most 64 bodies: the workgroup stages the adjacency in LDS, then one
-// wave works: neighbour sets as 64-bit masks, components by
-// Warshall's transitive closure (row k is final once step k has run, so all
-// lanes update in parallel), each body's island is its closure and its label
-// the closure's smallest body.  Positions: islands in label order, bodies in
+// wave works: neighbour sets as 64-bit masks, each island grown from its
+// smallest body by breadth-first steps that are single ballots, its label
+// that smallest body.  Positions: islands in label order (each
+// island's first position a scan of the sizes over the roots), bodies in
 // index order inside an island.
 template <bool DEV>
 __device__ inline void islands_small(const acs_args_rl &a, const RLView &v, int32_t *plan, uint8_t *smem)
@@ -430,22 +430,31 @@ __device__ inline void islands_small(const acs_args_rl &a, const RLView &v, int3
         const int32_t c = s_adj[k];
         if ((uint32_t)c < (uint32_t)n) reach |= 1ull << c;
     }
-    for (int32_t k = 0; k < n; k++) {
-        const uint64_t rk = lane_read64(reach, k);
-        if ((reach >> k) & 1ull) reach |= rk;
+    // components by breadth-first search on ballots, one island at a time:
+    // the island grows by every body with a neighbour in it (contact is
+    // symmetric) until it stops growing; a body without neighbours is an
+    // island of its own
+    const uint64_t nbrs = reach;
+    for (uint64_t todo = __builtin_amdgcn_ballot_w64(o1 > o0); todo;) {
+        uint64_t f = 1ull << __builtin_ctzll(todo);
+        for (;;) {
+            const uint64_t g = __builtin_amdgcn_ballot_w64((nbrs & f) != 0ull) | f;
+            if (g == f) break;
+            f = g;
+        }
+        if ((f >> lane) & 1ull) reach = f;
+        todo &= ~f;
     }
     const int32_t root = in ? __builtin_ctzll(reach) : lane;
     const bool isroot = in && root == lane;
     const uint64_t roots = __builtin_amdgcn_ballot_w64(isroot);
     const int32_t nisl = __builtin_popcountll(roots);
     const int32_t size = __builtin_popcountll(reach);
-    // first position of each island: sizes of the islands with smaller labels
-    int32_t start = 0, run = 0;
-    for (uint64_t rm = roots; rm; rm &= rm - 1) {
-        const int32_t r = __builtin_ctzll(rm);
-        if (root == r) start = run;
-        run += __builtin_popcountll(lane_read64(reach, r));
-    }
+    // first position of each island: the sizes of the islands with smaller
+    // labels, a scan over the roots read back at each body's root
+    int32_t nin;
+    const int32_t rstart = wave_exclusive_scan(isroot ? size : 0, &nin);
+    const int32_t start = __shfl(rstart, root & 63, 64);
     const uint64_t below = (1ull << lane) - 1ull;   // lane 0: empty
     const int32_t pos = start + __builtin_popcountll(reach & below);
     const int32_t ridx = __builtin_popcountll(roots & ((1ull << root) - 1ull));
@@ -469,9 +478,16 @@ __device__ inline void islands_small(const acs_args_rl &a, const RLView &v, int3
     const int32_t poff = wave_exclusive_scan(in ? db : 0, &ep);
     if (in) put<DEV>(&v.padj_off[lane], poff);
     if (lane == 0) put<DEV>(&v.padj_off[n], ep);
-    for (int32_t k = 0; in && k < db; k++) {
-        const int32_t c = s_adj[ob + k];
-        if (poff + k < cap) put<DEV>(&v.padj[poff + k], ((uint32_t)c < (uint32_t)n) ? s_inv[c] : lane);
+    // four neighbours at a time, so that their LDS reads overlap
+    for (int32_t k = 0; in && k < db; k += 4) {
+        int32_t c[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) c[u] = k + u < db ? s_adj[ob + k + u] : -1;
+#pragma unroll
+        for (int u = 0; u < 4; u++) c[u] = (uint32_t)c[u] < (uint32_t)n ? s_inv[c[u]] : lane;
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (k + u < db && poff + k + u < cap) put<DEV>(&v.padj[poff + k + u], c[u]);
     }
     // plan: multi-body islands in label order
     const bool multi = isroot && size >= 2;
