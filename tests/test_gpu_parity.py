@@ -176,6 +176,24 @@ def test_rl_steps_match_oracle(torch, path, n, W, wg):
         assert code == 0, msg
 
 
+@pytest.mark.parametrize("path", ["inorder", "device"])
+@pytest.mark.parametrize("n,radius", [(2, 0.01), (2, 0.3), (64, 0.01), (64, 0.3), (65, 0.3)])
+def test_rl_edge_scenes_match_oracle(torch, path, n, radius):
+    """The degenerate contact structures: the smallest scene apart and
+    touching, no contacts at all, and one island of every body on either
+    side of the one-wave limit; three steps against the oracle."""
+    sc = inputs.rl_scene(seed=11, n=n, radius=radius)
+    g = acs.RLSceneGPU(sc)
+    ref = O.Scene.from_inputs(sc)
+    with window(16, path) as w:
+        for step in range(3):
+            say(f"rl edge path={path} n={n} radius={radius} step={step}")
+            counts, _ = acs.rl_run(w, g, 1)
+            ref.step()
+            assert counts["kernels"] == len(ref.step_kernels())
+            compare_step(g, ref, step)
+
+
 def test_rl_full_episode_device(torch):
     """The timed workload: 64 spheres, 200 steps, W = 32, device path."""
     sc = inputs.rl_scene(seed=1, n=64)

@@ -138,13 +138,17 @@ def test_conv_tile_through_kernel_source(sim, h, cin, cout, k, s):
 
 
 @pytest.mark.timeout(180, method="thread")
-@pytest.mark.parametrize("n", [8, 33, 64, 80])
-def test_rl_prefix_through_kernel_source(sim, n):
+@pytest.mark.parametrize("n,radius", [(8, None), (33, None), (64, None), (80, None),
+                                      (2, 0.01), (2, 0.3), (64, 0.01), (64, 0.3), (65, 0.3)])
+def test_rl_prefix_through_kernel_source(sim, n, radius):
     """One RL step through the kernel source: predict, broadphase, islands
     and permute (the one-wave paths for at most 64 bodies, the workgroup
     paths above), then the plan's Jacobi kernels and integrate, against the
-    oracle's step: integer buffers and positions and velocities bit-exact."""
-    sc = inputs.rl_scene(seed=11, n=n)
+    oracle's step: integer buffers and positions and velocities bit-exact.
+    The edge scenes: the smallest scene, two bodies apart and touching, no
+    contacts at all (every body an island of its own), and one island of
+    every body on either side of the one-wave limit."""
+    sc = inputs.rl_scene(seed=11, n=n, radius=radius)
     off = acs.rl_layout(n)
     arena = np.zeros(int(off[acs.RL_END]), np.uint8)
     plan = np.zeros(acs.rl_plan_ints(n), np.int32)
@@ -178,6 +182,8 @@ def test_rl_prefix_through_kernel_source(sim, n):
     k = int(ref.meta[0])
     assert np.array_equal(region(acs.RL_ISL_OFF, np.int32, k + 1), ref.isl_off[:k + 1])
     m = int(ref.meta[1])
+    if radius is not None:   # the edge scene is the one named
+        assert (k, m) == ((n, 0) if radius < 0.05 else (1, 1))
     assert plan[0] == ref.meta[0] and plan[1] == ref.meta[1] and plan[2] == ref.meta[2]
     assert np.array_equal(plan[4:4 + 4 * m], ref.plan[:4 * m])
     assert np.array_equal(region(acs.RL_Q0, np.uint32, 4 * n), ref.Q0.view(np.uint32).reshape(-1))
