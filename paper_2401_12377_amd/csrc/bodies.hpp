@@ -238,16 +238,20 @@ __device__ inline uint64_t lane_read64(uint64_t x, int32_t l)
 __device__ inline float lane_readf(float x, int32_t l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l)); }
 
 // exclusive prefix sum over the wave's lanes in lane order; *total = sum of all
+// An inclusive scan inside each row of 16 lanes by DPP row shifts (a lane
+// whose source would leave the row adds 0), then the total of row 0 added to
+// rows 1 and 3 (row_bcast:15) and that of rows 0-1 to rows 2 and 3
+// (row_bcast:31); the total is lane 63's.
 __device__ inline int32_t wave_exclusive_scan(int32_t x, int32_t *total)
 {
-    const int32_t lane = threadIdx.x & 63;
     int32_t inc = x;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int32_t y = __shfl_up(inc, (unsigned)d, 64);
-        if (lane >= d) inc += y;
-    }
-    *total = __shfl(inc, 63, 64);
+    inc += __builtin_amdgcn_update_dpp(0, inc, 0x111, 0xf, 0xf, false);   // row_shr:1
+    inc += __builtin_amdgcn_update_dpp(0, inc, 0x112, 0xf, 0xf, false);   // row_shr:2
+    inc += __builtin_amdgcn_update_dpp(0, inc, 0x114, 0xf, 0xf, false);   // row_shr:4
+    inc += __builtin_amdgcn_update_dpp(0, inc, 0x118, 0xf, 0xf, false);   // row_shr:8
+    inc += __builtin_amdgcn_update_dpp(0, inc, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    inc += __builtin_amdgcn_update_dpp(0, inc, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    *total = __builtin_amdgcn_readlane(inc, 63);
     return inc - x;
 }
 

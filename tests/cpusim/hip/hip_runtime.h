@@ -9,6 +9,7 @@
 #pragma once
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <atomic>
@@ -168,6 +169,33 @@ inline acs_sim_v4f __builtin_amdgcn_mfma_f32_16x16x4f32(float a, float b, acs_si
     }
     w.bar.arrive_and_wait();
     return d;
+}
+
+// DPP move with the controls the device code uses: row_shr:1-15 and
+// row_bcast:15 / row_bcast:31.  A lane of a row or bank masked off, or whose
+// source is not valid (bound_ctrl false), keeps `old`.
+inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl)
+{
+    acs_sim::Wave &w = acs_sim::group->waves[acs_sim::tid / 64];
+    const int lane = (int)(acs_sim::tid % 64), row = lane / 16, col = lane % 16;
+    w.vals[lane] = (uint32_t)src;
+    w.bar.arrive_and_wait();
+    int from = -1;
+    if (ctrl >= 0x111 && ctrl <= 0x11f) {
+        const int k = ctrl - 0x110;
+        if (col >= k) from = lane - k;
+    } else if (ctrl == 0x142) {
+        if (row >= 1) from = 16 * row - 1;
+    } else if (ctrl == 0x143) {
+        if (row >= 2) from = 31;
+    } else {
+        abort();
+    }
+    int r = old;
+    if (((row_mask >> row) & 1) && ((bank_mask >> (col / 4)) & 1))
+        r = from >= 0 ? (int)(uint32_t)w.vals[from] : (bound_ctrl ? 0 : old);
+    w.bar.arrive_and_wait();
+    return r;
 }
 
 inline void __builtin_amdgcn_wave_barrier() { acs_sim::group->waves[acs_sim::tid / 64].bar.arrive_and_wait(); }
