@@ -191,9 +191,25 @@ __device__ inline RLView rl_view(uint64_t base, int32_t n)
 
 __device__ inline float dist2(float dx, float dy, float dz) { return fmaf(dz, dz, fmaf(dy, dy, dx * dx)); }
 
+// Inclusive prefix sum over a wave's 64 lanes: a scan inside each row of 16
+// lanes by DPP row shifts (a lane whose source would leave the row adds 0),
+// then the total of row 0 added to rows 1 and 3 (row_bcast:15) and that of
+// rows 0-1 to rows 2 and 3 (row_bcast:31).
+__device__ inline int32_t wave_inclusive_scan(int32_t x)
+{
+    int32_t inc = x;
+    inc += __builtin_amdgcn_update_dpp(0, inc, 0x111, 0xf, 0xf, false);   // row_shr:1
+    inc += __builtin_amdgcn_update_dpp(0, inc, 0x112, 0xf, 0xf, false);   // row_shr:2
+    inc += __builtin_amdgcn_update_dpp(0, inc, 0x114, 0xf, 0xf, false);   // row_shr:4
+    inc += __builtin_amdgcn_update_dpp(0, inc, 0x118, 0xf, 0xf, false);   // row_shr:8
+    inc += __builtin_amdgcn_update_dpp(0, inc, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    inc += __builtin_amdgcn_update_dpp(0, inc, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    return inc;
+}
+
 // Exclusive scan of data[0..n) in place; returns the total.  Thread t sums a
 // contiguous chunk; the 256 chunk sums are scanned inside each wave with
-// shuffles and across the four waves through tmp (4 ints).  Integer only, so
+// DPP and across the four waves through tmp (4 ints).  Integer only, so
 // the grouping does not change the result.
 __device__ inline int32_t block_exclusive_scan(int32_t *data, int32_t n, int32_t *tmp)
 {
@@ -202,12 +218,7 @@ __device__ inline int32_t block_exclusive_scan(int32_t *data, int32_t n, int32_t
     const int32_t lo = t * per < n ? t * per : n, hi = lo + per < n ? lo + per : n;
     int32_t s = 0;
     for (int32_t i = lo; i < hi; i++) s += data[i];
-    int32_t x = s;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int32_t y = __shfl_up(x, (unsigned)d, 64);
-        if (lane >= d) x += y;
-    }
+    const int32_t x = wave_inclusive_scan(s);
     if (lane == 63) tmp[wv] = x;
     __syncthreads();
     int32_t woff = 0;
@@ -238,19 +249,9 @@ __device__ inline uint64_t lane_read64(uint64_t x, int32_t l)
 __device__ inline float lane_readf(float x, int32_t l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l)); }
 
 // exclusive prefix sum over the wave's lanes in lane order; *total = sum of all
-// An inclusive scan inside each row of 16 lanes by DPP row shifts (a lane
-// whose source would leave the row adds 0), then the total of row 0 added to
-// rows 1 and 3 (row_bcast:15) and that of rows 0-1 to rows 2 and 3
-// (row_bcast:31); the total is lane 63's.
 __device__ inline int32_t wave_exclusive_scan(int32_t x, int32_t *total)
 {
-    int32_t inc = x;
-    inc += __builtin_amdgcn_update_dpp(0, inc, 0x111, 0xf, 0xf, false);   // row_shr:1
-    inc += __builtin_amdgcn_update_dpp(0, inc, 0x112, 0xf, 0xf, false);   // row_shr:2
-    inc += __builtin_amdgcn_update_dpp(0, inc, 0x114, 0xf, 0xf, false);   // row_shr:4
-    inc += __builtin_amdgcn_update_dpp(0, inc, 0x118, 0xf, 0xf, false);   // row_shr:8
-    inc += __builtin_amdgcn_update_dpp(0, inc, 0x142, 0xa, 0xf, false);   // row_bcast:15
-    inc += __builtin_amdgcn_update_dpp(0, inc, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    const int32_t inc = wave_inclusive_scan(x);
     *total = __builtin_amdgcn_readlane(inc, 63);
     return inc - x;
 }
