@@ -30,7 +30,8 @@ int acs_host_free(void *p);
  * int32 buffer of 4 + 4 * (n / 2) entries. */
 typedef struct {
     int32_t n;
-    int32_t iters;          /* Jacobi iterations per step (8) */
+    int32_t iters;          /* Jacobi iterations per step (8); even (sweeps alternate between Q0 and
+                               Q1 and integrate reads Q0), else ACS_EINVAL */
     float r, dt;
     uint64_t arena;
     int32_t *plan;
@@ -189,7 +190,7 @@ enum { ACS_SERVE_RL = 0, ACS_SERVE_DNN = 1 };
 typedef struct {
     int32_t kind;              /* ACS_SERVE_RL or ACS_SERVE_DNN */
     int32_t n;                 /* RL: bodies, 2..1024 */
-    int32_t iters;             /* RL: Jacobi iterations */
+    int32_t iters;             /* RL: Jacobi iterations, even (as in acs_rl_scene) */
     float r, dt;               /* RL: radius, time step */
     int32_t pad;
     double arrival_ns;         /* after the start of the run; non-decreasing over the array */

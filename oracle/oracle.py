@@ -56,56 +56,63 @@ _lib = None
 
 
 def lib():
+    """The oracle library, built on first use."""
     global _lib
     if _lib is None:
         path = os.path.join(HERE, "liboracle.so")
         if not os.path.exists(path):
             from oracle import build as _b
             _b.build()
-        L = C.CDLL(path)
-        L.or_overlap.argtypes = [C.c_uint64] * 4
-        L.or_overlap.restype = C.c_int
-        L.or_conflict.argtypes = [C.POINTER(Access), C.POINTER(Access)]
-        L.or_conflict.restype = C.c_int
-        L.or_conflict_literal.argtypes = [C.POINTER(Access), C.POINTER(Access)]
-        L.or_conflict_literal.restype = C.c_int
-        L.or_dag.argtypes = [C.c_int32, C.POINTER(Access), C.c_int32, C.c_void_p]
-        L.or_dag.restype = None
-        L.or_check_trace.argtypes = [C.c_int32, C.POINTER(Access), C.c_int32, C.c_void_p, C.c_int32,
-                                     C.c_int32, C.c_char_p, C.c_int32]
-        L.or_check_trace.restype = C.c_int32
-        L.or_tiny_access.argtypes = [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(TinyKernelC),
-                                     C.POINTER(Access)]
-        L.or_tiny_access.restype = None
-        L.or_tiny_run.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(TinyKernelC),
-                                  C.c_void_p]
-        L.or_tiny_run.restype = None
-        L.or_tree_sum.argtypes = [C.c_void_p, C.c_int64]
-        L.or_tree_sum.restype = C.c_float
-        L.or_rl_run_kernel.argtypes = [C.POINTER(SceneC), C.POINTER(RLKernelC)]
-        L.or_rl_run_kernel.restype = None
-        L.or_rl_access.argtypes = [C.POINTER(SceneC), C.POINTER(RLKernelC), C.POINTER(Access)]
-        L.or_rl_access.restype = None
-        L.or_rl_step_kernels.argtypes = [C.POINTER(SceneC), C.POINTER(RLKernelC), C.c_int32]
-        L.or_rl_step_kernels.restype = C.c_int32
-        L.or_rl_step.argtypes = [C.POINTER(SceneC)]
-        L.or_rl_step.restype = None
-        L.or_conv_hout.argtypes = [C.c_int32] * 3
-        L.or_conv_hout.restype = C.c_int32
-        L.or_conv_f32.argtypes = [C.c_void_p] * 4 + [C.c_int32] * 5
-        L.or_conv_f32.restype = None
-        L.or_conv_f64.argtypes = [C.c_void_p] * 5 + [C.c_int32] * 5
-        L.or_conv_f64.restype = None
-        L.or_relu.argtypes = [C.c_float]
-        L.or_relu.restype = C.c_float
-        L.or_join.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]
-        L.or_join.restype = None
-        L.or_avgpool.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32]
-        L.or_avgpool.restype = None
-        L.or_fc.argtypes = [C.c_void_p] * 4 + [C.c_int32] * 2
-        L.or_fc.restype = None
-        _lib = L
+        _lib = load(path)
     return _lib
+
+
+def load(path: str):
+    """Loads an oracle library from `path` with its signatures declared (the
+    built oracle, or a copy built elsewhere by a test)."""
+    L = C.CDLL(path)
+    L.or_overlap.argtypes = [C.c_uint64] * 4
+    L.or_overlap.restype = C.c_int
+    L.or_conflict.argtypes = [C.POINTER(Access), C.POINTER(Access)]
+    L.or_conflict.restype = C.c_int
+    L.or_conflict_literal.argtypes = [C.POINTER(Access), C.POINTER(Access)]
+    L.or_conflict_literal.restype = C.c_int
+    L.or_dag.argtypes = [C.c_int32, C.POINTER(Access), C.c_int32, C.c_void_p]
+    L.or_dag.restype = None
+    L.or_check_trace.argtypes = [C.c_int32, C.POINTER(Access), C.c_int32, C.c_void_p, C.c_int32,
+                                 C.c_int32, C.c_char_p, C.c_int32]
+    L.or_check_trace.restype = C.c_int32
+    L.or_tiny_access.argtypes = [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(TinyKernelC),
+                                 C.POINTER(Access)]
+    L.or_tiny_access.restype = None
+    L.or_tiny_run.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(TinyKernelC),
+                              C.c_void_p]
+    L.or_tiny_run.restype = None
+    L.or_tree_sum.argtypes = [C.c_void_p, C.c_int64]
+    L.or_tree_sum.restype = C.c_float
+    L.or_rl_run_kernel.argtypes = [C.POINTER(SceneC), C.POINTER(RLKernelC)]
+    L.or_rl_run_kernel.restype = None
+    L.or_rl_access.argtypes = [C.POINTER(SceneC), C.POINTER(RLKernelC), C.POINTER(Access)]
+    L.or_rl_access.restype = None
+    L.or_rl_step_kernels.argtypes = [C.POINTER(SceneC), C.POINTER(RLKernelC), C.c_int32]
+    L.or_rl_step_kernels.restype = C.c_int32
+    L.or_rl_step.argtypes = [C.POINTER(SceneC)]
+    L.or_rl_step.restype = None
+    L.or_conv_hout.argtypes = [C.c_int32] * 3
+    L.or_conv_hout.restype = C.c_int32
+    L.or_conv_f32.argtypes = [C.c_void_p] * 4 + [C.c_int32] * 5
+    L.or_conv_f32.restype = None
+    L.or_conv_f64.argtypes = [C.c_void_p] * 5 + [C.c_int32] * 5
+    L.or_conv_f64.restype = None
+    L.or_relu.argtypes = [C.c_float]
+    L.or_relu.restype = C.c_float
+    L.or_join.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]
+    L.or_join.restype = None
+    L.or_avgpool.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32]
+    L.or_avgpool.restype = None
+    L.or_fc.argtypes = [C.c_void_p] * 4 + [C.c_int32] * 2
+    L.or_fc.restype = None
+    return L
 
 
 # ---------------------------------------------------------------------------
@@ -229,7 +236,12 @@ class Scene:
     INT_FIELDS = ("deg", "adj_off", "adj", "label", "perm", "inv_perm", "isl_off", "padj_off",
                   "padj", "meta", "plan")
 
-    def __init__(self, n: int, r: float, dt: float, iters: int, x: np.ndarray, v: np.ndarray):
+    def __init__(self, n: int, r: float, dt: float, iters: int, x: np.ndarray, v: np.ndarray, L=None):
+        # Jacobi sweeps alternate Q0 -> Q1 -> Q0 and the integrator reads Q0,
+        # so a step is defined for an even number of sweeps only
+        if iters < 0 or iters % 2:
+            raise ValueError("the number of Jacobi iterations must be even and non-negative")
+        self._L = L if L is not None else lib()
         self.n = n
         e = max(1, n * (n - 1))
         self.X = np.array(x, dtype=np.float32).reshape(n, 4).copy()
@@ -254,26 +266,26 @@ class Scene:
             setattr(self.c, f, getattr(self, f).ctypes.data)
 
     @classmethod
-    def from_inputs(cls, sc):
-        return cls(sc.n, float(sc.radius), float(sc.dt), sc.iters, sc.x, sc.v)
+    def from_inputs(cls, sc, L=None):
+        return cls(sc.n, float(sc.radius), float(sc.dt), sc.iters, sc.x, sc.v, L=L)
 
     def step(self):
-        lib().or_rl_step(C.byref(self.c))
+        self._L.or_rl_step(C.byref(self.c))
 
     def run_kernel(self, op, island=0, it=0):
         k = RLKernelC(op, island, it)
-        lib().or_rl_run_kernel(C.byref(self.c), C.byref(k))
+        self._L.or_rl_run_kernel(C.byref(self.c), C.byref(k))
 
     def step_kernels(self):
         cap = 16 + self.c.iters * self.n
         arr = (RLKernelC * cap)()
-        m = lib().or_rl_step_kernels(C.byref(self.c), arr, cap)
+        m = self._L.or_rl_step_kernels(C.byref(self.c), arr, cap)
         return [(arr[i].op, arr[i].island, arr[i].iter) for i in range(m)]
 
     def access(self, op, island=0, it=0) -> Access:
         k = RLKernelC(op, island, it)
         a = Access()
-        lib().or_rl_access(C.byref(self.c), C.byref(k), C.byref(a))
+        self._L.or_rl_access(C.byref(self.c), C.byref(k), C.byref(a))
         return a
 
     @property

@@ -34,8 +34,10 @@ struct RangeList {
     void push(Range r)
     {
         if (n == cap) {
-            heap.assign(v, v + n);
-            heap.resize(cap * 2);
+            // copy into a new vector first: v may point into heap itself
+            std::vector<Range> grown(cap * 2);
+            std::copy(v, v + n, grown.begin());
+            heap.swap(grown);
             cap *= 2;
             v = heap.data();
         }
@@ -284,9 +286,8 @@ int make_desc(int32_t kid, const acs_seg *r, int32_t nr, const acs_seg *w, int32
         *why = "segment wraps past the end of the address space";
         return ACS_EINVAL;
     }
-    bool lossy = false;
-    shrink(rr, ACS_K_MAX);
-    shrink(ww, ACS_K_MAX);
+    bool lossy = shrink(rr, ACS_K_MAX);
+    lossy |= shrink(ww, ACS_K_MAX);
     while (rr.n + ww.n > ACS_K_MAX) {
         // give the writes at least half of the budget, the reads the rest
         const size_t wbud = std::min(ww.n, (size_t)std::max<int>(ACS_K_MAX / 2, ACS_K_MAX - (int)rr.n));

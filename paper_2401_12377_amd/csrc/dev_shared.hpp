@@ -65,6 +65,7 @@ struct HostCtrl {
     volatile uint64_t exited;               // set when the scheduler wave leaves
     volatile uint64_t checks;               // overlap tests made by the window wave (statistics)
     volatile uint64_t check_wave_tests[2];  // overlap tests made by each check wave (statistics)
+    volatile uint64_t published;            // work-queue entries published, sentinels excluded (at exit)
     acs_entry snap[ACS_W_MAX];
 };
 

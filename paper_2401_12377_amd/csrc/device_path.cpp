@@ -250,6 +250,21 @@ public:
             }
             checks_ = ctrl_->checks + ctrl_->check_wave_tests[0] + ctrl_->check_wave_tests[1];
             running_ = false;
+            // Workers take tickets with one wave-wide add of 1 per lane, which
+            // counts kWave per ticket only if the adds were combined into one
+            // read-modify-write; every worker takes one exit ticket.  Check
+            // that the count came out exactly so after a clean exit.
+            if (rc == ACS_OK && ctrl_->exited) {
+                uint64_t deq = 0;
+                const hipError_t e = hipMemcpy(&deq, &st_->deq, sizeof(deq), hipMemcpyDeviceToHost);
+                if (e != hipSuccess) {
+                    rc = hip_fail(e, "hipMemcpy(queue head)");
+                } else if (deq != 64ull * (ctrl_->published + (uint64_t)n_workers_)) {
+                    set_error(ACS_EDEVICE, "work-queue tickets do not add up: the workers' ticket count is broken");
+                    rc = ACS_EDEVICE;
+                }
+                if (rc != ACS_OK && err_ == ACS_OK) err_ = rc;
+            }
             float ms = 0.0f;
             if (hipEventElapsedTime(&ms, ev0_, ev1_) == hipSuccess) kernel_ns_ = (uint64_t)((double)ms * 1e6);
         }

@@ -886,6 +886,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
     }
     if (lane == 0) {
         __hip_atomic_store(&p.ctrl->checks, checks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&p.ctrl->published, pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         __hip_atomic_store(&p.ctrl->exited, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }

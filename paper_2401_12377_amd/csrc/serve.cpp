@@ -160,7 +160,8 @@ public:
             const acs_serve_request &q = req_[i];
             if (i > 0 && q.arrival_ns < req_[i - 1].arrival_ns) return ACS_EINVAL;
             if (q.kind == ACS_SERVE_RL) {
-                if (q.n < 2 || q.n > acs::kRLMaxBodies || q.iters < 0 || !q.input || !q.output) return ACS_EINVAL;
+                if (q.n < 2 || q.n > acs::kRLMaxBodies || q.iters < 0 || q.iters % 2 != 0 || !q.input || !q.output)
+                    return ACS_EINVAL;
             } else if (q.kind == ACS_SERVE_DNN) {
                 if (!cfg_.model || !q.input || !q.output || !q.logits) return ACS_EINVAL;
             } else {

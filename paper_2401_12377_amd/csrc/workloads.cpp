@@ -43,9 +43,11 @@ int acs_host_free(void *p)
 
 namespace {
 
+// Jacobi sweeps alternate Q0 -> Q1 -> Q0 and integrate reads Q0: an odd
+// sweep count would leave the last sweep's result unread, so it is refused.
 bool scene_ok(const acs_rl_scene *sc)
 {
-    return sc && sc->n >= 2 && sc->n <= acs::kRLMaxBodies && sc->plan && sc->iters >= 0;
+    return sc && sc->n >= 2 && sc->n <= acs::kRLMaxBodies && sc->plan && sc->iters >= 0 && sc->iters % 2 == 0;
 }
 
 }  // namespace

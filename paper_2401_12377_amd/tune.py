@@ -61,18 +61,20 @@ def time_config(scenes, cfg: dict, steps: int = 2, warmup: int = 1) -> float:
     return counts["kernels"] / dt
 
 
-def autotune(scenes, steps: int = 2, log=None, **space):
-    """Returns (best config, table of (config, kernels/s))."""
+def autotune(scenes, steps: int = 2, log=None, timer=None, **space):
+    """Returns (best config, table of (config, kernels/s)).  `timer(scenes,
+    cfg, steps)` measures one candidate (time_config unless given)."""
+    timer = timer or time_config
     table = []
     for cfg in candidates(**space):
-        v = time_config(scenes, cfg, steps)
+        v = timer(scenes, cfg, steps)
         table.append((cfg, v))
         if log:
             log(f"[tune] {cfg}: {v / 1e3:.0f}k kernels/s")
     best = dict(max(table, key=lambda t: t[1])[0])
     for qd in (256, 1024):
         cfg = dict(best, queue_depth=qd)
-        v = time_config(scenes, cfg, steps)
+        v = timer(scenes, cfg, steps)
         table.append((cfg, v))
         if log:
             log(f"[tune] {cfg}: {v / 1e3:.0f}k kernels/s")

@@ -287,6 +287,57 @@ def test_coalescing_is_conservative():
         w.destroy()
 
 
+def test_lossy_merge_of_one_kind_is_counted():
+    """Ten disjoint reads and no write do not fit ACS_K_MAX positions: the
+    merge adds bytes, which is recorded, and stays conservative."""
+    w = manual(2)
+    reads = [(1000 * i, 10) for i in range(10)]
+    sub(w, reads, [])
+    assert w.stats()["coalesced"] == 1
+    sub(w, [], [(1500, 1)])                 # a write into a gap the merge covered
+    assert w.scheduled_list()[1][3] != 0
+    w.destroy()
+    w = manual(2)
+    sub(w, [(1000 * i, 10) for i in range(8)], [])   # eight fit: exact
+    assert w.stats()["coalesced"] == 0
+    w.destroy()
+
+
+def test_more_than_sixty_four_ranges():
+    """Lists longer than the on-stack capacity spill to the heap (twice for
+    100 and 200 ranges) and still give a conservative, counted merge."""
+    rng = np.random.default_rng(11)
+    for n in (33, 65, 100, 200):
+        reads = [(int(s), 7) for s in rng.choice(1 << 20, size=n, replace=False) * 16]
+        writes = [(int(s), 5) for s in rng.choice(1 << 20, size=n // 2, replace=False) * 16 + (1 << 25)]
+        w = manual(2)
+        sub(w, reads, writes)
+        assert w.stats()["coalesced"] == 1
+        for r in reads[:10] + [(reads[-1][0] + 3, 1)]:
+            sub(w, [], [r])
+            lst = w.scheduled_list()
+            assert lst[-1][3] != 0, (n, r)
+            w.destroy()
+            w = manual(2)
+            sub(w, reads, writes)
+        w.destroy()
+
+
+def test_rl_driver_rejects_odd_sweep_counts():
+    """Sweeps alternate between the two position buffers and integrate reads
+    the first: an odd count is refused before anything is submitted."""
+    import ctypes as C
+    plan = (C.c_int32 * 64)()
+    for iters, want in ((1, acs.EINVAL), (7, acs.EINVAL), (-2, acs.EINVAL)):
+        sc = acs.RLSceneC(16, iters, 0.1, 1.0 / 120, 1 << 30, C.cast(plan, C.c_void_p))
+        w = manual(8)
+        steps = (C.c_double * 1)()
+        cnt = acs.RLCounts()
+        assert acs.lib().acs_rl_run(w.handle, C.byref(sc), 1, steps, C.byref(cnt)) == want
+        assert w.stats()["submitted"] == 0
+        w.destroy()
+
+
 def test_package_tiny_ranges_equal_oracle_ranges():
     st = inputs.tiny_stream(7)
     base = 1 << 36
