@@ -467,6 +467,15 @@ def main():
         return
     acs.lib()
     paths = args.paths.split(",")
+    if "graph_per_input" in paths:
+        # Its host process has ended with a segmentation fault inside the
+        # rebuild loop; the host code of that loop runs clean under the
+        # address and undefined-behaviour sanitizers on the CPU (thousands of
+        # steps with changing plans, tests/test_host_sanitize.py), so no cause
+        # has been shown in this code and the case stays off the GPU.
+        print("graph_per_input is switched off: its rebuild loop ended the process with a host-side "
+              "segmentation fault and no cause has been found in this code", file=sys.stderr)
+        sys.exit(2)
     res = {}
     for path in paths:
         log(f"[bench] {path}: warmup {args.warmup} episodes")
