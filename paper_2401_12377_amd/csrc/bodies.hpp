@@ -16,6 +16,39 @@
 
 namespace acs {
 
+// Global memory accesses go through pointers in the global address space.
+// A pointer the compiler cannot place (one loaded from a struct, or made
+// from an integer) is otherwise accessed with FLAT instructions, which count
+// on the LDS counter as well: every later wait for an LDS read would then
+// also wait for those loads and stores to complete, including device-scope
+// stores that travel to memory.  The CPU build of this source has no
+// address spaces.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define ACS_GAS __attribute__((address_space(1)))
+#else
+#define ACS_GAS
+#endif
+template <class T>
+__device__ __forceinline__ ACS_GAS T *gp(T *p)
+{
+    return (ACS_GAS T *)p;
+}
+
+// 16-byte loads of the vector types through global pointers (their class
+// types cannot bind a reference to an object in another address space)
+typedef float acs_f4v __attribute__((ext_vector_type(4)));
+typedef uint32_t acs_u4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld4(const ACS_GAS float4 *p)
+{
+    const acs_f4v v = *reinterpret_cast<const ACS_GAS acs_f4v *>(p);
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint4 ld4(const ACS_GAS uint4 *p)
+{
+    const acs_u4v v = *reinterpret_cast<const ACS_GAS acs_u4v *>(p);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 // LDS scratch every body may use (bytes).
 constexpr int kBodySmem = 40 * 1024;
 
@@ -38,29 +71,29 @@ __device__ inline void piece_range(uint32_t n, uint32_t piece, uint32_t np, uint
 // island plan) is stored with system scope.  The device-scope stores are
 // integer stores of the same bits (a 16-byte value as two 8-byte halves).
 template <bool DEV>
-__device__ __forceinline__ void put(int32_t *p, int32_t v)
+__device__ __forceinline__ void put(ACS_GAS int32_t *p, int32_t v)
 {
     if constexpr (DEV) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else *p = v;
 }
 
 template <bool DEV>
-__device__ __forceinline__ void put(float *p, float v)
+__device__ __forceinline__ void put(ACS_GAS float *p, float v)
 {
     if constexpr (DEV)
-        __hip_atomic_store(reinterpret_cast<uint32_t *>(p), (uint32_t)__float_as_uint(v), __ATOMIC_RELAXED,
+        __hip_atomic_store(reinterpret_cast<ACS_GAS uint32_t *>(p), (uint32_t)__float_as_uint(v), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     else *p = v;
 }
 
 template <bool DEV, typename V16>
-__device__ __forceinline__ void put16(V16 *p, const V16 &v)
+__device__ __forceinline__ void put16(ACS_GAS V16 *p, const V16 &v)
 {
     static_assert(sizeof(V16) == 16, "16-byte value");
     if constexpr (DEV) {
         uint64_t h[2];
         __builtin_memcpy(h, &v, 16);
-        uint64_t *q = reinterpret_cast<uint64_t *>(p);
+        ACS_GAS uint64_t *q = reinterpret_cast<ACS_GAS uint64_t *>(p);
         __hip_atomic_store(q, h[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(q + 1, h[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
@@ -69,7 +102,7 @@ __device__ __forceinline__ void put16(V16 *p, const V16 &v)
 }
 
 template <bool DEV>
-__device__ __forceinline__ void put_host(int32_t *p, int32_t v)
+__device__ __forceinline__ void put_host(ACS_GAS int32_t *p, int32_t v)
 {
     if constexpr (DEV) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     else *p = v;
@@ -96,7 +129,8 @@ __device__ inline void body_scale(const acs_args_scale &a, uint32_t piece, uint3
 {
     uint32_t lo, hi;
     piece_range(a.n, piece, np, lo, hi);
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += ACS_BLOCK) put<DEV>(&a.out[i], a.a * a.x[i]);
+    const ACS_GAS float *x = gp(a.x);
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += ACS_BLOCK) put<DEV>(gp(a.out) + i, a.a * x[i]);
 }
 
 template <bool DEV>
@@ -104,17 +138,18 @@ __device__ inline void body_axpy(const acs_args_axpy &a, uint32_t piece, uint32_
 {
     uint32_t lo, hi;
     piece_range(a.n, piece, np, lo, hi);
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += ACS_BLOCK) put<DEV>(&a.out[i], fmaf(a.a, a.x[i], a.y[i]));
+    const ACS_GAS float *x = gp(a.x), *y = gp(a.y);
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += ACS_BLOCK) put<DEV>(gp(a.out) + i, fmaf(a.a, x[i], y[i]));
 }
 
 __device__ inline float sum_leaf(const acs_args_sum &a, uint32_t g)
 {
     const uint32_t l0 = a.len[0], l1 = a.nin > 1 ? a.len[1] : 0, l2 = a.nin > 2 ? a.len[2] : 0;
-    if (g < l0) return a.in[0][g];
+    if (g < l0) return gp(a.in[0])[g];
     g -= l0;
-    if (g < l1) return a.in[1][g];
+    if (g < l1) return gp(a.in[1])[g];
     g -= l1;
-    if (g < l2) return a.in[2][g];
+    if (g < l2) return gp(a.in[2])[g];
     return 0.0f;
 }
 
@@ -155,37 +190,37 @@ __device__ inline void body_sum(const acs_args_sum &a, float *red)
         if (t < s) red[t] = red[t] + red[t + s];
         __syncthreads();
     }
-    if (t == 0) put<DEV>(a.out, red[0]);
+    if (t == 0) put<DEV>(gp(a.out), red[0]);
 }
 
 // ---------------------------------------------------------------------------
 // rigid-body RL step
 // ---------------------------------------------------------------------------
 struct RLView {
-    float4 *X, *V, *P, *Q0, *Q1;
-    int32_t *deg, *adj_off, *adj, *label, *perm, *inv_perm, *isl_off, *padj_off, *padj;
+    ACS_GAS float4 *X, *V, *P, *Q0, *Q1;
+    ACS_GAS int32_t *deg, *adj_off, *adj, *label, *perm, *inv_perm, *isl_off, *padj_off, *padj;
 };
 
 __device__ inline RLView rl_view(uint64_t base, int32_t n)
 {
     uint64_t off[ACS_RL_NREGIONS];
     rl_offsets(n, off);
-    char *b = reinterpret_cast<char *>(base);
+    ACS_GAS char *b = reinterpret_cast<ACS_GAS char *>(base);
     RLView v;
-    v.X = reinterpret_cast<float4 *>(b + off[ACS_RL_X]);
-    v.V = reinterpret_cast<float4 *>(b + off[ACS_RL_V]);
-    v.P = reinterpret_cast<float4 *>(b + off[ACS_RL_P]);
-    v.Q0 = reinterpret_cast<float4 *>(b + off[ACS_RL_Q0]);
-    v.Q1 = reinterpret_cast<float4 *>(b + off[ACS_RL_Q1]);
-    v.deg = reinterpret_cast<int32_t *>(b + off[ACS_RL_DEG]);
-    v.adj_off = reinterpret_cast<int32_t *>(b + off[ACS_RL_ADJ_OFF]);
-    v.adj = reinterpret_cast<int32_t *>(b + off[ACS_RL_ADJ]);
-    v.label = reinterpret_cast<int32_t *>(b + off[ACS_RL_LABEL]);
-    v.perm = reinterpret_cast<int32_t *>(b + off[ACS_RL_PERM]);
-    v.inv_perm = reinterpret_cast<int32_t *>(b + off[ACS_RL_INV_PERM]);
-    v.isl_off = reinterpret_cast<int32_t *>(b + off[ACS_RL_ISL_OFF]);
-    v.padj_off = reinterpret_cast<int32_t *>(b + off[ACS_RL_PADJ_OFF]);
-    v.padj = reinterpret_cast<int32_t *>(b + off[ACS_RL_PADJ]);
+    v.X = reinterpret_cast<ACS_GAS float4 *>(b + off[ACS_RL_X]);
+    v.V = reinterpret_cast<ACS_GAS float4 *>(b + off[ACS_RL_V]);
+    v.P = reinterpret_cast<ACS_GAS float4 *>(b + off[ACS_RL_P]);
+    v.Q0 = reinterpret_cast<ACS_GAS float4 *>(b + off[ACS_RL_Q0]);
+    v.Q1 = reinterpret_cast<ACS_GAS float4 *>(b + off[ACS_RL_Q1]);
+    v.deg = reinterpret_cast<ACS_GAS int32_t *>(b + off[ACS_RL_DEG]);
+    v.adj_off = reinterpret_cast<ACS_GAS int32_t *>(b + off[ACS_RL_ADJ_OFF]);
+    v.adj = reinterpret_cast<ACS_GAS int32_t *>(b + off[ACS_RL_ADJ]);
+    v.label = reinterpret_cast<ACS_GAS int32_t *>(b + off[ACS_RL_LABEL]);
+    v.perm = reinterpret_cast<ACS_GAS int32_t *>(b + off[ACS_RL_PERM]);
+    v.inv_perm = reinterpret_cast<ACS_GAS int32_t *>(b + off[ACS_RL_INV_PERM]);
+    v.isl_off = reinterpret_cast<ACS_GAS int32_t *>(b + off[ACS_RL_ISL_OFF]);
+    v.padj_off = reinterpret_cast<ACS_GAS int32_t *>(b + off[ACS_RL_PADJ_OFF]);
+    v.padj = reinterpret_cast<ACS_GAS int32_t *>(b + off[ACS_RL_PADJ]);
     return v;
 }
 
@@ -263,7 +298,7 @@ __device__ inline void body_rl_predict(const acs_args_rl &a, uint32_t piece, uin
     uint32_t lo, hi;
     piece_range((uint32_t)a.n, piece, np, lo, hi);
     for (uint32_t i = lo + threadIdx.x; i < hi; i += ACS_BLOCK) {
-        float4 x = v.X[i], u = v.V[i], p;
+        float4 x = ld4(&v.X[i]), u = ld4(&v.V[i]), p;
         p.x = fmaf(a.dt, u.x, x.x);
         p.y = fmaf(a.dt, u.y, x.y);
         p.z = fmaf(a.dt, u.z, x.z);
@@ -288,7 +323,7 @@ __device__ inline void broadphase_small(const acs_args_rl &a, const RLView &v, u
     const int32_t n = a.n, lane = threadIdx.x & 63, wv = wave_index();
     uint64_t *rows = reinterpret_cast<uint64_t *>(smem);   // [64]
     const bool in = lane < n;
-    const float4 pi = in ? v.P[lane] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const float4 pi = in ? ld4(&v.P[lane]) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const float two_r = 2.0f * a.r, thr = two_r * two_r;
     for (int32_t j = wv; j < n; j += 4) {
         const float xj = lane_readf(pi.x, j), yj = lane_readf(pi.y, j), zj = lane_readf(pi.z, j);
@@ -324,7 +359,7 @@ __device__ inline void body_rl_broadphase(const acs_args_rl &a, uint8_t *smem)
     int32_t *cnt = reinterpret_cast<int32_t *>(smem + 16 * n);     // max(n, 256) ints
     int32_t *deg = cnt + (n > ACS_BLOCK ? n : ACS_BLOCK);          // n ints
     int32_t *tmp = deg + n;                                        // 4 ints
-    for (int32_t i = t; i < n; i += ACS_BLOCK) Ps[i] = v.P[i];
+    for (int32_t i = t; i < n; i += ACS_BLOCK) Ps[i] = ld4(&v.P[i]);
     __syncthreads();
     const float two_r = 2.0f * a.r, thr = two_r * two_r;
     const int32_t Q = n <= 128 ? ACS_BLOCK / n : 1;   // chunks per body
@@ -400,7 +435,7 @@ __device__ inline void body_rl_broadphase(const acs_args_rl &a, uint8_t *smem)
 // island's first position a scan of the sizes over the roots), bodies in
 // index order inside an island.
 template <bool DEV>
-__device__ inline void islands_small(const acs_args_rl &a, const RLView &v, int32_t *plan, uint8_t *smem)
+__device__ inline void islands_small(const acs_args_rl &a, const RLView &v, ACS_GAS int32_t *plan, uint8_t *smem)
 {
     const int32_t n = a.n, lane = threadIdx.x & 63;
     const bool in = lane < n;
@@ -521,7 +556,7 @@ __device__ inline void body_rl_islands(const acs_args_rl &a, uint8_t *smem)
 {
     const int32_t n = a.n, t = threadIdx.x;
     RLView v = rl_view(a.base, n);
-    int32_t *plan = reinterpret_cast<int32_t *>(a.plan);
+    ACS_GAS int32_t *plan = reinterpret_cast<ACS_GAS int32_t *>(a.plan);
     if (n <= 64) {
         islands_small<DEV>(a, v, plan, smem);
         return;
@@ -549,7 +584,7 @@ __device__ inline void body_rl_islands(const acs_args_rl &a, uint8_t *smem)
     // one coalesced copy of the adjacency into LDS instead of dependent
     // global loads inside the propagation loop
     const int32_t E = aoff[n];
-    const int32_t *A = v.adj;
+    const int32_t *A = (const int32_t *)v.adj;   // global, or the LDS copy below
     if (E <= lds_cap) {
         for (int32_t k = t; k < E; k += ACS_BLOCK) adjs[k] = v.adj[k];
         __syncthreads();
@@ -644,7 +679,7 @@ __device__ inline void body_rl_permute(const acs_args_rl &a, uint32_t piece, uin
     piece_range((uint32_t)a.n, piece, np, lo, hi);
     for (uint32_t p = lo + threadIdx.x; p < hi; p += ACS_BLOCK) {
         const uint32_t b = (uint32_t)v.perm[p];
-        put16<DEV>(&v.Q0[p], v.P[b < (uint32_t)a.n ? b : p]);
+        put16<DEV>(&v.Q0[p], ld4(&v.P[b < (uint32_t)a.n ? b : p]));
     }
 }
 
@@ -653,11 +688,11 @@ template <bool DEV>
 __device__ inline void body_rl_jacobi(const acs_args_rl &a)
 {
     RLView v = rl_view(a.base, a.n);
-    const float4 *src = (a.iter % 2 == 0) ? v.Q0 : v.Q1;
-    float4 *dst = (a.iter % 2 == 0) ? v.Q1 : v.Q0;
+    const ACS_GAS float4 *src = (a.iter % 2 == 0) ? v.Q0 : v.Q1;
+    ACS_GAS float4 *dst = (a.iter % 2 == 0) ? v.Q1 : v.Q0;
     const float two_r = 2.0f * a.r;
     for (int32_t p = a.b0 + (int32_t)threadIdx.x; p < a.b1; p += ACS_BLOCK) {
-        const float4 qp = src[p];
+        const float4 qp = ld4(&src[p]);
         float ax = 0.0f, ay = 0.0f, az = 0.0f;
         const int32_t cap = a.n * (a.n - 1);
         int32_t e0 = v.padj_off[p], e1 = v.padj_off[p + 1];
@@ -666,7 +701,7 @@ __device__ inline void body_rl_jacobi(const acs_args_rl &a)
         for (int32_t e = e0; e < e1; e++) {
             int32_t q = v.padj[e];
             if ((uint32_t)q >= (uint32_t)a.n) q = p;   // never true for islands output
-            const float4 qq = src[q];
+            const float4 qq = ld4(&src[q]);
             const float dx = qp.x - qq.x, dy = qp.y - qq.y, dz = qp.z - qq.z;
             const float d = sqrtf(dist2(dx, dy, dz));
             const float pen = two_r - d;
@@ -719,8 +754,8 @@ __device__ inline void body_rl_integrate(const acs_args_rl &a, uint32_t piece, u
     const float wlo = a.r, whi = 1.0f - a.r;
     for (uint32_t i = lo + threadIdx.x; i < hi; i += ACS_BLOCK) {
         const uint32_t ip = (uint32_t)v.inv_perm[i];
-        const float4 q = v.Q0[ip < (uint32_t)a.n ? ip : i], p = v.P[i];
-        float4 u = v.V[i], x;
+        const float4 q = ld4(&v.Q0[ip < (uint32_t)a.n ? ip : i]), p = ld4(&v.P[i]);
+        float4 u = ld4(&v.V[i]), x;
         u.x = u.x + (q.x - p.x) / a.dt;
         u.y = u.y + (q.y - p.y) / a.dt;
         u.z = u.z + (q.z - p.z) / a.dt;
@@ -771,11 +806,11 @@ __device__ __forceinline__ void conv_load(const acs_args_conv &a, int32_t py, in
     v.a0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     v.a1 = v.a0;
     if (iy >= 0 && iy < hin && ix >= 0 && ix < hin) {
-        const float4 *src = reinterpret_cast<const float4 *>(a.in + ((int64_t)iy * hin + ix) * cin + ci0 + q * 8);
-        v.a0 = src[0];
-        v.a1 = src[1];
+        const ACS_GAS float4 *src = reinterpret_cast<const ACS_GAS float4 *>(gp(a.in) + ((int64_t)iy * hin + ix) * cin + ci0 + q * 8);
+        v.a0 = ld4(src);
+        v.a1 = ld4(src + 1);
     }
-    const float *wr = a.w + (int64_t)(kc0 + q * 8) * cout + n0 + j;
+    const ACS_GAS float *wr = gp(a.w) + (int64_t)(kc0 + q * 8) * cout + n0 + j;
 #pragma unroll
     for (int s = 0; s < 8; s++) {
         v.b0[s] = wr[(int64_t)s * cout];
@@ -835,7 +870,7 @@ __device__ inline void conv_tile(const acs_args_conv &a, int32_t m0, int32_t n0,
         v += part[(16 + row) * 32 + col];
         v += part[(32 + row) * 32 + col];
         v += part[(48 + row) * 32 + col];
-        put<DEV>(&a.out[(int64_t)(m0 + row) * cout + n0 + col], v + a.bias[n0 + col]);
+        put<DEV>(gp(a.out) + (int64_t)(m0 + row) * cout + n0 + col, v + gp(a.bias)[n0 + col]);
     }
 }
 
@@ -866,8 +901,8 @@ __device__ inline void body_join(const acs_args_join &a, uint32_t piece, uint32_
     if (v4) {
         const uint32_t hv = lo + (hi - lo) / 4 * 4;
         for (uint32_t q = lo / 4 + threadIdx.x; q < hv / 4; q += ACS_BLOCK) {
-            const float4 x = reinterpret_cast<const float4 *>(a.a)[q];
-            float4 y = a.b ? reinterpret_cast<const float4 *>(a.b)[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            const float4 x = ld4(reinterpret_cast<const ACS_GAS float4 *>(gp(a.a)) + q);
+            float4 y = a.b ? ld4(reinterpret_cast<const ACS_GAS float4 *>(gp(a.b)) + q) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             float4 r;
             if (a.b) {
                 r.x = relu(x.x + y.x);
@@ -880,14 +915,14 @@ __device__ inline void body_join(const acs_args_join &a, uint32_t piece, uint32_
                 r.z = relu(x.z);
                 r.w = relu(x.w);
             }
-            put16<DEV>(&reinterpret_cast<float4 *>(a.out)[q], r);
+            put16<DEV>(reinterpret_cast<ACS_GAS float4 *>(gp(a.out)) + q, r);
         }
         i = hv;
     }
     if (a.b) {
-        for (uint32_t e = i + threadIdx.x; e < hi; e += ACS_BLOCK) put<DEV>(&a.out[e], relu(a.a[e] + a.b[e]));
+        for (uint32_t e = i + threadIdx.x; e < hi; e += ACS_BLOCK) put<DEV>(gp(a.out) + e, relu(gp(a.a)[e] + gp(a.b)[e]));
     } else {
-        for (uint32_t e = i + threadIdx.x; e < hi; e += ACS_BLOCK) put<DEV>(&a.out[e], relu(a.a[e]));
+        for (uint32_t e = i + threadIdx.x; e < hi; e += ACS_BLOCK) put<DEV>(gp(a.out) + e, relu(gp(a.a)[e]));
     }
 }
 
@@ -902,12 +937,12 @@ __device__ inline void body_avgpool(const acs_args_avgpool &a)
         for (; q + 16 <= a.hw; q += 16) {
             float v[16];
 #pragma unroll
-            for (int u = 0; u < 16; u++) v[u] = a.in[(int64_t)(q + u) * a.c + c];
+            for (int u = 0; u < 16; u++) v[u] = gp(a.in)[(int64_t)(q + u) * a.c + c];
 #pragma unroll
             for (int u = 0; u < 16; u++) acc += v[u];
         }
-        for (; q < a.hw; q++) acc += a.in[(int64_t)q * a.c + c];
-        put<DEV>(&a.out[c], acc / (float)a.hw);
+        for (; q < a.hw; q++) acc += gp(a.in)[(int64_t)q * a.c + c];
+        put<DEV>(gp(a.out) + c, acc / (float)a.hw);
     }
 }
 
@@ -917,20 +952,20 @@ template <bool DEV>
 __device__ inline void body_fc(const acs_args_fc &a)
 {
     for (int32_t j = threadIdx.x; j < a.cout; j += ACS_BLOCK) {
-        float acc = a.bias[j];
+        float acc = gp(a.bias)[j];
         int32_t i = 0;
         for (; i + 16 <= a.cin; i += 16) {
             float x[16], w[16];
 #pragma unroll
             for (int u = 0; u < 16; u++) {
-                x[u] = a.in[i + u];
-                w[u] = a.w[(int64_t)(i + u) * a.cout + j];
+                x[u] = gp(a.in)[i + u];
+                w[u] = gp(a.w)[(int64_t)(i + u) * a.cout + j];
             }
 #pragma unroll
             for (int u = 0; u < 16; u++) acc = fmaf(x[u], w[u], acc);
         }
-        for (; i < a.cin; i++) acc = fmaf(a.in[i], a.w[(int64_t)i * a.cout + j], acc);
-        put<DEV>(&a.out[j], acc);
+        for (; i < a.cin; i++) acc = fmaf(gp(a.in)[i], gp(a.w)[(int64_t)i * a.cout + j], acc);
+        put<DEV>(gp(a.out) + j, acc);
     }
 }
 
@@ -939,9 +974,9 @@ template <bool DEV>
 __device__ inline void body_copy(const acs_args_copy &a, uint32_t piece, uint32_t np)
 {
     const uint64_t nv = a.bytes / 16;
-    const uint4 *src = reinterpret_cast<const uint4 *>(a.src);
-    uint4 *dst = reinterpret_cast<uint4 *>(a.dst);
-    for (uint64_t i = (uint64_t)piece * ACS_BLOCK + threadIdx.x; i < nv; i += (uint64_t)np * ACS_BLOCK) put16<DEV>(&dst[i], src[i]);
+    const ACS_GAS uint4 *src = reinterpret_cast<const ACS_GAS uint4 *>(gp(a.src));
+    ACS_GAS uint4 *dst = reinterpret_cast<ACS_GAS uint4 *>(gp(a.dst));
+    for (uint64_t i = (uint64_t)piece * ACS_BLOCK + threadIdx.x; i < nv; i += (uint64_t)np * ACS_BLOCK) put16<DEV>(&dst[i], ld4(&src[i]));
 }
 
 // one lane stores; the system-scope release orders it after the writes of
@@ -950,7 +985,7 @@ __device__ inline void body_copy(const acs_args_copy &a, uint32_t piece, uint32_
 // that sees the flag sees their results
 __device__ inline void body_signal(const acs_args_signal &a)
 {
-    if (threadIdx.x == 0) __hip_atomic_store(a.addr, a.value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (threadIdx.x == 0) __hip_atomic_store(gp(a.addr), a.value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 template <typename T>

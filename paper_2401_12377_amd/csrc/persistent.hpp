@@ -218,6 +218,7 @@ __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
 {
     const uint32_t lane = threadIdx.x & 63u;
     const int32_t G = p.n_groups;
+    ACS_GAS HostCtrl *const ctrl = gp(p.ctrl);
     // one window: a constant, so that ring positions are a mask, not a division
     const uint32_t depth = NG == 1 ? kLdsDescs : lds_depth(G), ring_cap = p.ring_mask + 1;
     constexpr uint32_t kRows = 8, kJobs = kRows * 4;   // descriptors per copy round
@@ -240,9 +241,9 @@ __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
         uint64_t t[NG];
 #pragma unroll
         for (int g = 0; g < NG; g++)
-            t[g] = g < G ? __hip_atomic_load(&p.ctrl->tail[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) : 0ull;
-        const uint64_t s0 = __hip_atomic_load(&p.ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        const uint64_t sr = __hip_atomic_load(&p.ctrl->snap_req, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            t[g] = g < G ? __hip_atomic_load(&ctrl->tail[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) : 0ull;
+        const uint64_t s0 = __hip_atomic_load(&ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        const uint64_t sr = __hip_atomic_load(&ctrl->snap_req, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         // Job j of the round is descriptor consumed[g] + (j - start[g]) of the
         // group g whose range [start[g], start[g] + cnt[g]) holds j.
         uint32_t cnt[NG], start[NG], total = 0;
@@ -287,8 +288,8 @@ __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
             dst_off[r] = ~0u;
             v[r] = make_uint4(0u, 0u, 0u, 0u);
             if (j < total) {
-                const DevDesc *src = p.ring + (uint64_t)gg * ring_cap + ((cons + ii) & p.ring_mask);
-                v[r] = reinterpret_cast<const uint4 *>(src)[c];
+                const ACS_GAS DevDesc *src = gp(p.ring) + (uint64_t)gg * ring_cap + ((cons + ii) & p.ring_mask);
+                v[r] = reinterpret_cast<const ACS_GAS uint4 *>(src)[c];
                 dst_off[r] = (gg * depth + ((ft + ii) & (depth - 1u))) * 256u + c * 16u;
             }
         }
@@ -323,7 +324,7 @@ __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
                 if (lane == 0) LDS_STORE(fc ? &fs->staged : &fs->tail[g], ftail[g]);
                 if (consumed[g] - told[g] >= tell_every) {
                     if (lane == 0)
-                        __hip_atomic_store(&p.ctrl->consumed[g], consumed[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                        __hip_atomic_store(&ctrl->consumed[g], consumed[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                     told[g] = consumed[g];
                 }
             }
@@ -332,7 +333,7 @@ __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
             for (int g = 0; g < NG; g++)
                 if (g < G && told[g] != consumed[g]) {
                     if (lane == 0)
-                        __hip_atomic_store(&p.ctrl->consumed[g], consumed[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                        __hip_atomic_store(&ctrl->consumed[g], consumed[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                     told[g] = consumed[g];
                 }
             if (st == 2) break;   // host abort: leave even if the window wave is gone
@@ -388,16 +389,16 @@ __device__ inline void check_wave(const DevParams &p, FetchShared *fs, uint32_t 
         }
     }
     if (lane == 0)
-        __hip_atomic_store(&p.ctrl->check_wave_tests[c], tests, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&gp(p.ctrl)->check_wave_tests[c], tests, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Trace records are written with device-scope stores like everything else
 // that workers touch: workers update t_start and t_end of a record with
 // atomics, which the write-back of a plain store's dirty bytes from the
 // window wave's L2 could later overwrite.
-__device__ inline void tput(int64_t *f, int64_t v) { __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ inline void tput(ACS_GAS int64_t *f, int64_t v) { __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
-__device__ inline void trace_insert(acs_trace_rec *r, uint64_t seq, int32_t slot, int32_t kid, uint64_t ev, uint64_t valid,
+__device__ inline void trace_insert(ACS_GAS acs_trace_rec *r, uint64_t seq, int32_t slot, int32_t kid, uint64_t ev, uint64_t valid,
                                     uint64_t up)
 {
     tput(&r->seq, (int64_t)seq);
@@ -406,8 +407,8 @@ __device__ inline void trace_insert(acs_trace_rec *r, uint64_t seq, int32_t slot
     tput(&r->ev_insert, (int64_t)ev);
     tput(&r->ev_dispatch, -1);
     tput(&r->ev_retire, -1);
-    tput(reinterpret_cast<int64_t *>(&r->valid_mask), (int64_t)valid);
-    tput(reinterpret_cast<int64_t *>(&r->up_mask), (int64_t)up);
+    tput(reinterpret_cast<ACS_GAS int64_t *>(&r->valid_mask), (int64_t)valid);
+    tput(reinterpret_cast<ACS_GAS int64_t *>(&r->up_mask), (int64_t)up);
     tput(&r->t_start, INT64_MAX);
     tput(&r->t_end, 0);
     tput(&r->t_dispatch, -1);
@@ -450,6 +451,9 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
     const uint32_t lane = threadIdx.x;
     const int W = p.W, G = p.n_groups;
     const bool tr = p.trace != nullptr;
+    ACS_GAS HostCtrl *const ctrl = gp(p.ctrl);
+    ACS_GAS DevState *const st = gp(p.st);
+    ACS_GAS acs_trace_rec *const trace = gp(p.trace);
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint32_t depth = NG == 1 ? kLdsDescs : lds_depth(G);   // a constant for one window
     const bool hc = NG == 1 && p.host_check > 0;
@@ -499,7 +503,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
     // valid they bound the positions an insertion must test
     uint64_t over4 = 0, over2 = 0;
 
-    if (lane == 0) __hip_atomic_store(&p.ctrl->alive, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (lane == 0) __hip_atomic_store(&ctrl->alive, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 
     for (uint32_t iter = 1;; iter++) {
         bool progress = false;
@@ -510,7 +514,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
         // read relaxed: the window wave reads no task results, and the
         // workers acquire before their bodies start.
         const bool mine = (exec >> lane) & 1ull;
-        const uint32_t cdone = mine ? __hip_atomic_load(&p.st->done[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+        const uint32_t cdone = mine ? __hip_atomic_load(&st->done[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
 
         // ---- admission in program order (per group) while a slot is free, a
         // bounded number of passes; each pass admits one kernel into every
@@ -547,7 +551,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                     const uint32_t np = npr < kMaxPieces ? npr : kMaxPieces;
                     // the descriptor goes to the task table as it is
                     if (lane < kDescCopyDwords)
-                        __hip_atomic_store(reinterpret_cast<uint32_t *>(&p.st->task[slot]) + lane, dw, __ATOMIC_RELAXED,
+                        __hip_atomic_store(reinterpret_cast<ACS_GAS uint32_t *>(&st->task[slot]) + lane, dw, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
                     uint64_t upm = 0;
                     if (!hc) {
@@ -581,7 +585,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                         mykid = kid;
                         mynp = np;
                         if (np > 1) target += kWave * np;
-                        __hip_atomic_store(&p.st->task[slot].ptarget, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&st->task[slot].ptarget, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
                     if (!hc) {
                         const uint64_t rbit = bit * repmul;
@@ -592,7 +596,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                         over2 = nseg > 2u ? (over2 | bit) : (over2 & ~bit);
                     }
                     if (tr && lane == 0 && seq < p.trace_cap) {
-                        trace_insert(&p.trace[seq], seq, slot, kid, ev, valid, upm);
+                        trace_insert(&trace[seq], seq, slot, kid, ev, valid, upm);
                     }
                     ev++;
                     valid |= bit;
@@ -639,7 +643,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                     for (int g = 0; g < NG; g++)
                         if ((adm >> g) & 1u) {
                             if (lane < kDescCopyDwords)
-                                __hip_atomic_store(reinterpret_cast<uint32_t *>(&p.st->task[newl[g]]) + lane, dwg[g],
+                                __hip_atomic_store(reinterpret_cast<ACS_GAS uint32_t *>(&st->task[newl[g]]) + lane, dwg[g],
                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                             newbits |= 1ull << newl[g];
                         }
@@ -673,9 +677,9 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                         const uint32_t npr = d->npieces;
                         mynp = npr < kMaxPieces ? npr : kMaxPieces;
                         if (mynp > 1) target += kWave * mynp;
-                        __hip_atomic_store(&p.st->task[lane].ptarget, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&st->task[lane].ptarget, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         if (tr && myseq < p.trace_cap) {
-                            trace_insert(&p.trace[myseq], myseq, (int32_t)lane, mykid, ev, valid & mygroup, up);
+                            trace_insert(&trace[myseq], myseq, (int32_t)lane, mykid, ev, valid & mygroup, up);
                         }
                     }
                     // write flags of the new occupants' ranges, for every replica lane
@@ -721,8 +725,8 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                 if (tr) {
                     const uint64_t now = wall_clock64();
                     if (((done >> lane) & 1ull) && myseq < p.trace_cap) {
-                        tput(&p.trace[myseq].ev_retire, (int64_t)(ev + __builtin_popcountll(done & lane_lt)));
-                        tput(&p.trace[myseq].t_retire, (int64_t)now);
+                        tput(&trace[myseq].ev_retire, (int64_t)(ev + __builtin_popcountll(done & lane_lt)));
+                        tput(&trace[myseq].t_retire, (int64_t)now);
                     }
                 }
                 ev += __builtin_popcountll(done);
@@ -766,9 +770,9 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                 const int j = __builtin_ctzll(m);
                 const uint64_t upj = readlane64(up, j);
                 if ((upj >> lane) & 1ull)
-                    __hip_atomic_store(&p.st->wait_target[j][lane], (uint32_t)(myseq + 1), __ATOMIC_RELAXED,
+                    __hip_atomic_store(&st->wait_target[j][lane], (uint32_t)(myseq + 1), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
-                if (lane == 0) __hip_atomic_store(&p.st->task[j].wait_mask, upj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (lane == 0) __hip_atomic_store(&st->task[j].wait_mask, upj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             // every task-table store of this wave (device scope) is complete
             // before any work-queue entry that points at it is stored.
@@ -792,7 +796,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
             if (mine && mynp == 1) {
                 const uint64_t t = pub + before;
                 const uint64_t v = ((uint64_t)(uint32_t)(t + 1) << 32) | ((uint64_t)lane << 24);
-                __hip_atomic_store(&p.st->ent[t & (kQueueCap - 1)], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&st->ent[t & (kQueueCap - 1)], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             for (uint64_t m = __ballot(mine && mynp > 1); m; m &= m - 1) {
                 const int l = __builtin_ctzll(m);
@@ -800,13 +804,13 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                 for (uint32_t q = lane; q < nl; q += kWave) {
                     const uint64_t t = pub + bl + q;
                     const uint64_t v = ((uint64_t)(uint32_t)(t + 1) << 32) | ((uint64_t)(uint32_t)l << 24) | q;
-                    __hip_atomic_store(&p.st->ent[t & (kQueueCap - 1)], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&st->ent[t & (kQueueCap - 1)], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
             if (mine) {
                 if (tr && myseq < p.trace_cap) {
-                    tput(&p.trace[myseq].ev_dispatch, (int64_t)(ev + rank));
-                    tput(&p.trace[myseq].t_dispatch, (int64_t)wall_clock64());
+                    tput(&trace[myseq].ev_dispatch, (int64_t)(ev + rank));
+                    tput(&trace[myseq].t_dispatch, (int64_t)wall_clock64());
                 }
             }
             pub += total;
@@ -832,7 +836,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
             for (int g = 0; g < NG; g++)
                 if ((drained >> g) & 1u) {
                     if (lane == 0)
-                        __hip_atomic_store(&p.ctrl->retired[g], retired[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                        __hip_atomic_store(&ctrl->retired[g], retired[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                     published[g] = retired[g];
                 }
         }
@@ -855,14 +859,14 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                     e.upstream_mask = up;
                     e.slot = (int32_t)lane;
                     e.reserved = 0;
-                    p.ctrl->snap[rank] = e;
+                    ctrl->snap[rank] = e;
                 }
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
                 if (lane == 0) {
-                    __hip_atomic_store(&p.ctrl->snap_count, (uint64_t)__builtin_popcountll(valid), __ATOMIC_RELAXED,
+                    __hip_atomic_store(&ctrl->snap_count, (uint64_t)__builtin_popcountll(valid), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_SYSTEM);
-                    __hip_atomic_store(&p.ctrl->snap_ack, sr, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+                    __hip_atomic_store(&ctrl->snap_ack, sr, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
                 }
                 snap_seen = sr;
             }
@@ -882,12 +886,12 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
     for (uint32_t i = lane; i < (uint32_t)p.n_workers; i += 64) {
         const uint64_t t = pub + i;
         const uint64_t v = ((uint64_t)(uint32_t)(t + 1) << 32) | ((uint64_t)kSentinelSlot << 24);
-        __hip_atomic_store(&p.st->ent[t & (kQueueCap - 1)], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&st->ent[t & (kQueueCap - 1)], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (lane == 0) {
-        __hip_atomic_store(&p.ctrl->checks, checks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        __hip_atomic_store(&p.ctrl->published, pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        __hip_atomic_store(&p.ctrl->exited, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&ctrl->checks, checks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&ctrl->published, pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&ctrl->exited, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -904,22 +908,25 @@ __device__ inline void worker(const DevParams &p, uint8_t *smem, Mail *mail)
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
     const bool wave0 = uni32(tid) < 64u;
     const bool tr = p.trace != nullptr;
+    ACS_GAS HostCtrl *const ctrl = gp(p.ctrl);
+    ACS_GAS DevState *const st = gp(p.st);
+    ACS_GAS acs_trace_rec *const trace = gp(p.trace);
     uint64_t *margs = reinterpret_cast<uint64_t *>(mail->args);
     for (;;) {
         if (wave0) {
             // every lane adds 1, so one ticket is kWave counts of deq: with a
             // value the same on all lanes the compiler issues one atomic and
             // a popcount, where a per-lane value costs a loop over the lanes
-            const uint64_t t = uni64(__hip_atomic_fetch_add(&p.st->deq, 1ull, __ATOMIC_RELAXED,
+            const uint64_t t = uni64(__hip_atomic_fetch_add(&st->deq, 1ull, __ATOMIC_RELAXED,
                                                             __HIP_MEMORY_SCOPE_AGENT)) / kWave;
             const uint32_t tag = (uint32_t)(t + 1);
             uint64_t v;
             for (uint32_t spin = 1;; spin++) {
-                v = uni64(__hip_atomic_load(&p.st->ent[t & (kQueueCap - 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                v = uni64(__hip_atomic_load(&st->ent[t & (kQueueCap - 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
                 if ((uint32_t)(v >> 32) == tag) break;
                 // a host abort releases waiting workers even if the window wave has left
                 if ((spin & 1023u) == 0 &&
-                    uni64(__hip_atomic_load(&p.ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) == 2ull) {
+                    uni64(__hip_atomic_load(&ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) == 2ull) {
                     v = (uint64_t)kSentinelSlot << 24;
                     break;
                 }
@@ -931,27 +938,27 @@ __device__ inline void worker(const DevParams &p, uint8_t *smem, Mail *mail)
             mail->slot = slot;
             mail->piece = (uint32_t)v & 0xFFFFFFu;
             if (slot != kSentinelSlot) {
-                const TaskEntry *te = &p.st->task[slot];
+                const ACS_GAS TaskEntry *te = &st->task[slot];
                 mail->kid = te->kid;
                 mail->np = te->npieces;
                 mail->ptarget = te->ptarget;
                 mail->seq = te->seq;
-                margs[lane & 7u] = reinterpret_cast<const uint64_t *>(te->args)[lane & 7u];
+                margs[lane & 7u] = reinterpret_cast<const ACS_GAS uint64_t *>(te->args)[lane & 7u];
                 // dispatched early: wait until every upstream kernel's counter
                 // has reached the value that marks it complete (lane s watches slot s)
                 const uint64_t wm = uni64(te->wait_mask);
                 if (wm != 0) {
                     const bool watch = (wm >> lane) & 1ull;
-                    const uint32_t tgt = watch ? p.st->wait_target[slot][lane] : 0u;
+                    const uint32_t tgt = watch ? st->wait_target[slot][lane] : 0u;
                     for (uint32_t spin = 1;; spin++) {
                         bool ok = true;
                         if (watch) {
-                            const uint32_t c = __hip_atomic_load(&p.st->done[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            const uint32_t c = __hip_atomic_load(&st->done[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                             ok = (int32_t)(c - tgt) >= 0;
                         }
                         if (__ballot(!ok) == 0) break;
                         if ((spin & 1023u) == 0 &&
-                            uni64(__hip_atomic_load(&p.ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) == 2ull)
+                            uni64(__hip_atomic_load(&ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) == 2ull)
                             break;
                         __builtin_amdgcn_s_sleep(1);
                     }
@@ -977,8 +984,10 @@ __device__ inline void worker(const DevParams &p, uint8_t *smem, Mail *mail)
                 // behind each other before the completion store below
                 const uint64_t t1 = uni64(wall_clock64()), t0 = uni64(mail->t0);
                 if (lane == 0) {
-                    atomicMin(reinterpret_cast<unsigned long long *>(&p.trace[seq].t_start), (unsigned long long)t0);
-                    atomicMax(reinterpret_cast<unsigned long long *>(&p.trace[seq].t_end), (unsigned long long)t1);
+                    __hip_atomic_fetch_min(reinterpret_cast<ACS_GAS uint64_t *>(&trace[seq].t_start), t0, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_fetch_max(reinterpret_cast<ACS_GAS uint64_t *>(&trace[seq].t_end), t1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
             // a kernel of several pieces is complete when the last piece is
@@ -988,12 +997,12 @@ __device__ inline void worker(const DevParams &p, uint8_t *smem, Mail *mail)
             bool last = true;
             if (np > 1) {
                 // every lane adds 1: a piece counts kWave (see the ticket above)
-                const uint32_t old = uni32(__hip_atomic_fetch_add(&p.st->cnt[slot], 1u, __ATOMIC_RELAXED,
+                const uint32_t old = uni32(__hip_atomic_fetch_add(&st->cnt[slot], 1u, __ATOMIC_RELAXED,
                                                                   __HIP_MEMORY_SCOPE_AGENT));
                 last = old + kWave == uni32(mail->ptarget);
             }
             if (last)
-                __hip_atomic_store(&p.st->done[slot], (uint32_t)(seq + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&st->done[slot], (uint32_t)(seq + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
