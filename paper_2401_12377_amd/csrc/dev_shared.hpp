@@ -11,15 +11,16 @@ namespace acs {
 
 constexpr int kSegs = ACS_K_MAX;
 
-// One submitted kernel as it travels from the host to the scheduler wave.
+// One submitted kernel as it travels from the host to the scheduler.
 // Segments are stored as [start, end) with end saturated at 2^64 - 1; unused
-// entries are the empty range [0, 0), which overlaps nothing.  The scheduler
-// copies the first kDescCopyDwords words into the task table when it inserts
-// the kernel (one 4-byte store per lane); the last 40 bytes hold what the
-// scheduler fills in at dispatch for the workers and, in host-check mode,
-// the upstream list the host computed.
+// entries are the empty range [0, 0), which overlaps nothing.  gseq numbers
+// the kernels of one window group without gaps (0, 1, 2, ...); completions
+// and dependency distances are kept in that numbering.  The FIFO wave copies
+// every descriptor, as the host wrote it, into the device-memory ring the
+// workers read (DevState::dring, at its group and gseq), and stages it in
+// LDS for the window.
 struct DevDesc {
-    uint64_t seq;
+    uint64_t seq;           // submission index over all groups (traces)
     int32_t kid;
     uint32_t npieces;
     uint32_t nseg;          // segments in use (reads and writes)
@@ -27,20 +28,21 @@ struct DevDesc {
     uint64_t s[kSegs];
     uint64_t e[kSegs];
     uint8_t args[ACS_ARGS_MAX];
-    // scheduler-owned part (the host leaves it zero)
-    uint64_t wait_mask;     // window slots still running when the kernel was dispatched
-    uint32_t ptarget;       // cnt[slot] after this kernel's last piece (npieces > 1; 64 per piece)
-    uint32_t pad0;
-    // host-check mode: bit d set when the host found the kernel submitted
-    // d + 1 places earlier in conflict with this one (read by the window wave
-    // from the staged copy; not part of the task table)
+    uint32_t gseq;          // index of the kernel within its window group
+    uint32_t group;
+    uint64_t pad0;
+    // bit b set: the kernel of the same group with gseq - 1 - b conflicts
+    // with this one.  Written by the host (host-check mode), by a check wave
+    // into the staged copy (the window then writes it into the ring), or by
+    // the window wave after its own checks.
     uint64_t host_up;
     uint32_t pad[4];
 };
 static_assert(sizeof(DevDesc) == 256, "descriptor must be 256 bytes");
 static_assert(offsetof(DevDesc, host_up) == 232, "host_up is dwords 58 and 59 of the descriptor");
-constexpr uint32_t kDescCopyDwords = 54;   // dwords of DevDesc the task table needs
+static_assert(offsetof(DevDesc, gseq) == 216 && offsetof(DevDesc, group) == 220, "gseq and group are dwords 54, 55");
 constexpr int kHostUpDword = 58;
+constexpr int kGseqDword = 54;
 constexpr int kSegStartDword = 6;          // s[k] is dwords 6 + 2k and 7 + 2k
 constexpr int kSegEndDword = 22;           // e[k] is dwords 22 + 2k and 23 + 2k
 static_assert(offsetof(DevDesc, s) == 4 * kSegStartDword && offsetof(DevDesc, e) == 4 * kSegEndDword,
@@ -69,35 +71,42 @@ struct HostCtrl {
     acs_entry snap[ACS_W_MAX];
 };
 
-// The task table holds, per window slot, the descriptor of the kernel in
-// that slot.  A kernel is handed to the workers as soon as every kernel it
-// waits for has been handed out; wait_mask and wait_target then tell its
-// workers which completion words must reach which values before the body may
-// start.
+// Completion.  The worker that finishes a kernel's last piece stores gseq + 1
+// into dseq[group][gseq % kSeqRing] (a device-scope store: it reaches a
+// polling wave on another XCD in a few hundred nanoseconds, an atomic
+// read-modify-write takes several times longer).  The window wave polls the
+// word of each kernel it holds; a worker whose kernel depends on kernel k of
+// its group waits until dseq[group][k % kSeqRing] has reached k + 1.  The
+// ring is large enough because no two kernels of one group in flight (or
+// waited for) are kSeqRing apart: admission holds a kernel while one 64 or
+// more older is still in the window, and dependencies reach back at most 64.
+// Kernels of several pieces count their pieces in cnt[group][gseq %
+// kSeqRing] first (64 per piece); the last piece resets the counter before
+// it marks the kernel complete.
 //
-// Completion is signalled with a device-scope store: the worker that
-// finishes a kernel's last piece writes seq + 1 (mod 2^32) into done[slot].
-// A store reaches another XCD's polling load in a few hundred nanoseconds,
-// an atomic read-modify-write takes several times longer, so the per-slot
-// piece counter cnt[] is touched only by kernels of more than one piece, to
-// find which piece is the last.
-using TaskEntry = DevDesc;
-
+// Work queue entries: tag (8 bits: (ticket >> 16) + 1, so that an entry left
+// from an earlier lap of the queue never matches) | group (8; kSentinelGroup
+// tells a worker to leave) | piece (16) | gseq (32).
 constexpr uint32_t kQueueCap = 1u << 16;       // work queue entries (power of two)
 constexpr uint32_t kMaxPieces = 256;           // pieces per task
-constexpr uint32_t kSentinelSlot = 0xFF;
+constexpr uint32_t kSentinelGroup = 0xFF;
+constexpr uint32_t kSeqRing = 128;             // completion words per group
+constexpr uint32_t kDescRing = 512;            // device descriptor ring entries per group
+
+constexpr uint64_t queue_entry(uint64_t ticket, uint32_t group, uint32_t piece, uint32_t gseq)
+{
+    return ((((ticket >> 16) + 1) & 0xFFull) << 56) | ((uint64_t)(group & 0xFFu) << 48) |
+           ((uint64_t)(piece & 0xFFFFu) << 32) | gseq;
+}
 
 // Device-resident scheduler state (device memory).
 struct DevState {
     uint64_t deq;                 // work-queue tickets taken by workers, 64 per ticket
     uint64_t pad0[31];
-    uint32_t cnt[ACS_W_MAX];      // per-slot piece counters, 64 per piece (monotonic, multi-piece kernels only)
-    uint64_t pad1[32];
-    uint32_t done[ACS_W_MAX];     // per-slot completion words: seq + 1 of the last kernel finished
-    uint64_t pad2[32];
-    TaskEntry task[ACS_W_MAX];
-    uint32_t wait_target[ACS_W_MAX][ACS_W_MAX];   // [slot][upstream slot]: done[] value to wait for
-    uint64_t ent[kQueueCap];      // work-queue entries: tag(32) | slot(8) | piece(24)
+    uint32_t dseq[kMaxGroups][kSeqRing];
+    uint32_t cnt[kMaxGroups][kSeqRing];
+    DevDesc dring[kMaxGroups][kDescRing];
+    uint64_t ent[kQueueCap];
 };
 
 struct DevParams {

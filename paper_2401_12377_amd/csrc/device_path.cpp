@@ -137,6 +137,8 @@ public:
             tmp.e[k] = d.e[k];
         }
         memcpy(tmp.args, d.args, ACS_ARGS_MAX);
+        tmp.gseq = (uint32_t)submitted_[g];   // the group's own numbering, without gaps
+        tmp.group = (uint32_t)g;
         if (hc_ > 0) tmp.host_up = host_check(d);
         memcpy((void *)&r, &tmp, sizeof(DevDesc));
         submitted_[g]++;
@@ -308,20 +310,19 @@ public:
 
 private:
     // Host-check mode (the split of Section IV-C): the new kernel is checked
-    // against the kernels submitted with the M sequence numbers before its
-    // own, the host's scheduled list.  The list is stale by design: some of
-    // them may have completed (the device drops those), and none older can
-    // still be in the window when the kernel is inserted (the device holds it
-    // back until that is so).  Bit d of the result: sequence number seq - 1 - d.
+    // against the M kernels submitted before it (one window group, numbered
+    // without gaps), the host's scheduled list.  The list is stale by design:
+    // some of them may have completed (the workers find those complete), and
+    // none older can still be in the window when the kernel is inserted (the
+    // device holds it back until that is so).  Bit k of the result: the
+    // kernel k + 1 places back.
     uint64_t host_check(const Desc &d)
     {
         const uint64_t M = (uint64_t)hc_;
         uint64_t mask = 0;
         for (uint64_t k = 0; k < std::min<uint64_t>(M, hist_n_); k++) {
             const Desc &o = hist_[(size_t)((hist_n_ - 1 - k) % M)];
-            const uint64_t back = d.seq - 1 - o.seq;
-            if (back >= M) break;   // older entries are farther back still
-            if (descs_conflict(o, d, &host_tests_)) mask |= 1ull << back;
+            if (descs_conflict(o, d, &host_tests_)) mask |= 1ull << k;
         }
         hist_[(size_t)(hist_n_ % M)] = d;
         hist_n_++;

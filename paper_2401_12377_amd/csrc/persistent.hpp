@@ -1,40 +1,45 @@
 // Wave-level building blocks of the persistent scheduler kernel (device code).
 //
 // Workgroup 0 is the window:
-//   wave 0  the window module.  Lane i owns window slot i: its read/write
-//           ranges, its upstream bitmask and its completion target live in
-//           that lane's registers.  Inserting a kernel is one pass in which
-//           every lane tests the new kernel's ranges against its own slot
-//           (Algorithm 1, both directions) and a ballot gives the new
-//           kernel's upstream mask.  Completions are seen by polling the
-//           per-slot completion counters; a ballot of finished slots clears
-//           those bits in every lane's mask at once.  The ready mask is a
-//           ballot of (valid, not executing, empty upstream mask); ready
-//           kernels are published, oldest first, as (slot, piece) entries of a
-//           work queue in device memory.
+//   wave 0  the window module.  Lane i owns window slot i: the group
+//           sequence number, piece count and upstream list (by distance) of
+//           the kernel it holds live in that lane's registers.  A pass admits
+//           every staged kernel that finds a free slot, in submission order,
+//           and publishes it to the workers at once: a kernel may start as
+//           soon as it is handed out, because its workers wait for the
+//           completion words of its upstream kernels themselves.  Completions
+//           are seen by polling those words; a ballot of the finished slots
+//           frees them.  With one window and the checks made ahead of it
+//           (check waves or the host) a pass handles all its kernels in
+//           lane-parallel steps; otherwise the wave tests each new kernel's
+//           ranges against its slots (Algorithm 1, both directions), one
+//           kernel per group per step, and turns the ballot of conflicting
+//           slots into the same upstream list.
 //   wave 1  the input FIFO: copies descriptors from the host-resident rings
-//           into small rings in LDS, so that host-memory latency never
+//           into the device-memory ring the workers read and into small
+//           rings in LDS for the window, so that host-memory latency never
 //           stalls the window loop.
 //   waves 2 and 3  (one window, checks ahead of the window) test each staged
 //           kernel against the 64 submitted before it, alternating between
 //           them, then hand it on to the window wave.
 // The lanes of the window wave may be split into up to eight groups, each an
 // independent window with its own input ring (for many independent task
-// graphs in one launch): one insertion pass then admits one kernel into every
-// group that has one waiting, with the same instructions.
+// graphs in one launch).
 // Workgroups 1.. are workers: each takes a ticket from the work queue, waits
-// for the entry with that ticket, runs one piece of the task body, and bumps
-// the slot's completion counter.
+// for the entry with that ticket, reads the kernel's descriptor, waits until
+// the kernels it depends on have completed, runs one piece of the task body
+// and, for the last piece, stores the kernel's completion word.
 //
 // Visibility between the waves runs on device-scope stores.  Every store that
-// another workgroup reads (task-table entries, task results) is a device-scope
-// store, which the hardware writes through the L2 of the storing XCD (the
-// XCDs' L2 caches are not coherent with each other), and it is complete once
-// the storing wave's vector-memory counter has drained.  So a wave publishes
-// by waiting for its own stores and then storing or counting the word that
-// announces them; the reader acquires (invalidating its stale cache lines)
-// after it has seen that word.  A release at device scope would instead write
-// back the whole L2 of the XCD, which serialises the pieces of a wide kernel.
+// another workgroup reads (descriptors, task results, completion words) is a
+// device-scope store, which the hardware writes through the L2 of the storing
+// XCD (the XCDs' L2 caches are not coherent with each other), and it is
+// complete once the storing wave's vector-memory counter has drained.  So a
+// wave publishes by waiting for its own stores and then storing the word
+// that announces them; the reader acquires (invalidating its stale cache
+// lines) after it has seen that word.  A release at device scope would
+// instead write back the whole L2 of the XCD, which serialises the pieces of
+// a wide kernel.
 //
 // Only HIP device built-ins are used here, so the same source also builds
 // for the host against an emulation of those built-ins (a CPU build used by
@@ -50,9 +55,11 @@ namespace acs {
 
 constexpr uint32_t kWave = 64;        // lanes of a wavefront
 constexpr uint32_t kLdsDescs = 128;   // descriptors staged in LDS (32 KB), shared by the groups (lds_depth)
-constexpr uint32_t kAdmitBatch = 16;  // insertion passes per loop (measured: admitting fewer
-                                      // while few kernels are out costs more in extra
-                                      // dispatch rounds than it saves in latency)
+constexpr uint32_t kAdmitBatch = 16;  // kernels per group admitted per loop with checks at insert
+constexpr uint32_t kSpan = 64;        // a kernel waits while one kSpan or more older (same
+                                      // group) is in the window: upstream lists reach back 64
+static_assert(kSeqRing >= 2 * kSpan, "completion ring must cover two spans");
+static_assert(kDescRing >= kLdsDescs + 2 * kSpan + 1, "descriptor ring must cover staging and window");
 
 struct FetchShared {
     uint32_t tail[kMaxGroups];   // descriptors ready for the window wave per group (FIFO or check wave)
@@ -85,9 +92,9 @@ __device__ inline void fetch_init(FetchShared *fs)
 }
 
 struct Mail {
-    uint32_t slot, piece;
+    uint32_t group, piece;
     int32_t kid;
-    uint32_t np, ptarget, pad;
+    uint32_t np, gseq, pad;
     uint64_t seq;
     uint64_t t0;
     uint8_t args[ACS_ARGS_MAX];
@@ -121,7 +128,7 @@ __device__ inline uint64_t readpair(uint32_t x, int l) { return ((uint64_t)readl
 // (the host/device split of Section IV-C with the host's part done by the
 // FIFO wave): every kernel is tested, in submission order, against the 64
 // submitted before it.  Lane l keeps the ranges of the latest kernel whose
-// sequence number is l mod 64, so one pass tests all 64 at once (Algorithm 1
+// group sequence number is l mod 64, so one pass tests all 64 at once (Algorithm 1
 // in both directions, as in the window wave).  A new read can only meet a
 // write, so it is tested against the first two positions only while no
 // kernel so far had a write at a later position (mw); the library lists a
@@ -159,7 +166,7 @@ __device__ inline uint64_t history_check(DevDesc *d, SeqHistory &h, uint32_t lan
         ns[m] = d->s[m];
         ne[m] = d->e[m];
     }
-    const uint64_t seq = readpair(dw, 0);
+    const uint32_t gq = readlane32(dw, kGseqDword);
     const uint32_t nraw = readlane32(dw, 4);
     const uint32_t nseg = nraw < (uint32_t)kSegs ? nraw : (uint32_t)kSegs;
     const uint32_t segmask = (1u << nseg) - 1u;
@@ -184,22 +191,22 @@ __device__ inline uint64_t history_check(DevDesc *d, SeqHistory &h, uint32_t lan
     }
     const uint32_t nw = (uint32_t)__builtin_popcount(wb);
     const uint64_t tests =
-        test ? (uint64_t)(nw * kSegs + (nseg - nw) * (h.mw > 2u ? kSegs : 2u)) * (seq < 64 ? seq : 64) : 0ull;
+        test ? (uint64_t)(nw * kSegs + (nseg - nw) * (h.mw > 2u ? kSegs : 2u)) * (gq < 64u ? gq : 64u) : 0ull;
     // bit b of the result is the kernel b + 1 places back, held by lane
-    // r - b mod 64 (r = seq - 1 mod 64): the lane mask reversed (lane l to
-    // bit 63 - l) and rotated right by 63 - r.  There is none when b >= seq.
+    // r - b mod 64 (r = gq - 1 mod 64): the lane mask reversed (lane l to
+    // bit 63 - l) and rotated right by 63 - r.  There is none when b >= gq.
     const uint64_t hm = __builtin_amdgcn_ballot_w64(hit);
-    const uint32_t rot = (63u - (uint32_t)((seq - 1u) & 63u)) & 63u;
+    const uint32_t rot = (63u - ((gq - 1u) & 63u)) & 63u;
     const uint64_t rv = __builtin_bitreverse64(hm);
     uint64_t up = rot ? ((rv >> rot) | (rv << (64u - rot))) : rv;
-    if (seq < 64) up &= (1ull << seq) - 1ull;
+    if (gq < 64u) up &= (1ull << gq) - 1ull;
     uint32_t *words = reinterpret_cast<uint32_t *>(d);
     if (test && lane == 0) {
         words[kHostUpDword] = (uint32_t)up;
         words[kHostUpDword + 1] = (uint32_t)(up >> 32);
     }
     // the kernel takes its place in the history
-    if (lane == (uint32_t)(seq & 63u)) {
+    if (lane == (gq & 63u)) {
 #pragma unroll
         for (int m = 0; m < kSegs; m++) {
             h.s[m] = (uint32_t)m < nseg ? ns[m] : 0ull;
@@ -219,6 +226,7 @@ __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
     const uint32_t lane = threadIdx.x & 63u;
     const int32_t G = p.n_groups;
     ACS_GAS HostCtrl *const ctrl = gp(p.ctrl);
+    ACS_GAS DevState *const st = gp(p.st);
     // one window: a constant, so that ring positions are a mask, not a division
     const uint32_t depth = NG == 1 ? kLdsDescs : lds_depth(G), ring_cap = p.ring_mask + 1;
     constexpr uint32_t kRows = 8, kJobs = kRows * 4;   // descriptors per copy round
@@ -272,6 +280,7 @@ __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
         // job 4r + l / 16
         uint4 v[kRows];
         uint32_t dst_off[kRows];
+        ACS_GAS uint64_t *ddst[kRows];   // the chunk's place in the device descriptor ring
 #pragma unroll
         for (int r = 0; r < (int)kRows; r++) {
             const uint32_t j = (uint32_t)r * 4u + lane / 16u, c = lane % 16u;
@@ -286,11 +295,15 @@ __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
                     ft = ftail[g];
                 }
             dst_off[r] = ~0u;
+            ddst[r] = nullptr;
             v[r] = make_uint4(0u, 0u, 0u, 0u);
             if (j < total) {
                 const ACS_GAS DevDesc *src = gp(p.ring) + (uint64_t)gg * ring_cap + ((cons + ii) & p.ring_mask);
-                v[r] = reinterpret_cast<const ACS_GAS uint4 *>(src)[c];
+                v[r] = ld4(reinterpret_cast<const ACS_GAS uint4 *>(src) + c);
                 dst_off[r] = (gg * depth + ((ft + ii) & (depth - 1u))) * 256u + c * 16u;
+                // the descriptor's group sequence number is its place in the group's ring
+                ddst[r] = reinterpret_cast<ACS_GAS uint64_t *>(&st->dring[gg][(uint32_t)(cons + ii) & (kDescRing - 1u)]) +
+                          2u * c;
             }
         }
         // control lines: newly published descriptors are read in later
@@ -310,9 +323,20 @@ __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
         }
         if (fresh) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
         if (total > 0) {
+            // the copy the workers read, with device scope (they run on
+            // other XCDs); complete before the window can hand the kernel out
+#pragma unroll
+            for (int r = 0; r < (int)kRows; r++)
+                if (ddst[r]) {
+                    __hip_atomic_store(ddst[r], ((uint64_t)v[r].y << 32) | v[r].x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(ddst[r] + 1, ((uint64_t)v[r].w << 32) | v[r].z, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                }
 #pragma unroll
             for (int r = 0; r < (int)kRows; r++)
                 if (dst_off[r] != ~0u) *reinterpret_cast<uint4 *>(reinterpret_cast<char *>(fs->ring) + dst_off[r]) = v[r];
+            // 0x0F70: vmcnt 0, expcnt 7, lgkmcnt 15
+            __builtin_amdgcn_s_waitcnt(0x0F70);
             // every lane's part of the copy lands before lane 0 publishes it
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -445,6 +469,35 @@ __device__ __forceinline__ uint64_t pair_hits(const DevDesc *d, uint32_t nseg, u
     return hits;
 }
 
+// Slots of the mask `cand` (one group) whose kernels the kernel with group
+// sequence number g and upstream list hup depends on (bit b of hup: the
+// kernel g - 1 - b).  Each lane tests the kernel of its own slot.
+__device__ __forceinline__ uint64_t slots_upstream(uint64_t cand, uint32_t myg, uint32_t g, uint64_t hup, uint32_t lane)
+{
+    const uint32_t back = g - 1u - myg;
+    return __builtin_amdgcn_ballot_w64(((cand >> lane) & 1ull) && back < 64u && ((hup >> (back & 63u)) & 1ull));
+}
+
+// Largest of x over the wave (x < 2^31): an inclusive running maximum by DPP
+// row shifts and row broadcasts (the prefix-sum pattern), read at lane 63.
+__device__ __forceinline__ uint32_t wave_max(uint32_t x)
+{
+    int32_t m = (int32_t)x, o;
+    o = __builtin_amdgcn_update_dpp(0, m, 0x111, 0xf, 0xf, false);   // row_shr:1
+    m = o > m ? o : m;
+    o = __builtin_amdgcn_update_dpp(0, m, 0x112, 0xf, 0xf, false);   // row_shr:2
+    m = o > m ? o : m;
+    o = __builtin_amdgcn_update_dpp(0, m, 0x114, 0xf, 0xf, false);   // row_shr:4
+    m = o > m ? o : m;
+    o = __builtin_amdgcn_update_dpp(0, m, 0x118, 0xf, 0xf, false);   // row_shr:8
+    m = o > m ? o : m;
+    o = __builtin_amdgcn_update_dpp(0, m, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    m = o > m ? o : m;
+    o = __builtin_amdgcn_update_dpp(0, m, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    m = o > m ? o : m;
+    return (uint32_t)__builtin_amdgcn_readlane(m, 63);
+}
+
 template <int NG>
 __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
 {
@@ -456,15 +509,20 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
     ACS_GAS acs_trace_rec *const trace = gp(p.trace);
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint32_t depth = NG == 1 ? kLdsDescs : lds_depth(G);   // a constant for one window
-    const bool hc = NG == 1 && p.host_check > 0;
-    const uint64_t hcm = (uint64_t)(p.host_check > 0 ? p.host_check : 0);
+    // One window with its checks made ahead of it (a check wave or the
+    // host): a kernel's upstream list arrives with it and admission needs no
+    // pair tests.  The host's list is already in the device ring; a check
+    // wave's is in the staged copy only, and the window stores it.
+    const bool ahead = NG == 1 && p.host_check > 0;
+    const bool store_up = !ahead || p.check_wave != 0;
+    const uint32_t M = ahead ? (uint32_t)p.host_check : kSpan;   // admission gate, in group sequence numbers
 
     // Slots: group g owns lanes [g * Wp, g * Wp + W), Wp = W rounded up to a
-    // power of two; span = G * Wp lanes hold slots.  When span < 64 the
-    // slots' ranges are replicated: lane l holds the ranges of slot lane
-    // l mod span, and its replica index l / span selects which of the new
-    // kernel's segments it tests, so R replicas divide the pair tests of an
-    // insertion by R.  Masks (valid, exec, upstream) are over slot lanes.
+    // power of two; span = G * Wp lanes hold slots.  When span < 64 and the
+    // window makes the pair tests, the slots' ranges are replicated: lane l
+    // holds the ranges of slot lane l mod span, and its replica index l / span
+    // selects which of the new kernel's segments it tests, so R replicas
+    // divide the pair tests of an insertion by R.  Masks are over slot lanes.
     const uint32_t Wp = W <= 1 ? 1u : (W <= 2 ? 2u : (W <= 4 ? 4u : (W <= 8 ? 8u : (W <= 16 ? 16u : (W <= 32 ? 32u : 64u)))));
     const uint32_t span = Wp * (uint32_t)G;
     const uint32_t R = (64u / span) < (uint32_t)kSegs ? 64u / span : (uint32_t)kSegs;   // replicas in use
@@ -476,16 +534,20 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
     uint64_t repmul = 0;   // bit r * span set for every replica r
     for (uint32_t r = 0; r < R; r++) repmul |= 1ull << (r * span);
 
-    // this lane's slot (sl; lanes whose replica index is R or more hold nothing)
-    uint64_t ss[kSegs], se[kSegs];
-#pragma unroll
-    for (int m = 0; m < kSegs; m++) ss[m] = se[m] = 0;
-    uint32_t target = 0, mynp = 0;
+    // the kernel in this lane's slot (slot lanes only)
+    uint32_t myg = 0, mynp = 0;   // group sequence number, pieces
     int32_t mykid = 0;
-    uint64_t up = 0, myseq = 0;
+    uint64_t myseq = 0, myhup = 0;   // submission index (traces), upstream list by distance
+    // pair tests: this lane's slot ranges (replicated), and per position the
+    // lanes whose slot range there is a write; unused and free positions hold
+    // the empty range [0, 0), which intersects nothing
+    uint64_t ss[kSegs], se[kSegs], wmask[kSegs];
+#pragma unroll
+    for (int m = 0; m < kSegs; m++) ss[m] = se[m] = wmask[m] = 0;
+    uint64_t over4 = 0, over2 = 0;   // slots using more than 4 (2) positions
 
     // wave-uniform state
-    uint64_t valid = 0, exec = 0, pub = 0, ev = 0, snap_seen = 0, checks = 0;
+    uint64_t valid = 0, pub = 0, ev = 0, snap_seen = 0, checks = 0;
     uint32_t head[NG];
     uint64_t retired[NG], published[NG];
 #pragma unroll
@@ -493,15 +555,6 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
         head[g] = 0;
         retired[g] = published[g] = 0;
     }
-    // wmask[m]: lanes whose slot segment m is a write.  Segments a slot does
-    // not use, and every segment of a free slot, are the empty range [0, 0),
-    // which intersects nothing, so the pair test needs no occupancy mask.
-    uint64_t wmask[kSegs];
-#pragma unroll
-    for (int m = 0; m < kSegs; m++) wmask[m] = 0;
-    // slots whose kernel uses more than 4 (more than 2) range positions; with
-    // valid they bound the positions an insertion must test
-    uint64_t over4 = 0, over2 = 0;
 
     if (lane == 0) __hip_atomic_store(&ctrl->alive, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 
@@ -509,110 +562,156 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
         bool progress = false;
         if ((iter & 4095u) == 0 && uni32(LDS_LOAD(&fs->stop)) == 2u) break;   // abort is honoured even while busy
 
-        // The completion words are polled first and examined after admission,
-        // so that the load's latency overlaps the insertion work.  They are
-        // read relaxed: the window wave reads no task results, and the
-        // workers acquire before their bodies start.
-        const bool mine = (exec >> lane) & 1ull;
-        const uint32_t cdone = mine ? __hip_atomic_load(&st->done[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+        // The completion words of the occupied slots are polled first and
+        // examined after admission, so that the load's latency overlaps the
+        // admission work.  Read relaxed: the window wave reads no task
+        // results, and the workers acquire before their bodies start.
+        const bool occ = (valid >> lane) & 1ull;
+        const uint32_t cdone =
+            occ ? __hip_atomic_load(&st->dseq[grp][myg & (kSeqRing - 1u)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
 
-        // ---- admission in program order (per group) while a slot is free, a
-        // bounded number of passes; each pass admits one kernel into every
-        // group that has one staged and a free slot
+        // ---- admission in program order (per group), strictly FIFO
         uint32_t ftail[NG];
 #pragma unroll
         for (int g = 0; g < NG; g++) ftail[g] = g < G ? uni32(LDS_LOAD(&fs->tail[g])) : 0u;
         bool staged = false;
 #pragma unroll
         for (int g = 0; g < NG; g++) staged |= g < G && head[g] != ftail[g];
+        uint64_t newly = 0;    // slots admitted now; all of them are handed out below
+        bool drain = false;    // upstream lists were stored into the device ring
         if (staged) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            const uint32_t passes = kAdmitBatch;
-            if constexpr (NG == 1) {
-                // one window: the descriptor is read once by the whole wave
-                // (lane i holds its 4-byte word i) and its fields are taken with
-                // readlane, so everything but the pair tests is scalar
+            if (NG == 1 && ahead) {
+                // every staged kernel that finds a free slot, at once: the
+                // r-th free slot (lane order) takes staged kernel head + r
+                const uint64_t freem = ~valid & wmaskslots;
+                uint32_t K = (uint32_t)__builtin_popcountll(freem);
+                const uint32_t nst = ftail[0] - head[0];
+                K = nst < K ? nst : K;
+                {
+                    // the gate of the split (Section IV-C): kernel head + r
+                    // waits while the window holds one more than M older,
+                    // counting the kernels admitted before it in this pass
+                    // (with an empty window the first of them is the oldest)
+                    const uint32_t oldest_back = (valid && K) ? wave_max(occ ? head[0] - myg : 0u) : 0u;
+                    const uint32_t room = oldest_back <= M ? M - oldest_back + 1u : 0u;
+                    K = room < K ? room : K;
+                }
+                if (K) {
+                    const uint32_t r = (uint32_t)__builtin_popcountll(freem & lane_lt);
+                    const bool take = ((freem >> lane) & 1ull) && r < K;
+                    newly = __builtin_amdgcn_ballot_w64(take);
+                    if (take) {
+                        const DevDesc *d = &fs->ring[(head[0] + r) & (depth - 1u)];
+                        myseq = d->seq;
+                        mykid = d->kid;
+                        const uint32_t npr = d->npieces;
+                        mynp = npr < kMaxPieces ? (npr ? npr : 1u) : kMaxPieces;
+                        myhup = d->host_up;
+                        myg = head[0] + r;
+                        if (store_up && myhup != 0)
+                            __hip_atomic_store(reinterpret_cast<ACS_GAS uint64_t *>(&st->dring[0][myg & (kDescRing - 1u)].host_up),
+                                               myhup, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    drain = store_up && __builtin_amdgcn_ballot_w64(take && myhup != 0) != 0;
+                    if (tr) {
+                        // the upstream slots at each insert, from the lists
+                        uint32_t k = 0;
+                        for (uint64_t m = newly; m; m &= m - 1, k++) {
+                            const int s = __builtin_ctzll(m);
+                            const uint64_t vin = valid | (newly & ((1ull << s) - 1ull));
+                            const uint64_t upm = slots_upstream(vin, myg, readlane32(myg, s), readlane64(myhup, s), lane);
+                            const uint64_t sq = readlane64(myseq, s);
+                            const int32_t kd = (int32_t)readlane32((uint32_t)mykid, s);
+                            if (lane == 0 && sq < p.trace_cap) trace_insert(&trace[sq], sq, s, kd, ev + k, vin, upm);
+                        }
+                    }
+                    ev += K;
+                    valid |= newly;
+                    head[0] += K;
+                    progress = true;
+                }
+            } else if constexpr (NG == 1) {
+                // checks at insert (Algorithm 1 both ways), one kernel per step;
+                // the descriptor is read once by the whole wave (lane i holds
+                // its 4-byte word i) and its fields are taken with readlane
                 const uint64_t full = wmaskslots & wpmask;
-                for (uint32_t pass = 0; pass < passes && head[0] != ftail[0] && valid != full; pass++) {
-                    const DevDesc *d = &fs->ring[head[0] & (depth - 1u)];
+                for (uint32_t pass = 0; pass < kAdmitBatch && head[0] != ftail[0] && valid != full; pass++) {
+                    const uint32_t gq = head[0];
+                    // a kernel more than kSpan older still in the window: wait
+                    if (__builtin_amdgcn_ballot_w64(((valid >> lane) & 1ull) && gq - myg > M) != 0) break;
+                    const DevDesc *d = &fs->ring[gq & (depth - 1u)];
                     const uint32_t dw = reinterpret_cast<const uint32_t *>(d)[lane];
-                    const uint64_t seq = readpair(dw, 0);
-                    // host-check mode: the host compared this kernel with the M
-                    // submitted before it only, so it waits while an older kernel
-                    // is still in the window (the upstream load module's gate)
-                    if (hc && __builtin_amdgcn_ballot_w64(((valid >> lane) & 1ull) && myseq + hcm < seq) != 0) break;
                     const int slot = __builtin_ctzll(~valid & full);
                     const uint64_t bit = 1ull << slot;
                     const uint32_t nraw = readlane32(dw, 4);
                     const uint32_t nseg = nraw < (uint32_t)kSegs ? nraw : (uint32_t)kSegs;
                     const uint32_t wb = readlane32(dw, 5);
-                    const int32_t kid = (int32_t)readlane32(dw, 2);
-                    const uint32_t npr = readlane32(dw, 3);
-                    const uint32_t np = npr < kMaxPieces ? npr : kMaxPieces;
-                    // the descriptor goes to the task table as it is
-                    if (lane < kDescCopyDwords)
-                        __hip_atomic_store(reinterpret_cast<ACS_GAS uint32_t *>(&st->task[slot]) + lane, dw, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
+                    uint64_t hits;
+                    if (valid & over4) hits = pair_hits<8, true>(d, nseg, wb, R, rep, ss, se, wmask);
+                    else if (valid & over2) hits = pair_hits<4, true>(d, nseg, wb, R, rep, ss, se, wmask);
+                    else hits = pair_hits<2, true>(d, nseg, wb, R, rep, ss, se, wmask);
                     uint64_t upm = 0;
-                    if (!hc) {
-                        uint64_t hits;
-                        if (valid & over4) hits = pair_hits<8, true>(d, nseg, wb, R, rep, ss, se, wmask);
-                        else if (valid & over2) hits = pair_hits<4, true>(d, nseg, wb, R, rep, ss, se, wmask);
-                        else hits = pair_hits<2, true>(d, nseg, wb, R, rep, ss, se, wmask);
-                        for (uint32_t r = 0; r < R; r++) upm |= (hits >> (r * span)) & spanmask;
-                    } else {
-                        // the list made ahead of the window, by distance back in
-                        // submission order; kernels that already left the
-                        // window drop out here
-                        const uint64_t hup = readpair(dw, kHostUpDword), back = seq - 1 - myseq;
-                        upm = __builtin_amdgcn_ballot_w64(((valid >> lane) & 1ull) && back < hcm &&
-                                                          ((hup >> (back & 63u)) & 1ull));
-                    }
+                    for (uint32_t r = 0; r < R; r++) upm |= (hits >> (r * span)) & spanmask;
                     upm &= valid;
-                    // the slot's ranges and their classes serve only the
-                    // window wave's own pair tests
-                    if (!hc && sl == (uint32_t)slot && rep < R) {
+                    // the same conflicts as an upstream list by distance
+                    uint64_t hup = 0;
+                    for (uint64_t m = upm; m; m &= m - 1) hup |= 1ull << ((gq - 1u - readlane32(myg, __builtin_ctzll(m))) & 63u);
+                    if (hup != 0) {
+                        if (lane == 0)
+                            __hip_atomic_store(reinterpret_cast<ACS_GAS uint64_t *>(&st->dring[0][gq & (kDescRing - 1u)].host_up), hup,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        drain = true;
+                    }
+                    if (sl == (uint32_t)slot && rep < R) {
 #pragma unroll
                         for (int m = 0; m < kSegs; m++) {
                             ss[m] = d->s[m];
                             se[m] = d->e[m];
                         }
                     }
-                    if (!hc) checks += (uint64_t)__builtin_popcountll(valid) * nseg * kSegs;
+                    checks += (uint64_t)__builtin_popcountll(valid) * nseg * kSegs;
+                    const uint64_t seq = readpair(dw, 0);
+                    const int32_t kid = (int32_t)readlane32(dw, 2);
+                    const uint32_t npr = readlane32(dw, 3);
                     if ((int)lane == slot) {
-                        up = upm;
                         myseq = seq;
                         mykid = kid;
-                        mynp = np;
-                        if (np > 1) target += kWave * np;
-                        __hip_atomic_store(&st->task[slot].ptarget, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        mynp = npr < kMaxPieces ? (npr ? npr : 1u) : kMaxPieces;
+                        myg = gq;
+                        myhup = hup;
                     }
-                    if (!hc) {
-                        const uint64_t rbit = bit * repmul;
+                    const uint64_t rbit = bit * repmul;
 #pragma unroll
-                        for (int m = 0; m < kSegs; m++)
-                            wmask[m] = ((uint32_t)m < nseg && ((wb >> m) & 1u)) ? (wmask[m] | rbit) : (wmask[m] & ~rbit);
-                        over4 = nseg > 4u ? (over4 | bit) : (over4 & ~bit);
-                        over2 = nseg > 2u ? (over2 | bit) : (over2 & ~bit);
-                    }
-                    if (tr && lane == 0 && seq < p.trace_cap) {
-                        trace_insert(&trace[seq], seq, slot, kid, ev, valid, upm);
-                    }
+                    for (int m = 0; m < kSegs; m++)
+                        wmask[m] = ((uint32_t)m < nseg && ((wb >> m) & 1u)) ? (wmask[m] | rbit) : (wmask[m] & ~rbit);
+                    over4 = nseg > 4u ? (over4 | bit) : (over4 & ~bit);
+                    over2 = nseg > 2u ? (over2 | bit) : (over2 & ~bit);
+                    if (tr && lane == 0 && seq < p.trace_cap) trace_insert(&trace[seq], seq, slot, kid, ev, valid, upm);
                     ev++;
                     valid |= bit;
+                    newly |= bit;
                     head[0]++;
                     progress = true;
                 }
             } else {
-                for (uint32_t pass = 0; pass < passes; pass++) {
-                    // which groups admit in this pass, and into which slot lane
+                for (uint32_t pass = 0; pass < kAdmitBatch; pass++) {
+                    // which groups admit in this step, and into which slot
+                    // lane: a group with a staged kernel, a free slot and no
+                    // kernel more than kSpan older than it in its window
+                    uint32_t hg = 0;
+#pragma unroll
+                    for (int g = 0; g < NG; g++)
+                        if ((uint32_t)g == grp) hg = head[g];
+                    const uint64_t gbad = __builtin_amdgcn_ballot_w64(((valid >> lane) & 1ull) && hg - myg > M);
                     uint32_t adm = 0;
                     uint32_t newl[NG];
-    #pragma unroll
+#pragma unroll
                     for (int g = 0; g < NG; g++) {
                         newl[g] = 0;
-                        if (g < G && head[g] != ftail[g]) {
-                            const uint64_t fr = ~valid & (((wmaskslots & wpmask)) << (g * Wp));
+                        const uint64_t gm = (wmaskslots & wpmask) << (g * Wp);
+                        if (g < G && head[g] != ftail[g] && (gbad & gm) == 0) {
+                            const uint64_t fr = ~valid & gm;
                             if (fr) {
                                 adm |= 1u << g;
                                 newl[g] = (uint32_t)__builtin_ctzll(fr);
@@ -620,90 +719,94 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                         }
                     }
                     if (!adm) break;
-                    // this lane's group: does it admit, from which staged descriptor, into which lane
+                    // this lane's group: does it admit, from which staged
+                    // descriptor, into which lane
                     const bool gin = (adm >> grp) & 1u;
-                    uint32_t hsel = 0, nsel = 0;
-    #pragma unroll
+                    uint32_t nsel = 0;
+#pragma unroll
                     for (int g = 0; g < NG; g++)
-                        if ((uint32_t)g == grp) {
-                            hsel = head[g];
-                            nsel = newl[g];
-                        }
-                    const DevDesc *d = &fs->ring[grp * depth + (hsel & (depth - 1u))];
-                    // each admitted descriptor goes to the task table as it is (one
-                    // 4-byte word per lane); all groups' words are read first so the
-                    // LDS latency is paid once
-                    uint32_t dwg[NG];
-    #pragma unroll
-                    for (int g = 0; g < NG; g++)
-                        dwg[g] = g < G ? reinterpret_cast<const uint32_t *>(&fs->ring[g * depth + (head[g] & (depth - 1u))])[lane]
-                                       : 0u;
+                        if ((uint32_t)g == grp) nsel = newl[g];
+                    const DevDesc *d = &fs->ring[grp * depth + (hg & (depth - 1u))];
                     uint64_t newbits = 0;
-    #pragma unroll
+#pragma unroll
                     for (int g = 0; g < NG; g++)
-                        if ((adm >> g) & 1u) {
-                            if (lane < kDescCopyDwords)
-                                __hip_atomic_store(reinterpret_cast<ACS_GAS uint32_t *>(&st->task[newl[g]]) + lane, dwg[g],
-                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            newbits |= 1ull << newl[g];
-                        }
+                        if ((adm >> g) & 1u) newbits |= 1ull << newl[g];
                     const uint32_t nraw = gin ? d->nseg : 0u;
                     const uint32_t nseg = nraw < (uint32_t)kSegs ? nraw : (uint32_t)kSegs;
                     const uint32_t wb = d->wbits;
-                    // segment k of each group's new kernel against every occupied
-                    // slot of the group; replica r takes k = r, r + R, ...
+                    // segment k of each group's new kernel against every
+                    // occupied slot of the group; replica r takes k = r, r + R, ...
                     uint64_t hits;
                     if (valid & over4) hits = pair_hits<8, false>(d, nseg, wb, R, rep, ss, se, wmask);
                     else if (valid & over2) hits = pair_hits<4, false>(d, nseg, wb, R, rep, ss, se, wmask);
                     else hits = pair_hits<2, false>(d, nseg, wb, R, rep, ss, se, wmask);
-                    // fold the replicas onto their slot lanes; a new slot's own lanes
-                    // may already hold its ranges: only occupied slots count
+                    // fold the replicas onto their slot lanes; a new slot's own
+                    // lanes may already hold its ranges: only occupied slots count
                     uint64_t upall = 0;
                     for (uint32_t r = 0; r < R; r++) upall |= (hits >> (r * span)) & spanmask;
                     upall &= valid;
                     checks += (uint64_t)__builtin_popcountll(valid) * kSegs * kSegs;
+                    // each admitted group's conflicts as an upstream list by distance
+                    uint64_t hupl = 0;   // this lane's group's list
+#pragma unroll
+                    for (int g = 0; g < NG; g++) {
+                        if (!((adm >> g) & 1u)) continue;
+                        const uint64_t gm = (wmaskslots & wpmask) << (g * Wp);
+                        const uint32_t gq = head[g];
+                        uint64_t hup = 0;
+                        for (uint64_t m = upall & gm; m; m &= m - 1)
+                            hup |= 1ull << ((gq - 1u - readlane32(myg, __builtin_ctzll(m))) & 63u);
+                        if (hup != 0) {
+                            if (lane == 0)
+                                __hip_atomic_store(
+                                    reinterpret_cast<ACS_GAS uint64_t *>(&st->dring[g][gq & (kDescRing - 1u)].host_up), hup,
+                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            drain = true;
+                        }
+                        if ((uint32_t)g == grp) hupl = hup;
+                    }
                     if (gin && sl == nsel && rep < R) {
                         // the new occupant's ranges, in every replica of its slot
-    #pragma unroll
+#pragma unroll
                         for (int m = 0; m < kSegs; m++) {
                             ss[m] = d->s[m];
                             se[m] = d->e[m];
                         }
                     }
                     if (gin && lane == nsel) {
-                        up = upall & mygroup;
                         myseq = d->seq;
                         mykid = d->kid;
                         const uint32_t npr = d->npieces;
-                        mynp = npr < kMaxPieces ? npr : kMaxPieces;
-                        if (mynp > 1) target += kWave * mynp;
-                        __hip_atomic_store(&st->task[lane].ptarget, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        mynp = npr < kMaxPieces ? (npr ? npr : 1u) : kMaxPieces;
+                        myg = hg;
+                        myhup = hupl;
                         if (tr && myseq < p.trace_cap) {
-                            trace_insert(&trace[myseq], myseq, (int32_t)lane, mykid, ev, valid & mygroup, up);
+                            const uint64_t rank = (uint64_t)__builtin_popcount(adm & ((1u << grp) - 1u));
+                            trace_insert(&trace[myseq], myseq, (int32_t)lane, mykid, ev + rank, valid & mygroup,
+                                         upall & mygroup);
                         }
                     }
-                    // write flags of the new occupants' ranges, for every replica lane
-                    // of a new slot at once: lane l is a new slot's replica when its
-                    // group admitted and its slot lane is that group's new lane
+                    // write flags of the new occupants' ranges, for every replica
+                    // lane of a new slot at once
                     {
                         const bool newrep = gin && sl == nsel && rep < R;
                         const uint64_t newlanes = __builtin_amdgcn_ballot_w64(newrep);
-    #pragma unroll
+#pragma unroll
                         for (int m = 0; m < kSegs; m++) {
                             const uint64_t wr = __builtin_amdgcn_ballot_w64(newrep && (uint32_t)m < nseg && ((wb >> m) & 1u));
                             wmask[m] = (wmask[m] & ~newlanes) | wr;
                         }
-                        // segment-count classes of the new occupants (slot lanes only)
                         const uint64_t big4 = __builtin_amdgcn_ballot_w64(newrep && rep == 0 && nseg > 4u);
                         const uint64_t big2 = __builtin_amdgcn_ballot_w64(newrep && rep == 0 && nseg > 2u);
                         over4 = (over4 & ~newbits) | big4;
                         over2 = (over2 & ~newbits) | big2;
                     }
-    #pragma unroll
+#pragma unroll
                     for (int g = 0; g < NG; g++)
                         if ((adm >> g) & 1u) head[g]++;
                     ev += (uint64_t)__builtin_popcount(adm);
                     valid |= newbits;
+                    newly |= newbits;
                     progress = true;
                 }
             }
@@ -718,9 +821,47 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
             }
         }
 
-        // ---- completions: clear finished slots from every upstream mask
+        // ---- dispatch.  Every admitted kernel is handed out at once: its
+        // workers wait for the completion words of the kernels in its
+        // upstream list themselves.  Entries are published in admission
+        // order (lane order within a pass), so every upstream kernel's
+        // entries precede its dependents' in the queue: a worker only ever
+        // waits for work that an earlier ticket holds.
+        if (newly) {
+            // the upstream lists stored above are complete before any entry
+            // that points at them.  0x0F70: vmcnt 0, expcnt 7, lgkmcnt 15.
+            if (drain) __builtin_amdgcn_s_waitcnt(0x0F70);
+            const bool mine = (newly >> lane) & 1ull;
+            int32_t total;
+            const uint32_t before = (uint32_t)wave_exclusive_scan(mine ? (int32_t)mynp : 0, &total);
+            // a kernel of one piece: its own lane writes the entry (one store
+            // for all of them); a kernel of several: the whole wave does
+            if (mine && mynp == 1) {
+                const uint64_t t = pub + before;
+                __hip_atomic_store(&st->ent[t & (kQueueCap - 1)], queue_entry(t, grp, 0, myg), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+            for (uint64_t m = __builtin_amdgcn_ballot_w64(mine && mynp > 1); m; m &= m - 1) {
+                const int l = __builtin_ctzll(m);
+                const uint32_t bl = readlane32(before, l), nl = readlane32(mynp, l), gl = readlane32(myg, l);
+                const uint32_t grl = (uint32_t)l / Wp;
+                for (uint32_t q = lane; q < nl; q += kWave) {
+                    const uint64_t t = pub + bl + q;
+                    __hip_atomic_store(&st->ent[t & (kQueueCap - 1)], queue_entry(t, grl, q, gl), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            if (tr && mine && myseq < p.trace_cap) {
+                tput(&trace[myseq].ev_dispatch, (int64_t)(ev + __builtin_popcountll(newly & lane_lt)));
+                tput(&trace[myseq].t_dispatch, (int64_t)wall_clock64());
+            }
+            pub += (uint64_t)(uint32_t)total;
+            ev += (uint64_t)__builtin_popcountll(newly);
+        }
+
+        // ---- completions: a slot whose kernel stored its word is free again
         {
-            const uint64_t done = __ballot(mine && (int32_t)(cdone - (uint32_t)(myseq + 1)) >= 0);
+            const uint64_t done = __builtin_amdgcn_ballot_w64(occ && (int32_t)(cdone - (myg + 1u)) >= 0);
             if (done) {
                 if (tr) {
                     const uint64_t now = wall_clock64();
@@ -729,11 +870,11 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                         tput(&trace[myseq].t_retire, (int64_t)now);
                     }
                 }
-                ev += __builtin_popcountll(done);
+                ev += (uint64_t)__builtin_popcountll(done);
 #pragma unroll
                 for (int g = 0; g < NG; g++)
-                    if (g < G) retired[g] += __builtin_popcountll(done & (wpmask << (g * Wp)));
-                if (!hc) {
+                    if (g < G) retired[g] += (uint64_t)__builtin_popcountll(done & (wpmask << (g * Wp)));
+                if (!ahead) {
                     if (((done >> sl) & 1ull) && rep < R) {
 #pragma unroll
                         for (int m = 0; m < kSegs; m++) ss[m] = se[m] = 0;
@@ -742,95 +883,19 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
 #pragma unroll
                     for (int m = 0; m < kSegs; m++) wmask[m] &= ~rdone;
                 }
-                up &= ~done;
                 valid &= ~done;
-                exec &= ~done;
                 progress = true;
             }
         }
 
-        // ---- dispatch.  A kernel with an empty upstream mask is ready (it
-        // may start at once); a kernel whose upstream kernels have all been
-        // handed to the workers is dispatched as well, together with the
-        // completion-counter values its workers must see before starting, so
-        // that a dependent kernel starts without a round trip through this
-        // wave.  Rounds repeat so that a chain inside the window goes out in
-        // one pass; entries are published oldest first, so every upstream
-        // kernel's work items precede its dependents' in the queue.
-        uint64_t newly = 0;
-        for (;;) {
-            const uint64_t out = exec | newly;
-            const bool cand = (((valid & ~out) >> lane) & 1ull) && (up & ~out) == 0;
-            const uint64_t r = __ballot(cand);
-            if (!r) break;
-            newly |= r;
-        }
-        if (newly) {
-            for (uint64_t m = newly; m; m &= m - 1) {
-                const int j = __builtin_ctzll(m);
-                const uint64_t upj = readlane64(up, j);
-                if ((upj >> lane) & 1ull)
-                    __hip_atomic_store(&st->wait_target[j][lane], (uint32_t)(myseq + 1), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                if (lane == 0) __hip_atomic_store(&st->task[j].wait_mask, upj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            // every task-table store of this wave (device scope) is complete
-            // before any work-queue entry that points at it is stored.
-            // 0x0F70: vmcnt 0, expcnt 7, lgkmcnt 15.
-            __builtin_amdgcn_s_waitcnt(0x0F70);
-            __builtin_amdgcn_wave_barrier();
-            const bool mine = (newly >> lane) & 1ull;
-            uint32_t before = 0, rank = 0, total = 0;
-            for (uint64_t m = newly; m; m &= m - 1) {
-                const int l = __builtin_ctzll(m);
-                const uint64_t sl = readlane64(myseq, l);
-                const uint32_t npl = readlane32(mynp, l);
-                if (sl < myseq) {
-                    before += npl;
-                    rank++;
-                }
-                total += npl;
-            }
-            // a kernel of one piece: its own lane writes the entry (one store
-            // for all of them); a kernel of several: the whole wave does
-            if (mine && mynp == 1) {
-                const uint64_t t = pub + before;
-                const uint64_t v = ((uint64_t)(uint32_t)(t + 1) << 32) | ((uint64_t)lane << 24);
-                __hip_atomic_store(&st->ent[t & (kQueueCap - 1)], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            for (uint64_t m = __ballot(mine && mynp > 1); m; m &= m - 1) {
-                const int l = __builtin_ctzll(m);
-                const uint32_t bl = readlane32(before, l), nl = readlane32(mynp, l);
-                for (uint32_t q = lane; q < nl; q += kWave) {
-                    const uint64_t t = pub + bl + q;
-                    const uint64_t v = ((uint64_t)(uint32_t)(t + 1) << 32) | ((uint64_t)(uint32_t)l << 24) | q;
-                    __hip_atomic_store(&st->ent[t & (kQueueCap - 1)], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
-            }
-            if (mine) {
-                if (tr && myseq < p.trace_cap) {
-                    tput(&trace[myseq].ev_dispatch, (int64_t)(ev + rank));
-                    tput(&trace[myseq].t_dispatch, (int64_t)wall_clock64());
-                }
-            }
-            pub += total;
-            ev += __builtin_popcountll(newly);
-            exec |= newly;
-            progress = true;
-        }
-
-        // ---- the host learns about completions when the window drains: one
+        // ---- the host learns about completions when a group drains: one
         // system-scope release covers every result (and trace record) of the
         // kernels retired so far
-        uint32_t drained = 0;   // groups that are empty and have news for the host
+        uint32_t drained = 0;
 #pragma unroll
         for (int g = 0; g < NG; g++)
             if (g < G && (valid & (wpmask << (g * Wp))) == 0 && retired[g] != published[g]) drained |= 1u << g;
         if (drained) {
-            // every result was stored with device scope before its completion
-            // was counted; the acquire and the system-scope release order the
-            // completions seen so far (and this wave's trace records) before
-            // the host is told
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
 #pragma unroll
             for (int g = 0; g < NG; g++)
@@ -842,9 +907,19 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
         }
 
         if (!progress) {
-            // snapshot of the window for the host (the scheduled list)
+            // snapshot of the window for the host (the scheduled list): the
+            // upstream slots of each kernel from its list; every kernel in the
+            // window has been handed out, so it is executing unless it still
+            // waits for an upstream kernel
             const uint64_t sr = uni64(LDS_LOAD(&fs->snap_req));
             if (sr != snap_seen) {
+                uint64_t myup = 0;
+                for (uint64_t m = valid; m; m &= m - 1) {
+                    const int s = __builtin_ctzll(m);
+                    const uint64_t gm = (wmaskslots & wpmask) << (((uint32_t)s / Wp) * Wp);
+                    const uint64_t u = slots_upstream(valid & gm, myg, readlane32(myg, s), readlane64(myhup, s), lane);
+                    if ((int)lane == s) myup = u;
+                }
                 const bool v = (valid >> lane) & 1ull;
                 uint32_t rank = 0;
                 for (uint64_t m = valid; m; m &= m - 1) {
@@ -855,8 +930,8 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                     acs_entry e;
                     e.seq = myseq;
                     e.kernel_id = mykid;
-                    e.state = up != 0 ? ACS_PENDING : (((exec >> lane) & 1ull) ? ACS_EXECUTING : ACS_READY);
-                    e.upstream_mask = up;
+                    e.state = myup != 0 ? ACS_PENDING : ACS_EXECUTING;
+                    e.upstream_mask = myup;
                     e.slot = (int32_t)lane;
                     e.reserved = 0;
                     ctrl->snap[rank] = e;
@@ -870,11 +945,11 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                 }
                 snap_seen = sr;
             }
-            const uint32_t st = uni32(LDS_LOAD(&fs->stop));
+            const uint32_t stp = uni32(LDS_LOAD(&fs->stop));
             bool empty = valid == 0;
 #pragma unroll
             for (int g = 0; g < NG; g++) empty &= g >= G || head[g] == uni32(LDS_LOAD(&fs->tail[g]));
-            if (st == 2u || (st == 1u && empty)) break;
+            if (stp == 2u || (stp == 1u && empty)) break;
             __builtin_amdgcn_s_sleep(1);
         }
     }
@@ -885,8 +960,8 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     for (uint32_t i = lane; i < (uint32_t)p.n_workers; i += 64) {
         const uint64_t t = pub + i;
-        const uint64_t v = ((uint64_t)(uint32_t)(t + 1) << 32) | ((uint64_t)kSentinelSlot << 24);
-        __hip_atomic_store(&st->ent[t & (kQueueCap - 1)], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&st->ent[t & (kQueueCap - 1)], queue_entry(t, kSentinelGroup, 0, 0), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     }
     if (lane == 0) {
         __hip_atomic_store(&ctrl->checks, checks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -899,12 +974,11 @@ __device__ inline void worker(const DevParams &p, uint8_t *smem, Mail *mail)
 {
     // Control flow here is uniform across each wave by construction: wave 0
     // (selected through readfirstlane, so the compiler sees a uniform branch)
-    // claims tickets and reports completions with all 64 lanes active, only
-    // lane 0 contributing a non-zero increment, and every value that decides
-    // a branch is taken from the first lane.  A lane-divergent region next to
-    // the workgroup barriers of this loop can be compiled into a loop that
-    // re-enters the barrier without the lanes of that region, which never
-    // terminates.
+    // claims tickets and reports completions with all 64 lanes active, and
+    // every value that decides a branch is taken from the first lane.  A
+    // lane-divergent region next to the workgroup barriers of this loop can
+    // be compiled into a loop that re-enters the barrier without the lanes of
+    // that region, which never terminates.
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
     const bool wave0 = uni32(tid) < 64u;
     const bool tr = p.trace != nullptr;
@@ -917,46 +991,49 @@ __device__ inline void worker(const DevParams &p, uint8_t *smem, Mail *mail)
             // every lane adds 1, so one ticket is kWave counts of deq: with a
             // value the same on all lanes the compiler issues one atomic and
             // a popcount, where a per-lane value costs a loop over the lanes
+            // (the host checks the final count after the kernel exits)
             const uint64_t t = uni64(__hip_atomic_fetch_add(&st->deq, 1ull, __ATOMIC_RELAXED,
                                                             __HIP_MEMORY_SCOPE_AGENT)) / kWave;
-            const uint32_t tag = (uint32_t)(t + 1);
+            const uint64_t tag = ((t >> 16) + 1u) & 0xFFu;
             uint64_t v;
             for (uint32_t spin = 1;; spin++) {
                 v = uni64(__hip_atomic_load(&st->ent[t & (kQueueCap - 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-                if ((uint32_t)(v >> 32) == tag) break;
+                if ((v >> 56) == tag) break;
                 // a host abort releases waiting workers even if the window wave has left
                 if ((spin & 1023u) == 0 &&
                     uni64(__hip_atomic_load(&ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) == 2ull) {
-                    v = (uint64_t)kSentinelSlot << 24;
+                    v = (uint64_t)kSentinelGroup << 48;
                     break;
                 }
                 __builtin_amdgcn_s_sleep(2);
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            const uint32_t slot = (uint32_t)(v >> 24) & 0xFFu;
+            const uint32_t grp = (uint32_t)(v >> 48) & 0xFFu, g = (uint32_t)v;
             // all lanes store the same values: no lane-divergent branch needed
-            mail->slot = slot;
-            mail->piece = (uint32_t)v & 0xFFFFFFu;
-            if (slot != kSentinelSlot) {
-                const ACS_GAS TaskEntry *te = &st->task[slot];
+            mail->group = grp;
+            mail->piece = (uint32_t)(v >> 32) & 0xFFFFu;
+            mail->gseq = g;
+            if (grp != kSentinelGroup) {
+                const ACS_GAS DevDesc *te = &st->dring[grp][g & (kDescRing - 1u)];
                 mail->kid = te->kid;
-                mail->np = te->npieces;
-                mail->ptarget = te->ptarget;
+                const uint32_t npr = te->npieces;
+                mail->np = npr < kMaxPieces ? (npr ? npr : 1u) : kMaxPieces;
                 mail->seq = te->seq;
                 margs[lane & 7u] = reinterpret_cast<const ACS_GAS uint64_t *>(te->args)[lane & 7u];
-                // dispatched early: wait until every upstream kernel's counter
-                // has reached the value that marks it complete (lane s watches slot s)
-                const uint64_t wm = uni64(te->wait_mask);
-                if (wm != 0) {
-                    const bool watch = (wm >> lane) & 1ull;
-                    const uint32_t tgt = watch ? st->wait_target[slot][lane] : 0u;
+                // wait until every upstream kernel has stored its completion
+                // word (lane b watches the kernel b + 1 places back)
+                const uint64_t hup = uni64(te->host_up);
+                if (hup != 0) {
+                    const bool watch = (hup >> lane) & 1ull;
+                    const uint32_t k = g - 1u - lane;
                     for (uint32_t spin = 1;; spin++) {
                         bool ok = true;
                         if (watch) {
-                            const uint32_t c = __hip_atomic_load(&st->done[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            ok = (int32_t)(c - tgt) >= 0;
+                            const uint32_t c =
+                                __hip_atomic_load(&st->dseq[grp][k & (kSeqRing - 1u)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            ok = (int32_t)(c - (k + 1u)) >= 0;
                         }
-                        if (__ballot(!ok) == 0) break;
+                        if (__builtin_amdgcn_ballot_w64(!ok) == 0) break;
                         if ((spin & 1023u) == 0 &&
                             uni64(__hip_atomic_load(&ctrl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) == 2ull)
                             break;
@@ -968,8 +1045,8 @@ __device__ inline void worker(const DevParams &p, uint8_t *smem, Mail *mail)
             }
         }
         __syncthreads();
-        const uint32_t slot = uni32(mail->slot);
-        if (slot == kSentinelSlot) break;
+        const uint32_t grp = uni32(mail->group);
+        if (grp == kSentinelGroup) break;
         run_body<true>((int32_t)uni32((uint32_t)mail->kid), mail->args, uni32(mail->piece), uni32(mail->np), smem);
         // each wave waits until its own result stores (device scope) are
         // complete, so that they are visible device-wide before wave 0 counts
@@ -992,17 +1069,23 @@ __device__ inline void worker(const DevParams &p, uint8_t *smem, Mail *mail)
             }
             // a kernel of several pieces is complete when the last piece is
             // counted; every piece's results were complete before its count,
-            // so the last count comes after all of them
-            const uint32_t np = uni32(mail->np);
+            // so the last count comes after all of them.  The last piece
+            // resets the counter for the next kernel at this ring place
+            // (which cannot be admitted before this one's word is seen).
+            const uint32_t np = uni32(mail->np), g = uni32(mail->gseq);
             bool last = true;
             if (np > 1) {
                 // every lane adds 1: a piece counts kWave (see the ticket above)
-                const uint32_t old = uni32(__hip_atomic_fetch_add(&st->cnt[slot], 1u, __ATOMIC_RELAXED,
+                const uint32_t old = uni32(__hip_atomic_fetch_add(&st->cnt[grp][g & (kSeqRing - 1u)], 1u, __ATOMIC_RELAXED,
                                                                   __HIP_MEMORY_SCOPE_AGENT));
-                last = old + kWave == uni32(mail->ptarget);
+                last = old + kWave == kWave * np;
+                if (last) {
+                    __hip_atomic_store(&st->cnt[grp][g & (kSeqRing - 1u)], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __builtin_amdgcn_s_waitcnt(0x0F70);
+                }
             }
             if (last)
-                __hip_atomic_store(&st->done[slot], (uint32_t)(seq + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&st->dseq[grp][g & (kSeqRing - 1u)], g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }

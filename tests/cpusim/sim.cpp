@@ -151,6 +151,8 @@ static int run_sim(int32_t W, int32_t n_groups, int32_t host_check, int32_t chec
         memcpy(d.s, descs[i].s, sizeof(d.s));
         memcpy(d.e, descs[i].e, sizeof(d.e));
         memcpy(d.args, descs[i].args, sizeof(d.args));
+        d.gseq = (uint32_t)sub[g];
+        d.group = (uint32_t)g;
         if (host_up) d.host_up = host_up[i];
         ring[(size_t)g * ring_cap + (sub[g] & (ring_cap - 1))] = d;
         sub[g]++;
