@@ -86,6 +86,27 @@ int acs_rl_run_graphs(const acs_rl_scene *scene, int32_t steps, int32_t device, 
  * Drains the window at the end; wall_ns receives submit-to-drain time. */
 int acs_nop_run(acs_window *w, int32_t n, int32_t chain, uint64_t spin_ns, double *wall_ns);
 
+/* Overhead probe with wider kernels: n independent no-op kernels of nsegs
+ * segments each (the first half reads, the rest writes, all disjoint from
+ * every other kernel's), so that every dependency check compares nsegs
+ * ranges per kernel and finds nothing.  nsegs in [1, 64] (beyond ACS_K_MAX
+ * merged as usual).  Drains the window; wall_ns as for acs_nop_run. */
+int acs_nop_segs_run(acs_window *w, int32_t n, int32_t nsegs, double *wall_ns);
+
+/* Cost of the host's dependency check (the table of Section IV-D measures
+ * the check for W = 16, 32 and 6, 10 read/write segments).  On a manual
+ * window of W slots, W - 1 kernels of nsegs disjoint segments each are kept
+ * in the window; then reps times a new kernel of nsegs segments, disjoint
+ * from all of them, is submitted (checked against the W - 1: every pair of
+ * segments is tested), taken and completed.  The same loop with an empty
+ * window gives the cost of everything but the check.  Segments beyond
+ * ACS_K_MAX are merged as acs_submit always does (conservative).
+ * ns_checked / ns_empty receive nanoseconds per submit-take-complete round
+ * with the full and the empty window; tests_out (may be NULL) the segment
+ * pairs tested per check.  No GPU is used.  ACS_EINVAL for W outside
+ * [2, 64], nsegs outside [2, 64] or reps < 1. */
+int acs_check_probe(int32_t W, int32_t nsegs, int32_t reps, double *ns_checked, double *ns_empty, double *tests_out);
+
 /* Dynamic DNN, batch 1 (the dynamic-network case study, Section II-C): cells
  * of two parallel gated branches, a 3x3 (pad 1) and a 1x1 convolution with
  * the cell's stride, joined by relu(sum of the branches that ran); a cell

@@ -234,6 +234,8 @@ def lib():
         L.acs_host_free.argtypes = [C.c_void_p]
         L.acs_rl_run.argtypes = [C.c_void_p, P(RLSceneC), C.c_int32, P(C.c_double), P(RLCounts)]
         L.acs_nop_run.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, P(C.c_double)]
+        L.acs_nop_segs_run.argtypes = [C.c_void_p, C.c_int32, C.c_int32, P(C.c_double)]
+        L.acs_check_probe.argtypes = [C.c_int32, C.c_int32, C.c_int32, P(C.c_double), P(C.c_double), P(C.c_double)]
         L.acs_dnn_submit.argtypes = [C.c_void_p, P(DNNGraphC), C.c_void_p, P(C.c_uint64)]
         L.acs_graph_begin.argtypes = [C.c_void_p]
         L.acs_graph_end.argtypes = [C.c_void_p, P(C.c_void_p)]
@@ -261,7 +263,7 @@ def lib():
         L.acs_serve_host_bytes.restype = C.c_uint64
         L.acs_serve_run.argtypes = [C.c_void_p, P(ServeConfigC), P(ServeRequestC), C.c_int32, P(ServeResultC),
                                     P(ServeStatsC)]
-        for f in ("acs_dag_submit", "acs_rl_run_graphs", "acs_poll", "acs_pool_alloc", "acs_pool_free", "acs_pool_info", "acs_serve_run",
+        for f in ("acs_nop_segs_run", "acs_check_probe", "acs_dag_submit", "acs_rl_run_graphs", "acs_poll", "acs_pool_alloc", "acs_pool_free", "acs_pool_info", "acs_serve_run",
                   "acs_window_configure", "acs_submit", "acs_sync", "acs_sync_timeout", "acs_scheduled_list",
                   "acs_trace_read", "acs_stats_get", "acs_window_destroy", "acs_window_stop", "acs_manual_take_ready",
                   "acs_manual_complete", "acs_last_error", "acs_rl_layout", "acs_host_free", "acs_rl_run",
@@ -676,6 +678,13 @@ def rl_run_graphs(scene_gpu: RLSceneGPU, steps: int, device: int = 0):
 def nop_run(win: Window, n: int, chain: bool, spin_ns: int = 0) -> float:
     t = C.c_double()
     _check(lib().acs_nop_run(win.handle, n, int(chain), spin_ns, C.byref(t)))
+    return t.value
+
+
+def nop_segs_run(win: Window, n: int, nsegs: int) -> float:
+    """n independent no-op kernels of nsegs disjoint segments each; wall ns."""
+    t = C.c_double()
+    _check(lib().acs_nop_segs_run(win.handle, n, nsegs, C.byref(t)))
     return t.value
 
 

@@ -3,6 +3,9 @@
 #include <stdint.h>
 
 #include <memory>
+#if defined(__x86_64__)
+#include <immintrin.h>
+#endif
 #include <string>
 #include <vector>
 
@@ -29,22 +32,72 @@ struct Desc {
 // Overlap of two half-open ranges (Algorithm 1's test).
 inline bool ranges_overlap(uint64_t s1, uint64_t e1, uint64_t s2, uint64_t e2) { return s1 < e2 && e1 > s2; }
 
+#if defined(__x86_64__)
+// The same test with four positions per AVX2 compare: every position of the
+// older kernel at once (unused positions hold [0, 0), which meets nothing),
+// unsigned order by flipping the sign bits.
+__attribute__((target("avx2"))) inline bool descs_conflict_avx2(const Desc &older, const Desc &newer)
+{
+    const __m256i sign = _mm256_set1_epi64x((long long)0x8000000000000000ull);
+    const __m256i os0 = _mm256_xor_si256(_mm256_loadu_si256(reinterpret_cast<const __m256i *>(older.s)), sign);
+    const __m256i os1 = _mm256_xor_si256(_mm256_loadu_si256(reinterpret_cast<const __m256i *>(older.s + 4)), sign);
+    const __m256i oe0 = _mm256_xor_si256(_mm256_loadu_si256(reinterpret_cast<const __m256i *>(older.e)), sign);
+    const __m256i oe1 = _mm256_xor_si256(_mm256_loadu_si256(reinterpret_cast<const __m256i *>(older.e + 4)), sign);
+    const uint32_t w = older.wbits;
+    auto bitmask = [](uint32_t b) { return (long long)(0ull - (uint64_t)(b & 1u)); };
+    const __m256i wm0 = _mm256_set_epi64x(bitmask(w >> 3), bitmask(w >> 2), bitmask(w >> 1), bitmask(w));
+    const __m256i wm1 = _mm256_set_epi64x(bitmask(w >> 7), bitmask(w >> 6), bitmask(w >> 5), bitmask(w >> 4));
+    for (uint32_t a = 0; a < newer.nseg; a++) {
+        const __m256i sa = _mm256_set1_epi64x((long long)(newer.s[a] ^ 0x8000000000000000ull));
+        const __m256i ea = _mm256_set1_epi64x((long long)(newer.e[a] ^ 0x8000000000000000ull));
+        // newer [sa, ea) meets older [s, e) iff sa < e and ea > s
+        __m256i m0 = _mm256_and_si256(_mm256_cmpgt_epi64(oe0, sa), _mm256_cmpgt_epi64(ea, os0));
+        __m256i m1 = _mm256_and_si256(_mm256_cmpgt_epi64(oe1, sa), _mm256_cmpgt_epi64(ea, os1));
+        if (!((newer.wbits >> a) & 1u)) {   // a read meets only writes
+            m0 = _mm256_and_si256(m0, wm0);
+            m1 = _mm256_and_si256(m1, wm1);
+        }
+        const __m256i m = _mm256_or_si256(m0, m1);
+        if (!_mm256_testz_si256(m, m)) return true;
+    }
+    return false;
+}
+#endif
+
 // Dependency of `newer` on `older`: the newer kernel's writes against all of
 // the older one's ranges, and its reads against the older one's writes.
+// make_desc lists a kernel's writes first, so the writes of a descriptor are
+// its first popcount(wbits) positions; each row of tests is branch-free.
+// `tests` counts the segment pairs the definition compares.
 inline bool descs_conflict(const Desc &older, const Desc &newer, uint64_t *tests)
 {
+#if defined(__x86_64__)
+    static const bool avx2 = __builtin_cpu_supports("avx2");
+    if (avx2) {
+        if (tests) {
+            const uint32_t nwn = (uint32_t)__builtin_popcount(newer.wbits), nwo = (uint32_t)__builtin_popcount(older.wbits);
+            *tests += (uint64_t)nwn * older.nseg + (uint64_t)(newer.nseg - nwn) * nwo;
+        }
+        return descs_conflict_avx2(older, newer);
+    }
+#endif
+    const uint32_t nn = newer.nseg, no = older.nseg;
+    const uint32_t nwn = (uint32_t)__builtin_popcount(newer.wbits), nwo = (uint32_t)__builtin_popcount(older.wbits);
+    const bool packed = newer.wbits == (1u << nwn) - 1u && older.wbits == (1u << nwo) - 1u;
     uint64_t n = 0;
     bool hit = false;
-    for (uint32_t a = 0; a < newer.nseg && !hit; a++) {
+    for (uint32_t a = 0; a < nn && !hit; a++) {
+        const uint64_t s = newer.s[a], e = newer.e[a];
+        // a write meets every range of the older kernel, a read only its writes
         const bool wa = (newer.wbits >> a) & 1u;
-        for (uint32_t b = 0; b < older.nseg; b++) {
+        const uint32_t lim = packed ? (wa ? no : nwo) : no;
+        bool row = false;
+        for (uint32_t b = 0; b < lim; b++) {
             const bool wb = (older.wbits >> b) & 1u;
-            n++;
-            if ((wa || wb) && ranges_overlap(newer.s[a], newer.e[a], older.s[b], older.e[b])) {
-                hit = true;
-                break;
-            }
+            row |= (wa | wb) & (s < older.e[b]) & (e > older.s[b]);
         }
+        n += lim;
+        hit = row;
     }
     if (tests) *tests += n;
     return hit;

@@ -143,6 +143,7 @@ struct SeqHistory {
     uint32_t w;                    // bit m: position m is a write
     uint32_t mw;                   // highest write position + 1 of any kernel so far (the same on
                                    // every lane)
+    uint32_t mn;                   // most positions any kernel so far uses (the same on every lane)
 };
 
 __device__ inline void history_init(SeqHistory &h)
@@ -151,6 +152,7 @@ __device__ inline void history_init(SeqHistory &h)
     for (int m = 0; m < kSegs; m++) h.s[m] = h.e[m] = 0;
     h.w = 0;
     h.mw = 0;
+    h.mn = 0;
 }
 
 // d: the staged descriptor (LDS).  test: check the kernel and write its
@@ -172,26 +174,30 @@ __device__ inline uint64_t history_check(DevDesc *d, SeqHistory &h, uint32_t lan
     const uint32_t segmask = (1u << nseg) - 1u;
     const uint32_t wb = readlane32(dw, 5) & segmask;
     const uint32_t wtop = wb ? 32u - (uint32_t)__builtin_clz(wb) : 0u;
+    // The new ranges are the broadcast values above (no readlane per range);
+    // positions beyond any kernel's count so far hold [0, 0) everywhere and
+    // are skipped.  Every branch here is on wave-uniform values.
+    const uint32_t mn = h.mn > nseg ? h.mn : nseg;
     bool hit = false;
-    for (uint32_t k = 0; test && k < nseg; k++) {
-        const uint64_t a0 = readpair(dw, kSegStartDword + 2 * (int)k), a1 = readpair(dw, kSegEndDword + 2 * (int)k);
-        // no branch per position: unused positions hold [0, 0), which
-        // meets nothing; only the reads' bound on positions is tested
+#pragma unroll
+    for (int k = 0; k < kSegs; k++) {
+        if (!test || (uint32_t)k >= nseg) break;
+        const uint64_t a0 = ns[k], a1 = ne[k];
         if ((wb >> k) & 1u) {
+            // a new write meets any intersecting range
 #pragma unroll
-            for (int m = 0; m < kSegs; m++) hit |= a0 < h.e[m] && a1 > h.s[m];
+            for (int m = 0; m < kSegs; m++)
+                if ((uint32_t)m < mn) hit |= a0 < h.e[m] && a1 > h.s[m];
         } else {
+            // a new read meets only writes, which sit at the first mw positions
 #pragma unroll
-            for (int m = 0; m < 2; m++) hit |= a0 < h.e[m] && a1 > h.s[m] && ((h.w >> m) & 1u);
-            if (h.mw > 2u) {
-#pragma unroll
-                for (int m = 2; m < kSegs; m++) hit |= a0 < h.e[m] && a1 > h.s[m] && ((h.w >> m) & 1u);
-            }
+            for (int m = 0; m < kSegs; m++)
+                if ((uint32_t)m < h.mw) hit |= a0 < h.e[m] && a1 > h.s[m] && ((h.w >> m) & 1u);
         }
     }
     const uint32_t nw = (uint32_t)__builtin_popcount(wb);
     const uint64_t tests =
-        test ? (uint64_t)(nw * kSegs + (nseg - nw) * (h.mw > 2u ? kSegs : 2u)) * (gq < 64u ? gq : 64u) : 0ull;
+        test ? (uint64_t)(nw * mn + (nseg - nw) * h.mw) * (gq < 64u ? gq : 64u) : 0ull;
     // bit b of the result is the kernel b + 1 places back, held by lane
     // r - b mod 64 (r = gq - 1 mod 64): the lane mask reversed (lane l to
     // bit 63 - l) and rotated right by 63 - r.  There is none when b >= gq.
@@ -215,6 +221,7 @@ __device__ inline uint64_t history_check(DevDesc *d, SeqHistory &h, uint32_t lan
         h.w = wb;
     }
     h.mw = wtop > h.mw ? wtop : h.mw;
+    h.mn = mn;
     return tests;
 }
 

@@ -169,6 +169,85 @@ int acs_nop_run(acs_window *w, int32_t n, int32_t chain, uint64_t spin_ns, doubl
     return rc;
 }
 
+int acs_nop_segs_run(acs_window *w, int32_t n, int32_t nsegs, double *out_ns)
+{
+    if (!w || n < 0 || nsegs < 1 || nsegs > 64) return ACS_EINVAL;
+    acs_args_nop a = {0};
+    std::vector<acs_seg> r, wr;
+    const double t0 = wall_ns();
+    for (int32_t i = 0; i < n; i++) {
+        // kernel i: nsegs ranges of 64 bytes, 4 KiB apart, in its own 1 MiB
+        // block of an address range nothing touches (no body reads them)
+        r.clear();
+        wr.clear();
+        const uint64_t base = (1ull << 40) + (uint64_t)(i % 65536) * (1ull << 20);
+        for (int32_t s = 0; s < nsegs; s++) (s < nsegs / 2 ? r : wr).push_back(acs_seg{base + 4096ull * s, 64});
+        const int rc = acs_submit(w, ACS_K_NOP, r.data(), (int32_t)r.size(), wr.data(), (int32_t)wr.size(), &a, sizeof(a), nullptr);
+        if (rc != ACS_OK) return rc;
+    }
+    const int rc = acs_sync(w);
+    if (out_ns) *out_ns = wall_ns() - t0;
+    return rc;
+}
+
+int acs_check_probe(int32_t W, int32_t nsegs, int32_t reps, double *ns_checked, double *ns_empty, double *tests_out)
+{
+    if (W < 2 || W > ACS_W_MAX || nsegs < 2 || nsegs > 64 || reps < 1 || !ns_checked || !ns_empty) return ACS_EINVAL;
+    // kernel k's segments: nsegs ranges of 64 bytes, 4 KiB apart, in its own
+    // 1 MiB block; the first half are reads, the rest writes
+    auto segs = [&](int32_t k, std::vector<acs_seg> &r, std::vector<acs_seg> &wr) {
+        r.clear();
+        wr.clear();
+        const uint64_t base = (1ull << 32) + (uint64_t)k * (1ull << 20);
+        for (int32_t s = 0; s < nsegs; s++) (s < nsegs / 2 ? r : wr).push_back(acs_seg{base + 4096ull * s, 64});
+    };
+    acs_args_nop a = {0};
+    double result[2] = {0, 0};
+    double tests = 0;
+    for (int pass = 0; pass < 2; pass++) {
+        acs_window *w = acs_window_create(W);
+        if (!w) return acs_last_error();
+        acs_config cfg;
+        acs_config_default(&cfg);
+        cfg.path = ACS_PATH_MANUAL;
+        cfg.queue_depth = 4096;
+        int rc = acs_window_configure(w, &cfg);
+        std::vector<acs_seg> r, wr;
+        const int32_t resident = pass == 0 ? W - 1 : 0;
+        for (int32_t k = 0; rc == ACS_OK && k < resident; k++) {
+            segs(k, r, wr);
+            rc = acs_submit(w, ACS_K_NOP, r.data(), (int32_t)r.size(), wr.data(), (int32_t)wr.size(), &a, sizeof(a), nullptr);
+        }
+        // the resident kernels are taken (executing) and never completed
+        uint64_t taken[ACS_W_MAX];
+        int32_t nt = 0;
+        if (rc == ACS_OK && resident > 0) rc = acs_manual_take_ready(w, taken, ACS_W_MAX, &nt);
+        acs_stats s0 = {}, s1 = {};
+        if (rc == ACS_OK) rc = acs_stats_get(w, &s0);
+        const double t0 = wall_ns();
+        for (int32_t i = 0; rc == ACS_OK && i < reps; i++) {
+            segs(W + i % 1024, r, wr);
+            uint64_t seq = 0, got = 0;
+            int32_t n = 0;
+            rc = acs_submit(w, ACS_K_NOP, r.data(), (int32_t)r.size(), wr.data(), (int32_t)wr.size(), &a, sizeof(a), &seq);
+            if (rc == ACS_OK) rc = acs_manual_take_ready(w, &got, 1, &n);
+            if (rc == ACS_OK && (n != 1 || got != seq)) rc = ACS_EKERNEL;
+            if (rc == ACS_OK) rc = acs_manual_complete(w, seq, 0);
+        }
+        const double t1 = wall_ns();
+        if (rc == ACS_OK) rc = acs_stats_get(w, &s1);
+        if (rc == ACS_OK && pass == 0) tests = (double)(s1.overlap_tests - s0.overlap_tests) / reps;
+        for (int32_t q = 0; q < nt; q++) (void)acs_manual_complete(w, taken[q], 0);
+        acs_window_destroy(w);
+        if (rc != ACS_OK) return rc;
+        result[pass] = (t1 - t0) / reps;
+    }
+    *ns_checked = result[0];
+    *ns_empty = result[1];
+    if (tests_out) *tests_out = tests;
+    return ACS_OK;
+}
+
 int acs_dnn_submit(acs_window *w, const acs_dnn_graph *g, const float *logits, uint64_t *n_kernels)
 {
     return acs::dnn_submit_group(w, 0, g, logits, n_kernels);

@@ -551,3 +551,20 @@ def test_dag_driver_rejects_malformed_graphs():
         assert acs.lib().acs_dag_submit(w.handle, acs.C.byref(g), None) == acs.EINVAL, mutate
         assert w.stats()["submitted"] == 0, mutate           # nothing went in before the check
         w.destroy()
+
+
+def test_check_probe_counts_every_segment_pair():
+    """The host check-cost probe (the overhead table of Section IV-D): with
+    W - 1 resident kernels of S segments (S/2 reads, the rest writes, all
+    disjoint), each check tests the new kernel's writes against every range
+    and its reads against the writes of every resident kernel."""
+    import ctypes as C
+    L = acs.lib()
+    for W, S in ((16, 6), (32, 6), (4, 2)):
+        a, b, t = C.c_double(), C.c_double(), C.c_double()
+        assert L.acs_check_probe(W, S, 2000, C.byref(a), C.byref(b), C.byref(t)) == 0
+        nr = S // 2
+        nw = S - nr
+        assert t.value == (W - 1) * (nw * S + nr * nw)
+        assert a.value > 0 and b.value > 0
+    assert L.acs_check_probe(1, 6, 10, C.byref(a), C.byref(b), None) == acs.EINVAL
