@@ -41,7 +41,13 @@ HBM_PEAK_GBS = 8000.0
 # (--copy-calibration).  Valid only for the kernel sources whose digest is
 # recorded and for the same workload and tuned configuration: any change
 # makes the figure stale (null).
-TRAFFIC = None
+TRAFFIC = {
+    "digest": "fbe82074373579cb",
+    "workload": (256, 20, json.dumps({"W": 32, "n_groups": 1, "wg_per_task": 1, "queue_depth": 256,
+                                      "host_check_depth": 32, "window_check": 0}, sort_keys=True)),
+    "fetch_kib": 500505.875, "write_kib": 835212.25,
+    "copy_bytes": 268435456, "copy_fetch_kib": 131085.25, "copy_write_kib": 262144.0,
+}
 KERNEL_SOURCES = ["kernels.hip", "persistent.hpp", "bodies.hpp", "dev_shared.hpp"]
 
 
@@ -353,14 +359,16 @@ def headline(acs, inputs, torch, args):
         log(f"[bench] headline run {i}: {dt * 1e3:.1f} ms, {counts['kernels'] / dt / 1e3:.0f}k kernels/s")
     # the single-stream baseline on the same scenes
     ino = []
-    gpu = [acs.RLSceneGPU(sc) for sc in scenes]
-    torch.cuda.synchronize()
-    with acs.Window(8, path="inorder") as w:
-        t0 = time.perf_counter()
-        c_in, _ = acs.rl_run_batch(w, gpu, args.batch_steps)
-        ino.append((time.perf_counter() - t0, c_in))
-    same = all(np.array_equal(a.view(np.uint32), g.get(acs.RL_X).view(np.uint32)) for a, g in zip(final, gpu))
-    log(f"[bench] headline in-order: {c_in['kernels'] / ino[0][0] / 1e3:.0f}k kernels/s")
+    same = None
+    if not args.no_inorder:
+        gpu = [acs.RLSceneGPU(sc) for sc in scenes]
+        torch.cuda.synchronize()
+        with acs.Window(8, path="inorder") as w:
+            t0 = time.perf_counter()
+            c_in, _ = acs.rl_run_batch(w, gpu, args.batch_steps)
+            ino.append((time.perf_counter() - t0, c_in))
+        same = all(np.array_equal(a.view(np.uint32), g.get(acs.RL_X).view(np.uint32)) for a, g in zip(final, gpu))
+        log(f"[bench] headline in-order: {c_in['kernels'] / ino[0][0] / 1e3:.0f}k kernels/s")
     return {"scenes": scenes, "sizes": sizes, "tuned": best, "candidates": len(table), "runs": runs,
             "inorder": ino, "device_equals_inorder": bool(same)}
 
@@ -486,6 +494,32 @@ def window_sweep(acs, inputs, torch, args):
     return out
 
 
+def profile_case(acs, inputs, torch, args):
+    """A short fixed run of one small workload on the device path (one
+    persistent launch) and then on the in-order stream, for counter runs:
+    the tiny random stream (64 kernels, W=8) 20 times, or the gated network
+    (W=16) on 8 inputs."""
+    for path in ("device", "inorder"):
+        if args.profile_case == "tiny":
+            st = inputs.tiny_stream(0)
+            arena = torch.from_numpy(st.init.copy()).cuda()
+            torch.cuda.synchronize()
+            with acs.Window(8, path=path) as w:
+                for _ in range(20):
+                    acs.submit_tiny_stream(w, st, arena.data_ptr())
+                    w.sync()
+        else:
+            net = acs.DNNGPU(inputs.dnn_weights(), inputs.DNN_CELLS, inputs.DNN_CLASSES)
+            with acs.Window(16, path=path) as w:
+                for sd in range(8):
+                    inp = inputs.dnn_input(sd)
+                    net.set_input(inp.x)
+                    acs.dnn_submit(w, net, inp.logits)
+                    w.sync()
+        torch.cuda.synchronize()
+        log(f"[bench] profile case {args.profile_case}: {path} done")
+
+
 def check_cost(acs):
     """The host's dependency check per insert at W in {16, 32} and 6 or 10
     read/write segments (the overhead table of Section IV-D), and the device
@@ -524,6 +558,11 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--config", default=None, help="tuned configuration as JSON (skips the autotuner)")
     ap.add_argument("--only-headline", action="store_true", help="the headline workload only (profiling runs)")
+    ap.add_argument("--no-inorder", action="store_true",
+                    help="skip the headline's in-order comparison (counter runs, where every dispatch is serialised)")
+    ap.add_argument("--profile-case", choices=("tiny", "dnn"), default=None,
+                    help="only run the tiny random stream or the gated network on the device and in-order paths "
+                         "(occupancy runs)")
     ap.add_argument("--episodes", type=int, default=3, help="64-sphere episodes timed per path")
     ap.add_argument("--physics-steps", type=int, default=200)
     ap.add_argument("--bodies", type=int, default=64)
@@ -564,6 +603,9 @@ def main():
         copy_calibration(torch)
         return
     acs.lib()
+    if args.profile_case:
+        profile_case(acs, inputs, torch, args)
+        return
     paths = args.paths.split(",")
     if "graph_per_input" in paths:
         # Its host process has ended with a segmentation fault inside the
@@ -583,8 +625,7 @@ def main():
     value = kernels / dt
     counts = runs[-1][1]
     kns = float(np.mean([r[2] for r in runs]))
-    ino_dt, ino_c = hl["inorder"][0]
-    ino_rate = ino_c["kernels"] / ino_dt
+    ino_rate = hl["inorder"][0][1]["kernels"] / hl["inorder"][0][0] if hl["inorder"] else None
     step_ms = np.concatenate([r[3] for r in runs]) / 1e6
     best = hl["tuned"]
     out = {
@@ -598,7 +639,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "speedup_vs_inorder": value / ino_rate,
+        "speedup_vs_inorder": value / ino_rate if ino_rate else None,
         "inorder_kernels_per_s": ino_rate,
         "dtype": "f32",
         "data": "synthetic",
@@ -619,7 +660,7 @@ def main():
                        "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes(wkey),
                        "kernel": f"k_persistent<{1 if best['n_groups'] <= 1 else (2 if best['n_groups'] <= 2 else (4 if best['n_groups'] <= 4 else 8))}>",
                        "launch_ms": kns / 1e6, "bytes_per_launch": bytes_per_launch, "kernel_digest": kernel_digest()}
-    log(f"[bench] headline: {value / 1e3:.0f}k kernels/s, {out['speedup_vs_inorder']:.2f}x in-order, "
+    log(f"[bench] headline: {value / 1e3:.0f}k kernels/s, {out['speedup_vs_inorder'] or 0:.2f}x in-order, "
         f"launch {kns / 1e6:.1f} ms, {achieved:.3f} GB/s algorithmic")
     if args.only_headline:
         print(json.dumps(out), flush=True)

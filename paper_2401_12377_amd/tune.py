@@ -6,8 +6,9 @@ candidate on the device path.
 Each candidate runs on its own copy of the scenes (the tuning steps do not
 advance the caller's scenes).  The search is exhaustive over (W, groups,
 workgroups per task, where the dependency checks run) with W in {8, 16, 32}
-and groups * pow2(W) <= 64, then over the queue depth for the best of those.
-With one group the checks may run in the check wave ahead of the window
+and groups * pow2(W) <= 64, then over the queue depth for the best of
+those.  Rates within 2% of the fastest count as equal, and the cheapest of
+those is taken.  With one group the checks may run in the check wave ahead of the window
 (the default), on the host against the last W kernels, or in the window
 wave; with more groups always in the window wave.
 """
@@ -61,9 +62,19 @@ def time_config(scenes, cfg: dict, steps: int = 2, warmup: int = 1) -> float:
     return counts["kernels"] / dt
 
 
-def autotune(scenes, steps: int = 2, log=None, timer=None, **space):
+def pick(table, tie: float = 0.0) -> dict:
+    """The fastest configuration of `table`; among those within a fraction
+    `tie` of it (timing noise), the one with the fewest workgroups per task,
+    then groups, then the shortest input queue, then the fastest."""
+    top = max(v for _, v in table)
+    close = [(c, v) for c, v in table if v >= (1.0 - tie) * top]
+    return dict(min(close, key=lambda t: (t[0]["wg_per_task"], t[0]["n_groups"], t[0]["queue_depth"], -t[1]))[0])
+
+
+def autotune(scenes, steps: int = 2, log=None, timer=None, tie: float = 0.02, **space):
     """Returns (best config, table of (config, kernels/s)).  `timer(scenes,
-    cfg, steps)` measures one candidate (time_config unless given)."""
+    cfg, steps)` measures one candidate (time_config unless given); `tie` is
+    the relative difference below which two rates count as equal (see pick)."""
     timer = timer or time_config
     table = []
     for cfg in candidates(**space):
@@ -71,12 +82,12 @@ def autotune(scenes, steps: int = 2, log=None, timer=None, **space):
         table.append((cfg, v))
         if log:
             log(f"[tune] {cfg}: {v / 1e3:.0f}k kernels/s")
-    best = dict(max(table, key=lambda t: t[1])[0])
+    best = pick(table, tie)
     for qd in (256, 1024):
         cfg = dict(best, queue_depth=qd)
         v = timer(scenes, cfg, steps)
         table.append((cfg, v))
         if log:
             log(f"[tune] {cfg}: {v / 1e3:.0f}k kernels/s")
-    best = dict(max(table, key=lambda t: t[1])[0])
+    best = pick([(c, v) for c, v in table if all(c[k] == best[k] for k in best if k != "queue_depth")], tie)
     return best, table

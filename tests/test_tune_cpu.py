@@ -44,10 +44,28 @@ def test_autotune_picks_the_fastest_then_refines_queue_depth():
         v = 1000.0 * cfg["W"] - 10 * cfg["n_groups"] + cfg["wg_per_task"] + (5 if cfg["window_check"] else 0)
         return v + (50 if cfg["queue_depth"] == 1024 else 0)
 
-    best, table = tune.autotune(None, steps=1, timer=timer)
+    best, table = tune.autotune(None, steps=1, timer=timer, tie=0.0)
     n = len(list(tune.candidates()))
     assert len(calls) == n + 2 and len(table) == n + 2
     assert best["W"] == 32 and best["n_groups"] == 1 and best["wg_per_task"] == 4 and best["window_check"] == 1
     assert best["queue_depth"] == 1024
     assert [c["queue_depth"] for c in calls[-2:]] == [256, 1024]
     assert all(calls[-1][k] == best[k] for k in best)
+
+
+def test_near_ties_go_to_the_cheapest_configuration():
+    # 32/host with one or two workgroups per task 0.4% apart, queue depths
+    # 0.8% apart: the cheaper of each pair is taken; a 5% gap is not a tie
+    rates = {(32, 1, "host"): 2098.0, (32, 2, "host"): 2089.0, (16, 1, "host"): 1812.0}
+
+    def timer(scenes, cfg, steps):
+        site = "host" if cfg["host_check_depth"] else ("window" if cfg["window_check"] else "wave")
+        v = rates.get((cfg["W"], cfg["wg_per_task"], site), 1000.0)
+        return v - (16.0 if cfg["queue_depth"] == 1024 else 0.0) + (2.0 if cfg["queue_depth"] == 4096 else 0.0)
+
+    best, _ = tune.autotune(None, steps=1, timer=timer)
+    assert best == {"W": 32, "n_groups": 1, "wg_per_task": 1, "queue_depth": 256, "host_check_depth": 32,
+                    "window_check": 0}
+    far = tune.pick([({"W": 8, "n_groups": 1, "wg_per_task": 1, "queue_depth": 256}, 95.0),
+                     ({"W": 32, "n_groups": 1, "wg_per_task": 2, "queue_depth": 4096}, 100.0)], tie=0.02)
+    assert far["W"] == 32
