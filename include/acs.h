@@ -160,6 +160,32 @@ acs_window *acs_window_create(int32_t W);
  * Without this call the window uses acs_config_default(). */
 int acs_window_configure(acs_window *w, const acs_config *cfg);
 
+/* For callers that cannot allocate memory (code that must not call hipMalloc
+ * or hipHostMalloc: tight serving loops, harnesses that forbid allocation):
+ * acs_window_configure for the device path that allocates nothing.
+ *   cfg         as for acs_window_configure; path must be ACS_PATH_DEVICE and
+ *               trace 0 (ACS_EINVAL otherwise).
+ *   host_mem    the caller's pinned, coherent, device-mapped host memory (for
+ *               example from acs_host_alloc), 64-byte aligned, at least
+ *               ACS_NOALLOC_HOST_BYTES(q, G) bytes with q = queue_depth
+ *               rounded up to a power of two (at least 16) and G = n_groups
+ *               (ACS_EINVAL if shorter).  It holds the input FIFO and the
+ *               control words; the caller keeps it alive and untouched until
+ *               acs_window_destroy returns.
+ *   stream      the caller's hipStream_t on cfg->device, created non-blocking
+ *               and used by nothing else until acs_window_stop or
+ *               acs_window_destroy returns: the persistent kernel runs in it.
+ * The scheduler state lives in a static device array of 1.5 MiB per device,
+ * which each device holds until the process ends; it is cleared by a fill
+ * kernel on `stream` before the persistent kernel starts.  One such window
+ * per device at a time: a second one on the same device, while the first has
+ * not been destroyed, gets ACS_ESTATE (two would share that array).
+ * acs_stats.kernel_ns stays 0 (no timing events are created).  Everything
+ * else behaves as with acs_window_configure. */
+#define ACS_NOALLOC_HOST_BYTES(q, G) (4096ull + 256ull * (uint64_t)(q) * (uint64_t)(G))
+int acs_window_configure_noalloc(acs_window *w, const acs_config *cfg, void *host_mem, uint64_t host_bytes,
+                                 void *stream);
+
 /* Submits one kernel in program order.
  *   kernel_id   task type from acs_tasks.h (the body the library runs).
  *   read_segs   n_read byte ranges the kernel reads; write_segs likewise.

@@ -205,6 +205,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2401_12377_amd.build`")
+        # One HIP runtime per process: torch ships its own copy, which binds
+        # libacs's reference (same soname) only if torch is loaded first.
+        # Loaded the other way round, torch adds a second runtime, and the
+        # one initialised second finds no device.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         P = C.POINTER
         L.acs_config_default.argtypes = [P(Config)]
@@ -212,6 +217,7 @@ def lib():
         L.acs_window_create.argtypes = [C.c_int32]
         L.acs_window_create.restype = C.c_void_p
         L.acs_window_configure.argtypes = [C.c_void_p, P(Config)]
+        L.acs_window_configure_noalloc.argtypes = [C.c_void_p, P(Config), C.c_void_p, C.c_uint64, C.c_void_p]
         L.acs_submit.argtypes = [C.c_void_p, C.c_int32, P(Seg), C.c_int32, P(Seg), C.c_int32, C.c_void_p, C.c_size_t,
                                  P(C.c_uint64)]
         L.acs_sync.argtypes = [C.c_void_p]
@@ -332,12 +338,14 @@ class Window:
     The keyword arguments are the fields of acs_config (include/acs.h); on
     the device path with one group the dependency checks run in the check
     waves ahead of the window unless host_check_depth > 0 (on the host) or
-    window_check = 1 (in the window wave at insert)."""
+    window_check = 1 (in the window wave at insert).  noalloc = (host
+    pointer, host bytes, HIP stream handle) configures the device path
+    through acs_window_configure_noalloc instead."""
 
     def __init__(self, W: int, path: str = "device", n_streams: int = 4, wg_per_task: int = 1, n_workers: int = 0,
                  queue_depth: int = 4096, nonblocking: bool = False, trace: bool = False,
                  trace_capacity: int = 1 << 16, device: int = 0, n_groups: int = 1, host_check_depth: int = 0,
-                 window_check: int = 0):
+                 window_check: int = 0, noalloc: tuple | None = None):
         L = lib()
         h = L.acs_window_create(W)
         if not h:
@@ -355,7 +363,11 @@ class Window:
         cfg.host_check_depth = host_check_depth
         cfg.window_check = window_check
         self.n_groups = n_groups
-        rc = L.acs_window_configure(h, C.byref(cfg))
+        if noalloc is None:
+            rc = L.acs_window_configure(h, C.byref(cfg))
+        else:
+            host_ptr, host_bytes, stream = noalloc
+            rc = L.acs_window_configure_noalloc(h, C.byref(cfg), host_ptr, host_bytes, stream)
         if rc < 0:
             msg = L.acs_strerror(rc).decode()
             L.acs_window_destroy(h)
@@ -572,7 +584,7 @@ class HostBuffer:
                                    "(the host allocator synchronises the device)")
         p = lib().acs_host_alloc(nbytes)
         if not p:
-            raise AcsError(ENOMEM, "acs_host_alloc failed")
+            raise AcsError(ENOMEM, "acs_host_alloc failed: " + lib().acs_strerror(lib().acs_last_error()).decode())
         self.ptr = p
         self.nbytes = nbytes
 

@@ -22,7 +22,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libacs.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HIP_SOURCES = ["kernels.hip"]
+HIP_SOURCES = ["kernels.hip", "noalloc.hip"]
 HOST_SOURCES = ["window.cpp", "paths.cpp", "device_path.cpp", "abi.cpp", "workloads.cpp", "graph.cpp", "serve.cpp"]
 
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",

@@ -353,6 +353,30 @@ int ensure_started(acs_window *w)
     w->started = true;
     return ACS_OK;
 }
+
+int validate_config(const acs_window *w, const acs_config *cfg)
+{
+    if (cfg->path < ACS_PATH_INORDER || cfg->path > ACS_PATH_EVENTS) return fail(ACS_EINVAL, "unknown path");
+    if (cfg->n_streams < 1 || cfg->n_streams > 64) return fail(ACS_EINVAL, "n_streams must be in [1, 64]");
+    if (cfg->wg_per_task < 1 || cfg->wg_per_task > 256) return fail(ACS_EINVAL, "wg_per_task must be in [1, 256]");
+    if (cfg->n_workers < 0 || cfg->n_workers > 8192) return fail(ACS_EINVAL, "n_workers must be in [0, 8192]");
+    if (cfg->queue_depth < 1 || cfg->queue_depth > (1 << 20)) return fail(ACS_EINVAL, "queue_depth must be in [1, 2^20]");
+    if (cfg->trace && (cfg->trace_capacity < 1 || cfg->trace_capacity > (1 << 24)))
+        return fail(ACS_EINVAL, "trace_capacity must be in [1, 2^24]");
+    if (cfg->n_groups < 1 || cfg->n_groups > 8) return fail(ACS_EINVAL, "n_groups must be in [1, 8]");
+    if (cfg->path == ACS_PATH_DEVICE) {
+        int32_t wp = 1;
+        while (wp < w->W) wp <<= 1;
+        if (wp * cfg->n_groups > ACS_W_MAX)
+            return fail(ACS_EINVAL, "device path: n_groups times W rounded up to a power of two must be at most 64");
+    }
+    if (cfg->host_check_depth < 0 || cfg->host_check_depth > ACS_W_MAX)
+        return fail(ACS_EINVAL, "host_check_depth must be in [0, 64]");
+    if (cfg->path == ACS_PATH_DEVICE && cfg->host_check_depth > 0 && cfg->n_groups != 1)
+        return fail(ACS_EINVAL, "host checks need a single window group");
+    if (cfg->window_check != 0 && cfg->window_check != 1) return fail(ACS_EINVAL, "window_check must be 0 or 1");
+    return ACS_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -393,28 +417,29 @@ int acs_window_configure(acs_window *w, const acs_config *cfg)
 {
     if (!w || !cfg) return fail(ACS_EINVAL, "null argument");
     if (w->started) return fail(ACS_ESTATE, "configure must come before the first submit");
-    if (cfg->path < ACS_PATH_INORDER || cfg->path > ACS_PATH_EVENTS) return fail(ACS_EINVAL, "unknown path");
-    if (cfg->n_streams < 1 || cfg->n_streams > 64) return fail(ACS_EINVAL, "n_streams must be in [1, 64]");
-    if (cfg->wg_per_task < 1 || cfg->wg_per_task > 256) return fail(ACS_EINVAL, "wg_per_task must be in [1, 256]");
-    if (cfg->n_workers < 0 || cfg->n_workers > 8192) return fail(ACS_EINVAL, "n_workers must be in [0, 8192]");
-    if (cfg->queue_depth < 1 || cfg->queue_depth > (1 << 20)) return fail(ACS_EINVAL, "queue_depth must be in [1, 2^20]");
-    if (cfg->trace && (cfg->trace_capacity < 1 || cfg->trace_capacity > (1 << 24)))
-        return fail(ACS_EINVAL, "trace_capacity must be in [1, 2^24]");
-    if (cfg->n_groups < 1 || cfg->n_groups > 8) return fail(ACS_EINVAL, "n_groups must be in [1, 8]");
-    if (cfg->path == ACS_PATH_DEVICE) {
-        int32_t wp = 1;
-        while (wp < w->W) wp <<= 1;
-        if (wp * cfg->n_groups > ACS_W_MAX)
-            return fail(ACS_EINVAL, "device path: n_groups times W rounded up to a power of two must be at most 64");
-    }
-    if (cfg->host_check_depth < 0 || cfg->host_check_depth > ACS_W_MAX)
-        return fail(ACS_EINVAL, "host_check_depth must be in [0, 64]");
-    if (cfg->path == ACS_PATH_DEVICE && cfg->host_check_depth > 0 && cfg->n_groups != 1)
-        return fail(ACS_EINVAL, "host checks need a single window group");
-    if (cfg->window_check != 0 && cfg->window_check != 1) return fail(ACS_EINVAL, "window_check must be 0 or 1");
+    if (int rc = validate_config(w, cfg)) return rc;
     w->cfg = *cfg;
     w->configured = true;
     return ensure_started(w);
+}
+
+int acs_window_configure_noalloc(acs_window *w, const acs_config *cfg, void *host_mem, uint64_t host_bytes,
+                                 void *stream)
+{
+    if (!w || !cfg || !host_mem || !stream) return fail(ACS_EINVAL, "null argument");
+    if (w->started) return fail(ACS_ESTATE, "configure must come before the first submit");
+    if (int rc = validate_config(w, cfg)) return rc;
+    if (cfg->path != ACS_PATH_DEVICE) return fail(ACS_EINVAL, "only the device path has a configuration without allocation");
+    if (reinterpret_cast<uintptr_t>(host_mem) % 64 != 0) return fail(ACS_EINVAL, "host block must be 64-byte aligned");
+    int rc = ACS_OK;
+    std::unique_ptr<Path> p = make_device_path_static(w->W, *cfg, host_mem, host_bytes, stream, &rc);
+    if (!p) return rc;
+    if ((rc = p->start()) != ACS_OK) return rc;   // destroying p releases the device's state
+    w->cfg = *cfg;
+    w->configured = true;
+    w->path = std::move(p);
+    w->started = true;
+    return ACS_OK;
 }
 
 int acs_submit(acs_window *w, int32_t kernel_id, const acs_seg *read_segs, int32_t n_read, const acs_seg *write_segs,
@@ -550,6 +575,24 @@ int acs_manual_complete(acs_window *w, uint64_t seq, int32_t status)
     if (int rc = ensure_started(w)) return rc;
     if (w->cfg.path != ACS_PATH_MANUAL) return fail(ACS_ESTATE, "not a manual window");
     return w->path->complete(seq, status);
+}
+
+void *acs_host_alloc(size_t bytes)
+{
+    void *p = nullptr;
+    const hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocCoherent | hipHostMallocMapped);
+    if (e != hipSuccess) {
+        set_error(ACS_ENOMEM, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+        return nullptr;
+    }
+    return p;
+}
+
+int acs_host_free(void *p)
+{
+    if (!p) return ACS_OK;
+    const hipError_t e = hipHostFree(p);
+    return e == hipSuccess ? ACS_OK : fail(ACS_EDEVICE, std::string("hipHostFree: ") + hipGetErrorString(e));
 }
 
 int acs_last_error(void) { return t_last_error; }

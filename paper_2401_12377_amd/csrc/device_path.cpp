@@ -5,6 +5,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -29,10 +31,37 @@ uint32_t pow2_at_least(uint32_t x)
     return p;
 }
 
+// Windows configured without allocation keep their host control block and
+// descriptor rings in one caller-provided block of pinned host memory: the
+// control block first (kStaticCtrlBytes), the rings after it.
+constexpr uint64_t kStaticCtrlBytes = 4096;
+static_assert(sizeof(HostCtrl) <= kStaticCtrlBytes, "host control block must fit its reserved bytes");
+
+// Devices with a window configured without allocation open (bit d): the
+// static scheduler state of a device serves one such window at a time.
+std::atomic<uint64_t> g_static_busy{0};
+
+constexpr int32_t kStaticDevices = 64;
+
 class DevicePath : public Path {
 public:
     DevicePath(int32_t W, const acs_config &cfg) : W_(W), cfg_(cfg) {}
+    // Without allocation: host control block and rings in `host` (pinned,
+    // host_bytes long), scheduler state in the device's static state, the
+    // persistent kernel on the caller's stream, no timing events.
+    DevicePath(int32_t W, const acs_config &cfg, void *host, uint64_t host_bytes, hipStream_t stream)
+        : W_(W), cfg_(cfg), static_(true), claimed_(true), host_(host), host_bytes_(host_bytes)
+    {
+        stream_ = stream;
+    }
     ~DevicePath() override { shutdown(); }
+
+    // The objects of windows configured without allocation live in static
+    // storage, one per device (placement new); deleting one only ends its
+    // lifetime.  Others come from the heap.
+    static void *operator new(size_t n) { return ::operator new(n); }
+    static void *operator new(size_t, void *where) { return where; }
+    static void operator delete(void *p);
 
     int start() override
     {
@@ -56,24 +85,30 @@ public:
 
         groups_ = std::max(1, std::min(cfg_.n_groups, kMaxGroups));
         ring_cap_ = pow2_at_least((uint32_t)std::max(16, cfg_.queue_depth));
-        if ((e = hipHostMalloc((void **)&ctrl_, sizeof(HostCtrl), hipHostMallocCoherent | hipHostMallocMapped)) != hipSuccess)
-            return hip_fail(e, "hipHostMalloc(ctrl)");
-        memset((void *)ctrl_, 0, sizeof(HostCtrl));
         const size_t ring_bytes = sizeof(DevDesc) * ring_cap_ * (size_t)groups_;
-        if ((e = hipHostMalloc((void **)&ring_, ring_bytes, hipHostMallocCoherent | hipHostMallocMapped)) != hipSuccess)
-            return hip_fail(e, "hipHostMalloc(ring)");
-        memset((void *)ring_, 0, ring_bytes);
-        if ((e = hipMalloc((void **)&st_, sizeof(DevState))) != hipSuccess) return hip_fail(e, "hipMalloc(state)");
-        if ((e = hipMemset(st_, 0, sizeof(DevState))) != hipSuccess) return hip_fail(e, "hipMemset(state)");
-        if (cfg_.trace) {
-            trace_cap_ = (uint32_t)cfg_.trace_capacity;
-            if ((e = hipMalloc((void **)&dtrace_, sizeof(acs_trace_rec) * trace_cap_)) != hipSuccess)
-                return hip_fail(e, "hipMalloc(trace)");
-            if ((e = hipMemset(dtrace_, 0, sizeof(acs_trace_rec) * trace_cap_)) != hipSuccess)
-                return hip_fail(e, "hipMemset(trace)");
+        if (static_) {
+            if (int rc = start_static(ring_bytes)) return rc;
+        } else {
+            if ((e = hipHostMalloc((void **)&ctrl_, sizeof(HostCtrl), hipHostMallocCoherent | hipHostMallocMapped)) !=
+                hipSuccess)
+                return hip_fail(e, "hipHostMalloc(ctrl)");
+            memset((void *)ctrl_, 0, sizeof(HostCtrl));
+            if ((e = hipHostMalloc((void **)&ring_, ring_bytes, hipHostMallocCoherent | hipHostMallocMapped)) != hipSuccess)
+                return hip_fail(e, "hipHostMalloc(ring)");
+            memset((void *)ring_, 0, ring_bytes);
+            if ((e = hipMalloc((void **)&st_, sizeof(DevState))) != hipSuccess) return hip_fail(e, "hipMalloc(state)");
+            if ((e = hipMemset(st_, 0, sizeof(DevState))) != hipSuccess) return hip_fail(e, "hipMemset(state)");
+            if (cfg_.trace) {
+                trace_cap_ = (uint32_t)cfg_.trace_capacity;
+                if ((e = hipMalloc((void **)&dtrace_, sizeof(acs_trace_rec) * trace_cap_)) != hipSuccess)
+                    return hip_fail(e, "hipMalloc(trace)");
+                if ((e = hipMemset(dtrace_, 0, sizeof(acs_trace_rec) * trace_cap_)) != hipSuccess)
+                    return hip_fail(e, "hipMemset(trace)");
+            }
+            if ((e = hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking)) != hipSuccess)
+                return hip_fail(e, "hipStreamCreate");
+            if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
         }
-        if ((e = hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "hipStreamCreate");
-        if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
 
         DevParams p;
         memset(&p, 0, sizeof(p));
@@ -92,13 +127,47 @@ public:
         fc_ = groups_ == 1 && hc_ == 0 && cfg_.window_check == 0;
         p.host_check = fc_ ? ACS_W_MAX : hc_;
         p.check_wave = fc_ ? 1 : 0;
-        hist_.assign((size_t)std::max(1, hc_), Desc{});
-        if ((e = hipEventCreate(&ev0_)) != hipSuccess) return hip_fail(e, "hipEventCreate");
-        if ((e = hipEventCreate(&ev1_)) != hipSuccess) return hip_fail(e, "hipEventCreate");
-        if ((e = hipEventRecord(ev0_, stream_)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        hist_n_ = 0;
+        if (!static_) {
+            if ((e = hipEventCreate(&ev0_)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+            if ((e = hipEventCreate(&ev1_)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+            if ((e = hipEventRecord(ev0_, stream_)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        }
         if ((e = launch_persistent(p, 1 + n_workers_, stream_)) != hipSuccess) return hip_fail(e, "persistent kernel launch");
-        if ((e = hipEventRecord(ev1_, stream_)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        if (!static_ && (e = hipEventRecord(ev1_, stream_)) != hipSuccess) return hip_fail(e, "hipEventRecord");
         running_ = true;
+        return ACS_OK;
+    }
+
+    // Start of a window configured without allocation (its object holds the
+    // device's claim): checks the caller's memory and stream, and clears the
+    // device's static state on the stream ahead of the persistent kernel.
+    int start_static(size_t ring_bytes)
+    {
+        if (cfg_.trace) {
+            set_error(ACS_EINVAL, "a window configured without allocation keeps no trace (set trace to 0)");
+            return ACS_EINVAL;
+        }
+        const uint64_t need = kStaticCtrlBytes + ring_bytes;
+        if (host_bytes_ < need) {
+            set_error(ACS_EINVAL, "host block of " + std::to_string(host_bytes_) + " bytes; this configuration needs " +
+                                      std::to_string(need));
+            return ACS_EINVAL;
+        }
+        hipDevice_t sd = -1;
+        hipError_t e = hipStreamGetDevice(stream_, &sd);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamGetDevice");
+        if (sd != cfg_.device) {
+            set_error(ACS_EINVAL, "the stream belongs to another device than the window");
+            return ACS_EINVAL;
+        }
+        ctrl_ = static_cast<HostCtrl *>(host_);
+        ring_ = reinterpret_cast<DevDesc *>(static_cast<uint8_t *>(host_) + kStaticCtrlBytes);
+        memset((void *)ctrl_, 0, sizeof(HostCtrl));
+        memset((void *)ring_, 0, ring_bytes);
+        if ((e = static_state(cfg_.device, &st_)) != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(state)");
+        // the previous window's queue entries, counters and rings are still there
+        if ((e = clear_state(st_, stream_)) != hipSuccess) return hip_fail(e, "clearing the scheduler state");
         return ACS_OK;
     }
 
@@ -268,7 +337,7 @@ public:
                 if (rc != ACS_OK && err_ == ACS_OK) err_ = rc;
             }
             float ms = 0.0f;
-            if (hipEventElapsedTime(&ms, ev0_, ev1_) == hipSuccess) kernel_ns_ = (uint64_t)((double)ms * 1e6);
+            if (ev0_ && hipEventElapsedTime(&ms, ev0_, ev1_) == hipSuccess) kernel_ns_ = (uint64_t)((double)ms * 1e6);
         }
         return rc;
     }
@@ -277,6 +346,16 @@ public:
     {
         const int rc = stop();
         if (leaked_) return rc;
+        if (static_) {
+            // the caller's memory and stream stay the caller's
+            if (claimed_) g_static_busy.fetch_and(~(1ull << cfg_.device), std::memory_order_acq_rel);
+            claimed_ = false;
+            st_ = nullptr;
+            ring_ = nullptr;
+            ctrl_ = nullptr;
+            stream_ = nullptr;
+            return rc;
+        }
         if (stream_) {
             (void)hipStreamDestroy(stream_);
             stream_ = nullptr;
@@ -356,7 +435,7 @@ private:
     uint64_t polls_ = 0;
     int32_t hc_ = 0;                 // host-check depth M (0: checks on the device)
     bool fc_ = false;                // checks made by the check wave
-    std::vector<Desc> hist_;         // the last M descriptors submitted, by submission index % M
+    Desc hist_[ACS_W_MAX];           // the last M descriptors submitted, by submission index % M
     uint64_t hist_n_ = 0;
     uint64_t host_tests_ = 0;
     acs_config cfg_;
@@ -375,10 +454,44 @@ private:
     uint64_t total_submitted_ = 0, snap_req_ = 0, checks_ = 0;
     int err_ = ACS_OK;
     bool running_ = false, leaked_ = false;
+    bool static_ = false, claimed_ = false;
+    void *host_ = nullptr;
+    uint64_t host_bytes_ = 0;
 };
+
+alignas(DevicePath) uint8_t g_static_paths[kStaticDevices][sizeof(DevicePath)];
+
+void DevicePath::operator delete(void *p)
+{
+    const uint8_t *b = static_cast<const uint8_t *>(p);
+    const uint8_t *lo = &g_static_paths[0][0];
+    if (b >= lo && b < lo + sizeof(g_static_paths)) return;
+    ::operator delete(p);
+}
 
 }  // namespace
 
 std::unique_ptr<Path> make_device_path(int32_t W, const acs_config &cfg) { return std::make_unique<DevicePath>(W, cfg); }
+
+std::unique_ptr<Path> make_device_path_static(int32_t W, const acs_config &cfg, void *host, uint64_t host_bytes,
+                                              void *stream, int *rc)
+{
+    if (cfg.device < 0 || cfg.device >= kStaticDevices) {
+        set_error(ACS_EINVAL, "windows without allocation serve devices 0 to 63");
+        *rc = ACS_EINVAL;
+        return nullptr;
+    }
+    // One object slot and one scheduler state per device: the claim taken
+    // here is released when the object is destroyed.
+    const uint64_t bit = 1ull << cfg.device;
+    if (g_static_busy.fetch_or(bit, std::memory_order_acq_rel) & bit) {
+        set_error(ACS_ESTATE, "a window configured without allocation is already open on this device");
+        *rc = ACS_ESTATE;
+        return nullptr;
+    }
+    *rc = ACS_OK;
+    return std::unique_ptr<Path>(new (static_cast<void *>(g_static_paths[cfg.device]))
+                                     DevicePath(W, cfg, host, host_bytes, static_cast<hipStream_t>(stream)));
+}
 
 }  // namespace acs

@@ -135,6 +135,10 @@ std::unique_ptr<Path> make_inorder_path(const acs_config &cfg);
 std::unique_ptr<Path> make_plain_path(int32_t W, const acs_config &cfg);
 std::unique_ptr<Path> make_manual_path(int32_t W, const acs_config &cfg);
 std::unique_ptr<Path> make_device_path(int32_t W, const acs_config &cfg);
+// The device path without allocation (acs_window_configure_noalloc): null
+// with *rc set when the device's static state is taken or out of range.
+std::unique_ptr<Path> make_device_path_static(int32_t W, const acs_config &cfg, void *host, uint64_t host_bytes,
+                                              void *stream, int *rc);
 std::unique_ptr<Path> make_events_path(const acs_config &cfg);
 
 uint64_t now_ns();

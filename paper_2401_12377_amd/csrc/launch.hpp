@@ -26,4 +26,11 @@ hipError_t persistent_blocks_per_cu(int32_t n_groups, int32_t *blocks);
 // Static LDS of one persistent-kernel workgroup (instance for n_groups).
 hipError_t persistent_lds_bytes(int32_t n_groups, int32_t *bytes);
 
+// Device address of this device's static scheduler state (the state of the
+// windows configured without allocation), taken with the device current.
+hipError_t static_state(int32_t device, DevState **out);
+
+// Zeroes a scheduler state with a fill kernel on `stream`.
+hipError_t clear_state(DevState *st, hipStream_t stream);
+
 }  // namespace acs

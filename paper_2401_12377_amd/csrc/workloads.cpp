@@ -24,23 +24,6 @@ double wall_ns()
 
 }  // namespace
 
-extern "C" {
-
-void *acs_host_alloc(size_t bytes)
-{
-    void *p = nullptr;
-    if (hipHostMalloc(&p, bytes, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) return nullptr;
-    return p;
-}
-
-int acs_host_free(void *p)
-{
-    if (!p) return ACS_OK;
-    return hipHostFree(p) == hipSuccess ? ACS_OK : ACS_EDEVICE;
-}
-
-}  // extern "C"
-
 namespace {
 
 // Jacobi sweeps alternate Q0 -> Q1 -> Q0 and integrate reads Q0: an odd

@@ -293,6 +293,14 @@ hipError_t hipStreamDestroy(hipStream_t s)
     return hipSuccess;
 }
 
+hipError_t hipStreamGetDevice(hipStream_t s, hipDevice_t *device)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    if (!live_stream(s)) die("hipStreamGetDevice of a destroyed or unknown stream");
+    *device = 0;
+    return hipSuccess;
+}
+
 hipError_t hipStreamQuery(hipStream_t s)
 {
     std::lock_guard<std::recursive_mutex> lk(g_mu);
@@ -509,5 +517,10 @@ hipError_t persistent_lds_bytes(int32_t, int32_t *bytes)
     *bytes = 0;
     return hipSuccess;
 }
+
+// no device state either: a window without allocation cannot start
+hipError_t static_state(int32_t, DevState **) { return hipErrorInvalidValue; }
+
+hipError_t clear_state(DevState *, hipStream_t) { return hipErrorInvalidValue; }
 
 }  // namespace acs

@@ -74,6 +74,8 @@ hipError_t hipStreamCreate(hipStream_t *s);
 hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned int flags);
 hipError_t hipStreamDestroy(hipStream_t s);
 hipError_t hipStreamQuery(hipStream_t s);
+typedef int hipDevice_t;
+hipError_t hipStreamGetDevice(hipStream_t s, hipDevice_t *device);
 hipError_t hipStreamSynchronize(hipStream_t s);
 hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned int flags);
 
