@@ -61,10 +61,13 @@ int acs_rl_run(acs_window *w, const acs_rl_scene *scene, int32_t steps, double *
 /* Batched scenes (many independent input-dependent graphs in one launch):
  * n_scenes scenes with disjoint arenas, scene i in window group i % n_groups
  * (the window must have acs_config.n_groups >= n_groups; use 1 on paths
- * without groups).  Per batched step: every scene's predict, broadphase,
- * islands and permute are submitted; then, group by group, the group is
- * drained, its scenes' plans read and their Jacobi and integrate kernels
- * submitted.  step_ns (if not NULL, `steps` entries) receives the wall time
+ * without groups).  Per batched step: the predicts of every scene are
+ * submitted, then every broadphase, every islands and every permute kernel;
+ * then, group by group, the group is drained, its scenes' plans read and
+ * their Jacobi kernels submitted iteration by iteration across the group's
+ * scenes, then their integrate kernels.  Each scene's own kernels keep their
+ * program order; scenes are independent, so the interleaving changes no
+ * result.  step_ns (if not NULL, `steps` entries) receives the wall time
  * of each batched step, which then ends with a full drain; counts the work
  * summed over scenes. */
 int acs_rl_run_batch(acs_window *w, const acs_rl_scene *scenes, int32_t n_scenes, int32_t n_groups, int32_t steps,

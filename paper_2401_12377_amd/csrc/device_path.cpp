@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <new>
 #include <string>
 #include <thread>
 #include <vector>
@@ -13,6 +14,7 @@
 #include "dev_shared.hpp"
 #include "internal.hpp"
 #include "launch.hpp"
+#include "segtable.hpp"
 
 namespace acs {
 
@@ -59,7 +61,7 @@ public:
     // The objects of windows configured without allocation live in static
     // storage, one per device (placement new); deleting one only ends its
     // lifetime.  Others come from the heap.
-    static void *operator new(size_t n) { return ::operator new(n); }
+    static void *operator new(size_t n) { return ::operator new(n, std::align_val_t(alignof(DevicePath))); }
     static void *operator new(size_t, void *where) { return where; }
     static void operator delete(void *p);
 
@@ -398,12 +400,17 @@ private:
     uint64_t host_check(const Desc &d)
     {
         const uint64_t M = (uint64_t)hc_;
+        const uint64_t n = std::min<uint64_t>(M, hist_n_);
+        // kernel j of the list sits in column j % M
+        uint64_t cols = 0;
+        for (uint64_t k = 0; k < n; k++) cols |= 1ull << ((hist_n_ - 1 - k) % M);
+        host_tests_ += hist_.pair_tests(cols, d);
         uint64_t mask = 0;
-        for (uint64_t k = 0; k < std::min<uint64_t>(M, hist_n_); k++) {
-            const Desc &o = hist_[(size_t)((hist_n_ - 1 - k) % M)];
-            if (descs_conflict(o, d, &host_tests_)) mask |= 1ull << k;
+        for (uint64_t hit = hist_.conflicts(cols, d); hit; hit &= hit - 1) {
+            const uint64_t c = (uint64_t)__builtin_ctzll(hit);
+            mask |= 1ull << ((hist_n_ - 1 - c) % M);   // column c holds the kernel that many places back, minus one
         }
-        hist_[(size_t)(hist_n_ % M)] = d;
+        hist_.put((int)(hist_n_ % M), d);
         hist_n_++;
         return mask;
     }
@@ -435,7 +442,7 @@ private:
     uint64_t polls_ = 0;
     int32_t hc_ = 0;                 // host-check depth M (0: checks on the device)
     bool fc_ = false;                // checks made by the check wave
-    Desc hist_[ACS_W_MAX];           // the last M descriptors submitted, by submission index % M
+    SegTable hist_;                  // the last M kernels submitted, kernel j in column j % M
     uint64_t hist_n_ = 0;
     uint64_t host_tests_ = 0;
     acs_config cfg_;
@@ -466,7 +473,7 @@ void DevicePath::operator delete(void *p)
     const uint8_t *b = static_cast<const uint8_t *>(p);
     const uint8_t *lo = &g_static_paths[0][0];
     if (b >= lo && b < lo + sizeof(g_static_paths)) return;
-    ::operator delete(p);
+    ::operator delete(p, std::align_val_t(alignof(DevicePath)));
 }
 
 }  // namespace

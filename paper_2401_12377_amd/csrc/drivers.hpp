@@ -30,22 +30,30 @@ public:
     // predict, broadphase, islands, permute
     int submit_prefix(acs_rl_counts &cnt)
     {
-        const acs_seg plan_seg = {(uint64_t)(uintptr_t)sc_->plan, 4ull * acs::rl_plan_ints(sc_->n)};
+        for (int k = 0; k < 4; k++)
+            if (int rc = submit_stage(k, cnt)) return rc;
+        return ACS_OK;
+    }
+
+    // kernel k of the first half: 0 predict, 1 broadphase, 2 islands, 3 permute
+    int submit_stage(int k, acs_rl_counts &cnt)
+    {
         a_.iter = a_.b0 = a_.b1 = 0;
-        {
+        if (k == 0) {
             const acs_seg r[2] = {region(ACS_RL_X), region(ACS_RL_V)};
             const acs_seg wr[1] = {region(ACS_RL_P)};
-            if (int rc = submit(ACS_K_RL_PREDICT, r, 2, wr, 1, cnt)) return rc;
+            return submit(ACS_K_RL_PREDICT, r, 2, wr, 1, cnt);
         }
-        {
+        if (k == 1) {
             const acs_seg r[1] = {region(ACS_RL_P)};
             const acs_seg wr[1] = {span(ACS_RL_DEG, ACS_RL_LABEL)};
-            if (int rc = submit(ACS_K_RL_BROADPHASE, r, 1, wr, 1, cnt)) return rc;
+            return submit(ACS_K_RL_BROADPHASE, r, 1, wr, 1, cnt);
         }
-        {
+        if (k == 2) {
+            const acs_seg plan_seg = {(uint64_t)(uintptr_t)sc_->plan, 4ull * acs::rl_plan_ints(sc_->n)};
             const acs_seg r[1] = {span(ACS_RL_DEG, ACS_RL_LABEL)};
             const acs_seg wr[2] = {span(ACS_RL_LABEL, ACS_RL_END), plan_seg};
-            if (int rc = submit(ACS_K_RL_ISLANDS, r, 1, wr, 2, cnt)) return rc;
+            return submit(ACS_K_RL_ISLANDS, r, 1, wr, 2, cnt);
         }
         const acs_seg r[2] = {region(ACS_RL_P), region(ACS_RL_PERM)};
         const acs_seg wr[1] = {region(ACS_RL_Q0)};
@@ -56,35 +64,60 @@ public:
     // (iteration-major) and integrate
     int submit_tail(acs_rl_counts &cnt)
     {
+        if (int rc = tail_begin(cnt)) return rc;
+        for (int32_t it = 0; it < sc_->iters; it++)
+            if (int rc = submit_iteration(it, cnt)) return rc;
+        return submit_integrate(cnt);
+    }
+
+    // Reads and checks the island plan (once the islands kernel completed).
+    int tail_begin(acs_rl_counts &cnt)
+    {
         const int32_t *plan = (const int32_t *)sc_->plan;
         const int32_t nmulti = __atomic_load_n(&plan[1], __ATOMIC_ACQUIRE);
         if (nmulti < 0 || nmulti > sc_->n / 2) return ACS_EKERNEL;
+        for (int32_t k = 0; k < nmulti; k++) {
+            const int32_t b0 = plan[4 + 4 * k], b1 = plan[5 + 4 * k], e0 = plan[6 + 4 * k], e1 = plan[7 + 4 * k];
+            if (b0 < 0 || b1 > sc_->n || b1 - b0 < 2 || e0 < 0 || e1 < e0 || e1 > sc_->n * (sc_->n - 1))
+                return ACS_EKERNEL;   // a plan row the islands kernel cannot produce
+        }
+        nmulti_ = nmulti;
         cnt.steps++;
         cnt.islands += (uint64_t)plan[0];
         cnt.multi_islands += (uint64_t)nmulti;
         cnt.edges += (uint64_t)plan[2];
-        for (int32_t it = 0; it < sc_->iters; it++) {
-            const int src = (it % 2 == 0) ? ACS_RL_Q0 : ACS_RL_Q1, dst = (it % 2 == 0) ? ACS_RL_Q1 : ACS_RL_Q0;
-            for (int32_t k = 0; k < nmulti; k++) {
-                const int32_t b0 = plan[4 + 4 * k], b1 = plan[5 + 4 * k], e0 = plan[6 + 4 * k], e1 = plan[7 + 4 * k];
-                if (b0 < 0 || b1 > sc_->n || b1 - b0 < 2 || e0 < 0 || e1 < e0 || e1 > sc_->n * (sc_->n - 1))
-                    return ACS_EKERNEL;   // a plan row the islands kernel cannot produce
-                a_.iter = it;
-                a_.b0 = b0;
-                a_.b1 = b1;
-                const acs_seg r[3] = {vec(src, b0, b1), ints(ACS_RL_PADJ_OFF, b0, b1 + 1), ints(ACS_RL_PADJ, e0, e1)};
-                const acs_seg wr[1] = {vec(dst, b0, b1)};
-                if (int rc = submit(ACS_K_RL_JACOBI, r, 3, wr, 1, cnt)) return rc;
-                cnt.jacobi_kernels++;
-                cnt.jacobi_bodies += (uint64_t)(b1 - b0);
-                cnt.jacobi_edges += (uint64_t)(e1 - e0);
-            }
+        return ACS_OK;
+    }
+
+    // Jacobi iteration `it` over every multi-body island (after tail_begin)
+    int submit_iteration(int32_t it, acs_rl_counts &cnt)
+    {
+        const int32_t *plan = (const int32_t *)sc_->plan;
+        const int src = (it % 2 == 0) ? ACS_RL_Q0 : ACS_RL_Q1, dst = (it % 2 == 0) ? ACS_RL_Q1 : ACS_RL_Q0;
+        for (int32_t k = 0; k < nmulti_; k++) {
+            const int32_t b0 = plan[4 + 4 * k], b1 = plan[5 + 4 * k], e0 = plan[6 + 4 * k], e1 = plan[7 + 4 * k];
+            a_.iter = it;
+            a_.b0 = b0;
+            a_.b1 = b1;
+            const acs_seg r[3] = {vec(src, b0, b1), ints(ACS_RL_PADJ_OFF, b0, b1 + 1), ints(ACS_RL_PADJ, e0, e1)};
+            const acs_seg wr[1] = {vec(dst, b0, b1)};
+            if (int rc = submit(ACS_K_RL_JACOBI, r, 3, wr, 1, cnt)) return rc;
+            cnt.jacobi_kernels++;
+            cnt.jacobi_bodies += (uint64_t)(b1 - b0);
+            cnt.jacobi_edges += (uint64_t)(e1 - e0);
         }
+        return ACS_OK;
+    }
+
+    int submit_integrate(acs_rl_counts &cnt)
+    {
         a_.iter = a_.b0 = a_.b1 = 0;
         const acs_seg r[4] = {region(ACS_RL_P), region(ACS_RL_V), region(ACS_RL_Q0), region(ACS_RL_INV_PERM)};
         const acs_seg wr[2] = {region(ACS_RL_X), region(ACS_RL_V)};
         return submit(ACS_K_RL_INTEGRATE, r, 4, wr, 2, cnt);
     }
+
+    int32_t iters() const { return sc_->iters; }
 
 private:
     acs_seg region(int r) const { return acs_seg{sc_->arena + off_[r], off_[r + 1] - off_[r]}; }
@@ -109,6 +142,7 @@ private:
     const acs_rl_scene *sc_;
     uint64_t off_[ACS_RL_NREGIONS];
     acs_args_rl a_;
+    int32_t nmulti_ = 0;
 };
 
 // Submits one inference of the gated network into window group `group`

@@ -23,11 +23,10 @@ int HostWindow::admit()
         Desc &d = slots_[slot];
         d = fifo_.front();
         fifo_.pop_front();
-        uint64_t up = 0;
-        for (uint64_t m = valid_; m; m &= m - 1) {
-            const int32_t i = __builtin_ctzll(m);
-            if (descs_conflict(slots_[i], d, &tests_)) up |= 1ull << i;
-        }
+        // every occupied slot at once (column = slot)
+        tests_ += table_.pair_tests(valid_, d);
+        const uint64_t up = table_.conflicts(valid_, d);
+        table_.put(slot, d);
         bool bad = poison_all_;
         for (size_t k = 0; k < failed_.size() && !bad; k++) bad = descs_conflict(failed_[k], d, &tests_);
         if (trace_on_ && d.seq < trace_cap_) {

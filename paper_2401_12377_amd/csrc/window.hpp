@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "segtable.hpp"
 
 namespace acs {
 
@@ -51,6 +52,7 @@ private:
     size_t fifo_cap_;
     std::deque<Desc> fifo_;
     Desc slots_[ACS_W_MAX];
+    SegTable table_;                  // each slot's ranges by position, for the conflict tests
     uint64_t up_[ACS_W_MAX] = {};
     uint64_t valid_ = 0, exec_ = 0, poison_ = 0;
     uint64_t ev_ = 0, tests_ = 0, n_poisoned_ = 0, n_retired_ = 0, n_dispatched_ = 0;

@@ -4,6 +4,7 @@
 // arguments, which bytes each kernel reads and writes.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <chrono>
 #include <vector>
 
@@ -69,17 +70,30 @@ int acs_rl_run_batch(acs_window *w, const acs_rl_scene *scenes, int32_t n_scenes
         if (!scene_ok(&scenes[i])) return ACS_EINVAL;
         st.emplace_back(w, i % n_groups, &scenes[i]);
     }
+    int32_t max_iters = 0;
+    for (auto &s : st) max_iters = std::max(max_iters, s.iters());
     acs_rl_counts cnt = {};
     for (int32_t step = 0; step < steps; step++) {
         const double t0 = wall_ns();
-        for (auto &s : st)
-            if (int rc = s.submit_prefix(cnt)) return rc;
+        // Scenes are independent, so their kernels may come in any
+        // interleaving; stage by stage across the scenes puts kernels of
+        // different scenes next to each other in the window, all ready.
+        for (int k = 0; k < 4; k++)
+            for (auto &s : st)
+                if (int rc = s.submit_stage(k, cnt)) return rc;
         // group by group: once a group has drained, its scenes' plans are
-        // readable; the other groups keep running meanwhile
+        // readable; the other groups keep running meanwhile.  Jacobi
+        // iteration by iteration across the group's scenes, then integrate.
         for (int32_t g = 0; g < n_groups; g++) {
             if (int rc = acs_sync_group(w, g, 0)) return rc;
             for (int32_t i = g; i < n_scenes; i += n_groups)
-                if (int rc = st[(size_t)i].submit_tail(cnt)) return rc;
+                if (int rc = st[(size_t)i].tail_begin(cnt)) return rc;
+            for (int32_t it = 0; it < max_iters; it++)
+                for (int32_t i = g; i < n_scenes; i += n_groups)
+                    if (it < st[(size_t)i].iters())
+                        if (int rc = st[(size_t)i].submit_iteration(it, cnt)) return rc;
+            for (int32_t i = g; i < n_scenes; i += n_groups)
+                if (int rc = st[(size_t)i].submit_integrate(cnt)) return rc;
         }
         if (step == steps - 1 || step_ns) {
             if (int rc = acs_sync(w)) return rc;

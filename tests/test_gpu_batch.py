@@ -61,20 +61,28 @@ def test_batch_matches_solo_oracle(torch, path, G, W, hc):
     refs = [O.Scene.from_inputs(sc) for sc in scs]
     # the oracle's kernel streams, in the order the driver submits them
     streams = {g: [] for g in range(G)}
+    def put(i, k):
+        refs[i].run_kernel(*k)
+        streams[i % G].append(shifted(refs[i].access(*k), (i + 1) << 46))
+
     for step in range(steps):
-        tails = []
-        for i, ref in enumerate(refs):
-            g = i % G
-            pre = [(O.RL_PREDICT, 0, 0), (O.RL_BROADPHASE, 0, 0), (O.RL_ISLANDS, 0, 0), (O.RL_PERMUTE, 0, 0)]
-            for k in pre:
-                ref.run_kernel(*k)
-                streams[g].append(shifted(ref.access(*k), (i + 1) << 46))
-            tails.append(ref.step_kernels()[4:])
+        # stage by stage across the scenes
+        for k in [(O.RL_PREDICT, 0, 0), (O.RL_BROADPHASE, 0, 0), (O.RL_ISLANDS, 0, 0), (O.RL_PERMUTE, 0, 0)]:
+            for i in range(len(refs)):
+                put(i, k)
+        tails = [ref.step_kernels()[4:] for ref in refs]
+        # per group: Jacobi iteration by iteration across its scenes, then integrate
         for g in range(G):
-            for i in range(g, len(refs), G):
+            mine = range(g, len(refs), G)
+            for it in range(max(refs[i].c.iters for i in mine)):
+                for i in mine:
+                    for k in tails[i]:
+                        if k[0] == O.RL_JACOBI and k[2] == it:
+                            put(i, k)
+            for i in mine:
                 for k in tails[i]:
-                    refs[i].run_kernel(*k)
-                    streams[g].append(shifted(refs[i].access(*k), (i + 1) << 46))
+                    if k[0] != O.RL_JACOBI:
+                        put(i, k)
     for i, (g_, ref) in enumerate(zip(gpu, refs)):
         assert np.array_equal(bits(g_.get(acs.RL_X)), bits(ref.X)), i
         assert np.array_equal(bits(g_.get(acs.RL_V)), bits(ref.V)), i
@@ -109,15 +117,17 @@ def test_group_sync_and_validation(torch):
         assert w.stats()["retired"] == counts["kernels"]
 
 
-@pytest.mark.parametrize("G,W,wg", [(1, 16, 2), (4, 16, 1)])
-def test_full_size_batch_matches_oracle(torch, G, W, wg):
+@pytest.mark.parametrize("G,W,wg,hc,qd", [(1, 16, 2, 0, 4096), (4, 16, 1, 0, 4096),
+                                          (1, 32, 1, 32, 256),     # the configuration the autotuner picks
+                                          (1, 32, 1, 0, 1024)])
+def test_full_size_batch_matches_oracle(torch, G, W, wg, hc, qd):
     """The batched workload at full size (256 scenes of 16-512 bodies, 20
     steps, one persistent launch): every scene's final state bit-identical to
     the oracle's program-order run of that scene alone."""
     scs = inputs.batched_scenes(3, 256)
     gpu = [acs.RLSceneGPU(sc) for sc in scs]
-    say(f"full batch G={G} W={W} wg={wg}")
-    with acs.Window(W, path="device", n_groups=G, wg_per_task=wg) as w:
+    say(f"full batch G={G} W={W} wg={wg} host_check={hc} queue={qd}")
+    with acs.Window(W, path="device", n_groups=G, wg_per_task=wg, host_check_depth=hc, queue_depth=qd) as w:
         counts, _ = acs.rl_run_batch(w, gpu, 20, n_groups=G)
     assert counts["steps"] == 20 * 256
     for i, (g, sc) in enumerate(zip(gpu, scs)):
