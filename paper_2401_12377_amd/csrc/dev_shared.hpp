@@ -18,35 +18,46 @@ constexpr int kSegs = ACS_K_MAX;
 // and dependency distances are kept in that numbering.  The FIFO wave copies
 // every descriptor, as the host wrote it, into the device-memory ring the
 // workers read (DevState::dring, at its group and gseq), and stages it in
-// LDS for the window.
+// LDS for the window.  Everything the window and the workers need when the
+// host makes the dependency checks sits in the first 128 bytes, the ranges
+// (needed only by checks on the device) in the last 128: in host-check mode
+// only the first half crosses from host memory.
 struct DevDesc {
     uint64_t seq;           // submission index over all groups (traces)
     int32_t kid;
     uint32_t npieces;
-    uint32_t nseg;          // segments in use (reads and writes)
-    uint32_t wbits;         // bit k set: segment k is a write
-    uint64_t s[kSegs];
-    uint64_t e[kSegs];
-    uint8_t args[ACS_ARGS_MAX];
     uint32_t gseq;          // index of the kernel within its window group
     uint32_t group;
-    uint64_t pad0;
     // bit b set: the kernel of the same group with gseq - 1 - b conflicts
     // with this one.  Written by the host (host-check mode), by a check wave
     // into the staged copy (the window then writes it into the ring), or by
     // the window wave after its own checks.
     uint64_t host_up;
-    uint32_t pad[4];
+    uint8_t args[ACS_ARGS_MAX];
+    uint32_t nseg;          // segments in use (reads and writes)
+    uint32_t wbits;         // bit k set: segment k is a write
+    uint32_t pad[6];
+    uint64_t s[kSegs];
+    uint64_t e[kSegs];
 };
 static_assert(sizeof(DevDesc) == 256, "descriptor must be 256 bytes");
-static_assert(offsetof(DevDesc, host_up) == 232, "host_up is dwords 58 and 59 of the descriptor");
-static_assert(offsetof(DevDesc, gseq) == 216 && offsetof(DevDesc, group) == 220, "gseq and group are dwords 54, 55");
-constexpr int kHostUpDword = 58;
-constexpr int kGseqDword = 54;
-constexpr int kSegStartDword = 6;          // s[k] is dwords 6 + 2k and 7 + 2k
-constexpr int kSegEndDword = 22;           // e[k] is dwords 22 + 2k and 23 + 2k
+constexpr int kKidDword = 2;
+constexpr int kNpiecesDword = 3;
+constexpr int kGseqDword = 4;
+constexpr int kHostUpDword = 6;
+constexpr int kNsegDword = 24;
+constexpr int kWbitsDword = 25;
+constexpr int kSegStartDword = 32;         // s[k] is dwords 32 + 2k and 33 + 2k
+constexpr int kSegEndDword = 48;           // e[k] is dwords 48 + 2k and 49 + 2k
+constexpr uint32_t kDescHeadBytes = 128;   // what the window and workers read
+static_assert(offsetof(DevDesc, kid) == 4 * kKidDword && offsetof(DevDesc, npieces) == 4 * kNpiecesDword &&
+                  offsetof(DevDesc, gseq) == 4 * kGseqDword && offsetof(DevDesc, host_up) == 4 * kHostUpDword &&
+                  offsetof(DevDesc, nseg) == 4 * kNsegDword && offsetof(DevDesc, wbits) == 4 * kWbitsDword,
+              "descriptor dwords");
 static_assert(offsetof(DevDesc, s) == 4 * kSegStartDword && offsetof(DevDesc, e) == 4 * kSegEndDword,
               "segment dwords");
+static_assert(offsetof(DevDesc, args) + ACS_ARGS_MAX <= kDescHeadBytes && offsetof(DevDesc, s) == kDescHeadBytes,
+              "the head holds everything but the ranges");
 
 constexpr int kMaxGroups = 8;   // independent windows served by one window wave
 

@@ -211,7 +211,8 @@ public:
         tmp.gseq = (uint32_t)submitted_[g];   // the group's own numbering, without gaps
         tmp.group = (uint32_t)g;
         if (hc_ > 0) tmp.host_up = host_check(d);
-        memcpy((void *)&r, &tmp, sizeof(DevDesc));
+        // with the checks on the host the device reads only the head
+        memcpy((void *)&r, &tmp, hc_ > 0 ? (size_t)kDescHeadBytes : sizeof(DevDesc));
         submitted_[g]++;
         total_submitted_++;
         __atomic_store_n(&ctrl_->tail[g], submitted_[g], __ATOMIC_RELEASE);

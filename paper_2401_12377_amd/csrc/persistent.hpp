@@ -169,10 +169,10 @@ __device__ inline uint64_t history_check(DevDesc *d, SeqHistory &h, uint32_t lan
         ne[m] = d->e[m];
     }
     const uint32_t gq = readlane32(dw, kGseqDword);
-    const uint32_t nraw = readlane32(dw, 4);
+    const uint32_t nraw = readlane32(dw, kNsegDword);
     const uint32_t nseg = nraw < (uint32_t)kSegs ? nraw : (uint32_t)kSegs;
     const uint32_t segmask = (1u << nseg) - 1u;
-    const uint32_t wb = readlane32(dw, 5) & segmask;
+    const uint32_t wb = readlane32(dw, kWbitsDword) & segmask;
     const uint32_t wtop = wb ? 32u - (uint32_t)__builtin_clz(wb) : 0u;
     // The new ranges are the broadcast values above (no readlane per range);
     // positions beyond any kernel's count so far hold [0, 0) everywhere and
@@ -236,7 +236,13 @@ __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
     ACS_GAS DevState *const st = gp(p.st);
     // one window: a constant, so that ring positions are a mask, not a division
     const uint32_t depth = NG == 1 ? kLdsDescs : lds_depth(G), ring_cap = p.ring_mask + 1;
-    constexpr uint32_t kRows = 8, kJobs = kRows * 4;   // descriptors per copy round
+    // With the checks on the host only each descriptor's first half is
+    // copied (8 chunks of 16 bytes instead of 16): 8 descriptors per row of
+    // the wave instead of 4.
+    const bool half = NG == 1 && p.host_check > 0 && p.check_wave == 0;
+    const uint32_t lgc = half ? 3u : 4u;           // log2 of the 16-byte chunks copied per descriptor
+    constexpr uint32_t kRows = 8;
+    const uint32_t jobs = kRows << (6u - lgc);     // descriptors per copy round
     uint64_t consumed[NG], htail[NG], told[NG];
     uint32_t ftail[NG];
 #pragma unroll
@@ -278,19 +284,19 @@ __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
                 const uint32_t space = depth - (ftail[g] - freed);
                 const uint64_t avail = htail[g] - consumed[g];
                 uint32_t n = avail < space ? (uint32_t)avail : space;
-                if (n > kJobs - total) n = kJobs - total;
+                if (n > jobs - total) n = jobs - total;
                 cnt[g] = n;
                 total += n;
             }
         }
-        // 16 bytes per lane per row: lane l of row r copies chunk l % 16 of
-        // job 4r + l / 16
+        // 16 bytes per lane per row: lane l of row r copies chunk l % c of
+        // job (64 / c) r + l / c, c = the chunks copied per descriptor
         uint4 v[kRows];
         uint32_t dst_off[kRows];
         ACS_GAS uint64_t *ddst[kRows];   // the chunk's place in the device descriptor ring
 #pragma unroll
         for (int r = 0; r < (int)kRows; r++) {
-            const uint32_t j = (uint32_t)r * 4u + lane / 16u, c = lane % 16u;
+            const uint32_t j = ((uint32_t)r << (6u - lgc)) + (lane >> lgc), c = lane & ((1u << lgc) - 1u);
             uint32_t gg = 0, ii = 0, ft = 0;
             uint64_t cons = 0;
 #pragma unroll
@@ -651,9 +657,9 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                     const uint32_t dw = reinterpret_cast<const uint32_t *>(d)[lane];
                     const int slot = __builtin_ctzll(~valid & full);
                     const uint64_t bit = 1ull << slot;
-                    const uint32_t nraw = readlane32(dw, 4);
+                    const uint32_t nraw = readlane32(dw, kNsegDword);
                     const uint32_t nseg = nraw < (uint32_t)kSegs ? nraw : (uint32_t)kSegs;
-                    const uint32_t wb = readlane32(dw, 5);
+                    const uint32_t wb = readlane32(dw, kWbitsDword);
                     uint64_t hits;
                     if (valid & over4) hits = pair_hits<8, true>(d, nseg, wb, R, rep, ss, se, wmask);
                     else if (valid & over2) hits = pair_hits<4, true>(d, nseg, wb, R, rep, ss, se, wmask);
@@ -679,8 +685,8 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                     }
                     checks += (uint64_t)__builtin_popcountll(valid) * nseg * kSegs;
                     const uint64_t seq = readpair(dw, 0);
-                    const int32_t kid = (int32_t)readlane32(dw, 2);
-                    const uint32_t npr = readlane32(dw, 3);
+                    const int32_t kid = (int32_t)readlane32(dw, kKidDword);
+                    const uint32_t npr = readlane32(dw, kNpiecesDword);
                     if ((int)lane == slot) {
                         myseq = seq;
                         mykid = kid;
