@@ -140,7 +140,53 @@ def test_dag_paths_agree_and_schedules_valid(torch, dag, seed):
         assert np.array_equal(bits(out), bits(res["inorder"][0])), key
         for i, y in enumerate(ys):
             assert np.array_equal(bits(y), bits(res["inorder"][1][i])), (key, i)
-    assert np.allclose(res["device"][0].astype(np.float64), ref.out, rtol=1e-4, atol=1e-4 * np.abs(ref.out).max())
+    assert np.abs(res["device"][0].astype(np.float64) - ref.out).max() <= 1e-5 * np.abs(ref.out).max()
+
+
+@pytest.mark.parametrize("kw", [{}, {"host_check_depth": 16}])
+def test_dag_nodes_teacher_forced(torch, dag, kw):
+    """Every node of the randomly wired network on the device path against
+    the oracle, each fed the GPU's own inputs of that node: aggregations,
+    pool and head bit-exact (same FP32 operations in the same order), every
+    convolution within 1e-5 * max(|exact|, sum of |terms|) of the oracle's
+    float64 sum; and the logits of the whole run against the oracle's FP32
+    network."""
+    graph, wts = dag
+    x = inputs.dag_input(graph, 3)
+    net = acs.DAGGPU(graph, wts)
+    net.set_input(x)
+    say(f"dag teacher-forced {kw}")
+    with acs.Window(16, path="device", **kw) as w:
+        acs.dag_submit(w, net)
+        assert w.sync_rc(SYNC_NS) == 0
+    ys = [t.cpu().numpy() for t in net.y]
+    aggs = [t.cpu().numpy() for t in net.agg]
+
+    def chain(srcs):
+        a = O.join(ys[srcs[0]], ys[srcs[1]] if len(srcs) > 1 else None)
+        for s in srcs[2:]:
+            a = O.join(a, ys[s])
+        return a
+
+    for i, ps in enumerate(graph.preds):
+        if ps:
+            assert np.array_equal(bits(aggs[i]), bits(chain(ps))), ("join", i)
+        inp = aggs[i] if ps else x
+        exact, mag = O.conv_f64(inp, wts.w[i], wts.b[i], 3, 1)
+        g = ys[i].astype(np.float64)
+        assert np.all(np.isfinite(g)), i
+        assert np.all(np.abs(g - exact) <= 1e-5 * np.maximum(np.abs(exact), mag)), ("conv", i)
+    sink = net.sink.cpu().numpy()
+    assert np.array_equal(bits(sink), bits(chain(graph.sinks))), "sink"
+    pool = net.pool.cpu().numpy()
+    assert np.array_equal(bits(pool), bits(O.avgpool(sink))), "pool"
+    out = net.out.cpu().numpy()
+    assert np.array_equal(bits(out), bits(O.fc(pool, wts.fc_w, wts.fc_b))), "head"
+    ref = O.StaticDAG(graph, wts, x)
+    ref.run()
+    err = np.abs(out.astype(np.float64) - ref.out).max() / np.abs(ref.out).max()
+    say(f"dag logits: max |gpu - oracle| / max |oracle| = {err:.3e}")
+    assert err <= 1e-5
 
 
 def test_dag_graph_replays(torch, dag):

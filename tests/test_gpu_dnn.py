@@ -8,8 +8,8 @@ Bars:
   oracle (same FP32 operations in the same order);
 * whole inferences: bit-identical across the in-order, plain and device
   paths; the device and plain schedules pass the oracle's trace checker with
-  the oracle's own dataflow ranges; the logits agree with the oracle's FP32
-  network to the FP32 propagation level.
+  the oracle's own dataflow ranges; the logits within 1e-5 of the largest
+  logit of the oracle's FP32 network.
 """
 import sys
 
@@ -167,7 +167,9 @@ def test_inference_paths_agree_and_schedules_valid(torch, model, seed):
         if not ref.g3[c]:
             assert np.all(np.isnan(results["device"][f"t3_{c}"]))
     out = results["device"]["out"].astype(np.float64)
-    assert np.allclose(out, ref.out, rtol=1e-4, atol=1e-4 * np.abs(ref.out).max())
+    err = np.abs(out - ref.out).max() / np.abs(ref.out).max()
+    say(f"dnn logits seed={seed}: max |gpu - oracle| / max |oracle| = {err:.3e}")
+    assert err <= 1e-5
 
 
 def test_many_inferences_one_window(torch, model):
