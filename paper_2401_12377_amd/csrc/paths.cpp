@@ -4,6 +4,7 @@
 
 #include <chrono>
 #include <thread>
+#include <deque>
 #include <vector>
 
 #include "internal.hpp"
@@ -266,10 +267,25 @@ private:
 };
 
 // ---------------------------------------------------------------------------
-// plain path: host window, ready kernels launched into a pool of streams
-// (one kernel per stream at a time), completions seen through events
+// plain path: host window feeding a pool of streams (the ACS-SW structure of
+// Section IV-B).  A ready kernel goes to an idle stream, else to the stream
+// with the shortest queue; a pending kernel whose upstream kernels are all
+// executing in one stream goes into that stream at once (stream order keeps
+// the edge).  Completions are seen through events, recorded only when a
+// completion is needed: when the window is full with kernels waiting in the
+// FIFO, when some kernel could not be handed out, or on a drain.  An event
+// after the last kernel of a stream marks every kernel before it (in trace
+// mode every kernel gets its own pair, for the execution intervals).  Every
+// other kernel costs one launch, as on the in-order stream.
 // ---------------------------------------------------------------------------
 class PlainPath : public Path {
+    static constexpr size_t kDepth = ACS_W_MAX;   // kernels per stream (no window holds more)
+    struct InFlight {
+        int32_t slot;
+        int32_t ev;    // event index marking the end of this kernel, or -1 (a later entry's covers it)
+        int32_t beg;   // trace mode: event index before the kernel, else -1
+    };
+
 public:
     PlainPath(int32_t W, const acs_config &cfg)
         : cfg_(cfg), win_(W, (size_t)cfg.queue_depth, cfg.trace != 0, (size_t)cfg.trace_capacity)
@@ -282,21 +298,24 @@ public:
         if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
         const int S = cfg_.n_streams;
         streams_.assign(S, nullptr);
-        done_.assign(S, nullptr);
-        begin_.assign(S, nullptr);
-        busy_.assign(S, -1);
-        const unsigned flags = cfg_.trace ? hipEventDefault : hipEventDisableTiming;
-        for (int s = 0; s < S; s++) {
+        q_.assign(S, {});
+        for (int s = 0; s < S; s++)
             if ((e = hipStreamCreateWithFlags(&streams_[s], hipStreamNonBlocking)) != hipSuccess)
                 return hip_fail(e, "hipStreamCreate");
-            if ((e = hipEventCreateWithFlags(&done_[s], flags)) != hipSuccess) return hip_fail(e, "hipEventCreate");
-            if (cfg_.trace && (e = hipEventCreate(&begin_[s])) != hipSuccess) return hip_fail(e, "hipEventCreate");
+        // enough events for every kernel in flight (two each with a trace)
+        const unsigned flags = cfg_.trace ? hipEventDefault : hipEventDisableTiming;
+        const size_t nev = 2 * (size_t)ACS_W_MAX + 2;   // at most two per kernel in flight
+        events_.assign(nev, nullptr);
+        for (size_t k = 0; k < nev; k++) {
+            if ((e = hipEventCreateWithFlags(&events_[k], flags)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+            free_ev_.push_back((int32_t)k);
         }
         if (cfg_.trace) {
             if ((e = hipEventCreate(&base_)) != hipSuccess) return hip_fail(e, "hipEventCreate");
             if ((e = hipEventRecord(base_, streams_[0])) != hipSuccess) return hip_fail(e, "hipEventRecord");
             (void)hipEventSynchronize(base_);
         }
+        for (int32_t k = 0; k < ACS_W_MAX; k++) stream_of_[k] = -1;
         started_ = true;
         return ACS_OK;
     }
@@ -322,7 +341,7 @@ public:
     {
         const uint64_t t0 = now_ns();
         while (!win_.drained()) {
-            progress();
+            progress(true);
             if (win_.drained()) break;
             if (timeout_ns && now_ns() - t0 > timeout_ns) {
                 set_error(ACS_ETIMEDOUT, "sync timed out");
@@ -336,7 +355,7 @@ public:
     int poll() override
     {
         if (!started_) return ACS_OK;
-        progress();
+        progress(true);   // a caller that polls waits for completions
         if (dev_err_) return dev_err_;
         return win_.first_error() ? ACS_EKERNEL : ACS_OK;
     }
@@ -353,13 +372,15 @@ public:
     {
         if (!started_) return ACS_OK;
         sync(0);
-        for (size_t s = 0; s < streams_.size(); s++) {
+        for (size_t s = 0; s < streams_.size(); s++)
             if (streams_[s]) (void)hipStreamDestroy(streams_[s]);
-            if (done_[s]) (void)hipEventDestroy(done_[s]);
-            if (begin_[s]) (void)hipEventDestroy(begin_[s]);
-        }
+        for (hipEvent_t ev : events_)
+            if (ev) (void)hipEventDestroy(ev);
         if (base_) (void)hipEventDestroy(base_);
         streams_.clear();
+        events_.clear();
+        free_ev_.clear();
+        q_.clear();
         base_ = nullptr;
         started_ = false;
         return ACS_OK;
@@ -374,82 +395,160 @@ public:
     }
 
 private:
-    // One pass of the window module and the scheduler module: retire what
-    // finished, admit from the FIFO, launch ready kernels into free streams.
-    void progress()
+    int32_t take_event()
     {
-        for (size_t s = 0; s < streams_.size(); s++) {
-            if (busy_[s] < 0) continue;
-            const hipError_t q = hipEventQuery(done_[s]);
-            if (q == hipErrorNotReady) continue;
+        const int32_t k = free_ev_.back();
+        free_ev_.pop_back();
+        return k;
+    }
+
+    // Retires the front kernels of stream s up to and including the first
+    // one whose end event has fired; false when none has.
+    bool retire_front(size_t s)
+    {
+        auto &q = q_[s];
+        size_t upto = 0;
+        hipError_t q_err = hipSuccess;
+        bool fired = false;
+        for (size_t k = 0; k < q.size(); k++) {
+            if (q[k].ev < 0) continue;
+            const hipError_t r = hipEventQuery(events_[(size_t)q[k].ev]);
+            if (r == hipErrorNotReady) break;
+            fired = true;
+            q_err = r;
+            upto = k + 1;
+        }
+        if (!fired) return false;
+        for (size_t k = 0; k < upto; k++) {
+            const InFlight f = q.front();
+            q.pop_front();
             int64_t ta = -1, tb = -1;
-            if (cfg_.trace) {
+            if (cfg_.trace && f.beg >= 0 && f.ev >= 0) {
                 float a = 0, b = 0;
-                (void)hipEventElapsedTime(&a, base_, begin_[s]);
-                (void)hipEventElapsedTime(&b, base_, done_[s]);
+                (void)hipEventElapsedTime(&a, base_, events_[(size_t)f.beg]);
+                (void)hipEventElapsedTime(&b, base_, events_[(size_t)f.ev]);
                 ta = (int64_t)((double)a * 1e6);
                 tb = (int64_t)((double)b * 1e6);
             }
             int32_t status = 0;
-            if (q != hipSuccess) {
+            if (q_err != hipSuccess) {
                 status = ACS_EDEVICE;
                 if (!dev_err_) dev_err_ = ACS_EDEVICE;
-                hip_fail(q, "kernel");
+                hip_fail(q_err, "kernel");
             }
-            win_.retire(busy_[s], status, ta, tb);
-            busy_[s] = -1;
+            if (f.ev >= 0) free_ev_.push_back(f.ev);
+            if (f.beg >= 0) free_ev_.push_back(f.beg);
+            stream_of_[f.slot] = -1;
+            win_.retire(f.slot, status, ta, tb);
         }
+        return true;
+    }
+
+    // Launches the kernel of `slot` into stream s; false on a launch error
+    // (the kernel is then retired as failed).
+    bool launch_into(int32_t slot, size_t s)
+    {
+        const Desc &d = win_.slot_desc(slot);
+        InFlight f{slot, -1, -1};
+        if (cfg_.trace) {
+            f.beg = take_event();
+            (void)hipEventRecord(events_[(size_t)f.beg], streams_[s]);
+        }
+        const hipError_t e = launch_task(d.kid, d.args, d.npieces, streams_[s]);
+        win_.mark_executing(slot);
+        if (e != hipSuccess) {
+            hip_fail(e, "kernel launch");
+            if (!dev_err_) dev_err_ = ACS_EDEVICE;
+            if (f.beg >= 0) free_ev_.push_back(f.beg);
+            win_.retire(slot, ACS_EDEVICE);
+            return false;
+        }
+        if (cfg_.trace) {
+            f.ev = take_event();
+            (void)hipEventRecord(events_[(size_t)f.ev], streams_[s]);
+        }
+        stream_of_[slot] = (int32_t)s;
+        q_[s].push_back(f);
+        return true;
+    }
+
+    // One pass of the window module and the scheduler module: retire what
+    // finished, admit from the FIFO, hand out what can run.
+    void progress(bool drain = false)
+    {
+        for (size_t s = 0; s < streams_.size(); s++)
+            if (!q_[s].empty()) retire_front(s);
         win_.admit();
-        int32_t ready[ACS_W_MAX];
+        bool blocked = false;   // some kernel could not be handed out
         for (;;) {
-            const int32_t k = win_.ready_slots(ready, ACS_W_MAX);
-            if (k == 0) break;
-            bool launched_any = false;
-            for (int32_t q = 0; q < k; q++) {
-                const int32_t slot = ready[q];
-                if (win_.poisoned(slot)) {
+            int32_t cand[ACS_W_MAX];
+            const int32_t k = win_.waiting_slots(cand, ACS_W_MAX);
+            bool any = false;
+            for (int32_t c = 0; c < k; c++) {
+                const int32_t slot = cand[c];
+                const uint64_t up = win_.upstream(slot);
+                if (up == 0 && win_.poisoned(slot)) {
                     win_.mark_executing(slot);
                     win_.retire(slot, 0);
-                    launched_any = true;
+                    any = true;
                     continue;
                 }
-                int32_t s = free_stream();
-                if (s < 0) return;
-                const Desc &d = win_.slot_desc(slot);
-                if (cfg_.trace) (void)hipEventRecord(begin_[s], streams_[s]);
-                hipError_t e = launch_task(d.kid, d.args, d.npieces, streams_[s]);
-                win_.mark_executing(slot);
-                if (e != hipSuccess) {
-                    hip_fail(e, "kernel launch");
-                    if (!dev_err_) dev_err_ = ACS_EDEVICE;
-                    win_.retire(slot, ACS_EDEVICE);
+                int32_t s = -1;
+                if (up == 0) {
+                    s = pick_stream();
+                } else if (!win_.poisoned(slot) && (up & ~win_.executing()) == 0) {
+                    // every upstream kernel runs: all in one stream?
+                    const int32_t s0 = stream_of_[__builtin_ctzll(up)];
+                    bool same = s0 >= 0;
+                    for (uint64_t m = up; m && same; m &= m - 1) same = stream_of_[__builtin_ctzll(m)] == s0;
+                    if (same && q_[(size_t)s0].size() < kDepth) s = s0;
+                }
+                if (s < 0) {
+                    blocked = true;
                     continue;
                 }
-                (void)hipEventRecord(done_[s], streams_[s]);
-                busy_[s] = slot;
-                launched_any = true;
+                launch_into(slot, (size_t)s);
+                any = true;
             }
-            if (!launched_any) break;
+            if (!any) break;
             win_.admit();
         }
+        // completions are needed: an end event behind each stream's last kernel
+        const bool need = drain || blocked || (win_.full() && !win_.fifo_empty());
+        if (need && !cfg_.trace)
+            for (size_t s = 0; s < streams_.size(); s++) {
+                if (q_[s].empty() || q_[s].back().ev >= 0) continue;
+                InFlight &last = q_[s].back();
+                last.ev = take_event();
+                (void)hipEventRecord(events_[(size_t)last.ev], streams_[s]);
+            }
     }
-    int32_t free_stream()
+
+    // an idle stream, else the least loaded one with room (-1 if none)
+    int32_t pick_stream()
     {
         const int32_t S = (int32_t)streams_.size();
+        int32_t best = -1;
         for (int32_t k = 0; k < S; k++) {
             const int32_t s = (rr_ + k) % S;
-            if (busy_[s] < 0) {
-                rr_ = (s + 1) % S;
-                return s;
+            const size_t len = q_[(size_t)s].size();
+            if (len == 0) {
+                best = s;
+                break;
             }
+            if (len < kDepth && (best < 0 || len < q_[(size_t)best].size())) best = s;
         }
-        return -1;
+        if (best >= 0) rr_ = (best + 1) % S;
+        return best;
     }
+
     acs_config cfg_;
     HostWindow win_;
     std::vector<hipStream_t> streams_;
-    std::vector<hipEvent_t> done_, begin_;
-    std::vector<int32_t> busy_;
+    std::vector<std::deque<InFlight>> q_;
+    std::vector<hipEvent_t> events_;
+    std::vector<int32_t> free_ev_;
+    int32_t stream_of_[ACS_W_MAX];
     hipEvent_t base_ = nullptr;
     int32_t rr_ = 0;
     int dev_err_ = ACS_OK;

@@ -66,6 +66,14 @@ int HostWindow::ready_slots(int32_t *out, int32_t cap) const
     return n;
 }
 
+int HostWindow::waiting_slots(int32_t *out, int32_t cap) const
+{
+    int32_t n = 0;
+    for (uint64_t m = valid_ & ~exec_; m && n < cap; m &= m - 1) out[n++] = __builtin_ctzll(m);
+    std::sort(out, out + n, [this](int32_t a, int32_t b) { return slots_[a].seq < slots_[b].seq; });
+    return n;
+}
+
 void HostWindow::mark_executing(int32_t slot)
 {
     exec_ |= 1ull << slot;

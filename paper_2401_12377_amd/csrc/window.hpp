@@ -19,6 +19,7 @@ public:
     bool fifo_empty() const { return fifo_.empty(); }
     void fifo_push(const Desc &d) { fifo_.push_back(d); }
     bool drained() const { return fifo_.empty() && valid_ == 0; }
+    bool full() const { return valid_ == ((W_ >= 64) ? ~0ull : ((1ull << W_) - 1ull)); }
 
     // a2 + a3: while a slot is free, moves the FIFO head into the lowest free
     // slot and computes its upstream mask against every occupied slot.
@@ -26,6 +27,10 @@ public:
 
     // Ready slots (valid, not executing, no upstream left), oldest first.
     int ready_slots(int32_t *out, int32_t cap) const;
+    // Slots not yet handed out (ready or pending), oldest first.
+    int waiting_slots(int32_t *out, int32_t cap) const;
+    // Slots this slot still waits for (in the window, not retired).
+    uint64_t upstream(int32_t slot) const { return up_[slot]; }
     bool poisoned(int32_t slot) const { return (poison_ >> slot) & 1ull; }
     void mark_executing(int32_t slot);
     // a6: frees the slot and clears it from every upstream mask.  A non-zero

@@ -134,7 +134,7 @@ def test_dag_paths_agree_and_schedules_valid(torch, dag, seed):
         assert n == len(ref.kernels())
         res[key] = (out, ys)
         if tr is not None:
-            code, msg = O.check_trace(accs, 16, tr, check_times=True, early=(path == "device"))
+            code, msg = O.check_trace(accs, 16, tr, check_times=True, early=True)
             assert code == 0, (key, msg)
     for key, (out, ys) in res.items():
         assert np.array_equal(bits(out), bits(res["inorder"][0])), key

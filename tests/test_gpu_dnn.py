@@ -157,7 +157,7 @@ def test_inference_paths_agree_and_schedules_valid(torch, model, seed):
         assert n == len(ref.kernels())
         results[path] = bufs
         if tr is not None:
-            code, msg = O.check_trace(accs, 16, tr, check_times=True, early=(path == "device"))
+            code, msg = O.check_trace(accs, 16, tr, check_times=True, early=True)
             assert code == 0, msg
     for path in ("plain", "device"):
         for key, v in results["inorder"].items():
