@@ -18,8 +18,10 @@
  *   ACS_PATH_INORDER  every kernel is launched at submit into one HIP stream;
  *                     no window.  The single-stream baseline of Section II.
  *   ACS_PATH_PLAIN    window checks on the host, ready kernels launched into a
- *                     pool of HIP streams, one kernel per stream at a time,
- *                     completions seen through HIP events (Section IV-B).
+ *                     pool of HIP streams (Section IV-B); a kernel whose
+ *                     upstream kernels all run in one stream is launched into
+ *                     that stream at once; completions seen through HIP events
+ *                     recorded when a completion is needed.
  *   ACS_PATH_DEVICE   window held on the GPU by a persistent scheduler kernel:
  *                     one wavefront keeps one window slot per lane, tests the
  *                     overlaps, builds the ready mask with a ballot and
@@ -186,7 +188,9 @@ int acs_window_configure(acs_window *w, const acs_config *cfg);
 int acs_window_configure_noalloc(acs_window *w, const acs_config *cfg, void *host_mem, uint64_t host_bytes,
                                  void *stream);
 
-/* Submits one kernel in program order.
+/* Submits one kernel in program order (Section III-D: kernels enter the
+ * input FIFO and then the window in submission order; Section IV-A: the
+ * kernel wrapper states the ranges its launch arguments touch).
  *   kernel_id   task type from acs_tasks.h (the body the library runs).
  *   read_segs   n_read byte ranges the kernel reads; write_segs likewise.
  *               Beyond ACS_K_MAX segments in total, neighbouring ranges of the
@@ -202,11 +206,14 @@ int acs_submit(acs_window *w, int32_t kernel_id,
                const acs_seg *write_segs, int32_t n_write,
                const void *args, size_t args_size, uint64_t *seq_out);
 
-/* Waits until every submitted kernel has completed.  Returns the first
+/* Waits until every submitted kernel has completed: the FIFO and the window
+ * are empty, every kernel retired (Section III-C, retirement frees a slot;
+ * the program's synchronisation point of Section IV-B).  Returns the first
  * sticky asynchronous error (ACS_EKERNEL, ACS_EDEVICE) if there was one. */
 int acs_sync(acs_window *w);
 
-/* As acs_sync but gives up after timeout_ns nanoseconds (ACS_ETIMEDOUT). */
+/* As acs_sync (Section III-C, IV-B) but gives up after timeout_ns
+ * nanoseconds (ACS_ETIMEDOUT); the window stays usable. */
 int acs_sync_timeout(acs_window *w, uint64_t timeout_ns);
 
 /* Window groups, for many independent task graphs in one launch.  With
@@ -275,8 +282,11 @@ int acs_stats_get(acs_window *w, acs_stats *out);
  * readable; further submits fail with ACS_ESTATE.  Returns the acs_sync status. */
 int acs_window_stop(acs_window *w);
 
-/* Waits for outstanding work, stops the persistent kernel if any, frees
- * everything the library owns.  Returns the final acs_sync status. */
+/* Waits for outstanding work (as acs_sync, Section III-C), stops the
+ * persistent kernel if any, frees everything the library owns (a window
+ * configured without allocation releases its device's static state and
+ * leaves the caller's memory and stream alone).  NULL is accepted.
+ * Returns the final acs_sync status. */
 int acs_window_destroy(acs_window *w);
 
 /* Manual path only: moves up to cap ready kernels (oldest first) to the
