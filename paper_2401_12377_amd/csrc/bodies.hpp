@@ -400,10 +400,26 @@ __device__ inline void body_rl_broadphase(const acs_args_rl &a, uint8_t *smem)
         if (t == 0) put<DEV>(&v.adj_off[n], total);
         return;
     }
+    // Partners in blocks of 8: the eight LDS loads of a block are issued
+    // together (all lanes read the same partner, a broadcast), so their
+    // latency is paid once per block; each block's contacts become a byte
+    // mask, counted in the first pass and walked in index order in the second.
+    auto block_mask = [&](const float4 &pi, int32_t i, int32_t j) -> uint32_t {
+        float4 q[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) q[u] = Ps[j + u];
+        uint32_t m = 0;
+#pragma unroll
+        for (int u = 0; u < 8; u++)
+            m |= (j + u != i && dist2(pi.x - q[u].x, pi.y - q[u].y, pi.z - q[u].z) < thr) ? (1u << u) : 0u;
+        return m;
+    };
+    const int32_t n8 = n & ~7;
     for (int32_t i = t; i < n; i += ACS_BLOCK) {
         const float4 pi = Ps[i];
         int32_t c = 0;
-        for (int32_t j = 0; j < n; j++) {
+        for (int32_t j = 0; j < n8; j += 8) c += __builtin_popcount(block_mask(pi, i, j));
+        for (int32_t j = n8; j < n; j++) {
             const float4 pj = Ps[j];
             c += (j != i && dist2(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z) < thr) ? 1 : 0;
         }
@@ -416,7 +432,9 @@ __device__ inline void body_rl_broadphase(const acs_args_rl &a, uint8_t *smem)
         put<DEV>(&v.adj_off[i], deg[i]);
         const float4 pi = Ps[i];
         int32_t k = deg[i];
-        for (int32_t j = 0; j < n; j++) {
+        for (int32_t j = 0; j < n8; j += 8)
+            for (uint32_t m = block_mask(pi, i, j); m; m &= m - 1) put<DEV>(&v.adj[k++], j + __builtin_ctz(m));
+        for (int32_t j = n8; j < n; j++) {
             const float4 pj = Ps[j];
             if (j != i && dist2(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z) < thr) put<DEV>(&v.adj[k++], j);
         }
@@ -590,6 +608,9 @@ __device__ inline void body_rl_islands(const acs_args_rl &a, uint8_t *smem)
         __syncthreads();
         A = adjs;
     }
+    // Labels only ever move to a smaller body of the same component, and a
+    // label's own label is taken too (a pointer jump), so the chains of
+    // labels shorten geometrically; the fixpoint is the component minimum.
     for (;;) {
         int changed = 0;
         for (int32_t i = t; i < n; i += ACS_BLOCK) {
@@ -601,6 +622,8 @@ __device__ inline void body_rl_islands(const acs_args_rl &a, uint8_t *smem)
                 int32_t l = __hip_atomic_load(&lab[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 m = l < m ? l : m;
             }
+            const int32_t jm = __hip_atomic_load(&lab[m], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            m = jm < m ? jm : m;
             if (m < own) {
                 __hip_atomic_store(&lab[i], m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 changed = 1;
@@ -620,17 +643,39 @@ __device__ inline void body_rl_islands(const acs_args_rl &a, uint8_t *smem)
     if (t == 0) sz[nisl] = n;
     __syncthreads();
     for (int32_t k = t; k <= nisl; k += ACS_BLOCK) put<DEV>(&v.isl_off[k], sz[k]);
-    // position of each body: island start + members before it
-    for (int32_t i = t; i < n; i += ACS_BLOCK) {
-        const int32_t root = lab[i];
-        int32_t rank = 0;
-        for (int32_t j = root; j < i; j++) rank += (lab[j] == root) ? 1 : 0;
-        const int32_t pos = sz[ridx[root]] + rank;
-        perm[pos] = i;
-        inv[i] = pos;
-        put<DEV>(&v.label[i], root);
-        put<DEV>(&v.perm[pos], i);
-        put<DEV>(&v.inv_perm[i], pos);
+    // Positions: bodies ordered by (label, index), islands in label order and
+    // bodies in index order inside each.  A bitonic sort of the keys
+    // label * 2048 + index (n <= 1024), padded to a power of two, in the
+    // perm and inv arrays (2n entries, at least the padded size).
+    int32_t P = 1;
+    while (P < n) P <<= 1;
+    int32_t *key = perm;
+    for (int32_t i = t; i < P; i += ACS_BLOCK) key[i] = i < n ? (lab[i] << 11) | i : 0x7FFFFFFF;
+    __syncthreads();
+    for (int32_t k = 2; k <= P; k <<= 1)
+        for (int32_t jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int32_t i = t; i < P; i += ACS_BLOCK) {
+                const int32_t l = i ^ jj;
+                if (l > i) {
+                    const int32_t a0 = key[i], a1 = key[l];
+                    const bool up = (i & k) == 0;
+                    if ((a0 > a1) == up) {
+                        key[i] = a1;
+                        key[l] = a0;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    // the n real keys sort first and name the body at each position; perm
+    // is rewritten in place, inv lands where only padding was
+    for (int32_t p = t; p < n; p += ACS_BLOCK) {
+        const int32_t i = key[p] & 2047;
+        perm[p] = i;
+        inv[i] = p;
+        put<DEV>(&v.label[i], lab[i]);
+        put<DEV>(&v.perm[p], i);
+        put<DEV>(&v.inv_perm[i], p);
     }
     __syncthreads();
     for (int32_t p = t; p < n; p += ACS_BLOCK) {
