@@ -400,46 +400,94 @@ __device__ inline void body_rl_broadphase(const acs_args_rl &a, uint8_t *smem)
         if (t == 0) put<DEV>(&v.adj_off[n], total);
         return;
     }
-    // Partners in blocks of 8: the eight LDS loads of a block are issued
-    // together (all lanes read the same partner, a broadcast), so their
-    // latency is paid once per block; each block's contacts become a byte
-    // mask, counted in the first pass and walked in index order in the second.
-    auto block_mask = [&](const float4 &pi, int32_t i, int32_t j) -> uint32_t {
-        float4 q[8];
-#pragma unroll
-        for (int u = 0; u < 8; u++) q[u] = Ps[j + u];
-        uint32_t m = 0;
-#pragma unroll
-        for (int u = 0; u < 8; u++)
-            m |= (j + u != i && dist2(pi.x - q[u].x, pi.y - q[u].y, pi.z - q[u].z) < thr) ? (1u << u) : 0u;
-        return m;
+    // Above 128 bodies: a uniform grid of cells a little wider than 2r (at
+    // most 12 per axis), so that a body's contacts lie in its own cell or
+    // the 26 around it (cell coordinates are clamped to the grid, which
+    // keeps two positions within 2r in neighbouring cells).  The contact
+    // test is the same expression as everywhere, so the contact set is the
+    // all-pairs one; each body's list is sorted into index order in LDS.
+    // Bodies whose lists do not fit in LDS go through the all-pairs walk.
+    const float cs = two_r * 1.0009765625f;
+    const float inv_cs = 1.0f / cs;
+    const int32_t C = (cs > 0.0f && inv_cs >= 1.0f) ? (inv_cs >= 12.0f ? 12 : (int32_t)inv_cs) : 1;
+    const int32_t NC = C * C * C;
+    int32_t *cstart = tmp + 4;            // NC + 1: bodies of cell c at sorted[cstart[c], cstart[c + 1])
+    int32_t *sorted = cstart + NC + 1;    // n
+    int32_t *cellof = sorted + n;         // n
+    int32_t *ladj = cellof + n;           // the sorted lists, while they fit
+    const int32_t lcap = (int32_t)(kBodySmem / 4) - (int32_t)(ladj - reinterpret_cast<int32_t *>(smem));
+    auto cell1 = [&](float x) -> int32_t {
+        const float f = fminf(fmaxf(x * inv_cs, 0.0f), (float)(C - 1));
+        return (int32_t)f;
     };
-    const int32_t n8 = n & ~7;
+    for (int32_t c = t; c <= NC; c += ACS_BLOCK) cstart[c] = 0;
+    __syncthreads();
     for (int32_t i = t; i < n; i += ACS_BLOCK) {
+        const float4 p = Ps[i];
+        const int32_t c = cell1(p.x) + C * (cell1(p.y) + C * cell1(p.z));
+        cellof[i] = c;
+        atomicAdd(&cstart[c], 1);
+    }
+    __syncthreads();
+    block_exclusive_scan(cstart, NC + 1, tmp);
+    // cstart[c] is now where cell c starts; place the bodies, then cstart[c]
+    // has moved to where cell c ends, which is where cell c + 1 starts
+    for (int32_t i = t; i < n; i += ACS_BLOCK) sorted[atomicAdd(&cstart[cellof[i]], 1)] = i;
+    __syncthreads();
+    // walks every partner of body i in the 27 cells around it
+    auto each_partner = [&](int32_t i, auto &&fn) {
         const float4 pi = Ps[i];
+        const int32_t c = cellof[i], cx = c % C, cy = (c / C) % C, cz = c / (C * C);
+        for (int32_t z = (cz > 0 ? cz - 1 : 0); z <= (cz < C - 1 ? cz + 1 : C - 1); z++)
+            for (int32_t y = (cy > 0 ? cy - 1 : 0); y <= (cy < C - 1 ? cy + 1 : C - 1); y++) {
+                const int32_t row = C * (y + C * z);
+                const int32_t x0 = cx > 0 ? cx - 1 : 0, x1 = cx < C - 1 ? cx + 1 : C - 1;
+                // cells x0..x1 of this row are contiguous in the sorted order
+                const int32_t k0 = row + x0 == 0 ? 0 : cstart[row + x0 - 1], k1 = cstart[row + x1];
+                for (int32_t k = k0; k < k1; k++) {
+                    const int32_t j = sorted[k];
+                    const float4 pj = Ps[j];
+                    if (j != i && dist2(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z) < thr) fn(j);
+                }
+            }
+    };
+    for (int32_t i = t; i < n; i += ACS_BLOCK) {
         int32_t c = 0;
-        for (int32_t j = 0; j < n8; j += 8) c += __builtin_popcount(block_mask(pi, i, j));
-        for (int32_t j = n8; j < n; j++) {
-            const float4 pj = Ps[j];
-            c += (j != i && dist2(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z) < thr) ? 1 : 0;
-        }
+        each_partner(i, [&](int32_t) { c++; });
         deg[i] = c;
         put<DEV>(&v.deg[i], c);
     }
     __syncthreads();
     const int32_t total = block_exclusive_scan(deg, n, tmp);
+    for (int32_t i = t; i < n; i += ACS_BLOCK) put<DEV>(&v.adj_off[i], deg[i]);
+    if (t == 0) put<DEV>(&v.adj_off[n], total);
+    if (total <= lcap) {
+        for (int32_t i = t; i < n; i += ACS_BLOCK) {
+            const int32_t o = deg[i];
+            int32_t k = o;
+            each_partner(i, [&](int32_t j) {
+                // insertion into the list so far, kept in index order
+                int32_t q = k++;
+                while (q > o && ladj[q - 1] > j) {
+                    ladj[q] = ladj[q - 1];
+                    q--;
+                }
+                ladj[q] = j;
+            });
+        }
+        __syncthreads();
+        for (int32_t k = t; k < total; k += ACS_BLOCK) put<DEV>(&v.adj[k], ladj[k]);
+        return;
+    }
+    // too many contacts for LDS: all partners in index order
     for (int32_t i = t; i < n; i += ACS_BLOCK) {
-        put<DEV>(&v.adj_off[i], deg[i]);
         const float4 pi = Ps[i];
         int32_t k = deg[i];
-        for (int32_t j = 0; j < n8; j += 8)
-            for (uint32_t m = block_mask(pi, i, j); m; m &= m - 1) put<DEV>(&v.adj[k++], j + __builtin_ctz(m));
-        for (int32_t j = n8; j < n; j++) {
+        for (int32_t j = 0; j < n; j++) {
             const float4 pj = Ps[j];
             if (j != i && dist2(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z) < thr) put<DEV>(&v.adj[k++], j);
         }
     }
-    if (t == 0) put<DEV>(&v.adj_off[n], total);
 }
 
 // Connected components by min-label propagation (the fixpoint labels every

@@ -140,7 +140,7 @@ def test_conv_tile_through_kernel_source(sim, h, cin, cout, k, s):
 @pytest.mark.timeout(180, method="thread")
 @pytest.mark.parametrize("n,radius", [(8, None), (33, None), (64, None), (80, None),
                                       (2, 0.01), (2, 0.3), (64, 0.01), (64, 0.3), (65, 0.3),
-                                      (137, None), (300, None), (257, 0.12)])
+                                      (137, None), (300, None), (257, 0.12), (700, 0.6), (1024, None)])
 def test_rl_prefix_through_kernel_source(sim, n, radius):
     """One RL step through the kernel source: predict, broadphase, islands
     and permute (the one-wave paths for at most 64 bodies, the workgroup
@@ -149,8 +149,9 @@ def test_rl_prefix_through_kernel_source(sim, n, radius):
     The edge scenes: the smallest scene, two bodies apart and touching, no
     contacts at all (every body an island of its own), one island of every
     body on either side of the one-wave limit, and scenes above 128 bodies
-    (partners in blocks of eight with a remainder, the sorted positions)
-    including one dense enough for long islands."""
+    (the cell grid, the sorted positions) including one dense enough for
+    long islands, one whose radius makes a single cell, and the largest
+    scene, whose lists do not fit in LDS (the all-pairs walk)."""
     sc = inputs.rl_scene(seed=11, n=n, radius=radius)
     off = acs.rl_layout(n)
     arena = np.zeros(int(off[acs.RL_END]), np.uint8)
