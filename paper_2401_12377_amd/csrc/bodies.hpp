@@ -656,29 +656,47 @@ __device__ inline void body_rl_islands(const acs_args_rl &a, uint8_t *smem)
         __syncthreads();
         A = adjs;
     }
-    // Labels only ever move to a smaller body of the same component, and a
-    // label's own label is taken too (a pointer jump), so the chains of
-    // labels shorten geometrically; the fixpoint is the component minimum.
-    for (;;) {
-        int changed = 0;
-        for (int32_t i = t; i < n; i += ACS_BLOCK) {
-            int32_t m = __hip_atomic_load(&lab[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            const int32_t own = m;
-            for (int32_t k = aoff[i]; k < aoff[i + 1]; k++) {
-                const int32_t c = A[k];
-                if ((uint32_t)c >= (uint32_t)n) continue;   // never true for broadphase output
-                int32_t l = __hip_atomic_load(&lab[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                m = l < m ? l : m;
-            }
-            const int32_t jm = __hip_atomic_load(&lab[m], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            m = jm < m ? jm : m;
-            if (m < own) {
-                __hip_atomic_store(&lab[i], m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                changed = 1;
+    // Connected components by union-find over the contact pairs: a root is
+    // only ever hooked under a smaller root (a compare-and-swap on its own
+    // label), so each component ends rooted at its smallest body; finds
+    // halve their paths, which keeps every label pointing at an ancestor.
+    auto ld = [&](int32_t x) { return __hip_atomic_load(&lab[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
+    auto find = [&](int32_t x) {
+        int32_t p = ld(x);
+        while (p != x) {
+            const int32_t q = ld(p);
+            if (q != p) __hip_atomic_store(&lab[x], q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            x = p;
+            p = q;
+        }
+        return x;
+    };
+    for (int32_t i = t; i < n; i += ACS_BLOCK)
+        for (int32_t k = aoff[i]; k < aoff[i + 1]; k++) {
+            const int32_t c = A[k];
+            if ((uint32_t)c >= (uint32_t)n || c <= i) continue;   // each pair once; never out of range for broadphase output
+            int32_t ri = find(i), rj = find(c);
+            while (ri != rj) {
+                if (ri > rj) {
+                    const int32_t s2 = ri;
+                    ri = rj;
+                    rj = s2;
+                }
+                int32_t expect = rj;
+                if (__hip_atomic_compare_exchange_strong(&lab[rj], &expect, ri, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP))
+                    break;
+                // rj was hooked elsewhere meanwhile: continue from the roots
+                ri = find(ri);
+                rj = find(expect);
             }
         }
-        if (!__syncthreads_or(changed)) break;
+    __syncthreads();
+    for (int32_t i = t; i < n; i += ACS_BLOCK) {
+        const int32_t r = find(i);
+        __hip_atomic_store(&lab[i], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
+    __syncthreads();
     // island index of each root (roots in ascending order)
     for (int32_t i = t; i < n; i += ACS_BLOCK) ridx[i] = (lab[i] == i) ? 1 : 0;
     __syncthreads();
