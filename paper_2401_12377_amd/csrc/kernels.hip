@@ -60,6 +60,26 @@ hipError_t launch_task(int32_t kid, const void *args, uint32_t npieces, hipStrea
     return hipLaunchKernel(k_table[kid], dim3(npieces), dim3(ACS_BLOCK), argv, 0, stream);
 }
 
+// Several ready tasks of the plain path in one launch (they do not depend on
+// each other): the task of a workgroup is found by a walk over the pieces,
+// the same for every thread of it.
+__global__ __launch_bounds__(ACS_BLOCK) void k_multi(MultiParams p)
+{
+    __shared__ __align__(16) uint8_t smem[kBodySmem];
+    const uint32_t b = blockIdx.x;
+    uint32_t i = 0;
+    while (i + 1 < p.n && b >= p.t[i + 1].first) i++;
+    run_body<false>(p.t[i].kid, p.t[i].args, b - p.t[i].first, p.t[i].np, smem);
+}
+
+hipError_t launch_multi(const MultiParams &p, hipStream_t stream)
+{
+    if (p.n == 0 || p.n > (uint32_t)kMultiMax || p.total == 0) return hipErrorInvalidValue;
+    MultiParams copy = p;
+    void *argv[1] = {&copy};
+    return hipLaunchKernel(reinterpret_cast<const void *>(&k_multi), dim3(p.total), dim3(ACS_BLOCK), argv, 0, stream);
+}
+
 // One instance per bound on the window groups (1, 2, 4, 8), so that a
 // single window does not carry the register pressure of eight.
 template <int NG>

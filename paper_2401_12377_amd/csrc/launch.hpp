@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include "acs.h"
 #include "dev_shared.hpp"
 
 namespace acs {
@@ -14,6 +15,23 @@ hipError_t launch_task(int32_t kid, const void *args, uint32_t npieces, hipStrea
 
 // The standalone kernel of task `kid` (for graph nodes), or null.
 const void *task_kernel(int32_t kid);
+
+// Several mutually independent tasks in one launch: workgroup b runs piece
+// b - first of the task whose pieces [first, first + np) hold b.
+constexpr int32_t kMultiMax = 32;
+struct MultiTask {
+    int32_t kid;
+    uint32_t np;
+    uint32_t first;
+    uint32_t pad;
+    uint8_t args[ACS_ARGS_MAX];
+};
+struct MultiParams {
+    uint32_t n;        // tasks
+    uint32_t total;    // workgroups: the sum of the tasks' pieces
+    MultiTask t[kMultiMax];
+};
+hipError_t launch_multi(const MultiParams &p, hipStream_t stream);
 
 // Launches the persistent scheduler kernel: workgroup 0 holds the window,
 // workgroups 1 .. grid-1 are workers.

@@ -271,15 +271,20 @@ private:
 // Section IV-B).  A ready kernel goes to an idle stream, else to the stream
 // with the shortest queue; a pending kernel whose upstream kernels are all
 // executing in one stream goes into that stream at once (stream order keeps
-// the edge).  Completions are seen through events, recorded only when a
-// completion is needed: when the window is full with kernels waiting in the
-// FIFO, when some kernel could not be handed out, or on a drain.  An event
-// after the last kernel of a stream marks every kernel before it (in trace
-// mode every kernel gets its own pair, for the execution intervals).  Every
-// other kernel costs one launch, as on the in-order stream.
+// the edge).  The kernels a stream takes in one scheduling round go out as
+// one launch (a multi-task kernel: they never depend on each other), which
+// divides the host's launch cost; on submit, kernels are held back until
+// eight wait or the window is full.  Completions are seen through events,
+// recorded only when a completion is needed: when the window is full with
+// kernels waiting in the FIFO, when some kernel could not be handed out, or
+// on a drain.  An event after the last kernel of a stream marks every kernel
+// before it (in trace mode every launch gets its own pair, for the
+// execution intervals).
 // ---------------------------------------------------------------------------
 class PlainPath : public Path {
     static constexpr size_t kDepth = ACS_W_MAX;   // kernels per stream (no window holds more)
+    static constexpr int32_t kBatch = 8;          // kernels held back on submit before a hand-out
+    static constexpr int32_t kMaxStreams = 64;
     struct InFlight {
         int32_t slot;
         int32_t ev;    // event index marking the end of this kernel, or -1 (a later entry's covers it)
@@ -306,6 +311,7 @@ public:
         const unsigned flags = cfg_.trace ? hipEventDefault : hipEventDisableTiming;
         const size_t nev = 2 * (size_t)ACS_W_MAX + 2;   // at most two per kernel in flight
         events_.assign(nev, nullptr);
+        ev_refs_.assign(nev, 0);
         for (size_t k = 0; k < nev; k++) {
             if ((e = hipEventCreateWithFlags(&events_[k], flags)) != hipSuccess) return hip_fail(e, "hipEventCreate");
             free_ev_.push_back((int32_t)k);
@@ -334,7 +340,7 @@ public:
             _mm_pause();
         }
         win_.fifo_push(d);
-        progress();
+        progress(false, true);
         return ACS_OK;
     }
     int sync(uint64_t timeout_ns) override
@@ -399,7 +405,13 @@ private:
     {
         const int32_t k = free_ev_.back();
         free_ev_.pop_back();
+        ev_refs_[(size_t)k] = 0;
         return k;
+    }
+    // an event may mark several kernels (a batch): freed with the last
+    void drop_event(int32_t k)
+    {
+        if (k >= 0 && --ev_refs_[(size_t)k] <= 0) free_ev_.push_back(k);
     }
 
     // Retires the front kernels of stream s up to and including the first
@@ -436,82 +448,139 @@ private:
                 if (!dev_err_) dev_err_ = ACS_EDEVICE;
                 hip_fail(q_err, "kernel");
             }
-            if (f.ev >= 0) free_ev_.push_back(f.ev);
-            if (f.beg >= 0) free_ev_.push_back(f.beg);
+            drop_event(f.ev);
+            drop_event(f.beg);
             stream_of_[f.slot] = -1;
             win_.retire(f.slot, status, ta, tb);
         }
         return true;
     }
 
-    // Launches the kernel of `slot` into stream s; false on a launch error
-    // (the kernel is then retired as failed).
-    bool launch_into(int32_t slot, size_t s)
+    // Launches the kernels of `slots` (mutually independent, already marked
+    // executing) into stream s: one task alone as its own kernel, several as
+    // one multi-task launch.  A launch error retires them as failed.
+    void launch_batch(const int32_t *slots, int32_t k, size_t s)
     {
-        const Desc &d = win_.slot_desc(slot);
-        InFlight f{slot, -1, -1};
+        int32_t beg = -1;
         if (cfg_.trace) {
-            f.beg = take_event();
-            (void)hipEventRecord(events_[(size_t)f.beg], streams_[s]);
+            beg = take_event();
+            (void)hipEventRecord(events_[(size_t)beg], streams_[s]);
         }
-        const hipError_t e = launch_task(d.kid, d.args, d.npieces, streams_[s]);
-        win_.mark_executing(slot);
+        hipError_t e;
+        if (k == 1) {
+            const Desc &d = win_.slot_desc(slots[0]);
+            e = launch_task(d.kid, d.args, d.npieces, streams_[s]);
+        } else {
+            MultiParams mp;
+            mp.n = (uint32_t)k;
+            mp.total = 0;
+            for (int32_t i = 0; i < k; i++) {
+                const Desc &d = win_.slot_desc(slots[i]);
+                MultiTask &t = mp.t[i];
+                t.kid = d.kid;
+                t.np = d.npieces;
+                t.first = mp.total;
+                t.pad = 0;
+                memcpy(t.args, d.args, ACS_ARGS_MAX);
+                mp.total += d.npieces;
+            }
+            e = launch_multi(mp, streams_[s]);
+        }
         if (e != hipSuccess) {
             hip_fail(e, "kernel launch");
             if (!dev_err_) dev_err_ = ACS_EDEVICE;
-            if (f.beg >= 0) free_ev_.push_back(f.beg);
-            win_.retire(slot, ACS_EDEVICE);
-            return false;
+            if (beg >= 0) free_ev_.push_back(beg);
+            for (int32_t i = 0; i < k; i++) {
+                stream_of_[slots[i]] = -1;
+                win_.retire(slots[i], ACS_EDEVICE);
+            }
+            return;
         }
+        int32_t end = -1;
         if (cfg_.trace) {
-            f.ev = take_event();
-            (void)hipEventRecord(events_[(size_t)f.ev], streams_[s]);
+            end = take_event();
+            (void)hipEventRecord(events_[(size_t)end], streams_[s]);
         }
-        stream_of_[slot] = (int32_t)s;
-        q_[s].push_back(f);
-        return true;
+        for (int32_t i = 0; i < k; i++) {
+            InFlight f{slots[i], -1, -1};
+            if (cfg_.trace) {
+                f.ev = end;
+                f.beg = beg;
+                ev_refs_[(size_t)end]++;
+                ev_refs_[(size_t)beg]++;
+            }
+            stream_of_[slots[i]] = (int32_t)s;
+            q_[s].push_back(f);
+        }
     }
 
     // One pass of the window module and the scheduler module: retire what
-    // finished, admit from the FIFO, hand out what can run.
-    void progress(bool drain = false)
+    // finished, admit from the FIFO, hand out what can run.  Everything that
+    // can run in a pass is mutually independent (a kernel whose upstream
+    // kernel is still waiting is not among them), so each stream takes its
+    // share as one launch.
+    void progress(bool drain = false, bool lazy = false)
     {
         for (size_t s = 0; s < streams_.size(); s++)
             if (!q_[s].empty()) retire_front(s);
         win_.admit();
+        // On submit, kernels are held back until a batch is worth a launch:
+        // kBatch of them wait, or the window is full (a drain, a poll or any
+        // other call hands out everything at once).
+        if (lazy && !win_.full() && win_.waiting() < kBatch) return;
         bool blocked = false;   // some kernel could not be handed out
-        for (;;) {
+        // One walk in age order.  A kernel joins the open batch of the stream
+        // that runs all its upstream kernels; if one of those is in that very
+        // batch, the batch is launched first (stream order then keeps the
+        // edge) and the kernel opens the next one.  Ready kernels share one
+        // stream per walk.
+        int32_t open[kMaxStreams][kMultiMax];
+        int32_t nopen[kMaxStreams] = {};
+        uint64_t inbatch[kMaxStreams] = {};
+        const int32_t S = (int32_t)streams_.size();
+        auto flush = [&](int32_t s) {
+            if (nopen[s] == 0) return;
+            launch_batch(open[s], nopen[s], (size_t)s);
+            nopen[s] = 0;
+            inbatch[s] = 0;
+        };
+        for (bool again = true; again;) {
+            again = false;
             int32_t cand[ACS_W_MAX];
             const int32_t k = win_.waiting_slots(cand, ACS_W_MAX);
-            bool any = false;
+            int32_t ready_stream = -1;
             for (int32_t c = 0; c < k; c++) {
                 const int32_t slot = cand[c];
                 const uint64_t up = win_.upstream(slot);
                 if (up == 0 && win_.poisoned(slot)) {
                     win_.mark_executing(slot);
                     win_.retire(slot, 0);
-                    any = true;
+                    again = true;   // a retirement may free an admission
                     continue;
                 }
                 int32_t s = -1;
                 if (up == 0) {
-                    s = pick_stream();
+                    if (ready_stream < 0) ready_stream = pick_stream();
+                    s = ready_stream;
                 } else if (!win_.poisoned(slot) && (up & ~win_.executing()) == 0) {
-                    // every upstream kernel runs: all in one stream?
+                    // every upstream kernel runs or is about to: all in one stream?
                     const int32_t s0 = stream_of_[__builtin_ctzll(up)];
                     bool same = s0 >= 0;
                     for (uint64_t m = up; m && same; m &= m - 1) same = stream_of_[__builtin_ctzll(m)] == s0;
-                    if (same && q_[(size_t)s0].size() < kDepth) s = s0;
+                    if (same) s = s0;
                 }
-                if (s < 0) {
+                if (s < 0 || q_[(size_t)s].size() + (size_t)nopen[s] >= kDepth) {
                     blocked = true;
                     continue;
                 }
-                launch_into(slot, (size_t)s);
-                any = true;
+                if ((up & inbatch[s]) != 0 || nopen[s] == kMultiMax) flush(s);
+                open[s][nopen[s]++] = slot;
+                inbatch[s] |= 1ull << slot;
+                win_.mark_executing(slot);
+                stream_of_[slot] = s;
             }
-            if (!any) break;
-            win_.admit();
+            for (int32_t s = 0; s < S; s++) flush(s);
+            if (win_.admit() > 0) again = true;
         }
         // completions are needed: an end event behind each stream's last kernel
         const bool need = drain || blocked || (win_.full() && !win_.fifo_empty());
@@ -520,6 +589,7 @@ private:
                 if (q_[s].empty() || q_[s].back().ev >= 0) continue;
                 InFlight &last = q_[s].back();
                 last.ev = take_event();
+                ev_refs_[(size_t)last.ev] = 1;
                 (void)hipEventRecord(events_[(size_t)last.ev], streams_[s]);
             }
     }
@@ -548,6 +618,7 @@ private:
     std::vector<std::deque<InFlight>> q_;
     std::vector<hipEvent_t> events_;
     std::vector<int32_t> free_ev_;
+    std::vector<int32_t> ev_refs_;   // kernels each event marks
     int32_t stream_of_[ACS_W_MAX];
     hipEvent_t base_ = nullptr;
     int32_t rr_ = 0;

@@ -20,6 +20,7 @@ public:
     void fifo_push(const Desc &d) { fifo_.push_back(d); }
     bool drained() const { return fifo_.empty() && valid_ == 0; }
     bool full() const { return valid_ == ((W_ >= 64) ? ~0ull : ((1ull << W_) - 1ull)); }
+    int32_t waiting() const { return __builtin_popcountll(valid_ & ~exec_); }
 
     // a2 + a3: while a slot is free, moves the FIFO head into the lowest free
     // slot and computes its upstream mask against every occupied slot.

@@ -503,6 +503,25 @@ const void *task_kernel(int32_t kid)
     return &g_tags[kid];
 }
 
+hipError_t launch_multi(const MultiParams &p, hipStream_t stream)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    if (p.n == 0 || p.n > (uint32_t)kMultiMax || p.total == 0) return hipErrorInvalidValue;
+    if (!live_stream(stream)) die("kernel launched on a destroyed or unknown stream");
+    std::vector<std::pair<int32_t, std::vector<uint8_t>>> ts;
+    std::vector<uint32_t> nps;
+    for (uint32_t i = 0; i < p.n; i++) {
+        const size_t sz = args_size(p.t[i].kid);
+        if (sz == 0 || p.t[i].np == 0) return hipErrorInvalidValue;
+        ts.emplace_back(p.t[i].kid, std::vector<uint8_t>(p.t[i].args, p.t[i].args + sz));
+        nps.push_back(p.t[i].np);
+    }
+    stream->q.push_back([ts, nps] {
+        for (size_t i = 0; i < ts.size(); i++) run_kernel(ts[i].first, ts[i].second, nps[i]);
+    });
+    return hipSuccess;
+}
+
 // the persistent kernel has no host stand-in: the device path cannot start
 hipError_t launch_persistent(const DevParams &, int32_t, hipStream_t) { return hipErrorInvalidValue; }
 
