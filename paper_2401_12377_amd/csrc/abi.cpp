@@ -11,7 +11,6 @@
 
 #include "internal.hpp"
 #include "launch.hpp"
-#include "conv_tiles.hpp"
 #include "rl_layout.hpp"
 
 
@@ -185,8 +184,8 @@ bool check_args(int32_t kid, const uint8_t *args, int32_t g, uint32_t &np, std::
             if (why) *why = "conv: output pixels must be a multiple of 16";
             return false;
         }
-        // one piece per output tile, at most 256 pieces (tiles are dealt round-robin)
-        np = (uint32_t)std::min<int64_t>(conv_tiles(m, a.cout), 256);
+        // one piece per 16 x 32 output tile, at most 256 pieces (tiles are dealt round-robin)
+        np = (uint32_t)std::min<int64_t>((m / 16) * (a.cout / 32), 256);
         return true;
     }
     case ACS_K_JOIN: {

@@ -12,7 +12,6 @@
 #include <stdint.h>
 
 #include "acs_tasks.h"
-#include "conv_tiles.hpp"
 #include "rl_layout.hpp"
 
 namespace acs {
@@ -909,7 +908,6 @@ struct ConvStep {
     float b0[8], b1[8];     // rows q * 8 + s of the step, columns n0 + j and n0 + 16 + j
 };
 
-template <int NW>
 __device__ __forceinline__ void conv_load(const acs_args_conv &a, int32_t py, int32_t px, int32_t n0, int32_t kc0,
                                           int32_t q, int32_t j, ConvStep &v)
 {
@@ -927,27 +925,24 @@ __device__ __forceinline__ void conv_load(const acs_args_conv &a, int32_t py, in
 #pragma unroll
     for (int s = 0; s < 8; s++) {
         v.b0[s] = wr[(int64_t)s * cout];
-        if (NW == 2) v.b1[s] = wr[(int64_t)s * cout + 16];
+        v.b1[s] = wr[(int64_t)s * cout + 16];
     }
 }
 
-// one step: eight k of the 16x16 products of each column half, in k order
-template <int NW>
+// one step: eight k of the 16x16 products of both column halves, in k order
 __device__ __forceinline__ void conv_mma(const ConvStep &v, acs_v4f &acc0, acs_v4f &acc1)
 {
     const float av[8] = {v.a0.x, v.a0.y, v.a0.z, v.a0.w, v.a1.x, v.a1.y, v.a1.z, v.a1.w};
 #pragma unroll
     for (int s = 0; s < 8; s++) {
         acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], v.b0[s], acc0, 0, 0, 0);
-        if (NW == 2) acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], v.b1[s], acc1, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], v.b1[s], acc1, 0, 0, 0);
     }
 }
 
-template <bool DEV, int NW>
+template <bool DEV>
 __device__ inline void conv_tile(const acs_args_conv &a, int32_t m0, int32_t n0, uint8_t *smem)
 {
-    // NW accumulators of 16 columns: a tile of 16 x 16 * NW outputs
-    constexpr int32_t TW = 16 * NW;
     const int32_t k = a.k, st = a.stride, pad = (k - 1) / 2, cout = a.cout;
     const int32_t hout = (a.hin + 2 * pad - k) / st + 1;
     const int32_t nsteps = k * k * a.cin / kConvKC;
@@ -958,34 +953,34 @@ __device__ inline void conv_tile(const acs_args_conv &a, int32_t m0, int32_t n0,
     // this wave's steps wv, wv + 4, ... with the loads of the next two in
     // flight while one is multiplied (three steps of operands resident)
     ConvStep s0, s1, s2;
-    if (wv < nsteps) conv_load<NW>(a, py, px, n0, wv * kConvKC, q, i, s0);
-    if (wv + 4 < nsteps) conv_load<NW>(a, py, px, n0, (wv + 4) * kConvKC, q, i, s1);
+    if (wv < nsteps) conv_load(a, py, px, n0, wv * kConvKC, q, i, s0);
+    if (wv + 4 < nsteps) conv_load(a, py, px, n0, (wv + 4) * kConvKC, q, i, s1);
     for (int32_t step = wv; step < nsteps; step += 12) {
-        if (step + 8 < nsteps) conv_load<NW>(a, py, px, n0, (step + 8) * kConvKC, q, i, s2);
-        conv_mma<NW>(s0, acc0, acc1);
+        if (step + 8 < nsteps) conv_load(a, py, px, n0, (step + 8) * kConvKC, q, i, s2);
+        conv_mma(s0, acc0, acc1);
         if (step + 4 >= nsteps) break;
-        if (step + 12 < nsteps) conv_load<NW>(a, py, px, n0, (step + 12) * kConvKC, q, i, s0);
-        conv_mma<NW>(s1, acc0, acc1);
+        if (step + 12 < nsteps) conv_load(a, py, px, n0, (step + 12) * kConvKC, q, i, s0);
+        conv_mma(s1, acc0, acc1);
         if (step + 8 >= nsteps) break;
-        if (step + 16 < nsteps) conv_load<NW>(a, py, px, n0, (step + 16) * kConvKC, q, i, s1);
-        conv_mma<NW>(s2, acc0, acc1);
+        if (step + 16 < nsteps) conv_load(a, py, px, n0, (step + 16) * kConvKC, q, i, s1);
+        conv_mma(s2, acc0, acc1);
     }
-    // partial tiles: part[w][row][col], 4 x 16 x TW floats
+    // partial tiles: part[w][row][col], 4 x 16 x 32 floats
     float *part = reinterpret_cast<float *>(smem);
 #pragma unroll
     for (int r = 0; r < 4; r++) {
         const int32_t row = 4 * q + r;
-        part[(wv * 16 + row) * TW + i] = acc0[r];
-        if (NW == 2) part[(wv * 16 + row) * TW + 16 + i] = acc1[r];
+        part[(wv * 16 + row) * 32 + i] = acc0[r];
+        part[(wv * 16 + row) * 32 + 16 + i] = acc1[r];
     }
     __syncthreads();
-    // 16 x TW outputs: wave order, then the bias
-    for (int32_t e = t; e < 16 * TW; e += ACS_BLOCK) {
-        const int32_t row = e / TW, col = e % TW;
-        float v = part[row * TW + col];
-        v += part[(16 + row) * TW + col];
-        v += part[(32 + row) * TW + col];
-        v += part[(48 + row) * TW + col];
+    // 512 outputs, two per thread: wave order, then the bias
+    for (int32_t e = t; e < 16 * 32; e += ACS_BLOCK) {
+        const int32_t row = e >> 5, col = e & 31;
+        float v = part[row * 32 + col];
+        v += part[(16 + row) * 32 + col];
+        v += part[(32 + row) * 32 + col];
+        v += part[(48 + row) * 32 + col];
         put<DEV>(gp(a.out) + (int64_t)(m0 + row) * cout + n0 + col, v + gp(a.bias)[n0 + col]);
     }
 }
@@ -996,12 +991,9 @@ template <bool DEV>
 __device__ inline void body_conv(const acs_args_conv &a, uint32_t piece, uint32_t np, uint8_t *smem)
 {
     const int32_t pad = (a.k - 1) / 2, hout = (a.hin + 2 * pad - a.k) / a.stride + 1;
-    const int32_t tw = conv_tile_cols((int64_t)hout * hout, a.cout);
-    const uint32_t ntn = (uint32_t)(a.cout / tw), ntiles = (uint32_t)(hout * hout / 16) * ntn;
+    const uint32_t ntn = (uint32_t)a.cout / 32u, ntiles = (uint32_t)(hout * hout / 16) * ntn;
     for (uint32_t tile = piece; tile < ntiles; tile += np) {
-        const int32_t m0 = (int32_t)(tile / ntn) * 16, n0 = (int32_t)(tile % ntn) * tw;
-        if (tw == 32) conv_tile<DEV, 2>(a, m0, n0, smem);
-        else conv_tile<DEV, 1>(a, m0, n0, smem);
+        conv_tile<DEV>(a, (int32_t)(tile / ntn) * 16, (int32_t)(tile % ntn) * 32, smem);
         __syncthreads();   // the next tile reuses the partial-tile buffer
     }
 }
