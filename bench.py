@@ -38,15 +38,19 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of one persistent-kernel launch of the headline workload, from
 # two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE, KiB per dispatch) scaled
 # by the same counters' reading on a device-to-device copy of known size
-# (--copy-calibration).  Valid only for the kernel sources whose digest is
-# recorded and for the same workload and tuned configuration: any change
-# makes the figure stale (null).
+# (--copy-calibration), one entry per tuned configuration that was measured.
+# Valid only for the kernel sources whose digest is recorded and for the same
+# workload and configuration: any change makes the figure stale (null).
+def _cfg_key(qd):
+    return (256, 20, json.dumps({"W": 32, "n_groups": 1, "wg_per_task": 1, "queue_depth": qd,
+                                 "host_check_depth": 32, "window_check": 0}, sort_keys=True))
+
+
 TRAFFIC = {
-    "digest": "034d8ab5799e7911",
-    "workload": (256, 20, json.dumps({"W": 32, "n_groups": 1, "wg_per_task": 1, "queue_depth": 256,
-                                      "host_check_depth": 32, "window_check": 0}, sort_keys=True)),
-    "fetch_kib": 341301.0, "write_kib": 607449.59375,
-    "copy_bytes": 268435456, "copy_fetch_kib": 131085.2708, "copy_write_kib": 262144.0,
+    "digest": "c5b4d3f6d24a36d1",
+    "copy_bytes": 268435456, "copy_fetch_kib": 131085.2083, "copy_write_kib": 262144.0,
+    "runs": [{"workload": _cfg_key(256), "fetch_kib": 336662.75, "write_kib": 594638.6875},
+             {"workload": _cfg_key(1024), "fetch_kib": 337056.25, "write_kib": 594109.84375}],
 }
 KERNEL_SOURCES = ["kernels.hip", "persistent.hpp", "bodies.hpp", "dev_shared.hpp"]
 
@@ -300,12 +304,15 @@ def dag_section(acs, inputs, torch, args):
 def traffic_bytes(workload_key):
     """Calibrated HBM bytes per launch, or None when not measured for these
     sources or for this workload and configuration."""
-    if TRAFFIC is None or TRAFFIC["digest"] != kernel_digest() or TRAFFIC["workload"] != workload_key:
+    if TRAFFIC is None or TRAFFIC["digest"] != kernel_digest():
+        return None
+    run = next((r for r in TRAFFIC["runs"] if r["workload"] == workload_key), None)
+    if run is None:
         return None
     # bytes per counter unit, from the copy that moved copy_bytes each way
     bf = TRAFFIC["copy_bytes"] / TRAFFIC["copy_fetch_kib"]
     bw = TRAFFIC["copy_bytes"] / TRAFFIC["copy_write_kib"]
-    return int(TRAFFIC["fetch_kib"] * bf + TRAFFIC["write_kib"] * bw)
+    return int(run["fetch_kib"] * bf + run["write_kib"] * bw)
 
 
 def algorithmic_bytes(counts: dict, sizes, steps: int) -> int:
