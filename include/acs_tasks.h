@@ -61,14 +61,19 @@ typedef struct { float *out; const float *in[3]; uint32_t len[3]; uint32_t nin; 
 /* Rigid-body RL scene.  `base` is the scene's device arena (acs_rl_layout);
  * `plan` is a host-visible int32 buffer of 4 + 4 * (n / 2) entries written by
  * the islands kernel: [0] islands, [1] multi-body islands, [2] directed edges,
- * then per multi-body island: first position, end position, first edge, end edge. */
+ * [3] the islands kernel's `iter` argument (a stamp), then per multi-body
+ * island: first position, end position, first edge, end edge.  Every entry
+ * is a system-scope store and the stamp is stored after all the others have
+ * completed, so a host that sees its stamp in [3] (acquire load) may read the
+ * plan while the window is still running. */
 typedef struct {
     uint64_t base;
     uint64_t plan;
     int32_t n;
     float r;
     float dt;
-    int32_t iter;            /* Jacobi: iteration index (even: Q0 -> Q1, odd: Q1 -> Q0) */
+    int32_t iter;            /* Jacobi: iteration index (even: Q0 -> Q1, odd: Q1 -> Q0);
+                                islands: the stamp stored last into plan[3] */
     int32_t b0, b1;          /* Jacobi: positions [b0, b1) of the island */
 } acs_args_rl;
 

@@ -101,11 +101,11 @@ __device__ __forceinline__ void put16(ACS_GAS V16 *p, const V16 &v)
     }
 }
 
-template <bool DEV>
+// Words the host reads while the kernel may still be running (the island
+// plan): system-scope stores, written through to host memory, on every path.
 __device__ __forceinline__ void put_host(ACS_GAS int32_t *p, int32_t v)
 {
-    if constexpr (DEV) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    else *p = v;
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // ---------------------------------------------------------------------------
@@ -604,17 +604,20 @@ __device__ inline void islands_small(const acs_args_rl &a, const RLView &v, ACS_
     const int32_t e1 = endp < n ? e1s : ep;
     if (multi) {
         const int32_t m = __builtin_popcountll(multis & below);
-        put_host<DEV>(&plan[4 + 4 * m + 0], start);
-        put_host<DEV>(&plan[4 + 4 * m + 1], endp);
-        put_host<DEV>(&plan[4 + 4 * m + 2], e0);
-        put_host<DEV>(&plan[4 + 4 * m + 3], e1);
+        put_host(&plan[4 + 4 * m + 0], start);
+        put_host(&plan[4 + 4 * m + 1], endp);
+        put_host(&plan[4 + 4 * m + 2], e0);
+        put_host(&plan[4 + 4 * m + 3], e1);
     }
     if (lane == 0) {
-        put_host<DEV>(&plan[0], nisl);
-        put_host<DEV>(&plan[1], (int32_t)__builtin_popcountll(multis));
-        put_host<DEV>(&plan[2], ep);
-        put_host<DEV>(&plan[3], 0);
+        put_host(&plan[0], nisl);
+        put_host(&plan[1], (int32_t)__builtin_popcountll(multis));
+        put_host(&plan[2], ep);
     }
+    // the stamp last, once this wave's plan stores have completed (the
+    // wave wrote the whole plan)
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt 0, expcnt 7, lgkmcnt 15
+    if (lane == 0) put_host(&plan[3], a.iter);
 }
 
 template <bool DEV>
@@ -768,18 +771,21 @@ __device__ inline void body_rl_islands(const acs_args_rl &a, uint8_t *smem)
     for (int32_t k = t; k < nisl; k += ACS_BLOCK) {
         if (sz[k + 1] - sz[k] >= 2) {
             const int32_t m = ridx[k];
-            put_host<DEV>(&plan[4 + 4 * m + 0], sz[k]);
-            put_host<DEV>(&plan[4 + 4 * m + 1], sz[k + 1]);
-            put_host<DEV>(&plan[4 + 4 * m + 2], poff[sz[k]]);
-            put_host<DEV>(&plan[4 + 4 * m + 3], poff[sz[k + 1]]);
+            put_host(&plan[4 + 4 * m + 0], sz[k]);
+            put_host(&plan[4 + 4 * m + 1], sz[k + 1]);
+            put_host(&plan[4 + 4 * m + 2], poff[sz[k]]);
+            put_host(&plan[4 + 4 * m + 3], poff[sz[k + 1]]);
         }
     }
     if (t == 0) {
-        put_host<DEV>(&plan[0], nisl);
-        put_host<DEV>(&plan[1], nmulti);
-        put_host<DEV>(&plan[2], Ep);
-        put_host<DEV>(&plan[3], 0);
+        put_host(&plan[0], nisl);
+        put_host(&plan[1], nmulti);
+        put_host(&plan[2], Ep);
     }
+    // the stamp last, once every wave's plan stores have completed
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt 0, expcnt 7, lgkmcnt 15
+    __syncthreads();
+    if (t == 0) put_host(&plan[3], a.iter);
 }
 
 template <bool DEV>

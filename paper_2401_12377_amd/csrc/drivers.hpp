@@ -5,6 +5,9 @@
 #pragma once
 #include <stdint.h>
 
+#include <chrono>
+#include <immintrin.h>
+
 #include "acs.h"
 #include "acs_tasks.h"
 #include "acs_workloads.h"
@@ -53,7 +56,16 @@ public:
             const acs_seg plan_seg = {(uint64_t)(uintptr_t)sc_->plan, 4ull * acs::rl_plan_ints(sc_->n)};
             const acs_seg r[1] = {span(ACS_RL_DEG, ACS_RL_LABEL)};
             const acs_seg wr[2] = {span(ACS_RL_LABEL, ACS_RL_END), plan_seg};
-            return submit(ACS_K_RL_ISLANDS, r, 1, wr, 2, cnt);
+            // The islands kernel stores this stamp into plan[3] after the
+            // rest of the plan.  No kernel is writing the plan now (the last
+            // islands kernel of this scene has been waited for), so the old
+            // stamp is cleared first and never mistaken for the new one.
+            stamp_ = stamp_ >= 0x7FFFFFFF ? 1 : stamp_ + 1;
+            __atomic_store_n(&((int32_t *)sc_->plan)[3], 0, __ATOMIC_RELAXED);
+            a_.iter = stamp_;
+            const int rc = submit(ACS_K_RL_ISLANDS, r, 1, wr, 2, cnt);
+            a_.iter = 0;
+            return rc;
         }
         const acs_seg r[2] = {region(ACS_RL_P), region(ACS_RL_PERM)};
         const acs_seg wr[1] = {region(ACS_RL_Q0)};
@@ -70,7 +82,26 @@ public:
         return submit_integrate(cnt);
     }
 
-    // Reads and checks the island plan (once the islands kernel completed).
+    // Waits until the islands kernel of this step has published the plan
+    // (its stamp in plan[3]) while the window keeps running: the host needs
+    // the island list before it can state the rest of the step, but not an
+    // empty window.  acs_poll keeps a host-side window dispatching and
+    // reports a failed window; a minute without the stamp is a time-out.
+    int wait_plan()
+    {
+        const int32_t *stamp = &((const int32_t *)sc_->plan)[3];
+        auto t0 = std::chrono::steady_clock::now();
+        for (uint32_t spin = 0;; spin++) {
+            if (__atomic_load_n(stamp, __ATOMIC_ACQUIRE) == stamp_) return ACS_OK;
+            if ((spin & 15u) == 0)
+                if (int rc = acs_poll(w_)) return rc;
+            if ((spin & 0xFFFFu) == 0xFFFFu && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(60))
+                return ACS_ETIMEDOUT;
+            _mm_pause();
+        }
+    }
+
+    // Reads and checks the island plan (once the islands kernel published it).
     int tail_begin(acs_rl_counts &cnt)
     {
         const int32_t *plan = (const int32_t *)sc_->plan;
@@ -143,6 +174,7 @@ private:
     uint64_t off_[ACS_RL_NREGIONS];
     acs_args_rl a_;
     int32_t nmulti_ = 0;
+    int32_t stamp_ = 0;   // of the last islands kernel submitted
 };
 
 // Submits one inference of the gated network into window group `group`

@@ -632,7 +632,8 @@ private:
 // stream becomes a wait on that kernel's completion event.  Dependencies
 // come from the same range test, against every kernel that may still be
 // running: the last kHist kernels, where a kernel leaves that history only
-// after its event has fired (the host waits for it if need be).
+// after its event has fired (seen by a query before each submit and on every
+// poll; the host waits for the oldest when the history is full).
 // ---------------------------------------------------------------------------
 class EventsPath : public Path {
 public:
@@ -656,6 +657,9 @@ public:
     int submit(const Desc &d) override
     {
         if (err_) return err_;
+        // kernels already complete leave the history first, so that they
+        // cost neither range tests nor waits
+        if (int rc = retire_fired(8)) return rc;
         if ((int32_t)hist_.size() == kHist)
             if (int rc = retire_oldest()) return rc;
         // newest conflicting kernel per stream: stream order covers the older ones
@@ -718,7 +722,12 @@ public:
         retired_ = submitted_;
         return err_;
     }
-    int poll() override { return err_; }
+    int poll() override
+    {
+        if (err_) return err_;
+        if (int rc = retire_fired(kHist)) return rc;
+        return err_;
+    }
     int scheduled_list(acs_entry *, int32_t, int32_t *n) override
     {
         if (n) *n = 0;
@@ -756,6 +765,20 @@ private:
         int32_t stream = 0;
         hipEvent_t ev = nullptr;
     };
+    // up to `max` kernels whose events have fired leave the history, oldest
+    // first (a query per kernel, none waits)
+    int retire_fired(int32_t max)
+    {
+        for (int32_t q = 0; q < max && !hist_.empty(); q++) {
+            const hipError_t e = hipEventQuery(hist_.front().ev);
+            if (e == hipErrorNotReady) break;
+            if (e != hipSuccess) return fail_dev(e, "hipEventQuery");
+            free_events_.push_back(hist_.front().ev);
+            hist_.erase(hist_.begin());
+            retired_++;
+        }
+        return ACS_OK;
+    }
     int retire_oldest()
     {
         const hipError_t e = hipEventSynchronize(hist_.front().ev);

@@ -46,8 +46,8 @@ int acs_rl_run(acs_window *w, const acs_rl_scene *sc, int32_t steps, double *ste
     double t_prev = wall_ns();
     for (int32_t step = 0; step < steps; step++) {
         if (int rc = s.submit_prefix(cnt)) return rc;
-        // the island list is known only now: drain, read the plan
-        if (int rc = acs_sync(w)) return rc;
+        // the island list is known only once the islands kernel has run
+        if (int rc = s.wait_plan()) return rc;
         const double t_now = wall_ns();
         if (step_ns && step > 0) step_ns[step - 1] = t_now - t_prev;
         t_prev = t_now;
@@ -81,11 +81,12 @@ int acs_rl_run_batch(acs_window *w, const acs_rl_scene *scenes, int32_t n_scenes
         for (int k = 0; k < 4; k++)
             for (auto &s : st)
                 if (int rc = s.submit_stage(k, cnt)) return rc;
-        // group by group: once a group has drained, its scenes' plans are
-        // readable; the other groups keep running meanwhile.  Jacobi
-        // iteration by iteration across the group's scenes, then integrate.
+        // group by group: once its scenes' plans are published, Jacobi
+        // iteration by iteration across the group's scenes, then integrate;
+        // the window keeps running meanwhile.
         for (int32_t g = 0; g < n_groups; g++) {
-            if (int rc = acs_sync_group(w, g, 0)) return rc;
+            for (int32_t i = g; i < n_scenes; i += n_groups)
+                if (int rc = st[(size_t)i].wait_plan()) return rc;
             for (int32_t i = g; i < n_scenes; i += n_groups)
                 if (int rc = st[(size_t)i].tail_begin(cnt)) return rc;
             for (int32_t it = 0; it < max_iters; it++)

@@ -70,7 +70,9 @@ void islands_hook(int32_t kid, const void *args)
     }
     plan[0] = islands;
     plan[2] = edges;
-    __atomic_store_n(&plan[1], m, __ATOMIC_RELEASE);
+    plan[1] = m;
+    // the stamp last, as the islands kernel stores it
+    __atomic_store_n(&plan[3], a.iter, __ATOMIC_RELEASE);
     g_multi += (uint64_t)m;
     g_jacobi_expected += (uint64_t)m * (uint64_t)g_iters;
 }
@@ -234,6 +236,61 @@ void part_paths()
     printf("paths: %llu kernels\n", (unsigned long long)kernels);
 }
 
+// The RL drivers on the host-side paths: each step waits for its islands
+// kernel's plan stamp (the kernel runs only when the path queries or
+// synchronises its streams), then submits the plan's Jacobi kernels.
+void part_rlrun()
+{
+    fake_hip_set_kernel_hook(islands_hook);
+    const int32_t paths[] = {ACS_PATH_INORDER, ACS_PATH_PLAIN, ACS_PATH_EVENTS};
+    uint64_t steps_total = 0;
+    for (int32_t path : paths)
+        for (int32_t n : {2, 9, 64, 200}) {
+            uint64_t off[ACS_RL_NREGIONS];
+            CHECK(acs_rl_layout(n, off) == ACS_OK);
+            const int32_t n_scenes = 3;
+            std::vector<void *> arenas(n_scenes);
+            std::vector<int32_t *> plans(n_scenes);
+            std::vector<acs_rl_scene> sc(n_scenes);
+            for (int32_t i = 0; i < n_scenes; i++) {
+                CHECK(hipMalloc(&arenas[i], off[ACS_RL_END]) == hipSuccess);
+                plans[i] = (int32_t *)acs_host_alloc(4 * (4 + 4 * (n / 2)));
+                CHECK(plans[i]);
+                plans[i][3] = 1;   // a stale stamp equal to the first one a driver uses
+                sc[i] = {n, g_iters, 0.05f, 1.0f / 120, (uint64_t)(uintptr_t)arenas[i], plans[i]};
+            }
+            acs_window *w = acs_window_create(1 + (int32_t)(rnd() % 64));
+            CHECK(w);
+            acs_config cfg;
+            acs_config_default(&cfg);
+            cfg.path = path;
+            cfg.n_streams = 1 + (int32_t)(rnd() % 8);
+            CHECK(acs_window_configure(w, &cfg) == ACS_OK);
+            const int32_t steps = n >= 200 ? 20 : 200;
+            std::vector<double> step_ns(steps);
+            acs_rl_counts cnt;
+            g_multi = g_jacobi_expected = 0;
+            const int rc = acs_rl_run(w, &sc[0], steps, step_ns.data(), &cnt);
+            if (rc != ACS_OK) printf("path %d, %d bodies: acs_rl_run returned %d\n", path, n, rc);
+            CHECK(rc == ACS_OK);
+            CHECK(cnt.steps == (uint64_t)steps && cnt.multi_islands == g_multi);
+            CHECK(cnt.kernels == 5ull * steps + g_jacobi_expected);
+            g_multi = g_jacobi_expected = 0;
+            CHECK(acs_rl_run_batch(w, sc.data(), n_scenes, 1, steps / 4, step_ns.data(), &cnt) == ACS_OK);
+            CHECK(cnt.steps == (uint64_t)(n_scenes * (steps / 4)) && cnt.multi_islands == g_multi);
+            CHECK(cnt.kernels == 5ull * n_scenes * (steps / 4) + g_jacobi_expected);
+            CHECK(acs_sync(w) == ACS_OK);
+            CHECK(acs_window_destroy(w) == ACS_OK);
+            for (int32_t i = 0; i < n_scenes; i++) {
+                CHECK(acs_host_free(plans[i]) == ACS_OK);
+                CHECK(hipFree(arenas[i]) == hipSuccess);
+            }
+            steps_total += (uint64_t)steps + (uint64_t)n_scenes * (uint64_t)(steps / 4);
+        }
+    fake_hip_set_kernel_hook(nullptr);
+    printf("rlrun: %llu driver steps\n", (unsigned long long)steps_total);
+}
+
 void part_ranges()
 {
     acs_window *w = acs_window_create(64);
@@ -279,6 +336,7 @@ int main(int argc, char **argv)
     if (!*only || !strcmp(only, "replay")) part_replay();
     if (!*only || !strcmp(only, "paths")) part_paths();
     if (!*only || !strcmp(only, "ranges")) part_ranges();
+    if (!*only || !strcmp(only, "rlrun")) part_rlrun();
     int64_t c[6];
     fake_hip_counts(c);
     printf("alive: streams %lld events %lld graphs %lld execs %lld device %lld host %lld\n", (long long)c[0],

@@ -1,7 +1,8 @@
 """libacs's host sources built with the address and undefined-behaviour
 sanitizers, against a host stand-in of the HIP runtime (tests/hostsan), and
 driven through the graph-per-input RL loop, graph recording and replay, the
-in-order, plain, events and manual paths, and submissions with hundreds of
+in-order, plain, events and manual paths, the RL drivers waiting for each
+step's island plan on the host-side paths, and submissions with hundreds of
 ranges.  Any sanitizer report, leak (other than the graph module's
 process-lifetime stream pool) or misuse of a runtime object (a destroyed
 stream, event or graph used again) fails the test.  CPU only."""
@@ -32,7 +33,7 @@ def driver(tmp_path_factory):
     return out
 
 
-@pytest.mark.parametrize("part", ["graphs", "replay", "paths", "ranges"])
+@pytest.mark.parametrize("part", ["graphs", "replay", "paths", "ranges", "rlrun"])
 def test_host_code_under_sanitizers(driver, part):
     env = dict(os.environ,
                ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
