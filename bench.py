@@ -456,13 +456,13 @@ def cpu_baseline(inputs, args):
 
 
 def window_sweep(acs, inputs, torch, args):
-    """Window size W in {8, 16, 32} (Section VI-D) on the tiny random stream
+    """Window size W in {8, 16, 32, 64} (Section VI-D) on the tiny random stream
     (latency of one 64-kernel stream), the 64-sphere episode (kernels/s) and
     the dynamic network (latency of one inference), device path."""
     import numpy as np
     out = {}
     st = inputs.tiny_stream(0)
-    for W in (8, 16, 32):
+    for W in (8, 16, 32, 64):
         arena = torch.from_numpy(st.init.copy()).cuda()
         torch.cuda.synchronize()
         lat = []

@@ -5,9 +5,10 @@ candidate on the device path.
 
 Each candidate runs on its own copy of the scenes (the tuning steps do not
 advance the caller's scenes).  The search is exhaustive over (W, groups,
-workgroups per task, where the dependency checks run) with W in {8, 16, 32}
-and groups * pow2(W) <= 64, then over the queue depth for the best of
-those.  Rates within 2% of the fastest count as equal, and the cheapest of
+workgroups per task, where the dependency checks run) with W in {8, 16, 32,
+48, 64} and groups * pow2(W) <= 64, then over the queue depth for the best
+of those.  Windows wider than the 32 the paper evaluates are included
+because a wider window exposes more independent kernels (Section VI-D).  Rates within 2% of the fastest count as equal, and the cheapest of
 those is taken.  With one group the checks may run in the check wave ahead of the window
 (the default), on the host against the last W kernels, or in the window
 wave; with more groups always in the window wave.
@@ -30,7 +31,7 @@ def _pow2(x: int) -> int:
 CHECK_SITES = ("wave", "host", "window")
 
 
-def candidates(windows=(8, 16, 32), groups=(1, 2, 4, 8), wg=(1, 2, 4), sites=CHECK_SITES):
+def candidates(windows=(8, 16, 32, 48, 64), groups=(1, 2, 4, 8), wg=(1, 2, 4), sites=CHECK_SITES):
     for W, G, g, site in itertools.product(windows, groups, wg, sites):
         if G * _pow2(W) > acs.W_MAX:
             continue

@@ -17,7 +17,7 @@ def test_candidates_cover_the_documented_space():
     keys = {(c["W"], c["n_groups"], c["wg_per_task"], c["host_check_depth"], c["window_check"]) for c in got}
     assert len(keys) == len(got), "duplicate candidates"
     want = set()
-    for W, G, g in itertools.product((8, 16, 32), (1, 2, 4, 8), (1, 2, 4)):
+    for W, G, g in itertools.product((8, 16, 32, 48, 64), (1, 2, 4, 8), (1, 2, 4)):
         if G * pow2(W) > acs.W_MAX:
             continue
         if G == 1:
@@ -47,7 +47,7 @@ def test_autotune_picks_the_fastest_then_refines_queue_depth():
     best, table = tune.autotune(None, steps=1, timer=timer, tie=0.0)
     n = len(list(tune.candidates()))
     assert len(calls) == n + 2 and len(table) == n + 2
-    assert best["W"] == 32 and best["n_groups"] == 1 and best["wg_per_task"] == 4 and best["window_check"] == 1
+    assert best["W"] == 64 and best["n_groups"] == 1 and best["wg_per_task"] == 4 and best["window_check"] == 1
     assert best["queue_depth"] == 1024
     assert [c["queue_depth"] for c in calls[-2:]] == [256, 1024]
     assert all(calls[-1][k] == best[k] for k in best)
