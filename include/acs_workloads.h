@@ -91,8 +91,9 @@ int acs_nop_run(acs_window *w, int32_t n, int32_t chain, uint64_t spin_ns, doubl
 
 /* Overhead probe with wider kernels: n independent no-op kernels of nsegs
  * segments each (the first half reads, the rest writes, all disjoint from
- * every other kernel's), so that every dependency check compares nsegs
- * ranges per kernel and finds nothing.  nsegs in [1, 64] (beyond ACS_K_MAX
+ * every other kernel's, each kernel's spread so that its bounding interval
+ * meets every other kernel's), so that every dependency check compares
+ * nsegs ranges per kernel and finds nothing.  nsegs in [1, 64] (beyond ACS_K_MAX
  * merged as usual).  Drains the window; wall_ns as for acs_nop_run. */
 int acs_nop_segs_run(acs_window *w, int32_t n, int32_t nsegs, double *wall_ns);
 
@@ -102,8 +103,11 @@ int acs_nop_segs_run(acs_window *w, int32_t n, int32_t nsegs, double *wall_ns);
  * in the window; then reps times a new kernel of nsegs segments, disjoint
  * from all of them, is submitted (checked against the W - 1: every pair of
  * segments is tested), taken and completed.  The same loop with an empty
- * window gives the cost of everything but the check.  Segments beyond
- * ACS_K_MAX are merged as acs_submit always does (conservative).
+ * window gives the cost of everything but the check.  Each kernel's segments
+ * are spread so that its bounding interval meets every other kernel's: the
+ * host's filter on those intervals passes every kernel to the full test.
+ * Segments beyond ACS_K_MAX are merged as acs_submit always does
+ * (conservative).
  * ns_checked / ns_empty receive nanoseconds per submit-take-complete round
  * with the full and the empty window; tests_out (may be NULL) the segment
  * pairs tested per check.  No GPU is used.  ACS_EINVAL for W outside

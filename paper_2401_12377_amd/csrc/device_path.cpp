@@ -130,6 +130,7 @@ public:
         p.host_check = fc_ ? ACS_W_MAX : hc_;
         p.check_wave = fc_ ? 1 : 0;
         hist_n_ = 0;
+        hist_col_ = 0;
         if (!static_) {
             if ((e = hipEventCreate(&ev0_)) != hipSuccess) return hip_fail(e, "hipEventCreate");
             if ((e = hipEventCreate(&ev1_)) != hipSuccess) return hip_fail(e, "hipEventCreate");
@@ -400,18 +401,22 @@ private:
     // kernel k + 1 places back.
     uint64_t host_check(const Desc &d)
     {
-        const uint64_t M = (uint64_t)hc_;
-        const uint64_t n = std::min<uint64_t>(M, hist_n_);
-        // kernel j of the list sits in column j % M
-        uint64_t cols = 0;
-        for (uint64_t k = 0; k < n; k++) cols |= 1ull << ((hist_n_ - 1 - k) % M);
+        const int32_t M = hc_;
+        // Kernel j of the list sits in column j mod M, and hist_col_ is the
+        // column of the next one: the list fills columns 0 .. n - 1 (all M
+        // once it is full), and column c holds the kernel
+        // (hist_col_ - 1 - c) mod M + 1 places back.
+        const uint64_t n = std::min<uint64_t>((uint64_t)M, hist_n_);
+        const uint64_t cols = n >= 64 ? ~0ull : (1ull << n) - 1ull;
         host_tests_ += hist_.pair_tests(cols, d);
         uint64_t mask = 0;
         for (uint64_t hit = hist_.conflicts(cols, d); hit; hit &= hit - 1) {
-            const uint64_t c = (uint64_t)__builtin_ctzll(hit);
-            mask |= 1ull << ((hist_n_ - 1 - c) % M);   // column c holds the kernel that many places back, minus one
+            int32_t b = hist_col_ - 1 - __builtin_ctzll(hit);
+            b += b < 0 ? M : 0;
+            mask |= 1ull << b;
         }
-        hist_.put((int)(hist_n_ % M), d);
+        hist_.put(hist_col_, d);
+        hist_col_ = hist_col_ + 1 == M ? 0 : hist_col_ + 1;
         hist_n_++;
         return mask;
     }
@@ -445,6 +450,7 @@ private:
     bool fc_ = false;                // checks made by the check wave
     SegTable hist_;                  // the last M kernels submitted, kernel j in column j % M
     uint64_t hist_n_ = 0;
+    int32_t hist_col_ = 0;           // column of the next kernel: hist_n_ mod M
     uint64_t host_tests_ = 0;
     acs_config cfg_;
     HostCtrl *ctrl_ = nullptr;

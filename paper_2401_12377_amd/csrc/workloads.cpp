@@ -34,6 +34,29 @@ bool scene_ok(const acs_rl_scene *sc)
     return sc && sc->n >= 2 && sc->n <= acs::kRLMaxBodies && sc->plan && sc->iters >= 0 && sc->iters % 2 == 0;
 }
 
+// The ranges of probe kernel k (k < 2048), 64 bytes each, the first half
+// reads and the rest writes: the first range in a low strip and the last in
+// a high strip (64-byte slots indexed by k), the others 4 KiB apart in a
+// block of 1 MiB of the kernel's own between the strips.  No two kernels
+// share a byte, every kernel's bounding interval meets every other's (so
+// every pair of ranges is tested), and merging ranges beyond the eight a
+// kernel keeps joins the nearest ones, inside the kernel's own block.
+void probe_segs(uint64_t base, int32_t k, int32_t nsegs, std::vector<acs_seg> &r, std::vector<acs_seg> &wr)
+{
+    r.clear();
+    wr.clear();
+    for (int32_t s = 0; s < nsegs; s++) {
+        uint64_t at;
+        if (s == 0)
+            at = base + 64ull * (uint64_t)k;
+        else if (s == nsegs - 1)
+            at = base + (4ull << 30) + 64ull * (uint64_t)k;
+        else
+            at = base + (1ull << 20) * (1ull + (uint64_t)k) + 4096ull * (uint64_t)s;
+        (s < nsegs / 2 ? r : wr).push_back(acs_seg{at, 64});
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -174,12 +197,8 @@ int acs_nop_segs_run(acs_window *w, int32_t n, int32_t nsegs, double *out_ns)
     std::vector<acs_seg> r, wr;
     const double t0 = wall_ns();
     for (int32_t i = 0; i < n; i++) {
-        // kernel i: nsegs ranges of 64 bytes, 4 KiB apart, in its own 1 MiB
-        // block of an address range nothing touches (no body reads them)
-        r.clear();
-        wr.clear();
-        const uint64_t base = (1ull << 40) + (uint64_t)(i % 65536) * (1ull << 20);
-        for (int32_t s = 0; s < nsegs; s++) (s < nsegs / 2 ? r : wr).push_back(acs_seg{base + 4096ull * s, 64});
+        // in an address range nothing touches (no body reads them)
+        probe_segs(1ull << 40, i % 2048, nsegs, r, wr);
         const int rc = acs_submit(w, ACS_K_NOP, r.data(), (int32_t)r.size(), wr.data(), (int32_t)wr.size(), &a, sizeof(a), nullptr);
         if (rc != ACS_OK) return rc;
     }
@@ -191,14 +210,7 @@ int acs_nop_segs_run(acs_window *w, int32_t n, int32_t nsegs, double *out_ns)
 int acs_check_probe(int32_t W, int32_t nsegs, int32_t reps, double *ns_checked, double *ns_empty, double *tests_out)
 {
     if (W < 2 || W > ACS_W_MAX || nsegs < 2 || nsegs > 64 || reps < 1 || !ns_checked || !ns_empty) return ACS_EINVAL;
-    // kernel k's segments: nsegs ranges of 64 bytes, 4 KiB apart, in its own
-    // 1 MiB block; the first half are reads, the rest writes
-    auto segs = [&](int32_t k, std::vector<acs_seg> &r, std::vector<acs_seg> &wr) {
-        r.clear();
-        wr.clear();
-        const uint64_t base = (1ull << 32) + (uint64_t)k * (1ull << 20);
-        for (int32_t s = 0; s < nsegs; s++) (s < nsegs / 2 ? r : wr).push_back(acs_seg{base + 4096ull * s, 64});
-    };
+    auto segs = [&](int32_t k, std::vector<acs_seg> &r, std::vector<acs_seg> &wr) { probe_segs(1ull << 32, k, nsegs, r, wr); };
     acs_args_nop a = {0};
     double result[2] = {0, 0};
     double tests = 0;

@@ -1,7 +1,9 @@
 // Checks the host's vectorised dependency test (segtable.hpp) against the
 // pairwise definition (descs_conflict) on random kernels: every instruction
 // set the host offers, tables placed at misaligned addresses, segment counts
-// 1-8 with random write masks, ranges that touch, nest, or stand apart.
+// 1-8 with random write masks, ranges that touch, nest, or stand apart, and
+// kernels kept inside one of a few far-apart blocks of memory (so that the
+// bounding-interval filter drops columns) or spread over several of them.
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -19,6 +21,9 @@ static Desc random_desc(std::mt19937_64 &r)
     d.nseg = 1 + (uint32_t)(r() % ACS_K_MAX);
     const uint32_t nw = (uint32_t)(r() % (d.nseg + 1));
     d.wbits = (1u << nw) - 1u;   // writes first, as make_desc orders them
+    // half of the kernels keep to one block out of 8, 1 GiB apart
+    const bool block = r() % 2;
+    const uint64_t base = (r() % 8) << 30;
     for (uint32_t k = 0; k < d.nseg; k++) {
         const int kind = (int)(r() % 8);
         uint64_t s, e;
@@ -29,7 +34,9 @@ static Desc random_desc(std::mt19937_64 &r)
             s = UINT64_MAX - 64 - (r() % 64);
             e = s + 1 + (r() % 64);
         } else {
-            s = (r() % 4096) * 16;   // small space: frequent overlaps and touching ends
+            // small space: frequent overlaps and touching ends; each range in
+            // a block of its own when the kernel is not kept to one
+            s = (block ? base : (r() % 8) << 30) + (r() % 4096) * 16;
             e = s + 1 + (r() % 512);
         }
         d.s[k] = s;
@@ -44,7 +51,7 @@ int main(int argc, char **argv)
     std::mt19937_64 r(7);
     // tables at 8-byte offsets from a 64-byte boundary
     alignas(64) static unsigned char buf[8 * sizeof(SegTable) + 64];
-    long checked = 0, hits = 0;
+    long checked = 0, hits = 0, filtered = 0;
     for (int off = 0; off < 8; off++) {
         SegTable *t = new (buf + 8 * off + off * sizeof(SegTable)) SegTable();
         Desc held[64];
@@ -62,14 +69,24 @@ int main(int argc, char **argv)
                     if (descs_conflict(held[i], nd, &tt)) want |= 1ull << i;
                     tests += tt;
                 }
-            const uint64_t got[3] = {t->conflicts_scalar(cols, nd), t->conflicts(cols, nd),
+            int64_t lo, hi;
+            SegTable::bounds(nd, lo, hi);
+            const uint64_t ns = t->near_scalar(cols, lo, hi);
+            if ((want & ~ns) != 0 || (ns & ~cols) != 0) {
+                printf("FILTER DROPPED A CONFLICT offset %d round %d\n", off, it);
+                return 1;
+            }
+            filtered += __builtin_popcountll(cols & ~ns);
+            const uint64_t got[6] = {t->conflicts_scalar(cols, nd), t->conflicts(cols, nd), t->conflicts_scalar(ns, nd),
 #if defined(__x86_64__)
-                                     __builtin_cpu_supports("avx2") ? t->conflicts_avx2(cols, nd) : want
+                                     __builtin_cpu_supports("avx2") ? t->conflicts_avx2(cols, nd) : want,
+                                     __builtin_cpu_supports("avx2") ? t->conflicts_avx2(t->near_avx2(cols, lo, hi), nd) : want,
+                                     __builtin_cpu_supports("avx512f") ? (t->near_avx512(cols, lo, hi) == ns ? want : ~want) : want
 #else
-                                     want
+                                     want, want, want
 #endif
             };
-            for (int v = 0; v < 3; v++)
+            for (int v = 0; v < 6; v++)
                 if (got[v] != want) {
                     printf("MISMATCH variant %d offset %d round %d: %llx vs %llx\n", v, off, it,
                            (unsigned long long)got[v], (unsigned long long)want);
@@ -88,6 +105,6 @@ int main(int argc, char **argv)
         }
         t->~SegTable();
     }
-    printf("ok %ld checks, %ld conflicts\n", checked, hits);
+    printf("ok %ld checks, %ld conflicts, %ld columns dropped by the bounds\n", checked, hits, filtered);
     return 0;
 }
