@@ -307,17 +307,19 @@ __device__ inline void fifo_wave(const DevParams &p, FetchShared *fs)
                     cons = consumed[g];
                     ft = ftail[g];
                 }
-            dst_off[r] = ~0u;
-            ddst[r] = nullptr;
-            v[r] = make_uint4(0u, 0u, 0u, 0u);
-            if (j < total) {
-                const ACS_GAS DevDesc *src = gp(p.ring) + (uint64_t)gg * ring_cap + ((cons + ii) & p.ring_mask);
-                v[r] = ld4(reinterpret_cast<const ACS_GAS uint4 *>(src) + c);
-                dst_off[r] = (gg * depth + ((ft + ii) & (depth - 1u))) * 256u + c * 16u;
-                // the descriptor's group sequence number is its place in the group's ring
-                ddst[r] = reinterpret_cast<ACS_GAS uint64_t *>(&st->dring[gg][(uint32_t)(cons + ii) & (kDescRing - 1u)]) +
-                          2u * c;
-            }
+            // Every lane loads, the lanes without a job from the ring's first
+            // slot (always mapped; the value is dropped): a load under a
+            // branch gets its own wait for completion, and the rows' host
+            // reads would follow each other instead of overlapping.
+            const bool job = j < total;
+            const ACS_GAS DevDesc *src =
+                gp(p.ring) + (job ? (uint64_t)gg * ring_cap + ((cons + ii) & p.ring_mask) : 0ull);
+            v[r] = ld4(reinterpret_cast<const ACS_GAS uint4 *>(src) + c);
+            dst_off[r] = job ? (gg * depth + ((ft + ii) & (depth - 1u))) * 256u + c * 16u : ~0u;
+            // the descriptor's group sequence number is its place in the group's ring
+            ddst[r] = job ? reinterpret_cast<ACS_GAS uint64_t *>(&st->dring[gg][(uint32_t)(cons + ii) & (kDescRing - 1u)]) +
+                                2u * c
+                          : nullptr;
         }
         // control lines: newly published descriptors are read in later
         // rounds, after this acquire
