@@ -131,6 +131,9 @@ public:
         p.check_wave = fc_ ? 1 : 0;
         hist_n_ = 0;
         hist_col_ = 0;
+        held_ranges_ = held_writes_ = 0;
+        memset(col_ranges_, 0, sizeof(col_ranges_));
+        memset(col_writes_, 0, sizeof(col_writes_));
         if (!static_) {
             if ((e = hipEventCreate(&ev0_)) != hipSuccess) return hip_fail(e, "hipEventCreate");
             if ((e = hipEventCreate(&ev1_)) != hipSuccess) return hip_fail(e, "hipEventCreate");
@@ -197,23 +200,26 @@ public:
             _mm_pause();
         }
         DevDesc &r = ring_[(size_t)g * ring_cap_ + (submitted_[g] & (ring_cap_ - 1))];
-        DevDesc tmp;
-        memset(&tmp, 0, sizeof(tmp));
-        tmp.seq = d.seq;
-        tmp.kid = d.kid;
-        tmp.npieces = d.npieces;
-        tmp.nseg = d.nseg;
-        tmp.wbits = d.wbits;
-        for (int k = 0; k < ACS_K_MAX; k++) {
-            tmp.s[k] = d.s[k];
-            tmp.e[k] = d.e[k];
+        // Written in place (the ring is ordinary cached host memory, and the
+        // device reads it only after the tail below says so).  With the
+        // checks on the host the device reads only the head, so the ranges
+        // are not written.
+        r.seq = d.seq;
+        r.kid = d.kid;
+        r.npieces = d.npieces;
+        r.gseq = (uint32_t)submitted_[g];   // the group's own numbering, without gaps
+        r.group = (uint32_t)g;
+        r.host_up = hc_ > 0 ? host_check(d) : 0;
+        memcpy(r.args, d.args, ACS_ARGS_MAX);
+        r.nseg = d.nseg;
+        r.wbits = d.wbits;
+        if (hc_ == 0) {
+            memset(r.pad, 0, sizeof(r.pad));
+            for (int k = 0; k < ACS_K_MAX; k++) {
+                r.s[k] = d.s[k];
+                r.e[k] = d.e[k];
+            }
         }
-        memcpy(tmp.args, d.args, ACS_ARGS_MAX);
-        tmp.gseq = (uint32_t)submitted_[g];   // the group's own numbering, without gaps
-        tmp.group = (uint32_t)g;
-        if (hc_ > 0) tmp.host_up = host_check(d);
-        // with the checks on the host the device reads only the head
-        memcpy((void *)&r, &tmp, hc_ > 0 ? (size_t)kDescHeadBytes : sizeof(DevDesc));
         submitted_[g]++;
         total_submitted_++;
         __atomic_store_n(&ctrl_->tail[g], submitted_[g], __ATOMIC_RELEASE);
@@ -408,13 +414,20 @@ private:
         // (hist_col_ - 1 - c) mod M + 1 places back.
         const uint64_t n = std::min<uint64_t>((uint64_t)M, hist_n_);
         const uint64_t cols = n >= 64 ? ~0ull : (1ull << n) - 1ull;
-        host_tests_ += hist_.pair_tests(cols, d);
+        // segment pairs the definition compares: a write against every held
+        // range, a read against every held write (running totals of the list)
+        const uint32_t nw = (uint32_t)__builtin_popcount(d.wbits & ((1u << d.nseg) - 1u));
+        host_tests_ += (uint64_t)nw * held_ranges_ + (uint64_t)(d.nseg - nw) * held_writes_;
         uint64_t mask = 0;
         for (uint64_t hit = hist_.conflicts(cols, d); hit; hit &= hit - 1) {
             int32_t b = hist_col_ - 1 - __builtin_ctzll(hit);
             b += b < 0 ? M : 0;
             mask |= 1ull << b;
         }
+        held_ranges_ += d.nseg - col_ranges_[hist_col_];
+        held_writes_ += nw - col_writes_[hist_col_];
+        col_ranges_[hist_col_] = (uint8_t)d.nseg;
+        col_writes_[hist_col_] = (uint8_t)nw;
         hist_.put(hist_col_, d);
         hist_col_ = hist_col_ + 1 == M ? 0 : hist_col_ + 1;
         hist_n_++;
@@ -451,6 +464,8 @@ private:
     SegTable hist_;                  // the last M kernels submitted, kernel j in column j % M
     uint64_t hist_n_ = 0;
     int32_t hist_col_ = 0;           // column of the next kernel: hist_n_ mod M
+    uint8_t col_ranges_[64] = {}, col_writes_[64] = {};   // ranges and writes of each column's kernel
+    uint32_t held_ranges_ = 0, held_writes_ = 0;        // their sums over the list
     uint64_t host_tests_ = 0;
     acs_config cfg_;
     HostCtrl *ctrl_ = nullptr;

@@ -844,8 +844,10 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
         // waits for work that an earlier ticket holds.
         if (newly) {
             // the upstream lists stored above are complete before any entry
-            // that points at them.  0x0F70: vmcnt 0, expcnt 7, lgkmcnt 15.
-            if (drain) __builtin_amdgcn_s_waitcnt(0x0F70);
+            // that points at them, and so are the trace records' initial
+            // values (else a worker's update of the record could land first
+            // and be overwritten).  0x0F70: vmcnt 0, expcnt 7, lgkmcnt 15.
+            if (drain || tr) __builtin_amdgcn_s_waitcnt(0x0F70);
             const bool mine = (newly >> lane) & 1ull;
             int32_t total;
             const uint32_t before = (uint32_t)wave_exclusive_scan(mine ? (int32_t)mynp : 0, &total);
