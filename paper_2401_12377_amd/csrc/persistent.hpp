@@ -836,6 +836,41 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
             }
         }
 
+        // ---- completions: a slot whose kernel stored its word is free again.
+        // Examined before this pass's work-queue stores are issued: waiting
+        // for the poll waits for every older memory operation of the wave,
+        // and the stores of the previous pass have had the admission work to
+        // complete, while this pass's would still be on their way to memory.
+        // Slots admitted in this pass were free when the poll was issued, so
+        // none of them is among those found complete.
+        {
+            const uint64_t done = __builtin_amdgcn_ballot_w64(occ && (int32_t)(cdone - (myg + 1u)) >= 0);
+            if (done) {
+                if (tr) {
+                    const uint64_t now = wall_clock64();
+                    if (((done >> lane) & 1ull) && myseq < p.trace_cap) {
+                        tput(&trace[myseq].ev_retire, (int64_t)(ev + __builtin_popcountll(done & lane_lt)));
+                        tput(&trace[myseq].t_retire, (int64_t)now);
+                    }
+                }
+                ev += (uint64_t)__builtin_popcountll(done);
+#pragma unroll
+                for (int g = 0; g < NG; g++)
+                    if (g < G) retired[g] += (uint64_t)__builtin_popcountll(done & (wpmask << (g * Wp)));
+                if (!ahead) {
+                    if (((done >> sl) & 1ull) && rep < R) {
+#pragma unroll
+                        for (int m = 0; m < kSegs; m++) ss[m] = se[m] = 0;
+                    }
+                    const uint64_t rdone = done * repmul;
+#pragma unroll
+                    for (int m = 0; m < kSegs; m++) wmask[m] &= ~rdone;
+                }
+                valid &= ~done;
+                progress = true;
+            }
+        }
+
         // ---- dispatch.  Every admitted kernel is handed out at once: its
         // workers wait for the completion words of the kernels in its
         // upstream list themselves.  Entries are published in admission
@@ -874,35 +909,6 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
             }
             pub += (uint64_t)(uint32_t)total;
             ev += (uint64_t)__builtin_popcountll(newly);
-        }
-
-        // ---- completions: a slot whose kernel stored its word is free again
-        {
-            const uint64_t done = __builtin_amdgcn_ballot_w64(occ && (int32_t)(cdone - (myg + 1u)) >= 0);
-            if (done) {
-                if (tr) {
-                    const uint64_t now = wall_clock64();
-                    if (((done >> lane) & 1ull) && myseq < p.trace_cap) {
-                        tput(&trace[myseq].ev_retire, (int64_t)(ev + __builtin_popcountll(done & lane_lt)));
-                        tput(&trace[myseq].t_retire, (int64_t)now);
-                    }
-                }
-                ev += (uint64_t)__builtin_popcountll(done);
-#pragma unroll
-                for (int g = 0; g < NG; g++)
-                    if (g < G) retired[g] += (uint64_t)__builtin_popcountll(done & (wpmask << (g * Wp)));
-                if (!ahead) {
-                    if (((done >> sl) & 1ull) && rep < R) {
-#pragma unroll
-                        for (int m = 0; m < kSegs; m++) ss[m] = se[m] = 0;
-                    }
-                    const uint64_t rdone = done * repmul;
-#pragma unroll
-                    for (int m = 0; m < kSegs; m++) wmask[m] &= ~rdone;
-                }
-                valid &= ~done;
-                progress = true;
-            }
         }
 
         // ---- the host learns about completions when a group drains: one
