@@ -89,6 +89,7 @@ enum { ACS_PATH_INORDER = 0, ACS_PATH_PLAIN = 1, ACS_PATH_DEVICE = 2, ACS_PATH_M
 #define ACS_W_MAX 64       /* one window slot per wavefront lane */
 #define ACS_K_MAX 8        /* read + write segments kept per kernel */
 #define ACS_ARGS_MAX 64    /* bytes of task arguments */
+#define ACS_HOST_CHECK_MAX 128 /* longest host check list (host_check_depth) */
 
 typedef struct {
     int32_t path;            /* ACS_PATH_* (default ACS_PATH_DEVICE) */
@@ -102,11 +103,14 @@ typedef struct {
     int32_t device;          /* HIP device ordinal (default 0) */
     int32_t n_groups;        /* independent windows of W slots each (default 1; see acs_submit_group) */
     int32_t host_check_depth;/* device path, one group: 0 (default) = dependency checks in the window
-                                wave; M in [1, 64] = the host/device split of Section IV-C: the host
-                                checks each kernel against the kernels of the M sequence numbers
-                                before it (its scheduled list, possibly stale), the device drops
-                                upstream kernels that already completed and holds a kernel back
-                                while one more than M older is still in the window.  Same
+                                wave; M in [1, ACS_HOST_CHECK_MAX] = the host/device split of
+                                Section IV-C: the host checks each kernel against the kernels of
+                                the M sequence numbers before it (its scheduled list, possibly
+                                stale), the device drops upstream kernels that already completed
+                                and holds a kernel back while one more than M older is still in
+                                the window.  M may exceed W: the list then also covers kernels
+                                that left the window or wait for a slot, so that one long
+                                kernel holds back only the kernels more than M after it.  Same
                                 schedules; other paths ignore it. */
     int32_t window_check;    /* device path, one group, host_check_depth 0: 0 (default) = the
                                 same split inside the device: a wave ahead of the window checks

@@ -26,6 +26,7 @@ PATH_INORDER, PATH_PLAIN, PATH_DEVICE, PATH_MANUAL, PATH_EVENTS = 0, 1, 2, 3, 4
 PATHS = {"inorder": PATH_INORDER, "plain": PATH_PLAIN, "device": PATH_DEVICE, "manual": PATH_MANUAL,
          "events": PATH_EVENTS}
 W_MAX, K_MAX, ARGS_MAX = 64, 8, 64
+HOST_CHECK_MAX = 128   # longest host check list (acs_config.host_check_depth)
 SEG_ALL = (0, (1 << 64) - 1)
 
 K_NOP, K_SCALE, K_AXPY, K_SUM = 0, 1, 2, 3

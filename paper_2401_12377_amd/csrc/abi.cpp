@@ -370,8 +370,8 @@ int validate_config(const acs_window *w, const acs_config *cfg)
         if (wp * cfg->n_groups > ACS_W_MAX)
             return fail(ACS_EINVAL, "device path: n_groups times W rounded up to a power of two must be at most 64");
     }
-    if (cfg->host_check_depth < 0 || cfg->host_check_depth > ACS_W_MAX)
-        return fail(ACS_EINVAL, "host_check_depth must be in [0, 64]");
+    if (cfg->host_check_depth < 0 || cfg->host_check_depth > ACS_HOST_CHECK_MAX)
+        return fail(ACS_EINVAL, "host_check_depth must be in [0, " + std::to_string(ACS_HOST_CHECK_MAX) + "]");
     if (cfg->path == ACS_PATH_DEVICE && cfg->host_check_depth > 0 && cfg->n_groups != 1)
         return fail(ACS_EINVAL, "host checks need a single window group");
     if (cfg->window_check != 0 && cfg->window_check != 1) return fail(ACS_EINVAL, "window_check must be 0 or 1");

@@ -36,7 +36,10 @@ struct DevDesc {
     uint8_t args[ACS_ARGS_MAX];
     uint32_t nseg;          // segments in use (reads and writes)
     uint32_t wbits;         // bit k set: segment k is a write
-    uint32_t pad[6];
+    // bit b set: the kernel with gseq - 65 - b conflicts (host checks
+    // against more than 64 kernels only; zero otherwise)
+    uint64_t host_up_hi;
+    uint32_t pad[4];
     uint64_t s[kSegs];
     uint64_t e[kSegs];
 };
@@ -47,12 +50,14 @@ constexpr int kGseqDword = 4;
 constexpr int kHostUpDword = 6;
 constexpr int kNsegDword = 24;
 constexpr int kWbitsDword = 25;
+constexpr int kHostUpHiDword = 26;
 constexpr int kSegStartDword = 32;         // s[k] is dwords 32 + 2k and 33 + 2k
 constexpr int kSegEndDword = 48;           // e[k] is dwords 48 + 2k and 49 + 2k
 constexpr uint32_t kDescHeadBytes = 128;   // what the window and workers read
 static_assert(offsetof(DevDesc, kid) == 4 * kKidDword && offsetof(DevDesc, npieces) == 4 * kNpiecesDword &&
                   offsetof(DevDesc, gseq) == 4 * kGseqDword && offsetof(DevDesc, host_up) == 4 * kHostUpDword &&
-                  offsetof(DevDesc, nseg) == 4 * kNsegDword && offsetof(DevDesc, wbits) == 4 * kWbitsDword,
+                  offsetof(DevDesc, nseg) == 4 * kNsegDword && offsetof(DevDesc, wbits) == 4 * kWbitsDword &&
+                  offsetof(DevDesc, host_up_hi) == 4 * kHostUpHiDword,
               "descriptor dwords");
 static_assert(offsetof(DevDesc, s) == 4 * kSegStartDword && offsetof(DevDesc, e) == 4 * kSegEndDword,
               "segment dwords");
@@ -90,7 +95,8 @@ struct HostCtrl {
 // its group waits until dseq[group][k % kSeqRing] has reached k + 1.  The
 // ring is large enough because no two kernels of one group in flight (or
 // waited for) are kSeqRing apart: admission holds a kernel while one 64 or
-// more older is still in the window, and dependencies reach back at most 64.
+// more older is still in the window (up to ACS_HOST_CHECK_MAX with the
+// checks on the host), and dependencies reach back no further.
 // Kernels of several pieces count their pieces in cnt[group][gseq %
 // kSeqRing] first (64 per piece); the last piece resets the counter before
 // it marks the kernel complete.
@@ -101,7 +107,7 @@ struct HostCtrl {
 constexpr uint32_t kQueueCap = 1u << 16;       // work queue entries (power of two)
 constexpr uint32_t kMaxPieces = 256;           // pieces per task
 constexpr uint32_t kSentinelGroup = 0xFF;
-constexpr uint32_t kSeqRing = 128;             // completion words per group
+constexpr uint32_t kSeqRing = 512;             // completion words per group
 constexpr uint32_t kDescRing = 512;            // device descriptor ring entries per group
 
 constexpr uint64_t queue_entry(uint64_t ticket, uint32_t group, uint32_t piece, uint32_t gseq)

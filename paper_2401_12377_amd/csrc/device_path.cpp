@@ -123,7 +123,7 @@ public:
         p.W = W_;
         p.n_workers = n_workers_;
         p.n_groups = groups_;
-        hc_ = groups_ == 1 ? std::max(0, std::min(cfg_.host_check_depth, ACS_W_MAX)) : 0;
+        hc_ = groups_ == 1 ? std::max(0, std::min(cfg_.host_check_depth, ACS_HOST_CHECK_MAX)) : 0;
         // one window: the checks run ahead of it, on the host when asked,
         // else in the check wave unless the window wave is asked to make them
         fc_ = groups_ == 1 && hc_ == 0 && cfg_.window_check == 0;
@@ -209,7 +209,10 @@ public:
         r.npieces = d.npieces;
         r.gseq = (uint32_t)submitted_[g];   // the group's own numbering, without gaps
         r.group = (uint32_t)g;
-        r.host_up = hc_ > 0 ? host_check(d) : 0;
+        uint64_t up_lo = 0, up_hi = 0;
+        if (hc_ > 0) host_check(d, up_lo, up_hi);
+        r.host_up = up_lo;
+        r.host_up_hi = up_hi;
         memcpy(r.args, d.args, ACS_ARGS_MAX);
         r.nseg = d.nseg;
         r.wbits = d.wbits;
@@ -403,35 +406,40 @@ private:
     // without gaps), the host's scheduled list.  The list is stale by design:
     // some of them may have completed (the workers find those complete), and
     // none older can still be in the window when the kernel is inserted (the
-    // device holds it back until that is so).  Bit k of the result: the
-    // kernel k + 1 places back.
-    uint64_t host_check(const Desc &d)
+    // device holds it back until that is so).  Bit b of lo: the kernel b + 1
+    // places back; bit b of hi: the kernel b + 65 places back (M > 64).
+    void host_check(const Desc &d, uint64_t &lo, uint64_t &hi)
     {
         const int32_t M = hc_;
-        // Kernel j of the list sits in column j mod M, and hist_col_ is the
-        // column of the next one: the list fills columns 0 .. n - 1 (all M
-        // once it is full), and column c holds the kernel
-        // (hist_col_ - 1 - c) mod M + 1 places back.
+        // Kernel j of the list sits in column j mod M (columns 64 and up in
+        // the second table), and hist_col_ is the column of the next one: the
+        // list fills columns 0 .. n - 1 (all M once it is full), and column c
+        // holds the kernel (hist_col_ - 1 - c) mod M + 1 places back.
         const uint64_t n = std::min<uint64_t>((uint64_t)M, hist_n_);
-        const uint64_t cols = n >= 64 ? ~0ull : (1ull << n) - 1ull;
         // segment pairs the definition compares: a write against every held
         // range, a read against every held write (running totals of the list)
         const uint32_t nw = (uint32_t)__builtin_popcount(d.wbits & ((1u << d.nseg) - 1u));
         host_tests_ += (uint64_t)nw * held_ranges_ + (uint64_t)(d.nseg - nw) * held_writes_;
-        uint64_t mask = 0;
-        for (uint64_t hit = hist_.conflicts(cols, d); hit; hit &= hit - 1) {
-            int32_t b = hist_col_ - 1 - __builtin_ctzll(hit);
-            b += b < 0 ? M : 0;
-            mask |= 1ull << b;
+        lo = hi = 0;
+        for (int32_t t = 0; t < 2 && 64ull * (uint64_t)t < n; t++) {
+            const uint64_t cnt = n - 64ull * (uint64_t)t;
+            const uint64_t cols = cnt >= 64 ? ~0ull : (1ull << cnt) - 1ull;
+            for (uint64_t hit = hist_[t].conflicts(cols, d); hit; hit &= hit - 1) {
+                int32_t b = hist_col_ - 1 - (64 * t + __builtin_ctzll(hit));
+                b += b < 0 ? M : 0;
+                if (b < 64)
+                    lo |= 1ull << b;
+                else
+                    hi |= 1ull << (b - 64);
+            }
         }
         held_ranges_ += d.nseg - col_ranges_[hist_col_];
         held_writes_ += nw - col_writes_[hist_col_];
         col_ranges_[hist_col_] = (uint8_t)d.nseg;
         col_writes_[hist_col_] = (uint8_t)nw;
-        hist_.put(hist_col_, d);
+        hist_[hist_col_ / 64].put(hist_col_ % 64, d);
         hist_col_ = hist_col_ + 1 == M ? 0 : hist_col_ + 1;
         hist_n_++;
-        return mask;
     }
 
     // A persistent kernel that left early (fault or abort) can no longer
@@ -461,10 +469,12 @@ private:
     uint64_t polls_ = 0;
     int32_t hc_ = 0;                 // host-check depth M (0: checks on the device)
     bool fc_ = false;                // checks made by the check wave
-    SegTable hist_;                  // the last M kernels submitted, kernel j in column j % M
+    SegTable hist_[2];               // the last M kernels submitted, kernel j in column j % M
+                                     // (columns 64 and up in the second table)
     uint64_t hist_n_ = 0;
     int32_t hist_col_ = 0;           // column of the next kernel: hist_n_ mod M
-    uint8_t col_ranges_[64] = {}, col_writes_[64] = {};   // ranges and writes of each column's kernel
+    uint8_t col_ranges_[ACS_HOST_CHECK_MAX] = {}, col_writes_[ACS_HOST_CHECK_MAX] = {};   // ranges and writes
+                                                                                          // of each column's kernel
     uint32_t held_ranges_ = 0, held_writes_ = 0;        // their sums over the list
     uint64_t host_tests_ = 0;
     acs_config cfg_;

@@ -58,8 +58,13 @@ constexpr uint32_t kLdsDescs = 128;   // descriptors staged in LDS (32 KB), shar
 constexpr uint32_t kAdmitBatch = 16;  // kernels per group admitted per loop with checks at insert
 constexpr uint32_t kSpan = 64;        // a kernel waits while one kSpan or more older (same
                                       // group) is in the window: upstream lists reach back 64
-static_assert(kSeqRing >= 2 * kSpan, "completion ring must cover two spans");
-static_assert(kDescRing >= kLdsDescs + 2 * kSpan + 1, "descriptor ring must cover staging and window");
+constexpr uint32_t kHostSpan = ACS_HOST_CHECK_MAX;   // the same with the checks on the host
+static_assert(kHostSpan >= kSpan && kHostSpan <= 128, "upstream lists are two 64-bit words");
+// Kernels in flight span at most kHostSpan + 1 sequence numbers and wait for
+// kernels at most kHostSpan before them: no two live completion words share a
+// place in the ring.
+static_assert(kSeqRing >= 2 * kHostSpan + 2, "completion ring must cover two spans");
+static_assert(kDescRing >= kLdsDescs + 2 * kHostSpan + 1, "descriptor ring must cover staging and window");
 
 struct FetchShared {
     uint32_t tail[kMaxGroups];   // descriptors ready for the window wave per group (FIFO or check wave)
@@ -485,12 +490,15 @@ __device__ __forceinline__ uint64_t pair_hits(const DevDesc *d, uint32_t nseg, u
 }
 
 // Slots of the mask `cand` (one group) whose kernels the kernel with group
-// sequence number g and upstream list hup depends on (bit b of hup: the
-// kernel g - 1 - b).  Each lane tests the kernel of its own slot.
-__device__ __forceinline__ uint64_t slots_upstream(uint64_t cand, uint32_t myg, uint32_t g, uint64_t hup, uint32_t lane)
+// sequence number g and upstream list (hup, hup2) depends on (bit b of hup:
+// the kernel g - 1 - b; bit b of hup2: the kernel g - 65 - b).  Each lane
+// tests the kernel of its own slot.
+__device__ __forceinline__ uint64_t slots_upstream(uint64_t cand, uint32_t myg, uint32_t g, uint64_t hup, uint64_t hup2,
+                                                   uint32_t lane)
 {
     const uint32_t back = g - 1u - myg;
-    return __builtin_amdgcn_ballot_w64(((cand >> lane) & 1ull) && back < 64u && ((hup >> (back & 63u)) & 1ull));
+    const uint64_t word = back < 64u ? hup : hup2;
+    return __builtin_amdgcn_ballot_w64(((cand >> lane) & 1ull) && back < 128u && ((word >> (back & 63u)) & 1ull));
 }
 
 // Largest of x over the wave (x < 2^31): an inclusive running maximum by DPP
@@ -553,6 +561,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
     uint32_t myg = 0, mynp = 0;   // group sequence number, pieces
     int32_t mykid = 0;
     uint64_t myseq = 0, myhup = 0;   // submission index (traces), upstream list by distance
+    uint64_t myhup2 = 0;             // its second word (distances 65 to 128, checks on the host)
     // pair tests: this lane's slot ranges (replicated), and per position the
     // lanes whose slot range there is a write; unused and free positions hold
     // the empty range [0, 0), which intersects nothing
@@ -623,6 +632,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                         const uint32_t npr = d->npieces;
                         mynp = npr < kMaxPieces ? (npr ? npr : 1u) : kMaxPieces;
                         myhup = d->host_up;
+                        myhup2 = d->host_up_hi;
                         myg = head[0] + r;
                         if (store_up && myhup != 0)
                             __hip_atomic_store(reinterpret_cast<ACS_GAS uint64_t *>(&st->dring[0][myg & (kDescRing - 1u)].host_up),
@@ -635,7 +645,8 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                         for (uint64_t m = newly; m; m &= m - 1, k++) {
                             const int s = __builtin_ctzll(m);
                             const uint64_t vin = valid | (newly & ((1ull << s) - 1ull));
-                            const uint64_t upm = slots_upstream(vin, myg, readlane32(myg, s), readlane64(myhup, s), lane);
+                            const uint64_t upm =
+                                slots_upstream(vin, myg, readlane32(myg, s), readlane64(myhup, s), readlane64(myhup2, s), lane);
                             const uint64_t sq = readlane64(myseq, s);
                             const int32_t kd = (int32_t)readlane32((uint32_t)mykid, s);
                             if (lane == 0 && sq < p.trace_cap) trace_insert(&trace[sq], sq, s, kd, ev + k, vin, upm);
@@ -695,6 +706,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                         mynp = npr < kMaxPieces ? (npr ? npr : 1u) : kMaxPieces;
                         myg = gq;
                         myhup = hup;
+                        myhup2 = 0;
                     }
                     const uint64_t rbit = bit * repmul;
 #pragma unroll
@@ -795,6 +807,7 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                         mynp = npr < kMaxPieces ? (npr ? npr : 1u) : kMaxPieces;
                         myg = hg;
                         myhup = hupl;
+                        myhup2 = 0;
                         if (tr && myseq < p.trace_cap) {
                             const uint64_t rank = (uint64_t)__builtin_popcount(adm & ((1u << grp) - 1u));
                             trace_insert(&trace[myseq], myseq, (int32_t)lane, mykid, ev + rank, valid & mygroup,
@@ -940,7 +953,8 @@ __device__ inline void window_wave(const DevParams &p, FetchShared *fs)
                 for (uint64_t m = valid; m; m &= m - 1) {
                     const int s = __builtin_ctzll(m);
                     const uint64_t gm = (wmaskslots & wpmask) << (((uint32_t)s / Wp) * Wp);
-                    const uint64_t u = slots_upstream(valid & gm, myg, readlane32(myg, s), readlane64(myhup, s), lane);
+                    const uint64_t u =
+                        slots_upstream(valid & gm, myg, readlane32(myg, s), readlane64(myhup, s), readlane64(myhup2, s), lane);
                     if ((int)lane == s) myup = u;
                 }
                 const bool v = (valid >> lane) & 1ull;
@@ -1044,17 +1058,24 @@ __device__ inline void worker(const DevParams &p, uint8_t *smem, Mail *mail)
                 mail->seq = te->seq;
                 margs[lane & 7u] = reinterpret_cast<const ACS_GAS uint64_t *>(te->args)[lane & 7u];
                 // wait until every upstream kernel has stored its completion
-                // word (lane b watches the kernel b + 1 places back)
+                // word (lane b watches the kernel b + 1 places back and, with
+                // the second word, the kernel b + 65 places back)
                 const uint64_t hup = uni64(te->host_up);
-                if (hup != 0) {
-                    const bool watch = (hup >> lane) & 1ull;
-                    const uint32_t k = g - 1u - lane;
+                const uint64_t hup2 = uni64(te->host_up_hi);
+                if ((hup | hup2) != 0) {
+                    const bool watch = (hup >> lane) & 1ull, watch2 = (hup2 >> lane) & 1ull;
+                    const uint32_t k = g - 1u - lane, k2 = g - 65u - lane;
                     for (uint32_t spin = 1;; spin++) {
                         bool ok = true;
                         if (watch) {
                             const uint32_t c =
                                 __hip_atomic_load(&st->dseq[grp][k & (kSeqRing - 1u)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                             ok = (int32_t)(c - (k + 1u)) >= 0;
+                        }
+                        if (hup2 != 0 && watch2) {
+                            const uint32_t c =
+                                __hip_atomic_load(&st->dseq[grp][k2 & (kSeqRing - 1u)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            ok = ok && (int32_t)(c - (k2 + 1u)) >= 0;
                         }
                         if (__builtin_amdgcn_ballot_w64(!ok) == 0) break;
                         if ((spin & 1023u) == 0 &&

@@ -8,10 +8,13 @@ advance the caller's scenes).  The search is exhaustive over (W, groups,
 workgroups per task, where the dependency checks run) with W in {8, 16, 32,
 48, 64} and groups * pow2(W) <= 64, then over the queue depth for the best
 of those.  Windows wider than the 32 the paper evaluates are included
-because a wider window exposes more independent kernels (Section VI-D).  Rates within 2% of the fastest count as equal, and the cheapest of
-those is taken.  With one group the checks may run in the check wave ahead of the window
-(the default), on the host against the last W kernels, or in the window
-wave; with more groups always in the window wave.
+because a wider window exposes more independent kernels (Section VI-D).
+Rates within 2% of the fastest count as equal, and the cheapest of those is
+taken.  With one group the checks may run in the check wave ahead of the
+window (the default), on the host against the last W kernels or the last 2W
+(at most 128: a long kernel then holds back only the kernels more than 2W
+after it), or in the window wave; with more groups always in the window
+wave.
 """
 from __future__ import annotations
 
@@ -28,7 +31,15 @@ def _pow2(x: int) -> int:
     return p
 
 
-CHECK_SITES = ("wave", "host", "window")
+CHECK_SITES = ("wave", "host", "host2", "window")
+
+
+def _host_depth(W: int, site: str) -> int:
+    if site == "host":
+        return W
+    if site == "host2":
+        return min(2 * W, acs.HOST_CHECK_MAX)
+    return 0
 
 
 def candidates(windows=(8, 16, 32, 48, 64), groups=(1, 2, 4, 8), wg=(1, 2, 4), sites=CHECK_SITES):
@@ -38,7 +49,7 @@ def candidates(windows=(8, 16, 32, 48, 64), groups=(1, 2, 4, 8), wg=(1, 2, 4), s
         if G > 1 and site != sites[0]:
             continue   # more than one group: the window wave checks, whatever is asked
         yield {"W": W, "n_groups": G, "wg_per_task": g, "queue_depth": 4096,
-               "host_check_depth": W if (G == 1 and site == "host") else 0,
+               "host_check_depth": _host_depth(W, site) if G == 1 else 0,
                "window_check": 1 if (G == 1 and site == "window") else 0}
 
 

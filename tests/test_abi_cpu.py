@@ -463,10 +463,15 @@ def test_graph_recording_states():
 
 
 def test_host_check_depth_validation():
-    for kw in ({"host_check_depth": 65}, {"host_check_depth": -1}, {"host_check_depth": 4, "n_groups": 2}):
+    for kw in ({"host_check_depth": 129}, {"host_check_depth": -1}, {"host_check_depth": 4, "n_groups": 2}):
         with pytest.raises(acs.AcsError) as e:
             acs.Window(8, path="device", **kw)
         assert e.value.code == acs.EINVAL
+    # the host's list may be longer than the window (up to 128 kernels); the
+    # range is checked on every path
+    with pytest.raises(acs.AcsError):
+        acs.Window(8, path="manual", host_check_depth=129)
+    acs.Window(8, path="manual", host_check_depth=128).destroy()
     # other paths accept and ignore it
     with acs.Window(8, path="manual", host_check_depth=4) as w:
         w.submit(acs.K_NOP, [], [(0, 1)], acs.ArgsNop(0))

@@ -119,7 +119,8 @@ def test_group_sync_and_validation(torch):
 
 @pytest.mark.parametrize("G,W,wg,hc,qd", [(1, 16, 2, 0, 4096), (4, 16, 1, 0, 4096),
                                           (1, 32, 1, 32, 256), (1, 48, 1, 48, 1024),   # the autotuner's picks
-                                          (1, 64, 1, 64, 1024), (1, 64, 1, 64, 256), (1, 32, 1, 0, 1024)])
+                                          (1, 64, 1, 64, 1024), (1, 64, 1, 64, 256), (1, 64, 1, 128, 256),
+                                          (1, 32, 1, 0, 1024)])
 def test_full_size_batch_matches_oracle(torch, G, W, wg, hc, qd):
     """The batched workload at full size (256 scenes of 16-512 bodies, 20
     steps, one persistent launch): every scene's final state bit-identical to

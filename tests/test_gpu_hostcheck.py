@@ -59,22 +59,48 @@ def test_tiny_stream_host_check(torch, W, M):
         assert 0 < stats["overlap_tests"] <= len(st.kernels) * M * acs.K_MAX * acs.K_MAX
 
 
-def test_rl_steps_host_check(torch):
+@pytest.mark.parametrize("W,M", [(32, 32), (64, 128), (16, 100)])
+def test_rl_steps_host_check(torch, W, M):
+    """Six physics steps (about 450 kernels): with M above 64 the host's
+    lists use their second word (a step's islands kernel reads what the next
+    step's broadphase writes, some 75 kernels later)."""
     sc = inputs.rl_scene(seed=1, n=64)
     g = acs.RLSceneGPU(sc)
     ref = O.Scene.from_inputs(sc)
     accs = []
-    with acs.Window(32, path="device", trace=True, host_check_depth=32, trace_capacity=1 << 16) as w:
+    with acs.Window(W, path="device", trace=True, host_check_depth=M, trace_capacity=1 << 16) as w:
         for step in range(6):
-            say(f"host check rl step={step}")
+            say(f"host check rl step={step} W={W} M={M}")
             acs.rl_run(w, g, 1)
             ref.step()
             accs += [ref.access(*k) for k in ref.step_kernels()]
             assert np.array_equal(bits(g.get(acs.RL_X)), bits(ref.X))
             assert np.array_equal(bits(g.get(acs.RL_V)), bits(ref.V))
         tr = w.trace()
-    code, msg = O.check_trace(accs, 32, tr, check_times=True, early=True)
+    code, msg = O.check_trace(accs, W, tr, check_times=True, early=True)
     assert code == 0, msg
+
+
+def test_second_word_orders_a_dependency_inside_the_gate(torch):
+    """A 2 ms kernel writes byte 0, a hundred short independent kernels
+    follow, then one reads byte 0, 101 places after the writer.  With M = 128
+    the host's list holds the writer: the reader is admitted while the writer
+    still runs (the gate does not hold it), and its workers wait for the
+    writer through the second word of its upstream list."""
+    buf = torch.zeros(8192, dtype=torch.uint8, device="cuda")
+    base = buf.data_ptr()
+    torch.cuda.current_stream().synchronize()
+    say("host check second word")
+    with acs.Window(8, path="device", trace=True, host_check_depth=128) as w:
+        w.submit(acs.K_NOP, [], [(base, 1)], acs.ArgsNop(2_000_000))
+        for i in range(100):
+            w.submit(acs.K_NOP, [], [(base + 64 * (i + 1), 1)], acs.ArgsNop(0))
+        w.submit(acs.K_NOP, [(base, 1)], [(base + 7000, 1)], acs.ArgsNop(0))
+        assert w.sync_rc(SYNC_NS) == 0
+        tr = w.trace()
+    assert tr["t_start"][101] >= tr["t_end"][0]
+    assert tr["ev_insert"][101] < tr["ev_retire"][0]
+    assert tr["up_mask"][101] == 1 << int(tr["slot"][0])
 
 
 def test_gate_orders_a_dependency_outside_the_host_list(torch):
@@ -99,7 +125,7 @@ def test_gate_orders_a_dependency_outside_the_host_list(torch):
 def test_host_check_paths_agree_on_an_episode(torch):
     sc = inputs.rl_scene(seed=2, n=64)
     finals = []
-    for M in (0, 32, 8):
+    for M in (0, 32, 8, 128):
         say(f"host check episode M={M}")
         g = acs.RLSceneGPU(sc)
         with acs.Window(32, path="device", host_check_depth=M) as w:

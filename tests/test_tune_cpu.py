@@ -21,7 +21,8 @@ def test_candidates_cover_the_documented_space():
         if G * pow2(W) > acs.W_MAX:
             continue
         if G == 1:
-            want |= {(W, 1, g, 0, 0), (W, 1, g, W, 0), (W, 1, g, 0, 1)}   # check wave, host, window wave
+            # check wave, host against W and against 2W (at most 128), window wave
+            want |= {(W, 1, g, 0, 0), (W, 1, g, W, 0), (W, 1, g, min(2 * W, 128), 0), (W, 1, g, 0, 1)}
         else:
             want.add((W, G, g, 0, 0))
     assert keys == want
@@ -59,7 +60,8 @@ def test_near_ties_go_to_the_cheapest_configuration():
     rates = {(32, 1, "host"): 2098.0, (32, 2, "host"): 2089.0, (16, 1, "host"): 1812.0}
 
     def timer(scenes, cfg, steps):
-        site = "host" if cfg["host_check_depth"] else ("window" if cfg["window_check"] else "wave")
+        site = ("host2" if cfg["host_check_depth"] > cfg["W"] else "host") if cfg["host_check_depth"] else \
+            ("window" if cfg["window_check"] else "wave")
         v = rates.get((cfg["W"], cfg["wg_per_task"], site), 1000.0)
         return v - (16.0 if cfg["queue_depth"] == 1024 else 0.0) + (2.0 if cfg["queue_depth"] == 4096 else 0.0)
 
