@@ -38,6 +38,7 @@ struct SegTable {
     uint64_t used[ACS_K_MAX];                      // bit i of row m: kernel i has an m-th range
     uint64_t wrow[ACS_K_MAX];                      // bit i of row m: that range is a write
     int64_t bs[kCols], be[kCols];                  // column i: bounding interval of its ranges
+    uint8_t cn[kCols];                             // column i: ranges held (rows at and past it are empty)
 
     SegTable()
     {
@@ -45,7 +46,10 @@ struct SegTable {
             for (int i = 0; i < kCols; i++) s[m][i] = e[m][i] = kEmpty;
             used[m] = wrow[m] = 0;
         }
-        for (int i = 0; i < kCols; i++) bs[i] = be[i] = kEmpty;
+        for (int i = 0; i < kCols; i++) {
+            bs[i] = be[i] = kEmpty;
+            cn[i] = 0;
+        }
     }
 
     // Bounding interval of d's ranges, flipped; [0, 0) when it has none.
@@ -59,17 +63,21 @@ struct SegTable {
         }
     }
 
-    // Column i takes the ranges of d (replacing what it held).
+    // Column i takes the ranges of d (replacing what it held).  Rows at and
+    // past both the old and the new range count are empty already.
     void put(int i, const Desc &d)
     {
         const uint64_t bit = 1ull << i;
-        for (int m = 0; m < ACS_K_MAX; m++) {
-            const bool u = (uint32_t)m < d.nseg, w = u && ((d.wbits >> m) & 1u);
+        const uint32_t n = d.nseg < (uint32_t)ACS_K_MAX ? d.nseg : (uint32_t)ACS_K_MAX;
+        const uint32_t rows = n > cn[i] ? n : cn[i];
+        for (uint32_t m = 0; m < rows; m++) {
+            const bool u = m < n, w = u && ((d.wbits >> m) & 1u);
             s[m][i] = u ? (int64_t)(d.s[m] ^ 0x8000000000000000ull) : kEmpty;
             e[m][i] = u ? (int64_t)(d.e[m] ^ 0x8000000000000000ull) : kEmpty;
             used[m] = u ? (used[m] | bit) : (used[m] & ~bit);
             wrow[m] = w ? (wrow[m] | bit) : (wrow[m] & ~bit);
         }
+        cn[i] = (uint8_t)n;
         bounds(d, bs[i], be[i]);
     }
 
