@@ -80,7 +80,7 @@ typedef struct {
 // number of groups of W slots.
 static int run_sim(int32_t W, int32_t n_groups, int32_t host_check, int32_t check_wave, int32_t n_workers, int32_t n,
                    const sim_desc *descs, const int32_t *groups, const uint64_t *host_up, uint32_t ring_cap,
-                   acs_trace_rec *trace_out, double timeout_s, uint64_t *retired_out)
+                   acs_trace_rec *trace_out, double timeout_s, uint64_t *retired_out, const uint64_t *host_up_hi = nullptr)
 {
     using namespace acs;
     int32_t wp = 1;
@@ -154,6 +154,7 @@ static int run_sim(int32_t W, int32_t n_groups, int32_t host_check, int32_t chec
         d.gseq = (uint32_t)sub[g];
         d.group = (uint32_t)g;
         if (host_up) d.host_up = host_up[i];
+        if (host_up_hi) d.host_up_hi = host_up_hi[i];
         ring[(size_t)g * ring_cap + (sub[g] & (ring_cap - 1))] = d;
         sub[g]++;
         __atomic_store_n(&ctrl->tail[g], sub[g], __ATOMIC_SEQ_CST);
@@ -213,6 +214,17 @@ int sim_run_hostcheck(int32_t W, int32_t M, int32_t n_workers, int32_t n, const 
 {
     if (M < 1 || M > 64 || !host_up) return -1;
     return run_sim(W, 1, M, 0, n_workers, n, descs, nullptr, host_up, ring_cap, trace_out, timeout_s, retired_out);
+}
+
+// The same with host lists longer than 64: host_up_hi[i] bit b is the kernel
+// b + 65 places before kernel i.
+int sim_run_hostcheck2(int32_t W, int32_t M, int32_t n_workers, int32_t n, const sim_desc *descs,
+                       const uint64_t *host_up, const uint64_t *host_up_hi, uint32_t ring_cap, acs_trace_rec *trace_out,
+                       double timeout_s, uint64_t *retired_out)
+{
+    if (M < 1 || M > ACS_HOST_CHECK_MAX || !host_up || !host_up_hi) return -1;
+    return run_sim(W, 1, M, 0, n_workers, n, descs, nullptr, host_up, ring_cap, trace_out, timeout_s, retired_out,
+                   host_up_hi);
 }
 
 // Check-wave mode: wave 2 computes each descriptor's upstream list over

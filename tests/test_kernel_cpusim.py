@@ -310,6 +310,47 @@ def test_host_check_mode_through_kernel_source(sim, seed, W, M, workers):
     assert code == 0, msg
 
 
+def host_lists2(accs, M):
+    """host_lists for M up to 128: bit d of lo[j] is the kernel j - 1 - d,
+    bit d of hi[j] the kernel j - 65 - d."""
+    lo = np.zeros(len(accs), np.uint64)
+    hi = np.zeros(len(accs), np.uint64)
+    for j in range(len(accs)):
+        for d in range(min(M, j)):
+            if O.conflict(accs[j - 1 - d], accs[j]):
+                if d < 64:
+                    lo[j] |= np.uint64(1 << d)
+                else:
+                    hi[j] |= np.uint64(1 << (d - 64))
+    return lo, hi
+
+
+@pytest.mark.timeout(300, method="thread")
+@pytest.mark.parametrize("seed,W,M,workers", [(7, 16, 100, 3), (8, 64, 128, 2), (9, 8, 128, 2)])
+def test_host_lists_longer_than_64_through_kernel_source(sim, seed, W, M, workers):
+    """Host lists over up to 128 kernels (two words per list) on streams of
+    200 kernels: same bits as in-order execution, and the trace passes the
+    checker (every conflicting kernel in the window at insert is an
+    upstream, including those 65 or more places back)."""
+    st = inputs.tiny_stream(seed, n_kernels=200)
+    arena = st.init.copy()
+    descs = _descs(st, arena.ctypes.data)
+    accs = O.tiny_accesses(st, base=arena.ctypes.data)
+    lo, hi = host_lists2(accs, M)
+    assert np.any(hi != 0)
+    n = len(st.kernels)
+    sim.sim_run_hostcheck2.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_uint32, C.c_void_p, C.c_double, C.POINTER(C.c_uint64)]
+    tr = np.zeros(n, dtype=acs.TRACE_DTYPE)
+    retired = C.c_uint64()
+    rc = sim.sim_run_hostcheck2(W, M, workers, n, descs, lo.ctypes.data, hi.ctypes.data, 64, tr.ctypes.data, 120.0,
+                                C.byref(retired))
+    assert rc == 0 and retired.value == n
+    assert np.array_equal(arena.view(np.uint32), O.tiny_run(st).view(np.uint32))
+    code, msg = O.check_trace(O.tiny_accesses(st), W, tr, check_times=True, early=True)
+    assert code == 0, msg
+
+
 @pytest.mark.timeout(300, method="thread")
 def test_host_check_gate_holds_back_past_a_long_kernel(sim):
     """A long kernel writes byte 0, twenty short independent kernels follow,
