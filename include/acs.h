@@ -181,7 +181,7 @@ int acs_window_configure(acs_window *w, const acs_config *cfg);
  *   stream      the caller's hipStream_t on cfg->device, created non-blocking
  *               and used by nothing else until acs_window_stop or
  *               acs_window_destroy returns: the persistent kernel runs in it.
- * The scheduler state lives in a static device array of 1.5 MiB per device,
+ * The scheduler state lives in a static device array of 1.6 MiB per device,
  * which each device holds until the process ends; it is cleared by a fill
  * kernel on `stream` before the persistent kernel starts.  One such window
  * per device at a time: a second one on the same device, while the first has

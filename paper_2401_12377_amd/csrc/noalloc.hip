@@ -13,7 +13,7 @@ namespace acs {
 
 static_assert(sizeof(DevState) % 256 == 0, "the state is cleared in 16-byte words and placed at 256 bytes");
 
-// 1.5 MiB per device, placed when this code object is loaded on the device
+// 1.6 MiB per device, placed when this code object is loaded on the device
 // and held until the process ends.  In host code the array's name is a
 // host-side stand-in: its device address comes from hipGetSymbolAddress,
 // taken once per device with that device current, and only that address
