@@ -65,7 +65,11 @@ typedef struct { float *out; const float *in[3]; uint32_t len[3]; uint32_t nin; 
  * island: first position, end position, first edge, end edge.  Every entry
  * is a system-scope store and the stamp is stored after all the others have
  * completed, so a host that sees its stamp in [3] (acquire load) may read the
- * plan while the window is still running. */
+ * plan while the window is still running.  Only the host reads the plan: on
+ * the device-resident path it is stored after the islands kernel has been
+ * marked complete (its dependents do not wait for host memory), so the
+ * kernel's completion alone does not make the plan readable; the stamp
+ * does. */
 typedef struct {
     uint64_t base;
     uint64_t plan;

@@ -50,8 +50,9 @@ typedef struct {
 } acs_rl_counts;
 
 /* Runs `steps` steps.  Per step: predict, broadphase, islands, permute are
- * submitted, the window is drained so that the plan (input-dependent island
- * list) can be read, then iters x (multi-body islands) Jacobi kernels in
+ * submitted, the host waits until the islands kernel's plan (the
+ * input-dependent island list) carries this step's stamp, while the window
+ * keeps running, then iters x (multi-body islands) Jacobi kernels in
  * iteration-major order and the integrate kernel are submitted.  step_ns (if
  * not NULL, `steps` entries) receives the wall time of each step measured
  * between consecutive plan reads; counts (if not NULL) the work done.
@@ -63,8 +64,9 @@ int acs_rl_run(acs_window *w, const acs_rl_scene *scene, int32_t steps, double *
  * (the window must have acs_config.n_groups >= n_groups; use 1 on paths
  * without groups).  Per batched step: the predicts of every scene are
  * submitted, then every broadphase, every islands and every permute kernel;
- * then, group by group, the group is drained, its scenes' plans read and
- * their Jacobi kernels submitted iteration by iteration across the group's
+ * then, group by group, the host waits for its scenes' plans (their stamps;
+ * the window keeps running), reads them and submits their Jacobi kernels
+ * iteration by iteration across the group's
  * scenes, then their integrate kernels.  Each scene's own kernels keep their
  * program order; scenes are independent, so the interleaving changes no
  * result.  step_ns (if not NULL, `steps` entries) receives the wall time
@@ -203,8 +205,9 @@ void acs_pool_destroy(acs_pool *p);
  * working memory; it is then submitted to the window group with the fewest
  * requests in flight.  An RL request is one step of a scene: its input
  * image is copied into its block, predict / broadphase / islands / permute
- * run, and a signal kernel tells the host that the island plan is readable;
- * the host then submits the plan's Jacobi kernels, integrate, a copy of the
+ * run, and a signal kernel tells the host that the islands kernel has
+ * completed; once the plan's stamp is also there the host submits the plan's
+ * Jacobi kernels, integrate, a copy of the
  * result out of the block and a final signal.  A DNN request is one
  * inference (acs_dnn_submit's kernels with activations in its block) and a
  * final signal.  The final signal reads the whole block and the output, so

@@ -108,6 +108,44 @@ __device__ __forceinline__ void put_host(ACS_GAS int32_t *p, int32_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// The island plan on its way to the host.  Standalone kernels store it to
+// host memory as they compute it.  In the persistent kernel the islands body
+// leaves it in LDS, at the end of the body scratch (`plan_stage`), and the
+// worker copies it out after it has marked the kernel complete: a store to
+// host memory takes from a microsecond to tens of microseconds to complete,
+// and no task on the device reads the plan (only the host does, after the
+// stamp), so the kernel's dependents need not wait for it.
+__device__ __forceinline__ int32_t *plan_stage(uint8_t *smem, int32_t n)
+{
+    return reinterpret_cast<int32_t *>(smem + kBodySmem) - rl_plan_ints(n);
+}
+
+template <bool DEV>
+__device__ __forceinline__ void plan_put(ACS_GAS int32_t *plan, int32_t *stage, int32_t i, int32_t v)
+{
+    if constexpr (DEV)
+        stage[i] = v;
+    else
+        put_host(&plan[i], v);
+}
+
+// Copies a staged plan to host memory, the stamp last once the rest has
+// completed (whole workgroup; the worker calls it after the completion store).
+__device__ inline void plan_publish(const acs_args_rl &a, uint8_t *smem)
+{
+    ACS_GAS int32_t *plan = reinterpret_cast<ACS_GAS int32_t *>(a.plan);
+    const int32_t *stage = plan_stage(smem, a.n);
+    const int32_t nm = stage[1];
+    const int32_t cnt = 4 + 4 * (nm < 0 ? 0 : (nm > a.n / 2 ? a.n / 2 : nm));
+    for (int32_t i = (int32_t)threadIdx.x; i < cnt; i += ACS_BLOCK)
+        if (i != 3) put_host(&plan[i], stage[i]);
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt 0, expcnt 7, lgkmcnt 15
+    __syncthreads();
+    if (threadIdx.x == 0) put_host(&plan[3], stage[3]);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // no-op with an optional busy wait on the constant wall clock
 // ---------------------------------------------------------------------------
@@ -602,22 +640,27 @@ __device__ inline void islands_small(const acs_args_rl &a, const RLView &v, ACS_
     const int32_t endp = start + size;
     const int32_t e1s = __shfl(poff, endp & 63, 64);   // every lane takes part in the shuffle
     const int32_t e1 = endp < n ? e1s : ep;
+    int32_t *stage = plan_stage(smem, n);
     if (multi) {
         const int32_t m = __builtin_popcountll(multis & below);
-        put_host(&plan[4 + 4 * m + 0], start);
-        put_host(&plan[4 + 4 * m + 1], endp);
-        put_host(&plan[4 + 4 * m + 2], e0);
-        put_host(&plan[4 + 4 * m + 3], e1);
+        plan_put<DEV>(plan, stage, 4 + 4 * m + 0, start);
+        plan_put<DEV>(plan, stage, 4 + 4 * m + 1, endp);
+        plan_put<DEV>(plan, stage, 4 + 4 * m + 2, e0);
+        plan_put<DEV>(plan, stage, 4 + 4 * m + 3, e1);
     }
     if (lane == 0) {
-        put_host(&plan[0], nisl);
-        put_host(&plan[1], (int32_t)__builtin_popcountll(multis));
-        put_host(&plan[2], ep);
+        plan_put<DEV>(plan, stage, 0, nisl);
+        plan_put<DEV>(plan, stage, 1, (int32_t)__builtin_popcountll(multis));
+        plan_put<DEV>(plan, stage, 2, ep);
     }
-    // the stamp last, once this wave's plan stores have completed (the
-    // wave wrote the whole plan)
-    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt 0, expcnt 7, lgkmcnt 15
-    if (lane == 0) put_host(&plan[3], a.iter);
+    if constexpr (DEV) {
+        if (lane == 0) stage[3] = a.iter;   // published after completion (plan_publish)
+    } else {
+        // the stamp last, once this wave's plan stores have completed (the
+        // wave wrote the whole plan)
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt 0, expcnt 7, lgkmcnt 15
+        if (lane == 0) put_host(&plan[3], a.iter);
+    }
 }
 
 template <bool DEV>
@@ -639,7 +682,8 @@ __device__ inline void body_rl_islands(const acs_args_rl &a, uint8_t *smem)
     int32_t *poff = inv + n;                            // n + 1
     int32_t *tmp = poff + n + 1;                        // 4
     int32_t *adjs = tmp + 4;                            // adjacency copy when it fits
-    const int32_t lds_cap = (int32_t)(kBodySmem / 4) - (int32_t)(adjs - lab);
+    int32_t *stage = plan_stage(smem, n);               // the plan (persistent kernel), at the end
+    const int32_t lds_cap = (int32_t)(stage - adjs);
 
     // offsets are clamped to the adjacency capacity so that a corrupt input
     // can never index outside the arena
@@ -771,21 +815,25 @@ __device__ inline void body_rl_islands(const acs_args_rl &a, uint8_t *smem)
     for (int32_t k = t; k < nisl; k += ACS_BLOCK) {
         if (sz[k + 1] - sz[k] >= 2) {
             const int32_t m = ridx[k];
-            put_host(&plan[4 + 4 * m + 0], sz[k]);
-            put_host(&plan[4 + 4 * m + 1], sz[k + 1]);
-            put_host(&plan[4 + 4 * m + 2], poff[sz[k]]);
-            put_host(&plan[4 + 4 * m + 3], poff[sz[k + 1]]);
+            plan_put<DEV>(plan, stage, 4 + 4 * m + 0, sz[k]);
+            plan_put<DEV>(plan, stage, 4 + 4 * m + 1, sz[k + 1]);
+            plan_put<DEV>(plan, stage, 4 + 4 * m + 2, poff[sz[k]]);
+            plan_put<DEV>(plan, stage, 4 + 4 * m + 3, poff[sz[k + 1]]);
         }
     }
     if (t == 0) {
-        put_host(&plan[0], nisl);
-        put_host(&plan[1], nmulti);
-        put_host(&plan[2], Ep);
+        plan_put<DEV>(plan, stage, 0, nisl);
+        plan_put<DEV>(plan, stage, 1, nmulti);
+        plan_put<DEV>(plan, stage, 2, Ep);
     }
-    // the stamp last, once every wave's plan stores have completed
-    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt 0, expcnt 7, lgkmcnt 15
-    __syncthreads();
-    if (t == 0) put_host(&plan[3], a.iter);
+    if constexpr (DEV) {
+        if (t == 0) stage[3] = a.iter;   // published after completion (plan_publish)
+    } else {
+        // the stamp last, once every wave's plan stores have completed
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt 0, expcnt 7, lgkmcnt 15
+        __syncthreads();
+        if (t == 0) put_host(&plan[3], a.iter);
+    }
 }
 
 template <bool DEV>

@@ -82,6 +82,15 @@ public:
         return submit_integrate(cnt);
     }
 
+    // True once the islands kernel of this step has published the plan (no
+    // wait).  On the device-resident path the plan reaches host memory after
+    // the islands kernel has completed, so a completion alone does not say
+    // that the plan is readable; its stamp does.
+    bool plan_ready() const
+    {
+        return __atomic_load_n(&((const int32_t *)sc_->plan)[3], __ATOMIC_ACQUIRE) == stamp_;
+    }
+
     // Waits until the islands kernel of this step has published the plan
     // (its stamp in plan[3]) while the window keeps running: the host needs
     // the island list before it can state the rest of the step, but not an

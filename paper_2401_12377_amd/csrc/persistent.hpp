@@ -1091,7 +1091,10 @@ __device__ inline void worker(const DevParams &p, uint8_t *smem, Mail *mail)
         __syncthreads();
         const uint32_t grp = uni32(mail->group);
         if (grp == kSentinelGroup) break;
-        run_body<true>((int32_t)uni32((uint32_t)mail->kid), mail->args, uni32(mail->piece), uni32(mail->np), smem);
+        // read before the barrier below: past it, wave 0 may take the next
+        // ticket and rewrite the mail
+        const uint32_t kid = uni32((uint32_t)mail->kid);
+        run_body<true>((int32_t)kid, mail->args, uni32(mail->piece), uni32(mail->np), smem);
         // each wave waits until its own result stores (device scope) are
         // complete, so that they are visible device-wide before wave 0 counts
         // the piece (the workgroup barrier alone waits only for LDS traffic).
@@ -1130,6 +1133,14 @@ __device__ inline void worker(const DevParams &p, uint8_t *smem, Mail *mail)
             }
             if (last)
                 __hip_atomic_store(&st->dseq[grp][g & (kSeqRing - 1u)], g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // an islands kernel's plan goes to the host only now (plan_publish),
+        // before the body scratch that holds it is used again; every wave
+        // takes this branch or none (kid was read before the barrier), and
+        // wave 0 rewrites the mail only after it
+        if (kid == (uint32_t)ACS_K_RL_ISLANDS) {
+            __syncthreads();
+            plan_publish(load_args<acs_args_rl>(mail->args), smem);
         }
     }
 }

@@ -225,6 +225,10 @@ public:
                     k++;
                     continue;
                 }
+                if (sl.phase == 1 && !sl.rl->plan_ready()) {
+                    k++;   // signalled, but the plan's stamp has not reached host memory yet
+                    continue;
+                }
                 last_progress = clock_ns();
                 if (sl.phase == 1) {
                     if (int rc = submit_rl_tail(s)) return rc;
