@@ -66,8 +66,9 @@ int acs_rl_run(acs_window *w, const acs_rl_scene *scene, int32_t steps, double *
  * submitted, then every broadphase, every islands and every permute kernel;
  * then, group by group, the host waits for its scenes' plans (their stamps;
  * the window keeps running), reads them and submits their Jacobi kernels
- * iteration by iteration across the group's
- * scenes, then their integrate kernels.  Each scene's own kernels keep their
+ * iteration by iteration and, within an iteration, island by island across
+ * the group's scenes (the k-th island of every scene that has one before any
+ * k+1-th), then their integrate kernels.  Each scene's own kernels keep their
  * program order; scenes are independent, so the interleaving changes no
  * result.  step_ns (if not NULL, `steps` entries) receives the wall time
  * of each batched step, which then ends with a full drain; counts the work

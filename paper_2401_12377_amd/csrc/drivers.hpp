@@ -132,22 +132,32 @@ public:
     // Jacobi iteration `it` over every multi-body island (after tail_begin)
     int submit_iteration(int32_t it, acs_rl_counts &cnt)
     {
-        const int32_t *plan = (const int32_t *)sc_->plan;
-        const int src = (it % 2 == 0) ? ACS_RL_Q0 : ACS_RL_Q1, dst = (it % 2 == 0) ? ACS_RL_Q1 : ACS_RL_Q0;
-        for (int32_t k = 0; k < nmulti_; k++) {
-            const int32_t b0 = plan[4 + 4 * k], b1 = plan[5 + 4 * k], e0 = plan[6 + 4 * k], e1 = plan[7 + 4 * k];
-            a_.iter = it;
-            a_.b0 = b0;
-            a_.b1 = b1;
-            const acs_seg r[3] = {vec(src, b0, b1), ints(ACS_RL_PADJ_OFF, b0, b1 + 1), ints(ACS_RL_PADJ, e0, e1)};
-            const acs_seg wr[1] = {vec(dst, b0, b1)};
-            if (int rc = submit(ACS_K_RL_JACOBI, r, 3, wr, 1, cnt)) return rc;
-            cnt.jacobi_kernels++;
-            cnt.jacobi_bodies += (uint64_t)(b1 - b0);
-            cnt.jacobi_edges += (uint64_t)(e1 - e0);
-        }
+        for (int32_t k = 0; k < nmulti_; k++)
+            if (int rc = submit_island(it, k, cnt)) return rc;
         return ACS_OK;
     }
+
+    // Jacobi iteration `it` over multi-body island k of the plan (after
+    // tail_begin; k < multi())
+    int submit_island(int32_t it, int32_t k, acs_rl_counts &cnt)
+    {
+        const int32_t *plan = (const int32_t *)sc_->plan;
+        const int src = (it % 2 == 0) ? ACS_RL_Q0 : ACS_RL_Q1, dst = (it % 2 == 0) ? ACS_RL_Q1 : ACS_RL_Q0;
+        const int32_t b0 = plan[4 + 4 * k], b1 = plan[5 + 4 * k], e0 = plan[6 + 4 * k], e1 = plan[7 + 4 * k];
+        a_.iter = it;
+        a_.b0 = b0;
+        a_.b1 = b1;
+        const acs_seg r[3] = {vec(src, b0, b1), ints(ACS_RL_PADJ_OFF, b0, b1 + 1), ints(ACS_RL_PADJ, e0, e1)};
+        const acs_seg wr[1] = {vec(dst, b0, b1)};
+        if (int rc = submit(ACS_K_RL_JACOBI, r, 3, wr, 1, cnt)) return rc;
+        cnt.jacobi_kernels++;
+        cnt.jacobi_bodies += (uint64_t)(b1 - b0);
+        cnt.jacobi_edges += (uint64_t)(e1 - e0);
+        return ACS_OK;
+    }
+
+    // multi-body islands of the plan read by tail_begin
+    int32_t multi() const { return nmulti_; }
 
     int submit_integrate(acs_rl_counts &cnt)
     {

@@ -112,10 +112,16 @@ int acs_rl_run_batch(acs_window *w, const acs_rl_scene *scenes, int32_t n_scenes
                 if (int rc = st[(size_t)i].wait_plan()) return rc;
             for (int32_t i = g; i < n_scenes; i += n_groups)
                 if (int rc = st[(size_t)i].tail_begin(cnt)) return rc;
+            // island by island across the scenes, so that the kernels next
+            // to each other touch different scenes' memory: the dependency
+            // check then drops them on their bounding intervals alone
+            int32_t max_multi = 0;
+            for (int32_t i = g; i < n_scenes; i += n_groups) max_multi = std::max(max_multi, st[(size_t)i].multi());
             for (int32_t it = 0; it < max_iters; it++)
-                for (int32_t i = g; i < n_scenes; i += n_groups)
-                    if (it < st[(size_t)i].iters())
-                        if (int rc = st[(size_t)i].submit_iteration(it, cnt)) return rc;
+                for (int32_t k = 0; k < max_multi; k++)
+                    for (int32_t i = g; i < n_scenes; i += n_groups)
+                        if (it < st[(size_t)i].iters() && k < st[(size_t)i].multi())
+                            if (int rc = st[(size_t)i].submit_island(it, k, cnt)) return rc;
             for (int32_t i = g; i < n_scenes; i += n_groups)
                 if (int rc = st[(size_t)i].submit_integrate(cnt)) return rc;
         }

@@ -71,14 +71,16 @@ def test_batch_matches_solo_oracle(torch, path, G, W, hc):
             for i in range(len(refs)):
                 put(i, k)
         tails = [ref.step_kernels()[4:] for ref in refs]
-        # per group: Jacobi iteration by iteration across its scenes, then integrate
+        # per group: Jacobi iteration by iteration, island by island across
+        # its scenes, then integrate
         for g in range(G):
             mine = range(g, len(refs), G)
             for it in range(max(refs[i].c.iters for i in mine)):
-                for i in mine:
-                    for k in tails[i]:
-                        if k[0] == O.RL_JACOBI and k[2] == it:
-                            put(i, k)
+                js = {i: [k for k in tails[i] if k[0] == O.RL_JACOBI and k[2] == it] for i in mine}
+                for kk in range(max(len(v) for v in js.values())):
+                    for i in mine:
+                        if kk < len(js[i]):
+                            put(i, js[i][kk])
             for i in mine:
                 for k in tails[i]:
                     if k[0] != O.RL_JACOBI:
