@@ -41,16 +41,18 @@ HBM_PEAK_GBS = 8000.0
 # (--copy-calibration), one entry per tuned configuration that was measured.
 # Valid only for the kernel sources whose digest is recorded and for the same
 # workload and configuration: any change makes the figure stale (null).
-def _cfg_key(qd):
+def _cfg_key(qd, hc=64):
     return (256, 20, json.dumps({"W": 64, "n_groups": 1, "wg_per_task": 1, "queue_depth": qd,
-                                 "host_check_depth": 64, "window_check": 0}, sort_keys=True))
+                                 "host_check_depth": hc, "window_check": 0}, sort_keys=True))
 
 
 TRAFFIC = {
     "digest": "65488b41e62ec398",
     "copy_bytes": 268435456, "copy_fetch_kib": 131085.2917, "copy_write_kib": 262144.0,
     "runs": [{"workload": _cfg_key(256), "fetch_kib": 318555.75, "write_kib": 587168.3125},
-             {"workload": _cfg_key(1024), "fetch_kib": 320026.9375, "write_kib": 586719.25}],
+             {"workload": _cfg_key(1024), "fetch_kib": 320026.9375, "write_kib": 586719.25},
+             {"workload": _cfg_key(256, 128), "fetch_kib": 323091.25, "write_kib": 587344.28125},
+             {"workload": _cfg_key(1024, 128), "fetch_kib": 323495.75, "write_kib": 586999.78125}],
 }
 KERNEL_SOURCES = ["kernels.hip", "persistent.hpp", "bodies.hpp", "dev_shared.hpp"]
 
